@@ -1,0 +1,207 @@
+/*
+ * etd_rdp.h -- C ABI of the MI355X (gfx950) ETD-RDP-IF reaction-diffusion
+ * stepper.
+ *
+ * The library advances   u_t = D Lap(u) + F(u)   (Section 2 of Asante-Asamani,
+ * Kleefeld and Wade, "A second-order exponential time differencing scheme for
+ * non-linear reaction-diffusion systems with dimensional splitting") with the
+ * second-order L-stable ETD-RDP-IF scheme: the d-dimensional frame of
+ * Section 6 (eq. donedone for d = 3, eq. done for d = 2).  Every split factor
+ * (I + (k/gamma) A_i)^{-1}, gamma in {1, 3, 4}, is applied as a batch of exact
+ * 1-D line solves (Section 7) fused with the pointwise reaction.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arithmetic is IEEE FP64 throughout.
+ *  - A state is a contiguous, caller-owned device array of s * N doubles,
+ *    N = n[0] * ... * n[d-1], laid out species-planar:
+ *        u[sigma][i_d]...[i_2][i_1],  i_1 (axis 1) fastest.
+ *    Axis i is the axis of the paper's A_i (eq. Ai): axis 1 carries B_p in the
+ *    innermost spatial Kronecker position, axis d in the outermost one.  The
+ *    scheme treats axis d differently from the others (its T/S solves come
+ *    after f*), so this ordering is part of the contract.  The paper's own
+ *    vector puts the species index innermost; that is a permutation of the
+ *    same data.
+ *  - Boundary conditions are homogeneous, one per axis (Section 2):
+ *    Dirichlet, Neumann or periodic, with the grids of Example 1.
+ *  - The library never allocates device memory.  Device data (tables and
+ *    carried intermediates) live in a caller-provided workspace whose size
+ *    etd_rdp_workspace_bytes() reports; it must be 256-byte aligned.
+ *  - Every call returns an int status: ETD_OK (0) or a negative ETD_ERR_*.
+ *    No C++ exception crosses the ABI.  Kernel faults surface at the caller's
+ *    next synchronisation; launch errors are reported as ETD_ERR_HIP and the
+ *    HIP code is kept in the context (etd_rdp_last_hip_error).
+ *  - A context may be used by one host thread / one stream at a time.
+ *  - Streams are passed as void* (a hipStream_t, or NULL for the null stream).
+ */
+#ifndef ETD_RDP_H_
+#define ETD_RDP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ETD_OK 0
+#define ETD_ERR_ARG (-1)          /* invalid argument (see etd_rdp_init)    */
+#define ETD_ERR_UNSUPPORTED (-2)  /* valid problem this build does not run  */
+#define ETD_ERR_WORKSPACE (-3)    /* workspace NULL, too small, misaligned  */
+#define ETD_ERR_HIP (-4)          /* a HIP runtime call failed              */
+#define ETD_ERR_INTERNAL (-5)     /* a table self-check failed              */
+
+/* ---- boundary conditions (Section 2, Example 1) ------------------------ */
+#define ETD_BC_DIRICHLET 0
+#define ETD_BC_NEUMANN 1
+#define ETD_BC_PERIODIC 2
+
+/* ---- reaction models F(u) --------------------------------------------- */
+/* params[] meaning per model; F is evaluated at (u + shift).               */
+#define ETD_RX_LINEAR 0       /* F = C u, C = params[0..s*s) row-major      */
+#define ETD_RX_ENZYME 1       /* s=1: F = -u/(1+u)            (Section 8.1) */
+#define ETD_RX_BRUSSELATOR 2  /* s=2: params a,b: a-(b+1)u+u^2v, bu-u^2v    */
+#define ETD_RX_GRAY_SCOTT 3   /* s=2: params F,kappa: -uv^2+F(1-u),
+                                 uv^2-(F+kappa)v                            */
+#define ETD_RX_SCHNAKENBERG 4 /* s=2: params a,b,gamma: g(a-u+u^2v),
+                                 g(b-u^2v)                                  */
+#define ETD_RX_CGL 5          /* s=2 (Re,Im), alpha=0: params beta:
+                                 u - (1+i beta) u |u|^2        (Section 8.3) */
+
+/* ---- time-stepping scheme --------------------------------------------- */
+#define ETD_SCHEME_RDP 0   /* ETD-RDP-IF, second order (Section 6)          */
+#define ETD_SCHEME_ETD1 1  /* predictor only: ETD1-IF with Pade-(0,1),
+                              first order (eq. duhamel3t)                    */
+
+#define ETD_MAX_DIM 3
+#define ETD_MAX_SPECIES 2
+#define ETD_MAX_PARAMS 16
+
+typedef struct etd_grid_t {
+  int32_t d;                  /* spatial dimension: 2 or 3                   */
+  int32_t s;                  /* number of species: 1 or 2                   */
+  int64_t n[ETD_MAX_DIM];     /* unknowns per axis, n[0] = axis 1 (fastest)  */
+  double h[ETD_MAX_DIM];      /* spacing per axis; 0 selects the unit-domain
+                                 default of Example 1: Dirichlet 1/(n+1),
+                                 Neumann 1/(n-1), periodic 1/n               */
+} etd_grid_t;
+
+typedef struct etd_reaction_t {
+  int32_t model;                    /* ETD_RX_*                              */
+  int32_t pad_;
+  double params[ETD_MAX_PARAMS];    /* model parameters (see ETD_RX_*)       */
+  double shift[ETD_MAX_SPECIES];    /* F evaluated at u + shift              */
+} etd_reaction_t;
+
+typedef struct etd_scheme_t {
+  int32_t scheme;                   /* ETD_SCHEME_RDP or ETD_SCHEME_ETD1     */
+  int32_t pad_;
+} etd_scheme_t;
+
+typedef struct etd_rdp_ctx etd_rdp_ctx;
+
+/*
+ * etd_rdp_init -- validate a problem and build its line-solve tables on the
+ * host.  Makes no HIP call, so it runs on machines without a GPU.
+ *
+ *  grid  : dimension, species, sizes, spacings (above).
+ *  bc    : bc[i] for axis i+1, one of ETD_BC_*.
+ *  D     : s diffusion coefficients, finite and >= 0 (diagonal D, Section 2).
+ *  k     : time step, finite and > 0.
+ *  scheme: NULL selects ETD_SCHEME_RDP.
+ *  rx    : reaction model and parameters; must match s.
+ *  out   : receives the new context (owned by the library; free it with
+ *          etd_rdp_destroy).
+ *
+ * Errors: ETD_ERR_ARG for a NULL pointer, d not in {2,3}, s not in {1,2},
+ * n below the minimum of its BC (Dirichlet 1, Neumann 2, periodic 3), a
+ * non-finite or non-positive h or k, a negative or non-finite D, an unknown
+ * model or one whose species count differs from s.  ETD_ERR_UNSUPPORTED when
+ * a line length n cannot be split into at most 64 chunks of at most 8 rows
+ * (n > 512, or n > 64 with no divisor m <= 8 such that n/m <= 64).
+ * ETD_ERR_INTERNAL if a table self-check fails.
+ */
+int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D,
+                 double k, const etd_scheme_t* scheme,
+                 const etd_reaction_t* rx, etd_rdp_ctx** out);
+
+/* Frees a context (NULL is allowed).  Device memory is the caller's. */
+int etd_rdp_destroy(etd_rdp_ctx* ctx);
+
+/*
+ * Bytes of device workspace a step needs: the factor tables plus three
+ * carried FP64 arrays of s*N values (the passes' intermediates).
+ */
+int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
+
+/*
+ * Byte offsets inside the workspace of the three carried arrays (each s*N
+ * doubles, same layout as u).  After a full step their contents are
+ * unspecified; etd_rdp_debug_passes leaves defined values in them.
+ */
+int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, size_t* off_c1,
+                             size_t* off_c2, size_t* off_w);
+
+/*
+ * etd_rdp_step -- advance u in place by nsteps time steps on `stream`.
+ *
+ *  u        : device, s*N doubles, caller-owned, read and overwritten.
+ *  ws       : device workspace of at least etd_rdp_workspace_bytes bytes,
+ *             256-byte aligned; its first use (or a change of ws) uploads
+ *             the tables with an asynchronous copy on `stream`.
+ *  nsteps   : >= 0; 0 is a no-op.
+ *  stream   : hipStream_t (NULL = null stream).  The call only enqueues work;
+ *             it does not synchronise.
+ * Errors: ETD_ERR_ARG (NULL ctx/u, nsteps < 0), ETD_ERR_WORKSPACE,
+ * ETD_ERR_HIP.
+ */
+int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
+                 int64_t nsteps, void* stream);
+
+/*
+ * etd_rdp_debug_passes -- run only the first `npasses` passes (1..d) of one
+ * step and stop, leaving the carried arrays in the workspace.  For d = 3:
+ * after pass 1 the workspace holds c1 = R_1 U, c2 = R_1 f(U), w = P_1 (U+kf);
+ * after pass 2: c1 = R_2 R_1 U, c2 = R_2 R_1 f, w = P_2 P_1 (U + k f).
+ * npasses = d is a full step (u is overwritten).  For testing each pass
+ * against the oracle's intermediates.
+ */
+int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws,
+                         size_t ws_bytes, int32_t npasses, void* stream);
+
+/*
+ * etd_rdp_run_pass -- run pass `pass` (1..d) of a step on its own, reading
+ * and writing the same arrays as inside a full step (pass 1 reads u and
+ * writes the carried arrays, middle passes update them in place, pass d
+ * reads them and writes u).  For timing the kernels one by one.
+ */
+int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
+                     int32_t pass, void* stream);
+
+/*
+ * etd_rdp_apply_solve -- x <- (I + (k/gamma) D_sigma A_axis)^{-1} x for a
+ * single-species grid array x of N doubles (layout as one species of u),
+ * gamma = 1, 3 or 4 (Section 7: the systems the scheme solves).  axis is
+ * 1-based.  Exposes the line solver alone for testing.
+ */
+int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes,
+                        int32_t axis, int32_t sigma, int32_t gamma,
+                        void* stream);
+
+/* Human-readable text of a status code (static storage). */
+const char* etd_rdp_status_string(int status);
+
+/* Last HIP error code seen by ctx (0 if none). */
+int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx);
+
+/* Chunk length m and chunk count C = n/m the line solver uses on an axis
+ * (1-based); for tests and tuning. */
+int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m,
+                       int32_t* chunks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETD_RDP_H_ */

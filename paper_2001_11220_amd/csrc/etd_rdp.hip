@@ -1,0 +1,606 @@
+// MI355X (gfx950) kernels and C ABI of the ETD-RDP-IF stepper.
+//
+// One time step of the d-dimensional frame of Section 6 (eq. donedone for
+// d = 3) runs as d fused passes, one per spatial axis:
+//
+//   pass 1 (axis 1, contiguous)   f = F(U); w = U + k f
+//                                 c1 = R_1 U, c2 = R_1 f, w <- P_1 w
+//   pass i (1 < i < d, strided)   c1 <- R_i c1, c2 <- R_i c2, w <- P_i w
+//   pass d (axis d, strided)      U* = P_d w; f* = F(U*)
+//                                 U <- T_d (9 c1 + 2k c2 + k f*)
+//                                    - S_d (8 c1 + 3k/2 c2 + k/2 f*)
+//
+// with P_i = (I + k A_i)^{-1}, T_i = (I + k/3 A_i)^{-1},
+// S_i = (I + k/4 A_i)^{-1} and R_i = 9 T_i - 8 S_i (the partial fractions of
+// Section 6).  Linearity of R_i lets the corrector brackets 9U + 2kf and
+// 8U + 3k/2 f be formed after the R factors, so only three arrays cross each
+// axis boundary.  Every solve is an exact line solve on a wavefront (see
+// etd_device.hpp).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/etd_rdp.h"
+#include "etd_device.hpp"
+#include "etd_tables.hpp"
+
+namespace etd {
+
+constexpr int kFirstBlock = 256;  // 4 lines per block in the contiguous pass
+constexpr int kTileLines = 16;    // lines per block in the strided passes
+
+// Table index of (axis, species, gamma-slot); slot 0: gamma=1, 1: 3, 2: 4.
+__host__ __device__ inline int tab_index(int axis0, int sigma, int slot, int S) {
+  return (axis0 * S + sigma) * 3 + slot;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: the contiguous axis.  One wavefront per line, all species.
+// ---------------------------------------------------------------------------
+template <int M, int S>
+__global__ __launch_bounds__(kFirstBlock) void k_first(
+    const double* __restrict__ u, double* __restrict__ c1,
+    double* __restrict__ c2, double* __restrict__ w,
+    const SolveTab* __restrict__ tabs, Rx rx, double k, int64_t n1,
+    int64_t nlines, int64_t N, int etd1) {
+  const int lane = threadIdx.x & 63;
+  const int64_t line = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (line >= nlines) return;  // uniform per wavefront
+  const int C = tabs[0].C;
+  const bool act = lane < C;
+  const int64_t off = line * n1 + (int64_t)lane * M;
+  double U[S][M], f[S][M];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j = 0; j < M; ++j) U[s][j] = act ? u[s * N + off + j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double uu[S], ff[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) uu[s] = U[s][j];
+    react<S>(rx, uu, ff);
+#pragma unroll
+    for (int s = 0; s < S; ++s) f[s][j] = ff[s];
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const SolveTab* P = tabs + tab_index(0, s, 0, S);
+    const SolveTab* T = tabs + tab_index(0, s, 1, S);
+    const SolveTab* Sx = tabs + tab_index(0, s, 2, S);
+    if (etd1) {
+      double x[1][M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) x[0][j] = fma(k, f[s][j], U[s][j]);
+      const SolveTab* tb[1] = {P};
+      line_solve<M, 1>(tb, x, lane);
+      if (act)
+#pragma unroll
+        for (int j = 0; j < M; ++j) w[s * N + off + j] = x[0][j];
+      continue;
+    }
+    double x[5][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[0][j] = U[s][j];
+      x[1][j] = U[s][j];
+      x[2][j] = f[s][j];
+      x[3][j] = f[s][j];
+      x[4][j] = fma(k, f[s][j], U[s][j]);
+    }
+    const SolveTab* tb[5] = {T, Sx, T, Sx, P};
+    line_solve<M, 5>(tb, x, lane);
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        c1[s * N + off + j] = 9.0 * x[0][j] - 8.0 * x[1][j];
+        c2[s * N + off + j] = 9.0 * x[2][j] - 8.0 * x[3][j];
+        w[s * N + off + j] = x[4][j];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Middle passes (3-D axis 2): purely linear, in place on c1, c2, w.
+// ---------------------------------------------------------------------------
+template <int M, int S>
+__global__ __launch_bounds__(1024) void k_mid(
+    double* __restrict__ c1, double* __restrict__ c2, double* __restrict__ w,
+    const SolveTab* __restrict__ tabs, Geom g, int etd1) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int64_t t = blockIdx.x / g.nFblk;
+  const int64_t f0 = (blockIdx.x % g.nFblk) << g.logW;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const SolveTab* P = tabs + tab_index(0, s, 0, S);
+    const SolveTab* T = tabs + tab_index(0, s, 1, S);
+    const SolveTab* Sx = tabs + tab_index(0, s, 2, S);
+    if (!etd1) {
+      double* arrs[2] = {c1 + s * g.N, c2 + s * g.N};
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        double v[M], x[2][M];
+        tile_load<M>(arrs[a], v, lds, g, f0, t);
+#pragma unroll
+        for (int j = 0; j < M; ++j) x[0][j] = x[1][j] = v[j];
+        const SolveTab* tb[2] = {T, Sx};
+        line_solve<M, 2>(tb, x, lane);
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[j] = 9.0 * x[0][j] - 8.0 * x[1][j];
+        tile_store<M>(arrs[a], v, lds, g, f0, t);
+      }
+    }
+    double x[1][M];
+    tile_load<M>(w + s * g.N, x[0], lds, g, f0, t);
+    const SolveTab* tb[1] = {P};
+    line_solve<M, 1>(tb, x, lane);
+    tile_store<M>(w + s * g.N, x[0], lds, g, f0, t);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Last pass (axis d): predictor solve, f*, corrector solves, new state.
+// ---------------------------------------------------------------------------
+template <int M, int S>
+__global__ __launch_bounds__(1024) void k_last(
+    double* __restrict__ u, const double* __restrict__ c1,
+    const double* __restrict__ c2, const double* __restrict__ w,
+    const SolveTab* __restrict__ tabs, Rx rx, double k, Geom g, int etd1) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int64_t t = blockIdx.x / g.nFblk;
+  const int64_t f0 = (blockIdx.x % g.nFblk) << g.logW;
+  double us[S][M];
+#pragma unroll
+  for (int s = 0; s < S; ++s) tile_load<M>(w + s * g.N, us[s], lds, g, f0, t);
+  {
+    const SolveTab* tb[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) tb[s] = tabs + tab_index(0, s, 0, S);
+    line_solve<M, S>(tb, us, lane);
+  }
+  if (etd1) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) tile_store<M>(u + s * g.N, us[s], lds, g, f0, t);
+    return;
+  }
+  double fs[S][M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double uu[S], ff[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) uu[s] = us[s][j];
+    react<S>(rx, uu, ff);
+#pragma unroll
+    for (int s = 0; s < S; ++s) fs[s][j] = ff[s];
+  }
+  const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double a[M], b[M], x[2][M];
+    tile_load<M>(c1 + s * g.N, a, lds, g, f0, t);
+    tile_load<M>(c2 + s * g.N, b, lds, g, f0, t);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[0][j] = fma(k, fs[s][j], fma(k2, b[j], 9.0 * a[j]));
+      x[1][j] = fma(k05, fs[s][j], fma(k15, b[j], 8.0 * a[j]));
+    }
+    const SolveTab* tb[2] = {tabs + tab_index(0, s, 1, S), tabs + tab_index(0, s, 2, S)};
+    line_solve<M, 2>(tb, x, lane);
+#pragma unroll
+    for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
+    tile_store<M>(u + s * g.N, a, lds, g, f0, t);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A single solve on one species array (testing aid for the line solver).
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kFirstBlock) void k_solve_contig(
+    double* __restrict__ x, const SolveTab* __restrict__ tab, int64_t n1,
+    int64_t nlines) {
+  const int lane = threadIdx.x & 63;
+  const int64_t line = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (line >= nlines) return;
+  const bool act = lane < tab->C;
+  const int64_t off = line * n1 + (int64_t)lane * M;
+  double v[1][M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[0][j] = act ? x[off + j] : 0.0;
+  const SolveTab* tb[1] = {tab};
+  line_solve<M, 1>(tb, v, lane);
+  if (act)
+#pragma unroll
+    for (int j = 0; j < M; ++j) x[off + j] = v[0][j];
+}
+
+template <int M>
+__global__ __launch_bounds__(1024) void k_solve_strided(
+    double* __restrict__ x, const SolveTab* __restrict__ tab, Geom g) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int64_t t = blockIdx.x / g.nFblk;
+  const int64_t f0 = (blockIdx.x % g.nFblk) << g.logW;
+  double v[1][M];
+  tile_load<M>(x, v[0], lds, g, f0, t);
+  const SolveTab* tb[1] = {tab};
+  line_solve<M, 1>(tb, v, lane);
+  tile_store<M>(x, v[0], lds, g, f0, t);
+}
+
+}  // namespace etd
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+using namespace etd;
+
+struct etd_rdp_ctx {
+  int d = 0, s = 0;
+  int64_t n[3] = {1, 1, 1};
+  double h[3] = {0, 0, 0};
+  int bc[3] = {0, 0, 0};
+  double D[ETD_MAX_SPECIES] = {0, 0};
+  double k = 0;
+  int scheme = ETD_SCHEME_RDP;
+  Rx rx{};
+  int m[3] = {0, 0, 0};
+  int64_t N = 0;
+  std::vector<SolveTab> tabs;  // [axis][species][3]
+  size_t tab_bytes = 0, arr_bytes = 0, ws_bytes = 0;
+  const void* uploaded_ws = nullptr;
+  int last_hip = 0;
+};
+
+namespace {
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int hip_fail(etd_rdp_ctx* c, hipError_t e) {
+  if (c) c->last_hip = static_cast<int>(e);
+  return ETD_ERR_HIP;
+}
+
+int species_of_model(int model) {
+  switch (model) {
+    case ETD_RX_ENZYME: return 1;
+    case ETD_RX_BRUSSELATOR:
+    case ETD_RX_GRAY_SCOTT:
+    case ETD_RX_SCHNAKENBERG:
+    case ETD_RX_CGL: return 2;
+    case ETD_RX_LINEAR: return 0;  // any s
+    default: return -1;
+  }
+}
+
+int check_ws(const etd_rdp_ctx* c, const void* ws, size_t bytes) {
+  if (!ws) return ETD_ERR_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return ETD_ERR_WORKSPACE;
+  if (bytes < c->ws_bytes) return ETD_ERR_WORKSPACE;
+  return ETD_OK;
+}
+
+int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st) {
+  if (c->uploaded_ws == ws) return ETD_OK;
+  hipError_t e = hipMemcpyAsync(ws, c->tabs.data(), c->tabs.size() * sizeof(SolveTab),
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(c, e);
+  c->uploaded_ws = ws;
+  return ETD_OK;
+}
+
+Geom make_geom(const etd_rdp_ctx* c, int axis0) {
+  Geom g{};
+  const int64_t n1 = c->n[0], n2 = c->n[1];
+  g.N = c->N;
+  g.n = static_cast<int>(c->n[axis0]);
+  g.C = g.n / c->m[axis0];
+  g.logW = 4;  // kTileLines
+  g.pitch = g.n + 1;
+  if (axis0 == 1 && c->d == 3) {  // lines (x, z) along y
+    g.nF = n1;
+    g.nT = c->n[2];
+    g.sRow = n1;
+    g.sT = n1 * n2;
+  } else if (axis0 == 1) {  // 2-D, lines x along y
+    g.nF = n1;
+    g.nT = 1;
+    g.sRow = n1;
+    g.sT = 0;
+  } else {  // axis 3: lines (x, y) along z
+    g.nF = n1 * n2;
+    g.nT = 1;
+    g.sRow = n1 * n2;
+    g.sT = 0;
+  }
+  g.nFblk = (g.nF + kTileLines - 1) / kTileLines;
+  return g;
+}
+
+template <typename KernelT>
+hipError_t set_lds(KernelT kern, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(bytes));
+}
+
+// Launchers, templated on the chunk length and species count.
+template <int M, int S>
+hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
+                        double* w, const SolveTab* tabs, hipStream_t st) {
+  const int64_t nlines = c->N / c->n[0];
+  const int per = kFirstBlock / 64;
+  const int64_t blocks = (nlines + per - 1) / per;
+  hipLaunchKernelGGL((k_first<M, S>), dim3(static_cast<unsigned>(blocks)), dim3(kFirstBlock),
+                     0, st, u, c1, c2, w, tabs, c->rx, c->k, c->n[0], nlines, c->N,
+                     c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M, int S>
+hipError_t launch_mid(const etd_rdp_ctx* c, double* c1, double* c2, double* w,
+                      const SolveTab* tabs, const Geom& g, hipStream_t st) {
+  const size_t lds = sizeof(double) * (size_t)g.pitch * kTileLines;
+  hipError_t e = set_lds(k_mid<M, S>, lds);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = g.nFblk * g.nT;
+  hipLaunchKernelGGL((k_mid<M, S>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kTileLines),
+                     lds, st, c1, c2, w, tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M, int S>
+hipError_t launch_last(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
+                       const double* w, const SolveTab* tabs, const Geom& g, hipStream_t st) {
+  const size_t lds = sizeof(double) * (size_t)g.pitch * kTileLines;
+  hipError_t e = set_lds(k_last<M, S>, lds);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = g.nFblk * g.nT;
+  hipLaunchKernelGGL((k_last<M, S>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kTileLines),
+                     lds, st, u, c1, c2, w, tabs, c->rx, c->k, g,
+                     c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_solve(const etd_rdp_ctx* c, double* x, const SolveTab* tab, int axis0,
+                        hipStream_t st) {
+  if (axis0 == 0) {
+    const int64_t nlines = c->N / c->n[0];
+    const int per = kFirstBlock / 64;
+    const int64_t blocks = (nlines + per - 1) / per;
+    hipLaunchKernelGGL((k_solve_contig<M>), dim3(static_cast<unsigned>(blocks)), dim3(kFirstBlock),
+                       0, st, x, tab, c->n[0], nlines);
+    return hipGetLastError();
+  }
+  const Geom g = make_geom(c, axis0);
+  const size_t lds = sizeof(double) * (size_t)g.pitch * kTileLines;
+  hipError_t e = set_lds(k_solve_strided<M>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_solve_strided<M>), dim3(static_cast<unsigned>(g.nFblk * g.nT)),
+                     dim3(64 * kTileLines), lds, st, x, tab, g);
+  return hipGetLastError();
+}
+
+// Runtime (m, s) -> template dispatch.
+#define ETD_DISPATCH_M(m, CALL) \
+  switch (m) {                  \
+    case 1: { constexpr int M_ = 1; CALL; } break; \
+    case 2: { constexpr int M_ = 2; CALL; } break; \
+    case 3: { constexpr int M_ = 3; CALL; } break; \
+    case 4: { constexpr int M_ = 4; CALL; } break; \
+    case 5: { constexpr int M_ = 5; CALL; } break; \
+    case 6: { constexpr int M_ = 6; CALL; } break; \
+    case 7: { constexpr int M_ = 7; CALL; } break; \
+    case 8: { constexpr int M_ = 8; CALL; } break; \
+    default: return ETD_ERR_INTERNAL;               \
+  }
+
+int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  const SolveTab* tabs = static_cast<const SolveTab*>(ws);
+  double* c1 = reinterpret_cast<double*>(base + c->tab_bytes);
+  double* c2 = reinterpret_cast<double*>(base + c->tab_bytes + c->arr_bytes);
+  double* w = reinterpret_cast<double*>(base + c->tab_bytes + 2 * c->arr_bytes);
+  const int S = c->s;
+  hipError_t e = hipSuccess;
+  for (int p = first; p < npasses; ++p) {
+    const SolveTab* ta = tabs + tab_index(p, 0, 0, S);
+    const int m = c->m[p];
+    if (p == 0) {
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1>(c, u, c1, c2, w, ta, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2>(c, u, c1, c2, w, ta, st))); }
+    } else if (p == c->d - 1) {
+      const Geom g = make_geom(c, p);
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, c1, c2, w, ta, g, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, c1, c2, w, ta, g, st))); }
+    } else {
+      const Geom g = make_geom(c, p);
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, c1, c2, w, ta, g, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, c1, c2, w, ta, g, st))); }
+    }
+    if (e != hipSuccess) return hip_fail(c, e);
+  }
+  return ETD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* etd_rdp_status_string(int status) {
+  switch (status) {
+    case ETD_OK: return "ok";
+    case ETD_ERR_ARG: return "invalid argument";
+    case ETD_ERR_UNSUPPORTED: return "unsupported problem for this build";
+    case ETD_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case ETD_ERR_HIP: return "HIP runtime error";
+    case ETD_ERR_INTERNAL: return "internal table self-check failed";
+    default: return "unknown status";
+  }
+}
+
+int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, double k,
+                 const etd_scheme_t* scheme, const etd_reaction_t* rx, etd_rdp_ctx** out) {
+  if (!grid || !bc || !D || !rx || !out) return ETD_ERR_ARG;
+  *out = nullptr;
+  const int d = grid->d, s = grid->s;
+  if (d < 2 || d > 3) return ETD_ERR_ARG;
+  if (s < 1 || s > ETD_MAX_SPECIES) return ETD_ERR_ARG;
+  if (!(std::isfinite(k) && k > 0)) return ETD_ERR_ARG;
+  const int want_s = species_of_model(rx->model);
+  if (want_s < 0 || (want_s > 0 && want_s != s)) return ETD_ERR_ARG;
+  int sch = scheme ? scheme->scheme : ETD_SCHEME_RDP;
+  if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
+  for (int i = 0; i < s; ++i)
+    if (!(std::isfinite(D[i]) && D[i] >= 0)) return ETD_ERR_ARG;
+  for (int i = 0; i < ETD_MAX_PARAMS; ++i)
+    if (!std::isfinite(rx->params[i])) return ETD_ERR_ARG;
+  for (int i = 0; i < s; ++i)
+    if (!std::isfinite(rx->shift[i])) return ETD_ERR_ARG;
+
+  etd_rdp_ctx* c = new (std::nothrow) etd_rdp_ctx();
+  if (!c) return ETD_ERR_INTERNAL;
+  c->d = d;
+  c->s = s;
+  c->k = k;
+  c->scheme = sch;
+  int64_t N = 1;
+  for (int i = 0; i < d; ++i) {
+    const int64_t n = grid->n[i];
+    const int b = bc[i];
+    if (b < 0 || b > 2) { delete c; return ETD_ERR_ARG; }
+    const int64_t nmin = (b == ETD_BC_DIRICHLET) ? 1 : (b == ETD_BC_NEUMANN ? 2 : 3);
+    if (n < nmin) { delete c; return ETD_ERR_ARG; }
+    double h = grid->h[i];
+    if (h == 0.0) h = (b == ETD_BC_DIRICHLET) ? 1.0 / (n + 1) : (b == ETD_BC_NEUMANN ? 1.0 / (n - 1) : 1.0 / n);
+    if (!(std::isfinite(h) && h > 0)) { delete c; return ETD_ERR_ARG; }
+    const int m = choose_chunk(n);
+    if (m == 0) { delete c; return ETD_ERR_UNSUPPORTED; }
+    c->n[i] = n;
+    c->h[i] = h;
+    c->bc[i] = b;
+    c->m[i] = m;
+    N *= n;
+  }
+  c->N = N;
+  for (int i = 0; i < s; ++i) c->D[i] = D[i];
+  c->rx.model = rx->model;
+  for (int i = 0; i < 16; ++i) c->rx.p[i] = rx->params[i];
+  for (int i = 0; i < s; ++i) c->rx.shift[i] = rx->shift[i];
+
+  const double gam[3] = {1.0, 3.0, 4.0};
+  c->tabs.resize(static_cast<size_t>(d) * s * 3);
+  for (int a = 0; a < d; ++a)
+    for (int sp = 0; sp < s; ++sp)
+      for (int gi = 0; gi < 3; ++gi) {
+        std::string err;
+        if (!build_solve_table(c->n[a], c->bc[a], c->h[a], k * c->D[sp] / gam[gi], c->m[a],
+                               &c->tabs[tab_index(a, sp, gi, s)], &err)) {
+          std::fprintf(stderr, "etd_rdp_init: table (axis %d, species %d, gamma %g): %s\n",
+                       a + 1, sp, gam[gi], err.c_str());
+          delete c;
+          return ETD_ERR_INTERNAL;
+        }
+      }
+  c->tab_bytes = round_up(c->tabs.size() * sizeof(SolveTab), 256);
+  c->arr_bytes = round_up(sizeof(double) * static_cast<size_t>(N) * s, 256);
+  c->ws_bytes = c->tab_bytes + 3 * c->arr_bytes;
+  *out = c;
+  return ETD_OK;
+}
+
+int etd_rdp_destroy(etd_rdp_ctx* ctx) {
+  delete ctx;
+  return ETD_OK;
+}
+
+int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return ETD_ERR_ARG;
+  *bytes = ctx->ws_bytes;
+  return ETD_OK;
+}
+
+int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, size_t* off_c1, size_t* off_c2,
+                             size_t* off_w) {
+  if (!ctx || !off_c1 || !off_c2 || !off_w) return ETD_ERR_ARG;
+  *off_c1 = ctx->tab_bytes;
+  *off_c2 = ctx->tab_bytes + ctx->arr_bytes;
+  *off_w = ctx->tab_bytes + 2 * ctx->arr_bytes;
+  return ETD_OK;
+}
+
+int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m, int32_t* chunks) {
+  if (!ctx || !m || !chunks || axis < 1 || axis > ctx->d) return ETD_ERR_ARG;
+  *m = ctx->m[axis - 1];
+  *chunks = static_cast<int32_t>(ctx->n[axis - 1] / ctx->m[axis - 1]);
+  return ETD_OK;
+}
+
+int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int64_t nsteps,
+                 void* stream) {
+  if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  if (nsteps == 0) return ETD_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    rc = run_passes(ctx, u, ws, 0, ctx->d, st);
+    if (rc) return rc;
+  }
+  return ETD_OK;
+}
+
+int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
+                         int32_t npasses, void* stream) {
+  if (!ctx || !u || npasses < 1 || npasses > ctx->d) return ETD_ERR_ARG;
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  return run_passes(ctx, u, ws, 0, npasses, st);
+}
+
+int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int32_t pass,
+                     void* stream) {
+  if (!ctx || !u || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  return run_passes(ctx, u, ws, pass - 1, pass, st);
+}
+
+int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, int32_t axis,
+                        int32_t sigma, int32_t gamma, void* stream) {
+  if (!ctx || !x || axis < 1 || axis > ctx->d || sigma < 0 || sigma >= ctx->s) return ETD_ERR_ARG;
+  const int slot = gamma == 1 ? 0 : (gamma == 3 ? 1 : (gamma == 4 ? 2 : -1));
+  if (slot < 0) return ETD_ERR_ARG;
+  int rc = check_ws(ctx, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  const SolveTab* tab = static_cast<const SolveTab*>(ws) + tab_index(axis - 1, sigma, slot, ctx->s);
+  hipError_t e = hipSuccess;
+  ETD_DISPATCH_M(ctx->m[axis - 1], e = launch_solve<M_>(ctx, x, tab, axis - 1, st));
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  return ETD_OK;
+}
+
+int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+}  // extern "C"

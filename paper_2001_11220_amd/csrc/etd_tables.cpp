@@ -1,0 +1,370 @@
+// Host construction of the line-solve tables (see etd_tables.hpp).
+//
+// The line matrix is I + coef * B_p with B_p from Example 1 of the paper.  The
+// tables encode an exact block elimination: chunk interiors are eliminated
+// with their (shared) Thomas factors and the separators solve the Schur
+// complement.  The Schur complement is assembled from the stencil below, so
+// the same code covers the three boundary conditions; the structure the GPU
+// kernels assume is then checked entry by entry, and the residual of the
+// whole chunked algorithm is checked on random right-hand sides.
+#include "etd_tables.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <utility>
+
+namespace etd {
+
+int choose_chunk(int64_t n) {
+  if (n < 1) return 0;
+  for (int m = 1; m <= kMaxM; ++m)
+    if (n % m == 0 && n / m <= kLanes) return m;
+  return 0;
+}
+
+namespace {
+
+using Entries = std::map<int64_t, double>;  // unknown index -> coefficient
+
+// The linear system on one line, with a ghost unknown (index -1) for the
+// Neumann reflection at row 0 so that row 0 keeps the interior stencil.
+struct LineSystem {
+  int64_t n;
+  int bc;
+  double r, delta;
+  bool ghost;
+
+  // Coefficients of equation e (-1 = ghost equation x_{-1} - x_1 = 0).
+  Entries eq(int64_t e) const {
+    Entries out;
+    if (e == -1) {
+      out[-1] += 1.0;
+      out[1] += -1.0;
+      return out;
+    }
+    out[e] += delta;
+    if (e > 0) {
+      out[e - 1] += -r;
+    } else if (bc == 1) {
+      out[-1] += -r;  // ghost x_{-1} = x_1
+    } else if (bc == 2) {
+      out[n - 1] += -r;  // periodic wrap
+    }
+    if (e < n - 1) {
+      out[e + 1] += -r;
+    } else if (bc == 1) {
+      out[n - 2] += -r;  // reflected x_n = x_{n-2}
+    } else if (bc == 2) {
+      out[0] += -r;
+    }
+    return out;
+  }
+};
+
+struct Split {
+  int64_t n;
+  int m, C, g;  // g = 1 if a ghost separator comes first
+  bool is_sep(int64_t u) const { return u == -1 || (u % m) == m - 1; }
+  int sep_index(int64_t u) const {
+    return u == -1 ? 0 : g + static_cast<int>(u / m);
+  }
+  int chunk(int64_t u) const { return static_cast<int>(u / m); }
+  int slot(int64_t u) const { return static_cast<int>(u % m); }
+};
+
+// Dense tridiagonal solve without pivoting (diagonally dominant input).
+void thomas(std::vector<double> a, std::vector<double> b, std::vector<double> c,
+            std::vector<double>& x) {
+  const size_t N = b.size();
+  for (size_t i = 1; i < N; ++i) {
+    double w = a[i] / b[i - 1];
+    b[i] -= w * c[i - 1];
+    x[i] -= w * x[i - 1];
+  }
+  x[N - 1] /= b[N - 1];
+  for (size_t i = N - 1; i-- > 0;) x[i] = (x[i] - c[i] * x[i + 1]) / b[i];
+}
+
+// The device algorithm, executed on the host for the residual self-check.
+void emulate(const SolveTab& t, const double* b, double* x) {
+  const int m = t.m, C = t.C, q = m - 1;
+  double g[kLanes][kMaxM] = {};
+  double d[kLanes] = {};
+  for (int c = 0; c < C; ++c) {
+    const double* bc = b + static_cast<int64_t>(c) * m;
+    if (q > 0) {
+      double y[kMaxM];
+      y[0] = bc[0] * t.ip[0];
+      for (int j = 1; j < q; ++j) y[j] = (bc[j] + t.r * y[j - 1]) * t.ip[j];
+      g[c][q - 1] = y[q - 1];
+      for (int j = q - 1; j-- > 0;) g[c][j] = y[j] + t.cp[j] * g[c][j + 1];
+    }
+  }
+  for (int c = 0; c < C; ++c) {
+    const int cn = (c + 1 == C) ? 0 : c + 1;
+    double v = b[static_cast<int64_t>(c) * m + m - 1];
+    if (q > 0) v += t.wl[c] * g[c][q - 1] + t.wr[c] * g[cn][0];
+    if (q > 1) v += t.wg[c] * g[c][1];
+    d[c] = v;
+  }
+  for (int st = 0; st < t.npcr; ++st) {
+    const int s = 1 << st;
+    double nd[kLanes];
+    for (int c = 0; c < C; ++c) {
+      double dm = (c - s >= 0) ? d[c - s] : 0.0;
+      double dp = (c + s < C) ? d[c + s] : 0.0;
+      nd[c] = d[c] - t.k1[st][c] * dm - t.k2[st][c] * dp;
+    }
+    std::memcpy(d, nd, sizeof(double) * C);
+  }
+  double s[kLanes];
+  for (int c = 0; c < C; ++c) s[c] = d[c] * t.inv[c];
+  if (t.sm) {
+    const double vy = s[0] + t.vfac * s[C - 1];
+    for (int c = 0; c < C; ++c) s[c] -= vy * t.smfac * t.z[c];
+  }
+  for (int c = 0; c < C; ++c) {
+    double sl;
+    if (c > 0) {
+      sl = s[c - 1];
+    } else {
+      sl = t.gh0 * s[0] + t.ghw * s[C - 1] + (q > 1 ? t.ghd * g[0][1] : 0.0);
+    }
+    double* xc = x + static_cast<int64_t>(c) * m;
+    for (int j = 0; j < q; ++j) xc[j] = g[c][j] + sl * t.al[j] + s[c] * t.be[j];
+    xc[m - 1] = s[c];
+  }
+}
+
+}  // namespace
+
+bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
+                       SolveTab* out, std::string* err) {
+  auto fail = [&](const std::string& why) {
+    if (err) *err = why;
+    return false;
+  };
+  if (m < 1 || m > kMaxM || n % m != 0 || n / m > kLanes || n < 1)
+    return fail("bad chunking");
+  std::memset(static_cast<void*>(out), 0, sizeof(SolveTab));
+  const double r = coef / (h * h);
+  LineSystem L{n, bc, r, 1.0 + 2.0 * r, bc == 1};
+  Split S{n, m, static_cast<int>(n / m), L.ghost ? 1 : 0};
+  const int C = S.C, q = m - 1, Cx = C + S.g;
+  SolveTab& t = *out;
+  t.r = r;
+  t.C = C;
+  t.m = m;
+
+  // Interior factors of T = tridiag(-r, 1+2r, -r) of size q.
+  std::vector<std::vector<double>> Tinv(q, std::vector<double>(q, 0.0));
+  if (q > 0) {
+    double p = L.delta;
+    for (int j = 0; j < q; ++j) {
+      if (j > 0) p = L.delta - r * r / p;
+      t.ip[j] = 1.0 / p;
+      t.cp[j] = r * t.ip[j];
+    }
+    for (int col = 0; col < q; ++col) {
+      std::vector<double> a(q, -r), b(q, L.delta), c(q, -r), x(q, 0.0);
+      x[col] = 1.0;
+      thomas(a, b, c, x);
+      for (int j = 0; j < q; ++j) Tinv[j][col] = x[j];
+    }
+    for (int j = 0; j < q; ++j) {
+      t.al[j] = r * Tinv[j][0];
+      t.be[j] = r * Tinv[j][q - 1];
+    }
+  }
+
+  // Assemble E_SS and collect E_IS / E_SI per chunk.
+  std::vector<std::vector<double>> Mx(Cx, std::vector<double>(Cx, 0.0));
+  struct Ent { int slot; int sep; double v; };
+  std::vector<std::vector<Ent>> EIS(C), ESI(C);  // per chunk
+  auto all_eqs = [&](auto&& fn) {
+    if (L.ghost) fn(int64_t(-1));
+    for (int64_t e = 0; e < n; ++e) fn(e);
+  };
+  bool bad = false;
+  std::string why;
+  all_eqs([&](int64_t e) {
+    Entries row = L.eq(e);
+    if (S.is_sep(e)) {
+      const int p = S.sep_index(e);
+      for (auto& kv : row) {
+        if (S.is_sep(kv.first)) Mx[p][S.sep_index(kv.first)] += kv.second;
+        else ESI[S.chunk(kv.first)].push_back({S.slot(kv.first), p, kv.second});
+      }
+    } else {
+      const int c = S.chunk(e), j = S.slot(e);
+      for (auto& kv : row) {
+        if (S.is_sep(kv.first)) {
+          EIS[c].push_back({j, S.sep_index(kv.first), kv.second});
+        } else {
+          // interior-interior coupling must be the shared T block
+          const int c2 = S.chunk(kv.first), j2 = S.slot(kv.first);
+          double want = (j2 == j) ? L.delta : -r;
+          if (c2 != c || std::abs(j2 - j) > 1 || kv.second != want) {
+            bad = true;
+            why = "interior block is not the shared tridiagonal";
+          }
+        }
+      }
+    }
+  });
+  if (bad) return fail(why);
+
+  // Expected interior-to-separator couplings: slot 0 to the left separator
+  // (previous chunk, ghost, periodic wrap, or none) and slot q-1 to the own
+  // separator, both -r.  These are what the spikes al/be encode.
+  for (int c = 0; c < C && q > 0; ++c) {
+    std::map<std::pair<int, int>, double> got;
+    for (auto& en : EIS[c]) got[{en.slot, en.sep}] += en.v;
+    std::map<std::pair<int, int>, double> want;
+    int left = -2;
+    if (c > 0) left = S.g + c - 1;
+    else if (bc == 1) left = 0;
+    else if (bc == 2) left = S.g + C - 1;
+    if (left >= 0) want[{0, left}] += -r;
+    want[{q - 1, S.g + c}] += -r;
+    if (got != want) return fail("unexpected interior-separator coupling");
+  }
+
+  // Schur complement Mx -= E_SI T^{-1} E_IS.
+  for (int c = 0; c < C; ++c)
+    for (auto& a : ESI[c])
+      for (auto& b : EIS[c])
+        Mx[a.sep][b.sep] -= a.v * Tinv[a.slot][b.slot] * b.v;
+
+  // Reduced right-hand-side weights.
+  double cg = 0.0;  // ghost equation: d_g = cg * g_0[1]
+  for (int c = 0; c < C; ++c) {
+    for (auto& a : ESI[c]) {
+      const int p = a.sep;
+      if (L.ghost && p == 0) {
+        if (c != 0 || a.slot != 1) return fail("unexpected ghost coupling");
+        cg += -a.v;
+        continue;
+      }
+      const int sc = p - S.g;  // separator's chunk
+      const int cn = (sc + 1 == C) ? 0 : sc + 1;
+      if (c == sc && a.slot == q - 1 && !(c == cn && a.slot == 0)) {
+        t.wl[sc] += -a.v;
+      } else if (c == cn && a.slot == 0 && c != sc) {
+        t.wr[sc] += -a.v;
+      } else {
+        return fail("unexpected separator-interior coupling");
+      }
+    }
+  }
+
+  // Eliminate the Neumann ghost separator.
+  std::vector<std::vector<double>> Mr(C, std::vector<double>(C, 0.0));
+  if (L.ghost) {
+    const double pg = Mx[0][0];
+    for (int i = 0; i < C; ++i)
+      for (int j = 0; j < C; ++j)
+        Mr[i][j] = Mx[i + 1][j + 1] - Mx[i + 1][0] * Mx[0][j + 1] / pg;
+    for (int i = 1; i < C; ++i)
+      if (Mx[i + 1][0] != 0.0) return fail("ghost couples beyond separator 0");
+    t.wg[0] = -(Mx[1][0] / pg) * cg;
+    t.ghd = cg / pg;
+    t.gh0 = -Mx[0][1] / pg;
+    if (q > 0)
+      for (int j = 1; j < C; ++j)
+        if (Mx[0][j + 1] != 0.0) return fail("ghost row couples beyond s_0");
+  } else {
+    Mr = Mx;
+    if (bc == 2) t.ghw = 1.0;
+  }
+
+  // Reduced matrix must be tridiagonal plus (periodic) two corners.
+  double scale = 0.0;
+  for (auto& row : Mr) for (double v : row) scale = std::max(scale, std::abs(v));
+  double ctop = 0.0, cbot = 0.0;
+  for (int i = 0; i < C; ++i)
+    for (int j = 0; j < C; ++j) {
+      if (std::abs(i - j) <= 1) continue;
+      const bool corner = (i == 0 && j == C - 1) || (i == C - 1 && j == 0);
+      if (corner && bc == 2) continue;
+      if (std::abs(Mr[i][j]) > 1e-14 * scale)
+        return fail("reduced matrix is not tridiagonal");
+    }
+  std::vector<double> ra(C, 0.0), rb(C, 0.0), rc(C, 0.0);
+  for (int i = 0; i < C; ++i) {
+    rb[i] = Mr[i][i];
+    if (i > 0) ra[i] = Mr[i][i - 1];
+    if (i + 1 < C) rc[i] = Mr[i][i + 1];
+  }
+  if (bc == 2 && C >= 3) {
+    ctop = Mr[0][C - 1];
+    cbot = Mr[C - 1][0];
+    const double gam = -rb[0];
+    rb[0] -= gam;
+    rb[C - 1] -= cbot * ctop / gam;
+    std::vector<double> u(C, 0.0);
+    u[0] = gam;
+    u[C - 1] = cbot;
+    thomas(ra, rb, rc, u);
+    for (int i = 0; i < C; ++i) t.z[i] = u[i];
+    t.vfac = ctop / gam;
+    t.smfac = 1.0 / (1.0 + t.z[0] + t.vfac * t.z[C - 1]);
+    t.sm = 1;
+  }
+
+  // Parallel cyclic reduction coefficients on the (non-cyclic) reduced matrix.
+  int npcr = 0;
+  while ((1 << npcr) < C) ++npcr;
+  t.npcr = npcr;
+  for (int st = 0; st < npcr; ++st) {
+    const int s = 1 << st;
+    std::vector<double> na(C, 0.0), nb(C, 0.0), nc(C, 0.0);
+    for (int i = 0; i < C; ++i) {
+      double k1 = (i - s >= 0) ? ra[i] / rb[i - s] : 0.0;
+      double k2 = (i + s < C) ? rc[i] / rb[i + s] : 0.0;
+      t.k1[st][i] = k1;
+      t.k2[st][i] = k2;
+      nb[i] = rb[i] - ((i - s >= 0) ? k1 * rc[i - s] : 0.0) -
+              ((i + s < C) ? k2 * ra[i + s] : 0.0);
+      na[i] = (i - s >= 0) ? -k1 * ra[i - s] : 0.0;
+      nc[i] = (i + s < C) ? -k2 * rc[i + s] : 0.0;
+    }
+    ra.swap(na);
+    rb.swap(nb);
+    rc.swap(nc);
+  }
+  for (int i = 0; i < C; ++i) t.inv[i] = 1.0 / rb[i];
+
+  // Residual self-check of the chunked algorithm on the original line matrix.
+  uint64_t state = 0x9E3779B97F4A7C15ull ^ static_cast<uint64_t>(n * 131 + bc);
+  std::vector<double> b(n), x(n);
+  for (int trial = 0; trial < 2; ++trial) {
+    for (int64_t i = 0; i < n; ++i) {
+      state = state * 6364136223846793005ull + 1442695040888963407ull;
+      b[i] = static_cast<double>(state >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    emulate(t, b.data(), x.data());
+    double rmax = 0.0, bmax = 0.0, xmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double lhs = L.delta * x[i];
+      double xl = 0.0, xr = 0.0;
+      if (i > 0) xl = x[i - 1];
+      else if (bc == 1) xl = (n > 1) ? x[1] : 0.0;
+      else if (bc == 2) xl = x[n - 1];
+      if (i < n - 1) xr = x[i + 1];
+      else if (bc == 1) xr = (n > 1) ? x[n - 2] : 0.0;
+      else if (bc == 2) xr = x[0];
+      lhs -= r * (xl + xr);
+      rmax = std::max(rmax, std::abs(lhs - b[i]));
+      bmax = std::max(bmax, std::abs(b[i]));
+      xmax = std::max(xmax, std::abs(x[i]));
+    }
+    if (!(rmax <= 1e-10 * (bmax + (1.0 + 4.0 * r) * xmax)))
+      return fail("residual self-check failed");
+  }
+  return true;
+}
+
+}  // namespace etd

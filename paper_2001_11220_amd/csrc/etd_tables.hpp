@@ -1,0 +1,79 @@
+// Line-solve tables for the shifted 1-D diffusion systems of the ETD-RDP-IF
+// scheme (Section 7 of the paper: (I + (k/gamma) D_sigma B_p) x = b along a
+// grid line, gamma in {1, 3, 4}).
+//
+// Solver layout (one wavefront per line, lane c owns chunk c):
+//   The line of n = C*m rows is cut into C <= 64 chunks of m <= 8 rows.  The
+//   last row of every chunk is a "separator"; the other m-1 rows are the
+//   chunk's interior.  Interior blocks are all the same constant-coefficient
+//   tridiagonal T = tridiag(-r, 1+2r, -r) whatever the boundary condition:
+//   the Neumann reflection at row 0 is carried by a ghost unknown x_{-1} = x_1
+//   and the periodic wrap by a coupling to the last separator, so all the
+//   boundary information ends up in the small reduced (Schur complement)
+//   system on the separators.
+//
+//   1. local solve   g = T^{-1} b_interior                 (Thomas, uniform)
+//   2. reduced RHS   d_c = b_sep + wl_c g_c[m-2] + wr_c g_{c+1}[0] + wg_c g_c[1]
+//   3. reduced solve s = Mred^{-1} d  by parallel cyclic reduction across the
+//      64 lanes (per-lane coefficients), plus a Sherman-Morrison rank-one
+//      correction when the reduced system is cyclic (periodic lines)
+//   4. correction    x_j = g_j + sl_c alpha_j + s_c beta_j,   x_sep = s_c
+//      with sl_c = s_{c-1} (c > 0) or the boundary ghost value for c = 0.
+//
+// Everything in this header is plain host C++ so it can be unit-tested
+// without a GPU; the device code reads the same POD structs.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace etd {
+
+constexpr int kMaxM = 8;       // max rows per chunk
+constexpr int kLanes = 64;     // wavefront width
+constexpr int kMaxPcr = 6;     // log2(64)
+
+// One line-solve operator (axis, species, gamma).  POD, 256-byte multiple,
+// copied verbatim to device memory.
+struct alignas(256) SolveTab {
+  // Wave-uniform chunk-interior factors, index j < m-1.
+  double ip[kMaxM];   // inverse pivots of T
+  double cp[kMaxM];   // back-substitution multipliers r * ip[j]
+  double al[kMaxM];   // left spike  r T^{-1} e_0
+  double be[kMaxM];   // right spike r T^{-1} e_{m-2}
+  double r;           // off-diagonal magnitude k D / (gamma h^2)
+  double ghd;         // lane 0 ghost: sl_0 = ghd g_0[1] + gh0 s_0 + ghw s_{C-1}
+  double gh0;
+  double ghw;
+  double vfac;        // Sherman-Morrison: v = e_0 + vfac e_{C-1}
+  double smfac;       // 1 / (1 + v.z); 0 when the reduced system is not cyclic
+  int32_t C;          // number of chunks (active lanes)
+  int32_t m;          // rows per chunk
+  int32_t npcr;       // PCR steps = ceil(log2 C)
+  int32_t sm;         // 1 if the Sherman-Morrison correction is applied
+  double pad0[2];
+  // Per-lane data, structure-of-arrays (index = lane).
+  double k1[kMaxPcr][kLanes];  // PCR multipliers of the lane-s neighbour
+  double k2[kMaxPcr][kLanes];  // PCR multipliers of the lane+s neighbour
+  double inv[kLanes];          // 1 / reduced diagonal after the last step
+  double wl[kLanes];           // reduced-RHS weights (step 2)
+  double wr[kLanes];
+  double wg[kLanes];
+  double z[kLanes];            // Sherman-Morrison vector Mred'^{-1} u
+};
+
+// Pick the chunk length for a line of n rows: the smallest m <= kMaxM that
+// divides n with n / m <= kLanes.  Returns 0 if none exists.
+int choose_chunk(int64_t n);
+
+// Build the table of (I + coef * B_p) on n rows with boundary condition bc
+// (0 Dirichlet, 1 Neumann, 2 periodic) and spacing h, coef = k D / gamma.
+// Uses chunk length m (n % m == 0, n / m <= 64).  Checks the structure the
+// device code relies on and, on random right-hand sides, the residual of the
+// chunked algorithm the tables encode; returns false and sets *err if a
+// check fails.
+bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
+                       SolveTab* out, std::string* err);
+
+}  // namespace etd

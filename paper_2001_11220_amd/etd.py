@@ -1,0 +1,234 @@
+"""ctypes binding of ``libetdrdp.so`` (the C ABI in ``include/etd_rdp.h``).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the scheme runs in the library's kernels.
+Importing this module loads the library and raises if it is missing, so no
+caller can silently fall back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libetdrdp.so")
+
+ETD_OK = 0
+ETD_ERR_ARG = -1
+ETD_ERR_UNSUPPORTED = -2
+ETD_ERR_WORKSPACE = -3
+ETD_ERR_HIP = -4
+ETD_ERR_INTERNAL = -5
+
+BC = {"dirichlet": 0, "neumann": 1, "periodic": 2}
+MODELS = {"linear": 0, "enzyme": 1, "brusselator": 2, "gray_scott": 3,
+          "schnakenberg": 4, "cgl": 5}
+# parameter order of each model in etd_reaction_t.params
+MODEL_PARAMS = {"enzyme": (), "brusselator": ("a", "b"), "gray_scott": ("F", "kappa"),
+                "schnakenberg": ("a", "b", "gamma"), "cgl": ("beta",)}
+SCHEMES = {"rdp": 0, "etd1": 1}
+
+MAX_DIM, MAX_SPECIES, MAX_PARAMS = 3, 2, 16
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("s", ctypes.c_int32),
+                ("n", ctypes.c_int64 * MAX_DIM), ("h", ctypes.c_double * MAX_DIM)]
+
+
+class Reaction(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("params", ctypes.c_double * MAX_PARAMS),
+                ("shift", ctypes.c_double * MAX_SPECIES)]
+
+
+class Scheme(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class EtdError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built; run `python -m paper_2001_11220_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "etd_rdp_init": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(I32), ctypes.POINTER(D), D,
+                                        ctypes.POINTER(Scheme), ctypes.POINTER(Reaction), ctypes.POINTER(P)]),
+        "etd_rdp_destroy": (ctypes.c_int, [P]),
+        "etd_rdp_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
+        "etd_rdp_workspace_layout": (ctypes.c_int, [P, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
+        "etd_rdp_step": (ctypes.c_int, [P, P, P, SZ, I64, P]),
+        "etd_rdp_debug_passes": (ctypes.c_int, [P, P, P, SZ, I32, P]),
+        "etd_rdp_run_pass": (ctypes.c_int, [P, P, P, SZ, I32, P]),
+        "etd_rdp_apply_solve": (ctypes.c_int, [P, P, P, SZ, I32, I32, I32, P]),
+        "etd_rdp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "etd_rdp_last_hip_error": (ctypes.c_int, [P]),
+        "etd_rdp_line_split": (ctypes.c_int, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_string(status: int) -> str:
+    return lib.etd_rdp_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != ETD_OK:
+        raise EtdError(status, what)
+
+
+def reaction_struct(model: str, params: dict, shift: Optional[Sequence[float]] = None,
+                    s: int = 2) -> Reaction:
+    rx = Reaction()
+    rx.model = MODELS[model]
+    if model == "linear":
+        C = params["C"]
+        flat = [float(v) for row in (C if hasattr(C[0], "__len__") else [C]) for v in row]
+        for i, v in enumerate(flat):
+            rx.params[i] = v
+    else:
+        for i, key in enumerate(MODEL_PARAMS[model]):
+            rx.params[i] = float(params[key])
+    sh = shift if shift is not None else params.get("shift")
+    if sh is not None:
+        for i, v in enumerate(sh):
+            rx.shift[i] = float(v)
+    return rx
+
+
+class EtdRdp:
+    """One ETD-RDP-IF problem on the GPU.
+
+    ``shape`` is ``(n_1, ..., n_d)`` (axis 1 first); states are torch float64
+    tensors of shape ``(s, n_d, ..., n_1)`` on a HIP device.  ``h`` entries of
+    0 (or ``None``) select the unit-domain spacing of each boundary condition.
+    """
+
+    def __init__(self, shape, bcs, D, k, model, params, h=None, shift=None,
+                 scheme="rdp", device=None):
+        d = len(shape)
+        s = len(D)
+        g = Grid()
+        g.d, g.s = d, s
+        for i in range(d):
+            g.n[i] = int(shape[i])
+            g.h[i] = float(h[i]) if h is not None and h[i] is not None else 0.0
+        bc_arr = (ctypes.c_int32 * MAX_DIM)(*[BC[b] if isinstance(b, str) else int(b) for b in bcs],
+                                            *([0] * (MAX_DIM - d)))
+        D_arr = (ctypes.c_double * MAX_SPECIES)(*[float(v) for v in D], *([0.0] * (MAX_SPECIES - s)))
+        sch = Scheme()
+        sch.scheme = SCHEMES[scheme]
+        rx = reaction_struct(model, params, shift, s)
+        ctx = ctypes.c_void_p()
+        _check(lib.etd_rdp_init(ctypes.byref(g), bc_arr, D_arr, float(k), ctypes.byref(sch),
+                                ctypes.byref(rx), ctypes.byref(ctx)), "etd_rdp_init")
+        self._ctx = ctx
+        self.shape, self.s, self.d = tuple(int(v) for v in shape), s, d
+        nb = ctypes.c_size_t()
+        _check(lib.etd_rdp_workspace_bytes(ctx, ctypes.byref(nb)), "etd_rdp_workspace_bytes")
+        self.ws_bytes = nb.value
+        self._ws = None
+        self._device = device
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib.etd_rdp_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        self.close()
+
+    # -- workspace ----------------------------------------------------------
+    def workspace(self):
+        """Device workspace (a torch uint8 tensor owned by this object)."""
+        import torch
+        if self._ws is None:
+            dev = self._device if self._device is not None else torch.device("cuda", torch.cuda.current_device())
+            self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        return self._ws
+
+    def _ws_ptr(self):
+        ws = self.workspace()
+        p = ws.data_ptr()
+        return p + (-p) % 256
+
+    def layout(self):
+        a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib.etd_rdp_workspace_layout(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "etd_rdp_workspace_layout")
+        return a.value, b.value, c.value
+
+    def carried(self):
+        """Views (c1, c2, w) of the carried arrays inside the workspace."""
+        import torch
+        ws = self.workspace()
+        base = self._ws_ptr() - ws.data_ptr()
+        n = self.s
+        for v in self.shape:
+            n *= v
+        out = []
+        for off in self.layout():
+            t = ws[base + off: base + off + 8 * n].view(torch.float64)
+            out.append(t.view((self.s,) + self.shape[::-1]))
+        return tuple(out)
+
+    def line_split(self, axis):
+        m, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.etd_rdp_line_split(self._ctx, axis, ctypes.byref(m), ctypes.byref(c)), "etd_rdp_line_split")
+        return m.value, c.value
+
+    # -- compute ------------------------------------------------------------
+    def _state_ptr(self, u, nspecies):
+        import torch
+        want = (nspecies,) + self.shape[::-1]
+        if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous() or tuple(u.shape) != want:
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {want}")
+        return u.data_ptr()
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(st.cuda_stream)
+
+    def step(self, u, nsteps=1, stream=None):
+        """Advance ``u`` in place by ``nsteps`` steps (asynchronous)."""
+        p = self._state_ptr(u, self.s)
+        _check(lib.etd_rdp_step(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                                self.ws_bytes, int(nsteps), self._stream(stream)), "etd_rdp_step")
+        return u
+
+    def debug_passes(self, u, npasses, stream=None):
+        p = self._state_ptr(u, self.s)
+        _check(lib.etd_rdp_debug_passes(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                                        self.ws_bytes, int(npasses), self._stream(stream)),
+               "etd_rdp_debug_passes")
+
+    def run_pass(self, u, npass, stream=None):
+        """Run pass ``npass`` (1..d) of a step alone (kernel timing)."""
+        p = self._state_ptr(u, self.s)
+        _check(lib.etd_rdp_run_pass(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                                    self.ws_bytes, int(npass), self._stream(stream)), "etd_rdp_run_pass")
+
+    def apply_solve(self, x, axis, sigma, gamma, stream=None):
+        p = self._state_ptr(x, 1)
+        _check(lib.etd_rdp_apply_solve(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                                       self.ws_bytes, int(axis), int(sigma), int(gamma),
+                                       self._stream(stream)), "etd_rdp_apply_solve")
+        return x

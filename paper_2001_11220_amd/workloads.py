@@ -1,0 +1,149 @@
+"""Seeded synthetic workloads (problem definitions and initial data).
+
+This module holds no arithmetic of the scheme: it only states the problems
+(grid, boundary conditions, coefficients, reaction parameters, step count)
+and draws their initial data from ``numpy.random.default_rng(seed)``.  The
+same arrays feed the GPU library and the CPU oracle.
+
+Workloads (the paper uses no external dataset; these stand in for the
+benchmark configurations of the build):
+
+* ``brusselator2d``   2-D Brusselator a=1, b=3.4, D=(0.02, 0.02), n=64^2,
+  Neumann (h = 1/63), k = 0.01, 100 steps, u, v = 0.5 + 0.1 U[0,1).
+* ``grayscott3d``     3-D Gray-Scott F=0.04, kappa=0.06, D=(2e-5, 1e-5),
+  n=256^3 periodic (h = 1/256), k = 1, 500 steps; u = 1, v = 0 except a
+  centred cube of side n/8 with u = 1 - 0.25 xi, v = 0.25 xi'.
+* ``schnakenberg3d``  3-D Schnakenberg a=0.1, b=0.9, gamma=1, D=(1, 10),
+  n=512^3, homogeneous Dirichlet on w = u - u* with u* = (a+b, b/(a+b)^2)
+  (h = 1/513), k = 1e-4, 200 steps, w = 1e-3 N(0,1).
+* ``schnakenberg3d_adjoint``  128^3 Neumann (h = 1/127), k = 1e-3, 400 steps,
+  u = u* + 1e-3 N(0,1) (unshifted).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    name: str
+    shape: Tuple[int, ...]          # (n_1, ..., n_d)
+    bcs: Tuple[str, ...]            # per axis
+    D: Tuple[float, ...]
+    k: float
+    model: str
+    params: Dict[str, float]
+    nsteps: int
+    h: Optional[Tuple[float, ...]] = None   # None: unit-domain default
+    shift: Optional[Tuple[float, ...]] = None
+    seed: int = 0
+    ic: str = "uniform_noise"
+    ic_args: Dict[str, float] = field(default_factory=dict)
+
+    @property
+    def s(self) -> int:
+        return len(self.D)
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.shape))
+
+    def state_shape(self) -> Tuple[int, ...]:
+        return (self.s,) + tuple(self.shape[::-1])
+
+    def hs(self) -> Tuple[float, ...]:
+        out = []
+        for i, (n, b) in enumerate(zip(self.shape, self.bcs)):
+            if self.h is not None and self.h[i]:
+                out.append(float(self.h[i]))
+            elif b == "dirichlet":
+                out.append(1.0 / (n + 1))
+            elif b == "neumann":
+                out.append(1.0 / (n - 1))
+            else:
+                out.append(1.0 / n)
+        return tuple(out)
+
+    def oracle_params(self) -> Dict[str, float]:
+        p = dict(self.params)
+        if self.shift is not None:
+            p["shift"] = list(self.shift)
+        return p
+
+    def initial(self) -> np.ndarray:
+        return initial_data(self)
+
+
+def initial_data(p: Problem) -> np.ndarray:
+    """Seeded initial state of shape ``(s, n_d, ..., n_1)`` (float64)."""
+    rng = np.random.default_rng(p.seed)
+    shp = p.state_shape()
+    if p.ic == "uniform_noise":
+        base = p.ic_args.get("base", 0.5)
+        amp = p.ic_args.get("amp", 0.1)
+        return np.stack([base + amp * rng.random(shp[1:]) for _ in range(p.s)])
+    if p.ic == "gaussian_noise":
+        amp = p.ic_args.get("amp", 1e-3)
+        out = amp * rng.standard_normal(shp)
+        if "offset" in p.ic_args:
+            off = p.ic_args["offset"]
+            for i in range(p.s):
+                out[i] += off[i]
+        return out
+    if p.ic == "cube_patch":
+        amp = p.ic_args.get("amp", 0.25)
+        u = np.ones(shp[1:])
+        v = np.zeros(shp[1:])
+        sl = []
+        for n in shp[1:]:
+            side = max(1, n // 8)
+            lo = (n - side) // 2
+            sl.append(slice(lo, lo + side))
+        sl = tuple(sl)
+        pshape = u[sl].shape
+        u[sl] = 1.0 - amp * rng.random(pshape)
+        v[sl] = amp * rng.random(pshape)
+        return np.stack([u, v])
+    raise ValueError(p.ic)
+
+
+def brusselator2d(n: int = 64, nsteps: int = 100, seed: int = 0) -> Problem:
+    return Problem("brusselator2d", (n, n), ("neumann", "neumann"), (0.02, 0.02), 0.01,
+                   "brusselator", {"a": 1.0, "b": 3.4}, nsteps, seed=seed,
+                   ic="uniform_noise", ic_args={"base": 0.5, "amp": 0.1})
+
+
+def grayscott3d(n: int = 256, nsteps: int = 500, seed: int = 0, shape=None) -> Problem:
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    return Problem("grayscott3d", shape, ("periodic",) * 3, (2e-5, 1e-5), 1.0,
+                   "gray_scott", {"F": 0.04, "kappa": 0.06}, nsteps, seed=seed,
+                   ic="cube_patch", ic_args={"amp": 0.25})
+
+
+SCHNAK = {"a": 0.1, "b": 0.9, "gamma": 1.0}
+SCHNAK_STEADY = (SCHNAK["a"] + SCHNAK["b"], SCHNAK["b"] / (SCHNAK["a"] + SCHNAK["b"]) ** 2)
+
+
+def schnakenberg3d(n: int = 512, nsteps: int = 200, seed: int = 0, shape=None) -> Problem:
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    return Problem("schnakenberg3d", shape, ("dirichlet",) * 3, (1.0, 10.0), 1e-4,
+                   "schnakenberg", dict(SCHNAK), nsteps, shift=SCHNAK_STEADY, seed=seed,
+                   ic="gaussian_noise", ic_args={"amp": 1e-3})
+
+
+def schnakenberg3d_adjoint(n: int = 128, nsteps: int = 400, seed: int = 0) -> Problem:
+    return Problem("schnakenberg3d_adjoint", (n, n, n), ("neumann",) * 3, (1.0, 10.0), 1e-3,
+                   "schnakenberg", dict(SCHNAK), nsteps, seed=seed, ic="gaussian_noise",
+                   ic_args={"amp": 1e-3, "offset": SCHNAK_STEADY})
+
+
+WORKLOADS = {
+    "brusselator2d": brusselator2d,
+    "grayscott3d": grayscott3d,
+    "schnakenberg3d": schnakenberg3d,
+    "schnakenberg3d_adjoint": schnakenberg3d_adjoint,
+}

@@ -1,0 +1,118 @@
+"""Host-side tests of the C ABI: the library loads, exports every declared
+entry point, validates arguments and builds self-checked line-solve tables.
+No HIP call is made (etd_rdp_init is host-only)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2001_11220_amd import etd
+    return etd
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(etd_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    etd = _lib()
+    names = _declared_functions()
+    assert "etd_rdp_init" in names and "etd_rdp_step" in names
+    for n in sorted(names):
+        assert hasattr(etd.lib, n), n
+
+
+def _init(shape, bcs, D=(0.1, 0.2), k=0.01, model="brusselator", params=None, h=None, scheme="rdp"):
+    etd = _lib()
+    params = params if params is not None else {"a": 1.0, "b": 3.0}
+    return etd.EtdRdp(shape, bcs, D, k, model, params, h=h, scheme=scheme)
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann", "periodic"])
+def test_tables_build_for_every_line_length(bc):
+    nmin = {"dirichlet": 1, "neumann": 2, "periodic": 3}[bc]
+    sizes = list(range(nmin, 70)) + [96, 128, 160, 192, 224, 256, 288, 320, 384, 416, 480, 512]
+    for n in sizes:
+        if not any(n % m == 0 and n // m <= 64 for m in range(1, 9)):
+            continue
+        p = _init((n, 4), (bc, "neumann"), D=(0.5, 3.0), k=0.3)
+        m, C = p.line_split(1)
+        assert m * C == n and C <= 64 and 1 <= m <= 8
+        p.close()
+
+
+def test_tables_build_for_stiff_coefficients():
+    # r = k D / h^2 up to ~5e6 still passes the residual self-check
+    for D in (1e-9, 1.0, 1e3):
+        p = _init((512, 64, 8), ("dirichlet", "periodic", "neumann"), D=(D, 10 * D), k=1.0)
+        p.close()
+
+
+def test_workspace_size_and_layout():
+    p = _init((64, 32, 16), ("neumann", "periodic", "dirichlet"))
+    N = 64 * 32 * 16
+    arr = ((8 * N * 2 + 255) // 256) * 256
+    c1, c2, w = p.layout()
+    assert c1 % 256 == 0 and c2 - c1 == arr and w - c2 == arr
+    assert p.ws_bytes == w + arr
+
+
+def test_invalid_arguments():
+    etd = _lib()
+    E = etd.EtdError
+    with pytest.raises(E) as e:
+        _init((8,), ("neumann",))  # d = 1 not supported by this build
+    assert e.value.status == etd.ETD_ERR_ARG
+    for bad in [dict(k=0.0), dict(k=float("nan")), dict(D=(-1.0, 0.1)), dict(D=(float("inf"), 0.1)),
+                dict(model="enzyme", params={}), dict(h=(-0.1, 0.0))]:
+        with pytest.raises(E) as e:
+            _init((8, 8), ("neumann", "neumann"), **bad)
+        assert e.value.status == etd.ETD_ERR_ARG, bad
+    with pytest.raises(E) as e:
+        _init((2, 8), ("periodic", "neumann"))  # periodic needs n >= 3
+    assert e.value.status == etd.ETD_ERR_ARG
+    with pytest.raises(E) as e:
+        _init((1, 8), ("neumann", "neumann"))  # Neumann needs n >= 2
+    assert e.value.status == etd.ETD_ERR_ARG
+    for n in (67, 1024, 8 * 64 + 8):
+        with pytest.raises(E) as e:
+            _init((n, 8), ("dirichlet", "neumann"))
+        assert e.value.status == etd.ETD_ERR_UNSUPPORTED, n
+
+
+def test_null_pointers_rejected():
+    etd = _lib()
+    out = ctypes.c_void_p()
+    assert etd.lib.etd_rdp_init(None, None, None, 0.1, None, None, ctypes.byref(out)) == etd.ETD_ERR_ARG
+    nb = ctypes.c_size_t()
+    assert etd.lib.etd_rdp_workspace_bytes(None, ctypes.byref(nb)) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_step(None, None, None, 0, 1, None) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_destroy(None) == etd.ETD_OK
+
+
+def test_step_validates_workspace_without_touching_the_gpu():
+    etd = _lib()
+    p = _init((16, 16), ("neumann", "neumann"))
+    ctx = p._ctx
+    fake_u = ctypes.c_void_p(0x1000)
+    # NULL, misaligned, too small: all rejected before any HIP call
+    assert etd.lib.etd_rdp_step(ctx, fake_u, None, p.ws_bytes, 1, None) == etd.ETD_ERR_WORKSPACE
+    assert etd.lib.etd_rdp_step(ctx, fake_u, ctypes.c_void_p(0x1008), p.ws_bytes, 1, None) == etd.ETD_ERR_WORKSPACE
+    assert etd.lib.etd_rdp_step(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes - 8, 1, None) == etd.ETD_ERR_WORKSPACE
+    assert etd.lib.etd_rdp_step(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, -1, None) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_apply_solve(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, 1, 0, 2, None) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_apply_solve(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, 3, 0, 1, None) == etd.ETD_ERR_ARG
+    assert etd.status_string(etd.ETD_ERR_WORKSPACE).startswith("workspace")
