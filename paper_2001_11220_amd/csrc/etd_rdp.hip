@@ -25,82 +25,132 @@
 #include <string>
 #include <vector>
 
-#include "../../include/etd_rdp.h"
+#include "etd_rdp.h"
 #include "etd_device.hpp"
 #include "etd_tables.hpp"
 
 namespace etd {
 
-constexpr int kFirstBlock = 256;  // 4 lines per block in the contiguous pass
-constexpr int kTileLines = 16;    // lines per block in the strided passes
+constexpr int kBlock = 64 * kBlockLines;  // one wavefront per line
+constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
 
 // Table index of (axis, species, gamma-slot); slot 0: gamma=1, 1: 3, 2: 4.
 __host__ __device__ inline int tab_index(int axis0, int sigma, int slot, int S) {
   return (axis0 * S + sigma) * 3 + slot;
 }
 
+template <int M>
+__device__ __forceinline__ void load_chunk(const double* __restrict__ p, double (&v)[M], bool act) {
+  if constexpr (M % 2 == 0) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) {
+      const double2 t = act ? q[j] : make_double2(0.0, 0.0);
+      v[2 * j] = t.x;
+      v[2 * j + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[j] = act ? p[j] : 0.0;
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void store_chunk(double* __restrict__ p, const double (&v)[M]) {
+  if constexpr (M % 2 == 0) {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) q[j] = make_double2(v[2 * j], v[2 * j + 1]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) p[j] = v[j];
+  }
+}
+
+// The tables of one axis: P (gamma 1), T (gamma 3), S (gamma 4) per species,
+// headers in global memory and per-lane parts staged in LDS.
+template <int S>
+struct AxisTabs {
+  const SolveTab* g;
+  const LaneTab* l;
+  __device__ const SolveTab* P(int s) const { return g + tab_index(0, s, 0, S); }
+  __device__ const SolveTab* T(int s) const { return g + tab_index(0, s, 1, S); }
+  __device__ const SolveTab* Sx(int s) const { return g + tab_index(0, s, 2, S); }
+  __device__ const LaneTab* lP(int s) const { return l + tab_index(0, s, 0, S); }
+  __device__ const LaneTab* lT(int s) const { return l + tab_index(0, s, 1, S); }
+  __device__ const LaneTab* lS(int s) const { return l + tab_index(0, s, 2, S); }
+};
+
 // ---------------------------------------------------------------------------
-// Pass 1: the contiguous axis.  One wavefront per line, all species.
+// Pass 1: the contiguous axis.  One wavefront per line, all species; a line's
+// chunk of M consecutive doubles per lane is read directly (16-byte aligned
+// vector loads when M is even: n_1 = C*M is then even too).
 // ---------------------------------------------------------------------------
 template <int M, int S>
-__global__ __launch_bounds__(kFirstBlock) void k_first(
+__global__ __launch_bounds__(kBlock) void k_first(
     const double* __restrict__ u, double* __restrict__ c1,
     double* __restrict__ c2, double* __restrict__ w,
     const SolveTab* __restrict__ tabs, Rx rx, double k, int64_t n1,
     int64_t nlines, int64_t N, int etd1) {
-  const int lane = threadIdx.x & 63;
-  const int64_t line = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (line >= nlines) return;  // uniform per wavefront
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int C = tabs[0].C;
-  const bool act = lane < C;
-  const int64_t off = line * n1 + (int64_t)lane * M;
-  double U[S][M], f[S][M];
+  TileWalk walk((nlines + kBlockLines - 1) / kBlockLines);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const int64_t line = tile * kBlockLines + wv;
+    if (line >= nlines) continue;  // no barriers below: waves are independent
+    const bool act = lane < C;
+    const int64_t off = line * n1 + (int64_t)lane * M;
+    double U[S][M], f[S][M];
 #pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int j = 0; j < M; ++j) U[s][j] = act ? u[s * N + off + j] : 0.0;
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    double uu[S], ff[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) uu[s] = U[s][j];
-    react<S>(rx, uu, ff);
-#pragma unroll
-    for (int s = 0; s < S; ++s) f[s][j] = ff[s];
-  }
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const SolveTab* P = tabs + tab_index(0, s, 0, S);
-    const SolveTab* T = tabs + tab_index(0, s, 1, S);
-    const SolveTab* Sx = tabs + tab_index(0, s, 2, S);
-    if (etd1) {
-      double x[1][M];
-#pragma unroll
-      for (int j = 0; j < M; ++j) x[0][j] = fma(k, f[s][j], U[s][j]);
-      const SolveTab* tb[1] = {P};
-      line_solve<M, 1>(tb, x, lane);
-      if (act)
-#pragma unroll
-        for (int j = 0; j < M; ++j) w[s * N + off + j] = x[0][j];
-      continue;
-    }
-    double x[5][M];
+    for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + off, U[s], act);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      x[0][j] = U[s][j];
-      x[1][j] = U[s][j];
-      x[2][j] = f[s][j];
-      x[3][j] = f[s][j];
-      x[4][j] = fma(k, f[s][j], U[s][j]);
+      double uu[S], ff[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) uu[s] = U[s][j];
+      react<S>(rx, uu, ff);
+#pragma unroll
+      for (int s = 0; s < S; ++s) f[s][j] = ff[s];
     }
-    const SolveTab* tb[5] = {T, Sx, T, Sx, P};
-    line_solve<M, 5>(tb, x, lane);
-    if (act) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (etd1) {
+        double x[1][M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) x[0][j] = fma(k, f[s][j], U[s][j]);
+        const SolveTab* tb[1] = {at.P(s)};
+        const LaneTab* lb[1] = {at.lP(s)};
+        line_solve<M, 1>(tb, lb, x, lane);
+        if (act) store_chunk<M>(w + s * N + off, x[0]);
+        continue;
+      }
+      double x[5][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        c1[s * N + off + j] = 9.0 * x[0][j] - 8.0 * x[1][j];
-        c2[s * N + off + j] = 9.0 * x[2][j] - 8.0 * x[3][j];
-        w[s * N + off + j] = x[4][j];
+        x[0][j] = U[s][j];
+        x[1][j] = f[s][j];
+        x[2][j] = U[s][j];
+        x[3][j] = f[s][j];
+        x[4][j] = fma(k, f[s][j], U[s][j]);
+      }
+      const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
+      const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
+      line_solve<M, 5>(tb, lb, x, lane);
+      if (act) {
+        double o[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) o[j] = 9.0 * x[0][j] - 8.0 * x[2][j];
+        store_chunk<M>(c1 + s * N + off, o);
+#pragma unroll
+        for (int j = 0; j < M; ++j) o[j] = 9.0 * x[1][j] - 8.0 * x[3][j];
+        store_chunk<M>(c2 + s * N + off, o);
+        store_chunk<M>(w + s * N + off, x[4]);
       }
     }
   }
@@ -110,38 +160,55 @@ __global__ __launch_bounds__(kFirstBlock) void k_first(
 // Middle passes (3-D axis 2): purely linear, in place on c1, c2, w.
 // ---------------------------------------------------------------------------
 template <int M, int S>
-__global__ __launch_bounds__(1024) void k_mid(
+__global__ __launch_bounds__(kBlock) void k_mid(
     double* __restrict__ c1, double* __restrict__ c2, double* __restrict__ w,
     const SolveTab* __restrict__ tabs, Geom g, int etd1) {
   extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
   const int lane = threadIdx.x & 63;
-  const int64_t t = blockIdx.x / g.nFblk;
-  const int64_t f0 = (blockIdx.x % g.nFblk) << g.logW;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const int64_t t = tile / g.nFblk;
+    const int64_t f0 = (tile % g.nFblk) * kBlockLines;
+    const int64_t base = f0 + t * g.sT;
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const SolveTab* P = tabs + tab_index(0, s, 0, S);
-    const SolveTab* T = tabs + tab_index(0, s, 1, S);
-    const SolveTab* Sx = tabs + tab_index(0, s, 2, S);
-    if (!etd1) {
-      double* arrs[2] = {c1 + s * g.N, c2 + s * g.N};
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        double v[M], x[2][M];
-        tile_load<M>(arrs[a], v, lds, g, f0, t);
-#pragma unroll
-        for (int j = 0; j < M; ++j) x[0][j] = x[1][j] = v[j];
-        const SolveTab* tb[2] = {T, Sx};
-        line_solve<M, 2>(tb, x, lane);
-#pragma unroll
-        for (int j = 0; j < M; ++j) v[j] = 9.0 * x[0][j] - 8.0 * x[1][j];
-        tile_store<M>(arrs[a], v, lds, g, f0, t);
+    for (int s = 0; s < S; ++s) {
+      if (etd1) {
+        double x[1][M];
+        tile_load<M>(w + s * g.N, x[0], tl, g, base, f0, cur);
+        const SolveTab* tb[1] = {at.P(s)};
+        const LaneTab* lb[1] = {at.lP(s)};
+        line_solve<M, 1>(tb, lb, x, lane);
+        tile_store<M>(w + s * g.N, x[0], tl, g, base, f0, cur);
+        continue;
       }
+      double x[5][M];
+      tile_load<M>(c1 + s * g.N, x[0], tl, g, base, f0, cur);
+      tile_load<M>(c2 + s * g.N, x[1], tl, g, base, f0, cur);
+      tile_load<M>(w + s * g.N, x[4], tl, g, base, f0, cur);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        x[2][j] = x[0][j];
+        x[3][j] = x[1][j];
+      }
+      const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
+      const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
+      line_solve<M, 5>(tb, lb, x, lane);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
+        x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
+      }
+      tile_store<M>(c1 + s * g.N, x[0], tl, g, base, f0, cur);
+      tile_store<M>(c2 + s * g.N, x[1], tl, g, base, f0, cur);
+      tile_store<M>(w + s * g.N, x[4], tl, g, base, f0, cur);
     }
-    double x[1][M];
-    tile_load<M>(w + s * g.N, x[0], lds, g, f0, t);
-    const SolveTab* tb[1] = {P};
-    line_solve<M, 1>(tb, x, lane);
-    tile_store<M>(w + s * g.N, x[0], lds, g, f0, t);
   }
 }
 
@@ -149,54 +216,70 @@ __global__ __launch_bounds__(1024) void k_mid(
 // Last pass (axis d): predictor solve, f*, corrector solves, new state.
 // ---------------------------------------------------------------------------
 template <int M, int S>
-__global__ __launch_bounds__(1024) void k_last(
+__global__ __launch_bounds__(kBlock) void k_last(
     double* __restrict__ u, const double* __restrict__ c1,
     const double* __restrict__ c2, const double* __restrict__ w,
     const SolveTab* __restrict__ tabs, Rx rx, double k, Geom g, int etd1) {
   extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
   const int lane = threadIdx.x & 63;
-  const int64_t t = blockIdx.x / g.nFblk;
-  const int64_t f0 = (blockIdx.x % g.nFblk) << g.logW;
-  double us[S][M];
-#pragma unroll
-  for (int s = 0; s < S; ++s) tile_load<M>(w + s * g.N, us[s], lds, g, f0, t);
-  {
-    const SolveTab* tb[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) tb[s] = tabs + tab_index(0, s, 0, S);
-    line_solve<M, S>(tb, us, lane);
-  }
-  if (etd1) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) tile_store<M>(u + s * g.N, us[s], lds, g, f0, t);
-    return;
-  }
-  double fs[S][M];
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    double uu[S], ff[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) uu[s] = us[s][j];
-    react<S>(rx, uu, ff);
-#pragma unroll
-    for (int s = 0; s < S; ++s) fs[s][j] = ff[s];
-  }
   const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const int64_t t = tile / g.nFblk;
+    const int64_t f0 = (tile % g.nFblk) * kBlockLines;
+    const int64_t base = f0 + t * g.sT;
+    double us[S][M];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    double a[M], b[M], x[2][M];
-    tile_load<M>(c1 + s * g.N, a, lds, g, f0, t);
-    tile_load<M>(c2 + s * g.N, b, lds, g, f0, t);
+    for (int s = 0; s < S; ++s) tile_load<M>(w + s * g.N, us[s], tl, g, base, f0, cur);
+    {
+      const SolveTab* tb[S];
+      const LaneTab* lb[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        tb[s] = at.P(s);
+        lb[s] = at.lP(s);
+      }
+      line_solve<M, S>(tb, lb, us, lane);
+    }
+    if (etd1) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) tile_store<M>(u + s * g.N, us[s], tl, g, base, f0, cur);
+      continue;
+    }
+    // us holds U*; f* = F(U*) overwrites it.
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      x[0][j] = fma(k, fs[s][j], fma(k2, b[j], 9.0 * a[j]));
-      x[1][j] = fma(k05, fs[s][j], fma(k15, b[j], 8.0 * a[j]));
-    }
-    const SolveTab* tb[2] = {tabs + tab_index(0, s, 1, S), tabs + tab_index(0, s, 2, S)};
-    line_solve<M, 2>(tb, x, lane);
+      double uu[S], ff[S];
 #pragma unroll
-    for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
-    tile_store<M>(u + s * g.N, a, lds, g, f0, t);
+      for (int s = 0; s < S; ++s) uu[s] = us[s][j];
+      react<S>(rx, uu, ff);
+#pragma unroll
+      for (int s = 0; s < S; ++s) us[s][j] = ff[s];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double a[M], b[M], x[2][M];
+      tile_load<M>(c1 + s * g.N, a, tl, g, base, f0, cur);
+      tile_load<M>(c2 + s * g.N, b, tl, g, base, f0, cur);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        x[0][j] = fma(k, us[s][j], fma(k2, b[j], 9.0 * a[j]));
+        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], 8.0 * a[j]));
+      }
+      const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
+      const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
+      line_solve<M, 2>(tb, lb, x, lane);
+#pragma unroll
+      for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
+      tile_store<M>(u + s * g.N, a, tl, g, base, f0, cur);
+    }
   }
 }
 
@@ -204,36 +287,53 @@ __global__ __launch_bounds__(1024) void k_last(
 // A single solve on one species array (testing aid for the line solver).
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(kFirstBlock) void k_solve_contig(
+__global__ __launch_bounds__(kBlock) void k_solve_contig(
     double* __restrict__ x, const SolveTab* __restrict__ tab, int64_t n1,
     int64_t nlines) {
-  const int lane = threadIdx.x & 63;
-  const int64_t line = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (line >= nlines) return;
-  const bool act = lane < tab->C;
-  const int64_t off = line * n1 + (int64_t)lane * M;
-  double v[1][M];
-#pragma unroll
-  for (int j = 0; j < M; ++j) v[0][j] = act ? x[off + j] : 0.0;
-  const SolveTab* tb[1] = {tab};
-  line_solve<M, 1>(tb, v, lane);
-  if (act)
-#pragma unroll
-    for (int j = 0; j < M; ++j) x[off + j] = v[0][j];
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  stage_lane_tabs(tab, 1, lt);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  TileWalk walk((nlines + kBlockLines - 1) / kBlockLines);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const int64_t line = tile * kBlockLines + wv;
+    if (line >= nlines) continue;
+    const bool act = lane < tab->C;
+    const int64_t off = line * n1 + (int64_t)lane * M;
+    double v[1][M];
+    load_chunk<M>(x + off, v[0], act);
+    const SolveTab* tb[1] = {tab};
+    const LaneTab* lb[1] = {lt};
+    line_solve<M, 1>(tb, lb, v, lane);
+    if (act) store_chunk<M>(x + off, v[0]);
+  }
 }
 
 template <int M>
-__global__ __launch_bounds__(1024) void k_solve_strided(
+__global__ __launch_bounds__(kBlock) void k_solve_strided(
     double* __restrict__ x, const SolveTab* __restrict__ tab, Geom g) {
   extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* tl = lds + sizeof(LaneTab) / sizeof(double);
+  stage_lane_tabs(tab, 1, lt);
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t t = blockIdx.x / g.nFblk;
-  const int64_t f0 = (blockIdx.x % g.nFblk) << g.logW;
-  double v[1][M];
-  tile_load<M>(x, v[0], lds, g, f0, t);
-  const SolveTab* tb[1] = {tab};
-  line_solve<M, 1>(tb, v, lane);
-  tile_store<M>(x, v[0], lds, g, f0, t);
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const int64_t t = tile / g.nFblk;
+    const int64_t f0 = (tile % g.nFblk) * kBlockLines;
+    const int64_t base = f0 + t * g.sT;
+    double v[1][M];
+    tile_load<M>(x, v[0], tl, g, base, f0, cur);
+    const SolveTab* tb[1] = {tab};
+    const LaneTab* lb[1] = {lt};
+    line_solve<M, 1>(tb, lb, v, lane);
+    tile_store<M>(x, v[0], tl, g, base, f0, cur);
+  }
 }
 
 }  // namespace etd
@@ -298,14 +398,16 @@ int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st) {
   return ETD_OK;
 }
 
-Geom make_geom(const etd_rdp_ctx* c, int axis0) {
+Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds) {
   Geom g{};
   const int64_t n1 = c->n[0], n2 = c->n[1];
   g.N = c->N;
   g.n = static_cast<int>(c->n[axis0]);
   g.C = g.n / c->m[axis0];
-  g.logW = 4;  // kTileLines
   g.pitch = g.n + 1;
+  g.tile = kBlockLines * g.pitch;
+  // Two tile buffers (one barrier per move) when two blocks still fit a CU.
+  g.nbuf = (fixed_lds + 2 * sizeof(double) * (size_t)g.tile <= kLdsMax / 2) ? 2 : 1;
   if (axis0 == 1 && c->d == 3) {  // lines (x, z) along y
     g.nF = n1;
     g.nT = c->n[2];
@@ -322,8 +424,13 @@ Geom make_geom(const etd_rdp_ctx* c, int axis0) {
     g.sRow = n1 * n2;
     g.sT = 0;
   }
-  g.nFblk = (g.nF + kTileLines - 1) / kTileLines;
+  g.nFblk = (g.nF + kBlockLines - 1) / kBlockLines;
   return g;
+}
+
+size_t lane_lds(int ntabs) { return sizeof(LaneTab) * (size_t)ntabs; }
+size_t geom_lds(const Geom& g, size_t fixed_lds) {
+  return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
 }
 
 template <typename KernelT>
@@ -333,61 +440,101 @@ hipError_t set_lds(KernelT kern, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
+// Persistent grid: as many blocks as fit on the device at once (a multiple
+// of 8, one range of tiles per XCD), but no more than the tiles need.
+template <typename KernelT>
+hipError_t persistent_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(kern), kBlock, lds);
+  if (e != hipSuccess) return e;
+  int64_t g = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
+  g = (g / 8) * 8;
+  const int64_t need = ((ntiles + 7) / 8) * 8;
+  if (g > need) g = need;
+  if (g < 8) g = 8;
+  *grid = static_cast<unsigned>(g);
+  return hipSuccess;
+}
+
 // Launchers, templated on the chunk length and species count.
 template <int M, int S>
 hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                         double* w, const SolveTab* tabs, hipStream_t st) {
   const int64_t nlines = c->N / c->n[0];
-  const int per = kFirstBlock / 64;
-  const int64_t blocks = (nlines + per - 1) / per;
-  hipLaunchKernelGGL((k_first<M, S>), dim3(static_cast<unsigned>(blocks)), dim3(kFirstBlock),
-                     0, st, u, c1, c2, w, tabs, c->rx, c->k, c->n[0], nlines, c->N,
-                     c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  const size_t lds = lane_lds(3 * S);
+  hipError_t e = set_lds(k_first<M, S>, lds);
+  if (e != hipSuccess) return e;
+  unsigned grid;
+  e = persistent_grid(k_first<M, S>, lds, (nlines + kBlockLines - 1) / kBlockLines, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_first<M, S>), dim3(grid), dim3(kBlock), lds, st, u, c1, c2, w, tabs,
+                     c->rx, c->k, c->n[0], nlines, c->N, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int M, int S>
 hipError_t launch_mid(const etd_rdp_ctx* c, double* c1, double* c2, double* w,
-                      const SolveTab* tabs, const Geom& g, hipStream_t st) {
-  const size_t lds = sizeof(double) * (size_t)g.pitch * kTileLines;
+                      const SolveTab* tabs, int axis0, hipStream_t st) {
+  const size_t fixed = lane_lds(3 * S);
+  const Geom g = make_geom(c, axis0, fixed);
+  const size_t lds = geom_lds(g, fixed);
   hipError_t e = set_lds(k_mid<M, S>, lds);
   if (e != hipSuccess) return e;
-  const int64_t blocks = g.nFblk * g.nT;
-  hipLaunchKernelGGL((k_mid<M, S>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kTileLines),
-                     lds, st, c1, c2, w, tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  unsigned grid;
+  e = persistent_grid(k_mid<M, S>, lds, g.nFblk * g.nT, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mid<M, S>), dim3(grid), dim3(kBlock), lds, st, c1, c2, w, tabs, g,
+                     c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int M, int S>
 hipError_t launch_last(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
-                       const double* w, const SolveTab* tabs, const Geom& g, hipStream_t st) {
-  const size_t lds = sizeof(double) * (size_t)g.pitch * kTileLines;
+                       const double* w, const SolveTab* tabs, int axis0, hipStream_t st) {
+  const size_t fixed = lane_lds(3 * S);
+  const Geom g = make_geom(c, axis0, fixed);
+  const size_t lds = geom_lds(g, fixed);
   hipError_t e = set_lds(k_last<M, S>, lds);
   if (e != hipSuccess) return e;
-  const int64_t blocks = g.nFblk * g.nT;
-  hipLaunchKernelGGL((k_last<M, S>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kTileLines),
-                     lds, st, u, c1, c2, w, tabs, c->rx, c->k, g,
-                     c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  unsigned grid;
+  e = persistent_grid(k_last<M, S>, lds, g.nFblk * g.nT, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_last<M, S>), dim3(grid), dim3(kBlock), lds, st, u, c1, c2, w, tabs,
+                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int M>
 hipError_t launch_solve(const etd_rdp_ctx* c, double* x, const SolveTab* tab, int axis0,
                         hipStream_t st) {
+  const size_t fixed = lane_lds(1);
+  unsigned grid;
   if (axis0 == 0) {
     const int64_t nlines = c->N / c->n[0];
-    const int per = kFirstBlock / 64;
-    const int64_t blocks = (nlines + per - 1) / per;
-    hipLaunchKernelGGL((k_solve_contig<M>), dim3(static_cast<unsigned>(blocks)), dim3(kFirstBlock),
-                       0, st, x, tab, c->n[0], nlines);
+    hipError_t e = set_lds(k_solve_contig<M>, fixed);
+    if (e != hipSuccess) return e;
+    e = persistent_grid(k_solve_contig<M>, fixed, (nlines + kBlockLines - 1) / kBlockLines, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_solve_contig<M>), dim3(grid), dim3(kBlock), fixed, st, x, tab, c->n[0],
+                       nlines);
     return hipGetLastError();
   }
-  const Geom g = make_geom(c, axis0);
-  const size_t lds = sizeof(double) * (size_t)g.pitch * kTileLines;
+  const Geom g = make_geom(c, axis0, fixed);
+  const size_t lds = geom_lds(g, fixed);
   hipError_t e = set_lds(k_solve_strided<M>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve_strided<M>), dim3(static_cast<unsigned>(g.nFblk * g.nT)),
-                     dim3(64 * kTileLines), lds, st, x, tab, g);
+  e = persistent_grid(k_solve_strided<M>, lds, g.nFblk * g.nT, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_solve_strided<M>), dim3(grid), dim3(kBlock), lds, st, x, tab, g);
   return hipGetLastError();
 }
 
@@ -420,13 +567,11 @@ int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipS
       if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1>(c, u, c1, c2, w, ta, st))); }
       else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2>(c, u, c1, c2, w, ta, st))); }
     } else if (p == c->d - 1) {
-      const Geom g = make_geom(c, p);
-      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, c1, c2, w, ta, g, st))); }
-      else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, c1, c2, w, ta, g, st))); }
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, c1, c2, w, ta, p, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, c1, c2, w, ta, p, st))); }
     } else {
-      const Geom g = make_geom(c, p);
-      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, c1, c2, w, ta, g, st))); }
-      else { ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, c1, c2, w, ta, g, st))); }
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, c1, c2, w, ta, p, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, c1, c2, w, ta, p, st))); }
     }
     if (e != hipSuccess) return hip_fail(c, e);
   }

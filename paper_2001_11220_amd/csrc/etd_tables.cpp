@@ -104,26 +104,27 @@ void emulate(const SolveTab& t, const double* b, double* x) {
   }
   for (int c = 0; c < C; ++c) {
     const int cn = (c + 1 == C) ? 0 : c + 1;
+    const bool last = (c + 1 == C);
     double v = b[static_cast<int64_t>(c) * m + m - 1];
-    if (q > 0) v += t.wl[c] * g[c][q - 1] + t.wr[c] * g[cn][0];
-    if (q > 1) v += t.wg[c] * g[c][1];
+    if (q > 0) v += (last ? t.wl_last : t.wl_gen) * g[c][q - 1] + (last ? t.wr_last : t.wr_gen) * g[cn][0];
+    if (q > 1 && c == 0) v += t.wg0 * g[c][1];
     d[c] = v;
   }
   for (int st = 0; st < t.npcr; ++st) {
-    const int s = 1 << st;
+    const int sh = 1 << st;
     double nd[kLanes];
     for (int c = 0; c < C; ++c) {
-      double dm = (c - s >= 0) ? d[c - s] : 0.0;
-      double dp = (c + s < C) ? d[c + s] : 0.0;
-      nd[c] = d[c] - t.k1[st][c] * dm - t.k2[st][c] * dp;
+      double dm = (c - sh >= 0) ? d[c - sh] : 0.0;
+      double dp = (c + sh < C) ? d[c + sh] : 0.0;
+      nd[c] = d[c] - t.lane.k1[st][c] * dm - t.lane.k2[st][c] * dp;
     }
     std::memcpy(d, nd, sizeof(double) * C);
   }
   double s[kLanes];
-  for (int c = 0; c < C; ++c) s[c] = d[c] * t.inv[c];
+  for (int c = 0; c < C; ++c) s[c] = d[c] * t.lane.inv[c];
   if (t.sm) {
-    const double vy = s[0] + t.vfac * s[C - 1];
-    for (int c = 0; c < C; ++c) s[c] -= vy * t.smfac * t.z[c];
+    const double gam = (s[0] + t.vfac * s[C - 1]) * t.smfac;
+    for (int c = 0; c < C; ++c) s[c] -= gam * t.lane.z[c];
   }
   for (int c = 0; c < C; ++c) {
     double sl;
@@ -238,7 +239,9 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
       for (auto& b : EIS[c])
         Mx[a.sep][b.sep] -= a.v * Tinv[a.slot][b.slot] * b.v;
 
-  // Reduced right-hand-side weights.
+  // Reduced right-hand-side weights (per separator, then checked to be
+  // uniform apart from the first and last separator).
+  std::vector<double> wl(C, 0.0), wr(C, 0.0), wg(C, 0.0);
   double cg = 0.0;  // ghost equation: d_g = cg * g_0[1]
   for (int c = 0; c < C; ++c) {
     for (auto& a : ESI[c]) {
@@ -251,9 +254,9 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
       const int sc = p - S.g;  // separator's chunk
       const int cn = (sc + 1 == C) ? 0 : sc + 1;
       if (c == sc && a.slot == q - 1 && !(c == cn && a.slot == 0)) {
-        t.wl[sc] += -a.v;
+        wl[sc] += -a.v;
       } else if (c == cn && a.slot == 0 && c != sc) {
-        t.wr[sc] += -a.v;
+        wr[sc] += -a.v;
       } else {
         return fail("unexpected separator-interior coupling");
       }
@@ -269,7 +272,7 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
         Mr[i][j] = Mx[i + 1][j + 1] - Mx[i + 1][0] * Mx[0][j + 1] / pg;
     for (int i = 1; i < C; ++i)
       if (Mx[i + 1][0] != 0.0) return fail("ghost couples beyond separator 0");
-    t.wg[0] = -(Mx[1][0] / pg) * cg;
+    wg[0] = -(Mx[1][0] / pg) * cg;
     t.ghd = cg / pg;
     t.gh0 = -Mx[0][1] / pg;
     if (q > 0)
@@ -308,9 +311,9 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
     u[0] = gam;
     u[C - 1] = cbot;
     thomas(ra, rb, rc, u);
-    for (int i = 0; i < C; ++i) t.z[i] = u[i];
+    for (int i = 0; i < C; ++i) t.lane.z[i] = u[i];
     t.vfac = ctop / gam;
-    t.smfac = 1.0 / (1.0 + t.z[0] + t.vfac * t.z[C - 1]);
+    t.smfac = 1.0 / (1.0 + t.lane.z[0] + t.vfac * t.lane.z[C - 1]);
     t.sm = 1;
   }
 
@@ -319,23 +322,34 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   while ((1 << npcr) < C) ++npcr;
   t.npcr = npcr;
   for (int st = 0; st < npcr; ++st) {
-    const int s = 1 << st;
+    const int sh = 1 << st;
     std::vector<double> na(C, 0.0), nb(C, 0.0), nc(C, 0.0);
     for (int i = 0; i < C; ++i) {
-      double k1 = (i - s >= 0) ? ra[i] / rb[i - s] : 0.0;
-      double k2 = (i + s < C) ? rc[i] / rb[i + s] : 0.0;
-      t.k1[st][i] = k1;
-      t.k2[st][i] = k2;
-      nb[i] = rb[i] - ((i - s >= 0) ? k1 * rc[i - s] : 0.0) -
-              ((i + s < C) ? k2 * ra[i + s] : 0.0);
-      na[i] = (i - s >= 0) ? -k1 * ra[i - s] : 0.0;
-      nc[i] = (i + s < C) ? -k2 * rc[i + s] : 0.0;
+      const double k1 = (i - sh >= 0) ? ra[i] / rb[i - sh] : 0.0;
+      const double k2 = (i + sh < C) ? rc[i] / rb[i + sh] : 0.0;
+      t.lane.k1[st][i] = k1;
+      t.lane.k2[st][i] = k2;
+      nb[i] = rb[i] - ((i - sh >= 0) ? k1 * rc[i - sh] : 0.0) -
+              ((i + sh < C) ? k2 * ra[i + sh] : 0.0);
+      na[i] = (i - sh >= 0) ? -k1 * ra[i - sh] : 0.0;
+      nc[i] = (i + sh < C) ? -k2 * rc[i + sh] : 0.0;
     }
     ra.swap(na);
     rb.swap(nb);
     rc.swap(nc);
   }
-  for (int i = 0; i < C; ++i) t.inv[i] = 1.0 / rb[i];
+  for (int i = 0; i < C; ++i) t.lane.inv[i] = 1.0 / rb[i];
+
+  // Uniform reduced-RHS weights.
+  t.wl_gen = r;
+  t.wr_gen = r;
+  t.wl_last = wl[C - 1];
+  t.wr_last = wr[C - 1];
+  t.wg0 = wg[0];
+  for (int c = 0; c + 1 < C; ++c)
+    if (q > 0 && (wl[c] != r || wr[c] != r)) return fail("non-uniform reduced weights");
+  for (int c = 1; c < C; ++c)
+    if (wg[c] != 0.0) return fail("ghost weight beyond separator 0");
 
   // Residual self-check of the chunked algorithm on the original line matrix.
   uint64_t state = 0x9E3779B97F4A7C15ull ^ static_cast<uint64_t>(n * 131 + bc);

@@ -14,9 +14,12 @@
 //
 //   1. local solve   g = T^{-1} b_interior                 (Thomas, uniform)
 //   2. reduced RHS   d_c = b_sep + wl_c g_c[m-2] + wr_c g_{c+1}[0] + wg_c g_c[1]
-//   3. reduced solve s = Mred^{-1} d  by parallel cyclic reduction across the
-//      64 lanes (per-lane coefficients), plus a Sherman-Morrison rank-one
-//      correction when the reduced system is cyclic (periodic lines)
+//      (wl, wr take one value for c < C-1 and another for c = C-1; wg is
+//      non-zero for c = 0 only)
+//   3. reduced solve s = Mred^{-1} d by parallel cyclic reduction across the
+//      lanes of the wavefront (per-lane multipliers, staged in LDS), plus a
+//      Sherman-Morrison rank-one correction when the reduced system is
+//      cyclic (periodic lines)
 //   4. correction    x_j = g_j + sl_c alpha_j + s_c beta_j,   x_sep = s_c
 //      with sl_c = s_{c-1} (c > 0) or the boundary ghost value for c = 0.
 //
@@ -34,15 +37,28 @@ constexpr int kMaxM = 8;       // max rows per chunk
 constexpr int kLanes = 64;     // wavefront width
 constexpr int kMaxPcr = 6;     // log2(64)
 
+// Per-lane data of one line-solve operator, in the order a kernel copies it
+// into LDS (structure of arrays, index = lane = separator).
+struct LaneTab {
+  double k1[kMaxPcr][kLanes];  // PCR multipliers of the lane-s neighbour
+  double k2[kMaxPcr][kLanes];  // PCR multipliers of the lane+s neighbour
+  double inv[kLanes];          // 1 / reduced diagonal after the last step
+  double z[kLanes];            // Sherman-Morrison vector Mred'^{-1} u
+};
+
 // One line-solve operator (axis, species, gamma).  POD, 256-byte multiple,
-// copied verbatim to device memory.
+// copied verbatim to device memory.  The header fields are uniform across a
+// wavefront (chunk-interior factors are indexed by the row inside the chunk).
 struct alignas(256) SolveTab {
-  // Wave-uniform chunk-interior factors, index j < m-1.
+  // Chunk-interior factors, index j < m-1.
   double ip[kMaxM];   // inverse pivots of T
   double cp[kMaxM];   // back-substitution multipliers r * ip[j]
   double al[kMaxM];   // left spike  r T^{-1} e_0
   double be[kMaxM];   // right spike r T^{-1} e_{m-2}
   double r;           // off-diagonal magnitude k D / (gamma h^2)
+  double wl_gen, wl_last;  // reduced-RHS weights of g_c[m-2]
+  double wr_gen, wr_last;  // reduced-RHS weights of g_{c+1}[0]
+  double wg0;              // reduced-RHS weight of g_0[1] (Neumann ghost)
   double ghd;         // lane 0 ghost: sl_0 = ghd g_0[1] + gh0 s_0 + ghw s_{C-1}
   double gh0;
   double ghw;
@@ -52,15 +68,7 @@ struct alignas(256) SolveTab {
   int32_t m;          // rows per chunk
   int32_t npcr;       // PCR steps = ceil(log2 C)
   int32_t sm;         // 1 if the Sherman-Morrison correction is applied
-  double pad0[2];
-  // Per-lane data, structure-of-arrays (index = lane).
-  double k1[kMaxPcr][kLanes];  // PCR multipliers of the lane-s neighbour
-  double k2[kMaxPcr][kLanes];  // PCR multipliers of the lane+s neighbour
-  double inv[kLanes];          // 1 / reduced diagonal after the last step
-  double wl[kLanes];           // reduced-RHS weights (step 2)
-  double wr[kLanes];
-  double wg[kLanes];
-  double z[kLanes];            // Sherman-Morrison vector Mred'^{-1} u
+  LaneTab lane;
 };
 
 // Pick the chunk length for a line of n rows: the smallest m <= kMaxM that
