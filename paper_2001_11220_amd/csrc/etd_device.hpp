@@ -78,6 +78,20 @@ __device__ __forceinline__ void react(const Rx& rx, const double (&uin)[S],
   }
 }
 
+// Value of v in lane src (src uniform), via readlane.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Value of v in lane addr/4 (ds_bpermute with a precomputed byte address).
+__device__ __forceinline__ double bperm(int addr, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 // Exact line solves on a wavefront.
 //
 // A block holds kBlockLines lines, one per wavefront; lane c of a wavefront
@@ -105,67 +119,104 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
                                            const LaneTab* const (&lt)[K],
                                            double (&x)[K][M], int lane) {
   constexpr int Q = M - 1;
+  // Uniform table fields, fetched before any cross-lane traffic.
+  struct Hdr {
+    double ip[Q > 0 ? Q : 1], cp[Q > 0 ? Q : 1], al[Q > 0 ? Q : 1], be[Q > 0 ? Q : 1];
+    double r, wlg, wll, wrg, wrl, wg0, gh0, ghw, ghd, vfac, smfac;
+    int sm;
+  } h[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const SolveTab* t = tab[k];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      h[k].ip[j] = t->ip[j];
+      h[k].cp[j] = t->cp[j];
+      h[k].al[j] = t->al[j];
+      h[k].be[j] = t->be[j];
+    }
+    h[k].r = t->r;
+    h[k].wlg = t->wl_gen;
+    h[k].wll = t->wl_last;
+    h[k].wrg = t->wr_gen;
+    h[k].wrl = t->wr_last;
+    h[k].wg0 = t->wg0;
+    h[k].gh0 = t->gh0;
+    h[k].ghw = t->ghw;
+    h[k].ghd = t->ghd;
+    h[k].vfac = t->vfac;
+    h[k].smfac = t->smfac;
+    h[k].sm = t->sm;
+  }
+  const int C = tab[0]->C;
+  const int npcr = tab[0]->npcr;
   // 1. Thomas on the chunk interior (factors shared by every chunk).
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if constexpr (Q > 0) {
-      const SolveTab* t = tab[k];
-      const double r = t->r;
-      double y = x[k][0] * t->ip[0];
+      double y = x[k][0] * h[k].ip[0];
       x[k][0] = y;
 #pragma unroll
       for (int j = 1; j < Q; ++j) {
-        y = fma(r, y, x[k][j]) * t->ip[j];
+        y = fma(h[k].r, y, x[k][j]) * h[k].ip[j];
         x[k][j] = y;
       }
 #pragma unroll
-      for (int j = Q - 2; j >= 0; --j) x[k][j] = fma(t->cp[j], x[k][j + 1], x[k][j]);
+      for (int j = Q - 2; j >= 0; --j) x[k][j] = fma(h[k].cp[j], x[k][j + 1], x[k][j]);
     }
   }
   // 2. Right-hand side of the reduced separator system.
-  const int C = tab[0]->C;
   const bool last = (lane + 1 == C);
-  const int nxt = last ? 0 : lane + 1;
+  const int lane4 = lane * 4;
+  const int a_next = last ? 0 : lane4 + 4;
   double d[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const SolveTab* t = tab[k];
     double v = x[k][M - 1];
     if constexpr (Q > 0) {
-      const double gn = __shfl(x[k][0], nxt);
-      v = fma(last ? t->wl_last : t->wl_gen, x[k][Q - 1], v);
-      v = fma(last ? t->wr_last : t->wr_gen, gn, v);
+      const double gn = bperm(a_next, x[k][0]);
+      const double wl = last ? h[k].wll : h[k].wlg;
+      const double wr = last ? h[k].wrl : h[k].wrg;
+      v = fma(wl, x[k][Q - 1], v);
+      v = fma(wr, gn, v);
     }
-    if constexpr (Q > 1) v = fma(lane == 0 ? t->wg0 : 0.0, x[k][1], v);
+    if constexpr (Q > 1) {
+      const double wg = (lane == 0) ? h[k].wg0 : 0.0;
+      v = fma(wg, x[k][1], v);
+    }
     d[k] = v;
   }
-  // 3. Parallel cyclic reduction across the lanes.
-  const int npcr = tab[0]->npcr;
-  for (int st = 0; st < npcr; ++st) {
-    const int sh = 1 << st;
+  // 3. Parallel cyclic reduction across the lanes.  Lanes with no neighbour
+  // at distance sh have a zero multiplier; they read a wrapped-around lane.
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double dm = __shfl_up(d[k], sh);
-      const double dp = __shfl_down(d[k], sh);
-      d[k] = d[k] - lt[k]->k1[st][lane] * dm - lt[k]->k2[st][lane] * dp;
+  for (int st = 0; st < kMaxPcr; ++st) {
+    if (st < npcr) {
+      const int a_up = (lane4 - (4 << st)) & 255;
+      const int a_dn = (lane4 + (4 << st)) & 255;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double dm = bperm(a_up, d[k]);
+        const double dp = bperm(a_dn, d[k]);
+        d[k] = d[k] - lt[k]->k1[st][lane] * dm - lt[k]->k2[st][lane] * dp;
+      }
     }
   }
   // 4. Separators, cyclic fix, and back to the chunk.
+  const int a_prev = (lane4 - 4) & 255;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const SolveTab* t = tab[k];
     double s = d[k] * lt[k]->inv[lane];
-    if (t->sm) {
-      const double vy = __shfl(s, 0) + t->vfac * __shfl(s, C - 1);
-      s = fma(-vy * t->smfac, lt[k]->z[lane], s);
+    if (h[k].sm) {
+      const double vy = lane_value(s, 0) + h[k].vfac * lane_value(s, C - 1);
+      s = fma(-vy * h[k].smfac, lt[k]->z[lane], s);
     }
-    const double sprev = __shfl_up(s, 1);
-    const double slast = __shfl(s, C - 1);
-    double ghost = fma(t->gh0, s, t->ghw * slast);
-    if constexpr (Q > 1) ghost = fma(t->ghd, x[k][1], ghost);
+    const double sprev = bperm(a_prev, s);
+    const double slast = lane_value(s, C - 1);
+    double ghost = fma(h[k].gh0, s, h[k].ghw * slast);
+    if constexpr (Q > 1) ghost = fma(h[k].ghd, x[k][1], ghost);
     const double sl = (lane == 0) ? ghost : sprev;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) x[k][j] = fma(sl, t->al[j], fma(s, t->be[j], x[k][j]));
+    for (int j = 0; j < Q; ++j) x[k][j] = fma(sl, h[k].al[j], fma(s, h[k].be[j], x[k][j]));
     x[k][M - 1] = s;
   }
 }
@@ -196,7 +247,7 @@ struct TileWalk {
 // of line (f, t) is at  f + j*sRow + t*sT.
 struct Geom {
   int64_t nF, nT, sRow, sT, N;  // N = species stride
-  int n, C, pitch, nbuf;        // nbuf: 1 or 2 LDS tile buffers
+  int n, C, pitch, nbuf;        // pitch = 8 (mod 32); nbuf: 1 or 2 buffers
   int64_t nFblk;                // blocks per t
   int tile;                     // doubles per tile buffer
 };
@@ -212,23 +263,27 @@ struct TileCursor {
   int buf = 0;
 };
 
+// Thread tid of the block moves, for i = 0..M-1, element (row q*M + i,
+// column col) of the tile, with col = tid % kBlockLines and q = tid /
+// kBlockLines (the chunk).  In LDS that element sits at col*pitch + i*C + q:
+// a wavefront's 64 writes then cover 8 columns x 8 consecutive chunks, which
+// with pitch = 8 (mod 32) doubles hit every bank pair exactly twice, and the
+// line readers (lane = chunk) read consecutive addresses.
 template <int M>
 __device__ __forceinline__ void tile_load(const double* __restrict__ A,
                                           double (&x)[M], double* lds,
                                           const Geom& g, int64_t base,
                                           int64_t f0, TileCursor& cur) {
   const int tid = threadIdx.x;
-  const int col = tid & (kBlockLines - 1), r0 = tid / kBlockLines;
+  const int col = tid & (kBlockLines - 1), q = tid / kBlockLines;
   double* L = lds + cur.buf * g.tile;
-  const bool colok = f0 + col < g.nF;
-  const double* src = A + base + col + r0 * g.sRow;
+  if (q < g.C && f0 + col < g.nF) {
+    const double* src = A + base + col + (int64_t)(q * M) * g.sRow;
 #pragma unroll
-  for (int i = 0; i < M; ++i) {
-    const int row = r0 + 64 * i;
-    if (row < g.n) {
-      const double v = colok ? src[(int64_t)(64 * i) * g.sRow] : 0.0;
-      L[col * g.pitch + (row % M) * g.C + row / M] = v;
-    }
+    for (int i = 0; i < M; ++i) L[col * g.pitch + i * g.C + q] = src[i * g.sRow];
+  } else if (q < g.C) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) L[col * g.pitch + i * g.C + q] = 0.0;
   }
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63;
@@ -251,13 +306,11 @@ __device__ __forceinline__ void tile_store(double* __restrict__ A,
     for (int j = 0; j < M; ++j) L[w * g.pitch + j * g.C + lane] = x[j];
   }
   __syncthreads();
-  const int col = tid & (kBlockLines - 1), r0 = tid / kBlockLines;
-  const bool colok = f0 + col < g.nF;
-  double* dst = A + base + col + r0 * g.sRow;
+  const int col = tid & (kBlockLines - 1), q = tid / kBlockLines;
+  if (q < g.C && f0 + col < g.nF) {
+    double* dst = A + base + col + (int64_t)(q * M) * g.sRow;
 #pragma unroll
-  for (int i = 0; i < M; ++i) {
-    const int row = r0 + 64 * i;
-    if (row < g.n && colok) dst[(int64_t)(64 * i) * g.sRow] = L[col * g.pitch + (row % M) * g.C + row / M];
+    for (int i = 0; i < M; ++i) dst[i * g.sRow] = L[col * g.pitch + i * g.C + q];
   }
   if (g.nbuf == 1) __syncthreads();
   else cur.buf ^= 1;

@@ -404,7 +404,7 @@ Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds) {
   g.N = c->N;
   g.n = static_cast<int>(c->n[axis0]);
   g.C = g.n / c->m[axis0];
-  g.pitch = g.n + 1;
+  g.pitch = g.n + ((8 - g.n % 32) + 32) % 32;  // = 8 (mod 32), see tile_load
   g.tile = kBlockLines * g.pitch;
   // Two tile buffers (one barrier per move) when two blocks still fit a CU.
   g.nbuf = (fixed_lds + 2 * sizeof(double) * (size_t)g.tile <= kLdsMax / 2) ? 2 : 1;
