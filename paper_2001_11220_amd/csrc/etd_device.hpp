@@ -269,21 +269,34 @@ struct TileCursor {
 // a wavefront's 64 writes then cover 8 columns x 8 consecutive chunks, which
 // with pitch = 8 (mod 32) doubles hit every bank pair exactly twice, and the
 // line readers (lane = chunk) read consecutive addresses.
+//
+// A load is split in two so that it can be software-pipelined:
+//   tile_fetch  issues this thread's global loads into registers;
+//   tile_commit writes them to LDS and hands each wave its line's chunk.
 template <int M>
-__device__ __forceinline__ void tile_load(const double* __restrict__ A,
-                                          double (&x)[M], double* lds,
-                                          const Geom& g, int64_t base,
-                                          int64_t f0, TileCursor& cur) {
+__device__ __forceinline__ void tile_fetch(const double* __restrict__ A, double (&r)[M],
+                                           const Geom& g, int64_t base, int64_t f0) {
   const int tid = threadIdx.x;
   const int col = tid & (kBlockLines - 1), q = tid / kBlockLines;
-  double* L = lds + cur.buf * g.tile;
   if (q < g.C && f0 + col < g.nF) {
     const double* src = A + base + col + (int64_t)(q * M) * g.sRow;
 #pragma unroll
-    for (int i = 0; i < M; ++i) L[col * g.pitch + i * g.C + q] = src[i * g.sRow];
-  } else if (q < g.C) {
+    for (int i = 0; i < M; ++i) r[i] = src[i * g.sRow];
+  } else {
 #pragma unroll
-    for (int i = 0; i < M; ++i) L[col * g.pitch + i * g.C + q] = 0.0;
+    for (int i = 0; i < M; ++i) r[i] = 0.0;
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M], double* lds,
+                                            const Geom& g, TileCursor& cur) {
+  const int tid = threadIdx.x;
+  const int col = tid & (kBlockLines - 1), q = tid / kBlockLines;
+  double* L = lds + cur.buf * g.tile;
+  if (q < g.C) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) L[col * g.pitch + i * g.C + q] = r[i];
   }
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63;
@@ -315,5 +328,15 @@ __device__ __forceinline__ void tile_store(double* __restrict__ A,
   if (g.nbuf == 1) __syncthreads();
   else cur.buf ^= 1;
 }
+
+// A tile position (t, f0) and its base offset for a tile index.
+struct TilePos {
+  int64_t f0, base;
+  __device__ __forceinline__ TilePos(int64_t tile, const Geom& g) {
+    const int64_t t = tile / g.nFblk;
+    f0 = (tile % g.nFblk) * kBlockLines;
+    base = f0 + t * g.sT;
+  }
+};
 
 }  // namespace etd

@@ -99,16 +99,33 @@ __global__ __launch_bounds__(kBlock) void k_first(
   const AxisTabs<S> at{tabs, lt};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int C = tabs[0].C;
+  const bool act = lane < C;
+  // Each wavefront walks its own lines; the next line's U is fetched into
+  // registers before the current line is solved.
   TileWalk walk((nlines + kBlockLines - 1) / kBlockLines);
   int64_t tile;
-  while (walk.next(tile)) {
-    const int64_t line = tile * kBlockLines + wv;
-    if (line >= nlines) continue;  // no barriers below: waves are independent
-    const bool act = lane < C;
+  auto line_of = [&](int64_t tl) { return tl * kBlockLines + wv; };
+  bool have = walk.next(tile);
+  while (have && line_of(tile) >= nlines) have = walk.next(tile);
+  double Un[S][M];
+  if (have) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + line_of(tile) * n1 + (int64_t)lane * M, Un[s], act);
+  }
+  while (have) {
+    const int64_t line = line_of(tile);
     const int64_t off = line * n1 + (int64_t)lane * M;
     double U[S][M], f[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + off, U[s], act);
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int j = 0; j < M; ++j) U[s][j] = Un[s][j];
+    have = walk.next(tile);
+    while (have && line_of(tile) >= nlines) have = walk.next(tile);
+    if (have) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + line_of(tile) * n1 + (int64_t)lane * M, Un[s], act);
+    }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       double uu[S], ff[S];
@@ -158,6 +175,8 @@ __global__ __launch_bounds__(kBlock) void k_first(
 
 // ---------------------------------------------------------------------------
 // Middle passes (3-D axis 2): purely linear, in place on c1, c2, w.
+// Work items are (tile, species); the next item's tiles are fetched into
+// registers while the current one is solved.
 // ---------------------------------------------------------------------------
 template <int M, int S>
 __global__ __launch_bounds__(kBlock) void k_mid(
@@ -173,47 +192,65 @@ __global__ __launch_bounds__(kBlock) void k_mid(
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
-  while (walk.next(tile)) {
-    const int64_t t = tile / g.nFblk;
-    const int64_t f0 = (tile % g.nFblk) * kBlockLines;
-    const int64_t base = f0 + t * g.sT;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (etd1) {
-        double x[1][M];
-        tile_load<M>(w + s * g.N, x[0], tl, g, base, f0, cur);
-        const SolveTab* tb[1] = {at.P(s)};
-        const LaneTab* lb[1] = {at.lP(s)};
-        line_solve<M, 1>(tb, lb, x, lane);
-        tile_store<M>(w + s * g.N, x[0], tl, g, base, f0, cur);
-        continue;
-      }
-      double x[5][M];
-      tile_load<M>(c1 + s * g.N, x[0], tl, g, base, f0, cur);
-      tile_load<M>(c2 + s * g.N, x[1], tl, g, base, f0, cur);
-      tile_load<M>(w + s * g.N, x[4], tl, g, base, f0, cur);
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        x[2][j] = x[0][j];
-        x[3][j] = x[1][j];
-      }
-      const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
-      const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
-      line_solve<M, 5>(tb, lb, x, lane);
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
-        x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
-      }
-      tile_store<M>(c1 + s * g.N, x[0], tl, g, base, f0, cur);
-      tile_store<M>(c2 + s * g.N, x[1], tl, g, base, f0, cur);
-      tile_store<M>(w + s * g.N, x[4], tl, g, base, f0, cur);
+  bool have = walk.next(tile);
+  int s = 0;
+  double pf[3][M];
+  auto fetch = [&](int64_t tl_, int s_) {
+    const TilePos p(tl_, g);
+    if (!etd1) {
+      tile_fetch<M>(c1 + s_ * g.N, pf[0], g, p.base, p.f0);
+      tile_fetch<M>(c2 + s_ * g.N, pf[1], g, p.base, p.f0);
     }
+    tile_fetch<M>(w + s_ * g.N, pf[2], g, p.base, p.f0);
+  };
+  if (have) fetch(tile, 0);
+  while (have) {
+    const TilePos pos(tile, g);
+    const int sc = s;
+    double x[5][M];
+    if (!etd1) {
+      tile_commit<M>(pf[0], x[0], tl, g, cur);
+      tile_commit<M>(pf[1], x[1], tl, g, cur);
+    }
+    tile_commit<M>(pf[2], x[4], tl, g, cur);
+    if (++s == S) {
+      s = 0;
+      have = walk.next(tile);
+    }
+    if (have) fetch(tile, s);
+    if (etd1) {
+      double y[1][M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) y[0][j] = x[4][j];
+      const SolveTab* tb[1] = {at.P(sc)};
+      const LaneTab* lb[1] = {at.lP(sc)};
+      line_solve<M, 1>(tb, lb, y, lane);
+      tile_store<M>(w + sc * g.N, y[0], tl, g, pos.base, pos.f0, cur);
+      continue;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[2][j] = x[0][j];
+      x[3][j] = x[1][j];
+    }
+    const SolveTab* tb[5] = {at.T(sc), at.T(sc), at.Sx(sc), at.Sx(sc), at.P(sc)};
+    const LaneTab* lb[5] = {at.lT(sc), at.lT(sc), at.lS(sc), at.lS(sc), at.lP(sc)};
+    line_solve<M, 5>(tb, lb, x, lane);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
+      x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
+    }
+    tile_store<M>(c1 + sc * g.N, x[0], tl, g, pos.base, pos.f0, cur);
+    tile_store<M>(c2 + sc * g.N, x[1], tl, g, pos.base, pos.f0, cur);
+    tile_store<M>(w + sc * g.N, x[4], tl, g, pos.base, pos.f0, cur);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Last pass (axis d): predictor solve, f*, corrector solves, new state.
+// Per tile the loads come in groups (w of all species; then c1, c2 of each
+// species); each group is fetched into registers one group ahead.
 // ---------------------------------------------------------------------------
 template <int M, int S>
 __global__ __launch_bounds__(kBlock) void k_last(
@@ -231,13 +268,31 @@ __global__ __launch_bounds__(kBlock) void k_last(
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
-  while (walk.next(tile)) {
-    const int64_t t = tile / g.nFblk;
-    const int64_t f0 = (tile % g.nFblk) * kBlockLines;
-    const int64_t base = f0 + t * g.sT;
+  bool have = walk.next(tile);
+  double pf[2][M];
+  auto fetch_w = [&](int64_t tl_) {
+    const TilePos p(tl_, g);
+#pragma unroll
+    for (int s = 0; s < S; ++s) tile_fetch<M>(w + s * g.N, pf[s], g, p.base, p.f0);
+  };
+  auto fetch_c = [&](int64_t tl_, int s_) {
+    const TilePos p(tl_, g);
+    tile_fetch<M>(c1 + s_ * g.N, pf[0], g, p.base, p.f0);
+    tile_fetch<M>(c2 + s_ * g.N, pf[1], g, p.base, p.f0);
+  };
+  if (have) fetch_w(tile);
+  while (have) {
+    const TilePos pos(tile, g);
+    const int64_t tcur = tile;
     double us[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) tile_load<M>(w + s * g.N, us[s], tl, g, base, f0, cur);
+    for (int s = 0; s < S; ++s) tile_commit<M>(pf[s], us[s], tl, g, cur);
+    if (etd1) {
+      have = walk.next(tile);
+      if (have) fetch_w(tile);
+    } else {
+      fetch_c(tcur, 0);
+    }
     {
       const SolveTab* tb[S];
       const LaneTab* lb[S];
@@ -250,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_last(
     }
     if (etd1) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M>(u + s * g.N, us[s], tl, g, base, f0, cur);
+      for (int s = 0; s < S; ++s) tile_store<M>(u + s * g.N, us[s], tl, g, pos.base, pos.f0, cur);
       continue;
     }
     // us holds U*; f* = F(U*) overwrites it.
@@ -266,8 +321,14 @@ __global__ __launch_bounds__(kBlock) void k_last(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double a[M], b[M], x[2][M];
-      tile_load<M>(c1 + s * g.N, a, tl, g, base, f0, cur);
-      tile_load<M>(c2 + s * g.N, b, tl, g, base, f0, cur);
+      tile_commit<M>(pf[0], a, tl, g, cur);
+      tile_commit<M>(pf[1], b, tl, g, cur);
+      if (s + 1 < S) {
+        fetch_c(tcur, s + 1);
+      } else {
+        have = walk.next(tile);
+        if (have) fetch_w(tile);
+      }
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         x[0][j] = fma(k, us[s][j], fma(k2, b[j], 9.0 * a[j]));
@@ -278,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_last(
       line_solve<M, 2>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
-      tile_store<M>(u + s * g.N, a, tl, g, base, f0, cur);
+      tile_store<M>(u + s * g.N, a, tl, g, pos.base, pos.f0, cur);
     }
   }
 }
@@ -324,15 +385,14 @@ __global__ __launch_bounds__(kBlock) void k_solve_strided(
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   while (walk.next(tile)) {
-    const int64_t t = tile / g.nFblk;
-    const int64_t f0 = (tile % g.nFblk) * kBlockLines;
-    const int64_t base = f0 + t * g.sT;
-    double v[1][M];
-    tile_load<M>(x, v[0], tl, g, base, f0, cur);
+    const TilePos pos(tile, g);
+    double r[M], v[1][M];
+    tile_fetch<M>(x, r, g, pos.base, pos.f0);
+    tile_commit<M>(r, v[0], tl, g, cur);
     const SolveTab* tb[1] = {tab};
     const LaneTab* lb[1] = {lt};
     line_solve<M, 1>(tb, lb, v, lane);
-    tile_store<M>(x, v[0], tl, g, base, f0, cur);
+    tile_store<M>(x, v[0], tl, g, pos.base, pos.f0, cur);
   }
 }
 
