@@ -40,8 +40,14 @@ def pass_words(d: int):
     return [4] + [6] * (d - 2) + [4]
 
 
-def pass_names(d: int):
-    return ["k_first"] + ["k_mid"] * (d - 2) + ["k_last"]
+def pass_names(e, d: int):
+    """Kernel names (as rocprofv3 prints them, shortened) of each pass."""
+    names = []
+    for p in range(1, d + 1):
+        m, _ = e.line_split(p)
+        kind = "k_first" if p == 1 else ("k_last" if p == d else "k_mid")
+        names.append(f"{kind}<{m}, {e.s}>")
+    return names
 
 
 def cpu_baseline(name: str, budget_s: float = 12.0):
@@ -80,6 +86,8 @@ def main():
     ap.add_argument("--workload", default="grayscott3d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-steps", type=int, default=50)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -124,7 +132,7 @@ def main():
     # Per-pass kernel timing (each pass alone, same arrays as in a step).
     d = len(prob.shape)
     words = pass_words(d)
-    names = pass_names(d)
+    names = pass_names(e, d)
     per = []
     for p in range(1, d + 1):
         e.run_pass(u, p)
@@ -144,13 +152,17 @@ def main():
     dom = max(per, key=lambda r: r["avg_ms"])
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            rec = tr.get(prob.name, {}).get(dom["kernel"])
-            if rec and rec.get("kernel_rev") == _kernel_rev():
-                traffic = rec["bytes_per_launch"]
-        except Exception:
-            traffic = None
+        from paper_2001_11220_amd.profiling import kernel_rev
+        tr = json.load(open(TRAFFIC_FILE)).get(prob.name, {})
+        rec = tr.get("kernels", {}).get(dom["kernel"])
+        if rec and tr.get("kernel_rev") == kernel_rev():
+            traffic = rec["bytes_per_launch"]
+    if args.calib_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     step_bytes = sum(words) * 8 * cs
     roof = {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["kernel"],
@@ -183,16 +195,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-
-
-def _kernel_rev():
-    """Hash of the kernel sources, to invalidate stored counter traffic."""
-    import hashlib
-    h = hashlib.sha1()
-    for fn in ("etd_rdp.hip", "etd_device.hpp", "etd_tables.hpp", "etd_tables.cpp"):
-        with open(os.path.join(ROOT, "paper_2001_11220_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:12]
 
 
 if __name__ == "__main__":
