@@ -245,3 +245,14 @@ def test_grayscott3d_full_size_one_step_sampled():
     x0s = [0, 101, 128, 255]
     ref = _sampled_step_reference(prob, u0, x0s)
     assert rel_l2(got[..., x0s], ref) < 1e-12
+
+
+def test_schnakenberg3d_full_size_one_step_sampled():
+    """512^3 Dirichlet (chunk length 8, r up to ~263), benchmark launch
+    configuration; planes x = x0 checked against the oracle."""
+    prob = W.schnakenberg3d()
+    u0 = prob.initial()
+    got = gpu_run(prob, u0, 1)
+    x0s = [0, 255, 511]
+    ref = _sampled_step_reference(prob, u0, x0s)
+    assert rel_l2(got[..., x0s], ref) < 1e-12
