@@ -81,7 +81,8 @@ def cpu_baseline(name: str, budget_s: float = 12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="grayscott3d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,7 +102,13 @@ def main():
     from paper_2001_11220_amd import workloads as W
     from paper_2001_11220_amd.etd import EtdRdp
 
+    if args.workload == "brusselator_ensemble":
+        if args.steps is None:
+            args.steps = 200
+        return bench_ensemble(args)
     prob = W.WORKLOADS[args.workload]()
+    if args.steps is None:
+        args.steps = prob.nsteps
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     e = EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
@@ -193,6 +200,78 @@ def main():
                    "state_finite": finite},
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args):
+    """1024 independent 2-D Brusselators of uneven size, all steps recorded in
+    one HIP graph; reported against the plain 2-D solver at N = 512."""
+    import numpy as np
+    import torch
+
+    from paper_2001_11220_amd import workloads as W
+    from paper_2001_11220_amd.etd import EtdRdp, EtdRdpBatch
+
+    ens = W.brusselator_ensemble()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    b = EtdRdpBatch(ens.instances, ens.s, ens.model, ens.k, device=dev)
+    u = b.pack(ens.states)
+    stream = torch.cuda.current_stream()
+    steps = args.steps
+    print(f"[bench] ensemble of {b.n} instances, {ens.cell_species:.3e} cell-species, "
+          f"{b.launches_per_step} launches/step, ws={b.ws_bytes/2**30:.2f} GiB", file=sys.stderr, flush=True)
+    b.step(u, steps, use_graph=True)  # records the graph (untimed warm-up of `steps` steps)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    b.step(u, steps, use_graph=True)  # one graph launch
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / steps
+    value = ens.cell_species * steps / (ms / 1e3)
+    finite = bool(torch.isfinite(u).all().item())
+    # plain 2-D solver at the largest instance size, same coefficients range
+    p = EtdRdp((512, 512), ("neumann", "periodic"), (0.02, 0.02), ens.k, ens.model,
+               {"a": 1.0, "b": 3.0}, device=dev)
+    up = torch.from_numpy(np.stack([0.5 + 0.1 * np.random.default_rng(1).random((512, 512))
+                                    for _ in range(2)])).to(dev)
+    p.step(up, 20)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    p.step(up, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev0.elapsed_time(ev1) / steps
+    plain_value = 2 * 512 * 512 / (plain_ms / 1e3)
+    print(f"[bench] ensemble {ms_step*1e3:.1f} us/step; plain 512^2 {plain_ms*1e3:.1f} us/step",
+          file=sys.stderr, flush=True)
+    eff = 64 * value / 1e9  # 2-D: 8 words per cell-species-step
+    out = {
+        "metric": "cell-species-steps/sec",
+        "value": value,
+        "unit": "cell-species-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": steps,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded instance parameters and initial data, no dataset)",
+        "config": {"workload": "brusselator_ensemble", "instances": b.n,
+                   "cell_species": ens.cell_species, "launches_per_step": b.launches_per_step,
+                   "graph": "all steps in one HIP graph launch", "state_finite": finite},
+        "roofline": {"bound": "hbm", "achieved": eff, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": eff / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole step (all groups, 2 passes)",
+                     "alg_bytes_per_step": 64 * ens.cell_species},
+        "plain_2d_512": {"value": plain_value, "ms_per_step": plain_ms,
+                         "effective_GBps": 64 * plain_value / 1e9},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

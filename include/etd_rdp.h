@@ -200,6 +200,60 @@ int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx);
 int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m,
                        int32_t* chunks);
 
+/* ======================================================================
+ * Ensembles: many independent 2-D problems of uneven size advanced together.
+ * All instances share the number of species s, the reaction model, the time
+ * step k and the scheme; each has its own grid, boundary conditions,
+ * diffusion coefficients and reaction parameters.  The states are packed
+ * back to back in one device array, instance i at the offset (in doubles)
+ * that etd_rdp_batch_offsets reports, each laid out like a single problem's
+ * state.
+ * ====================================================================== */
+
+typedef struct etd_instance_t {
+  int64_t n[2];                     /* unknowns on axis 1 (fastest), axis 2 */
+  double h[2];                      /* spacing; 0 = unit-domain default     */
+  int32_t bc[2];                    /* ETD_BC_* per axis                    */
+  double D[ETD_MAX_SPECIES];        /* diffusion coefficients               */
+  double params[ETD_MAX_PARAMS];    /* reaction parameters (see ETD_RX_*)   */
+  double shift[ETD_MAX_SPECIES];    /* F evaluated at u + shift             */
+} etd_instance_t;
+
+typedef struct etd_rdp_batch etd_rdp_batch;
+
+/*
+ * etd_rdp_batch_init -- validate ninst >= 1 instances and build their tables
+ * on the host (no HIP call).  s and model as in etd_rdp_init; every instance
+ * obeys etd_rdp_init's rules for d = 2.  Errors as etd_rdp_init.
+ */
+int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s,
+                       int32_t model, double k, const etd_scheme_t* scheme,
+                       etd_rdp_batch** out);
+
+int etd_rdp_batch_destroy(etd_rdp_batch* b);
+
+/* offsets[0..ninst]: start of instance i in the packed state (doubles);
+ * offsets[ninst] is the total length.  Offsets are multiples of 32. */
+int etd_rdp_batch_offsets(const etd_rdp_batch* b, int64_t* offsets);
+
+/* Device workspace bytes (tables, instance descriptors, tile maps and the
+ * three carried arrays); 256-byte aligned. */
+int etd_rdp_batch_workspace_bytes(const etd_rdp_batch* b, size_t* bytes);
+
+/*
+ * etd_rdp_batch_step -- advance every instance by nsteps steps on `stream`.
+ * use_graph != 0 records the whole nsteps sequence of launches into one HIP
+ * graph (on a private capture stream) and launches that graph on `stream`;
+ * the graph is kept and replayed while (u, ws, nsteps) stay the same.
+ * Otherwise the kernels are launched one by one.  Asynchronous.
+ */
+int etd_rdp_batch_step(etd_rdp_batch* b, double* u_packed, void* ws,
+                       size_t ws_bytes, int64_t nsteps, int32_t use_graph,
+                       void* stream);
+
+/* Number of kernel launches of one step (for tests and reports). */
+int etd_rdp_batch_launches_per_step(const etd_rdp_batch* b, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

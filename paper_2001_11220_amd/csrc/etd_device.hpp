@@ -339,4 +339,54 @@ struct TilePos {
   }
 };
 
+constexpr int kBlock = 64 * kBlockLines;  // one wavefront per line
+constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
+
+// Table index of (axis, species, gamma-slot); slot 0: gamma=1, 1: 3, 2: 4.
+__host__ __device__ inline int tab_index(int axis0, int sigma, int slot, int S) {
+  return (axis0 * S + sigma) * 3 + slot;
+}
+
+template <int M>
+__device__ __forceinline__ void load_chunk(const double* __restrict__ p, double (&v)[M], bool act) {
+  if constexpr (M % 2 == 0) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) {
+      const double2 t = act ? q[j] : make_double2(0.0, 0.0);
+      v[2 * j] = t.x;
+      v[2 * j + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[j] = act ? p[j] : 0.0;
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void store_chunk(double* __restrict__ p, const double (&v)[M]) {
+  if constexpr (M % 2 == 0) {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) q[j] = make_double2(v[2 * j], v[2 * j + 1]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) p[j] = v[j];
+  }
+}
+
+// The tables of one axis: P (gamma 1), T (gamma 3), S (gamma 4) per species,
+// headers in global memory and per-lane parts staged in LDS.
+template <int S>
+struct AxisTabs {
+  const SolveTab* g;
+  const LaneTab* l;
+  __device__ const SolveTab* P(int s) const { return g + tab_index(0, s, 0, S); }
+  __device__ const SolveTab* T(int s) const { return g + tab_index(0, s, 1, S); }
+  __device__ const SolveTab* Sx(int s) const { return g + tab_index(0, s, 2, S); }
+  __device__ const LaneTab* lP(int s) const { return l + tab_index(0, s, 0, S); }
+  __device__ const LaneTab* lT(int s) const { return l + tab_index(0, s, 1, S); }
+  __device__ const LaneTab* lS(int s) const { return l + tab_index(0, s, 2, S); }
+};
+
 }  // namespace etd

@@ -1,0 +1,59 @@
+// Host-side launch helpers shared by the single-problem and ensemble paths.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "etd_device.hpp"
+
+namespace etd {
+
+inline size_t lane_lds(int ntabs) { return sizeof(LaneTab) * (size_t)ntabs; }
+
+template <typename KernelT>
+hipError_t set_lds(KernelT kern, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(bytes));
+}
+
+// Persistent grid: as many blocks as fit on the device at once (a multiple
+// of 8, one range of tiles per XCD), but no more than the tiles need.
+template <typename KernelT>
+hipError_t persistent_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(kern), kBlock, lds);
+  if (e != hipSuccess) return e;
+  int64_t g = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
+  g = (g / 8) * 8;
+  const int64_t need = ((ntiles + 7) / 8) * 8;
+  if (g > need) g = need;
+  if (g < 8) g = 8;
+  *grid = static_cast<unsigned>(g);
+  return hipSuccess;
+}
+
+// Runtime (m, s) -> template dispatch.
+#define ETD_DISPATCH_M(m, CALL) \
+  switch (m) {                  \
+    case 1: { constexpr int M_ = 1; CALL; } break; \
+    case 2: { constexpr int M_ = 2; CALL; } break; \
+    case 3: { constexpr int M_ = 3; CALL; } break; \
+    case 4: { constexpr int M_ = 4; CALL; } break; \
+    case 5: { constexpr int M_ = 5; CALL; } break; \
+    case 6: { constexpr int M_ = 6; CALL; } break; \
+    case 7: { constexpr int M_ = 7; CALL; } break; \
+    case 8: { constexpr int M_ = 8; CALL; } break; \
+    default: return ETD_ERR_INTERNAL;               \
+  }
+
+
+}  // namespace etd

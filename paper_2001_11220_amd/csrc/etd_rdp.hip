@@ -27,59 +27,10 @@
 
 #include "etd_rdp.h"
 #include "etd_device.hpp"
+#include "etd_launch.hpp"
 #include "etd_tables.hpp"
 
 namespace etd {
-
-constexpr int kBlock = 64 * kBlockLines;  // one wavefront per line
-constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
-
-// Table index of (axis, species, gamma-slot); slot 0: gamma=1, 1: 3, 2: 4.
-__host__ __device__ inline int tab_index(int axis0, int sigma, int slot, int S) {
-  return (axis0 * S + sigma) * 3 + slot;
-}
-
-template <int M>
-__device__ __forceinline__ void load_chunk(const double* __restrict__ p, double (&v)[M], bool act) {
-  if constexpr (M % 2 == 0) {
-    const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-    for (int j = 0; j < M / 2; ++j) {
-      const double2 t = act ? q[j] : make_double2(0.0, 0.0);
-      v[2 * j] = t.x;
-      v[2 * j + 1] = t.y;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = act ? p[j] : 0.0;
-  }
-}
-
-template <int M>
-__device__ __forceinline__ void store_chunk(double* __restrict__ p, const double (&v)[M]) {
-  if constexpr (M % 2 == 0) {
-    double2* q = reinterpret_cast<double2*>(p);
-#pragma unroll
-    for (int j = 0; j < M / 2; ++j) q[j] = make_double2(v[2 * j], v[2 * j + 1]);
-  } else {
-#pragma unroll
-    for (int j = 0; j < M; ++j) p[j] = v[j];
-  }
-}
-
-// The tables of one axis: P (gamma 1), T (gamma 3), S (gamma 4) per species,
-// headers in global memory and per-lane parts staged in LDS.
-template <int S>
-struct AxisTabs {
-  const SolveTab* g;
-  const LaneTab* l;
-  __device__ const SolveTab* P(int s) const { return g + tab_index(0, s, 0, S); }
-  __device__ const SolveTab* T(int s) const { return g + tab_index(0, s, 1, S); }
-  __device__ const SolveTab* Sx(int s) const { return g + tab_index(0, s, 2, S); }
-  __device__ const LaneTab* lP(int s) const { return l + tab_index(0, s, 0, S); }
-  __device__ const LaneTab* lT(int s) const { return l + tab_index(0, s, 1, S); }
-  __device__ const LaneTab* lS(int s) const { return l + tab_index(0, s, 2, S); }
-};
 
 // ---------------------------------------------------------------------------
 // Pass 1: the contiguous axis.  One wavefront per line, all species; a line's
@@ -488,41 +439,8 @@ Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds) {
   return g;
 }
 
-size_t lane_lds(int ntabs) { return sizeof(LaneTab) * (size_t)ntabs; }
 size_t geom_lds(const Geom& g, size_t fixed_lds) {
   return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
-}
-
-template <typename KernelT>
-hipError_t set_lds(KernelT kern, size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(bytes));
-}
-
-// Persistent grid: as many blocks as fit on the device at once (a multiple
-// of 8, one range of tiles per XCD), but no more than the tiles need.
-template <typename KernelT>
-hipError_t persistent_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid) {
-  static int ncu = 0;
-  if (ncu == 0) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-  }
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(kern), kBlock, lds);
-  if (e != hipSuccess) return e;
-  int64_t g = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
-  g = (g / 8) * 8;
-  const int64_t need = ((ntiles + 7) / 8) * 8;
-  if (g > need) g = need;
-  if (g < 8) g = 8;
-  *grid = static_cast<unsigned>(g);
-  return hipSuccess;
 }
 
 // Launchers, templated on the chunk length and species count.
@@ -597,20 +515,6 @@ hipError_t launch_solve(const etd_rdp_ctx* c, double* x, const SolveTab* tab, in
   hipLaunchKernelGGL((k_solve_strided<M>), dim3(grid), dim3(kBlock), lds, st, x, tab, g);
   return hipGetLastError();
 }
-
-// Runtime (m, s) -> template dispatch.
-#define ETD_DISPATCH_M(m, CALL) \
-  switch (m) {                  \
-    case 1: { constexpr int M_ = 1; CALL; } break; \
-    case 2: { constexpr int M_ = 2; CALL; } break; \
-    case 3: { constexpr int M_ = 3; CALL; } break; \
-    case 4: { constexpr int M_ = 4; CALL; } break; \
-    case 5: { constexpr int M_ = 5; CALL; } break; \
-    case 6: { constexpr int M_ = 6; CALL; } break; \
-    case 7: { constexpr int M_ = 7; CALL; } break; \
-    case 8: { constexpr int M_ = 8; CALL; } break; \
-    default: return ETD_ERR_INTERNAL;               \
-  }
 
 int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipStream_t st) {
   char* base = static_cast<char*>(ws);

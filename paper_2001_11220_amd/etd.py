@@ -44,6 +44,12 @@ class Reaction(ctypes.Structure):
                 ("shift", ctypes.c_double * MAX_SPECIES)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64 * 2), ("h", ctypes.c_double * 2), ("bc", ctypes.c_int32 * 2),
+                ("D", ctypes.c_double * MAX_SPECIES), ("params", ctypes.c_double * MAX_PARAMS),
+                ("shift", ctypes.c_double * MAX_SPECIES)]
+
+
 class Scheme(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
@@ -72,6 +78,13 @@ def _load():
         "etd_rdp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "etd_rdp_last_hip_error": (ctypes.c_int, [P]),
         "etd_rdp_line_split": (ctypes.c_int, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "etd_rdp_batch_init": (ctypes.c_int, [I32, ctypes.POINTER(Instance), I32, I32, D,
+                                              ctypes.POINTER(Scheme), ctypes.POINTER(P)]),
+        "etd_rdp_batch_destroy": (ctypes.c_int, [P]),
+        "etd_rdp_batch_offsets": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+        "etd_rdp_batch_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
+        "etd_rdp_batch_step": (ctypes.c_int, [P, P, P, SZ, I64, I32, P]),
+        "etd_rdp_batch_launches_per_step": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -232,3 +245,96 @@ class EtdRdp:
                                        self.ws_bytes, int(axis), int(sigma), int(gamma),
                                        self._stream(stream)), "etd_rdp_apply_solve")
         return x
+
+
+class EtdRdpBatch:
+    """An ensemble of independent 2-D problems advanced together.
+
+    ``instances``: sequence of dicts with keys ``shape`` (n_1, n_2), ``bcs``,
+    ``D`` and ``params`` (and optionally ``h``, ``shift``).  The packed state
+    is one float64 device tensor of ``offsets[-1]`` doubles; instance i is
+    ``u[offsets[i]: offsets[i] + s*n_1*n_2]`` viewed as ``(s, n_2, n_1)``.
+    """
+
+    def __init__(self, instances, s, model, k, scheme="rdp", device=None):
+        n = len(instances)
+        arr = (Instance * n)()
+        for i, ins in enumerate(instances):
+            a = arr[i]
+            for q in range(2):
+                a.n[q] = int(ins["shape"][q])
+                h = ins.get("h")
+                a.h[q] = float(h[q]) if h is not None and h[q] else 0.0
+                b = ins["bcs"][q]
+                a.bc[q] = BC[b] if isinstance(b, str) else int(b)
+            for q, v in enumerate(ins["D"]):
+                a.D[q] = float(v)
+            rx = reaction_struct(model, ins["params"], ins.get("shift"), s)
+            for q in range(MAX_PARAMS):
+                a.params[q] = rx.params[q]
+            for q in range(MAX_SPECIES):
+                a.shift[q] = rx.shift[q]
+        sch = Scheme()
+        sch.scheme = SCHEMES[scheme]
+        ctx = ctypes.c_void_p()
+        _check(lib.etd_rdp_batch_init(n, arr, int(s), MODELS[model], float(k), ctypes.byref(sch),
+                                      ctypes.byref(ctx)), "etd_rdp_batch_init")
+        self._ctx = ctx
+        self.n, self.s = n, int(s)
+        self.shapes = [tuple(int(v) for v in ins["shape"]) for ins in instances]
+        offs = (ctypes.c_int64 * (n + 1))()
+        _check(lib.etd_rdp_batch_offsets(ctx, offs), "etd_rdp_batch_offsets")
+        self.offsets = [int(v) for v in offs]
+        nb = ctypes.c_size_t()
+        _check(lib.etd_rdp_batch_workspace_bytes(ctx, ctypes.byref(nb)), "etd_rdp_batch_workspace_bytes")
+        self.ws_bytes = nb.value
+        lp = ctypes.c_int32()
+        _check(lib.etd_rdp_batch_launches_per_step(ctx, ctypes.byref(lp)), "etd_rdp_batch_launches_per_step")
+        self.launches_per_step = lp.value
+        self._ws = None
+        self._device = device
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib.etd_rdp_batch_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            dev = self._device if self._device is not None else torch.device("cuda", torch.cuda.current_device())
+            self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        return self._ws
+
+    def _ws_ptr(self):
+        ws = self.workspace()
+        p = ws.data_ptr()
+        return p + (-p) % 256
+
+    def pack(self, states):
+        """Pack per-instance numpy/torch states (s, n_2, n_1) into one
+        float64 torch tensor (on the workspace's device)."""
+        import torch
+        ws = self.workspace()
+        u = torch.zeros(self.offsets[-1], dtype=torch.float64, device=ws.device)
+        for i, st in enumerate(states):
+            t = torch.as_tensor(st, dtype=torch.float64).reshape(-1)
+            u[self.offsets[i]: self.offsets[i] + t.numel()] = t.to(ws.device)
+        return u
+
+    def view(self, u, i):
+        n1, n2 = self.shapes[i]
+        return u[self.offsets[i]: self.offsets[i] + self.s * n1 * n2].view(self.s, n2, n1)
+
+    def step(self, u, nsteps=1, use_graph=True, stream=None):
+        import torch
+        if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous() or u.numel() != self.offsets[-1]:
+            raise ValueError("expected the packed contiguous float64 device state")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib.etd_rdp_batch_step(self._ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(self._ws_ptr()),
+                                      self.ws_bytes, int(nsteps), 1 if use_graph else 0,
+                                      ctypes.c_void_p(st.cuda_stream)), "etd_rdp_batch_step")
+        return u

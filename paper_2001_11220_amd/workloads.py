@@ -141,6 +141,45 @@ def schnakenberg3d_adjoint(n: int = 128, nsteps: int = 400, seed: int = 0) -> Pr
                    ic_args={"amp": 1e-3, "offset": SCHNAK_STEADY})
 
 
+@dataclass
+class Ensemble:
+    """A batch of independent 2-D problems (one reaction model, one k)."""
+    name: str
+    model: str
+    k: float
+    nsteps: int
+    instances: list          # dicts: shape, bcs, D, params
+    states: list             # initial states, (s, n_2, n_1) each
+
+    @property
+    def s(self) -> int:
+        return len(self.instances[0]["D"])
+
+    @property
+    def cell_species(self) -> int:
+        return sum(ins["shape"][0] * ins["shape"][1] for ins in self.instances) * self.s
+
+
+def brusselator_ensemble(ninst: int = 1024, nsteps: int = 200, seed: int = 0,
+                         sizes=tuple(range(64, 513, 32))) -> Ensemble:
+    """Independent 2-D Brusselators (a = 1): per instance, in draw order,
+    N ~ U(sizes), b ~ U[2, 4], D1, D2 ~ U[1e-3, 5e-2], bc_x, bc_y ~
+    U{Neumann, periodic}; square N x N grids on the unit square; initial data
+    0.5 + 0.1 U[0, 1) per cell and species; k = 0.005."""
+    rng = np.random.default_rng(seed)
+    insts = []
+    for _ in range(ninst):
+        n = int(rng.choice(np.asarray(sizes)))
+        b = float(rng.uniform(2.0, 4.0))
+        d1 = float(rng.uniform(1e-3, 5e-2))
+        d2 = float(rng.uniform(1e-3, 5e-2))
+        bcs = tuple("neumann" if rng.integers(2) == 0 else "periodic" for _ in range(2))
+        insts.append({"shape": (n, n), "bcs": bcs, "D": (d1, d2), "params": {"a": 1.0, "b": b}})
+    states = [np.stack([0.5 + 0.1 * rng.random((ins["shape"][1], ins["shape"][0])) for _ in range(2)])
+              for ins in insts]
+    return Ensemble("brusselator_ensemble", "brusselator", 0.005, nsteps, insts, states)
+
+
 WORKLOADS = {
     "brusselator2d": brusselator2d,
     "grayscott3d": grayscott3d,
