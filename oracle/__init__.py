@@ -32,4 +32,10 @@ from .etd_rdp_oracle import (  # noqa: F401
     etd1_if_step,
     r_rdp,
     r_pade01,
+    adjoint_step,
+    param_names,
+    reaction_jacobian,
+    reaction_param_grads,
+    solve_axis_T,
+    laplacian_axis,
 )

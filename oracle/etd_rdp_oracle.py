@@ -273,3 +273,187 @@ def etd1_if_step(U, k, D, bcs, hs, model, params):
     for i in range(1, U.ndim):
         y = solve_axis(y, i, k * D, bcs[i - 1], hs[i - 1])
     return y
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode of one step (not in the paper: the chain rule applied to the
+# frame of Section 6, used to check the GPU adjoint)
+# ---------------------------------------------------------------------------
+
+MODEL_PARAM_NAMES = {"enzyme": (), "brusselator": ("a", "b"), "gray_scott": ("F", "kappa"),
+                     "schnakenberg": ("a", "b", "gamma"), "cgl": ("beta",)}
+
+
+def param_names(model, s):
+    if model == "linear":
+        return tuple(f"C{i}{j}" for i in range(s) for j in range(s))
+    return MODEL_PARAM_NAMES[model]
+
+
+def reaction_jacobian(model, params, U):
+    """J[i][j] = dF_i/du_j at every cell (arrays shaped like U[0])."""
+    shift = params.get("shift")
+    if shift is not None:
+        U = U + np.asarray(shift, dtype=np.float64).reshape((-1,) + (1,) * (U.ndim - 1))
+    one = np.ones_like(U[0])
+    if model == "linear":
+        C = np.atleast_2d(np.asarray(params["C"], dtype=np.float64))
+        s = C.shape[0]
+        return [[C[i, j] * one for j in range(s)] for i in range(s)]
+    if model == "enzyme":
+        return [[-1.0 / (1.0 + U[0]) ** 2]]
+    u, v = U[0], U[1]
+    if model == "brusselator":
+        b = params["b"]
+        return [[-(b + 1.0) + 2 * u * v, u * u], [b - 2 * u * v, -u * u]]
+    if model == "gray_scott":
+        F, kap = params["F"], params["kappa"]
+        return [[-v * v - F, -2 * u * v], [v * v, 2 * u * v - (F + kap)]]
+    if model == "schnakenberg":
+        g = params["gamma"]
+        return [[g * (-1.0 + 2 * u * v), g * u * u], [-2 * g * u * v, -g * u * u]]
+    if model == "cgl":
+        beta = params["beta"]
+        p, q = u, v
+        m2 = p * p + q * q
+        return [[1 - m2 - 2 * p * (p - beta * q), beta * m2 - 2 * q * (p - beta * q)],
+                [-beta * m2 - 2 * p * (q + beta * p), 1 - m2 - 2 * q * (q + beta * p)]]
+    raise ValueError(model)
+
+
+def reaction_param_grads(model, params, U):
+    """dF/dtheta for each model parameter: a list (over parameters) of
+    arrays shaped like U."""
+    shift = params.get("shift")
+    if shift is not None:
+        U = U + np.asarray(shift, dtype=np.float64).reshape((-1,) + (1,) * (U.ndim - 1))
+    z = np.zeros_like(U[0])
+    one = np.ones_like(U[0])
+    if model == "linear":
+        s = U.shape[0]
+        out = []
+        for i in range(s):
+            for j in range(s):
+                g = np.zeros_like(U)
+                g[i] = U[j]
+                out.append(g)
+        return out
+    if model == "enzyme":
+        return []
+    u, v = U[0], U[1]
+    if model == "brusselator":
+        return [np.stack([one, z]), np.stack([-u, u])]
+    if model == "gray_scott":
+        return [np.stack([1.0 - u, -v]), np.stack([z, -v])]
+    if model == "schnakenberg":
+        a, b, g = params["a"], params["b"], params["gamma"]
+        return [np.stack([g * one, z]), np.stack([z, g * one]),
+                np.stack([a - u + u * u * v, b - u * u * v])]
+    if model == "cgl":
+        m2 = u * u + v * v
+        return [np.stack([v * m2, -u * m2])]
+    raise ValueError(model)
+
+
+def _jac_T(J, w):
+    s = len(J)
+    return np.stack([sum(J[i][j] * w[i] for i in range(s)) for j in range(s)])
+
+
+def solve_axis_T(U, axis, coefs, bc, h):
+    """Apply (I + c B_p)^{-T} along `axis` (dense transposed solve per species)."""
+    d = U.ndim - 1
+    npax = d - axis + 1
+    out = np.empty_like(U)
+    n = U.shape[npax]
+    for sigma in range(U.shape[0]):
+        M = line_matrix(n, bc, h, float(coefs[sigma]))
+        X = np.moveaxis(U[sigma], npax - 1, 0)
+        shp = X.shape
+        Y = np.linalg.solve(M.T, X.reshape(n, -1))
+        out[sigma] = np.moveaxis(Y.reshape(shp), 0, npax - 1)
+    return out
+
+
+def laplacian_axis(U, axis, bc, h):
+    """B_p (the discrete -Laplacian of Example 1) applied along `axis`."""
+    d = U.ndim - 1
+    npax = d - axis + 1
+    n = U.shape[npax]
+    B = laplacian_matrix(n, bc, h)
+    out = np.empty_like(U)
+    for sigma in range(U.shape[0]):
+        X = np.moveaxis(U[sigma], npax - 1, 0)
+        shp = X.shape
+        out[sigma] = np.moveaxis((B @ X.reshape(n, -1)).reshape(shp), 0, npax - 1)
+    return out
+
+
+def adjoint_step(U, lam, k, D, bcs, hs, model, params):
+    """Vector-Jacobian product of one ETD-RDP-IF step.
+
+    Given U_n and lam = dL/dU_{n+1}, returns (dL/dU_n, dL/dD, dL/dtheta) for
+    this step, where theta are the reaction parameters (``param_names``).
+    A solve x = M^{-1} y with M = I + (k/gamma) D_sigma B_p contributes
+    -(k/gamma) <M^{-T} xbar, B_p x>_sigma to dL/dD_sigma.
+    """
+    U = np.asarray(U, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    d = U.ndim - 1
+    s = U.shape[0]
+    gD = np.zeros(s)
+    gth = np.zeros(len(param_names(model, s)))
+
+    def dgrad(ybar, x, axis, gamma):
+        Lx = laplacian_axis(x, axis, bcs[axis - 1], hs[axis - 1])
+        for sg in range(s):
+            gD[sg] += -(k / gamma) * float(np.sum(ybar[sg] * Lx[sg]))
+
+    def pgrad(Uat, fbar):
+        for i, dF in enumerate(reaction_param_grads(model, params, Uat)):
+            gth[i] += float(np.sum(dF * fbar))
+
+    # forward recomputation
+    f = reaction(model, params, U)
+    ys = [U + k * f]
+    for i in range(1, d + 1):
+        ys.append(solve_axis(ys[-1], i, k * D, bcs[i - 1], hs[i - 1]))
+    Ustar = ys[d]
+    cU, cf = [U], [f]
+    for i in range(1, d):
+        cU.append(apply_R(cU[-1], i, k, D, bcs[i - 1], hs[i - 1]))
+        cf.append(apply_R(cf[-1], i, k, D, bcs[i - 1], hs[i - 1]))
+    fs = reaction(model, params, Ustar)
+    f1 = 9.0 * cU[-1] + 2.0 * k * cf[-1] + k * fs
+    f2 = 8.0 * cU[-1] + 1.5 * k * cf[-1] + 0.5 * k * fs
+    bd, hd = bcs[d - 1], hs[d - 1]
+    # reverse: U_{n+1} = T_d f1 - S_d f2
+    a = solve_axis_T(lam, d, k * D / 3.0, bd, hd)
+    b = solve_axis_T(lam, d, k * D / 4.0, bd, hd)
+    dgrad(a, solve_axis(f1, d, k * D / 3.0, bd, hd), d, 3.0)
+    dgrad(-b, solve_axis(f2, d, k * D / 4.0, bd, hd), d, 4.0)
+    fsbar = k * a - 0.5 * k * b
+    pgrad(Ustar, fsbar)
+    ybar = _jac_T(reaction_jacobian(model, params, Ustar), fsbar)
+    cUbar = 9.0 * a - 8.0 * b
+    cfbar = 2.0 * k * a - 1.5 * k * b
+    for i in range(d, 0, -1):  # predictor chain P_d ... P_1
+        yin = solve_axis_T(ybar, i, k * D, bcs[i - 1], hs[i - 1])
+        dgrad(yin, ys[i], i, 1.0)
+        ybar = yin
+    nu = ybar
+    for i in range(d - 1, 0, -1):  # R chains, R_i = 9 T_i - 8 S_i
+        bc_, h_ = bcs[i - 1], hs[i - 1]
+        nxt = []
+        for cbar, cin in ((cUbar, cU[i - 1]), (cfbar, cf[i - 1])):
+            tb = solve_axis_T(9.0 * cbar, i, k * D / 3.0, bc_, h_)
+            sb = solve_axis_T(-8.0 * cbar, i, k * D / 4.0, bc_, h_)
+            dgrad(tb, solve_axis(cin, i, k * D / 3.0, bc_, h_), i, 3.0)
+            dgrad(sb, solve_axis(cin, i, k * D / 4.0, bc_, h_), i, 4.0)
+            nxt.append(tb + sb)
+        cUbar, cfbar = nxt
+    fbar = cfbar + k * nu
+    pgrad(U, fbar)
+    lam_n = cUbar + nu + _jac_T(reaction_jacobian(model, params, U), fbar)
+    return lam_n, gD, gth
