@@ -201,6 +201,52 @@ int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m,
                        int32_t* chunks);
 
 /* ======================================================================
+ * Reverse mode (gradients through a time step).
+ *
+ * The scheme is differentiated exactly, step by step, as a function of the
+ * state U_n, the diffusion coefficients D and the reaction parameters theta
+ * (the chain rule of the frame of Section 6, eqs. done / donedone; the paper
+ * itself gives no adjoint).  A gradient vector holds etd_rdp_grad_size()
+ * doubles: dL/dD_0 .. dL/dD_{s-1}, then dL/dtheta for the model's parameters
+ * in params[] order (linear: C row-major; enzyme: none; Brusselator: a, b;
+ * Gray-Scott: F, kappa; Schnakenberg: a, b, gamma; CGL: beta).  The shift is
+ * a constant, not a parameter.
+ * ====================================================================== */
+
+/* Number of gradient entries, s + (number of reaction parameters). */
+int etd_rdp_grad_size(const etd_rdp_ctx* ctx, int32_t* n);
+
+/* Device workspace bytes etd_rdp_adjoint needs: the tables, 6 (d = 3) or 3
+ * (d = 2) carried arrays of s*N doubles and the gradient block sums.  It is
+ * at least etd_rdp_workspace_bytes, and etd_rdp_step accepts the same buffer
+ * (with the same layout of its first three carried arrays), so one
+ * workspace serves a forward sweep and its reverse sweep. */
+int etd_rdp_adjoint_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
+
+/*
+ * etd_rdp_adjoint -- one reverse step.  With U_{n+1} = Phi(U_n; D, theta)
+ * the step etd_rdp_step takes:
+ *   lam_n = (dPhi/dU_n)^T lam_np1,
+ *   grad += (dPhi/d(D, theta))^T lam_np1   (accumulated, not overwritten).
+ *
+ *  u_n     : device, s*N doubles (layout of u), the state the step started
+ *            from; read only.
+ *  lam_np1 : device, s*N doubles, dL/dU_{n+1}; read only.
+ *  lam_n   : device, s*N doubles, receives dL/dU_n.  May be lam_np1 (the
+ *            update is then in place); must not overlap u_n.
+ *  grad    : device, etd_rdp_grad_size() doubles, caller-initialised.
+ *  ws      : device workspace of etd_rdp_adjoint_workspace_bytes, 256-byte
+ *            aligned; its carried arrays are overwritten.
+ * The result is bitwise reproducible for a given device (fixed reduction
+ * order).  Asynchronous on `stream`.
+ * Errors: ETD_ERR_ARG (NULL pointer, u_n == lam_n), ETD_ERR_UNSUPPORTED
+ * (scheme ETD1), ETD_ERR_WORKSPACE, ETD_ERR_HIP.
+ */
+int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1,
+                    double* lam_n, double* grad, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* ======================================================================
  * Ensembles: many independent 2-D problems of uneven size advanced together.
  * All instances share the number of species s, the reaction model, the time
  * step k and the scheme; each has its own grid, boundary conditions,

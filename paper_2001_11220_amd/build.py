@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libetdrdp.so")
 
-SOURCES = ["etd_rdp.hip", "etd_batch.hip", "etd_tables.cpp"]
+SOURCES = ["etd_rdp.hip", "etd_adjoint.hip", "etd_batch.hip", "etd_tables.cpp"]
 
 HIPCC_FLAGS = [
     "-O3",

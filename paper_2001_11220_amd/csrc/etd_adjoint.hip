@@ -1,0 +1,655 @@
+// Reverse mode of one ETD-RDP-IF step on gfx950: given U_n and
+// lam = dL/dU_{n+1}, computes dL/dU_n and accumulates dL/dD (diffusion
+// coefficients) and dL/dtheta (reaction parameters).
+//
+// The step of Section 6 (eq. donedone for d = 3) is
+//   U* = P_d...P_1 (U + k f),  f = F(U)
+//   U_{n+1} = T_d f1 - S_d f2,  f1 = 9 R'U + 2k R'f + k f*,
+//                               f2 = 8 R'U + 3k/2 R'f + k/2 f*
+// with R' = R_{d-1}...R_1, f* = F(U*).  Its chain rule, pass by pass in
+// reverse order (axis d first):
+//   a = T_d^T lam, b = S_d^T lam
+//   f*bar = k a - k/2 b;  mu = J(U*)^T f*bar;  nu = P_1^T...P_d^T mu
+//   (R'U)bar = 9a - 8b,  (R'f)bar = 2k a - 3k/2 b, pulled back through
+//   R_i^T = 9 T_i^T - 8 S_i^T for i = d-1..1
+//   fbar = R'^T (R'f)bar + k nu,  lam_n = R'^T (R'U)bar + nu + J(U)^T fbar
+//   dL/dtheta += (dF/dtheta(U))^T fbar + (dF/dtheta(U*))^T f*bar
+// and every solve x = M^{-1} y, M = I + (k/gamma) D_sigma A_i, adds
+// -(k/gamma) <M^{-T} xbar, A_i x / D_sigma> to dL/dD_sigma.
+//
+// Transposed solves reuse the forward tables: A_i is symmetric for
+// Dirichlet and periodic closures, and for the Neumann closure of
+// Example 1 W A_i is symmetric with W = diag(1/2, 1, ..., 1, 1/2), so
+// M^{-T} = W M^{-1} W^{-1}: double the two end rows, solve, halve them.
+//
+// Kernels (one wavefront per line, as in the forward passes):
+//   ka_last   axis d: recompute U*, f*, f1, f2; 6 solves per species
+//   ka_mid    axis 2 of 3-D: 10 solves per species
+//   ka_first  axis 1: recompute f, U + k f; 10 solves per species; lam_n
+// The forward carried arrays the reverse passes need come from a forward
+// recompute into two workspace triples.  Gradient sums are per-block
+// partials in the workspace, added in a fixed order by one final kernel,
+// so a call is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "etd_ctx.hpp"
+#include "etd_device.hpp"
+#include "etd_launch.hpp"
+#include "etd_rdp.h"
+#include "etd_tables.hpp"
+
+namespace etd {
+
+constexpr int kRed = kBlockLines * kGradSlots;  // LDS doubles for block sums
+
+// Neumann transposes: scale the line's first and last rows by f.
+template <int M>
+__device__ __forceinline__ void ends_scale(double (&x)[M], int lane, int C, double f) {
+  x[0] *= (lane == 0) ? f : 1.0;
+  x[M - 1] *= (lane == C - 1) ? f : 1.0;
+}
+
+// sum_j yb_j (B x)_j over this lane's rows, B the second difference
+// [-1 2 -1] of the axis with its boundary closure (Example 1); 0 on lanes
+// without a chunk.  All 64 lanes must call it together.
+template <int M>
+__device__ __forceinline__ double lap_dot(const double (&yb)[M], const double (&x)[M], int lane,
+                                          int C, int bc) {
+  const int lane4 = lane * 4;
+  const double pl = bperm((lane4 - 4) & 255, x[M - 1]);  // row c*M - 1
+  const double pr = bperm((lane4 + 4) & 255, x[0]);      // row c*M + M
+  const double xlast = lane_value(x[M - 1], C - 1);
+  const double xfirst = lane_value(x[0], 0);
+  double xl = pl, xr = pr;
+  if (lane == 0) {
+    xl = (bc == ETD_BC_PERIODIC) ? xlast : 0.0;
+    if (bc == ETD_BC_NEUMANN) xl = (M > 1) ? x[M > 1 ? 1 : 0] : pr;
+  }
+  if (lane == C - 1) {
+    xr = (bc == ETD_BC_PERIODIC) ? xfirst : 0.0;
+    if (bc == ETD_BC_NEUMANN) xr = (M > 1) ? x[M > 1 ? M - 2 : 0] : pl;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double left = (j > 0) ? x[j > 0 ? j - 1 : 0] : xl;
+    const double right = (j < M - 1) ? x[j < M - 1 ? j + 1 : 0] : xr;
+    acc = fma(yb[j], 2.0 * x[j] - left - right, acc);
+  }
+  return (lane < C) ? acc : 0.0;
+}
+
+// At one cell u (+ shift): jt = J(u)^T fb and g[p] = (dF/dtheta_p(u)) . fb.
+template <int S>
+__device__ __forceinline__ void react_adj(const Rx& rx, const double (&uin)[S],
+                                          const double (&fb)[S], double (&jt)[S],
+                                          double (&g)[kGradSlots - S]) {
+#pragma unroll
+  for (int p = 0; p < kGradSlots - S; ++p) g[p] = 0.0;
+  double u[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) u[i] = uin[i] + rx.shift[i];
+  if (rx.model == kLinear) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < S; ++i) acc = fma(rx.p[i * S + j], fb[i], acc);
+      jt[j] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) g[i * S + j] = fb[i] * u[j];
+    return;
+  }
+  if constexpr (S == 1) {
+    const double q = 1.0 / (1.0 + u[0]);
+    jt[0] = -q * q * fb[0];
+  } else {
+    const double a = u[0], b = u[1], f0 = fb[0], f1 = fb[1];
+    if (rx.model == kBrusselator) {
+      const double B = rx.p[1];
+      const double ab2 = 2.0 * a * b, aa = a * a;
+      jt[0] = (ab2 - B - 1.0) * f0 + (B - ab2) * f1;
+      jt[1] = aa * (f0 - f1);
+      g[0] = f0;
+      g[1] = a * (f1 - f0);
+    } else if (rx.model == kGrayScott) {
+      const double F = rx.p[0], kap = rx.p[1];
+      const double bb = b * b, ab2 = 2.0 * a * b;
+      jt[0] = (-bb - F) * f0 + bb * f1;
+      jt[1] = -ab2 * f0 + (ab2 - F - kap) * f1;
+      g[0] = (1.0 - a) * f0 - b * f1;
+      g[1] = -b * f1;
+    } else if (rx.model == kSchnakenberg) {
+      const double A = rx.p[0], B = rx.p[1], gm = rx.p[2];
+      const double aab = a * a * b, ab2 = 2.0 * a * b, aa = a * a;
+      jt[0] = gm * ((ab2 - 1.0) * f0 - ab2 * f1);
+      jt[1] = gm * aa * (f0 - f1);
+      g[0] = gm * f0;
+      g[1] = gm * f1;
+      g[2] = (A - a + aab) * f0 + (B - aab) * f1;
+    } else {  // complex Ginzburg-Landau
+      const double beta = rx.p[0];
+      const double m2 = a * a + b * b;
+      const double pa = a - beta * b, pb = b + beta * a;
+      const double j00 = 1.0 - m2 - 2.0 * a * pa, j01 = beta * m2 - 2.0 * b * pa;
+      const double j10 = -beta * m2 - 2.0 * a * pb, j11 = 1.0 - m2 - 2.0 * b * pb;
+      jt[0] = j00 * f0 + j10 * f1;
+      jt[1] = j01 * f0 + j11 * f1;
+      g[0] = m2 * (b * f0 - a * f1);
+    }
+  }
+}
+
+// Block sum of acc[] (fixed order) into part[blockIdx.x][*].  All threads of
+// the block call it once, at the end of the kernel.
+__device__ __forceinline__ void block_partials(const double (&acc)[kGradSlots], double* red,
+                                               double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kGradSlots; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wv * kGradSlots + q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kGradSlots) {
+    double t = 0.0;
+    for (int w = 0; w < kBlockLines; ++w) t += red[w * kGradSlots + threadIdx.x];
+    part[(int64_t)blockIdx.x * kGradSlots + threadIdx.x] = t;
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void tile_load(const double* __restrict__ A, double (&x)[M], double* tl,
+                                          const Geom& g, const TilePos& p, TileCursor& cur) {
+  double r[M];
+  tile_fetch<M>(A, r, g, p.base, p.f0);
+  tile_commit<M>(r, x, tl, g, cur);
+}
+
+// ---------------------------------------------------------------------------
+// Axis d (last forward pass).  In: the forward carried (c, cf, w) that pass d
+// reads (R'U, R'f, P_{d-1}...P_1 (U + k f)) and lam; out, in place: their
+// adjoints ((R'U)bar, (R'f)bar, P_d^T mu).
+// ---------------------------------------------------------------------------
+template <int M, int S>
+__global__ __launch_bounds__(kBlock) void ka_last(
+    double* c1, double* c2, double* w, const double* __restrict__ lam,
+    const SolveTab* __restrict__ tabs, Rx rx, double k, Geom g, int bc, double dsc,
+    double* __restrict__ part) {
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  double* tl = red + kRed;
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int C = g.C;
+  const bool neu = (bc == ETD_BC_NEUMANN);
+  const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
+  double acc[kGradSlots];
+#pragma unroll
+  for (int q = 0; q < kGradSlots; ++q) acc[q] = 0.0;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const TilePos pos(tile, g);
+    const bool valid = (lane < C) && (pos.f0 + wv < g.nF);
+    double us[S][M], fb[S][M];
+#pragma unroll
+    for (int s = 0; s < S; ++s) tile_load<M>(w + s * g.N, us[s], tl, g, pos, cur);
+    {
+      const SolveTab* tb[S];
+      const LaneTab* lb[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        tb[s] = at.P(s);
+        lb[s] = at.lP(s);
+      }
+      line_solve<M, S>(tb, lb, us, lane);  // U*
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double uu[S], ff[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) uu[s] = us[s][j];
+      react<S>(rx, uu, ff);
+#pragma unroll
+      for (int s = 0; s < S; ++s) fb[s][j] = ff[s];  // f*
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double x[4][M], cb[M];
+      tile_load<M>(c1 + s * g.N, x[0], tl, g, pos, cur);
+      tile_load<M>(c2 + s * g.N, cb, tl, g, pos, cur);
+      tile_load<M>(lam + s * g.N, x[2], tl, g, pos, cur);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const double ca = x[0][j];
+        x[0][j] = fma(k, fb[s][j], fma(k2, cb[j], 9.0 * ca));
+        x[1][j] = fma(k05, fb[s][j], fma(k15, cb[j], 8.0 * ca));
+        x[3][j] = x[2][j];
+      }
+      if (neu) {
+        ends_scale<M>(x[2], lane, C, 2.0);
+        ends_scale<M>(x[3], lane, C, 2.0);
+      }
+      const SolveTab* tb[4] = {at.T(s), at.Sx(s), at.T(s), at.Sx(s)};
+      const LaneTab* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
+      line_solve<M, 4>(tb, lb, x, lane);
+      if (neu) {
+        ends_scale<M>(x[2], lane, C, 0.5);
+        ends_scale<M>(x[3], lane, C, 0.5);
+      }
+      // x[2] = a = T^T lam, x[3] = b = S^T lam
+      acc[s] += (dsc / 3.0) * lap_dot<M>(x[2], x[0], lane, C, bc) -
+                (dsc / 4.0) * lap_dot<M>(x[3], x[1], lane, C, bc);
+      double o[M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) o[j] = fma(9.0, x[2][j], -8.0 * x[3][j]);
+      tile_store<M>(c1 + s * g.N, o, tl, g, pos.base, pos.f0, cur);
+#pragma unroll
+      for (int j = 0; j < M; ++j) o[j] = fma(k2, x[2][j], -k15 * x[3][j]);
+      tile_store<M>(c2 + s * g.N, o, tl, g, pos.base, pos.f0, cur);
+#pragma unroll
+      for (int j = 0; j < M; ++j) fb[s][j] = fma(k, x[2][j], -k05 * x[3][j]);  // f*bar
+    }
+    // mu = J(U*)^T f*bar, parameter gradient at U*.
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double uu[S], ff[S], jt[S], gp[kGradSlots - S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        uu[s] = us[s][j];
+        ff[s] = fb[s][j];
+      }
+      react_adj<S>(rx, uu, ff, jt, gp);
+#pragma unroll
+      for (int s = 0; s < S; ++s) fb[s][j] = jt[s];
+#pragma unroll
+      for (int q = 0; q < kGradSlots - S; ++q) acc[S + q] += valid ? gp[q] : 0.0;
+    }
+    {
+      const SolveTab* tb[S];
+      const LaneTab* lb[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        tb[s] = at.P(s);
+        lb[s] = at.lP(s);
+        if (neu) ends_scale<M>(fb[s], lane, C, 2.0);
+      }
+      line_solve<M, S>(tb, lb, fb, lane);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (neu) ends_scale<M>(fb[s], lane, C, 0.5);
+      acc[s] += dsc * lap_dot<M>(fb[s], us[s], lane, C, bc);
+      tile_store<M>(w + s * g.N, fb[s], tl, g, pos.base, pos.f0, cur);
+    }
+  }
+  block_partials(acc, red, part);
+}
+
+// ---------------------------------------------------------------------------
+// Axis 2 of a 3-D step.  In: the forward carried (c1, c2, w) after pass 1
+// (R_1 U, R_1 f, P_1 (U + k f)) and the adjoints (b1, b2, bw) of pass 2's
+// outputs; out, in place of (c1, c2, w): the adjoints of pass 2's inputs.
+// ---------------------------------------------------------------------------
+template <int M, int S>
+__global__ __launch_bounds__(kBlock) void ka_mid(
+    double* c1, double* c2, double* w, const double* __restrict__ b1,
+    const double* __restrict__ b2, const double* __restrict__ bw,
+    const SolveTab* __restrict__ tabs, Geom g, int bc, double dsc, double* __restrict__ part) {
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  double* tl = red + kRed;
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63;
+  const int C = g.C;
+  const bool neu = (bc == ETD_BC_NEUMANN);
+  double acc[kGradSlots];
+#pragma unroll
+  for (int q = 0; q < kGradSlots; ++q) acc[q] = 0.0;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const TilePos pos(tile, g);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double* const fw[2] = {c1 + s * g.N, c2 + s * g.N};
+      const double* const bk[2] = {b1 + s * g.N, b2 + s * g.N};
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {  // R_2 U-chain, then f-chain
+        double x[4][M];
+        tile_load<M>(fw[r], x[0], tl, g, pos, cur);
+        tile_load<M>(bk[r], x[2], tl, g, pos, cur);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          x[1][j] = x[0][j];
+          x[3][j] = x[2][j];
+        }
+        if (neu) {
+          ends_scale<M>(x[2], lane, C, 2.0);
+          ends_scale<M>(x[3], lane, C, 2.0);
+        }
+        const SolveTab* tb[4] = {at.T(s), at.Sx(s), at.T(s), at.Sx(s)};
+        const LaneTab* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
+        line_solve<M, 4>(tb, lb, x, lane);
+        if (neu) {
+          ends_scale<M>(x[2], lane, C, 0.5);
+          ends_scale<M>(x[3], lane, C, 0.5);
+        }
+        acc[s] += (3.0 * dsc) * lap_dot<M>(x[2], x[0], lane, C, bc) -
+                  (2.0 * dsc) * lap_dot<M>(x[3], x[1], lane, C, bc);
+        double o[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) o[j] = fma(9.0, x[2][j], -8.0 * x[3][j]);
+        tile_store<M>(fw[r], o, tl, g, pos.base, pos.f0, cur);
+      }
+      double y[2][M];
+      tile_load<M>(w + s * g.N, y[0], tl, g, pos, cur);
+      tile_load<M>(bw + s * g.N, y[1], tl, g, pos, cur);
+      if (neu) ends_scale<M>(y[1], lane, C, 2.0);
+      const SolveTab* tb[2] = {at.P(s), at.P(s)};
+      const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
+      line_solve<M, 2>(tb, lb, y, lane);
+      if (neu) ends_scale<M>(y[1], lane, C, 0.5);
+      acc[s] += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
+      tile_store<M>(w + s * g.N, y[1], tl, g, pos.base, pos.f0, cur);
+    }
+  }
+  block_partials(acc, red, part);
+}
+
+// ---------------------------------------------------------------------------
+// Axis 1 (first forward pass).  In: U_n and the adjoints (b1, b2, bw) of
+// pass 1's outputs (R_1 U, R_1 f, P_1 (U + k f)); out: lam_n.
+// ---------------------------------------------------------------------------
+template <int M, int S>
+__global__ __launch_bounds__(kBlock) void ka_first(
+    const double* __restrict__ u, const double* __restrict__ b1,
+    const double* __restrict__ b2, const double* __restrict__ bw,
+    double* __restrict__ lam_out, const SolveTab* __restrict__ tabs, Rx rx, double k,
+    int64_t n1, int64_t nlines, int64_t N, int bc, double dsc, double* __restrict__ part) {
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int C = tabs[0].C;
+  const bool act = lane < C;
+  const bool neu = (bc == ETD_BC_NEUMANN);
+  double acc[kGradSlots];
+#pragma unroll
+  for (int q = 0; q < kGradSlots; ++q) acc[q] = 0.0;
+  TileWalk walk((nlines + kBlockLines - 1) / kBlockLines);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const int64_t line = tile * kBlockLines + wv;
+    if (line >= nlines) continue;  // wave-uniform
+    const int64_t off = line * n1 + (int64_t)lane * M;
+    double U[S][M], f[S][M], Ub[S][M], fbar[S][M];
+#pragma unroll
+    for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + off, U[s], act);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double uu[S], ff[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) uu[s] = U[s][j];
+      react<S>(rx, uu, ff);
+#pragma unroll
+      for (int s = 0; s < S; ++s) f[s][j] = ff[s];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {  // R_1 U, then R_1 f
+        double x[4][M];
+        load_chunk<M>((r == 0 ? b1 : b2) + s * N + off, x[2], act);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          x[0][j] = (r == 0) ? U[s][j] : f[s][j];
+          x[1][j] = x[0][j];
+          x[3][j] = x[2][j];
+        }
+        if (neu) {
+          ends_scale<M>(x[2], lane, C, 2.0);
+          ends_scale<M>(x[3], lane, C, 2.0);
+        }
+        const SolveTab* tb[4] = {at.T(s), at.Sx(s), at.T(s), at.Sx(s)};
+        const LaneTab* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
+        line_solve<M, 4>(tb, lb, x, lane);
+        if (neu) {
+          ends_scale<M>(x[2], lane, C, 0.5);
+          ends_scale<M>(x[3], lane, C, 0.5);
+        }
+        acc[s] += (3.0 * dsc) * lap_dot<M>(x[2], x[0], lane, C, bc) -
+                  (2.0 * dsc) * lap_dot<M>(x[3], x[1], lane, C, bc);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const double v = fma(9.0, x[2][j], -8.0 * x[3][j]);
+          if (r == 0) Ub[s][j] = v;
+          else fbar[s][j] = v;
+        }
+      }
+      double y[2][M];
+      load_chunk<M>(bw + s * N + off, y[1], act);
+#pragma unroll
+      for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[s][j], U[s][j]);
+      if (neu) ends_scale<M>(y[1], lane, C, 2.0);
+      const SolveTab* tb[2] = {at.P(s), at.P(s)};
+      const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
+      line_solve<M, 2>(tb, lb, y, lane);
+      if (neu) ends_scale<M>(y[1], lane, C, 0.5);
+      acc[s] += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        Ub[s][j] += y[1][j];
+        fbar[s][j] = fma(k, y[1][j], fbar[s][j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double uu[S], ff[S], jt[S], gp[kGradSlots - S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        uu[s] = U[s][j];
+        ff[s] = fbar[s][j];
+      }
+      react_adj<S>(rx, uu, ff, jt, gp);
+#pragma unroll
+      for (int s = 0; s < S; ++s) Ub[s][j] += jt[s];
+#pragma unroll
+      for (int q = 0; q < kGradSlots - S; ++q) acc[S + q] += act ? gp[q] : 0.0;
+    }
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) store_chunk<M>(lam_out + s * N + off, Ub[s]);
+    }
+  }
+  block_partials(acc, red, part);
+}
+
+// grad[q] += sum over passes p < npass and blocks b < nblk[p] of
+// part[p][b][q], q < nq, in a fixed order.  One block of 256 threads.
+__global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ part, int nb0,
+                                                     int nb1, int nb2, int nq,
+                                                     double* __restrict__ grad) {
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  const int nb[kAdjPasses] = {nb0, nb1, nb2};
+  for (int q = 0; q < nq; ++q) {
+    double t = 0.0;
+    for (int p = 0; p < kAdjPasses; ++p) {
+      const double* src = part + (int64_t)p * kAdjMaxBlocks * kGradSlots;
+      for (int b = tid; b < nb[p]; b += 256) t += src[(int64_t)b * kGradSlots + q];
+    }
+    sh[tid] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) sh[tid] += sh[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) grad[q] += sh[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+inline size_t adj_fixed_lds(int S) { return lane_lds(3 * S) + sizeof(double) * kRed; }
+
+template <typename KernelT>
+hipError_t adj_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid) {
+  hipError_t e = set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  e = persistent_grid(kern, lds, ntiles, grid);
+  if (e != hipSuccess) return e;
+  if (*grid > static_cast<unsigned>(kAdjMaxBlocks)) *grid = kAdjMaxBlocks;
+  return hipSuccess;
+}
+
+double d_scale(const etd_rdp_ctx* c, int axis0) { return -c->k / (c->h[axis0] * c->h[axis0]); }
+
+template <int M, int S>
+hipError_t launch_ka_last(const etd_rdp_ctx* c, double* const (&X)[3], const double* lam,
+                          const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
+  const int a = c->d - 1;
+  const size_t fixed = adj_fixed_lds(S);
+  const Geom g = make_geom(c, a, fixed);
+  const size_t lds = geom_lds(g, fixed);
+  hipError_t e = adj_grid(ka_last<M, S>, lds, g.nFblk * g.nT, nblk);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((ka_last<M, S>), dim3(*nblk), dim3(kBlock), lds, st, X[0], X[1], X[2], lam,
+                     tabs, c->rx, c->k, g, c->bc[a], d_scale(c, a), part);
+  return hipGetLastError();
+}
+
+template <int M, int S>
+hipError_t launch_ka_mid(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&B)[3],
+                         const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
+  const int a = 1;
+  const size_t fixed = adj_fixed_lds(S);
+  const Geom g = make_geom(c, a, fixed);
+  const size_t lds = geom_lds(g, fixed);
+  hipError_t e = adj_grid(ka_mid<M, S>, lds, g.nFblk * g.nT, nblk);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((ka_mid<M, S>), dim3(*nblk), dim3(kBlock), lds, st, A[0], A[1], A[2], B[0],
+                     B[1], B[2], tabs, g, c->bc[a], d_scale(c, a), part);
+  return hipGetLastError();
+}
+
+template <int M, int S>
+hipError_t launch_ka_first(const etd_rdp_ctx* c, const double* u, double* const (&A)[3],
+                           double* lam_out, const SolveTab* tabs, double* part, unsigned* nblk,
+                           hipStream_t st) {
+  const int64_t nlines = c->N / c->n[0];
+  const size_t lds = adj_fixed_lds(S);
+  hipError_t e = adj_grid(ka_first<M, S>, lds, (nlines + kBlockLines - 1) / kBlockLines, nblk);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((ka_first<M, S>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1], A[2],
+                     lam_out, tabs, c->rx, c->k, c->n[0], nlines, c->N, c->bc[0], d_scale(c, 0),
+                     part);
+  return hipGetLastError();
+}
+
+int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* lam_out,
+                double* grad, void* ws, hipStream_t st) {
+  const SolveTab* tabs = static_cast<const SolveTab*>(ws);
+  double* const A[3] = {ws_array(c, ws, 0), ws_array(c, ws, 1), ws_array(c, ws, 2)};
+  const int nB = (c->d == 3) ? 3 : 0;
+  double* const B[3] = {ws_array(c, ws, nB), ws_array(c, ws, nB + 1), ws_array(c, ws, nB + 2)};
+  double* part = ws_array(c, ws, c->d == 3 ? 6 : 3);
+  const int S = c->s;
+  // Forward recompute of the carried triples: A after pass 1, B after pass 2.
+  int rc = launch_pass(c, 0, const_cast<double*>(u), A, A, tabs, st);
+  if (rc) return rc;
+  if (c->d == 3) {
+    rc = launch_pass(c, 1, nullptr, A, B, tabs, st);
+    if (rc) return rc;
+  }
+  unsigned nb[kAdjPasses] = {0, 0, 0};
+  hipError_t e = hipSuccess;
+  // Axis d: reads the triple pass d reads (B in 3-D, A in 2-D) and lam.
+  {
+    const int a = c->d - 1, m = c->m[a];
+    const SolveTab* ta = tabs + tab_index(a, 0, 0, S);
+    double* const(&X)[3] = (c->d == 3) ? B : A;
+    double* pp = part;
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 1>(c, X, lam_in, ta, pp, &nb[0], st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 2>(c, X, lam_in, ta, pp, &nb[0], st))); }
+    if (e != hipSuccess) return hip_fail(c, e);
+  }
+  if (c->d == 3) {
+    const int m = c->m[1];
+    const SolveTab* ta = tabs + tab_index(1, 0, 0, S);
+    double* pp = part + (size_t)kAdjMaxBlocks * kGradSlots;
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 1>(c, A, B, ta, pp, &nb[1], st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 2>(c, A, B, ta, pp, &nb[1], st))); }
+    if (e != hipSuccess) return hip_fail(c, e);
+  }
+  {
+    const int m = c->m[0];
+    const SolveTab* ta = tabs + tab_index(0, 0, 0, S);
+    double* pp = part + 2 * (size_t)kAdjMaxBlocks * kGradSlots;
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1>(c, u, A, lam_out, ta, pp, &nb[2], st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 2>(c, u, A, lam_out, ta, pp, &nb[2], st))); }
+    if (e != hipSuccess) return hip_fail(c, e);
+  }
+  hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, part, (int)nb[0], (int)nb[1],
+                     (int)nb[2], c->s + c->nparams, grad);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e);
+  return ETD_OK;
+}
+
+}  // namespace
+}  // namespace etd
+
+using namespace etd;
+
+extern "C" {
+
+int etd_rdp_grad_size(const etd_rdp_ctx* ctx, int32_t* n) {
+  if (!ctx || !n) return ETD_ERR_ARG;
+  *n = ctx->s + ctx->nparams;
+  return ETD_OK;
+}
+
+int etd_rdp_adjoint_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return ETD_ERR_ARG;
+  *bytes = ctx->adj_ws_bytes;
+  return ETD_OK;
+}
+
+int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1, double* lam_n,
+                    double* grad, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !u_n || !lam_np1 || !lam_n || !grad) return ETD_ERR_ARG;
+  if (u_n == lam_n) return ETD_ERR_ARG;
+  if (ctx->scheme != ETD_SCHEME_RDP) return ETD_ERR_UNSUPPORTED;
+  int rc = check_ws(ws, ws_bytes, ctx->adj_ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  return run_adjoint(ctx, u_n, lam_np1, lam_n, grad, ws, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Host-side state of one single-problem context and the helpers that the
+// forward stepper (etd_rdp.hip) and the reverse-mode step (etd_adjoint.hip)
+// share.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "etd_device.hpp"
+#include "etd_rdp.h"
+#include "etd_tables.hpp"
+
+struct etd_rdp_ctx {
+  int d = 0, s = 0;
+  int64_t n[3] = {1, 1, 1};
+  double h[3] = {0, 0, 0};
+  int bc[3] = {0, 0, 0};
+  double D[ETD_MAX_SPECIES] = {0, 0};
+  double k = 0;
+  int scheme = ETD_SCHEME_RDP;
+  etd::Rx rx{};
+  int nparams = 0;             // reaction parameters with a gradient
+  int m[3] = {0, 0, 0};
+  int64_t N = 0;
+  std::vector<etd::SolveTab> tabs;  // [axis][species][3]
+  size_t tab_bytes = 0, arr_bytes = 0, ws_bytes = 0;
+  size_t part_bytes = 0, adj_ws_bytes = 0;
+  const void* uploaded_ws = nullptr;
+  int last_hip = 0;
+};
+
+namespace etd {
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Reverse-mode step: gradient slots per block (s diffusion coefficients, then
+// the reaction parameters), the most blocks a reverse pass launches, and the
+// number of reverse passes that write block partial sums.
+constexpr int kGradSlots = 8;
+constexpr int kAdjMaxBlocks = 2048;
+constexpr int kAdjPasses = 3;
+
+// Reaction parameters of a model that carry a gradient (its params[] prefix).
+int reaction_param_count(int model, int s);
+
+// Records e in the context and returns ETD_ERR_HIP.
+int hip_fail(etd_rdp_ctx* c, hipError_t e);
+
+// ETD_ERR_WORKSPACE unless ws is non-NULL, 256-byte aligned and has at least
+// `need` bytes.
+int check_ws(const void* ws, size_t have, size_t need);
+
+// Uploads the tables to the front of ws, unless ws already holds them.
+int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st);
+
+// Geometry of a strided pass over axis axis0 (0-based, >= 1).
+Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds);
+size_t geom_lds(const Geom& g, size_t fixed_lds);
+
+// The i-th carried array (s*N doubles) of a workspace.
+inline double* ws_array(const etd_rdp_ctx* c, void* ws, int i) {
+  return reinterpret_cast<double*>(static_cast<char*>(ws) + c->tab_bytes + i * c->arr_bytes);
+}
+
+// Launches forward pass p (0-based) of one step.  Pass 0 reads u and writes
+// the carried triple `out`; a middle pass reads `in` and writes `out` (the
+// two may be the same arrays); the last pass reads `in` and writes u.
+int launch_pass(etd_rdp_ctx* c, int p, double* u, double* const (&in)[3],
+                double* const (&out)[3], const SolveTab* tabs, hipStream_t st);
+
+}  // namespace etd

@@ -29,6 +29,7 @@
 #include "etd_device.hpp"
 #include "etd_launch.hpp"
 #include "etd_tables.hpp"
+#include "etd_ctx.hpp"
 
 namespace etd {
 
@@ -125,14 +126,15 @@ __global__ __launch_bounds__(kBlock) void k_first(
 }
 
 // ---------------------------------------------------------------------------
-// Middle passes (3-D axis 2): purely linear, in place on c1, c2, w.
+// Middle passes (3-D axis 2): purely linear, (c1, c2, w) -> (o1, o2, ow);
+// the outputs may be the inputs (each line is read before it is written).
 // Work items are (tile, species); the next item's tiles are fetched into
 // registers while the current one is solved.
 // ---------------------------------------------------------------------------
 template <int M, int S>
 __global__ __launch_bounds__(kBlock) void k_mid(
-    double* __restrict__ c1, double* __restrict__ c2, double* __restrict__ w,
-    const SolveTab* __restrict__ tabs, Geom g, int etd1) {
+    const double* c1, const double* c2, const double* w, double* o1, double* o2,
+    double* ow, const SolveTab* __restrict__ tabs, Geom g, int etd1) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
   double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_mid(
       const SolveTab* tb[1] = {at.P(sc)};
       const LaneTab* lb[1] = {at.lP(sc)};
       line_solve<M, 1>(tb, lb, y, lane);
-      tile_store<M>(w + sc * g.N, y[0], tl, g, pos.base, pos.f0, cur);
+      tile_store<M>(ow + sc * g.N, y[0], tl, g, pos.base, pos.f0, cur);
       continue;
     }
 #pragma unroll
@@ -192,9 +194,9 @@ __global__ __launch_bounds__(kBlock) void k_mid(
       x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
       x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
     }
-    tile_store<M>(c1 + sc * g.N, x[0], tl, g, pos.base, pos.f0, cur);
-    tile_store<M>(c2 + sc * g.N, x[1], tl, g, pos.base, pos.f0, cur);
-    tile_store<M>(w + sc * g.N, x[4], tl, g, pos.base, pos.f0, cur);
+    tile_store<M>(o1 + sc * g.N, x[0], tl, g, pos.base, pos.f0, cur);
+    tile_store<M>(o2 + sc * g.N, x[1], tl, g, pos.base, pos.f0, cur);
+    tile_store<M>(ow + sc * g.N, x[4], tl, g, pos.base, pos.f0, cur);
   }
 }
 
@@ -355,31 +357,30 @@ __global__ __launch_bounds__(kBlock) void k_solve_strided(
 
 using namespace etd;
 
-struct etd_rdp_ctx {
-  int d = 0, s = 0;
-  int64_t n[3] = {1, 1, 1};
-  double h[3] = {0, 0, 0};
-  int bc[3] = {0, 0, 0};
-  double D[ETD_MAX_SPECIES] = {0, 0};
-  double k = 0;
-  int scheme = ETD_SCHEME_RDP;
-  Rx rx{};
-  int m[3] = {0, 0, 0};
-  int64_t N = 0;
-  std::vector<SolveTab> tabs;  // [axis][species][3]
-  size_t tab_bytes = 0, arr_bytes = 0, ws_bytes = 0;
-  const void* uploaded_ws = nullptr;
-  int last_hip = 0;
-};
-
-namespace {
-
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+namespace etd {
 
 int hip_fail(etd_rdp_ctx* c, hipError_t e) {
   if (c) c->last_hip = static_cast<int>(e);
   return ETD_ERR_HIP;
 }
+
+int check_ws(const void* ws, size_t have, size_t need) {
+  if (!ws) return ETD_ERR_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return ETD_ERR_WORKSPACE;
+  if (have < need) return ETD_ERR_WORKSPACE;
+  return ETD_OK;
+}
+
+int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st) {
+  if (c->uploaded_ws == ws) return ETD_OK;
+  hipError_t e = hipMemcpyAsync(ws, c->tabs.data(), c->tabs.size() * sizeof(SolveTab),
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(c, e);
+  c->uploaded_ws = ws;
+  return ETD_OK;
+}
+
+namespace {
 
 int species_of_model(int model) {
   switch (model) {
@@ -393,20 +394,17 @@ int species_of_model(int model) {
   }
 }
 
-int check_ws(const etd_rdp_ctx* c, const void* ws, size_t bytes) {
-  if (!ws) return ETD_ERR_WORKSPACE;
-  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return ETD_ERR_WORKSPACE;
-  if (bytes < c->ws_bytes) return ETD_ERR_WORKSPACE;
-  return ETD_OK;
-}
+}  // namespace
 
-int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st) {
-  if (c->uploaded_ws == ws) return ETD_OK;
-  hipError_t e = hipMemcpyAsync(ws, c->tabs.data(), c->tabs.size() * sizeof(SolveTab),
-                                hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(c, e);
-  c->uploaded_ws = ws;
-  return ETD_OK;
+int reaction_param_count(int model, int s) {
+  switch (model) {
+    case ETD_RX_LINEAR: return s * s;
+    case ETD_RX_BRUSSELATOR:
+    case ETD_RX_GRAY_SCOTT: return 2;
+    case ETD_RX_SCHNAKENBERG: return 3;
+    case ETD_RX_CGL: return 1;
+    default: return 0;
+  }
 }
 
 Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds) {
@@ -443,6 +441,8 @@ size_t geom_lds(const Geom& g, size_t fixed_lds) {
   return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
 }
 
+namespace {
+
 // Launchers, templated on the chunk length and species count.
 template <int M, int S>
 hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
@@ -460,7 +460,8 @@ hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, doubl
 }
 
 template <int M, int S>
-hipError_t launch_mid(const etd_rdp_ctx* c, double* c1, double* c2, double* w,
+hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
+                      const double* w, double* o1, double* o2, double* ow,
                       const SolveTab* tabs, int axis0, hipStream_t st) {
   const size_t fixed = lane_lds(3 * S);
   const Geom g = make_geom(c, axis0, fixed);
@@ -470,8 +471,8 @@ hipError_t launch_mid(const etd_rdp_ctx* c, double* c1, double* c2, double* w,
   unsigned grid;
   e = persistent_grid(k_mid<M, S>, lds, g.nFblk * g.nT, &grid);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<M, S>), dim3(grid), dim3(kBlock), lds, st, c1, c2, w, tabs, g,
-                     c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  hipLaunchKernelGGL((k_mid<M, S>), dim3(grid), dim3(kBlock), lds, st, c1, c2, w, o1, o2, ow,
+                     tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -516,33 +517,45 @@ hipError_t launch_solve(const etd_rdp_ctx* c, double* x, const SolveTab* tab, in
   return hipGetLastError();
 }
 
-int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipStream_t st) {
-  char* base = static_cast<char*>(ws);
-  const SolveTab* tabs = static_cast<const SolveTab*>(ws);
-  double* c1 = reinterpret_cast<double*>(base + c->tab_bytes);
-  double* c2 = reinterpret_cast<double*>(base + c->tab_bytes + c->arr_bytes);
-  double* w = reinterpret_cast<double*>(base + c->tab_bytes + 2 * c->arr_bytes);
+}  // namespace
+
+int launch_pass(etd_rdp_ctx* c, int p, double* u, double* const (&in)[3],
+                double* const (&out)[3], const SolveTab* tabs, hipStream_t st) {
   const int S = c->s;
+  const SolveTab* ta = tabs + tab_index(p, 0, 0, S);
+  const int m = c->m[p];
   hipError_t e = hipSuccess;
-  for (int p = first; p < npasses; ++p) {
-    const SolveTab* ta = tabs + tab_index(p, 0, 0, S);
-    const int m = c->m[p];
-    if (p == 0) {
-      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1>(c, u, c1, c2, w, ta, st))); }
-      else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2>(c, u, c1, c2, w, ta, st))); }
-    } else if (p == c->d - 1) {
-      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, c1, c2, w, ta, p, st))); }
-      else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, c1, c2, w, ta, p, st))); }
+  if (p == 0) {
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1>(c, u, out[0], out[1], out[2], ta, st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2>(c, u, out[0], out[1], out[2], ta, st))); }
+  } else if (p == c->d - 1) {
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, in[0], in[1], in[2], ta, p, st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, in[0], in[1], in[2], ta, p, st))); }
+  } else {
+    if (S == 1) {
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, p, st)));
     } else {
-      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, c1, c2, w, ta, p, st))); }
-      else { ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, c1, c2, w, ta, p, st))); }
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, p, st)));
     }
-    if (e != hipSuccess) return hip_fail(c, e);
+  }
+  if (e != hipSuccess) return hip_fail(c, e);
+  return ETD_OK;
+}
+
+namespace {
+
+int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipStream_t st) {
+  const SolveTab* tabs = static_cast<const SolveTab*>(ws);
+  double* const carried[3] = {ws_array(c, ws, 0), ws_array(c, ws, 1), ws_array(c, ws, 2)};
+  for (int p = first; p < npasses; ++p) {
+    const int rc = launch_pass(c, p, u, carried, carried, tabs, st);
+    if (rc) return rc;
   }
   return ETD_OK;
 }
 
 }  // namespace
+}  // namespace etd
 
 extern "C" {
 
@@ -624,6 +637,9 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   c->tab_bytes = round_up(c->tabs.size() * sizeof(SolveTab), 256);
   c->arr_bytes = round_up(sizeof(double) * static_cast<size_t>(N) * s, 256);
   c->ws_bytes = c->tab_bytes + 3 * c->arr_bytes;
+  c->nparams = reaction_param_count(rx->model, s);
+  c->part_bytes = round_up(sizeof(double) * kAdjPasses * kAdjMaxBlocks * kGradSlots, 256);
+  c->adj_ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes + c->part_bytes;
   *out = c;
   return ETD_OK;
 }
@@ -658,7 +674,7 @@ int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m, int32_t
 int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int64_t nsteps,
                  void* stream) {
   if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;
-  int rc = check_ws(ctx, ws, ws_bytes);
+  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   if (nsteps == 0) return ETD_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -674,7 +690,7 @@ int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int64_t
 int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                          int32_t npasses, void* stream) {
   if (!ctx || !u || npasses < 1 || npasses > ctx->d) return ETD_ERR_ARG;
-  int rc = check_ws(ctx, ws, ws_bytes);
+  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = ensure_tables(ctx, ws, st);
@@ -685,7 +701,7 @@ int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
 int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int32_t pass,
                      void* stream) {
   if (!ctx || !u || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
-  int rc = check_ws(ctx, ws, ws_bytes);
+  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = ensure_tables(ctx, ws, st);
@@ -698,7 +714,7 @@ int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, 
   if (!ctx || !x || axis < 1 || axis > ctx->d || sigma < 0 || sigma >= ctx->s) return ETD_ERR_ARG;
   const int slot = gamma == 1 ? 0 : (gamma == 3 ? 1 : (gamma == 4 ? 2 : -1));
   if (slot < 0) return ETD_ERR_ARG;
-  int rc = check_ws(ctx, ws, ws_bytes);
+  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = ensure_tables(ctx, ws, st);

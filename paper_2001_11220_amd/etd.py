@@ -78,6 +78,9 @@ def _load():
         "etd_rdp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "etd_rdp_last_hip_error": (ctypes.c_int, [P]),
         "etd_rdp_line_split": (ctypes.c_int, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "etd_rdp_grad_size": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
+        "etd_rdp_adjoint_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
+        "etd_rdp_adjoint": (ctypes.c_int, [P, P, P, P, P, P, SZ, P]),
         "etd_rdp_batch_init": (ctypes.c_int, [I32, ctypes.POINTER(Instance), I32, I32, D,
                                               ctypes.POINTER(Scheme), ctypes.POINTER(P)]),
         "etd_rdp_batch_destroy": (ctypes.c_int, [P]),
@@ -152,11 +155,26 @@ class EtdRdp:
                                 ctypes.byref(rx), ctypes.byref(ctx)), "etd_rdp_init")
         self._ctx = ctx
         self.shape, self.s, self.d = tuple(int(v) for v in shape), s, d
+        self.D = tuple(float(v) for v in D)
+        self.model = model
+        self._rx_params = tuple(float(rx.params[i]) for i in range(MAX_PARAMS))
         nb = ctypes.c_size_t()
         _check(lib.etd_rdp_workspace_bytes(ctx, ctypes.byref(nb)), "etd_rdp_workspace_bytes")
         self.ws_bytes = nb.value
+        _check(lib.etd_rdp_adjoint_workspace_bytes(ctx, ctypes.byref(nb)),
+               "etd_rdp_adjoint_workspace_bytes")
+        self.adj_ws_bytes = nb.value
+        gs = ctypes.c_int32()
+        _check(lib.etd_rdp_grad_size(ctx, ctypes.byref(gs)), "etd_rdp_grad_size")
+        self.grad_size = gs.value
         self._ws = None
+        self._ws_cap = 0
         self._device = device
+
+    def param_vector(self):
+        """The values the gradient vector refers to: D, then the reaction
+        parameters (params[] order)."""
+        return list(self.D) + list(self._rx_params[: self.grad_size - self.s])
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -168,12 +186,18 @@ class EtdRdp:
         self.close()
 
     # -- workspace ----------------------------------------------------------
-    def workspace(self):
-        """Device workspace (a torch uint8 tensor owned by this object)."""
+    def workspace(self, nbytes=None):
+        """Device workspace (a torch uint8 tensor owned by this object) of at
+        least ``nbytes`` bytes (default: what a forward step needs).  Growing
+        it replaces the buffer; the adjoint's workspace also serves forward
+        steps."""
         import torch
-        if self._ws is None:
+        need = self.ws_bytes if nbytes is None else max(int(nbytes), self.ws_bytes)
+        if self._ws is None or self._ws_cap < need:
             dev = self._device if self._device is not None else torch.device("cuda", torch.cuda.current_device())
-            self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+            self._ws = None
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+            self._ws_cap = need
         return self._ws
 
     def _ws_ptr(self):
@@ -238,6 +262,26 @@ class EtdRdp:
         p = self._state_ptr(u, self.s)
         _check(lib.etd_rdp_run_pass(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
                                     self.ws_bytes, int(npass), self._stream(stream)), "etd_rdp_run_pass")
+
+    def adjoint(self, u_n, lam, lam_out=None, grad=None, stream=None):
+        """One reverse step: returns (dL/dU_n, grad) for lam = dL/dU_{n+1}.
+        ``grad`` (float64 device tensor of ``grad_size``) is accumulated into;
+        a zero one is made if it is None.  ``lam_out`` may be ``lam``."""
+        import torch
+        pu = self._state_ptr(u_n, self.s)
+        pl = self._state_ptr(lam, self.s)
+        if lam_out is None:
+            lam_out = torch.empty_like(lam)
+        po = self._state_ptr(lam_out, self.s)
+        if grad is None:
+            grad = torch.zeros(self.grad_size, dtype=torch.float64, device=lam.device)
+        if grad.dtype != torch.float64 or not grad.is_cuda or not grad.is_contiguous() or grad.numel() != self.grad_size:
+            raise ValueError(f"grad must be a contiguous float64 device tensor of {self.grad_size}")
+        self.workspace(self.adj_ws_bytes)
+        _check(lib.etd_rdp_adjoint(self._ctx, ctypes.c_void_p(pu), ctypes.c_void_p(pl), ctypes.c_void_p(po),
+                                   ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(self._ws_ptr()),
+                                   self._ws_cap, self._stream(stream)), "etd_rdp_adjoint")
+        return lam_out, grad
 
     def apply_solve(self, x, axis, sigma, gamma, stream=None):
         p = self._state_ptr(x, 1)

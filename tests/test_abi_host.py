@@ -116,3 +116,49 @@ def test_step_validates_workspace_without_touching_the_gpu():
     assert etd.lib.etd_rdp_apply_solve(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, 1, 0, 2, None) == etd.ETD_ERR_ARG
     assert etd.lib.etd_rdp_apply_solve(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, 3, 0, 1, None) == etd.ETD_ERR_ARG
     assert etd.status_string(etd.ETD_ERR_WORKSPACE).startswith("workspace")
+
+
+def test_adjoint_workspace_and_gradient_size():
+    N = 64 * 32 * 16
+    arr = ((8 * N * 2 + 255) // 256) * 256
+    p = _init((64, 32, 16), ("neumann", "periodic", "dirichlet"))
+    c1, _, _ = p.layout()
+    # tables, six carried arrays (3-D), block sums; the forward layout is a prefix
+    assert p.adj_ws_bytes > c1 + 6 * arr and p.adj_ws_bytes >= p.ws_bytes
+    q = _init((64, 32), ("neumann", "periodic"))
+    arr2 = ((8 * 64 * 32 * 2 + 255) // 256) * 256
+    assert q.adj_ws_bytes > q.layout()[0] + 3 * arr2
+    sizes = {"brusselator": ({"a": 1.0, "b": 3.0}, 2, 4), "gray_scott": ({"F": 0.04, "kappa": 0.06}, 2, 4),
+             "schnakenberg": ({"a": 0.1, "b": 0.9, "gamma": 1.0}, 2, 5), "cgl": ({"beta": 0.5}, 2, 3),
+             "linear": ({"C": [[0.1, 0.2], [0.3, 0.4]]}, 2, 6), "enzyme": ({}, 1, 1)}
+    for model, (params, s, n) in sizes.items():
+        D = (0.1, 0.2)[:s]
+        e = _init((16, 16), ("neumann", "neumann"), D=D, model=model, params=params)
+        assert e.grad_size == n, model
+        assert len(e.param_vector()) == n
+        assert e.param_vector()[:s] == list(D)
+    e = _init((16, 16), ("neumann", "neumann"), D=(0.3,), model="linear", params={"C": [[-0.5]]})
+    assert e.grad_size == 2 and e.param_vector() == [0.3, -0.5]
+
+
+def test_adjoint_validates_arguments_without_touching_the_gpu():
+    etd = _lib()
+    p = _init((16, 16), ("neumann", "neumann"))
+    ctx = p._ctx
+    u, lam, lo, g = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000))
+    ws = ctypes.c_void_p(0x10000)
+    f = etd.lib.etd_rdp_adjoint
+    assert f(None, u, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert f(ctx, None, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert f(ctx, u, None, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert f(ctx, u, lam, None, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert f(ctx, u, lam, lo, None, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert f(ctx, u, lam, u, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG  # lam_n == u_n
+    assert f(ctx, u, lam, lo, g, None, p.adj_ws_bytes, None) == etd.ETD_ERR_WORKSPACE
+    assert f(ctx, u, lam, lo, g, ctypes.c_void_p(0x10008), p.adj_ws_bytes, None) == etd.ETD_ERR_WORKSPACE
+    # the forward workspace is too small for the reverse step
+    assert f(ctx, u, lam, lo, g, ws, p.ws_bytes, None) == etd.ETD_ERR_WORKSPACE
+    q = _init((16, 16), ("neumann", "neumann"), scheme="etd1")
+    assert f(q._ctx, u, lam, lo, g, ws, q.adj_ws_bytes, None) == etd.ETD_ERR_UNSUPPORTED
+    n = ctypes.c_int32()
+    assert etd.lib.etd_rdp_grad_size(None, ctypes.byref(n)) == etd.ETD_ERR_ARG

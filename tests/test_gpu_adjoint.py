@@ -1,0 +1,231 @@
+"""GPU parity of the reverse-mode step (etd_rdp_adjoint) and of the
+checkpointed trajectory gradient, against the oracle's adjoint (which its own
+tests pin to central differences).
+
+Tolerances: dL/dU_n rel-L2 <= 1e-11; each gradient entry within
+1e-9 |g| + 1e-11 max|g| of the oracle (the entries are sums over every cell,
+so only their rounding order differs); trajectory gradients vs the chained
+oracle <= 1e-10; vs central differences of the GPU forward <= 1e-5."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2001_11220_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SCHNAK = {"a": 0.1, "b": 0.9, "gamma": 1.0}
+# (shape (n_1, ...), bcs, D, k, model, params, shift, ic offset)
+CASES = {
+    "schnak3d_neumann": ((96, 12, 10), ("neumann",) * 3, (1.0, 10.0), 1e-3, "schnakenberg", SCHNAK, None, (1.0, 0.9)),
+    "grayscott3d_periodic": ((64, 8, 96), ("periodic",) * 3, (2e-5, 1e-5), 1.0, "gray_scott",
+                             {"F": 0.04, "kappa": 0.06}, None, (0.7, 0.2)),
+    "bruss3d_mixed": ((72, 10, 24), ("neumann", "periodic", "dirichlet"), (0.02, 0.011), 0.05, "brusselator",
+                      {"a": 1.0, "b": 3.4}, None, (1.0, 3.4)),
+    "cgl3d_mixed": ((20, 136, 12), ("dirichlet", "neumann", "periodic"), (0.01, 0.01), 0.05, "cgl",
+                    {"beta": 1.3}, None, (0.3, -0.2)),
+    "gs3d_m8_neumann": ((512, 6, 8), ("neumann",) * 3, (2e-5, 1e-5), 1.0, "gray_scott",
+                        {"F": 0.035, "kappa": 0.065}, None, (0.8, 0.1)),
+    "lin1_3d_m4": ((40, 24, 200), ("neumann", "periodic", "dirichlet"), (0.02,), 0.04, "linear",
+                   {"C": [[-0.7]]}, None, (0.0,)),
+    "bruss2d_neumann": ((64, 64), ("neumann", "neumann"), (0.02, 0.02), 0.01, "brusselator",
+                        {"a": 1.0, "b": 3.4}, None, (0.5, 0.5)),
+    "lin2_2d_m3": ((192, 40), ("periodic", "dirichlet"), (0.03, 0.005), 0.02, "linear",
+                   {"C": [[-1.0, 0.4], [0.3, -0.2]]}, None, (0.0, 0.0)),
+    "enzyme2d_m4": ((256, 48), ("dirichlet", "neumann"), (0.05,), 0.02, "enzyme", {}, None, (0.5,)),
+    "schnak2d_m7_shift": ((448, 20), ("dirichlet", "dirichlet"), (1.0, 10.0), 1e-4, "schnakenberg", SCHNAK,
+                          (1.0, 0.9), (0.0, 0.0)),
+    "cgl2d_m5_m6": ((320, 384), ("periodic", "neumann"), (0.001, 0.002), 0.02, "cgl", {"beta": -0.6}, None,
+                    (0.2, 0.4)),
+}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _etd():
+    from paper_2001_11220_amd import etd
+    return etd
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def hs_of(shape, bcs):
+    return W.Problem("t", tuple(shape), tuple(bcs), (1.0,), 1.0, "linear", {}, 1).hs()
+
+
+def oracle_params(model, params, shift):
+    p = dict(params)
+    if shift is not None:
+        p["shift"] = list(shift)
+    return p
+
+
+def make_inputs(shape, s, offset, seed):
+    rng = np.random.default_rng(seed)
+    sshape = (s,) + tuple(shape[::-1])
+    U = np.stack([offset[i] + 0.2 * rng.random(sshape[1:]) for i in range(s)])
+    lam = rng.standard_normal(sshape)
+    return U, lam
+
+
+def check_grad(g, go):
+    g, go = np.asarray(g), np.asarray(go)
+    scale = float(np.max(np.abs(go))) if go.size else 0.0
+    tol = 1e-9 * np.abs(go) + 1e-11 * scale
+    assert np.all(np.abs(g - go) <= tol), (g, go)
+
+
+def gpu_adjoint(e, U, lam, grad=None, inplace=False):
+    torch = _torch()
+    u = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    l = torch.from_numpy(np.ascontiguousarray(lam)).cuda()
+    out = l if inplace else None
+    g = None if grad is None else torch.from_numpy(np.asarray(grad, dtype=np.float64).copy()).cuda()
+    lo, g = e.adjoint(u, l, lam_out=out, grad=g)
+    torch.cuda.synchronize()
+    return lo.cpu().numpy(), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_step_matches_oracle(name):
+    shape, bcs, D, k, model, params, shift, offset = CASES[name]
+    s = len(D)
+    print(f"[adjoint step] {name} shape={shape}", flush=True)
+    e = _etd().EtdRdp(shape, bcs, D, k, model, params, shift=shift)
+    U, lam = make_inputs(shape, s, offset, seed=len(name))
+    lo, g = gpu_adjoint(e, U, lam)
+    lo_o, gD, gth = O.adjoint_step(U, lam, k, D, bcs, hs_of(shape, bcs), model,
+                                   oracle_params(model, params, shift))
+    assert rel_l2(lo, lo_o) <= 1e-11
+    check_grad(g, np.concatenate([gD, gth]))
+
+
+def test_adjoint_in_place_accumulating_and_deterministic():
+    shape, bcs, D, k, model, params, shift, offset = CASES["bruss3d_mixed"]
+    e = _etd().EtdRdp(shape, bcs, D, k, model, params, shift=shift)
+    U, lam = make_inputs(shape, 2, offset, seed=5)
+    lo1, g1 = gpu_adjoint(e, U, lam)
+    lo2, g2 = gpu_adjoint(e, U, lam, inplace=True)
+    assert np.array_equal(lo1, lo2) and np.array_equal(g1, g2)
+    base = np.arange(1.0, 1.0 + e.grad_size)
+    _, g3 = gpu_adjoint(e, U, lam, grad=base)
+    assert np.allclose(g3 - base, g1, rtol=1e-13, atol=1e-13 * np.max(np.abs(g1)))
+    # the forward step still works from the (larger) adjoint workspace
+    torch = _torch()
+    u = torch.from_numpy(U.copy()).cuda()
+    e.step(u, 1)
+    torch.cuda.synchronize()
+    ref = O.etd_rdp_if_step(U, k, D, bcs, hs_of(shape, bcs), model, params)
+    assert rel_l2(u.cpu().numpy(), ref) <= 1e-12
+
+
+def test_adjoint_full_size_schnakenberg_128():
+    """The 128^3 Neumann Schnakenberg gradient workload: one reverse step at
+    full size against the oracle."""
+    prob = W.schnakenberg3d_adjoint()
+    print(f"[adjoint step] {prob.name} shape={prob.shape}", flush=True)
+    e = _etd().EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h, shift=prob.shift)
+    U = prob.initial()
+    lam = np.random.default_rng(3).standard_normal(U.shape)
+    lo, g = gpu_adjoint(e, U, lam)
+    lo_o, gD, gth = O.adjoint_step(U, lam, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params())
+    assert rel_l2(lo, lo_o) <= 1e-11
+    check_grad(g, np.concatenate([gD, gth]))
+
+
+# ---------------------------------------------------------------------------
+# Checkpointed trajectories through torch.autograd
+# ---------------------------------------------------------------------------
+
+def _traj_problem():
+    shape, bcs = (48, 40), ("neumann", "periodic")
+    D, k, model, params = (0.02, 0.011), 0.05, "brusselator", {"a": 1.0, "b": 3.4}
+    return shape, bcs, D, k, model, params
+
+
+@pytest.mark.parametrize("every", [1, 5, 20])
+def test_trajectory_gradient_matches_chained_oracle(every):
+    torch = _torch()
+    from paper_2001_11220_amd.adjoint import trajectory
+    shape, bcs, D, k, model, params = _traj_problem()
+    nsteps = 13
+    e = _etd().EtdRdp(shape, bcs, D, k, model, params)
+    rng = np.random.default_rng(8)
+    U0 = np.stack([1.0 + 0.3 * rng.random(shape[::-1]), 3.4 + 0.3 * rng.random(shape[::-1])])
+    Wt = rng.standard_normal(U0.shape)
+    u0 = torch.from_numpy(U0.copy()).cuda().requires_grad_(True)
+    p = torch.tensor(e.param_vector(), dtype=torch.float64, requires_grad=True)
+    uT = trajectory(e, u0, nsteps, p, checkpoint_every=every)
+    loss = (uT * torch.from_numpy(Wt).cuda()).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    # oracle: forward states, then the chained reverse steps
+    hs = hs_of(shape, bcs)
+    states = [U0]
+    for _ in range(nsteps):
+        states.append(O.etd_rdp_if_step(states[-1], k, D, bcs, hs, model, params))
+    assert rel_l2(uT.detach().cpu().numpy(), states[-1]) <= 1e-11
+    lam = Wt.copy()
+    gsum = np.zeros(e.grad_size)
+    for n in range(nsteps - 1, -1, -1):
+        lam, gD, gth = O.adjoint_step(states[n], lam, k, D, bcs, hs, model, params)
+        gsum += np.concatenate([gD, gth])
+    assert rel_l2(u0.grad.cpu().numpy(), lam) <= 1e-10
+    g = p.grad.numpy()
+    assert np.all(np.abs(g - gsum) <= 1e-10 * np.abs(gsum) + 1e-12 * np.max(np.abs(gsum))), (g, gsum)
+
+
+def test_trajectory_gradient_matches_finite_differences():
+    torch = _torch()
+    from paper_2001_11220_amd.adjoint import trajectory
+    shape, bcs, D, k, model, params = _traj_problem()
+    nsteps = 10
+    rng = np.random.default_rng(9)
+    U0 = np.stack([1.0 + 0.3 * rng.random(shape[::-1]), 3.4 + 0.3 * rng.random(shape[::-1])])
+    Wt = torch.from_numpy(rng.standard_normal(U0.shape)).cuda()
+    e = _etd().EtdRdp(shape, bcs, D, k, model, params)
+    p = torch.tensor(e.param_vector(), dtype=torch.float64, requires_grad=True)
+    u0 = torch.from_numpy(U0.copy()).cuda()
+    loss = (trajectory(e, u0, nsteps, p, checkpoint_every=4) * Wt).sum()
+    loss.backward()
+    g = p.grad.numpy()
+    base = e.param_vector()
+
+    def L(vec):
+        Dv, th = tuple(vec[:2]), {"a": vec[2], "b": vec[3]}
+        f = _etd().EtdRdp(shape, bcs, Dv, k, model, th)
+        u = torch.from_numpy(U0.copy()).cuda()
+        f.step(u, nsteps)
+        return float((u * Wt).sum())
+
+    # Central differences with relative step 1e-4: truncation ~1e-8 and
+    # rounding of |L| ~ 1e2 over a change of ~1e-5 ~1e-7, both below 1e-5.
+    for i in range(len(base)):
+        hstep = 1e-4 * abs(base[i])
+        vp, vm = list(base), list(base)
+        vp[i] += hstep
+        vm[i] -= hstep
+        fd = (L(vp) - L(vm)) / (2 * hstep)
+        assert abs(fd - g[i]) <= 1e-5 * abs(fd), (i, fd, g[i])
+    # directional derivative along a random initial-state perturbation
+    u0 = torch.from_numpy(U0.copy()).cuda().requires_grad_(True)
+    loss = (trajectory(e, u0, nsteps, checkpoint_every=3) * Wt).sum()
+    loss.backward()
+    v = torch.from_numpy(rng.standard_normal(U0.shape)).cuda()
+    dd = float((u0.grad * v).sum())
+    eps = 1e-4
+
+    def Lu(x):
+        u = x.clone()
+        e.step(u, nsteps)
+        return float((u * Wt).sum())
+
+    u0d = u0.detach()
+    fd = (Lu(u0d + eps * v) - Lu(u0d - eps * v)) / (2 * eps)
+    assert abs(fd - dd) <= 1e-5 * abs(fd), (fd, dd)
