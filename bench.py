@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--workload", default="grayscott3d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-steps", type=int, default=50)
+    ap.add_argument("--checkpoint-every", type=int, default=20,
+                    help="gradient workload: steps between stored states")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -106,6 +108,8 @@ def main():
         if args.steps is None:
             args.steps = 200
         return bench_ensemble(args)
+    if args.workload == "schnakenberg3d_adjoint":
+        return bench_adjoint(args)
     prob = W.WORKLOADS[args.workload]()
     if args.steps is None:
         args.steps = prob.nsteps
@@ -272,6 +276,143 @@ def bench_ensemble(args):
         "plain_2d_512": {"value": plain_value, "ms_per_step": plain_ms,
                          "effective_GBps": 64 * plain_value / 1e9},
         "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_adjoint(budget_s: float = 12.0):
+    """The oracle's forward step plus reverse step, single-threaded, on a
+    64^3 sample of the gradient workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    from paper_2001_11220_amd import workloads as W
+
+    prob = W.schnakenberg3d_adjoint(n=64)
+    u = prob.initial()
+    lam = np.random.default_rng(1).standard_normal(u.shape)
+    cs = prob.cells * prob.s
+    with threadpool_limits(limits=1):
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            un = O.etd_rdp_if_step(u, prob.k, prob.D, prob.bcs, prob.hs(), prob.model,
+                                   prob.oracle_params())
+            lam, _, _ = O.adjoint_step(u, lam, prob.k, prob.D, prob.bcs, prob.hs(), prob.model,
+                                       prob.oracle_params())
+            u = un
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or steps >= 1000:
+                break
+    return {"value": cs * steps / el, "unit": "cell-species-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"schnakenberg3d_adjoint at 64x64x64: {steps} forward + reverse step pairs "
+                      f"in {el:.1f} s, 1 thread"}
+
+
+def bench_adjoint(args):
+    """Gradient of a trajectory loss with respect to the initial state, D and
+    the reaction parameters: 128^3 Neumann Schnakenberg, 400 steps,
+    checkpoints every m steps, loss = sum (U(T) - U_target)^2 with U_target
+    from reaction parameters perturbed by up to 5%.  value counts the
+    cell-species-steps of the trajectory per second of forward + backward."""
+    import numpy as np
+    import torch
+
+    from paper_2001_11220_amd import workloads as W
+    from paper_2001_11220_amd.adjoint import trajectory
+    from paper_2001_11220_amd.etd import EtdRdp
+
+    prob = W.schnakenberg3d_adjoint()
+    steps = args.steps if args.steps is not None else prob.nsteps
+    every = args.checkpoint_every
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    e = EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
+               shift=prob.shift, device=dev)
+    u0 = torch.from_numpy(prob.initial()).to(dev)
+    rng = np.random.default_rng(prob.seed + 1)
+    th_t = {key: v * (1.0 + 0.05 * rng.uniform(-1.0, 1.0)) for key, v in prob.params.items()}
+    et = EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, th_t, h=prob.h, shift=prob.shift,
+                device=dev)
+    target = u0.clone()
+    et.step(target, steps)
+    et.close()
+    e.workspace(e.adj_ws_bytes)
+    stream = torch.cuda.current_stream()
+    cs = prob.cells * prob.s
+    print(f"[bench] {prob.name} shape={prob.shape} steps={steps} checkpoint every {every}, "
+          f"ws={e.adj_ws_bytes/2**30:.2f} GiB", file=sys.stderr, flush=True)
+
+    def grad_run(nsteps):
+        x = u0.clone().requires_grad_(True)
+        p = torch.tensor(e.param_vector(), dtype=torch.float64, requires_grad=True)
+        uT = trajectory(e, x, nsteps, p, checkpoint_every=every)
+        loss = ((uT - target) ** 2).sum()
+        loss.backward()
+        return loss, x.grad, p.grad
+
+    grad_run(min(args.warmup, steps))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    loss, gx, gp = grad_run(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    finite = bool(torch.isfinite(gx).all().item()) and bool(torch.isfinite(gp).all().item())
+    # plain forward of the same trajectory
+    u = u0.clone()
+    e.step(u, 10)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    e.step(u, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1)
+    # one reverse step alone, repeated
+    lam = torch.randn_like(u0)
+    g = torch.zeros(e.grad_size, dtype=torch.float64, device=dev)
+    e.adjoint(u0, lam, lam_out=lam, grad=g)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.pass_steps):
+        e.adjoint(u0, lam, lam_out=lam, grad=g)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    adj_ms = ev0.elapsed_time(ev1) / args.pass_steps
+    value = cs * steps / (ms / 1e3)
+    # Reverse step: forward recompute of passes 1-2 (4 + 6 words), reverse
+    # passes for axis 3 (7), axis 2 (9) and axis 1 (5): 31 words per cell-species.
+    adj_bytes = 31 * 8 * cs
+    adj_gbs = adj_bytes / (adj_ms / 1e3) / 1e9
+    print(f"[bench] gradient {ms:.1f} ms ({ms/steps:.3f} ms/step); forward alone {fwd_ms:.1f} ms; "
+          f"reverse step {adj_ms*1e3:.1f} us ({adj_gbs:.0f} GB/s algorithmic); loss={float(loss):.6e}",
+          file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_adjoint()
+    out = {
+        "metric": "cell-species-steps/sec",
+        "value": value,
+        "unit": "cell-species-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": min(args.warmup, steps),
+        "ms_per_step": ms / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded initial data and target, no dataset)",
+        "config": {"workload": prob.name, "grid": list(prob.shape), "bcs": list(prob.bcs),
+                   "species": prob.s, "k": prob.k, "model": prob.model,
+                   "gradient": "dL/d(u0, D, a, b, gamma) of sum (U(T) - U_target)^2",
+                   "checkpoint_every": every, "grad_finite": finite,
+                   "forward_only_ms": fwd_ms, "gradient_over_forward": ms / fwd_ms},
+        "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": adj_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "etd_rdp_adjoint (one reverse step: 2 forward + 3 reverse passes)",
+                     "avg_launch_us": adj_ms * 1e3, "alg_bytes_per_launch": adj_bytes},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
