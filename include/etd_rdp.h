@@ -130,18 +130,27 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D,
 int etd_rdp_destroy(etd_rdp_ctx* ctx);
 
 /*
- * Bytes of device workspace a step needs: the factor tables plus three
- * carried FP64 arrays of s*N values (the passes' intermediates).
+ * Bytes of device workspace a step needs: the factor tables plus the
+ * carried FP64 arrays of s*N values each (the passes' intermediates): one
+ * triple (c1, c2, w) written by pass 1 and, for d = 3, a second triple
+ * written by pass 2 (six arrays in 3-D, three in 2-D).
  */
 int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
 
 /*
- * Byte offsets inside the workspace of the three carried arrays (each s*N
- * doubles, same layout as u).  After a full step their contents are
- * unspecified; etd_rdp_debug_passes leaves defined values in them.
+ * etd_rdp_workspace_layout -- where pass `pass` (1..d-1) leaves its carried
+ * triple (c1, c2, w): byte offsets of the three arrays inside the workspace
+ * and, in strides[0..d-1], the element stride (in doubles) of axes 1..d
+ * inside each species plane (species planes are N doubles apart).  Each
+ * pass writes the layout the next pass reads line by line: pass 1 writes
+ * axis 2 fastest, then axis 1, then axis 3 ([z][x][y]); pass 2 writes axis 3
+ * fastest, then axis 2, then axis 1 ([x][y][z]).  After a full step the
+ * contents are unspecified; etd_rdp_debug_passes leaves defined values.
+ * Errors: ETD_ERR_ARG (NULL pointer, pass outside 1..d-1).
  */
-int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, size_t* off_c1,
-                             size_t* off_c2, size_t* off_w);
+int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass,
+                             size_t* off_c1, size_t* off_c2, size_t* off_w,
+                             int64_t* strides);
 
 /*
  * etd_rdp_step -- advance u in place by nsteps time steps on `stream`.
@@ -161,9 +170,10 @@ int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
 
 /*
  * etd_rdp_debug_passes -- run only the first `npasses` passes (1..d) of one
- * step and stop, leaving the carried arrays in the workspace.  For d = 3:
- * after pass 1 the workspace holds c1 = R_1 U, c2 = R_1 f(U), w = P_1 (U+kf);
- * after pass 2: c1 = R_2 R_1 U, c2 = R_2 R_1 f, w = P_2 P_1 (U + k f).
+ * step and stop, leaving the carried arrays in the workspace (see
+ * etd_rdp_workspace_layout).  Pass 1's triple holds c1 = R_1 U,
+ * c2 = R_1 f(U), w = P_1 (U + k f); pass 2's (d = 3) holds c1 = R_2 R_1 U,
+ * c2 = R_2 R_1 f, w = P_2 P_1 (U + k f).
  * npasses = d is a full step (u is overwritten).  For testing each pass
  * against the oracle's intermediates.
  */
@@ -173,8 +183,9 @@ int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws,
 /*
  * etd_rdp_run_pass -- run pass `pass` (1..d) of a step on its own, reading
  * and writing the same arrays as inside a full step (pass 1 reads u and
- * writes the carried arrays, middle passes update them in place, pass d
- * reads them and writes u).  For timing the kernels one by one.
+ * writes its triple, pass 2 of a 3-D step reads that and writes its own,
+ * pass d reads the last triple and writes u).  For timing the kernels one
+ * by one.
  */
 int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                      int32_t pass, void* stream);
@@ -216,11 +227,11 @@ int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m,
 /* Number of gradient entries, s + (number of reaction parameters). */
 int etd_rdp_grad_size(const etd_rdp_ctx* ctx, int32_t* n);
 
-/* Device workspace bytes etd_rdp_adjoint needs: the tables, 6 (d = 3) or 3
+/* Device workspace bytes etd_rdp_adjoint needs: the tables, 9 (d = 3) or 6
  * (d = 2) carried arrays of s*N doubles and the gradient block sums.  It is
  * at least etd_rdp_workspace_bytes, and etd_rdp_step accepts the same buffer
- * (with the same layout of its first three carried arrays), so one
- * workspace serves a forward sweep and its reverse sweep. */
+ * (its carried arrays come first, in the same places), so one workspace
+ * serves a forward sweep and its reverse sweep. */
 int etd_rdp_adjoint_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
 
 /*

@@ -26,8 +26,10 @@
 //   ka_last   axis d: recompute U*, f*, f1, f2; 6 solves per species
 //   ka_mid    axis 2 of 3-D: 10 solves per species
 //   ka_first  axis 1: recompute f, U + k f; 10 solves per species; lam_n
-// The forward carried arrays the reverse passes need come from a forward
-// recompute into two workspace triples.  Gradient sums are per-block
+// The forward carried triples the reverse passes need come from a forward
+// recompute (k_first, and k_mid in 3-D); the reverse passes read them line
+// by line and keep the adjoints in a third triple in u's layout, which
+// ka_first reads line by line.  Gradient sums are per-block
 // partials in the workspace, added in a fixed order by one final kernel,
 // so a call is bitwise reproducible.
 #include <hip/hip_runtime.h>
@@ -167,22 +169,24 @@ __device__ __forceinline__ void block_partials(const double (&acc)[kGradSlots], 
 
 template <int M>
 __device__ __forceinline__ void tile_load(const double* __restrict__ A, double (&x)[M], double* tl,
-                                          const Geom& g, const TilePos& p, TileCursor& cur) {
+                                          const PassGeom& g, const TileAt& p, TileCursor& cur) {
   double r[M];
-  tile_fetch<M>(A, r, g, p.base, p.f0);
+  tile_fetch<M>(A, r, g, p);
   tile_commit<M>(r, x, tl, g, cur);
 }
 
 // ---------------------------------------------------------------------------
-// Axis d (last forward pass).  In: the forward carried (c, cf, w) that pass d
-// reads (R'U, R'f, P_{d-1}...P_1 (U + k f)) and lam; out, in place: their
-// adjoints ((R'U)bar, (R'f)bar, P_d^T mu).
+// Axis d (last forward pass), tiles as in k_last.  In: the triple X that pass
+// d reads (R'U, R'f, P_{d-1}...P_1 (U + k f); read line by line) and lam (in
+// u's layout); out: their adjoints ((R'U)bar, (R'f)bar, P_d^T mu) into the
+// triple Y in u's layout.
 // ---------------------------------------------------------------------------
 template <int M, int S>
 __global__ __launch_bounds__(kBlock) void ka_last(
-    double* c1, double* c2, double* w, const double* __restrict__ lam,
-    const SolveTab* __restrict__ tabs, Rx rx, double k, Geom g, int bc, double dsc,
-    double* __restrict__ part) {
+    const double* __restrict__ c1, const double* __restrict__ c2, const double* __restrict__ w,
+    const double* __restrict__ lam, double* __restrict__ y1, double* __restrict__ y2,
+    double* __restrict__ yw, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
+    int bc, double dsc, double* __restrict__ part) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
   double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
@@ -201,11 +205,11 @@ __global__ __launch_bounds__(kBlock) void ka_last(
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   while (walk.next(tile)) {
-    const TilePos pos(tile, g);
+    const TileAt pos(tile, g);
     const bool valid = (lane < C) && (pos.f0 + wv < g.nF);
     double us[S][M], fb[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) tile_load<M>(w + s * g.N, us[s], tl, g, pos, cur);
+    for (int s = 0; s < S; ++s) line_load<M>(w + s * g.N, us[s], g, pos);
     {
       const SolveTab* tb[S];
       const LaneTab* lb[S];
@@ -228,8 +232,8 @@ __global__ __launch_bounds__(kBlock) void ka_last(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double x[4][M], cb[M];
-      tile_load<M>(c1 + s * g.N, x[0], tl, g, pos, cur);
-      tile_load<M>(c2 + s * g.N, cb, tl, g, pos, cur);
+      line_load<M>(c1 + s * g.N, x[0], g, pos);
+      line_load<M>(c2 + s * g.N, cb, g, pos);
       tile_load<M>(lam + s * g.N, x[2], tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
@@ -255,10 +259,10 @@ __global__ __launch_bounds__(kBlock) void ka_last(
       double o[M];
 #pragma unroll
       for (int j = 0; j < M; ++j) o[j] = fma(9.0, x[2][j], -8.0 * x[3][j]);
-      tile_store<M>(c1 + s * g.N, o, tl, g, pos.base, pos.f0, cur);
+      tile_store<M>(y1 + s * g.N, o, tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) o[j] = fma(k2, x[2][j], -k15 * x[3][j]);
-      tile_store<M>(c2 + s * g.N, o, tl, g, pos.base, pos.f0, cur);
+      tile_store<M>(y2 + s * g.N, o, tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) fb[s][j] = fma(k, x[2][j], -k05 * x[3][j]);  // f*bar
     }
@@ -292,22 +296,23 @@ __global__ __launch_bounds__(kBlock) void ka_last(
     for (int s = 0; s < S; ++s) {
       if (neu) ends_scale<M>(fb[s], lane, C, 0.5);
       acc[s] += dsc * lap_dot<M>(fb[s], us[s], lane, C, bc);
-      tile_store<M>(w + s * g.N, fb[s], tl, g, pos.base, pos.f0, cur);
+      tile_store<M>(yw + s * g.N, fb[s], tl, g, pos, cur);
     }
   }
   block_partials(acc, red, part);
 }
 
 // ---------------------------------------------------------------------------
-// Axis 2 of a 3-D step.  In: the forward carried (c1, c2, w) after pass 1
-// (R_1 U, R_1 f, P_1 (U + k f)) and the adjoints (b1, b2, bw) of pass 2's
-// outputs; out, in place of (c1, c2, w): the adjoints of pass 2's inputs.
+// Axis 2 of a 3-D step.  Tiles of 8 y-lines with adjacent x.  In: the
+// forward triple (c1, c2, w) pass 2 reads (R_1 U, R_1 f, P_1 (U + k f); read
+// line by line) and, in u's layout, the adjoints (y1, y2, yw) of pass 2's
+// outputs; out, in place of (y1, y2, yw): the adjoints of pass 2's inputs.
 // ---------------------------------------------------------------------------
 template <int M, int S>
 __global__ __launch_bounds__(kBlock) void ka_mid(
-    double* c1, double* c2, double* w, const double* __restrict__ b1,
-    const double* __restrict__ b2, const double* __restrict__ bw,
-    const SolveTab* __restrict__ tabs, Geom g, int bc, double dsc, double* __restrict__ part) {
+    const double* __restrict__ c1, const double* __restrict__ c2, const double* __restrict__ w,
+    double* __restrict__ y1, double* __restrict__ y2, double* __restrict__ yw,
+    const SolveTab* __restrict__ tabs, PassGeom g, int bc, double dsc, double* __restrict__ part) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
   double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
@@ -325,15 +330,15 @@ __global__ __launch_bounds__(kBlock) void ka_mid(
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   while (walk.next(tile)) {
-    const TilePos pos(tile, g);
+    const TileAt pos(tile, g);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      double* const fw[2] = {c1 + s * g.N, c2 + s * g.N};
-      const double* const bk[2] = {b1 + s * g.N, b2 + s * g.N};
+      const double* const fw[2] = {c1 + s * g.N, c2 + s * g.N};
+      double* const bk[2] = {y1 + s * g.N, y2 + s * g.N};
 #pragma unroll
       for (int r = 0; r < 2; ++r) {  // R_2 U-chain, then f-chain
         double x[4][M];
-        tile_load<M>(fw[r], x[0], tl, g, pos, cur);
+        line_load<M>(fw[r], x[0], g, pos);
         tile_load<M>(bk[r], x[2], tl, g, pos, cur);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -356,26 +361,26 @@ __global__ __launch_bounds__(kBlock) void ka_mid(
         double o[M];
 #pragma unroll
         for (int j = 0; j < M; ++j) o[j] = fma(9.0, x[2][j], -8.0 * x[3][j]);
-        tile_store<M>(fw[r], o, tl, g, pos.base, pos.f0, cur);
+        tile_store<M>(bk[r], o, tl, g, pos, cur);
       }
       double y[2][M];
-      tile_load<M>(w + s * g.N, y[0], tl, g, pos, cur);
-      tile_load<M>(bw + s * g.N, y[1], tl, g, pos, cur);
+      line_load<M>(w + s * g.N, y[0], g, pos);
+      tile_load<M>(yw + s * g.N, y[1], tl, g, pos, cur);
       if (neu) ends_scale<M>(y[1], lane, C, 2.0);
       const SolveTab* tb[2] = {at.P(s), at.P(s)};
       const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
       line_solve<M, 2>(tb, lb, y, lane);
       if (neu) ends_scale<M>(y[1], lane, C, 0.5);
       acc[s] += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
-      tile_store<M>(w + s * g.N, y[1], tl, g, pos.base, pos.f0, cur);
+      tile_store<M>(yw + s * g.N, y[1], tl, g, pos, cur);
     }
   }
   block_partials(acc, red, part);
 }
 
 // ---------------------------------------------------------------------------
-// Axis 1 (first forward pass).  In: U_n and the adjoints (b1, b2, bw) of
-// pass 1's outputs (R_1 U, R_1 f, P_1 (U + k f)); out: lam_n.
+// Axis 1 (first forward pass).  In: U_n and, in u's layout, the adjoints
+// (b1, b2, bw) of pass 1's outputs (R_1 U, R_1 f, P_1 (U + k f)); out: lam_n.
 // ---------------------------------------------------------------------------
 template <int M, int S>
 __global__ __launch_bounds__(kBlock) void ka_first(
@@ -530,29 +535,30 @@ double d_scale(const etd_rdp_ctx* c, int axis0) { return -c->k / (c->h[axis0] * 
 
 template <int M, int S>
 hipError_t launch_ka_last(const etd_rdp_ctx* c, double* const (&X)[3], const double* lam,
-                          const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
+                          double* const (&Y)[3], const SolveTab* tabs, double* part,
+                          unsigned* nblk, hipStream_t st) {
   const int a = c->d - 1;
   const size_t fixed = adj_fixed_lds(S);
-  const Geom g = make_geom(c, a, fixed);
-  const size_t lds = geom_lds(g, fixed);
+  const PassGeom g = pass_geom(c, kPassLast, fixed, kBlockLines);
+  const size_t lds = pass_lds(g, fixed);
   hipError_t e = adj_grid(ka_last<M, S>, lds, g.nFblk * g.nT, nblk);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((ka_last<M, S>), dim3(*nblk), dim3(kBlock), lds, st, X[0], X[1], X[2], lam,
-                     tabs, c->rx, c->k, g, c->bc[a], d_scale(c, a), part);
+                     Y[0], Y[1], Y[2], tabs, c->rx, c->k, g, c->bc[a], d_scale(c, a), part);
   return hipGetLastError();
 }
 
 template <int M, int S>
-hipError_t launch_ka_mid(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&B)[3],
+hipError_t launch_ka_mid(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&Y)[3],
                          const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
   const int a = 1;
   const size_t fixed = adj_fixed_lds(S);
-  const Geom g = make_geom(c, a, fixed);
-  const size_t lds = geom_lds(g, fixed);
+  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, kBlockLines);
+  const size_t lds = pass_lds(g, fixed);
   hipError_t e = adj_grid(ka_mid<M, S>, lds, g.nFblk * g.nT, nblk);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((ka_mid<M, S>), dim3(*nblk), dim3(kBlock), lds, st, A[0], A[1], A[2], B[0],
-                     B[1], B[2], tabs, g, c->bc[a], d_scale(c, a), part);
+  hipLaunchKernelGGL((ka_mid<M, S>), dim3(*nblk), dim3(kBlock), lds, st, A[0], A[1], A[2], Y[0],
+                     Y[1], Y[2], tabs, g, c->bc[a], d_scale(c, a), part);
   return hipGetLastError();
 }
 
@@ -573,12 +579,14 @@ hipError_t launch_ka_first(const etd_rdp_ctx* c, const double* u, double* const 
 int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* lam_out,
                 double* grad, void* ws, hipStream_t st) {
   const SolveTab* tabs = static_cast<const SolveTab*>(ws);
+  // A: pass 1's triple, B: pass 2's (3-D), Y: the adjoints, in u's layout.
   double* const A[3] = {ws_array(c, ws, 0), ws_array(c, ws, 1), ws_array(c, ws, 2)};
-  const int nB = (c->d == 3) ? 3 : 0;
-  double* const B[3] = {ws_array(c, ws, nB), ws_array(c, ws, nB + 1), ws_array(c, ws, nB + 2)};
-  double* part = ws_array(c, ws, c->d == 3 ? 6 : 3);
+  double* const B[3] = {ws_array(c, ws, 3), ws_array(c, ws, 4), ws_array(c, ws, 5)};
+  const int nY = (c->d == 3) ? 6 : 3;
+  double* const Y[3] = {ws_array(c, ws, nY), ws_array(c, ws, nY + 1), ws_array(c, ws, nY + 2)};
+  double* part = ws_array(c, ws, nY + 3);
   const int S = c->s;
-  // Forward recompute of the carried triples: A after pass 1, B after pass 2.
+  // Forward recompute of the carried triples.
   int rc = launch_pass(c, 0, const_cast<double*>(u), A, A, tabs, st);
   if (rc) return rc;
   if (c->d == 3) {
@@ -593,24 +601,24 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
     const SolveTab* ta = tabs + tab_index(a, 0, 0, S);
     double* const(&X)[3] = (c->d == 3) ? B : A;
     double* pp = part;
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 1>(c, X, lam_in, ta, pp, &nb[0], st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 2>(c, X, lam_in, ta, pp, &nb[0], st))); }
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 1>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 2>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
     if (e != hipSuccess) return hip_fail(c, e);
   }
   if (c->d == 3) {
     const int m = c->m[1];
     const SolveTab* ta = tabs + tab_index(1, 0, 0, S);
     double* pp = part + (size_t)kAdjMaxBlocks * kGradSlots;
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 1>(c, A, B, ta, pp, &nb[1], st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 2>(c, A, B, ta, pp, &nb[1], st))); }
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 1>(c, A, Y, ta, pp, &nb[1], st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 2>(c, A, Y, ta, pp, &nb[1], st))); }
     if (e != hipSuccess) return hip_fail(c, e);
   }
   {
     const int m = c->m[0];
     const SolveTab* ta = tabs + tab_index(0, 0, 0, S);
     double* pp = part + 2 * (size_t)kAdjMaxBlocks * kGradSlots;
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1>(c, u, A, lam_out, ta, pp, &nb[2], st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 2>(c, u, A, lam_out, ta, pp, &nb[2], st))); }
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 2>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
     if (e != hipSuccess) return hip_fail(c, e);
   }
   hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, part, (int)nb[0], (int)nb[1],

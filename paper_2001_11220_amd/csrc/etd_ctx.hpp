@@ -59,14 +59,19 @@ int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st);
 Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds);
 size_t geom_lds(const Geom& g, size_t fixed_lds);
 
+// Pass geometries of the single-problem stepper (see PassGeom).
+enum PassKind : int { kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3 };
+PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines);
+size_t pass_lds(const PassGeom& g, size_t fixed_lds);
+
 // The i-th carried array (s*N doubles) of a workspace.
 inline double* ws_array(const etd_rdp_ctx* c, void* ws, int i) {
   return reinterpret_cast<double*>(static_cast<char*>(ws) + c->tab_bytes + i * c->arr_bytes);
 }
 
 // Launches forward pass p (0-based) of one step.  Pass 0 reads u and writes
-// the carried triple `out`; a middle pass reads `in` and writes `out` (the
-// two may be the same arrays); the last pass reads `in` and writes u.
+// the carried triple `out`; a middle pass reads `in` and writes `out` (which
+// must not overlap); the last pass reads `in` and writes u.
 int launch_pass(etd_rdp_ctx* c, int p, double* u, double* const (&in)[3],
                 double* const (&out)[3], const SolveTab* tabs, hipStream_t st);
 

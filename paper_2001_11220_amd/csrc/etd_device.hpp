@@ -339,6 +339,102 @@ struct TilePos {
   }
 };
 
+template <int M>
+__device__ __forceinline__ void load_chunk(const double* __restrict__ p, double (&v)[M], bool act);
+
+// Geometry of one pass of the single-problem stepper.  Each pass reads the
+// lines it solves contiguously and writes its outputs transposed, in the
+// layout the next pass reads contiguously:
+//   lines (f, t), f in [0, nF) in tiles of kBlockLines consecutive f,
+//   t in [0, nT);
+//   direct access: line (f, t) is contiguous at f*inF + t*inT;
+//   transposed access: row j of line (f, t) is at f + t*outT + j*outRow, so
+//   a tile's rows are runs of kBlockLines adjacent doubles.
+struct PassGeom {
+  int64_t nF, nT, nFblk;
+  int64_t inF, inT, outT, outRow;
+  int64_t N;                    // species stride
+  int n, C, pitch, nbuf, tile;  // line length, chunks, LDS pitch/buffers/size
+  int lines;                    // lines per tile = wavefronts per block
+};
+
+struct TileAt {
+  int64_t t, f0;
+  __device__ __forceinline__ TileAt(int64_t tile, const PassGeom& g)
+      : t(tile / g.nFblk), f0((tile % g.nFblk) * g.lines) {}
+};
+
+// This wave's chunk of its line (f0 + wave, t) read directly; zeros for a
+// line past nF or a lane without a chunk.
+template <int M>
+__device__ __forceinline__ void line_load(const double* __restrict__ A, double (&v)[M],
+                                          const PassGeom& g, const TileAt& p) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t f = p.f0 + w;
+  const bool ok = (lane < g.C) && (f < g.nF);
+  const double* src = ok ? A + f * g.inF + p.t * g.inT + (int64_t)lane * M : A;
+  load_chunk<M>(src, v, ok);
+}
+
+// Transposed read, split for software pipelining as tile_fetch/tile_commit
+// above: thread (col, q) fetches rows q*M+i of column f0+col.  L is the
+// number of lines per tile (g.lines); the block has 64*L threads.
+template <int M, int L = kBlockLines>
+__device__ __forceinline__ void tile_fetch(const double* __restrict__ A, double (&r)[M],
+                                           const PassGeom& g, const TileAt& p) {
+  const int tid = threadIdx.x;
+  const int col = tid & (L - 1), q = tid / L;
+  if (q < g.C && p.f0 + col < g.nF) {
+    const double* src = A + p.f0 + col + p.t * g.outT + (int64_t)(q * M) * g.outRow;
+#pragma unroll
+    for (int i = 0; i < M; ++i) r[i] = src[i * g.outRow];
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) r[i] = 0.0;
+  }
+}
+
+template <int M, int L = kBlockLines>
+__device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M], double* lds,
+                                            const PassGeom& g, TileCursor& cur) {
+  const int tid = threadIdx.x;
+  const int col = tid & (L - 1), q = tid / L;
+  double* T = lds + cur.buf * g.tile;
+  if (q < g.C) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) T[col * g.pitch + i * g.C + q] = r[i];
+  }
+  __syncthreads();
+  const int w = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int j = 0; j < M; ++j) x[j] = (lane < g.C) ? T[w * g.pitch + j * g.C + lane] : 0.0;
+  if (g.nbuf == 1) __syncthreads();
+  else cur.buf ^= 1;
+}
+
+// Transposed write of every wave's line chunk (all threads call it).
+template <int M, int L = kBlockLines>
+__device__ __forceinline__ void tile_store(double* __restrict__ A, const double (&x)[M],
+                                           double* lds, const PassGeom& g, const TileAt& p,
+                                           TileCursor& cur) {
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  double* T = lds + cur.buf * g.tile;
+  if (lane < g.C) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) T[w * g.pitch + j * g.C + lane] = x[j];
+  }
+  __syncthreads();
+  const int col = tid & (L - 1), q = tid / L;
+  if (q < g.C && p.f0 + col < g.nF) {
+    double* dst = A + p.f0 + col + p.t * g.outT + (int64_t)(q * M) * g.outRow;
+#pragma unroll
+    for (int i = 0; i < M; ++i) dst[i * g.outRow] = T[col * g.pitch + i * g.C + q];
+  }
+  if (g.nbuf == 1) __syncthreads();
+  else cur.buf ^= 1;
+}
+
 constexpr int kBlock = 64 * kBlockLines;  // one wavefront per line
 constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
 

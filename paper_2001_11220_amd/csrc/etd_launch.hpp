@@ -19,7 +19,8 @@ hipError_t set_lds(KernelT kern, size_t bytes) {
 // Persistent grid: as many blocks as fit on the device at once (a multiple
 // of 8, one range of tiles per XCD), but no more than the tiles need.
 template <typename KernelT>
-hipError_t persistent_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid) {
+hipError_t persistent_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid,
+                           int threads = kBlock) {
   static int ncu = 0;
   if (ncu == 0) {
     int dev = 0;
@@ -30,7 +31,7 @@ hipError_t persistent_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* g
   }
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(kern), kBlock, lds);
+      &per_cu, reinterpret_cast<const void*>(kern), threads, lds);
   if (e != hipSuccess) return e;
   int64_t g = (int64_t)(per_cu > 0 ? per_cu : 1) * ncu;
   g = (g / 8) * 8;

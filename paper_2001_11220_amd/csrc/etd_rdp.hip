@@ -33,51 +33,63 @@
 
 namespace etd {
 
+// Data layouts.  The state u is [s][i_d]...[i_1] (axis 1 fastest).  Each
+// pass reads the lines it solves contiguously and writes its three outputs
+// transposed, in the layout the next pass reads contiguously:
+//   pass 1 writes A in [s][z][x][y] (3-D) or [s][x][y] (2-D),
+//   pass 2 (3-D) writes B in [s][x][y][z],
+//   pass d writes u.
+// A tile is 8 or 16 lines (kLinesFor) with adjacent indices in the output's
+// fastest dimension, so every transposed row write is a run of adjacent
+// doubles.
+
+// Waves per SIMD the pass kernels ask the compiler to fit (register budget):
+// four while a chunk's rows leave room.
+template <int M>
+constexpr int kMinWaves = (M <= 4) ? 4 : 2;
+
+// Lines per tile (= wavefronts per block) of the pass kernels: 16, so that a
+// transposed row is a whole 128-byte cache line, where the 128-register
+// budget of a 1024-thread block holds a chunk; 8 otherwise.
+template <int M>
+constexpr int kLinesFor = (M <= 4) ? 16 : 8;
+
 // ---------------------------------------------------------------------------
-// Pass 1: the contiguous axis.  One wavefront per line, all species; a line's
-// chunk of M consecutive doubles per lane is read directly (16-byte aligned
-// vector loads when M is even: n_1 = C*M is then even too).
+// Pass 1 (axis 1).  Tiles of 8 x-lines with adjacent y; the next tile's U is
+// fetched into registers while the current tile is solved.
 // ---------------------------------------------------------------------------
-template <int M, int S>
-__global__ __launch_bounds__(kBlock) void k_first(
-    const double* __restrict__ u, double* __restrict__ c1,
-    double* __restrict__ c2, double* __restrict__ w,
-    const SolveTab* __restrict__ tabs, Rx rx, double k, int64_t n1,
-    int64_t nlines, int64_t N, int etd1) {
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
+    const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
+    double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
+    int etd1) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
   stage_lane_tabs(tabs, 3 * S, lt);
   __syncthreads();
   const AxisTabs<S> at{tabs, lt};
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int C = tabs[0].C;
-  const bool act = lane < C;
-  // Each wavefront walks its own lines; the next line's U is fetched into
-  // registers before the current line is solved.
-  TileWalk walk((nlines + kBlockLines - 1) / kBlockLines);
+  const int lane = threadIdx.x & 63;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
-  auto line_of = [&](int64_t tl) { return tl * kBlockLines + wv; };
   bool have = walk.next(tile);
-  while (have && line_of(tile) >= nlines) have = walk.next(tile);
   double Un[S][M];
-  if (have) {
+  auto fetch = [&](int64_t tl_) {
+    const TileAt p(tl_, g);
 #pragma unroll
-    for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + line_of(tile) * n1 + (int64_t)lane * M, Un[s], act);
-  }
+    for (int s = 0; s < S; ++s) line_load<M>(u + s * g.N, Un[s], g, p);
+  };
+  if (have) fetch(tile);
   while (have) {
-    const int64_t line = line_of(tile);
-    const int64_t off = line * n1 + (int64_t)lane * M;
+    const TileAt pos(tile, g);
     double U[S][M], f[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
       for (int j = 0; j < M; ++j) U[s][j] = Un[s][j];
     have = walk.next(tile);
-    while (have && line_of(tile) >= nlines) have = walk.next(tile);
-    if (have) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + line_of(tile) * n1 + (int64_t)lane * M, Un[s], act);
-    }
+    if (have) fetch(tile);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       double uu[S], ff[S];
@@ -96,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_first(
         const SolveTab* tb[1] = {at.P(s)};
         const LaneTab* lb[1] = {at.lP(s)};
         line_solve<M, 1>(tb, lb, x, lane);
-        if (act) store_chunk<M>(w + s * N + off, x[0]);
+        tile_store<M, L>(w + s * g.N, x[0], tl, g, pos, cur);
         continue;
       }
       double x[5][M];
@@ -111,30 +123,29 @@ __global__ __launch_bounds__(kBlock) void k_first(
       const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
       const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
       line_solve<M, 5>(tb, lb, x, lane);
-      if (act) {
-        double o[M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) o[j] = 9.0 * x[0][j] - 8.0 * x[2][j];
-        store_chunk<M>(c1 + s * N + off, o);
-#pragma unroll
-        for (int j = 0; j < M; ++j) o[j] = 9.0 * x[1][j] - 8.0 * x[3][j];
-        store_chunk<M>(c2 + s * N + off, o);
-        store_chunk<M>(w + s * N + off, x[4]);
+      for (int j = 0; j < M; ++j) {
+        x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
+        x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
       }
+      tile_store<M, L>(c1 + s * g.N, x[0], tl, g, pos, cur);
+      tile_store<M, L>(c2 + s * g.N, x[1], tl, g, pos, cur);
+      tile_store<M, L>(w + s * g.N, x[4], tl, g, pos, cur);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Middle passes (3-D axis 2): purely linear, (c1, c2, w) -> (o1, o2, ow);
-// the outputs may be the inputs (each line is read before it is written).
-// Work items are (tile, species); the next item's tiles are fetched into
-// registers while the current one is solved.
+// Middle pass (3-D axis 2): purely linear, (c1, c2, w) -> (o1, o2, ow).
+// Tiles of 8 y-lines with adjacent z; work items are (tile, species) and the
+// next item's lines are fetched into registers while the current one is
+// solved.
 // ---------------------------------------------------------------------------
-template <int M, int S>
-__global__ __launch_bounds__(kBlock) void k_mid(
-    const double* c1, const double* c2, const double* w, double* o1, double* o2,
-    double* ow, const SolveTab* __restrict__ tabs, Geom g, int etd1) {
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
+    const double* __restrict__ c1, const double* __restrict__ c2,
+    const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
+    double* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
   double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
@@ -149,23 +160,24 @@ __global__ __launch_bounds__(kBlock) void k_mid(
   int s = 0;
   double pf[3][M];
   auto fetch = [&](int64_t tl_, int s_) {
-    const TilePos p(tl_, g);
+    const TileAt p(tl_, g);
     if (!etd1) {
-      tile_fetch<M>(c1 + s_ * g.N, pf[0], g, p.base, p.f0);
-      tile_fetch<M>(c2 + s_ * g.N, pf[1], g, p.base, p.f0);
+      line_load<M>(c1 + s_ * g.N, pf[0], g, p);
+      line_load<M>(c2 + s_ * g.N, pf[1], g, p);
     }
-    tile_fetch<M>(w + s_ * g.N, pf[2], g, p.base, p.f0);
+    line_load<M>(w + s_ * g.N, pf[2], g, p);
   };
   if (have) fetch(tile, 0);
   while (have) {
-    const TilePos pos(tile, g);
+    const TileAt pos(tile, g);
     const int sc = s;
     double x[5][M];
-    if (!etd1) {
-      tile_commit<M>(pf[0], x[0], tl, g, cur);
-      tile_commit<M>(pf[1], x[1], tl, g, cur);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[0][j] = pf[0][j];
+      x[1][j] = pf[1][j];
+      x[4][j] = pf[2][j];
     }
-    tile_commit<M>(pf[2], x[4], tl, g, cur);
     if (++s == S) {
       s = 0;
       have = walk.next(tile);
@@ -178,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_mid(
       const SolveTab* tb[1] = {at.P(sc)};
       const LaneTab* lb[1] = {at.lP(sc)};
       line_solve<M, 1>(tb, lb, y, lane);
-      tile_store<M>(ow + sc * g.N, y[0], tl, g, pos.base, pos.f0, cur);
+      tile_store<M, L>(ow + sc * g.N, y[0], tl, g, pos, cur);
       continue;
     }
 #pragma unroll
@@ -194,22 +206,23 @@ __global__ __launch_bounds__(kBlock) void k_mid(
       x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
       x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
     }
-    tile_store<M>(o1 + sc * g.N, x[0], tl, g, pos.base, pos.f0, cur);
-    tile_store<M>(o2 + sc * g.N, x[1], tl, g, pos.base, pos.f0, cur);
-    tile_store<M>(ow + sc * g.N, x[4], tl, g, pos.base, pos.f0, cur);
+    tile_store<M, L>(o1 + sc * g.N, x[0], tl, g, pos, cur);
+    tile_store<M, L>(o2 + sc * g.N, x[1], tl, g, pos, cur);
+    tile_store<M, L>(ow + sc * g.N, x[4], tl, g, pos, cur);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Last pass (axis d): predictor solve, f*, corrector solves, new state.
-// Per tile the loads come in groups (w of all species; then c1, c2 of each
-// species); each group is fetched into registers one group ahead.
+// Tiles of 8 lines with adjacent x.  Per tile the loads come in groups (w of
+// all species; then c1, c2 of each species); each group is fetched into
+// registers one group ahead.
 // ---------------------------------------------------------------------------
-template <int M, int S>
-__global__ __launch_bounds__(kBlock) void k_last(
-    double* __restrict__ u, const double* __restrict__ c1,
-    const double* __restrict__ c2, const double* __restrict__ w,
-    const SolveTab* __restrict__ tabs, Rx rx, double k, Geom g, int etd1) {
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
+    double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
+    const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
+    PassGeom g, int etd1) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
   double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
@@ -222,24 +235,26 @@ __global__ __launch_bounds__(kBlock) void k_last(
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   bool have = walk.next(tile);
-  double pf[2][M];
+  double pf[2][M];  // S <= 2
   auto fetch_w = [&](int64_t tl_) {
-    const TilePos p(tl_, g);
+    const TileAt p(tl_, g);
 #pragma unroll
-    for (int s = 0; s < S; ++s) tile_fetch<M>(w + s * g.N, pf[s], g, p.base, p.f0);
+    for (int s = 0; s < S; ++s) line_load<M>(w + s * g.N, pf[s], g, p);
   };
   auto fetch_c = [&](int64_t tl_, int s_) {
-    const TilePos p(tl_, g);
-    tile_fetch<M>(c1 + s_ * g.N, pf[0], g, p.base, p.f0);
-    tile_fetch<M>(c2 + s_ * g.N, pf[1], g, p.base, p.f0);
+    const TileAt p(tl_, g);
+    line_load<M>(c1 + s_ * g.N, pf[0], g, p);
+    line_load<M>(c2 + s_ * g.N, pf[1], g, p);
   };
   if (have) fetch_w(tile);
   while (have) {
-    const TilePos pos(tile, g);
+    const TileAt pos(tile, g);
     const int64_t tcur = tile;
     double us[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) tile_commit<M>(pf[s], us[s], tl, g, cur);
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int j = 0; j < M; ++j) us[s][j] = pf[s][j];
     if (etd1) {
       have = walk.next(tile);
       if (have) fetch_w(tile);
@@ -258,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_last(
     }
     if (etd1) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M>(u + s * g.N, us[s], tl, g, pos.base, pos.f0, cur);
+      for (int s = 0; s < S; ++s) tile_store<M, L>(u + s * g.N, us[s], tl, g, pos, cur);
       continue;
     }
     // us holds U*; f* = F(U*) overwrites it.
@@ -274,8 +289,11 @@ __global__ __launch_bounds__(kBlock) void k_last(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double a[M], b[M], x[2][M];
-      tile_commit<M>(pf[0], a, tl, g, cur);
-      tile_commit<M>(pf[1], b, tl, g, cur);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        a[j] = pf[0][j];
+        b[j] = pf[1][j];
+      }
       if (s + 1 < S) {
         fetch_c(tcur, s + 1);
       } else {
@@ -292,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_last(
       line_solve<M, 2>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
-      tile_store<M>(u + s * g.N, a, tl, g, pos.base, pos.f0, cur);
+      tile_store<M, L>(u + s * g.N, a, tl, g, pos, cur);
     }
   }
 }
@@ -441,53 +459,111 @@ size_t geom_lds(const Geom& g, size_t fixed_lds) {
   return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
 }
 
+PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines) {
+  const int64_t n1 = c->n[0], n2 = c->n[1], n3 = (c->d == 3) ? c->n[2] : 1;
+  PassGeom g{};
+  g.N = c->N;
+  int axis0 = 0;
+  switch (kind) {
+    case kPassFirst:  // x-lines (y, z) of u -> A (y fastest)
+      axis0 = 0;
+      g.nF = n2; g.nT = n3;
+      g.inF = n1; g.inT = n1 * n2;
+      g.outT = n1 * n2; g.outRow = n2;
+      break;
+    case kPassMid:  // y-lines (z, x) of A -> B (z fastest)
+      axis0 = 1;
+      g.nF = n3; g.nT = n1;
+      g.inF = n1 * n2; g.inT = n2;
+      g.outT = n2 * n3; g.outRow = n3;
+      break;
+    case kPassLast:  // lines (x, y) along axis d of B (3-D) or A (2-D) -> u
+      axis0 = c->d - 1;
+      g.nF = n1;
+      if (c->d == 3) {
+        g.nT = n2; g.inF = n2 * n3; g.inT = n3;
+        g.outT = n1; g.outRow = n1 * n2;
+      } else {
+        g.nT = 1; g.inF = n2; g.inT = 0;
+        g.outT = 0; g.outRow = n1;
+      }
+      break;
+    default:  // kPassAdjMid: y-lines (x, z), direct from A, transposed in u's layout
+      axis0 = 1;
+      g.nF = n1; g.nT = n3;
+      g.inF = n2; g.inT = n1 * n2;
+      g.outT = n1 * n2; g.outRow = n1;
+      break;
+  }
+  g.n = static_cast<int>(c->n[axis0]);
+  g.C = g.n / c->m[axis0];
+  g.pitch = g.n + ((8 - g.n % 32) + 32) % 32;  // = 8 (mod 32), see tile_store
+  g.lines = lines;
+  g.tile = lines * g.pitch;
+  // Two tile buffers (one barrier per move) when they fit beside the tables:
+  // in half the LDS for 8-line blocks (two blocks per CU), in all of it for
+  // 16-line blocks (their register budget allows one block per CU).
+  const size_t lds_cap = (lines >= 16) ? kLdsMax : kLdsMax / 2;
+  g.nbuf = (fixed_lds + 2 * sizeof(double) * (size_t)g.tile <= lds_cap) ? 2 : 1;
+  g.nFblk = (g.nF + lines - 1) / lines;
+  return g;
+}
+
+size_t pass_lds(const PassGeom& g, size_t fixed_lds) {
+  return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
+}
+
 namespace {
 
 // Launchers, templated on the chunk length and species count.
 template <int M, int S>
 hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                         double* w, const SolveTab* tabs, hipStream_t st) {
-  const int64_t nlines = c->N / c->n[0];
-  const size_t lds = lane_lds(3 * S);
-  hipError_t e = set_lds(k_first<M, S>, lds);
+  const size_t fixed = lane_lds(3 * S);
+  constexpr int L = kLinesFor<M>;
+  const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_first<M, S, L>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_first<M, S>, lds, (nlines + kBlockLines - 1) / kBlockLines, &grid);
+  e = persistent_grid(k_first<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_first<M, S>), dim3(grid), dim3(kBlock), lds, st, u, c1, c2, w, tabs,
-                     c->rx, c->k, c->n[0], nlines, c->N, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  hipLaunchKernelGGL((k_first<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int M, int S>
 hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
                       const double* w, double* o1, double* o2, double* ow,
-                      const SolveTab* tabs, int axis0, hipStream_t st) {
+                      const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds(3 * S);
-  const Geom g = make_geom(c, axis0, fixed);
-  const size_t lds = geom_lds(g, fixed);
-  hipError_t e = set_lds(k_mid<M, S>, lds);
+  constexpr int L = kLinesFor<M>;
+  const PassGeom g = pass_geom(c, kPassMid, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_mid<M, S, L>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_mid<M, S>, lds, g.nFblk * g.nT, &grid);
+  e = persistent_grid(k_mid<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<M, S>), dim3(grid), dim3(kBlock), lds, st, c1, c2, w, o1, o2, ow,
+  hipLaunchKernelGGL((k_mid<M, S, L>), dim3(grid), dim3(64 * L), lds, st, c1, c2, w, o1, o2, ow,
                      tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int M, int S>
 hipError_t launch_last(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
-                       const double* w, const SolveTab* tabs, int axis0, hipStream_t st) {
+                       const double* w, const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds(3 * S);
-  const Geom g = make_geom(c, axis0, fixed);
-  const size_t lds = geom_lds(g, fixed);
-  hipError_t e = set_lds(k_last<M, S>, lds);
+  constexpr int L = kLinesFor<M>;
+  const PassGeom g = pass_geom(c, kPassLast, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_last<M, S, L>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_last<M, S>, lds, g.nFblk * g.nT, &grid);
+  e = persistent_grid(k_last<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_last<M, S>), dim3(grid), dim3(kBlock), lds, st, u, c1, c2, w, tabs,
+  hipLaunchKernelGGL((k_last<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
                      c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
@@ -529,13 +605,13 @@ int launch_pass(etd_rdp_ctx* c, int p, double* u, double* const (&in)[3],
     if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1>(c, u, out[0], out[1], out[2], ta, st))); }
     else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2>(c, u, out[0], out[1], out[2], ta, st))); }
   } else if (p == c->d - 1) {
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, in[0], in[1], in[2], ta, p, st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, in[0], in[1], in[2], ta, p, st))); }
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, in[0], in[1], in[2], ta, st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, in[0], in[1], in[2], ta, st))); }
   } else {
     if (S == 1) {
-      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, p, st)));
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     } else {
-      ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, p, st)));
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     }
   }
   if (e != hipSuccess) return hip_fail(c, e);
@@ -544,11 +620,16 @@ int launch_pass(etd_rdp_ctx* c, int p, double* u, double* const (&in)[3],
 
 namespace {
 
+// Passes first..npasses-1 of a step: pass 1 writes A, pass 2 (3-D) reads A
+// and writes B, pass d reads the last triple written.
 int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipStream_t st) {
   const SolveTab* tabs = static_cast<const SolveTab*>(ws);
-  double* const carried[3] = {ws_array(c, ws, 0), ws_array(c, ws, 1), ws_array(c, ws, 2)};
+  double* const A[3] = {ws_array(c, ws, 0), ws_array(c, ws, 1), ws_array(c, ws, 2)};
+  double* const B[3] = {ws_array(c, ws, 3), ws_array(c, ws, 4), ws_array(c, ws, 5)};
   for (int p = first; p < npasses; ++p) {
-    const int rc = launch_pass(c, p, u, carried, carried, tabs, st);
+    const bool into_b = (p == 1 && c->d == 3);
+    const bool from_b = (p == 2);
+    const int rc = launch_pass(c, p, u, from_b ? B : A, into_b ? B : A, tabs, st);
     if (rc) return rc;
   }
   return ETD_OK;
@@ -636,10 +717,10 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
       }
   c->tab_bytes = round_up(c->tabs.size() * sizeof(SolveTab), 256);
   c->arr_bytes = round_up(sizeof(double) * static_cast<size_t>(N) * s, 256);
-  c->ws_bytes = c->tab_bytes + 3 * c->arr_bytes;
+  c->ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes;
   c->nparams = reaction_param_count(rx->model, s);
   c->part_bytes = round_up(sizeof(double) * kAdjPasses * kAdjMaxBlocks * kGradSlots, 256);
-  c->adj_ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes + c->part_bytes;
+  c->adj_ws_bytes = c->tab_bytes + (d == 3 ? 9 : 6) * c->arr_bytes + c->part_bytes;
   *out = c;
   return ETD_OK;
 }
@@ -655,12 +736,24 @@ int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes) {
   return ETD_OK;
 }
 
-int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, size_t* off_c1, size_t* off_c2,
-                             size_t* off_w) {
-  if (!ctx || !off_c1 || !off_c2 || !off_w) return ETD_ERR_ARG;
-  *off_c1 = ctx->tab_bytes;
-  *off_c2 = ctx->tab_bytes + ctx->arr_bytes;
-  *off_w = ctx->tab_bytes + 2 * ctx->arr_bytes;
+int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass, size_t* off_c1,
+                             size_t* off_c2, size_t* off_w, int64_t* strides) {
+  if (!ctx || !off_c1 || !off_c2 || !off_w || !strides) return ETD_ERR_ARG;
+  if (pass < 1 || pass > ctx->d - 1) return ETD_ERR_ARG;
+  const int first = (pass == 1) ? 0 : 3;
+  *off_c1 = ctx->tab_bytes + first * ctx->arr_bytes;
+  *off_c2 = ctx->tab_bytes + (first + 1) * ctx->arr_bytes;
+  *off_w = ctx->tab_bytes + (first + 2) * ctx->arr_bytes;
+  const int64_t n1 = ctx->n[0], n2 = ctx->n[1], n3 = (ctx->d == 3) ? ctx->n[2] : 1;
+  if (pass == 1) {  // [z][x][y]
+    strides[0] = n2;
+    strides[1] = 1;
+    if (ctx->d == 3) strides[2] = n1 * n2;
+  } else {  // [x][y][z]
+    strides[0] = n2 * n3;
+    strides[1] = n3;
+    strides[2] = 1;
+  }
   return ETD_OK;
 }
 

@@ -70,7 +70,8 @@ def _load():
                                         ctypes.POINTER(Scheme), ctypes.POINTER(Reaction), ctypes.POINTER(P)]),
         "etd_rdp_destroy": (ctypes.c_int, [P]),
         "etd_rdp_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
-        "etd_rdp_workspace_layout": (ctypes.c_int, [P, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
+        "etd_rdp_workspace_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ),
+                                                    ctypes.POINTER(SZ), ctypes.POINTER(I64)]),
         "etd_rdp_step": (ctypes.c_int, [P, P, P, SZ, I64, P]),
         "etd_rdp_debug_passes": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_run_pass": (ctypes.c_int, [P, P, P, SZ, I32, P]),
@@ -205,24 +206,29 @@ class EtdRdp:
         p = ws.data_ptr()
         return p + (-p) % 256
 
-    def layout(self):
+    def layout(self, npass=1):
+        """(offsets of c1, c2, w in bytes, element strides of axes 1..d) of
+        the carried triple pass ``npass`` writes."""
         a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
-        _check(lib.etd_rdp_workspace_layout(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
-               "etd_rdp_workspace_layout")
-        return a.value, b.value, c.value
+        st = (ctypes.c_int64 * MAX_DIM)()
+        _check(lib.etd_rdp_workspace_layout(self._ctx, int(npass), ctypes.byref(a), ctypes.byref(b),
+                                            ctypes.byref(c), st), "etd_rdp_workspace_layout")
+        return (a.value, b.value, c.value), tuple(int(st[i]) for i in range(self.d))
 
-    def carried(self):
-        """Views (c1, c2, w) of the carried arrays inside the workspace."""
+    def carried(self, npass=1):
+        """Views (c1, c2, w) of the triple pass ``npass`` wrote, each with the
+        state's logical shape (s, n_d, ..., n_1)."""
         import torch
         ws = self.workspace()
         base = self._ws_ptr() - ws.data_ptr()
-        n = self.s
+        N = 1
         for v in self.shape:
-            n *= v
+            N *= v
+        offs, strides = self.layout(npass)
         out = []
-        for off in self.layout():
-            t = ws[base + off: base + off + 8 * n].view(torch.float64)
-            out.append(t.view((self.s,) + self.shape[::-1]))
+        for off in offs:
+            flat = ws[base + off: base + off + 8 * N * self.s].view(torch.float64)
+            out.append(flat.as_strided((self.s,) + self.shape[::-1], (N,) + strides[::-1]))
         return tuple(out)
 
     def line_split(self, axis):

@@ -65,9 +65,19 @@ def test_workspace_size_and_layout():
     p = _init((64, 32, 16), ("neumann", "periodic", "dirichlet"))
     N = 64 * 32 * 16
     arr = ((8 * N * 2 + 255) // 256) * 256
-    c1, c2, w = p.layout()
+    (c1, c2, w), st1 = p.layout(1)
     assert c1 % 256 == 0 and c2 - c1 == arr and w - c2 == arr
-    assert p.ws_bytes == w + arr
+    assert st1 == (32, 1, 64 * 32)  # [z][x][y]
+    (d1, d2, dw), st2 = p.layout(2)
+    assert d1 == w + arr and d2 - d1 == arr and dw - d2 == arr
+    assert st2 == (32 * 16, 16, 1)  # [x][y][z]
+    assert p.ws_bytes == dw + arr
+    q = _init((64, 32), ("neumann", "periodic"))
+    (e1, _, ew), st = q.layout(1)
+    assert st == (32, 1) and q.ws_bytes == ew + ((8 * 64 * 32 * 2 + 255) // 256) * 256
+    etd = _lib()
+    with pytest.raises(etd.EtdError):
+        q.layout(2)
 
 
 def test_invalid_arguments():
@@ -122,12 +132,12 @@ def test_adjoint_workspace_and_gradient_size():
     N = 64 * 32 * 16
     arr = ((8 * N * 2 + 255) // 256) * 256
     p = _init((64, 32, 16), ("neumann", "periodic", "dirichlet"))
-    c1, _, _ = p.layout()
-    # tables, six carried arrays (3-D), block sums; the forward layout is a prefix
-    assert p.adj_ws_bytes > c1 + 6 * arr and p.adj_ws_bytes >= p.ws_bytes
+    (c1, _, _), _ = p.layout(1)
+    # tables, nine carried arrays (3-D), block sums; the forward layout is a prefix
+    assert p.adj_ws_bytes > c1 + 9 * arr and p.adj_ws_bytes >= p.ws_bytes
     q = _init((64, 32), ("neumann", "periodic"))
     arr2 = ((8 * 64 * 32 * 2 + 255) // 256) * 256
-    assert q.adj_ws_bytes > q.layout()[0] + 3 * arr2
+    assert q.adj_ws_bytes > q.layout(1)[0][0] + 6 * arr2
     sizes = {"brusselator": ({"a": 1.0, "b": 3.0}, 2, 4), "gray_scott": ({"F": 0.04, "kappa": 0.06}, 2, 4),
              "schnakenberg": ({"a": 0.1, "b": 0.9, "gamma": 1.0}, 2, 5), "cgl": ({"beta": 0.5}, 2, 3),
              "linear": ({"C": [[0.1, 0.2], [0.3, 0.4]]}, 2, 6), "enzyme": ({}, 1, 1)}

@@ -121,7 +121,7 @@ def test_pass_intermediates_3d(bcs):
         u = torch.from_numpy(u0.copy()).cuda()
         e.debug_passes(u, npass)
         torch.cuda.synchronize()
-        got = [t.cpu().numpy() for t in e.carried()]
+        got = [t.cpu().numpy() for t in e.carried(npass)]
         for g, key in zip(got, keys):
             assert rel_l2(g, ref[key]) < 1e-13, (npass, key, rel_l2(g, ref[key]))
 
