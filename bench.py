@@ -15,6 +15,7 @@ state, which is resident in HBM before timing starts.  Prints one JSON line.
                cell-species: pass 1 reads U and writes c1, c2, w (4 words),
                a middle pass reads and writes all three (6 words), the last
                pass reads three and writes U (4 words); 1 word = 8 bytes.
+               step_effective_GBps is the same ratio for the whole step.
 * cpu_baseline the FP64 oracle on the host, one thread, on a bounded
                sample of the same workload (stated in "sample").
 """
@@ -41,12 +42,14 @@ def pass_words(d: int):
 
 
 def pass_names(e, d: int):
-    """Kernel names (as rocprofv3 prints them, shortened) of each pass."""
+    """Kernel names (as rocprofv3 prints them, shortened) of each pass: the
+    chunk length m, the species count and the lines per tile (16 when
+    m <= 4, else 8)."""
     names = []
     for p in range(1, d + 1):
         m, _ = e.line_split(p)
         kind = "k_first" if p == 1 else ("k_last" if p == d else "k_mid")
-        names.append(f"{kind}<{m}, {e.s}>")
+        names.append(f"{kind}<{m}, {e.s}, {16 if m <= 4 else 8}>")
     return names
 
 
