@@ -59,9 +59,8 @@ __device__ __forceinline__ void ends_scale(double (&x)[M], int lane, int C, doub
 template <int M>
 __device__ __forceinline__ double lap_dot(const double (&yb)[M], const double (&x)[M], int lane,
                                           int C, int bc) {
-  const int lane4 = lane * 4;
-  const double pl = bperm((lane4 - 4) & 255, x[M - 1]);  // row c*M - 1
-  const double pr = bperm((lane4 + 4) & 255, x[0]);      // row c*M + M
+  const double pl = from_prev(x[M - 1]);  // row c*M - 1
+  const double pr = from_next(x[0]);      // row c*M + M
   const double xlast = lane_value(x[M - 1], C - 1);
   const double xfirst = lane_value(x[0], 0);
   double xl = pl, xr = pr;

@@ -92,6 +92,28 @@ __device__ __forceinline__ double bperm(int addr, double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Value of v from lane-1 (0 on lane 0) and from lane+1 (0 on lane 63):
+// DPP wavefront shifts, on the vector ALU instead of the LDS pipe.
+__device__ __forceinline__ double from_prev(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_next(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Values of v from lane-32 (on lanes 32..63; a lane's own value below) and
+// from lane+32 (on lanes 0..31; own value above): one permlane32 swap.
+__device__ __forceinline__ void halves_swap(double v, double& up, double& dn) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  up = __hiloint2double(hi[0], lo[0]);
+  dn = __hiloint2double(hi[1], lo[1]);
+}
+
 // Exact line solves on a wavefront.
 //
 // A block holds kBlockLines lines, one per wavefront; lane c of a wavefront
@@ -165,7 +187,8 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       for (int j = Q - 2; j >= 0; --j) x[k][j] = fma(h[k].cp[j], x[k][j + 1], x[k][j]);
     }
   }
-  // 2. Right-hand side of the reduced separator system.
+  // 2. Right-hand side of the reduced separator system.  The last chunk's
+  // right neighbour is row 0 (it only matters for the periodic closure).
   const bool last = (lane + 1 == C);
   const int lane4 = lane * 4;
   const int a_next = last ? 0 : lane4 + 4;
@@ -187,9 +210,19 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
     d[k] = v;
   }
   // 3. Parallel cyclic reduction across the lanes.  Lanes with no neighbour
-  // at distance sh have a zero multiplier; they read a wrapped-around lane.
+  // at distance sh have a zero multiplier; what they read there does not
+  // matter.  Distance 1 uses DPP shifts, distance 32 a permlane32 swap, the
+  // others ds_bpermute.
+  if (npcr > 0) {
 #pragma unroll
-  for (int st = 0; st < kMaxPcr; ++st) {
+    for (int k = 0; k < K; ++k) {
+      const double dm = from_prev(d[k]);
+      const double dp = from_next(d[k]);
+      d[k] = d[k] - lt[k]->k1[0][lane] * dm - lt[k]->k2[0][lane] * dp;
+    }
+  }
+#pragma unroll
+  for (int st = 1; st < kMaxPcr - 1; ++st) {
     if (st < npcr) {
       const int a_up = (lane4 - (4 << st)) & 255;
       const int a_dn = (lane4 + (4 << st)) & 255;
@@ -201,8 +234,15 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       }
     }
   }
+  if (npcr > kMaxPcr - 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double dm, dp;
+      halves_swap(d[k], dm, dp);
+      d[k] = d[k] - lt[k]->k1[kMaxPcr - 1][lane] * dm - lt[k]->k2[kMaxPcr - 1][lane] * dp;
+    }
+  }
   // 4. Separators, cyclic fix, and back to the chunk.
-  const int a_prev = (lane4 - 4) & 255;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double s = d[k] * lt[k]->inv[lane];
@@ -210,7 +250,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       const double vy = lane_value(s, 0) + h[k].vfac * lane_value(s, C - 1);
       s = fma(-vy * h[k].smfac, lt[k]->z[lane], s);
     }
-    const double sprev = bperm(a_prev, s);
+    const double sprev = from_prev(s);
     const double slast = lane_value(s, C - 1);
     double ghost = fma(h[k].gh0, s, h[k].ghw * slast);
     if constexpr (Q > 1) ghost = fma(h[k].ghd, x[k][1], ghost);
