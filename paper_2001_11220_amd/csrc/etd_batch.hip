@@ -2,10 +2,10 @@
 //
 // Every instance runs the same two passes as a single 2-D problem (the frame
 // of Section 6, eq. done): pass 1 along axis 1 (f, w, R_1 U, R_1 f, P_1 w)
-// and pass 2 along axis 2 (P_2, f*, T_2 / S_2).  Instances are grouped by the
-// chunk length m of the pass's axis (one kernel instantiation per m); one
-// launch per (pass, group) walks the group's tiles, 8 lines each, in
-// instance order.  A persistent block re-stages the per-lane PCR data in LDS
+// and pass 2 along axis 2 (P_2, f*, T_2 / S_2), with the same data layouts
+// and tiles.  Instances are grouped by the chunk length m of the pass's axis
+// (one kernel instantiation per m); one launch per (pass, group) walks the
+// group's tiles, 8 or 16 lines each, in instance order.  A persistent block re-stages the per-lane PCR data in LDS
 // only when its next tile belongs to another instance.  The launches of all
 // steps can be recorded into one HIP graph.
 #include <hip/hip_runtime.h>
@@ -26,31 +26,38 @@
 
 namespace etd {
 
-// Device descriptor of one instance.
+// Device descriptor of one instance: its offset in the packed arrays and the
+// geometry of its two passes.  Pass 1 reads x-lines of u and writes the
+// instance's carried triple with y fastest ([s][x][y]); pass 2 reads those
+// y-lines and writes u (the same rotation as the single-problem 2-D step).
 struct BatchInst {
-  int64_t off;            // start of the instance's state (doubles)
-  int64_t N;              // n1 * n2: species stride
-  int64_t n1, n2;
+  int64_t off;            // start of the instance's state and carried arrays
+  PassGeom g1, g2;        // pass geometries (tile buffers sized per group)
   const SolveTab* tab1;   // 3*S tables of axis 1
   const SolveTab* tab2;   // 3*S tables of axis 2
   Rx rx;
 };
 
-// Pass 1 of the ensemble (contiguous axis): one wavefront per line.
-template <int M, int S>
-__global__ __launch_bounds__(kBlock) void kb_first(
+// Pass 1 of the ensemble (axis 1).  A tile is L x-lines of one instance with
+// adjacent y; tile_loc gives its first line / L.
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
     const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
     double* __restrict__ w, const BatchInst* __restrict__ insts,
     const int* __restrict__ tile_inst, const int* __restrict__ tile_loc, int64_t ntiles,
     double k, int etd1) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  const int lane = threadIdx.x & 63;
   int staged = -1;
+  TileCursor cur;
   TileWalk walk(ntiles);
   int64_t tile;
   while (walk.next(tile)) {
-    const int ii = tile_inst[tile];
+    // Wave-uniform by construction; readfirstlane lets the descriptor loads
+    // go to scalar registers.
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const BatchInst& I = insts[ii];
     if (ii != staged) {
       __syncthreads();
@@ -59,14 +66,11 @@ __global__ __launch_bounds__(kBlock) void kb_first(
       staged = ii;
     }
     const AxisTabs<S> at{I.tab1, lt};
-    const int64_t line = (int64_t)tile_loc[tile] * kBlockLines + wv;
-    if (line >= I.n2) continue;
-    const int C = I.tab1[0].C;
-    const bool act = lane < C;
-    const int64_t off = I.off + line * I.n1 + (int64_t)lane * M;
+    const PassGeom g = I.g1;
+    const TileAt pos(0, (int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
     double U[S][M], f[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) load_chunk<M>(u + s * I.N + off, U[s], act);
+    for (int s = 0; s < S; ++s) line_load<M>(u + I.off + s * g.N, U[s], g, pos);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       double uu[S], ff[S];
@@ -78,6 +82,7 @@ __global__ __launch_bounds__(kBlock) void kb_first(
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+      const int64_t o = I.off + s * g.N;
       if (etd1) {
         double x[1][M];
 #pragma unroll
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void kb_first(
         const SolveTab* tb[1] = {at.P(s)};
         const LaneTab* lb[1] = {at.lP(s)};
         line_solve<M, 1>(tb, lb, x, lane);
-        if (act) store_chunk<M>(w + s * I.N + off, x[0]);
+        tile_store<M, L>(w + o, x[0], tl, g, pos, cur);
         continue;
       }
       double x[5][M];
@@ -100,29 +105,27 @@ __global__ __launch_bounds__(kBlock) void kb_first(
       const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
       const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
       line_solve<M, 5>(tb, lb, x, lane);
-      if (act) {
-        double o[M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) o[j] = 9.0 * x[0][j] - 8.0 * x[2][j];
-        store_chunk<M>(c1 + s * I.N + off, o);
-#pragma unroll
-        for (int j = 0; j < M; ++j) o[j] = 9.0 * x[1][j] - 8.0 * x[3][j];
-        store_chunk<M>(c2 + s * I.N + off, o);
-        store_chunk<M>(w + s * I.N + off, x[4]);
+      for (int j = 0; j < M; ++j) {
+        x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
+        x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
       }
+      tile_store<M, L>(c1 + o, x[0], tl, g, pos, cur);
+      tile_store<M, L>(c2 + o, x[1], tl, g, pos, cur);
+      tile_store<M, L>(w + o, x[4], tl, g, pos, cur);
     }
   }
 }
 
-// Pass 2 of the ensemble (axis 2, stride n1): tiles of 8 adjacent x-lines
-// moved through LDS.  tile_cap is the LDS tile buffer size (doubles) the
-// launch reserved: at least 8 * pitch of every instance in the group.
-template <int M, int S>
-__global__ __launch_bounds__(kBlock) void kb_last(
+// Pass 2 of the ensemble (axis 2).  A tile is L y-lines of one instance with
+// adjacent x, read line by line from the carried triple; u is written
+// through the LDS transpose.
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_last(
     double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
     const double* __restrict__ w, const BatchInst* __restrict__ insts,
     const int* __restrict__ tile_inst, const int* __restrict__ tile_loc, int64_t ntiles,
-    double k, int nbuf, int tile_cap, int etd1) {
+    double k, int etd1) {
   extern __shared__ double lds[];
   LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
   double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
@@ -133,7 +136,9 @@ __global__ __launch_bounds__(kBlock) void kb_last(
   TileWalk walk(ntiles);
   int64_t tile;
   while (walk.next(tile)) {
-    const int ii = tile_inst[tile];
+    // Wave-uniform by construction; readfirstlane lets the descriptor loads
+    // go to scalar registers.
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const BatchInst& I = insts[ii];
     if (ii != staged) {
       __syncthreads();
@@ -142,27 +147,11 @@ __global__ __launch_bounds__(kBlock) void kb_last(
       staged = ii;
     }
     const AxisTabs<S> at{I.tab2, lt};
-    Geom g;
-    g.nF = I.n1;
-    g.nT = 1;
-    g.sRow = I.n1;
-    g.sT = 0;
-    g.N = I.N;
-    g.n = static_cast<int>(I.n2);
-    g.C = I.tab2[0].C;
-    g.pitch = g.n + ((8 - g.n % 32) + 32) % 32;
-    g.nbuf = nbuf;
-    g.tile = tile_cap;
-    g.nFblk = (I.n1 + kBlockLines - 1) / kBlockLines;
-    const int64_t f0 = (int64_t)tile_loc[tile] * kBlockLines;
-    const int64_t base = I.off + f0;
+    const PassGeom g = I.g2;
+    const TileAt pos(0, (int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
     double us[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      double r[M];
-      tile_fetch<M>(w + s * g.N, r, g, base, f0);
-      tile_commit<M>(r, us[s], tl, g, cur);
-    }
+    for (int s = 0; s < S; ++s) line_load<M>(w + I.off + s * g.N, us[s], g, pos);
     {
       const SolveTab* tb[S];
       const LaneTab* lb[S];
@@ -175,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void kb_last(
     }
     if (etd1) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M>(u + s * g.N, us[s], tl, g, base, f0, cur);
+      for (int s = 0; s < S; ++s) tile_store<M, L>(u + I.off + s * g.N, us[s], tl, g, pos, cur);
       continue;
     }
 #pragma unroll
@@ -189,11 +178,10 @@ __global__ __launch_bounds__(kBlock) void kb_last(
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      double a[M], b[M], x[2][M], r[M];
-      tile_fetch<M>(c1 + s * g.N, r, g, base, f0);
-      tile_commit<M>(r, a, tl, g, cur);
-      tile_fetch<M>(c2 + s * g.N, r, g, base, f0);
-      tile_commit<M>(r, b, tl, g, cur);
+      const int64_t o = I.off + s * g.N;
+      double a[M], b[M], x[2][M];
+      line_load<M>(c1 + o, a, g, pos);
+      line_load<M>(c2 + o, b, g, pos);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         x[0][j] = fma(k, us[s][j], fma(k2, b[j], 9.0 * a[j]));
@@ -204,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void kb_last(
       line_solve<M, 2>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
-      tile_store<M>(u + s * g.N, a, tl, g, base, f0, cur);
+      tile_store<M, L>(u + o, a, tl, g, pos, cur);
     }
   }
 }
@@ -217,10 +205,13 @@ namespace {
 
 struct Group {
   int m = 0;
+  int lines = 8;                  // lines per tile (lines_for(m))
   std::vector<int> inst;          // instance ids, ascending
   std::vector<int> tile_inst;     // per tile
   std::vector<int> tile_loc;      // per tile: tile index inside its instance
-  int max_n = 0;                  // largest line length (pass 2 LDS sizing)
+  int max_n = 0;                  // largest line length
+  int tile = 0, nbuf = 1;         // LDS tile buffer (doubles) and buffer count
+  size_t lds = 0;                 // dynamic LDS of the launch
   size_t off_tile_inst = 0, off_tile_loc = 0;  // workspace offsets
 };
 
@@ -271,18 +262,62 @@ void build_groups(etd_rdp_batch* b, int axis, std::vector<Group>& out) {
   for (int i = 0; i < b->ninst; ++i) {
     const int64_t n = axis == 0 ? b->n1[i] : b->n2[i];
     const int64_t lines = axis == 0 ? b->n2[i] : b->n1[i];
-    Group& g = by_m[choose_chunk(n)];
-    g.m = choose_chunk(n);
+    const int m = choose_chunk(n);
+    Group& g = by_m[m];
+    g.m = m;
+    g.lines = lines_for(m);
     g.inst.push_back(i);
     g.max_n = std::max<int>(g.max_n, static_cast<int>(n));
-    const int64_t nt = (lines + kBlockLines - 1) / kBlockLines;
+    const int64_t nt = (lines + g.lines - 1) / g.lines;
     for (int64_t t = 0; t < nt; ++t) {
       g.tile_inst.push_back(i);
       g.tile_loc.push_back(static_cast<int>(t));
     }
   }
   out.clear();
-  for (auto& kv : by_m) out.push_back(kv.second);
+  const size_t fixed = lane_lds(3 * b->s);
+  for (auto& kv : by_m) {
+    Group& g = kv.second;
+    g.tile = g.lines * tile_pitch(g.max_n);
+    g.nbuf = tile_buffers(fixed, g.lines, g.tile);
+    g.lds = fixed + sizeof(double) * (size_t)g.nbuf * g.tile;
+    out.push_back(g);
+  }
+}
+
+// Pass geometry of one instance inside its group.
+PassGeom inst_geom(const etd_rdp_batch* b, int i, int axis, const Group& grp) {
+  const int64_t n1 = b->n1[i], n2 = b->n2[i];
+  PassGeom g{};
+  g.N = n1 * n2;
+  g.nT = 1;
+  g.inT = 0;
+  g.outT = 0;
+  if (axis == 0) {  // x-lines (f = y) of u -> [x][y]
+    g.nF = n2;
+    g.inF = n1;
+    g.outRow = n2;
+    g.n = static_cast<int>(n1);
+  } else {  // y-lines (f = x) of [x][y] -> u
+    g.nF = n1;
+    g.inF = n2;
+    g.outRow = n1;
+    g.n = static_cast<int>(n2);
+  }
+  g.C = g.n / grp.m;
+  g.pitch = tile_pitch(g.n);
+  g.lines = grp.lines;
+  g.tile = grp.tile;
+  g.nbuf = grp.nbuf;
+  g.nFblk = (g.nF + grp.lines - 1) / grp.lines;
+  return g;
+}
+
+const Group& group_of(const std::vector<Group>& gs, int64_t n) {
+  const int m = choose_chunk(n);
+  for (const Group& g : gs)
+    if (g.m == m) return g;
+  return gs.front();  // unreachable: every instance is in a group
 }
 
 // Static workspace image: tables, instance descriptors (device pointers into
@@ -296,9 +331,8 @@ void build_image(etd_rdp_batch* b, char* ws) {
   for (int i = 0; i < b->ninst; ++i) {
     BatchInst d{};
     d.off = b->offsets[i];
-    d.n1 = b->n1[i];
-    d.n2 = b->n2[i];
-    d.N = d.n1 * d.n2;
+    d.g1 = inst_geom(b, i, 0, group_of(b->g1, b->n1[i]));
+    d.g2 = inst_geom(b, i, 1, group_of(b->g2, b->n2[i]));
     d.tab1 = dev_tabs + (static_cast<size_t>(i) * 2 + 0) * 3 * S;
     d.tab2 = dev_tabs + (static_cast<size_t>(i) * 2 + 1) * 3 * S;
     d.rx.model = b->model;
@@ -316,14 +350,14 @@ void build_image(etd_rdp_batch* b, char* ws) {
 template <int M, int S>
 hipError_t launch_b1(const etd_rdp_batch* b, const Group& g, const double* u, char* ws,
                      hipStream_t st) {
-  const size_t lds = lane_lds(3 * S);
-  hipError_t e = set_lds(kb_first<M, S>, lds);
+  constexpr int L = kLinesFor<M>;
+  hipError_t e = set_lds(kb_first<M, S, L>, g.lds);
   if (e != hipSuccess) return e;
   unsigned grid;
   const int64_t nt = static_cast<int64_t>(g.tile_inst.size());
-  e = persistent_grid(kb_first<M, S>, lds, nt, &grid);
+  e = persistent_grid(kb_first<M, S, L>, g.lds, nt, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((kb_first<M, S>), dim3(grid), dim3(kBlock), lds, st, u,
+  hipLaunchKernelGGL((kb_first<M, S, L>), dim3(grid), dim3(64 * L), g.lds, st, u,
                      reinterpret_cast<double*>(ws + b->off_c1), reinterpret_cast<double*>(ws + b->off_c2),
                      reinterpret_cast<double*>(ws + b->off_w),
                      reinterpret_cast<const BatchInst*>(ws + b->off_insts),
@@ -335,24 +369,20 @@ hipError_t launch_b1(const etd_rdp_batch* b, const Group& g, const double* u, ch
 
 template <int M, int S>
 hipError_t launch_b2(const etd_rdp_batch* b, const Group& g, double* u, char* ws, hipStream_t st) {
-  const size_t fixed = lane_lds(3 * S);
-  const int pitch = g.max_n + ((8 - g.max_n % 32) + 32) % 32;
-  const int tile = kBlockLines * pitch;
-  const int nbuf = (fixed + 2 * sizeof(double) * (size_t)tile <= kLdsMax / 2) ? 2 : 1;
-  const size_t lds = fixed + sizeof(double) * (size_t)nbuf * tile;
-  hipError_t e = set_lds(kb_last<M, S>, lds);
+  constexpr int L = kLinesFor<M>;
+  hipError_t e = set_lds(kb_last<M, S, L>, g.lds);
   if (e != hipSuccess) return e;
   unsigned grid;
   const int64_t nt = static_cast<int64_t>(g.tile_inst.size());
-  e = persistent_grid(kb_last<M, S>, lds, nt, &grid);
+  e = persistent_grid(kb_last<M, S, L>, g.lds, nt, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((kb_last<M, S>), dim3(grid), dim3(kBlock), lds, st, u,
+  hipLaunchKernelGGL((kb_last<M, S, L>), dim3(grid), dim3(64 * L), g.lds, st, u,
                      reinterpret_cast<const double*>(ws + b->off_c1),
                      reinterpret_cast<const double*>(ws + b->off_c2),
                      reinterpret_cast<const double*>(ws + b->off_w),
                      reinterpret_cast<const BatchInst*>(ws + b->off_insts),
                      reinterpret_cast<const int*>(ws + g.off_tile_inst),
-                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, b->k, nbuf, tile,
+                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, b->k,
                      b->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }

@@ -402,6 +402,7 @@ struct TileAt {
   int64_t t, f0;
   __device__ __forceinline__ TileAt(int64_t tile, const PassGeom& g)
       : t(tile / g.nFblk), f0((tile % g.nFblk) * g.lines) {}
+  __device__ __forceinline__ TileAt(int64_t t_, int64_t f0_) : t(t_), f0(f0_) {}
 };
 
 // This wave's chunk of its line (f0 + wave, t) read directly; zeros for a

@@ -42,6 +42,30 @@ hipError_t persistent_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* g
   return hipSuccess;
 }
 
+// Lines per tile (= wavefronts per block) of the pass kernels: 16, so that a
+// transposed row is a whole 128-byte cache line, where the 128-register
+// budget of a 1024-thread block holds a chunk (m <= 4); 8 otherwise.
+constexpr int lines_for(int m) { return (m <= 4) ? 16 : 8; }
+template <int M>
+constexpr int kLinesFor = lines_for(M);
+
+// Waves per SIMD the pass kernels ask the compiler to fit (register budget):
+// four while a chunk's rows leave room.
+template <int M>
+constexpr int kMinWaves = (M <= 4) ? 4 : 2;
+
+// LDS pitch of a line of n rows in a tile buffer: n rounded up to 8 (mod 32)
+// doubles, so that the transposes are bank-conflict free.
+inline int tile_pitch(int n) { return n + ((8 - n % 32) + 32) % 32; }
+
+// Tile buffers: two (one barrier per move) when they fit beside the fixed
+// LDS: in half the LDS for 8-line blocks (two blocks per CU), in all of it
+// for 16-line blocks (their register budget allows one block per CU).
+inline int tile_buffers(size_t fixed_lds, int lines, int tile_doubles) {
+  const size_t cap = (lines >= 16) ? kLdsMax : kLdsMax / 2;
+  return (fixed_lds + 2 * sizeof(double) * (size_t)tile_doubles <= cap) ? 2 : 1;
+}
+
 // Runtime (m, s) -> template dispatch.
 #define ETD_DISPATCH_M(m, CALL) \
   switch (m) {                  \

@@ -43,17 +43,6 @@ namespace etd {
 // fastest dimension, so every transposed row write is a run of adjacent
 // doubles.
 
-// Waves per SIMD the pass kernels ask the compiler to fit (register budget):
-// four while a chunk's rows leave room.
-template <int M>
-constexpr int kMinWaves = (M <= 4) ? 4 : 2;
-
-// Lines per tile (= wavefronts per block) of the pass kernels: 16, so that a
-// transposed row is a whole 128-byte cache line, where the 128-register
-// budget of a 1024-thread block holds a chunk; 8 otherwise.
-template <int M>
-constexpr int kLinesFor = (M <= 4) ? 16 : 8;
-
 // ---------------------------------------------------------------------------
 // Pass 1 (axis 1).  Tiles of 8 x-lines with adjacent y; the next tile's U is
 // fetched into registers while the current tile is solved.
@@ -497,14 +486,10 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines) 
   }
   g.n = static_cast<int>(c->n[axis0]);
   g.C = g.n / c->m[axis0];
-  g.pitch = g.n + ((8 - g.n % 32) + 32) % 32;  // = 8 (mod 32), see tile_store
+  g.pitch = tile_pitch(g.n);
   g.lines = lines;
   g.tile = lines * g.pitch;
-  // Two tile buffers (one barrier per move) when they fit beside the tables:
-  // in half the LDS for 8-line blocks (two blocks per CU), in all of it for
-  // 16-line blocks (their register budget allows one block per CU).
-  const size_t lds_cap = (lines >= 16) ? kLdsMax : kLdsMax / 2;
-  g.nbuf = (fixed_lds + 2 * sizeof(double) * (size_t)g.tile <= lds_cap) ? 2 : 1;
+  g.nbuf = tile_buffers(fixed_lds, lines, g.tile);
   g.nFblk = (g.nF + lines - 1) / lines;
   return g;
 }
