@@ -202,6 +202,217 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
 }
 
 // ---------------------------------------------------------------------------
+// Middle pass, streamed: the same work as k_mid in phases of one input array
+// each (T and S on c1, T and S on c2, P on w), so that only one input and its
+// two solves are in registers; the next phase's input is fetched while the
+// current one is solved.  Fewer registers per wave than k_mid, for long
+// chunks.
+// ---------------------------------------------------------------------------
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, 4) void k_mid_s(
+    const double* __restrict__ c1, const double* __restrict__ c2,
+    const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
+    double* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63;
+  const int first_phase = etd1 ? 2 : 0;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  bool have = walk.next(tile);
+  int s = 0, ph = first_phase;
+  double pf[M];
+  auto src = [&](int ph_) { return ph_ == 0 ? c1 : (ph_ == 1 ? c2 : w); };
+  auto fetch = [&](int64_t tl_, int s_, int ph_) {
+    line_load<M>(src(ph_) + s_ * g.N, pf, g, TileAt(tl_, g));
+  };
+  if (have) fetch(tile, 0, ph);
+  while (have) {
+    const TileAt pos(tile, g);
+    const int sc = s, pc = ph;
+    double x[2][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[0][j] = pf[j];
+      x[1][j] = pf[j];
+    }
+    if (++ph == 3) {
+      ph = first_phase;
+      if (++s == S) {
+        s = 0;
+        have = walk.next(tile);
+      }
+    }
+    if (have) fetch(tile, s, ph);
+    if (pc == 2) {
+      double y[1][M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) y[0][j] = x[0][j];
+      const SolveTab* tb[1] = {at.P(sc)};
+      const LaneTab* lb[1] = {at.lP(sc)};
+      line_solve<M, 1>(tb, lb, y, lane);
+      tile_store<M, L>(ow + sc * g.N, y[0], tl, g, pos, cur);
+    } else {
+      const SolveTab* tb[2] = {at.T(sc), at.Sx(sc)};
+      const LaneTab* lb[2] = {at.lT(sc), at.lS(sc)};
+      line_solve<M, 2>(tb, lb, x, lane);
+#pragma unroll
+      for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
+      tile_store<M, L>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1, streamed: the work of k_first in phases of at most two solves per
+// species (T and S on U, T and S on f, P on U + k f), so that a 16-line tile
+// of long chunks fits the register budget.  Only U is kept; a species' f is
+// re-evaluated (pointwise) where a phase needs it.  Lines are read when a
+// tile starts.
+// ---------------------------------------------------------------------------
+template <int S, int M>
+__device__ __forceinline__ void react_species(const Rx& rx, const double (&U)[S][M], int s,
+                                              double (&f)[M]) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double uu[S], ff[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) uu[q] = U[q][j];
+    react<S>(rx, uu, ff);
+    f[j] = ff[s];
+  }
+}
+
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, 4) void k_first_s(
+    const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
+    double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
+    int etd1) {
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const TileAt pos(tile, g);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      // The tile's lines of every species (the later species' reads hit L2).
+      double U[S][M], f[M];
+#pragma unroll
+      for (int q = 0; q < S; ++q) line_load<M>(u + q * g.N, U[q], g, pos);
+      react_species<S, M>(rx, U, s, f);
+      double y[1][M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], U[s][j]);
+      {
+        const SolveTab* tb[1] = {at.P(s)};
+        const LaneTab* lb[1] = {at.lP(s)};
+        line_solve<M, 1>(tb, lb, y, lane);
+        tile_store<M, L>(w + s * g.N, y[0], tl, g, pos, cur);
+      }
+      if (etd1) continue;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {  // R_1 f, then R_1 U
+        double x[2][M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          x[0][j] = (r == 0) ? f[j] : U[s][j];
+          x[1][j] = x[0][j];
+        }
+        const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
+        const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
+        line_solve<M, 2>(tb, lb, x, lane);
+#pragma unroll
+        for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
+        tile_store<M, L>((r == 0 ? c2 : c1) + s * g.N, x[0], tl, g, pos, cur);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Last pass, streamed: the work of k_last with the corrector inputs read per
+// species when they are used and no cross-tile prefetch, so that a 16-line
+// tile of long chunks fits the register budget.
+// ---------------------------------------------------------------------------
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, 4) void k_last_s(
+    double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
+    const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
+    PassGeom g, int etd1) {
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63;
+  const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const TileAt pos(tile, g);
+    double us[S][M];
+#pragma unroll
+    for (int s = 0; s < S; ++s) line_load<M>(w + s * g.N, us[s], g, pos);
+    {
+      const SolveTab* tb[S];
+      const LaneTab* lb[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        tb[s] = at.P(s);
+        lb[s] = at.lP(s);
+      }
+      line_solve<M, S>(tb, lb, us, lane);
+    }
+    if (etd1) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) tile_store<M, L>(u + s * g.N, us[s], tl, g, pos, cur);
+      continue;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double uu[S], ff[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) uu[s] = us[s][j];
+      react<S>(rx, uu, ff);
+#pragma unroll
+      for (int s = 0; s < S; ++s) us[s][j] = ff[s];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double x[2][M], b[M];
+      line_load<M>(c1 + s * g.N, x[0], g, pos);
+      line_load<M>(c2 + s * g.N, b, g, pos);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const double a = x[0][j];
+        x[0][j] = fma(k, us[s][j], fma(k2, b[j], 9.0 * a));
+        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], 8.0 * a));
+      }
+      const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
+      const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
+      line_solve<M, 2>(tb, lb, x, lane);
+#pragma unroll
+      for (int j = 0; j < M; ++j) x[0][j] = x[0][j] - x[1][j];
+      tile_store<M, L>(u + s * g.N, x[0], tl, g, pos, cur);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Last pass (axis d): predictor solve, f*, corrector solves, new state.
 // Tiles of 8 lines with adjacent x.  Per tile the loads come in groups (w of
 // all species; then c1, c2 of each species); each group is fetched into
@@ -500,10 +711,54 @@ size_t pass_lds(const PassGeom& g, size_t fixed_lds) {
 
 namespace {
 
+// Chunk lengths from which the passes run streamed (k_first_s, k_mid_s,
+// k_last_s), and the lines per tile those use.
+constexpr int kStreamFirstFrom = 8;
+constexpr int kStreamMidFrom = 5;
+constexpr int kStreamLastFrom = 5;
+constexpr int kStreamLines = 16;
+
 // Launchers, templated on the chunk length and species count.
+template <int M, int S>
+hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
+                          double* w, const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds(3 * S);
+  constexpr int L = kStreamLines;
+  const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_first_s<M, S, L>, lds);
+  if (e != hipSuccess) return e;
+  unsigned grid;
+  e = persistent_grid(k_first_s<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_first_s<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M, int S>
+hipError_t launch_last_s(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
+                         const double* w, const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds(3 * S);
+  constexpr int L = kStreamLines;
+  const PassGeom g = pass_geom(c, kPassLast, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_last_s<M, S, L>, lds);
+  if (e != hipSuccess) return e;
+  unsigned grid;
+  e = persistent_grid(k_last_s<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_last_s<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
 template <int M, int S>
 hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                         double* w, const SolveTab* tabs, hipStream_t st) {
+  if constexpr (M >= kStreamFirstFrom) {
+    return launch_first_s<M, S>(c, u, c1, c2, w, tabs, st);
+  }
   const size_t fixed = lane_lds(3 * S);
   constexpr int L = kLinesFor<M>;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
@@ -519,9 +774,30 @@ hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, doubl
 }
 
 template <int M, int S>
+hipError_t launch_mid_s(const etd_rdp_ctx* c, const double* c1, const double* c2,
+                        const double* w, double* o1, double* o2, double* ow,
+                        const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds(3 * S);
+  constexpr int L = kStreamLines;
+  const PassGeom g = pass_geom(c, kPassMid, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_mid_s<M, S, L>, lds);
+  if (e != hipSuccess) return e;
+  unsigned grid;
+  e = persistent_grid(k_mid_s<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mid_s<M, S, L>), dim3(grid), dim3(64 * L), lds, st, c1, c2, w, o1, o2,
+                     ow, tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M, int S>
 hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
                       const double* w, double* o1, double* o2, double* ow,
                       const SolveTab* tabs, hipStream_t st) {
+  if constexpr (M >= kStreamMidFrom) {
+    return launch_mid_s<M, S>(c, c1, c2, w, o1, o2, ow, tabs, st);
+  }
   const size_t fixed = lane_lds(3 * S);
   constexpr int L = kLinesFor<M>;
   const PassGeom g = pass_geom(c, kPassMid, fixed, L);
@@ -539,6 +815,9 @@ hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
 template <int M, int S>
 hipError_t launch_last(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
                        const double* w, const SolveTab* tabs, hipStream_t st) {
+  if constexpr (M >= kStreamLastFrom) {
+    return launch_last_s<M, S>(c, u, c1, c2, w, tabs, st);
+  }
   const size_t fixed = lane_lds(3 * S);
   constexpr int L = kLinesFor<M>;
   const PassGeom g = pass_geom(c, kPassLast, fixed, L);
