@@ -42,15 +42,8 @@ def pass_words(d: int):
 
 
 def pass_names(e, d: int):
-    """Kernel names (as rocprofv3 prints them, shortened) of each pass: the
-    chunk length m, the species count and the lines per tile (16 when
-    m <= 4, else 8)."""
-    names = []
-    for p in range(1, d + 1):
-        m, _ = e.line_split(p)
-        kind = "k_first" if p == 1 else ("k_last" if p == d else "k_mid")
-        names.append(f"{kind}<{m}, {e.s}, {16 if m <= 4 else 8}>")
-    return names
+    """Kernel names (as rocprofv3 prints them, shortened) of each pass."""
+    return [e.pass_kernel(p) for p in range(1, d + 1)]
 
 
 def cpu_baseline(name: str, budget_s: float = 12.0):

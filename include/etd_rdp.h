@@ -206,6 +206,13 @@ const char* etd_rdp_status_string(int status);
 /* Last HIP error code seen by ctx (0 if none). */
 int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx);
 
+/* Name of the kernel pass `pass` (1..d) launches, as profilers print it
+ * without the namespace and arguments (for example "k_mid<4, 2, 16>"),
+ * written NUL-terminated into name[0..size).  For reports.  Errors:
+ * ETD_ERR_ARG (NULL, pass out of range, buffer too small). */
+int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name,
+                        size_t size);
+
 /* Chunk length m and chunk count C = n/m the line solver uses on an axis
  * (1-based); for tests and tuning. */
 int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m,

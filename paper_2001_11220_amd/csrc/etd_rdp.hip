@@ -1085,4 +1085,17 @@ int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, 
 
 int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
 
+int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t size) {
+  if (!ctx || !name || size == 0 || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
+  const int p = pass - 1, m = ctx->m[p];
+  const bool first = (p == 0), last = (p == ctx->d - 1);
+  const bool streamed = first ? (m >= kStreamFirstFrom)
+                              : (last ? (m >= kStreamLastFrom) : (m >= kStreamMidFrom));
+  const char* base = first ? "k_first" : (last ? "k_last" : "k_mid");
+  const int lines = streamed ? kStreamLines : lines_for(m);
+  const int n = std::snprintf(name, size, "%s%s<%d, %d, %d>", base, streamed ? "_s" : "", m,
+                              ctx->s, lines);
+  return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
+}
+
 }  // extern "C"

@@ -79,6 +79,7 @@ def _load():
         "etd_rdp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "etd_rdp_last_hip_error": (ctypes.c_int, [P]),
         "etd_rdp_line_split": (ctypes.c_int, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "etd_rdp_pass_kernel": (ctypes.c_int, [P, I32, ctypes.c_char_p, SZ]),
         "etd_rdp_grad_size": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
         "etd_rdp_adjoint_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
         "etd_rdp_adjoint": (ctypes.c_int, [P, P, P, P, P, P, SZ, P]),
@@ -230,6 +231,12 @@ class EtdRdp:
             flat = ws[base + off: base + off + 8 * N * self.s].view(torch.float64)
             out.append(flat.as_strided((self.s,) + self.shape[::-1], (N,) + strides[::-1]))
         return tuple(out)
+
+    def pass_kernel(self, npass):
+        """Name of the kernel pass ``npass`` launches (as profilers print it)."""
+        buf = ctypes.create_string_buffer(64)
+        _check(lib.etd_rdp_pass_kernel(self._ctx, int(npass), buf, 64), "etd_rdp_pass_kernel")
+        return buf.value.decode()
 
     def line_split(self, axis):
         m, c = ctypes.c_int32(), ctypes.c_int32()
