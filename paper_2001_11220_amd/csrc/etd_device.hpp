@@ -114,6 +114,27 @@ __device__ __forceinline__ void halves_swap(double v, double& up, double& dn) {
   dn = __hiloint2double(hi[1], lo[1]);
 }
 
+// Values of v from lane-16 (up) and lane+16 (dn) on the lanes that have
+// them, on the vector ALU: v_permlane16_swap gives rows (0,0,2,2) and
+// (1,1,3,3) of the four 16-lane rows; a permlane32 swap of those supplies
+// row 1 for row 2 (up) and row 2 for row 1 (dn).  Lanes without a neighbour
+// at distance 16 get some other lane's value.
+__device__ __forceinline__ unsigned shift16_half(unsigned x, bool row1, bool row2, unsigned& dn) {
+  const auto q = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // (0,0,2,2), (1,1,3,3)
+  const auto a = __builtin_amdgcn_permlane32_swap(q[1], q[1], false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(q[0], q[0], false, false);
+  dn = row1 ? b[1] : q[1];
+  return row2 ? a[0] : q[0];
+}
+__device__ __forceinline__ void quarters_shift(double v, bool row1, bool row2, double& up,
+                                               double& dn) {
+  unsigned dlo, dhi;
+  const unsigned ulo = shift16_half(static_cast<unsigned>(__double2loint(v)), row1, row2, dlo);
+  const unsigned uhi = shift16_half(static_cast<unsigned>(__double2hiint(v)), row1, row2, dhi);
+  up = __hiloint2double(static_cast<int>(uhi), static_cast<int>(ulo));
+  dn = __hiloint2double(static_cast<int>(dhi), static_cast<int>(dlo));
+}
+
 // Exact line solves on a wavefront.
 //
 // A block holds kBlockLines lines, one per wavefront; lane c of a wavefront
@@ -211,8 +232,8 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   }
   // 3. Parallel cyclic reduction across the lanes.  Lanes with no neighbour
   // at distance sh have a zero multiplier; what they read there does not
-  // matter.  Distance 1 uses DPP shifts, distance 32 a permlane32 swap, the
-  // others ds_bpermute.
+  // matter.  Distance 1 uses DPP shifts, distances 16 and 32 permlane
+  // swaps, the others ds_bpermute.
   if (npcr > 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -222,7 +243,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
     }
   }
 #pragma unroll
-  for (int st = 1; st < kMaxPcr - 1; ++st) {
+  for (int st = 1; st < kMaxPcr - 2; ++st) {
     if (st < npcr) {
       const int a_up = (lane4 - (4 << st)) & 255;
       const int a_dn = (lane4 + (4 << st)) & 255;
@@ -232,6 +253,15 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
         const double dp = bperm(a_dn, d[k]);
         d[k] = d[k] - lt[k]->k1[st][lane] * dm - lt[k]->k2[st][lane] * dp;
       }
+    }
+  }
+  if (npcr > kMaxPcr - 2) {
+    const bool row1 = (lane >> 4) == 1, row2 = (lane >> 4) == 2;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double dm, dp;
+      quarters_shift(d[k], row1, row2, dm, dp);
+      d[k] = d[k] - lt[k]->k1[kMaxPcr - 2][lane] * dm - lt[k]->k2[kMaxPcr - 2][lane] * dp;
     }
   }
   if (npcr > kMaxPcr - 1) {
