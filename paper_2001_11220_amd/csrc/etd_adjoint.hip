@@ -24,7 +24,8 @@
 //
 // Kernels (one wavefront per line, as in the forward passes):
 //   ka_last   axis d: recompute U*, f*, f1, f2; 6 solves per species
-//   ka_mid    axis 2 of 3-D: 10 solves per species
+//   ka_mid    axis 2 of 3-D: 10 solves per species (ka_mid_s: the same in
+//             phases of two solves, for short chunks)
 //   ka_first  axis 1: recompute f, U + k f; 10 solves per species; lam_n
 // The forward carried triples the reverse passes need come from a forward
 // recompute (k_first, and k_mid in 3-D); the reverse passes read them line
@@ -45,6 +46,7 @@
 namespace etd {
 
 constexpr int kRed = kBlockLines * kGradSlots;  // LDS doubles for block sums
+constexpr int kRedMax = 16 * kGradSlots;        // ... for blocks of up to 16 waves
 
 // Neumann transposes: scale the line's first and last rows by f.
 template <int M>
@@ -148,6 +150,7 @@ __device__ __forceinline__ void react_adj(const Rx& rx, const double (&uin)[S],
 
 // Block sum of acc[] (fixed order) into part[blockIdx.x][*].  All threads of
 // the block call it once, at the end of the kernel.
+template <int W>
 __device__ __forceinline__ void block_partials(const double (&acc)[kGradSlots], double* red,
                                                double* __restrict__ part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -161,17 +164,17 @@ __device__ __forceinline__ void block_partials(const double (&acc)[kGradSlots], 
   __syncthreads();
   if (threadIdx.x < kGradSlots) {
     double t = 0.0;
-    for (int w = 0; w < kBlockLines; ++w) t += red[w * kGradSlots + threadIdx.x];
+    for (int w = 0; w < W; ++w) t += red[w * kGradSlots + threadIdx.x];
     part[(int64_t)blockIdx.x * kGradSlots + threadIdx.x] = t;
   }
 }
 
-template <int M>
+template <int M, int L>
 __device__ __forceinline__ void tile_load(const double* __restrict__ A, double (&x)[M], double* tl,
                                           const PassGeom& g, const TileAt& p, TileCursor& cur) {
   double r[M];
-  tile_fetch<M>(A, r, g, p);
-  tile_commit<M>(r, x, tl, g, cur);
+  tile_fetch<M, L>(A, r, g, p);
+  tile_commit<M, L>(r, x, tl, g, cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void ka_last(
       double x[4][M], cb[M];
       line_load<M>(c1 + s * g.N, x[0], g, pos);
       line_load<M>(c2 + s * g.N, cb, g, pos);
-      tile_load<M>(lam + s * g.N, x[2], tl, g, pos, cur);
+      tile_load<M, kBlockLines>(lam + s * g.N, x[2], tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const double ca = x[0][j];
@@ -258,10 +261,10 @@ __global__ __launch_bounds__(kBlock) void ka_last(
       double o[M];
 #pragma unroll
       for (int j = 0; j < M; ++j) o[j] = fma(9.0, x[2][j], -8.0 * x[3][j]);
-      tile_store<M>(y1 + s * g.N, o, tl, g, pos, cur);
+      tile_store<M, kBlockLines>(y1 + s * g.N, o, tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) o[j] = fma(k2, x[2][j], -k15 * x[3][j]);
-      tile_store<M>(y2 + s * g.N, o, tl, g, pos, cur);
+      tile_store<M, kBlockLines>(y2 + s * g.N, o, tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) fb[s][j] = fma(k, x[2][j], -k05 * x[3][j]);  // f*bar
     }
@@ -295,10 +298,10 @@ __global__ __launch_bounds__(kBlock) void ka_last(
     for (int s = 0; s < S; ++s) {
       if (neu) ends_scale<M>(fb[s], lane, C, 0.5);
       acc[s] += dsc * lap_dot<M>(fb[s], us[s], lane, C, bc);
-      tile_store<M>(yw + s * g.N, fb[s], tl, g, pos, cur);
+      tile_store<M, kBlockLines>(yw + s * g.N, fb[s], tl, g, pos, cur);
     }
   }
-  block_partials(acc, red, part);
+  block_partials<kBlockLines>(acc, red, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void ka_mid(
       for (int r = 0; r < 2; ++r) {  // R_2 U-chain, then f-chain
         double x[4][M];
         line_load<M>(fw[r], x[0], g, pos);
-        tile_load<M>(bk[r], x[2], tl, g, pos, cur);
+        tile_load<M, kBlockLines>(bk[r], x[2], tl, g, pos, cur);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
           x[1][j] = x[0][j];
@@ -360,21 +363,100 @@ __global__ __launch_bounds__(kBlock) void ka_mid(
         double o[M];
 #pragma unroll
         for (int j = 0; j < M; ++j) o[j] = fma(9.0, x[2][j], -8.0 * x[3][j]);
-        tile_store<M>(bk[r], o, tl, g, pos, cur);
+        tile_store<M, kBlockLines>(bk[r], o, tl, g, pos, cur);
       }
       double y[2][M];
       line_load<M>(w + s * g.N, y[0], g, pos);
-      tile_load<M>(yw + s * g.N, y[1], tl, g, pos, cur);
+      tile_load<M, kBlockLines>(yw + s * g.N, y[1], tl, g, pos, cur);
       if (neu) ends_scale<M>(y[1], lane, C, 2.0);
       const SolveTab* tb[2] = {at.P(s), at.P(s)};
       const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
       line_solve<M, 2>(tb, lb, y, lane);
       if (neu) ends_scale<M>(y[1], lane, C, 0.5);
       acc[s] += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
-      tile_store<M>(yw + s * g.N, y[1], tl, g, pos, cur);
+      tile_store<M, kBlockLines>(yw + s * g.N, y[1], tl, g, pos, cur);
     }
   }
-  block_partials(acc, red, part);
+  block_partials<kBlockLines>(acc, red, part);
+}
+
+// ---------------------------------------------------------------------------
+// Axis 2, streamed: the work of ka_mid in phases of two solves (a forward
+// solve and the transposed solve of the same matrix), one species per work
+// item, so that 16-line tiles fit the register budget.
+// ---------------------------------------------------------------------------
+template <int M, int S, int L>
+__global__ __launch_bounds__(64 * L, 4) void ka_mid_s(
+    const double* __restrict__ c1, const double* __restrict__ c2, const double* __restrict__ w,
+    double* __restrict__ y1, double* __restrict__ y2, double* __restrict__ yw,
+    const SolveTab* __restrict__ tabs, PassGeom g, int bc, double dsc, double* __restrict__ part) {
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  double* tl = red + kRedMax;
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63;
+  const int C = g.C;
+  const bool neu = (bc == ETD_BC_NEUMANN);
+  double acc[kGradSlots];
+#pragma unroll
+  for (int q = 0; q < kGradSlots; ++q) acc[q] = 0.0;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT * S);
+  int64_t item;
+  while (walk.next(item)) {
+    const int s = static_cast<int>(item % S);
+    const TileAt pos(item / S, g);
+    double da = 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {  // R_2 U-chain, then f-chain
+      const double* fw = (r == 0 ? c1 : c2) + s * g.N;
+      double* bk = (r == 0 ? y1 : y2) + s * g.N;
+      double cin[M], yin[M], a[M];
+      line_load<M>(fw, cin, g, pos);
+      tile_load<M, L>(bk, yin, tl, g, pos, cur);
+      if (neu) ends_scale<M>(yin, lane, C, 2.0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {  // T (gamma 3), then S (gamma 4)
+        double x[2][M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          x[0][j] = cin[j];
+          x[1][j] = yin[j];
+        }
+        const SolveTab* tb[2] = {h == 0 ? at.T(s) : at.Sx(s), h == 0 ? at.T(s) : at.Sx(s)};
+        const LaneTab* lb[2] = {h == 0 ? at.lT(s) : at.lS(s), h == 0 ? at.lT(s) : at.lS(s)};
+        line_solve<M, 2>(tb, lb, x, lane);
+        if (neu) ends_scale<M>(x[1], lane, C, 0.5);
+        const double dot = lap_dot<M>(x[1], x[0], lane, C, bc);
+        if (h == 0) {
+          da += (3.0 * dsc) * dot;
+#pragma unroll
+          for (int j = 0; j < M; ++j) a[j] = x[1][j];
+        } else {
+          da -= (2.0 * dsc) * dot;
+#pragma unroll
+          for (int j = 0; j < M; ++j) a[j] = fma(9.0, a[j], -8.0 * x[1][j]);
+        }
+      }
+      tile_store<M, L>(bk, a, tl, g, pos, cur);
+    }
+    double y[2][M];
+    line_load<M>(w + s * g.N, y[0], g, pos);
+    tile_load<M, L>(yw + s * g.N, y[1], tl, g, pos, cur);
+    if (neu) ends_scale<M>(y[1], lane, C, 2.0);
+    const SolveTab* tb[2] = {at.P(s), at.P(s)};
+    const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
+    line_solve<M, 2>(tb, lb, y, lane);
+    if (neu) ends_scale<M>(y[1], lane, C, 0.5);
+    da += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
+    tile_store<M, L>(yw + s * g.N, y[1], tl, g, pos, cur);
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc[q] += (q == s) ? da : 0.0;
+  }
+  block_partials<L>(acc, red, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void ka_first(
       for (int s = 0; s < S; ++s) store_chunk<M>(lam_out + s * N + off, Ub[s]);
     }
   }
-  block_partials(acc, red, part);
+  block_partials<kBlockLines>(acc, red, part);
 }
 
 // grad[q] += sum over passes p < npass and blocks b < nblk[p] of
@@ -521,16 +603,39 @@ namespace {
 inline size_t adj_fixed_lds(int S) { return lane_lds(3 * S) + sizeof(double) * kRed; }
 
 template <typename KernelT>
-hipError_t adj_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid) {
+hipError_t adj_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid,
+                    int threads = kBlock) {
   hipError_t e = set_lds(kern, lds);
   if (e != hipSuccess) return e;
-  e = persistent_grid(kern, lds, ntiles, grid);
+  e = persistent_grid(kern, lds, ntiles, grid, threads);
   if (e != hipSuccess) return e;
   if (*grid > static_cast<unsigned>(kAdjMaxBlocks)) *grid = kAdjMaxBlocks;
   return hipSuccess;
 }
 
 double d_scale(const etd_rdp_ctx* c, int axis0) { return -c->k / (c->h[axis0] * c->h[axis0]); }
+
+// Chunk lengths up to which the axis-2 reverse pass runs streamed (ka_mid_s,
+// 16-line tiles); longer chunks keep ka_mid.  (Streamed forms of the other
+// two reverse passes spill at 128 registers and measured slower.)
+constexpr int kAdjStreamMidTo = 2;
+constexpr int kAdjStreamLines = 16;
+inline size_t adj_fixed_lds_s(int S) { return lane_lds(3 * S) + sizeof(double) * kRedMax; }
+
+template <int M, int S>
+hipError_t launch_ka_mid_s(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&Y)[3],
+                           const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
+  constexpr int L = kAdjStreamLines;
+  const int a = 1;
+  const size_t fixed = adj_fixed_lds_s(S);
+  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = adj_grid(ka_mid_s<M, S, L>, lds, g.nFblk * g.nT * S, nblk, 64 * L);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((ka_mid_s<M, S, L>), dim3(*nblk), dim3(64 * L), lds, st, A[0], A[1], A[2],
+                     Y[0], Y[1], Y[2], tabs, g, c->bc[a], d_scale(c, a), part);
+  return hipGetLastError();
+}
 
 template <int M, int S>
 hipError_t launch_ka_last(const etd_rdp_ctx* c, double* const (&X)[3], const double* lam,
@@ -550,6 +655,7 @@ hipError_t launch_ka_last(const etd_rdp_ctx* c, double* const (&X)[3], const dou
 template <int M, int S>
 hipError_t launch_ka_mid(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&Y)[3],
                          const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
+  if constexpr (M <= kAdjStreamMidTo) return launch_ka_mid_s<M, S>(c, A, Y, tabs, part, nblk, st);
   const int a = 1;
   const size_t fixed = adj_fixed_lds(S);
   const PassGeom g = pass_geom(c, kPassAdjMid, fixed, kBlockLines);
@@ -565,6 +671,7 @@ template <int M, int S>
 hipError_t launch_ka_first(const etd_rdp_ctx* c, const double* u, double* const (&A)[3],
                            double* lam_out, const SolveTab* tabs, double* part, unsigned* nblk,
                            hipStream_t st) {
+
   const int64_t nlines = c->N / c->n[0];
   const size_t lds = adj_fixed_lds(S);
   hipError_t e = adj_grid(ka_first<M, S>, lds, (nlines + kBlockLines - 1) / kBlockLines, nblk);

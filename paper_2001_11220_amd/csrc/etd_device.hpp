@@ -450,7 +450,7 @@ __device__ __forceinline__ void line_load(const double* __restrict__ A, double (
 // Transposed read, split for software pipelining as tile_fetch/tile_commit
 // above: thread (col, q) fetches rows q*M+i of column f0+col.  L is the
 // number of lines per tile (g.lines); the block has 64*L threads.
-template <int M, int L = kBlockLines>
+template <int M, int L>
 __device__ __forceinline__ void tile_fetch(const double* __restrict__ A, double (&r)[M],
                                            const PassGeom& g, const TileAt& p) {
   const int tid = threadIdx.x;
@@ -465,7 +465,7 @@ __device__ __forceinline__ void tile_fetch(const double* __restrict__ A, double 
   }
 }
 
-template <int M, int L = kBlockLines>
+template <int M, int L>
 __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M], double* lds,
                                             const PassGeom& g, TileCursor& cur) {
   const int tid = threadIdx.x;
@@ -484,7 +484,7 @@ __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M]
 }
 
 // Transposed write of every wave's line chunk (all threads call it).
-template <int M, int L = kBlockLines>
+template <int M, int L>
 __device__ __forceinline__ void tile_store(double* __restrict__ A, const double (&x)[M],
                                            double* lds, const PassGeom& g, const TileAt& p,
                                            TileCursor& cur) {
