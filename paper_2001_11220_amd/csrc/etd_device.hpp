@@ -93,15 +93,17 @@ __device__ __forceinline__ double bperm(int addr, double v) {
 }
 
 // Value of v from lane-1 (0 on lane 0) and from lane+1 (0 on lane 63):
-// DPP wavefront shifts, on the vector ALU instead of the LDS pipe.
+// DPP wavefront shifts, on the vector ALU instead of the LDS pipe.  The
+// bound-control bit makes the lane without a source read zero, so no
+// register has to be cleared first.
 __device__ __forceinline__ double from_prev(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_next(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -135,6 +137,17 @@ __device__ __forceinline__ void quarters_shift(double v, bool row1, bool row2, d
   dn = __hiloint2double(static_cast<int>(dhi), static_cast<int>(dlo));
 }
 
+// A zero the optimiser cannot see through (an empty asm statement, no
+// instruction).  Offsetting the table pointers by it keeps their header loads
+// where they are used: the headers are the same for every line, so without it
+// the compiler hoists all of them out of the tile loop and holds them in
+// scalar registers for the whole kernel, which spills.
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
 // Exact line solves on a wavefront.
 //
 // A block holds kBlockLines lines, one per wavefront; lane c of a wavefront
@@ -162,37 +175,26 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
                                            const LaneTab* const (&lt)[K],
                                            double (&x)[K][M], int lane) {
   constexpr int Q = M - 1;
-  // Uniform table fields, fetched before any cross-lane traffic.
+  // Uniform table fields: the interior factors here, the correction factors
+  // after the reduction, so that only one group is held in scalar registers
+  // at a time.  The reduced-RHS weights, which differ on the first and last
+  // lane, are per-lane LDS data.
   struct Hdr {
-    double ip[Q > 0 ? Q : 1], cp[Q > 0 ? Q : 1], al[Q > 0 ? Q : 1], be[Q > 0 ? Q : 1];
-    double r, wlg, wll, wrg, wrl, wg0, gh0, ghw, ghd, vfac, smfac;
-    int sm;
+    double ip[Q > 0 ? Q : 1], cp[Q > 0 ? Q : 1], r;
   } h[K];
+  const int z0 = opaque_zero();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const SolveTab* t = tab[k];
+    const SolveTab* t = tab[k] + z0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       h[k].ip[j] = t->ip[j];
       h[k].cp[j] = t->cp[j];
-      h[k].al[j] = t->al[j];
-      h[k].be[j] = t->be[j];
     }
     h[k].r = t->r;
-    h[k].wlg = t->wl_gen;
-    h[k].wll = t->wl_last;
-    h[k].wrg = t->wr_gen;
-    h[k].wrl = t->wr_last;
-    h[k].wg0 = t->wg0;
-    h[k].gh0 = t->gh0;
-    h[k].ghw = t->ghw;
-    h[k].ghd = t->ghd;
-    h[k].vfac = t->vfac;
-    h[k].smfac = t->smfac;
-    h[k].sm = t->sm;
   }
-  const int C = tab[0]->C;
-  const int npcr = tab[0]->npcr;
+  const int C = (tab[0] + z0)->C;
+  const int npcr = (tab[0] + z0)->npcr;
   // 1. Thomas on the chunk interior (factors shared by every chunk).
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -210,24 +212,18 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   }
   // 2. Right-hand side of the reduced separator system.  The last chunk's
   // right neighbour is row 0 (it only matters for the periodic closure).
-  const bool last = (lane + 1 == C);
   const int lane4 = lane * 4;
-  const int a_next = last ? 0 : lane4 + 4;
+  const int a_next = (lane + 1 == C) ? 0 : lane4 + 4;
   double d[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double v = x[k][M - 1];
     if constexpr (Q > 0) {
       const double gn = bperm(a_next, x[k][0]);
-      const double wl = last ? h[k].wll : h[k].wlg;
-      const double wr = last ? h[k].wrl : h[k].wrg;
-      v = fma(wl, x[k][Q - 1], v);
-      v = fma(wr, gn, v);
+      v = fma(lt[k]->wl[lane], x[k][Q - 1], v);
+      v = fma(lt[k]->wr[lane], gn, v);
     }
-    if constexpr (Q > 1) {
-      const double wg = (lane == 0) ? h[k].wg0 : 0.0;
-      v = fma(wg, x[k][1], v);
-    }
+    if constexpr (Q > 1) v = fma(lt[k]->wg[lane], x[k][1], v);
     d[k] = v;
   }
   // 3. Parallel cyclic reduction across the lanes.  Lanes with no neighbour
@@ -272,21 +268,26 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       d[k] = d[k] - lt[k]->k1[kMaxPcr - 1][lane] * dm - lt[k]->k2[kMaxPcr - 1][lane] * dp;
     }
   }
-  // 4. Separators, cyclic fix, and back to the chunk.
+  // 4. Separators, cyclic fix, and back to the chunk.  The left separator
+  // of chunk c is s_{c-1}; for chunk 0 it is the boundary ghost.
+  const int z1 = opaque_zero();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
+    const SolveTab* t = tab[k] + z1;
     double s = d[k] * lt[k]->inv[lane];
-    if (h[k].sm) {
-      const double vy = lane_value(s, 0) + h[k].vfac * lane_value(s, C - 1);
-      s = fma(-vy * h[k].smfac, lt[k]->z[lane], s);
+    if (t->sm) {
+      const double vy = lane_value(s, 0) + t->vfac * lane_value(s, C - 1);
+      s = fma(-vy * t->smfac, lt[k]->z[lane], s);
     }
+    // The shift runs on all lanes before the select: under a branch that
+    // masked off lane 0, lane 1 would read an inactive lane.
     const double sprev = from_prev(s);
     const double slast = lane_value(s, C - 1);
-    double ghost = fma(h[k].gh0, s, h[k].ghw * slast);
-    if constexpr (Q > 1) ghost = fma(h[k].ghd, x[k][1], ghost);
+    double ghost = fma(t->gh0, s, t->ghw * slast);
+    if constexpr (Q > 1) ghost = fma(t->ghd, x[k][1], ghost);
     const double sl = (lane == 0) ? ghost : sprev;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) x[k][j] = fma(sl, h[k].al[j], fma(s, h[k].be[j], x[k][j]));
+    for (int j = 0; j < Q; ++j) x[k][j] = fma(sl, t->al[j], fma(s, t->be[j], x[k][j]));
     x[k][M - 1] = s;
   }
 }

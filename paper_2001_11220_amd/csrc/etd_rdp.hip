@@ -44,8 +44,10 @@ namespace etd {
 // doubles.
 
 // ---------------------------------------------------------------------------
-// Pass 1 (axis 1).  Tiles of 8 x-lines with adjacent y; the next tile's U is
-// fetched into registers while the current tile is solved.
+// Pass 1 (axis 1).  Tiles of 8 or 16 x-lines with adjacent y; the next
+// tile's U is fetched into registers while the last species of the current
+// tile is solved (once this tile's U is no longer needed, so that the two
+// never occupy registers together).
 // ---------------------------------------------------------------------------
 template <int M, int S, int L>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
@@ -77,8 +79,6 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
     for (int s = 0; s < S; ++s)
 #pragma unroll
       for (int j = 0; j < M; ++j) U[s][j] = Un[s][j];
-    have = walk.next(tile);
-    if (have) fetch(tile);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       double uu[S], ff[S];
@@ -94,6 +94,10 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
         double x[1][M];
 #pragma unroll
         for (int j = 0; j < M; ++j) x[0][j] = fma(k, f[s][j], U[s][j]);
+        if (s == S - 1) {
+          have = walk.next(tile);
+          if (have) fetch(tile);
+        }
         const SolveTab* tb[1] = {at.P(s)};
         const LaneTab* lb[1] = {at.lP(s)};
         line_solve<M, 1>(tb, lb, x, lane);
@@ -108,6 +112,10 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
         x[2][j] = U[s][j];
         x[3][j] = f[s][j];
         x[4][j] = fma(k, f[s][j], U[s][j]);
+      }
+      if (s == S - 1) {
+        have = walk.next(tile);
+        if (have) fetch(tile);
       }
       const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
       const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};

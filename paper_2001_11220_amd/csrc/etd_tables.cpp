@@ -104,10 +104,9 @@ void emulate(const SolveTab& t, const double* b, double* x) {
   }
   for (int c = 0; c < C; ++c) {
     const int cn = (c + 1 == C) ? 0 : c + 1;
-    const bool last = (c + 1 == C);
     double v = b[static_cast<int64_t>(c) * m + m - 1];
-    if (q > 0) v += (last ? t.wl_last : t.wl_gen) * g[c][q - 1] + (last ? t.wr_last : t.wr_gen) * g[cn][0];
-    if (q > 1 && c == 0) v += t.wg0 * g[c][1];
+    if (q > 0) v += t.lane.wl[c] * g[c][q - 1] + t.lane.wr[c] * g[cn][0];
+    if (q > 1) v += t.lane.wg[c] * g[c][1];
     d[c] = v;
   }
   for (int st = 0; st < t.npcr; ++st) {
@@ -350,6 +349,13 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
     if (q > 0 && (wl[c] != r || wr[c] != r)) return fail("non-uniform reduced weights");
   for (int c = 1; c < C; ++c)
     if (wg[c] != 0.0) return fail("ghost weight beyond separator 0");
+  // Per-lane copies of the weights (zero on lanes without a chunk): the
+  // device reads these instead of selecting between the uniform values.
+  for (int c = 0; c < C; ++c) {
+    t.lane.wl[c] = (c + 1 == C) ? t.wl_last : t.wl_gen;
+    t.lane.wr[c] = (c + 1 == C) ? t.wr_last : t.wr_gen;
+    t.lane.wg[c] = (c == 0) ? t.wg0 : 0.0;
+  }
 
   // Residual self-check of the chunked algorithm on the original line matrix.
   uint64_t state = 0x9E3779B97F4A7C15ull ^ static_cast<uint64_t>(n * 131 + bc);

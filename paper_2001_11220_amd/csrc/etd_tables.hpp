@@ -15,7 +15,7 @@
 //   1. local solve   g = T^{-1} b_interior                 (Thomas, uniform)
 //   2. reduced RHS   d_c = b_sep + wl_c g_c[m-2] + wr_c g_{c+1}[0] + wg_c g_c[1]
 //      (wl, wr take one value for c < C-1 and another for c = C-1; wg is
-//      non-zero for c = 0 only)
+//      non-zero for c = 0 only; all three are per-lane arrays)
 //   3. reduced solve s = Mred^{-1} d by parallel cyclic reduction across the
 //      lanes of the wavefront (per-lane multipliers, staged in LDS), plus a
 //      Sherman-Morrison rank-one correction when the reduced system is
@@ -44,6 +44,9 @@ struct LaneTab {
   double k2[kMaxPcr][kLanes];  // PCR multipliers of the lane+s neighbour
   double inv[kLanes];          // 1 / reduced diagonal after the last step
   double z[kLanes];            // Sherman-Morrison vector Mred'^{-1} u
+  double wl[kLanes];           // reduced-RHS weight of g_c[m-2]
+  double wr[kLanes];           // reduced-RHS weight of g_{c+1}[0]
+  double wg[kLanes];           // reduced-RHS weight of g_c[1] (lane 0 only)
 };
 
 // One line-solve operator (axis, species, gamma).  POD, 256-byte multiple,
