@@ -94,9 +94,18 @@ typedef struct etd_reaction_t {
   double shift[ETD_MAX_SPECIES];    /* F evaluated at u + shift              */
 } etd_reaction_t;
 
+/* Lines per wavefront of the forward passes (etd_scheme_t.lines_per_wave).
+ * A wavefront solves one grid line with up to 64 chunks, or two lines of
+ * 32 chunks each when the line length is n = 32 m with 5 <= m <= 8 (fewer
+ * cross-lane reduction levels per line, 32-line tiles).  Results agree with
+ * the one-line form to rounding (the chunking differs). */
+#define ETD_LINES_AUTO 0   /* two where n allows and a pass has >= 32768 lines */
+#define ETD_LINES_ONE 1    /* always one                                       */
+#define ETD_LINES_TWO 2    /* two wherever n allows                            */
+
 typedef struct etd_scheme_t {
   int32_t scheme;                   /* ETD_SCHEME_RDP or ETD_SCHEME_ETD1     */
-  int32_t pad_;
+  int32_t lines_per_wave;           /* ETD_LINES_*; ignored by the batch API */
 } etd_scheme_t;
 
 typedef struct etd_rdp_ctx etd_rdp_ctx;
@@ -109,7 +118,7 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  *  bc    : bc[i] for axis i+1, one of ETD_BC_*.
  *  D     : s diffusion coefficients, finite and >= 0 (diagonal D, Section 2).
  *  k     : time step, finite and > 0.
- *  scheme: NULL selects ETD_SCHEME_RDP.
+ *  scheme: NULL selects ETD_SCHEME_RDP with ETD_LINES_AUTO.
  *  rx    : reaction model and parameters; must match s.
  *  out   : receives the new context (owned by the library; free it with
  *          etd_rdp_destroy).
@@ -117,7 +126,8 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  * Errors: ETD_ERR_ARG for a NULL pointer, d not in {2,3}, s not in {1,2},
  * n below the minimum of its BC (Dirichlet 1, Neumann 2, periodic 3), a
  * non-finite or non-positive h or k, a negative or non-finite D, an unknown
- * model or one whose species count differs from s.  ETD_ERR_UNSUPPORTED when
+ * model or one whose species count differs from s, lines_per_wave not one of
+ * ETD_LINES_*.  ETD_ERR_UNSUPPORTED when
  * a line length n cannot be split into at most 64 chunks of at most 8 rows
  * (n > 512, or n > 64 with no divisor m <= 8 such that n/m <= 64).
  * ETD_ERR_INTERNAL if a table self-check fails.

@@ -628,7 +628,7 @@ hipError_t launch_ka_mid_s(const etd_rdp_ctx* c, double* const (&A)[3], double* 
   constexpr int L = kAdjStreamLines;
   const int a = 1;
   const size_t fixed = adj_fixed_lds_s(S);
-  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, L);
+  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, L, true);
   const size_t lds = pass_lds(g, fixed);
   hipError_t e = adj_grid(ka_mid_s<M, S, L>, lds, g.nFblk * g.nT * S, nblk, 64 * L);
   if (e != hipSuccess) return e;
@@ -643,7 +643,7 @@ hipError_t launch_ka_last(const etd_rdp_ctx* c, double* const (&X)[3], const dou
                           unsigned* nblk, hipStream_t st) {
   const int a = c->d - 1;
   const size_t fixed = adj_fixed_lds(S);
-  const PassGeom g = pass_geom(c, kPassLast, fixed, kBlockLines);
+  const PassGeom g = pass_geom(c, kPassLast, fixed, kBlockLines, true);
   const size_t lds = pass_lds(g, fixed);
   hipError_t e = adj_grid(ka_last<M, S>, lds, g.nFblk * g.nT, nblk);
   if (e != hipSuccess) return e;
@@ -658,7 +658,7 @@ hipError_t launch_ka_mid(const etd_rdp_ctx* c, double* const (&A)[3], double* co
   if constexpr (M <= kAdjStreamMidTo) return launch_ka_mid_s<M, S>(c, A, Y, tabs, part, nblk, st);
   const int a = 1;
   const size_t fixed = adj_fixed_lds(S);
-  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, kBlockLines);
+  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, kBlockLines, true);
   const size_t lds = pass_lds(g, fixed);
   hipError_t e = adj_grid(ka_mid<M, S>, lds, g.nFblk * g.nT, nblk);
   if (e != hipSuccess) return e;
@@ -703,8 +703,8 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
   hipError_t e = hipSuccess;
   // Axis d: reads the triple pass d reads (B in 3-D, A in 2-D) and lam.
   {
-    const int a = c->d - 1, m = c->m[a];
-    const SolveTab* ta = tabs + tab_index(a, 0, 0, S);
+    const int a = c->d - 1, m = c->m1[a];
+    const SolveTab* ta = tabs + c->tab1 + tab_index(a, 0, 0, S);
     double* const(&X)[3] = (c->d == 3) ? B : A;
     double* pp = part;
     if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 1>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
@@ -712,16 +712,16 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
     if (e != hipSuccess) return hip_fail(c, e);
   }
   if (c->d == 3) {
-    const int m = c->m[1];
-    const SolveTab* ta = tabs + tab_index(1, 0, 0, S);
+    const int m = c->m1[1];
+    const SolveTab* ta = tabs + c->tab1 + tab_index(1, 0, 0, S);
     double* pp = part + (size_t)kAdjMaxBlocks * kGradSlots;
     if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 1>(c, A, Y, ta, pp, &nb[1], st))); }
     else { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 2>(c, A, Y, ta, pp, &nb[1], st))); }
     if (e != hipSuccess) return hip_fail(c, e);
   }
   {
-    const int m = c->m[0];
-    const SolveTab* ta = tabs + tab_index(0, 0, 0, S);
+    const int m = c->m1[0];
+    const SolveTab* ta = tabs + c->tab1 + tab_index(0, 0, 0, S);
     double* pp = part + 2 * (size_t)kAdjMaxBlocks * kGradSlots;
     if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
     else { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 2>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }

@@ -22,9 +22,15 @@ struct etd_rdp_ctx {
   int scheme = ETD_SCHEME_RDP;
   etd::Rx rx{};
   int nparams = 0;             // reaction parameters with a gradient
-  int m[3] = {0, 0, 0};
+  int m[3] = {0, 0, 0};         // chunk length of the forward passes' tables
+  int P[3] = {1, 1, 1};         // lines per wavefront of the forward passes
+  int m1[3] = {0, 0, 0};        // chunk length with one line per wavefront
   int64_t N = 0;
-  std::vector<etd::SolveTab> tabs;  // [axis][species][3]
+  // [axis][species][3] for the forward passes; when some axis runs two lines
+  // per wavefront, a second set with one line per wavefront follows at index
+  // tab1 (the reverse-mode kernels and single solves use it), else tab1 = 0.
+  std::vector<etd::SolveTab> tabs;
+  int tab1 = 0;
   size_t tab_bytes = 0, arr_bytes = 0, ws_bytes = 0;
   size_t part_bytes = 0, adj_ws_bytes = 0;
   const void* uploaded_ws = nullptr;
@@ -34,6 +40,19 @@ struct etd_rdp_ctx {
 namespace etd {
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Two lines per wavefront: an axis whose lines are n = 32 m rows with
+// m in [kMinTwoLineM, kMaxM] runs its forward pass with 32 chunks of m rows
+// per line and two lines per wavefront (the streamed kernels); returns m, or
+// 0 when the axis runs one line per wavefront.
+constexpr int kMinTwoLineM = 5;
+// Lines a pass needs before ETD_LINES_AUTO takes two lines per wavefront:
+// 1024 tiles of 32 lines, four per block of a persistent grid.
+constexpr int64_t kTwoLineMinLines = 32768;
+inline int two_line_chunk(int64_t n) {
+  const int64_t m = n / 32;
+  return (n % 32 == 0 && m >= kMinTwoLineM && m <= kMaxM) ? static_cast<int>(m) : 0;
+}
 
 // Reverse-mode step: gradient slots per block (s diffusion coefficients, then
 // the reaction parameters), the most blocks a reverse pass launches, and the
@@ -55,13 +74,16 @@ int check_ws(const void* ws, size_t have, size_t need);
 // Uploads the tables to the front of ws, unless ws already holds them.
 int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st);
 
-// Geometry of a strided pass over axis axis0 (0-based, >= 1).
+// Geometry of a strided single-solve pass over axis axis0 (0-based, >= 1),
+// one line per wavefront.
 Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds);
 size_t geom_lds(const Geom& g, size_t fixed_lds);
 
-// Pass geometries of the single-problem stepper (see PassGeom).
+// Pass geometries of the single-problem stepper (see PassGeom), with the
+// forward passes' chunking or (one_line) the one-line-per-wavefront one.
 enum PassKind : int { kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3 };
-PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines);
+PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines,
+                   bool one_line = false);
 size_t pass_lds(const PassGeom& g, size_t fixed_lds);
 
 // The i-th carried array (s*N doubles) of a workspace.

@@ -148,6 +148,37 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
+// Value of v from lane ^ 16 (the other 16-lane row of the same 32-lane
+// half): v_permlane16_swap gives rows (0,0,2,2) and (1,1,3,3); the odd rows
+// take the first, the even rows the second.
+__device__ __forceinline__ double rows_swap16(double v, bool odd_row) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(static_cast<int>(odd_row ? hi[0] : hi[1]),
+                          static_cast<int>(odd_row ? lo[0] : lo[1]));
+}
+
+// Lines per wavefront.  With P = 1 a wavefront solves one line, lane c
+// holding chunk c.  With P = 2 it solves two lines of exactly 32 chunks
+// each: lane c holds chunk c % 32 of the wavefront's line c / 32 (its
+// segment).  Cross-lane reads that leave a segment only ever meet a zero
+// multiplier, so the exchanges are the same as for one line.
+template <int P>
+constexpr int kSegLanes = 64 / P;
+
+// Value of v in lane idx of this lane's segment (idx uniform).
+template <int P>
+__device__ __forceinline__ double seg_value(double v, int idx, int lane) {
+  if constexpr (P == 1) {
+    return lane_value(v, idx);
+  } else {
+    static_assert(P == 2, "one or two lines per wavefront");
+    const double a = lane_value(v, idx);
+    const double b = lane_value(v, kSegLanes<P> + idx);
+    return (lane >= kSegLanes<P>) ? b : a;
+  }
+}
+
 // Exact line solves on a wavefront.
 //
 // A block holds kBlockLines lines, one per wavefront; lane c of a wavefront
@@ -170,11 +201,13 @@ __device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tab
 // chunk of right-hand side k on entry and of the solution on exit, with
 // table tab[k] (header in global memory, uniform) and lt[k] (per-lane data
 // in LDS).  All 64 lanes must call it together.
-template <int M, int K>
+template <int M, int K, int P = 1>
 __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
                                            const LaneTab* const (&lt)[K],
                                            double (&x)[K][M], int lane) {
   constexpr int Q = M - 1;
+  // Chunk of this lane within its line (the per-lane table index).
+  const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
   // Uniform table fields: the interior factors here, the correction factors
   // after the reduction, so that only one group is held in scalar registers
   // at a time.  The reduced-RHS weights, which differ on the first and last
@@ -211,31 +244,33 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
     }
   }
   // 2. Right-hand side of the reduced separator system.  The last chunk's
-  // right neighbour is row 0 (it only matters for the periodic closure).
+  // right neighbour is row 0 of the same line (it only matters for the
+  // periodic closure).
   const int lane4 = lane * 4;
-  const int a_next = (lane + 1 == C) ? 0 : lane4 + 4;
+  const int a_next = (c + 1 == C) ? (lane - c) * 4 : lane4 + 4;
   double d[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double v = x[k][M - 1];
     if constexpr (Q > 0) {
       const double gn = bperm(a_next, x[k][0]);
-      v = fma(lt[k]->wl[lane], x[k][Q - 1], v);
-      v = fma(lt[k]->wr[lane], gn, v);
+      v = fma(lt[k]->wl[c], x[k][Q - 1], v);
+      v = fma(lt[k]->wr[c], gn, v);
     }
-    if constexpr (Q > 1) v = fma(lt[k]->wg[lane], x[k][1], v);
+    if constexpr (Q > 1) v = fma(lt[k]->wg[c], x[k][1], v);
     d[k] = v;
   }
   // 3. Parallel cyclic reduction across the lanes.  Lanes with no neighbour
   // at distance sh have a zero multiplier; what they read there does not
   // matter.  Distance 1 uses DPP shifts, distances 16 and 32 permlane
-  // swaps, the others ds_bpermute.
+  // swaps, the others ds_bpermute.  With two lines per wavefront the last
+  // level has distance 16, within the 32-lane halves: one row swap.
   if (npcr > 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const double dm = from_prev(d[k]);
       const double dp = from_next(d[k]);
-      d[k] = d[k] - lt[k]->k1[0][lane] * dm - lt[k]->k2[0][lane] * dp;
+      d[k] = d[k] - lt[k]->k1[0][c] * dm - lt[k]->k2[0][c] * dp;
     }
   }
 #pragma unroll
@@ -247,25 +282,34 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       for (int k = 0; k < K; ++k) {
         const double dm = bperm(a_up, d[k]);
         const double dp = bperm(a_dn, d[k]);
-        d[k] = d[k] - lt[k]->k1[st][lane] * dm - lt[k]->k2[st][lane] * dp;
+        d[k] = d[k] - lt[k]->k1[st][c] * dm - lt[k]->k2[st][c] * dp;
       }
     }
   }
   if (npcr > kMaxPcr - 2) {
-    const bool row1 = (lane >> 4) == 1, row2 = (lane >> 4) == 2;
+    if constexpr (P == 1) {
+      const bool row1 = (lane >> 4) == 1, row2 = (lane >> 4) == 2;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double dm, dp;
-      quarters_shift(d[k], row1, row2, dm, dp);
-      d[k] = d[k] - lt[k]->k1[kMaxPcr - 2][lane] * dm - lt[k]->k2[kMaxPcr - 2][lane] * dp;
+      for (int k = 0; k < K; ++k) {
+        double dm, dp;
+        quarters_shift(d[k], row1, row2, dm, dp);
+        d[k] = d[k] - lt[k]->k1[kMaxPcr - 2][c] * dm - lt[k]->k2[kMaxPcr - 2][c] * dp;
+      }
+    } else {
+      const bool odd_row = ((lane >> 4) & 1) != 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double dx = rows_swap16(d[k], odd_row);
+        d[k] = d[k] - lt[k]->k1[kMaxPcr - 2][c] * dx - lt[k]->k2[kMaxPcr - 2][c] * dx;
+      }
     }
   }
-  if (npcr > kMaxPcr - 1) {
+  if (P == 1 && npcr > kMaxPcr - 1) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double dm, dp;
       halves_swap(d[k], dm, dp);
-      d[k] = d[k] - lt[k]->k1[kMaxPcr - 1][lane] * dm - lt[k]->k2[kMaxPcr - 1][lane] * dp;
+      d[k] = d[k] - lt[k]->k1[kMaxPcr - 1][c] * dm - lt[k]->k2[kMaxPcr - 1][c] * dp;
     }
   }
   // 4. Separators, cyclic fix, and back to the chunk.  The left separator
@@ -274,18 +318,18 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const SolveTab* t = tab[k] + z1;
-    double s = d[k] * lt[k]->inv[lane];
+    double s = d[k] * lt[k]->inv[c];
     if (t->sm) {
-      const double vy = lane_value(s, 0) + t->vfac * lane_value(s, C - 1);
-      s = fma(-vy * t->smfac, lt[k]->z[lane], s);
+      const double vy = seg_value<P>(s, 0, lane) + t->vfac * seg_value<P>(s, C - 1, lane);
+      s = fma(-vy * t->smfac, lt[k]->z[c], s);
     }
     // The shift runs on all lanes before the select: under a branch that
     // masked off lane 0, lane 1 would read an inactive lane.
     const double sprev = from_prev(s);
-    const double slast = lane_value(s, C - 1);
+    const double slast = seg_value<P>(s, C - 1, lane);
     double ghost = fma(t->gh0, s, t->ghw * slast);
     if constexpr (Q > 1) ghost = fma(t->ghd, x[k][1], ghost);
-    const double sl = (lane == 0) ? ghost : sprev;
+    const double sl = (c == 0) ? ghost : sprev;
 #pragma unroll
     for (int j = 0; j < Q; ++j) x[k][j] = fma(sl, t->al[j], fma(s, t->be[j], x[k][j]));
     x[k][M - 1] = s;
@@ -436,15 +480,17 @@ struct TileAt {
   __device__ __forceinline__ TileAt(int64_t t_, int64_t f0_) : t(t_), f0(f0_) {}
 };
 
-// This wave's chunk of its line (f0 + wave, t) read directly; zeros for a
-// line past nF or a lane without a chunk.
-template <int M>
+// This lane's chunk of its line read directly; zeros for a line past nF or
+// a lane without a chunk.  Wavefront w holds lines f0 + w*P .. f0 + w*P + P-1
+// of the tile (one per segment).
+template <int M, int P = 1>
 __device__ __forceinline__ void line_load(const double* __restrict__ A, double (&v)[M],
                                           const PassGeom& g, const TileAt& p) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t f = p.f0 + w;
-  const bool ok = (lane < g.C) && (f < g.nF);
-  const double* src = ok ? A + f * g.inF + p.t * g.inT + (int64_t)lane * M : A;
+  const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
+  const int64_t f = p.f0 + w * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
+  const bool ok = (c < g.C) && (f < g.nF);
+  const double* src = ok ? A + f * g.inF + p.t * g.inT + (int64_t)c * M : A;
   load_chunk<M>(src, v, ok);
 }
 
@@ -484,17 +530,21 @@ __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M]
   else cur.buf ^= 1;
 }
 
-// Transposed write of every wave's line chunk (all threads call it).
-template <int M, int L>
+// Transposed write of every wave's line chunks (all threads call it).  The
+// block has 64*L/P threads; in the write-out thread (col, q) moves rows
+// q*M .. q*M+M-1 of the tile's line col.
+template <int M, int L, int P = 1>
 __device__ __forceinline__ void tile_store(double* __restrict__ A, const double (&x)[M],
                                            double* lds, const PassGeom& g, const TileAt& p,
                                            TileCursor& cur) {
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
+  const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
+  const int li = w * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
   double* T = lds + cur.buf * g.tile;
-  if (lane < g.C) {
+  if (c < g.C) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) T[w * g.pitch + j * g.C + lane] = x[j];
+    for (int j = 0; j < M; ++j) T[li * g.pitch + j * g.C + c] = x[j];
   }
   __syncthreads();
   const int col = tid & (L - 1), q = tid / L;

@@ -216,8 +216,8 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
 // current one is solved.  Fewer registers per wave than k_mid, for long
 // chunks.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L>
-__global__ __launch_bounds__(64 * L, 4) void k_mid_s(
+template <int M, int S, int L, int P>
+__global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
     const double* __restrict__ c1, const double* __restrict__ c2,
     const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
     double* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(64 * L, 4) void k_mid_s(
   double pf[M];
   auto src = [&](int ph_) { return ph_ == 0 ? c1 : (ph_ == 1 ? c2 : w); };
   auto fetch = [&](int64_t tl_, int s_, int ph_) {
-    line_load<M>(src(ph_) + s_ * g.N, pf, g, TileAt(tl_, g));
+    line_load<M, P>(src(ph_) + s_ * g.N, pf, g, TileAt(tl_, g));
   };
   if (have) fetch(tile, 0, ph);
   while (have) {
@@ -263,15 +263,15 @@ __global__ __launch_bounds__(64 * L, 4) void k_mid_s(
       for (int j = 0; j < M; ++j) y[0][j] = x[0][j];
       const SolveTab* tb[1] = {at.P(sc)};
       const LaneTab* lb[1] = {at.lP(sc)};
-      line_solve<M, 1>(tb, lb, y, lane);
-      tile_store<M, L>(ow + sc * g.N, y[0], tl, g, pos, cur);
+      line_solve<M, 1, P>(tb, lb, y, lane);
+      tile_store<M, L, P>(ow + sc * g.N, y[0], tl, g, pos, cur);
     } else {
       const SolveTab* tb[2] = {at.T(sc), at.Sx(sc)};
       const LaneTab* lb[2] = {at.lT(sc), at.lS(sc)};
-      line_solve<M, 2>(tb, lb, x, lane);
+      line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
-      tile_store<M, L>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
+      tile_store<M, L, P>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
     }
   }
 }
@@ -296,8 +296,8 @@ __device__ __forceinline__ void react_species(const Rx& rx, const double (&U)[S]
   }
 }
 
-template <int M, int S, int L>
-__global__ __launch_bounds__(64 * L, 4) void k_first_s(
+template <int M, int S, int L, int P>
+__global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
     double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
     int etd1) {
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(64 * L, 4) void k_first_s(
       // The tile's lines of every species (the later species' reads hit L2).
       double U[S][M], f[M];
 #pragma unroll
-      for (int q = 0; q < S; ++q) line_load<M>(u + q * g.N, U[q], g, pos);
+      for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, U[q], g, pos);
       react_species<S, M>(rx, U, s, f);
       double y[1][M];
 #pragma unroll
@@ -326,8 +326,8 @@ __global__ __launch_bounds__(64 * L, 4) void k_first_s(
       {
         const SolveTab* tb[1] = {at.P(s)};
         const LaneTab* lb[1] = {at.lP(s)};
-        line_solve<M, 1>(tb, lb, y, lane);
-        tile_store<M, L>(w + s * g.N, y[0], tl, g, pos, cur);
+        line_solve<M, 1, P>(tb, lb, y, lane);
+        tile_store<M, L, P>(w + s * g.N, y[0], tl, g, pos, cur);
       }
       if (etd1) continue;
 #pragma unroll
@@ -340,10 +340,10 @@ __global__ __launch_bounds__(64 * L, 4) void k_first_s(
         }
         const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
         const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
-        line_solve<M, 2>(tb, lb, x, lane);
+        line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
         for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
-        tile_store<M, L>((r == 0 ? c2 : c1) + s * g.N, x[0], tl, g, pos, cur);
+        tile_store<M, L, P>((r == 0 ? c2 : c1) + s * g.N, x[0], tl, g, pos, cur);
       }
     }
   }
@@ -354,8 +354,8 @@ __global__ __launch_bounds__(64 * L, 4) void k_first_s(
 // species when they are used and no cross-tile prefetch, so that a 16-line
 // tile of long chunks fits the register budget.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L>
-__global__ __launch_bounds__(64 * L, 4) void k_last_s(
+template <int M, int S, int L, int P>
+__global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
     const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
     PassGeom g, int etd1) {
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(64 * L, 4) void k_last_s(
     const TileAt pos(tile, g);
     double us[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) line_load<M>(w + s * g.N, us[s], g, pos);
+    for (int s = 0; s < S; ++s) line_load<M, P>(w + s * g.N, us[s], g, pos);
     {
       const SolveTab* tb[S];
       const LaneTab* lb[S];
@@ -383,11 +383,11 @@ __global__ __launch_bounds__(64 * L, 4) void k_last_s(
         tb[s] = at.P(s);
         lb[s] = at.lP(s);
       }
-      line_solve<M, S>(tb, lb, us, lane);
+      line_solve<M, S, P>(tb, lb, us, lane);
     }
     if (etd1) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M, L>(u + s * g.N, us[s], tl, g, pos, cur);
+      for (int s = 0; s < S; ++s) tile_store<M, L, P>(u + s * g.N, us[s], tl, g, pos, cur);
       continue;
     }
 #pragma unroll
@@ -402,8 +402,8 @@ __global__ __launch_bounds__(64 * L, 4) void k_last_s(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double x[2][M], b[M];
-      line_load<M>(c1 + s * g.N, x[0], g, pos);
-      line_load<M>(c2 + s * g.N, b, g, pos);
+      line_load<M, P>(c1 + s * g.N, x[0], g, pos);
+      line_load<M, P>(c2 + s * g.N, b, g, pos);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const double a = x[0][j];
@@ -412,10 +412,10 @@ __global__ __launch_bounds__(64 * L, 4) void k_last_s(
       }
       const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
       const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
-      line_solve<M, 2>(tb, lb, x, lane);
+      line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) x[0][j] = x[0][j] - x[1][j];
-      tile_store<M, L>(u + s * g.N, x[0], tl, g, pos, cur);
+      tile_store<M, L, P>(u + s * g.N, x[0], tl, g, pos, cur);
     }
   }
 }
@@ -638,7 +638,7 @@ Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds) {
   const int64_t n1 = c->n[0], n2 = c->n[1];
   g.N = c->N;
   g.n = static_cast<int>(c->n[axis0]);
-  g.C = g.n / c->m[axis0];
+  g.C = g.n / c->m1[axis0];
   g.pitch = g.n + ((8 - g.n % 32) + 32) % 32;  // = 8 (mod 32), see tile_load
   g.tile = kBlockLines * g.pitch;
   // Two tile buffers (one barrier per move) when two blocks still fit a CU.
@@ -667,7 +667,7 @@ size_t geom_lds(const Geom& g, size_t fixed_lds) {
   return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
 }
 
-PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines) {
+PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, bool one_line) {
   const int64_t n1 = c->n[0], n2 = c->n[1], n3 = (c->d == 3) ? c->n[2] : 1;
   PassGeom g{};
   g.N = c->N;
@@ -704,7 +704,7 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines) 
       break;
   }
   g.n = static_cast<int>(c->n[axis0]);
-  g.C = g.n / c->m[axis0];
+  g.C = g.n / (one_line ? c->m1[axis0] : c->m[axis0]);
   g.pitch = tile_pitch(g.n);
   g.lines = lines;
   g.tile = lines * g.pitch;
@@ -720,43 +720,45 @@ size_t pass_lds(const PassGeom& g, size_t fixed_lds) {
 namespace {
 
 // Chunk lengths from which the passes run streamed (k_first_s, k_mid_s,
-// k_last_s), and the lines per tile those use.
+// k_last_s), and the wavefronts per block those use (a tile is
+// kStreamWaves * P lines).  Axes with two lines per wavefront always run
+// streamed.
 constexpr int kStreamFirstFrom = 8;
 constexpr int kStreamMidFrom = 5;
 constexpr int kStreamLastFrom = 5;
-constexpr int kStreamLines = 16;
+constexpr int kStreamWaves = 16;
 
 // Launchers, templated on the chunk length and species count.
-template <int M, int S>
+template <int M, int S, int P>
 hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                           double* w, const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds(3 * S);
-  constexpr int L = kStreamLines;
+  constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_first_s<M, S, L>, lds);
+  hipError_t e = set_lds(k_first_s<M, S, L, P>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_first_s<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  e = persistent_grid(k_first_s<M, S, L, P>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_first_s<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+  hipLaunchKernelGGL((k_first_s<M, S, L, P>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
                      c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S>
+template <int M, int S, int P>
 hipError_t launch_last_s(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
                          const double* w, const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds(3 * S);
-  constexpr int L = kStreamLines;
+  constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassLast, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_last_s<M, S, L>, lds);
+  hipError_t e = set_lds(k_last_s<M, S, L, P>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_last_s<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  e = persistent_grid(k_last_s<M, S, L, P>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_last_s<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+  hipLaunchKernelGGL((k_last_s<M, S, L, P>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
                      c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
@@ -764,8 +766,11 @@ hipError_t launch_last_s(const etd_rdp_ctx* c, double* u, const double* c1, cons
 template <int M, int S>
 hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                         double* w, const SolveTab* tabs, hipStream_t st) {
+  if constexpr (M >= kMinTwoLineM) {
+    if (c->P[0] == 2) return launch_first_s<M, S, 2>(c, u, c1, c2, w, tabs, st);
+  }
   if constexpr (M >= kStreamFirstFrom) {
-    return launch_first_s<M, S>(c, u, c1, c2, w, tabs, st);
+    return launch_first_s<M, S, 1>(c, u, c1, c2, w, tabs, st);
   }
   const size_t fixed = lane_lds(3 * S);
   constexpr int L = kLinesFor<M>;
@@ -781,20 +786,20 @@ hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, doubl
   return hipGetLastError();
 }
 
-template <int M, int S>
+template <int M, int S, int P>
 hipError_t launch_mid_s(const etd_rdp_ctx* c, const double* c1, const double* c2,
                         const double* w, double* o1, double* o2, double* ow,
                         const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds(3 * S);
-  constexpr int L = kStreamLines;
+  constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassMid, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_mid_s<M, S, L>, lds);
+  hipError_t e = set_lds(k_mid_s<M, S, L, P>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_mid_s<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  e = persistent_grid(k_mid_s<M, S, L, P>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid_s<M, S, L>), dim3(grid), dim3(64 * L), lds, st, c1, c2, w, o1, o2,
+  hipLaunchKernelGGL((k_mid_s<M, S, L, P>), dim3(grid), dim3(64 * kStreamWaves), lds, st, c1, c2, w, o1, o2,
                      ow, tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
@@ -803,8 +808,11 @@ template <int M, int S>
 hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
                       const double* w, double* o1, double* o2, double* ow,
                       const SolveTab* tabs, hipStream_t st) {
+  if constexpr (M >= kMinTwoLineM) {
+    if (c->P[1] == 2) return launch_mid_s<M, S, 2>(c, c1, c2, w, o1, o2, ow, tabs, st);
+  }
   if constexpr (M >= kStreamMidFrom) {
-    return launch_mid_s<M, S>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    return launch_mid_s<M, S, 1>(c, c1, c2, w, o1, o2, ow, tabs, st);
   }
   const size_t fixed = lane_lds(3 * S);
   constexpr int L = kLinesFor<M>;
@@ -823,8 +831,11 @@ hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
 template <int M, int S>
 hipError_t launch_last(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
                        const double* w, const SolveTab* tabs, hipStream_t st) {
+  if constexpr (M >= kMinTwoLineM) {
+    if (c->P[c->d - 1] == 2) return launch_last_s<M, S, 2>(c, u, c1, c2, w, tabs, st);
+  }
   if constexpr (M >= kStreamLastFrom) {
-    return launch_last_s<M, S>(c, u, c1, c2, w, tabs, st);
+    return launch_last_s<M, S, 1>(c, u, c1, c2, w, tabs, st);
   }
   const size_t fixed = lane_lds(3 * S);
   constexpr int L = kLinesFor<M>;
@@ -936,6 +947,8 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   if (want_s < 0 || (want_s > 0 && want_s != s)) return ETD_ERR_ARG;
   int sch = scheme ? scheme->scheme : ETD_SCHEME_RDP;
   if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
+  const int lpw = scheme ? scheme->lines_per_wave : ETD_LINES_AUTO;
+  if (lpw != ETD_LINES_AUTO && lpw != ETD_LINES_ONE && lpw != ETD_LINES_TWO) return ETD_ERR_ARG;
   for (int i = 0; i < s; ++i)
     if (!(std::isfinite(D[i]) && D[i] >= 0)) return ETD_ERR_ARG;
   for (int i = 0; i < ETD_MAX_PARAMS; ++i)
@@ -950,6 +963,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   c->k = k;
   c->scheme = sch;
   int64_t N = 1;
+  for (int i = 0; i < d; ++i) N *= grid->n[i];
   for (int i = 0; i < d; ++i) {
     const int64_t n = grid->n[i];
     const int b = bc[i];
@@ -961,11 +975,15 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     if (!(std::isfinite(h) && h > 0)) { delete c; return ETD_ERR_ARG; }
     const int m = choose_chunk(n);
     if (m == 0) { delete c; return ETD_ERR_UNSUPPORTED; }
+    const int64_t lines = N / n;
+    const bool two_ok = (lpw == ETD_LINES_TWO) || (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines);
+    const int m2 = two_ok ? two_line_chunk(n) : 0;
     c->n[i] = n;
     c->h[i] = h;
     c->bc[i] = b;
-    c->m[i] = m;
-    N *= n;
+    c->m1[i] = m;
+    c->m[i] = m2 ? m2 : m;
+    c->P[i] = m2 ? 2 : 1;
   }
   c->N = N;
   for (int i = 0; i < s; ++i) c->D[i] = D[i];
@@ -974,19 +992,25 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   for (int i = 0; i < s; ++i) c->rx.shift[i] = rx->shift[i];
 
   const double gam[3] = {1.0, 3.0, 4.0};
-  c->tabs.resize(static_cast<size_t>(d) * s * 3);
-  for (int a = 0; a < d; ++a)
-    for (int sp = 0; sp < s; ++sp)
-      for (int gi = 0; gi < 3; ++gi) {
-        std::string err;
-        if (!build_solve_table(c->n[a], c->bc[a], c->h[a], k * c->D[sp] / gam[gi], c->m[a],
-                               &c->tabs[tab_index(a, sp, gi, s)], &err)) {
-          std::fprintf(stderr, "etd_rdp_init: table (axis %d, species %d, gamma %g): %s\n",
-                       a + 1, sp, gam[gi], err.c_str());
-          delete c;
-          return ETD_ERR_INTERNAL;
+  const int nt = d * s * 3;
+  bool two = false;
+  for (int a = 0; a < d; ++a) two = two || (c->P[a] == 2);
+  c->tab1 = two ? nt : 0;
+  c->tabs.resize(static_cast<size_t>(two ? 2 * nt : nt));
+  for (int set = 0; set < (two ? 2 : 1); ++set)
+    for (int a = 0; a < d; ++a)
+      for (int sp = 0; sp < s; ++sp)
+        for (int gi = 0; gi < 3; ++gi) {
+          std::string err;
+          const int m = (set == 0) ? c->m[a] : c->m1[a];
+          if (!build_solve_table(c->n[a], c->bc[a], c->h[a], k * c->D[sp] / gam[gi], m,
+                                 &c->tabs[set * nt + tab_index(a, sp, gi, s)], &err)) {
+            std::fprintf(stderr, "etd_rdp_init: table (axis %d, species %d, gamma %g): %s\n",
+                         a + 1, sp, gam[gi], err.c_str());
+            delete c;
+            return ETD_ERR_INTERNAL;
+          }
         }
-      }
   c->tab_bytes = round_up(c->tabs.size() * sizeof(SolveTab), 256);
   c->arr_bytes = round_up(sizeof(double) * static_cast<size_t>(N) * s, 256);
   c->ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes;
@@ -1084,9 +1108,10 @@ int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, 
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = ensure_tables(ctx, ws, st);
   if (rc) return rc;
-  const SolveTab* tab = static_cast<const SolveTab*>(ws) + tab_index(axis - 1, sigma, slot, ctx->s);
+  const SolveTab* tab =
+      static_cast<const SolveTab*>(ws) + ctx->tab1 + tab_index(axis - 1, sigma, slot, ctx->s);
   hipError_t e = hipSuccess;
-  ETD_DISPATCH_M(ctx->m[axis - 1], e = launch_solve<M_>(ctx, x, tab, axis - 1, st));
+  ETD_DISPATCH_M(ctx->m1[axis - 1], e = launch_solve<M_>(ctx, x, tab, axis - 1, st));
   if (e != hipSuccess) return hip_fail(ctx, e);
   return ETD_OK;
 }
@@ -1095,14 +1120,14 @@ int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx) { return ctx ? ctx->last_hip 
 
 int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t size) {
   if (!ctx || !name || size == 0 || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
-  const int p = pass - 1, m = ctx->m[p];
+  const int p = pass - 1, m = ctx->m[p], P = ctx->P[p];
   const bool first = (p == 0), last = (p == ctx->d - 1);
-  const bool streamed = first ? (m >= kStreamFirstFrom)
-                              : (last ? (m >= kStreamLastFrom) : (m >= kStreamMidFrom));
+  const bool streamed = (P == 2) || (first ? (m >= kStreamFirstFrom)
+                                           : (last ? (m >= kStreamLastFrom) : (m >= kStreamMidFrom)));
   const char* base = first ? "k_first" : (last ? "k_last" : "k_mid");
-  const int lines = streamed ? kStreamLines : lines_for(m);
-  const int n = std::snprintf(name, size, "%s%s<%d, %d, %d>", base, streamed ? "_s" : "", m,
-                              ctx->s, lines);
+  const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d>", base, m, ctx->s,
+                                         kStreamWaves * P, P)
+                         : std::snprintf(name, size, "%s<%d, %d, %d>", base, m, ctx->s, lines_for(m));
   return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
 }
 

@@ -51,7 +51,7 @@ class Instance(ctypes.Structure):
 
 
 class Scheme(ctypes.Structure):
-    _fields_ = [("scheme", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+    _fields_ = [("scheme", ctypes.c_int32), ("lines_per_wave", ctypes.c_int32)]
 
 
 class EtdError(RuntimeError):
@@ -135,10 +135,11 @@ class EtdRdp:
     ``shape`` is ``(n_1, ..., n_d)`` (axis 1 first); states are torch float64
     tensors of shape ``(s, n_d, ..., n_1)`` on a HIP device.  ``h`` entries of
     0 (or ``None``) select the unit-domain spacing of each boundary condition.
+    ``lines_per_wave`` is "auto", 1 or 2 (ETD_LINES_* of the C ABI).
     """
 
     def __init__(self, shape, bcs, D, k, model, params, h=None, shift=None,
-                 scheme="rdp", device=None):
+                 scheme="rdp", device=None, lines_per_wave="auto"):
         d = len(shape)
         s = len(D)
         g = Grid()
@@ -151,6 +152,7 @@ class EtdRdp:
         D_arr = (ctypes.c_double * MAX_SPECIES)(*[float(v) for v in D], *([0.0] * (MAX_SPECIES - s)))
         sch = Scheme()
         sch.scheme = SCHEMES[scheme]
+        sch.lines_per_wave = 0 if lines_per_wave == "auto" else int(lines_per_wave)
         rx = reaction_struct(model, params, shift, s)
         ctx = ctypes.c_void_p()
         _check(lib.etd_rdp_init(ctypes.byref(g), bc_arr, D_arr, float(k), ctypes.byref(sch),

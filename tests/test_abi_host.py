@@ -35,10 +35,11 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(etd.lib, n), n
 
 
-def _init(shape, bcs, D=(0.1, 0.2), k=0.01, model="brusselator", params=None, h=None, scheme="rdp"):
+def _init(shape, bcs, D=(0.1, 0.2), k=0.01, model="brusselator", params=None, h=None, scheme="rdp",
+          lines_per_wave="auto"):
     etd = _lib()
     params = params if params is not None else {"a": 1.0, "b": 3.0}
-    return etd.EtdRdp(shape, bcs, D, k, model, params, h=h, scheme=scheme)
+    return etd.EtdRdp(shape, bcs, D, k, model, params, h=h, scheme=scheme, lines_per_wave=lines_per_wave)
 
 
 @pytest.mark.parametrize("bc", ["dirichlet", "neumann", "periodic"])
@@ -52,6 +53,29 @@ def test_tables_build_for_every_line_length(bc):
         m, C = p.line_split(1)
         assert m * C == n and C <= 64 and 1 <= m <= 8
         p.close()
+
+
+def test_lines_per_wave_option():
+    from paper_2001_11220_amd import etd
+    bcs = ("periodic", "neumann", "dirichlet")
+    # automatic: two lines per wavefront only for n = 32 m (m = 5..8) on a
+    # pass with at least 32768 lines
+    big = _init((256, 256, 160), bcs)
+    assert [big.line_split(a) for a in (1, 2, 3)] == [(8, 32), (8, 32), (5, 32)]
+    assert big.pass_kernel(1) == "k_first_s<8, 2, 32, 2>"
+    small = _init((256, 12, 10), bcs)
+    assert small.line_split(1) == (4, 64) and small.pass_kernel(1) == "k_first<4, 2, 16>"
+    two = _init((256, 12, 10), bcs, lines_per_wave=2)
+    assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_s<8, 2, 32, 2>"
+    assert two.line_split(2) == (1, 12)  # lengths that are not 32 m keep one line
+    one = _init((256, 192, 160), bcs, lines_per_wave=1)
+    assert [one.line_split(a) for a in (1, 2, 3)] == [(4, 64), (3, 64), (4, 40)]
+    part = _init((256, 192, 160), bcs)  # axis 1 has 30720 lines: one line per wavefront
+    assert [part.line_split(a) for a in (1, 2, 3)] == [(4, 64), (6, 32), (5, 32)]
+    for p in (big, small, two, one, part):
+        p.close()
+    with pytest.raises(etd.EtdError):
+        _init((64, 64), ("periodic",) * 2, lines_per_wave=3)
 
 
 def test_tables_build_for_stiff_coefficients():

@@ -38,6 +38,11 @@ CASES = {
                           (1.0, 0.9), (0.0, 0.0)),
     "cgl2d_m5_m6": ((320, 384), ("periodic", "neumann"), (0.001, 0.002), 0.02, "cgl", {"beta": -0.6}, None,
                     (0.2, 0.4)),
+    # forward recompute with two lines per wavefront, reverse passes with one
+    "bruss3d_two_line": ((192, 12, 256), ("neumann", "periodic", "dirichlet"), (0.02, 0.011), 0.05,
+                         "brusselator", {"a": 1.0, "b": 3.4}, None, (1.0, 3.4)),
+    "gs2d_two_line": ((256, 160), ("periodic", "neumann"), (2e-5, 1e-5), 1.0, "gray_scott",
+                      {"F": 0.04, "kappa": 0.06}, None, (0.7, 0.2)),
 }
 
 
@@ -97,7 +102,8 @@ def test_adjoint_step_matches_oracle(name):
     shape, bcs, D, k, model, params, shift, offset = CASES[name]
     s = len(D)
     print(f"[adjoint step] {name} shape={shape}", flush=True)
-    e = _etd().EtdRdp(shape, bcs, D, k, model, params, shift=shift)
+    lpw = 2 if "two_line" in name else "auto"
+    e = _etd().EtdRdp(shape, bcs, D, k, model, params, shift=shift, lines_per_wave=lpw)
     U, lam = make_inputs(shape, s, offset, seed=len(name))
     lo, g = gpu_adjoint(e, U, lam)
     lo_o, gD, gth = O.adjoint_step(U, lam, k, D, bcs, hs_of(shape, bcs), model,

@@ -28,14 +28,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-def make(prob, scheme="rdp"):
+def make(prob, scheme="rdp", lines_per_wave="auto"):
     return _etd().EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params,
-                         h=prob.h, shift=prob.shift, scheme=scheme)
+                         h=prob.h, shift=prob.shift, scheme=scheme, lines_per_wave=lines_per_wave)
 
 
-def gpu_run(prob, u0, nsteps, scheme="rdp"):
+def gpu_run(prob, u0, nsteps, scheme="rdp", lines_per_wave="auto"):
     torch = _torch()
-    e = make(prob, scheme)
+    e = make(prob, scheme, lines_per_wave)
     u = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
     e.step(u, nsteps)
     torch.cuda.synchronize()
@@ -148,6 +148,20 @@ ONE_STEP = [
     P((2, 3, 1), ("neumann", "periodic", "dirichlet")),  # smallest line lengths
 ]
 
+# Lines of 32 m rows, m = 5..8, forced to two lines per wavefront: every
+# pass, every boundary condition, one and two species, ragged tile tails.
+TWO_LINE = [
+    P((256, 12, 10), ("neumann", "periodic", "dirichlet")),
+    P((10, 192, 13), ("dirichlet", "periodic", "neumann"), model="gray_scott",
+      params={"F": 0.04, "kappa": 0.06}, D=(2e-5, 1e-5), k=1.0, ic="cube_patch"),
+    P((12, 160, 224), ("periodic", "neumann", "periodic"), model="schnakenberg",
+      params={"a": 0.1, "b": 0.9, "gamma": 1.0}, D=(1.0, 10.0), k=1e-4, shift=W.SCHNAK_STEADY,
+      ic="gaussian_noise"),
+    P((224, 256), ("periodic", "dirichlet"), model="enzyme", params={}, D=(0.2,), k=0.05),
+    P((192, 7), ("neumann", "periodic"), model="cgl", params={"beta": 1.3}, D=(1.0, 1.0), k=0.05,
+      h=(0.5, 0.5)),
+]
+
 
 @pytest.mark.parametrize("prob", ONE_STEP, ids=lambda p: f"{p.model}-{'x'.join(map(str, p.shape))}")
 def test_one_step_matches_oracle(prob):
@@ -155,6 +169,20 @@ def test_one_step_matches_oracle(prob):
     got = gpu_run(prob, u0, 1)
     ref = oracle_run(prob, u0, 1)
     assert rel_l2(got, ref) < 1e-12, rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("prob", TWO_LINE, ids=lambda p: f"{p.model}-{'x'.join(map(str, p.shape))}")
+def test_two_lines_per_wave_matches_oracle(prob):
+    e = make(prob, lines_per_wave=2)
+    names = [e.pass_kernel(p) for p in range(1, len(prob.shape) + 1)]
+    e.close()
+    assert any(nm.endswith(", 2>") for nm in names), names
+    u0 = prob.initial()
+    got = gpu_run(prob, u0, 2, lines_per_wave=2)
+    ref = oracle_run(prob, u0, 2)
+    assert rel_l2(got, ref) < 1e-12, rel_l2(got, ref)
+    one = gpu_run(prob, u0, 2, lines_per_wave=1)
+    assert rel_l2(got, one) < 1e-13, rel_l2(got, one)
 
 
 def test_brusselator2d_100_steps_full_size():
@@ -173,10 +201,11 @@ def test_grayscott3d_100_steps_small():
     assert rel_l2(got, ref) < 1e-10, rel_l2(got, ref)
 
 
-def test_etd1_predictor_matches_oracle():
-    prob = P((48, 40, 20), ("neumann", "periodic", "dirichlet"))
+@pytest.mark.parametrize("shape,lpw", [((48, 40, 20), "auto"), ((160, 12, 224), 2)])
+def test_etd1_predictor_matches_oracle(shape, lpw):
+    prob = P(shape, ("neumann", "periodic", "dirichlet"))
     u0 = prob.initial()
-    got = gpu_run(prob, u0, 1, scheme="etd1")
+    got = gpu_run(prob, u0, 1, scheme="etd1", lines_per_wave=lpw)
     ref = O.etd1_if_step(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params())
     assert rel_l2(got, ref) < 1e-12
 
