@@ -188,12 +188,16 @@ constexpr int kBlockLines = 8;
 
 // Copy the per-lane parts of `nt` consecutive tables into LDS.  All threads
 // of the block call it; a barrier must follow before use.
+// With W < 64 only the first W entries of every array are copied.
+template <int W = kLanes>
 __device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tabs, int nt,
-                                                LaneTab* dst) {
-  constexpr int W = sizeof(LaneTab) / sizeof(double);
-  for (int i = threadIdx.x; i < nt * W; i += blockDim.x) {
-    const int t = i / W, j = i - t * W;
-    reinterpret_cast<double*>(dst + t)[j] = reinterpret_cast<const double*>(&tabs[t].lane)[j];
+                                                LaneTabT<W>* dst) {
+  constexpr int E = kLaneTabRows * W;  // doubles per staged table
+  for (int i = threadIdx.x; i < nt * E; i += blockDim.x) {
+    const int t = i / E, j = i - t * E;
+    const int row = j / W, col = j - row * W;
+    reinterpret_cast<double*>(dst + t)[j] =
+        reinterpret_cast<const double*>(&tabs[t].lane)[row * kLanes + col];
   }
 }
 
@@ -203,7 +207,7 @@ __device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tab
 // in LDS).  All 64 lanes must call it together.
 template <int M, int K, int P = 1>
 __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
-                                           const LaneTab* const (&lt)[K],
+                                           const LaneTabT<kSegLanes<P>>* const (&lt)[K],
                                            double (&x)[K][M], int lane) {
   constexpr int Q = M - 1;
   // Chunk of this lane within its line (the per-lane table index).
@@ -595,16 +599,16 @@ __device__ __forceinline__ void store_chunk(double* __restrict__ p, const double
 
 // The tables of one axis: P (gamma 1), T (gamma 3), S (gamma 4) per species,
 // headers in global memory and per-lane parts staged in LDS.
-template <int S>
+template <int S, int W = kLanes>
 struct AxisTabs {
   const SolveTab* g;
-  const LaneTab* l;
+  const LaneTabT<W>* l;
   __device__ const SolveTab* P(int s) const { return g + tab_index(0, s, 0, S); }
   __device__ const SolveTab* T(int s) const { return g + tab_index(0, s, 1, S); }
   __device__ const SolveTab* Sx(int s) const { return g + tab_index(0, s, 2, S); }
-  __device__ const LaneTab* lP(int s) const { return l + tab_index(0, s, 0, S); }
-  __device__ const LaneTab* lT(int s) const { return l + tab_index(0, s, 1, S); }
-  __device__ const LaneTab* lS(int s) const { return l + tab_index(0, s, 2, S); }
+  __device__ const LaneTabT<W>* lP(int s) const { return l + tab_index(0, s, 0, S); }
+  __device__ const LaneTabT<W>* lT(int s) const { return l + tab_index(0, s, 1, S); }
+  __device__ const LaneTabT<W>* lS(int s) const { return l + tab_index(0, s, 2, S); }
 };
 
 }  // namespace etd

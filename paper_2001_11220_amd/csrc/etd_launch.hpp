@@ -7,7 +7,8 @@
 
 namespace etd {
 
-inline size_t lane_lds(int ntabs) { return sizeof(LaneTab) * (size_t)ntabs; }
+template <int W = kLanes>
+inline size_t lane_lds(int ntabs) { return sizeof(LaneTabT<W>) * (size_t)ntabs; }
 
 template <typename KernelT>
 hipError_t set_lds(KernelT kern, size_t bytes) {

@@ -222,11 +222,12 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
     const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
     double* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
   extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
-  stage_lane_tabs(tabs, 3 * S, lt);
+  using LT = LaneTabT<kSegLanes<P>>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  double* tl = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   const int first_phase = etd1 ? 2 : 0;
   TileCursor cur;
@@ -262,12 +263,12 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = x[0][j];
       const SolveTab* tb[1] = {at.P(sc)};
-      const LaneTab* lb[1] = {at.lP(sc)};
+      const LT* lb[1] = {at.lP(sc)};
       line_solve<M, 1, P>(tb, lb, y, lane);
       tile_store<M, L, P>(ow + sc * g.N, y[0], tl, g, pos, cur);
     } else {
       const SolveTab* tb[2] = {at.T(sc), at.Sx(sc)};
-      const LaneTab* lb[2] = {at.lT(sc), at.lS(sc)};
+      const LT* lb[2] = {at.lT(sc), at.lS(sc)};
       line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
@@ -302,11 +303,12 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
     int etd1) {
   extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
-  stage_lane_tabs(tabs, 3 * S, lt);
+  using LT = LaneTabT<kSegLanes<P>>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  double* tl = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
       for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], U[s][j]);
       {
         const SolveTab* tb[1] = {at.P(s)};
-        const LaneTab* lb[1] = {at.lP(s)};
+        const LT* lb[1] = {at.lP(s)};
         line_solve<M, 1, P>(tb, lb, y, lane);
         tile_store<M, L, P>(w + s * g.N, y[0], tl, g, pos, cur);
       }
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
           x[1][j] = x[0][j];
         }
         const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
-        const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
+        const LT* lb[2] = {at.lT(s), at.lS(s)};
         line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
         for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
@@ -360,11 +362,12 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
     PassGeom g, int etd1) {
   extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
-  stage_lane_tabs(tabs, 3 * S, lt);
+  using LT = LaneTabT<kSegLanes<P>>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  double* tl = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
   TileCursor cur;
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     for (int s = 0; s < S; ++s) line_load<M, P>(w + s * g.N, us[s], g, pos);
     {
       const SolveTab* tb[S];
-      const LaneTab* lb[S];
+      const LT* lb[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         tb[s] = at.P(s);
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
         x[1][j] = fma(k05, us[s][j], fma(k15, b[j], 8.0 * a));
       }
       const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
-      const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
+      const LT* lb[2] = {at.lT(s), at.lS(s)};
       line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) x[0][j] = x[0][j] - x[1][j];
@@ -732,7 +735,7 @@ constexpr int kStreamWaves = 16;
 template <int M, int S, int P>
 hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                           double* w, const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds(3 * S);
+  const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
   const size_t lds = pass_lds(g, fixed);
@@ -749,7 +752,7 @@ hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, dou
 template <int M, int S, int P>
 hipError_t launch_last_s(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
                          const double* w, const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds(3 * S);
+  const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassLast, fixed, L);
   const size_t lds = pass_lds(g, fixed);
@@ -790,7 +793,7 @@ template <int M, int S, int P>
 hipError_t launch_mid_s(const etd_rdp_ctx* c, const double* c1, const double* c2,
                         const double* w, double* o1, double* o2, double* ow,
                         const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds(3 * S);
+  const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassMid, fixed, L);
   const size_t lds = pass_lds(g, fixed);

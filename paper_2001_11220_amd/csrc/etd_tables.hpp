@@ -37,17 +37,22 @@ constexpr int kMaxM = 8;       // max rows per chunk
 constexpr int kLanes = 64;     // wavefront width
 constexpr int kMaxPcr = 6;     // log2(64)
 
-// Per-lane data of one line-solve operator, in the order a kernel copies it
-// into LDS (structure of arrays, index = lane = separator).
-struct LaneTab {
-  double k1[kMaxPcr][kLanes];  // PCR multipliers of the lane-s neighbour
-  double k2[kMaxPcr][kLanes];  // PCR multipliers of the lane+s neighbour
-  double inv[kLanes];          // 1 / reduced diagonal after the last step
-  double z[kLanes];            // Sherman-Morrison vector Mred'^{-1} u
-  double wl[kLanes];           // reduced-RHS weight of g_c[m-2]
-  double wr[kLanes];           // reduced-RHS weight of g_{c+1}[0]
-  double wg[kLanes];           // reduced-RHS weight of g_c[1] (lane 0 only)
+// Per-lane data of one line-solve operator (structure of arrays, index =
+// chunk = separator), for W chunks.  Tables hold W = 64; a kernel that solves
+// two lines of 32 chunks per wavefront copies the first 32 of every array
+// into LDS (LaneTabT<32>), the others all 64.
+template <int W>
+struct LaneTabT {
+  double k1[kMaxPcr][W];  // PCR multipliers of the lane-s neighbour
+  double k2[kMaxPcr][W];  // PCR multipliers of the lane+s neighbour
+  double inv[W];          // 1 / reduced diagonal after the last step
+  double z[W];            // Sherman-Morrison vector Mred'^{-1} u
+  double wl[W];           // reduced-RHS weight of g_c[m-2]
+  double wr[W];           // reduced-RHS weight of g_{c+1}[0]
+  double wg[W];           // reduced-RHS weight of g_c[1] (lane 0 only)
 };
+using LaneTab = LaneTabT<kLanes>;
+constexpr int kLaneTabRows = 2 * kMaxPcr + 5;  // arrays of W doubles in a LaneTabT
 
 // One line-solve operator (axis, species, gamma).  POD, 256-byte multiple,
 // copied verbatim to device memory.  The header fields are uniform across a
