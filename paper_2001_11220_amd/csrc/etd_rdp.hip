@@ -279,10 +279,9 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
 
 // ---------------------------------------------------------------------------
 // Pass 1, streamed: the work of k_first in phases of at most two solves per
-// species (T and S on U, T and S on f, P on U + k f), so that a 16-line tile
-// of long chunks fits the register budget.  Only U is kept; a species' f is
-// re-evaluated (pointwise) where a phase needs it.  Lines are read when a
-// tile starts.
+// species (P on U + k f, T and S on f, T and S on U), so that a 16- or
+// 32-line tile of long chunks fits the register budget.  Each species' pass
+// evaluates its f from the tile's lines of every species.
 // ---------------------------------------------------------------------------
 template <int S, int M>
 __device__ __forceinline__ void react_species(const Rx& rx, const double (&U)[S][M], int s,
@@ -312,19 +311,38 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
   const int lane = threadIdx.x & 63;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
-  int64_t tile;
-  while (walk.next(tile)) {
+  int64_t tile, next;
+  bool have = walk.next(tile);
+  // The first species' pass over a tile starts from lines fetched during the
+  // previous tile's last phase (when its U is no longer live); later species
+  // re-read the tile's lines (L2 hits).
+  double Un[S][M];
+  auto fetch = [&](int64_t t_) {
+    const TileAt p(t_, g);
+#pragma unroll
+    for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, Un[q], g, p);
+  };
+  if (have) fetch(tile);
+  while (have) {
     const TileAt pos(tile, g);
+    const bool have_next = walk.next(next);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      // The tile's lines of every species (the later species' reads hit L2).
       double U[S][M], f[M];
 #pragma unroll
-      for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, U[q], g, pos);
+      for (int q = 0; q < S; ++q) {
+        if (s == 0) {
+#pragma unroll
+          for (int j = 0; j < M; ++j) U[q][j] = Un[q][j];
+        } else {
+          line_load<M, P>(u + q * g.N, U[q], g, pos);
+        }
+      }
       react_species<S, M>(rx, U, s, f);
       double y[1][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], U[s][j]);
+      if (etd1 && s == S - 1 && have_next) fetch(next);
       {
         const SolveTab* tb[1] = {at.P(s)};
         const LT* lb[1] = {at.lP(s)};
@@ -340,6 +358,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
           x[0][j] = (r == 0) ? f[j] : U[s][j];
           x[1][j] = x[0][j];
         }
+        if (r == 1 && s == S - 1 && have_next) fetch(next);
         const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
         const LT* lb[2] = {at.lT(s), at.lS(s)};
         line_solve<M, 2, P>(tb, lb, x, lane);
@@ -348,6 +367,8 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
         tile_store<M, L, P>((r == 0 ? c2 : c1) + s * g.N, x[0], tl, g, pos, cur);
       }
     }
+    tile = next;
+    have = have_next;
   }
 }
 
