@@ -383,7 +383,7 @@ def bench_adjoint(args):
     adj_bytes = 31 * 8 * cs
     adj_gbs = adj_bytes / (adj_ms / 1e3) / 1e9
     print(f"[bench] gradient {ms:.1f} ms ({ms/steps:.3f} ms/step); forward alone {fwd_ms:.1f} ms; "
-          f"reverse step {adj_ms*1e3:.1f} us ({adj_gbs:.0f} GB/s algorithmic); loss={float(loss):.6e}",
+          f"reverse step {adj_ms*1e3:.1f} us ({adj_gbs:.0f} GB/s algorithmic); loss={float(loss.detach()):.6e}",
           file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline_adjoint()
     out = {
