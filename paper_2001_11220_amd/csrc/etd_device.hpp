@@ -536,8 +536,8 @@ __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M]
 
 // Transposed write of every wave's line chunks (all threads call it).  The
 // block has 64*L/P threads; in the write-out thread (col, q) moves rows
-// q*M .. q*M+M-1 of the tile's line col.
-template <int M, int L, int P = 1>
+// q*M .. q*M+M-1 of the tile's line col.  NT: non-temporal global stores.
+template <int M, int L, int P = 1, bool NT = false>
 __device__ __forceinline__ void tile_store(double* __restrict__ A, const double (&x)[M],
                                            double* lds, const PassGeom& g, const TileAt& p,
                                            TileCursor& cur) {
@@ -555,7 +555,14 @@ __device__ __forceinline__ void tile_store(double* __restrict__ A, const double 
   if (q < g.C && p.f0 + col < g.nF) {
     double* dst = A + p.f0 + col + p.t * g.outT + (int64_t)(q * M) * g.outRow;
 #pragma unroll
-    for (int i = 0; i < M; ++i) dst[i * g.outRow] = T[col * g.pitch + i * g.C + q];
+    for (int i = 0; i < M; ++i) {
+      const double v = T[col * g.pitch + i * g.C + q];
+      if constexpr (NT) {
+        __builtin_nontemporal_store(v, dst + i * g.outRow);
+      } else {
+        dst[i * g.outRow] = v;
+      }
+    }
   }
   if (g.nbuf == 1) __syncthreads();
   else cur.buf ^= 1;

@@ -49,7 +49,7 @@ namespace etd {
 // tile is solved (once this tile's U is no longer needed, so that the two
 // never occupy registers together).
 // ---------------------------------------------------------------------------
-template <int M, int S, int L>
+template <int M, int S, int L, bool NT>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
     const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
     double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
         const SolveTab* tb[1] = {at.P(s)};
         const LaneTab* lb[1] = {at.lP(s)};
         line_solve<M, 1>(tb, lb, x, lane);
-        tile_store<M, L>(w + s * g.N, x[0], tl, g, pos, cur);
+        tile_store<M, L, 1, NT>(w + s * g.N, x[0], tl, g, pos, cur);
         continue;
       }
       double x[5][M];
@@ -125,9 +125,9 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
         x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
         x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
       }
-      tile_store<M, L>(c1 + s * g.N, x[0], tl, g, pos, cur);
-      tile_store<M, L>(c2 + s * g.N, x[1], tl, g, pos, cur);
-      tile_store<M, L>(w + s * g.N, x[4], tl, g, pos, cur);
+      tile_store<M, L, 1, NT>(c1 + s * g.N, x[0], tl, g, pos, cur);
+      tile_store<M, L, 1, NT>(c2 + s * g.N, x[1], tl, g, pos, cur);
+      tile_store<M, L, 1, NT>(w + s * g.N, x[4], tl, g, pos, cur);
     }
   }
 }
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
 // next item's lines are fetched into registers while the current one is
 // solved.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L>
+template <int M, int S, int L, bool NT>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
     const double* __restrict__ c1, const double* __restrict__ c2,
     const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
       const SolveTab* tb[1] = {at.P(sc)};
       const LaneTab* lb[1] = {at.lP(sc)};
       line_solve<M, 1>(tb, lb, y, lane);
-      tile_store<M, L>(ow + sc * g.N, y[0], tl, g, pos, cur);
+      tile_store<M, L, 1, NT>(ow + sc * g.N, y[0], tl, g, pos, cur);
       continue;
     }
 #pragma unroll
@@ -203,9 +203,9 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
       x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
       x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
     }
-    tile_store<M, L>(o1 + sc * g.N, x[0], tl, g, pos, cur);
-    tile_store<M, L>(o2 + sc * g.N, x[1], tl, g, pos, cur);
-    tile_store<M, L>(ow + sc * g.N, x[4], tl, g, pos, cur);
+    tile_store<M, L, 1, NT>(o1 + sc * g.N, x[0], tl, g, pos, cur);
+    tile_store<M, L, 1, NT>(o2 + sc * g.N, x[1], tl, g, pos, cur);
+    tile_store<M, L, 1, NT>(ow + sc * g.N, x[4], tl, g, pos, cur);
   }
 }
 
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
 // current one is solved.  Fewer registers per wave than k_mid, for long
 // chunks.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, int P>
+template <int M, int S, int L, int P, bool NT>
 __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
     const double* __restrict__ c1, const double* __restrict__ c2,
     const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
@@ -265,14 +265,14 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
       const SolveTab* tb[1] = {at.P(sc)};
       const LT* lb[1] = {at.lP(sc)};
       line_solve<M, 1, P>(tb, lb, y, lane);
-      tile_store<M, L, P>(ow + sc * g.N, y[0], tl, g, pos, cur);
+      tile_store<M, L, P, NT>(ow + sc * g.N, y[0], tl, g, pos, cur);
     } else {
       const SolveTab* tb[2] = {at.T(sc), at.Sx(sc)};
       const LT* lb[2] = {at.lT(sc), at.lS(sc)};
       line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
-      tile_store<M, L, P>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
+      tile_store<M, L, P, NT>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
     }
   }
 }
@@ -296,7 +296,7 @@ __device__ __forceinline__ void react_species(const Rx& rx, const double (&U)[S]
   }
 }
 
-template <int M, int S, int L, int P>
+template <int M, int S, int L, int P, bool NT>
 __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
     double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
         const SolveTab* tb[1] = {at.P(s)};
         const LT* lb[1] = {at.lP(s)};
         line_solve<M, 1, P>(tb, lb, y, lane);
-        tile_store<M, L, P>(w + s * g.N, y[0], tl, g, pos, cur);
+        tile_store<M, L, P, NT>(w + s * g.N, y[0], tl, g, pos, cur);
       }
       if (etd1) continue;
 #pragma unroll
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
         line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
         for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
-        tile_store<M, L, P>((r == 0 ? c2 : c1) + s * g.N, x[0], tl, g, pos, cur);
+        tile_store<M, L, P, NT>((r == 0 ? c2 : c1) + s * g.N, x[0], tl, g, pos, cur);
       }
     }
     tile = next;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
 // species when they are used and no cross-tile prefetch, so that a 16-line
 // tile of long chunks fits the register budget.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, int P>
+template <int M, int S, int L, int P, bool NT>
 __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
     const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     }
     if (etd1) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M, L, P>(u + s * g.N, us[s], tl, g, pos, cur);
+      for (int s = 0; s < S; ++s) tile_store<M, L, P, NT>(u + s * g.N, us[s], tl, g, pos, cur);
       continue;
     }
 #pragma unroll
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
       line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) x[0][j] = x[0][j] - x[1][j];
-      tile_store<M, L, P>(u + s * g.N, x[0], tl, g, pos, cur);
+      tile_store<M, L, P, NT>(u + s * g.N, x[0], tl, g, pos, cur);
     }
   }
 }
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
 // all species; then c1, c2 of each species); each group is fetched into
 // registers one group ahead.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L>
+template <int M, int S, int L, bool NT>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
     double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
     const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
     }
     if (etd1) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M, L>(u + s * g.N, us[s], tl, g, pos, cur);
+      for (int s = 0; s < S; ++s) tile_store<M, L, 1, NT>(u + s * g.N, us[s], tl, g, pos, cur);
       continue;
     }
     // us holds U*; f* = F(U*) overwrites it.
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
       line_solve<M, 2>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
-      tile_store<M, L>(u + s * g.N, a, tl, g, pos, cur);
+      tile_store<M, L, 1, NT>(u + s * g.N, a, tl, g, pos, cur);
     }
   }
 }
@@ -752,37 +752,64 @@ constexpr int kStreamMidFrom = 5;
 constexpr int kStreamLastFrom = 5;
 constexpr int kStreamWaves = 16;
 
+// Carried arrays of at least kNtMinBytes are written with non-temporal
+// stores: the next pass reads them only after the whole array has streamed
+// through the caches, so keeping them there only evicts lines this pass
+// still reads (pass 1's second species re-reads its tile's lines).  Smaller
+// arrays stay cache-resident between passes.
+constexpr size_t kNtMinBytes = size_t(64) << 20;
+inline bool use_nt(const etd_rdp_ctx* c) {
+  return sizeof(double) * static_cast<size_t>(c->s) * static_cast<size_t>(c->N) >= kNtMinBytes;
+}
+
 // Launchers, templated on the chunk length and species count.
-template <int M, int S, int P>
+template <int M, int S, int P, bool NT>
 hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                           double* w, const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_first_s<M, S, L, P>, lds);
+  hipError_t e = set_lds(k_first_s<M, S, L, P, NT>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_first_s<M, S, L, P>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+  e = persistent_grid(k_first_s<M, S, L, P, NT>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_first_s<M, S, L, P>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
+  hipLaunchKernelGGL((k_first_s<M, S, L, P, NT>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
                      c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S, int P>
+template <int M, int S, int P, bool NT>
 hipError_t launch_last_s(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
                          const double* w, const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassLast, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_last_s<M, S, L, P>, lds);
+  hipError_t e = set_lds(k_last_s<M, S, L, P, NT>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_last_s<M, S, L, P>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+  e = persistent_grid(k_last_s<M, S, L, P, NT>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_last_s<M, S, L, P>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
+  hipLaunchKernelGGL((k_last_s<M, S, L, P, NT>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
+                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M, int S, bool NT>
+hipError_t launch_first_n(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
+                        double* w, const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds(3 * S);
+  constexpr int L = kLinesFor<M>;
+  const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_first<M, S, L, NT>, lds);
+  if (e != hipSuccess) return e;
+  unsigned grid;
+  e = persistent_grid(k_first<M, S, L, NT>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_first<M, S, L, NT>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
                      c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
@@ -790,27 +817,23 @@ hipError_t launch_last_s(const etd_rdp_ctx* c, double* u, const double* c1, cons
 template <int M, int S>
 hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
                         double* w, const SolveTab* tabs, hipStream_t st) {
+  // Non-temporal stores for large arrays (see use_nt).
+  const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
-    if (c->P[0] == 2) return launch_first_s<M, S, 2>(c, u, c1, c2, w, tabs, st);
+    if (c->P[0] == 2)
+      return nt ? launch_first_s<M, S, 2, true>(c, u, c1, c2, w, tabs, st)
+                : launch_first_s<M, S, 2, false>(c, u, c1, c2, w, tabs, st);
   }
   if constexpr (M >= kStreamFirstFrom) {
-    return launch_first_s<M, S, 1>(c, u, c1, c2, w, tabs, st);
+    return nt ? launch_first_s<M, S, 1, true>(c, u, c1, c2, w, tabs, st)
+              : launch_first_s<M, S, 1, false>(c, u, c1, c2, w, tabs, st);
+  } else {
+    return nt ? launch_first_n<M, S, true>(c, u, c1, c2, w, tabs, st)
+              : launch_first_n<M, S, false>(c, u, c1, c2, w, tabs, st);
   }
-  const size_t fixed = lane_lds(3 * S);
-  constexpr int L = kLinesFor<M>;
-  const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_first<M, S, L>, lds);
-  if (e != hipSuccess) return e;
-  unsigned grid;
-  e = persistent_grid(k_first<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_first<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
-                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
-  return hipGetLastError();
 }
 
-template <int M, int S, int P>
+template <int M, int S, int P, bool NT>
 hipError_t launch_mid_s(const etd_rdp_ctx* c, const double* c1, const double* c2,
                         const double* w, double* o1, double* o2, double* ow,
                         const SolveTab* tabs, hipStream_t st) {
@@ -818,13 +841,31 @@ hipError_t launch_mid_s(const etd_rdp_ctx* c, const double* c1, const double* c2
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassMid, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_mid_s<M, S, L, P>, lds);
+  hipError_t e = set_lds(k_mid_s<M, S, L, P, NT>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_mid_s<M, S, L, P>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+  e = persistent_grid(k_mid_s<M, S, L, P, NT>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid_s<M, S, L, P>), dim3(grid), dim3(64 * kStreamWaves), lds, st, c1, c2, w, o1, o2,
+  hipLaunchKernelGGL((k_mid_s<M, S, L, P, NT>), dim3(grid), dim3(64 * kStreamWaves), lds, st, c1, c2, w, o1, o2,
                      ow, tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int M, int S, bool NT>
+hipError_t launch_mid_n(const etd_rdp_ctx* c, const double* c1, const double* c2,
+                      const double* w, double* o1, double* o2, double* ow,
+                      const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds(3 * S);
+  constexpr int L = kLinesFor<M>;
+  const PassGeom g = pass_geom(c, kPassMid, fixed, L);
+  const size_t lds = pass_lds(g, fixed);
+  hipError_t e = set_lds(k_mid<M, S, L, NT>, lds);
+  if (e != hipSuccess) return e;
+  unsigned grid;
+  e = persistent_grid(k_mid<M, S, L, NT>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mid<M, S, L, NT>), dim3(grid), dim3(64 * L), lds, st, c1, c2, w, o1, o2, ow,
+                     tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -832,47 +873,56 @@ template <int M, int S>
 hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
                       const double* w, double* o1, double* o2, double* ow,
                       const SolveTab* tabs, hipStream_t st) {
+  // Non-temporal stores for large arrays (see use_nt).
+  const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
-    if (c->P[1] == 2) return launch_mid_s<M, S, 2>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    if (c->P[1] == 2)
+      return nt ? launch_mid_s<M, S, 2, true>(c, c1, c2, w, o1, o2, ow, tabs, st)
+                : launch_mid_s<M, S, 2, false>(c, c1, c2, w, o1, o2, ow, tabs, st);
   }
   if constexpr (M >= kStreamMidFrom) {
-    return launch_mid_s<M, S, 1>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    return nt ? launch_mid_s<M, S, 1, true>(c, c1, c2, w, o1, o2, ow, tabs, st)
+              : launch_mid_s<M, S, 1, false>(c, c1, c2, w, o1, o2, ow, tabs, st);
+  } else {
+    return nt ? launch_mid_n<M, S, true>(c, c1, c2, w, o1, o2, ow, tabs, st)
+              : launch_mid_n<M, S, false>(c, c1, c2, w, o1, o2, ow, tabs, st);
   }
+}
+
+template <int M, int S, bool NT>
+hipError_t launch_last_n(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
+                       const double* w, const SolveTab* tabs, hipStream_t st) {
   const size_t fixed = lane_lds(3 * S);
   constexpr int L = kLinesFor<M>;
-  const PassGeom g = pass_geom(c, kPassMid, fixed, L);
+  const PassGeom g = pass_geom(c, kPassLast, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_mid<M, S, L>, lds);
+  hipError_t e = set_lds(k_last<M, S, L, NT>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_mid<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  e = persistent_grid(k_last<M, S, L, NT>, lds, g.nFblk * g.nT, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<M, S, L>), dim3(grid), dim3(64 * L), lds, st, c1, c2, w, o1, o2, ow,
-                     tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  hipLaunchKernelGGL((k_last<M, S, L, NT>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int M, int S>
 hipError_t launch_last(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
                        const double* w, const SolveTab* tabs, hipStream_t st) {
+  // Non-temporal stores for large arrays (see use_nt).
+  const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
-    if (c->P[c->d - 1] == 2) return launch_last_s<M, S, 2>(c, u, c1, c2, w, tabs, st);
+    if (c->P[c->d - 1] == 2)
+      return nt ? launch_last_s<M, S, 2, true>(c, u, c1, c2, w, tabs, st)
+                : launch_last_s<M, S, 2, false>(c, u, c1, c2, w, tabs, st);
   }
   if constexpr (M >= kStreamLastFrom) {
-    return launch_last_s<M, S, 1>(c, u, c1, c2, w, tabs, st);
+    return nt ? launch_last_s<M, S, 1, true>(c, u, c1, c2, w, tabs, st)
+              : launch_last_s<M, S, 1, false>(c, u, c1, c2, w, tabs, st);
+  } else {
+    return nt ? launch_last_n<M, S, true>(c, u, c1, c2, w, tabs, st)
+              : launch_last_n<M, S, false>(c, u, c1, c2, w, tabs, st);
   }
-  const size_t fixed = lane_lds(3 * S);
-  constexpr int L = kLinesFor<M>;
-  const PassGeom g = pass_geom(c, kPassLast, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_last<M, S, L>, lds);
-  if (e != hipSuccess) return e;
-  unsigned grid;
-  e = persistent_grid(k_last<M, S, L>, lds, g.nFblk * g.nT, &grid, 64 * L);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_last<M, S, L>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
-                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
-  return hipGetLastError();
 }
 
 template <int M>
@@ -1149,9 +1199,11 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const bool streamed = (P == 2) || (first ? (m >= kStreamFirstFrom)
                                            : (last ? (m >= kStreamLastFrom) : (m >= kStreamMidFrom)));
   const char* base = first ? "k_first" : (last ? "k_last" : "k_mid");
-  const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d>", base, m, ctx->s,
-                                         kStreamWaves * P, P)
-                         : std::snprintf(name, size, "%s<%d, %d, %d>", base, m, ctx->s, lines_for(m));
+  const char* nt = use_nt(ctx) ? "true" : "false";
+  const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s>", base, m, ctx->s,
+                                         kStreamWaves * P, P, nt)
+                         : std::snprintf(name, size, "%s<%d, %d, %d, %s>", base, m, ctx->s,
+                                         lines_for(m), nt);
   return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
 }
 

@@ -176,7 +176,7 @@ def test_two_lines_per_wave_matches_oracle(prob):
     e = make(prob, lines_per_wave=2)
     names = [e.pass_kernel(p) for p in range(1, len(prob.shape) + 1)]
     e.close()
-    assert any(nm.endswith(", 2>") for nm in names), names
+    assert any("_s<" in nm and nm.split(", ")[3] == "2" for nm in names), names
     u0 = prob.initial()
     got = gpu_run(prob, u0, 2, lines_per_wave=2)
     ref = oracle_run(prob, u0, 2)
