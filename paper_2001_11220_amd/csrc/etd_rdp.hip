@@ -296,11 +296,10 @@ __device__ __forceinline__ void react_species(const Rx& rx, const double (&U)[S]
   }
 }
 
-template <int M, int S, int L, int P, bool NT>
+template <int M, int S, int L, int P, bool NT, bool E1>
 __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
-    double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
-    int etd1) {
+    double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g) {
   extern __shared__ double lds[];
   using LT = LaneTabT<kSegLanes<P>>;
   LT* lt = reinterpret_cast<LT*>(lds);
@@ -313,9 +312,11 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile, next;
   bool have = walk.next(tile);
-  // The first species' pass over a tile starts from lines fetched during the
-  // previous tile's last phase (when its U is no longer live); later species
-  // re-read the tile's lines (L2 hits).
+  // A tile's lines are fetched during the previous tile's last phase (when
+  // its U is no longer live; the last tile re-reads its own, unused, so that
+  // the buffer is dead between its uses); later species re-read the tile's
+  // lines (mostly from HBM: parking them in LDS instead cost the second tile
+  // buffer and measured slower).
   double Un[S][M];
   auto fetch = [&](int64_t t_) {
     const TileAt p(t_, g);
@@ -323,48 +324,58 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, Un[q], g, p);
   };
   if (have) fetch(tile);
+  // Phase helpers; with pre set, the lines of tile pf are fetched once the
+  // phase's right-hand side is built (every pass over a tile fetches once).
+  auto first_p_phase = [&](const double (&Us)[M], const double (&fs)[M], int s_,
+                           const TileAt& pos, bool pre, int64_t pf) {  // w = P_1 (U + k f)
+    double y[1][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) y[0][j] = fma(k, fs[j], Us[j]);
+    if (pre) fetch(pf);
+    const SolveTab* tb[1] = {at.P(s_)};
+    const LT* lb[1] = {at.lP(s_)};
+    line_solve<M, 1, P>(tb, lb, y, lane);
+    tile_store<M, L, P, NT>(w + s_ * g.N, y[0], tl, g, pos, cur);
+  };
+  auto first_rs_phase = [&](const double (&v)[M], int s_, double* out, const TileAt& pos,
+                            bool pre, int64_t pf) {  // out = R_1 v = 9 T_1 v - 8 S_1 v
+    double x[2][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[0][j] = v[j];
+      x[1][j] = v[j];
+    }
+    if (pre) fetch(pf);
+    const SolveTab* tb[2] = {at.T(s_), at.Sx(s_)};
+    const LT* lb[2] = {at.lT(s_), at.lS(s_)};
+    line_solve<M, 2, P>(tb, lb, x, lane);
+#pragma unroll
+    for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
+    tile_store<M, L, P, NT>(out + s_ * g.N, x[0], tl, g, pos, cur);
+  };
+  // The scheme (E1: the ETD1 predictor alone) is a template parameter, so
+  // that each scheme's phase sequence is allocated registers on its own.
   while (have) {
     const TileAt pos(tile, g);
     const bool have_next = walk.next(next);
+    double U[S][M];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int j = 0; j < M; ++j) U[q][j] = Un[q][j];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      double U[S][M], f[M];
+      if (s > 0) {
 #pragma unroll
-      for (int q = 0; q < S; ++q) {
-        if (s == 0) {
-#pragma unroll
-          for (int j = 0; j < M; ++j) U[q][j] = Un[q][j];
-        } else {
-          line_load<M, P>(u + q * g.N, U[q], g, pos);
-        }
+        for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, U[q], g, pos);
       }
+      double f[M];
       react_species<S, M>(rx, U, s, f);
-      double y[1][M];
-#pragma unroll
-      for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], U[s][j]);
-      if (etd1 && s == S - 1 && have_next) fetch(next);
-      {
-        const SolveTab* tb[1] = {at.P(s)};
-        const LT* lb[1] = {at.lP(s)};
-        line_solve<M, 1, P>(tb, lb, y, lane);
-        tile_store<M, L, P, NT>(w + s * g.N, y[0], tl, g, pos, cur);
-      }
-      if (etd1) continue;
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {  // R_1 f, then R_1 U
-        double x[2][M];
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          x[0][j] = (r == 0) ? f[j] : U[s][j];
-          x[1][j] = x[0][j];
-        }
-        if (r == 1 && s == S - 1 && have_next) fetch(next);
-        const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
-        const LT* lb[2] = {at.lT(s), at.lS(s)};
-        line_solve<M, 2, P>(tb, lb, x, lane);
-#pragma unroll
-        for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
-        tile_store<M, L, P, NT>((r == 0 ? c2 : c1) + s * g.N, x[0], tl, g, pos, cur);
+      const int64_t pf = have_next ? next : tile;
+      first_p_phase(U[s], f, s, pos, E1 && s == S - 1, pf);
+      if (!E1) {
+        first_rs_phase(f, s, c2, pos, false, pf);
+        first_rs_phase(U[s], s, c1, pos, s == S - 1, pf);
       }
     }
     tile = next;
@@ -770,14 +781,18 @@ hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, dou
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_first_s<M, S, L, P, NT>, lds);
-  if (e != hipSuccess) return e;
-  unsigned grid;
-  e = persistent_grid(k_first_s<M, S, L, P, NT>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_first_s<M, S, L, P, NT>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
-                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
-  return hipGetLastError();
+  auto go = [&](auto kern) {
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    unsigned grid;
+    e = persistent_grid(kern, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
+                       c->rx, c->k, g);
+    return hipGetLastError();
+  };
+  return (c->scheme == ETD_SCHEME_ETD1) ? go(k_first_s<M, S, L, P, NT, true>)
+                                        : go(k_first_s<M, S, L, P, NT, false>);
 }
 
 template <int M, int S, int P, bool NT>
@@ -1200,8 +1215,10 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
                                            : (last ? (m >= kStreamLastFrom) : (m >= kStreamMidFrom)));
   const char* base = first ? "k_first" : (last ? "k_last" : "k_mid");
   const char* nt = use_nt(ctx) ? "true" : "false";
-  const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s>", base, m, ctx->s,
-                                         kStreamWaves * P, P, nt)
+  // Streamed pass 1 also carries the scheme (true: the ETD1 predictor alone).
+  const char* e1 = first ? (ctx->scheme == ETD_SCHEME_ETD1 ? ", true" : ", false") : "";
+  const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s%s>", base, m, ctx->s,
+                                         kStreamWaves * P, P, nt, e1)
                          : std::snprintf(name, size, "%s<%d, %d, %d, %s>", base, m, ctx->s,
                                          lines_for(m), nt);
   return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
