@@ -1,10 +1,11 @@
 // Device building blocks of the ETD-RDP-IF passes for gfx950 (wave64).
 //
 //  * react<S>        pointwise reaction F(u) of the built-in models
-//  * line_solve<M,K> K simultaneous exact solves of (I + (k/gamma) D B_p) x = b
-//                    on grid lines held one per wavefront: lane c holds rows
-//                    [c*M, c*M+M) in registers (see etd_tables.hpp for the
-//                    chunk / separator elimination and its tables)
+//  * line_solve<M,K,P> K simultaneous exact solves of (I + (k/gamma) D B_p) x = b
+//                    on grid lines held one (or two) per wavefront: lane c
+//                    holds rows [c*M, c*M+M) of its line in registers (see
+//                    etd_tables.hpp for the chunk / separator elimination and
+//                    its tables)
 //  * TileWalk        XCD-aware persistent-block iteration over tiles
 //  * tile_load / tile_store  coalesced movement of the block's lines of a
 //                    strided axis between HBM and registers through LDS
@@ -201,10 +202,12 @@ __device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tab
   }
 }
 
-// K exact solves at once on this wavefront's line: x[k] holds this lane's
-// chunk of right-hand side k on entry and of the solution on exit, with
-// table tab[k] (header in global memory, uniform) and lt[k] (per-lane data
-// in LDS).  All 64 lanes must call it together.
+// K exact solves at once on this wavefront's line(s): x[k] holds this
+// lane's chunk of right-hand side k on entry and of the solution on exit,
+// with table tab[k] (header in global memory, uniform) and lt[k] (per-lane
+// data in LDS, indexed by the lane's chunk).  P lines per wavefront (1 or
+// 2; with 2, the table has exactly 32 chunks).  All 64 lanes must call it
+// together.
 template <int M, int K, int P = 1>
 __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
                                            const LaneTabT<kSegLanes<P>>* const (&lt)[K],

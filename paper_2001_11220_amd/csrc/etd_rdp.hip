@@ -134,9 +134,9 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
 
 // ---------------------------------------------------------------------------
 // Middle pass (3-D axis 2): purely linear, (c1, c2, w) -> (o1, o2, ow).
-// Tiles of 8 y-lines with adjacent z; work items are (tile, species) and the
-// next item's lines are fetched into registers while the current one is
-// solved.
+// Tiles of 8 or 16 y-lines with adjacent z; work items are (tile, species)
+// and the next item's lines are fetched into registers while the current one
+// is solved.
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, bool NT>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
@@ -385,8 +385,9 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
 
 // ---------------------------------------------------------------------------
 // Last pass, streamed: the work of k_last with the corrector inputs read per
-// species when they are used and no cross-tile prefetch, so that a 16-line
-// tile of long chunks fits the register budget.
+// species when they are used and no cross-tile prefetch (one measured no
+// faster), so that a 16- or 32-line tile of long chunks fits the register
+// budget.
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, int P, bool NT>
 __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
 
 // ---------------------------------------------------------------------------
 // Last pass (axis d): predictor solve, f*, corrector solves, new state.
-// Tiles of 8 lines with adjacent x.  Per tile the loads come in groups (w of
+// Tiles of 8 or 16 lines with adjacent x.  Per tile the loads come in groups (w of
 // all species; then c1, c2 of each species); each group is fetched into
 // registers one group ahead.
 // ---------------------------------------------------------------------------
