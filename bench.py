@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--pass-steps", type=int, default=50)
     ap.add_argument("--checkpoint-every", type=int, default=20,
                     help="gradient workload: steps between stored states")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
+                    help="arithmetic and storage type of the single-problem workloads")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -100,6 +102,9 @@ def main():
     from paper_2001_11220_amd import workloads as W
     from paper_2001_11220_amd.etd import EtdRdp
 
+    if args.precision != "f64" and args.workload in ("brusselator_ensemble", "schnakenberg3d_adjoint"):
+        print(f"bench.py: workload {args.workload} runs in f64 only", file=sys.stderr)
+        sys.exit(2)
     if args.workload == "brusselator_ensemble":
         if args.steps is None:
             args.steps = 200
@@ -112,8 +117,9 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     e = EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
-               shift=prob.shift, device=dev)
-    u = torch.from_numpy(prob.initial()).to(dev)
+               shift=prob.shift, device=dev, precision=args.precision)
+    esize = 8 if args.precision == "f64" else 4
+    u = torch.from_numpy(prob.initial()).to(dev, torch.float64 if esize == 8 else torch.float32)
     e.workspace()
     stream = torch.cuda.current_stream()
     print(f"[bench] {prob.name} shape={prob.shape} bcs={prob.bcs} ws={e.ws_bytes/2**30:.2f} GiB",
@@ -151,7 +157,7 @@ def main():
         b.record(stream)
         torch.cuda.synchronize()
         t_ms = a.elapsed_time(b) / args.pass_steps
-        byts = words[p - 1] * 8 * cs
+        byts = words[p - 1] * esize * cs
         per.append({"pass": p, "kernel": names[p - 1], "avg_ms": t_ms, "alg_bytes": byts,
                     "GBps": byts / (t_ms / 1e3) / 1e9})
         print(f"[bench] pass {p} ({names[p-1]}): {t_ms*1e3:.1f} us/launch, "
@@ -170,7 +176,7 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    step_bytes = sum(words) * 8 * cs
+    step_bytes = sum(words) * esize * cs
     roof = {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["kernel"],
             "pass": dom["pass"], "avg_launch_us": dom["avg_ms"] * 1e3,
@@ -193,7 +199,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.precision,
         "data": "synthetic (seeded initial data, no dataset)",
         "config": {"workload": prob.name, "grid": list(prob.shape), "bcs": list(prob.bcs),
                    "species": prob.s, "k": prob.k, "model": prob.model,

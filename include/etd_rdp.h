@@ -103,9 +103,20 @@ typedef struct etd_reaction_t {
 #define ETD_LINES_ONE 1    /* always one                                       */
 #define ETD_LINES_TWO 2    /* two wherever n allows                            */
 
+/* Element type of the state and of the carried arrays
+ * (etd_scheme_t.precision).  The line-solve tables are built and held in
+ * FP64 either way; an FP32 context converts them when its kernels load them.
+ * FP32 contexts step with etd_rdp_step_f32 / etd_rdp_run_pass_f32; the
+ * reverse-mode step, the single solves, debug_passes and the batch API are
+ * FP64 only (ETD_ERR_UNSUPPORTED). */
+#define ETD_PRECISION_F64 0
+#define ETD_PRECISION_F32 1
+
 typedef struct etd_scheme_t {
   int32_t scheme;                   /* ETD_SCHEME_RDP or ETD_SCHEME_ETD1     */
   int32_t lines_per_wave;           /* ETD_LINES_*; ignored by the batch API */
+  int32_t precision;                /* ETD_PRECISION_*                       */
+  int32_t reserved;                 /* must be 0                             */
 } etd_scheme_t;
 
 typedef struct etd_rdp_ctx etd_rdp_ctx;
@@ -127,7 +138,7 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  * n below the minimum of its BC (Dirichlet 1, Neumann 2, periodic 3), a
  * non-finite or non-positive h or k, a negative or non-finite D, an unknown
  * model or one whose species count differs from s, lines_per_wave not one of
- * ETD_LINES_*.  ETD_ERR_UNSUPPORTED when
+ * ETD_LINES_*, precision not one of ETD_PRECISION_*.  ETD_ERR_UNSUPPORTED when
  * a line length n cannot be split into at most 64 chunks of at most 8 rows
  * (n > 512, or n > 64 with no divisor m <= 8 such that n/m <= 64).
  * ETD_ERR_INTERNAL if a table self-check fails.
@@ -179,6 +190,17 @@ int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                  int64_t nsteps, void* stream);
 
 /*
+ * etd_rdp_step_f32 -- etd_rdp_step for a context created with
+ * ETD_PRECISION_F32: u holds s*N floats (same layout), the carried arrays
+ * are FP32 and every solve and reaction evaluation runs in FP32 arithmetic
+ * (tables converted from FP64).  The workspace size is
+ * etd_rdp_workspace_bytes of that context.  ETD_ERR_ARG if the context is
+ * FP64 (and etd_rdp_step returns ETD_ERR_ARG for an FP32 context).
+ */
+int etd_rdp_step_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes,
+                     int64_t nsteps, void* stream);
+
+/*
  * etd_rdp_debug_passes -- run only the first `npasses` passes (1..d) of one
  * step and stop, leaving the carried arrays in the workspace (see
  * etd_rdp_workspace_layout).  Pass 1's triple holds c1 = R_1 U,
@@ -200,6 +222,10 @@ int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws,
 int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                      int32_t pass, void* stream);
 
+/* etd_rdp_run_pass for an ETD_PRECISION_F32 context (u holds floats). */
+int etd_rdp_run_pass_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes,
+                         int32_t pass, void* stream);
+
 /*
  * etd_rdp_apply_solve -- x <- (I + (k/gamma) D_sigma A_axis)^{-1} x for a
  * single-species grid array x of N doubles (layout as one species of u),
@@ -217,7 +243,8 @@ const char* etd_rdp_status_string(int status);
 int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx);
 
 /* Name of the kernel pass `pass` (1..d) launches, as profilers print it
- * without the namespace and arguments (for example "k_mid<4, 2, 16>"),
+ * without the namespace and arguments (for example
+ * "k_mid_s<8, 2, 32, 2, true, double>"),
  * written NUL-terminated into name[0..size).  For reports.  Errors:
  * ETD_ERR_ARG (NULL, pass out of range, buffer too small). */
 int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name,

@@ -693,10 +693,10 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
   double* part = ws_array(c, ws, nY + 3);
   const int S = c->s;
   // Forward recompute of the carried triples.
-  int rc = launch_pass(c, 0, const_cast<double*>(u), A, A, tabs, st);
+  int rc = launch_pass<double>(c, 0, const_cast<double*>(u), A, A, tabs, st);
   if (rc) return rc;
   if (c->d == 3) {
-    rc = launch_pass(c, 1, nullptr, A, B, tabs, st);
+    rc = launch_pass<double>(c, 1, nullptr, A, B, tabs, st);
     if (rc) return rc;
   }
   unsigned nb[kAdjPasses] = {0, 0, 0};
@@ -757,7 +757,7 @@ int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1, 
                     double* grad, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !u_n || !lam_np1 || !lam_n || !grad) return ETD_ERR_ARG;
   if (u_n == lam_n) return ETD_ERR_ARG;
-  if (ctx->scheme != ETD_SCHEME_RDP) return ETD_ERR_UNSUPPORTED;
+  if (ctx->scheme != ETD_SCHEME_RDP || ctx->precision != ETD_PRECISION_F64) return ETD_ERR_UNSUPPORTED;
   int rc = check_ws(ws, ws_bytes, ctx->adj_ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);

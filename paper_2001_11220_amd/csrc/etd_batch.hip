@@ -420,6 +420,7 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s, int
   if (ws_ < 0 || (ws_ > 0 && ws_ != s)) return ETD_ERR_ARG;
   if (!(std::isfinite(k) && k > 0)) return ETD_ERR_ARG;
   const int sch = scheme ? scheme->scheme : ETD_SCHEME_RDP;
+  if (scheme && scheme->precision != ETD_PRECISION_F64) return ETD_ERR_UNSUPPORTED;
   if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
   etd_rdp_batch* b = new (std::nothrow) etd_rdp_batch();
   if (!b) return ETD_ERR_INTERNAL;

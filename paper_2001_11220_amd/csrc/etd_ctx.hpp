@@ -20,6 +20,7 @@ struct etd_rdp_ctx {
   double D[ETD_MAX_SPECIES] = {0, 0};
   double k = 0;
   int scheme = ETD_SCHEME_RDP;
+  int precision = ETD_PRECISION_F64;  // element type of u and the carried arrays
   etd::Rx rx{};
   int nparams = 0;             // reaction parameters with a gradient
   int m[3] = {0, 0, 0};         // chunk length of the forward passes' tables
@@ -40,6 +41,11 @@ struct etd_rdp_ctx {
 namespace etd {
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bytes of one state / carried-array element of a context.
+inline size_t elem_bytes(const etd_rdp_ctx* c) {
+  return c->precision == ETD_PRECISION_F32 ? sizeof(float) : sizeof(double);
+}
 
 // Two lines per wavefront: an axis whose lines are n = 32 m rows with
 // m in [kMinTwoLineM, kMaxM] runs its forward pass with 32 chunks of m rows
@@ -82,19 +88,23 @@ size_t geom_lds(const Geom& g, size_t fixed_lds);
 // Pass geometries of the single-problem stepper (see PassGeom), with the
 // forward passes' chunking or (one_line) the one-line-per-wavefront one.
 enum PassKind : int { kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3 };
+// esize: bytes per element of the tile buffers.
 PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines,
-                   bool one_line = false);
-size_t pass_lds(const PassGeom& g, size_t fixed_lds);
+                   bool one_line = false, size_t esize = sizeof(double));
+size_t pass_lds(const PassGeom& g, size_t fixed_lds, size_t esize = sizeof(double));
 
-// The i-th carried array (s*N doubles) of a workspace.
-inline double* ws_array(const etd_rdp_ctx* c, void* ws, int i) {
-  return reinterpret_cast<double*>(static_cast<char*>(ws) + c->tab_bytes + i * c->arr_bytes);
+// The i-th carried array (s*N elements) of a workspace.
+template <typename T = double>
+inline T* ws_array(const etd_rdp_ctx* c, void* ws, int i) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + c->tab_bytes + i * c->arr_bytes);
 }
 
 // Launches forward pass p (0-based) of one step.  Pass 0 reads u and writes
 // the carried triple `out`; a middle pass reads `in` and writes `out` (which
 // must not overlap); the last pass reads `in` and writes u.
-int launch_pass(etd_rdp_ctx* c, int p, double* u, double* const (&in)[3],
-                double* const (&out)[3], const SolveTab* tabs, hipStream_t st);
+// Instantiated for double and float (the context's precision).
+template <typename T>
+int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[3],
+                const SolveTab* tabs, hipStream_t st);
 
 }  // namespace etd

@@ -34,45 +34,44 @@ struct Rx {
 };
 
 // F(u + shift) at one cell.  The model id is uniform across the launch.
-template <int S>
-__device__ __forceinline__ void react(const Rx& rx, const double (&uin)[S],
-                                      double (&f)[S]) {
-  double u[S];
+template <int S, typename T = double>
+__device__ __forceinline__ void react(const Rx& rx, const T (&uin)[S], T (&f)[S]) {
+  T u[S];
 #pragma unroll
-  for (int i = 0; i < S; ++i) u[i] = uin[i] + rx.shift[i];
+  for (int i = 0; i < S; ++i) u[i] = uin[i] + static_cast<T>(rx.shift[i]);
   if (rx.model == kLinear) {
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      double acc = 0.0;
+      T acc = 0;
 #pragma unroll
-      for (int j = 0; j < S; ++j) acc = fma(rx.p[i * S + j], u[j], acc);
+      for (int j = 0; j < S; ++j) acc = fma(static_cast<T>(rx.p[i * S + j]), u[j], acc);
       f[i] = acc;
     }
     return;
   }
   if constexpr (S == 1) {
     // Michaelis-Menten enzyme kinetics: -u / (1 + u).
-    f[0] = -u[0] / (1.0 + u[0]);
+    f[0] = -u[0] / (T(1) + u[0]);
   } else {
-    const double a = u[0], b = u[1];
+    const T a = u[0], b = u[1];
     if (rx.model == kBrusselator) {
-      const double A = rx.p[0], B = rx.p[1];
-      const double aab = a * a * b;
-      f[0] = A - (B + 1.0) * a + aab;
+      const T A = static_cast<T>(rx.p[0]), B = static_cast<T>(rx.p[1]);
+      const T aab = a * a * b;
+      f[0] = A - (B + T(1)) * a + aab;
       f[1] = B * a - aab;
     } else if (rx.model == kGrayScott) {
-      const double F = rx.p[0], kap = rx.p[1];
-      const double abb = a * b * b;
-      f[0] = -abb + F * (1.0 - a);
+      const T F = static_cast<T>(rx.p[0]), kap = static_cast<T>(rx.p[1]);
+      const T abb = a * b * b;
+      f[0] = -abb + F * (T(1) - a);
       f[1] = abb - (F + kap) * b;
     } else if (rx.model == kSchnakenberg) {
-      const double A = rx.p[0], B = rx.p[1], g = rx.p[2];
-      const double aab = a * a * b;
+      const T A = static_cast<T>(rx.p[0]), B = static_cast<T>(rx.p[1]), g = static_cast<T>(rx.p[2]);
+      const T aab = a * a * b;
       f[0] = g * (A - a + aab);
       f[1] = g * (B - aab);
     } else {  // complex Ginzburg-Landau, alpha = 0, (Re, Im)
-      const double beta = rx.p[0];
-      const double m2 = a * a + b * b;
+      const T beta = static_cast<T>(rx.p[0]);
+      const T m2 = a * a + b * b;
       f[0] = a - (a - beta * b) * m2;
       f[1] = b - (b + beta * a) * m2;
     }
@@ -159,6 +158,36 @@ __device__ __forceinline__ double rows_swap16(double v, bool odd_row) {
                           static_cast<int>(odd_row ? lo[0] : lo[1]));
 }
 
+// The same moves for 32-bit values (single precision): one instruction each.
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ float bperm(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ float from_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ void halves_swap(float v, float& up, float& dn) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  up = __uint_as_float(r[0]);
+  dn = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void quarters_shift(float v, bool row1, bool row2, float& up,
+                                               float& dn) {
+  unsigned d;
+  const unsigned u = shift16_half(__float_as_uint(v), row1, row2, d);
+  up = __uint_as_float(u);
+  dn = __uint_as_float(d);
+}
+__device__ __forceinline__ float rows_swap16(float v, bool odd_row) {
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(odd_row ? q[0] : q[1]);
+}
+
 // Lines per wavefront.  With P = 1 a wavefront solves one line, lane c
 // holding chunk c.  With P = 2 it solves two lines of exactly 32 chunks
 // each: lane c holds chunk c % 32 of the wavefront's line c / 32 (its
@@ -168,14 +197,14 @@ template <int P>
 constexpr int kSegLanes = 64 / P;
 
 // Value of v in lane idx of this lane's segment (idx uniform).
-template <int P>
-__device__ __forceinline__ double seg_value(double v, int idx, int lane) {
+template <int P, typename T>
+__device__ __forceinline__ T seg_value(T v, int idx, int lane) {
   if constexpr (P == 1) {
     return lane_value(v, idx);
   } else {
     static_assert(P == 2, "one or two lines per wavefront");
-    const double a = lane_value(v, idx);
-    const double b = lane_value(v, kSegLanes<P> + idx);
+    const T a = lane_value(v, idx);
+    const T b = lane_value(v, kSegLanes<P> + idx);
     return (lane >= kSegLanes<P>) ? b : a;
   }
 }
@@ -189,16 +218,17 @@ constexpr int kBlockLines = 8;
 
 // Copy the per-lane parts of `nt` consecutive tables into LDS.  All threads
 // of the block call it; a barrier must follow before use.
-// With W < 64 only the first W entries of every array are copied.
-template <int W = kLanes>
+// With W < 64 only the first W entries of every array are copied; values
+// are converted to the element type T.
+template <int W = kLanes, typename T = double>
 __device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tabs, int nt,
-                                                LaneTabT<W>* dst) {
-  constexpr int E = kLaneTabRows * W;  // doubles per staged table
+                                                LaneTabT<W, T>* dst) {
+  constexpr int E = kLaneTabRows * W;  // values per staged table
   for (int i = threadIdx.x; i < nt * E; i += blockDim.x) {
     const int t = i / E, j = i - t * E;
     const int row = j / W, col = j - row * W;
-    reinterpret_cast<double*>(dst + t)[j] =
-        reinterpret_cast<const double*>(&tabs[t].lane)[row * kLanes + col];
+    reinterpret_cast<T*>(dst + t)[j] =
+        static_cast<T>(reinterpret_cast<const double*>(&tabs[t].lane)[row * kLanes + col]);
   }
 }
 
@@ -208,10 +238,10 @@ __device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tab
 // data in LDS, indexed by the lane's chunk).  P lines per wavefront (1 or
 // 2; with 2, the table has exactly 32 chunks).  All 64 lanes must call it
 // together.
-template <int M, int K, int P = 1>
+template <int M, int K, int P = 1, typename T = double>
 __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
-                                           const LaneTabT<kSegLanes<P>>* const (&lt)[K],
-                                           double (&x)[K][M], int lane) {
+                                           const LaneTabT<kSegLanes<P>, T>* const (&lt)[K],
+                                           T (&x)[K][M], int lane) {
   constexpr int Q = M - 1;
   // Chunk of this lane within its line (the per-lane table index).
   const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
@@ -220,7 +250,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   // at a time.  The reduced-RHS weights, which differ on the first and last
   // lane, are per-lane LDS data.
   struct Hdr {
-    double ip[Q > 0 ? Q : 1], cp[Q > 0 ? Q : 1], r;
+    T ip[Q > 0 ? Q : 1], cp[Q > 0 ? Q : 1], r;
   } h[K];
   const int z0 = opaque_zero();
 #pragma unroll
@@ -228,10 +258,10 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
     const SolveTab* t = tab[k] + z0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      h[k].ip[j] = t->ip[j];
-      h[k].cp[j] = t->cp[j];
+      h[k].ip[j] = static_cast<T>(t->ip[j]);
+      h[k].cp[j] = static_cast<T>(t->cp[j]);
     }
-    h[k].r = t->r;
+    h[k].r = static_cast<T>(t->r);
   }
   const int C = (tab[0] + z0)->C;
   const int npcr = (tab[0] + z0)->npcr;
@@ -239,7 +269,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if constexpr (Q > 0) {
-      double y = x[k][0] * h[k].ip[0];
+      T y = x[k][0] * h[k].ip[0];
       x[k][0] = y;
 #pragma unroll
       for (int j = 1; j < Q; ++j) {
@@ -255,12 +285,12 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   // periodic closure).
   const int lane4 = lane * 4;
   const int a_next = (c + 1 == C) ? (lane - c) * 4 : lane4 + 4;
-  double d[K];
+  T d[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double v = x[k][M - 1];
+    T v = x[k][M - 1];
     if constexpr (Q > 0) {
-      const double gn = bperm(a_next, x[k][0]);
+      const T gn = bperm(a_next, x[k][0]);
       v = fma(lt[k]->wl[c], x[k][Q - 1], v);
       v = fma(lt[k]->wr[c], gn, v);
     }
@@ -275,8 +305,8 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   if (npcr > 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const double dm = from_prev(d[k]);
-      const double dp = from_next(d[k]);
+      const T dm = from_prev(d[k]);
+      const T dp = from_next(d[k]);
       d[k] = d[k] - lt[k]->k1[0][c] * dm - lt[k]->k2[0][c] * dp;
     }
   }
@@ -287,8 +317,8 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       const int a_dn = (lane4 + (4 << st)) & 255;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double dm = bperm(a_up, d[k]);
-        const double dp = bperm(a_dn, d[k]);
+        const T dm = bperm(a_up, d[k]);
+        const T dp = bperm(a_dn, d[k]);
         d[k] = d[k] - lt[k]->k1[st][c] * dm - lt[k]->k2[st][c] * dp;
       }
     }
@@ -298,7 +328,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       const bool row1 = (lane >> 4) == 1, row2 = (lane >> 4) == 2;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        double dm, dp;
+        T dm, dp;
         quarters_shift(d[k], row1, row2, dm, dp);
         d[k] = d[k] - lt[k]->k1[kMaxPcr - 2][c] * dm - lt[k]->k2[kMaxPcr - 2][c] * dp;
       }
@@ -306,7 +336,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
       const bool odd_row = ((lane >> 4) & 1) != 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double dx = rows_swap16(d[k], odd_row);
+        const T dx = rows_swap16(d[k], odd_row);
         d[k] = d[k] - lt[k]->k1[kMaxPcr - 2][c] * dx - lt[k]->k2[kMaxPcr - 2][c] * dx;
       }
     }
@@ -314,7 +344,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   if (P == 1 && npcr > kMaxPcr - 1) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      double dm, dp;
+      T dm, dp;
       halves_swap(d[k], dm, dp);
       d[k] = d[k] - lt[k]->k1[kMaxPcr - 1][c] * dm - lt[k]->k2[kMaxPcr - 1][c] * dp;
     }
@@ -325,20 +355,21 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const SolveTab* t = tab[k] + z1;
-    double s = d[k] * lt[k]->inv[c];
+    T s = d[k] * lt[k]->inv[c];
     if (t->sm) {
-      const double vy = seg_value<P>(s, 0, lane) + t->vfac * seg_value<P>(s, C - 1, lane);
-      s = fma(-vy * t->smfac, lt[k]->z[c], s);
+      const T vy = seg_value<P>(s, 0, lane) + static_cast<T>(t->vfac) * seg_value<P>(s, C - 1, lane);
+      s = fma(-vy * static_cast<T>(t->smfac), lt[k]->z[c], s);
     }
     // The shift runs on all lanes before the select: under a branch that
     // masked off lane 0, lane 1 would read an inactive lane.
-    const double sprev = from_prev(s);
-    const double slast = seg_value<P>(s, C - 1, lane);
-    double ghost = fma(t->gh0, s, t->ghw * slast);
-    if constexpr (Q > 1) ghost = fma(t->ghd, x[k][1], ghost);
-    const double sl = (c == 0) ? ghost : sprev;
+    const T sprev = from_prev(s);
+    const T slast = seg_value<P>(s, C - 1, lane);
+    T ghost = fma(static_cast<T>(t->gh0), s, static_cast<T>(t->ghw) * slast);
+    if constexpr (Q > 1) ghost = fma(static_cast<T>(t->ghd), x[k][1], ghost);
+    const T sl = (c == 0) ? ghost : sprev;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) x[k][j] = fma(sl, t->al[j], fma(s, t->be[j], x[k][j]));
+    for (int j = 0; j < Q; ++j)
+      x[k][j] = fma(sl, static_cast<T>(t->al[j]), fma(s, static_cast<T>(t->be[j]), x[k][j]));
     x[k][M - 1] = s;
   }
 }
@@ -461,8 +492,8 @@ struct TilePos {
   }
 };
 
-template <int M>
-__device__ __forceinline__ void load_chunk(const double* __restrict__ p, double (&v)[M], bool act);
+template <int M, typename T>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ p, T (&v)[M], bool act);
 
 // Geometry of one pass of the single-problem stepper.  Each pass reads the
 // lines it solves contiguously and writes its outputs transposed, in the
@@ -490,14 +521,14 @@ struct TileAt {
 // This lane's chunk of its line read directly; zeros for a line past nF or
 // a lane without a chunk.  Wavefront w holds lines f0 + w*P .. f0 + w*P + P-1
 // of the tile (one per segment).
-template <int M, int P = 1>
-__device__ __forceinline__ void line_load(const double* __restrict__ A, double (&v)[M],
+template <int M, int P = 1, typename T = double>
+__device__ __forceinline__ void line_load(const T* __restrict__ A, T (&v)[M],
                                           const PassGeom& g, const TileAt& p) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
   const int64_t f = p.f0 + w * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
   const bool ok = (c < g.C) && (f < g.nF);
-  const double* src = ok ? A + f * g.inF + p.t * g.inT + (int64_t)c * M : A;
+  const T* src = ok ? A + f * g.inF + p.t * g.inT + (int64_t)c * M : A;
   load_chunk<M>(src, v, ok);
 }
 
@@ -540,26 +571,26 @@ __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M]
 // Transposed write of every wave's line chunks (all threads call it).  The
 // block has 64*L/P threads; in the write-out thread (col, q) moves rows
 // q*M .. q*M+M-1 of the tile's line col.  NT: non-temporal global stores.
-template <int M, int L, int P = 1, bool NT = false>
-__device__ __forceinline__ void tile_store(double* __restrict__ A, const double (&x)[M],
-                                           double* lds, const PassGeom& g, const TileAt& p,
+template <int M, int L, int P = 1, bool NT = false, typename T = double>
+__device__ __forceinline__ void tile_store(T* __restrict__ A, const T (&x)[M],
+                                           T* lds, const PassGeom& g, const TileAt& p,
                                            TileCursor& cur) {
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
   const int li = w * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
-  double* T = lds + cur.buf * g.tile;
+  T* B = lds + cur.buf * g.tile;
   if (c < g.C) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) T[li * g.pitch + j * g.C + c] = x[j];
+    for (int j = 0; j < M; ++j) B[li * g.pitch + j * g.C + c] = x[j];
   }
   __syncthreads();
   const int col = tid & (L - 1), q = tid / L;
   if (q < g.C && p.f0 + col < g.nF) {
-    double* dst = A + p.f0 + col + p.t * g.outT + (int64_t)(q * M) * g.outRow;
+    T* dst = A + p.f0 + col + p.t * g.outT + (int64_t)(q * M) * g.outRow;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      const double v = T[col * g.pitch + i * g.C + q];
+      const T v = B[col * g.pitch + i * g.C + q];
       if constexpr (NT) {
         __builtin_nontemporal_store(v, dst + i * g.outRow);
       } else {
@@ -579,9 +610,29 @@ __host__ __device__ inline int tab_index(int axis0, int sigma, int slot, int S) 
   return (axis0 * S + sigma) * 3 + slot;
 }
 
-template <int M>
-__device__ __forceinline__ void load_chunk(const double* __restrict__ p, double (&v)[M], bool act) {
-  if constexpr (M % 2 == 0) {
+// A lane's chunk of M consecutive values, with 16-byte loads where the chunk
+// length allows (chunk offsets and line starts are multiples of M).
+template <int M, typename T>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ p, T (&v)[M], bool act) {
+  if constexpr (sizeof(T) == 4 && M % 4 == 0) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int j = 0; j < M / 4; ++j) {
+      const float4 t = act ? q[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[4 * j] = t.x;
+      v[4 * j + 1] = t.y;
+      v[4 * j + 2] = t.z;
+      v[4 * j + 3] = t.w;
+    }
+  } else if constexpr (sizeof(T) == 4 && M % 2 == 0) {
+    const float2* q = reinterpret_cast<const float2*>(p);
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) {
+      const float2 t = act ? q[j] : make_float2(0.f, 0.f);
+      v[2 * j] = t.x;
+      v[2 * j + 1] = t.y;
+    }
+  } else if constexpr (sizeof(T) == 8 && M % 2 == 0) {
     const double2* q = reinterpret_cast<const double2*>(p);
 #pragma unroll
     for (int j = 0; j < M / 2; ++j) {
@@ -591,13 +642,13 @@ __device__ __forceinline__ void load_chunk(const double* __restrict__ p, double 
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = act ? p[j] : 0.0;
+    for (int j = 0; j < M; ++j) v[j] = act ? p[j] : T(0);
   }
 }
 
-template <int M>
-__device__ __forceinline__ void store_chunk(double* __restrict__ p, const double (&v)[M]) {
-  if constexpr (M % 2 == 0) {
+template <int M, typename T>
+__device__ __forceinline__ void store_chunk(T* __restrict__ p, const T (&v)[M]) {
+  if constexpr (sizeof(T) == 8 && M % 2 == 0) {
     double2* q = reinterpret_cast<double2*>(p);
 #pragma unroll
     for (int j = 0; j < M / 2; ++j) q[j] = make_double2(v[2 * j], v[2 * j + 1]);
@@ -609,16 +660,16 @@ __device__ __forceinline__ void store_chunk(double* __restrict__ p, const double
 
 // The tables of one axis: P (gamma 1), T (gamma 3), S (gamma 4) per species,
 // headers in global memory and per-lane parts staged in LDS.
-template <int S, int W = kLanes>
+template <int S, int W = kLanes, typename E = double>
 struct AxisTabs {
   const SolveTab* g;
-  const LaneTabT<W>* l;
+  const LaneTabT<W, E>* l;
   __device__ const SolveTab* P(int s) const { return g + tab_index(0, s, 0, S); }
   __device__ const SolveTab* T(int s) const { return g + tab_index(0, s, 1, S); }
   __device__ const SolveTab* Sx(int s) const { return g + tab_index(0, s, 2, S); }
-  __device__ const LaneTabT<W>* lP(int s) const { return l + tab_index(0, s, 0, S); }
-  __device__ const LaneTabT<W>* lT(int s) const { return l + tab_index(0, s, 1, S); }
-  __device__ const LaneTabT<W>* lS(int s) const { return l + tab_index(0, s, 2, S); }
+  __device__ const LaneTabT<W, E>* lP(int s) const { return l + tab_index(0, s, 0, S); }
+  __device__ const LaneTabT<W, E>* lT(int s) const { return l + tab_index(0, s, 1, S); }
+  __device__ const LaneTabT<W, E>* lS(int s) const { return l + tab_index(0, s, 2, S); }
 };
 
 }  // namespace etd

@@ -7,8 +7,8 @@
 
 namespace etd {
 
-template <int W = kLanes>
-inline size_t lane_lds(int ntabs) { return sizeof(LaneTabT<W>) * (size_t)ntabs; }
+template <int W = kLanes, typename T = double>
+inline size_t lane_lds(int ntabs) { return sizeof(LaneTabT<W, T>) * (size_t)ntabs; }
 
 template <typename KernelT>
 hipError_t set_lds(KernelT kern, size_t bytes) {
@@ -62,9 +62,9 @@ inline int tile_pitch(int n) { return n + ((8 - n % 32) + 32) % 32; }
 // Tile buffers: two (one barrier per move) when they fit beside the fixed
 // LDS: in half the LDS for 8-line blocks (two blocks per CU), in all of it
 // for 16-line blocks (their register budget allows one block per CU).
-inline int tile_buffers(size_t fixed_lds, int lines, int tile_doubles) {
+inline int tile_buffers(size_t fixed_lds, int lines, int tile_elems, size_t elem_bytes = 8) {
   const size_t cap = (lines >= 16) ? kLdsMax : kLdsMax / 2;
-  return (fixed_lds + 2 * sizeof(double) * (size_t)tile_doubles <= cap) ? 2 : 1;
+  return (fixed_lds + 2 * elem_bytes * (size_t)tile_elems <= cap) ? 2 : 1;
 }
 
 // Runtime (m, s) -> template dispatch.

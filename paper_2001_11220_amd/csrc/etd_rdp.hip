@@ -49,23 +49,25 @@ namespace etd {
 // tile is solved (once this tile's U is no longer needed, so that the two
 // never occupy registers together).
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, bool NT>
+template <int M, int S, int L, bool NT, typename T>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
-    const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
-    double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
+    const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
+    T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k, PassGeom g,
     int etd1) {
-  extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kLanes, T>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   stage_lane_tabs(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kLanes, T> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   bool have = walk.next(tile);
-  double Un[S][M];
+  T Un[S][M];
   auto fetch = [&](int64_t tl_) {
     const TileAt p(tl_, g);
 #pragma unroll
@@ -74,14 +76,14 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
   if (have) fetch(tile);
   while (have) {
     const TileAt pos(tile, g);
-    double U[S][M], f[S][M];
+    T U[S][M], f[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
       for (int j = 0; j < M; ++j) U[s][j] = Un[s][j];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double uu[S], ff[S];
+      T uu[S], ff[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) uu[s] = U[s][j];
       react<S>(rx, uu, ff);
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       if (etd1) {
-        double x[1][M];
+        T x[1][M];
 #pragma unroll
         for (int j = 0; j < M; ++j) x[0][j] = fma(k, f[s][j], U[s][j]);
         if (s == S - 1) {
@@ -99,12 +101,12 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
           if (have) fetch(tile);
         }
         const SolveTab* tb[1] = {at.P(s)};
-        const LaneTab* lb[1] = {at.lP(s)};
+        const LT* lb[1] = {at.lP(s)};
         line_solve<M, 1>(tb, lb, x, lane);
         tile_store<M, L, 1, NT>(w + s * g.N, x[0], tl, g, pos, cur);
         continue;
       }
-      double x[5][M];
+      T x[5][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         x[0][j] = U[s][j];
@@ -118,12 +120,12 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
         if (have) fetch(tile);
       }
       const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
-      const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
+      const LT* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
       line_solve<M, 5>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
-        x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
+        x[0][j] = T(9) * x[0][j] - T(8) * x[2][j];
+        x[1][j] = T(9) * x[1][j] - T(8) * x[3][j];
       }
       tile_store<M, L, 1, NT>(c1 + s * g.N, x[0], tl, g, pos, cur);
       tile_store<M, L, 1, NT>(c2 + s * g.N, x[1], tl, g, pos, cur);
@@ -138,24 +140,26 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
 // and the next item's lines are fetched into registers while the current one
 // is solved.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, bool NT>
+template <int M, int S, int L, bool NT, typename T>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
-    const double* __restrict__ c1, const double* __restrict__ c2,
-    const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
-    double* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
-  extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+    const T* __restrict__ c1, const T* __restrict__ c2,
+    const T* __restrict__ w, T* __restrict__ o1, T* __restrict__ o2,
+    T* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kLanes, T>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   stage_lane_tabs(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kLanes, T> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   bool have = walk.next(tile);
   int s = 0;
-  double pf[3][M];
+  T pf[3][M];
   auto fetch = [&](int64_t tl_, int s_) {
     const TileAt p(tl_, g);
     if (!etd1) {
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
   while (have) {
     const TileAt pos(tile, g);
     const int sc = s;
-    double x[5][M];
+    T x[5][M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       x[0][j] = pf[0][j];
@@ -181,11 +185,11 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
     }
     if (have) fetch(tile, s);
     if (etd1) {
-      double y[1][M];
+      T y[1][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = x[4][j];
       const SolveTab* tb[1] = {at.P(sc)};
-      const LaneTab* lb[1] = {at.lP(sc)};
+      const LT* lb[1] = {at.lP(sc)};
       line_solve<M, 1>(tb, lb, y, lane);
       tile_store<M, L, 1, NT>(ow + sc * g.N, y[0], tl, g, pos, cur);
       continue;
@@ -196,12 +200,12 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
       x[3][j] = x[1][j];
     }
     const SolveTab* tb[5] = {at.T(sc), at.T(sc), at.Sx(sc), at.Sx(sc), at.P(sc)};
-    const LaneTab* lb[5] = {at.lT(sc), at.lT(sc), at.lS(sc), at.lS(sc), at.lP(sc)};
+    const LT* lb[5] = {at.lT(sc), at.lT(sc), at.lS(sc), at.lS(sc), at.lP(sc)};
     line_solve<M, 5>(tb, lb, x, lane);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
-      x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
+      x[0][j] = T(9) * x[0][j] - T(8) * x[2][j];
+      x[1][j] = T(9) * x[1][j] - T(8) * x[3][j];
     }
     tile_store<M, L, 1, NT>(o1 + sc * g.N, x[0], tl, g, pos, cur);
     tile_store<M, L, 1, NT>(o2 + sc * g.N, x[1], tl, g, pos, cur);
@@ -216,18 +220,19 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
 // current one is solved.  Fewer registers per wave than k_mid, for long
 // chunks.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, int P, bool NT>
+template <int M, int S, int L, int P, bool NT, typename T>
 __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
-    const double* __restrict__ c1, const double* __restrict__ c2,
-    const double* __restrict__ w, double* __restrict__ o1, double* __restrict__ o2,
-    double* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
-  extern __shared__ double lds[];
-  using LT = LaneTabT<kSegLanes<P>>;
+    const T* __restrict__ c1, const T* __restrict__ c2,
+    const T* __restrict__ w, T* __restrict__ o1, T* __restrict__ o2,
+    T* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kSegLanes<P>, T>;
   LT* lt = reinterpret_cast<LT*>(lds);
-  double* tl = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>, T> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   const int first_phase = etd1 ? 2 : 0;
   TileCursor cur;
@@ -235,7 +240,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
   int64_t tile;
   bool have = walk.next(tile);
   int s = 0, ph = first_phase;
-  double pf[M];
+  T pf[M];
   auto src = [&](int ph_) { return ph_ == 0 ? c1 : (ph_ == 1 ? c2 : w); };
   auto fetch = [&](int64_t tl_, int s_, int ph_) {
     line_load<M, P>(src(ph_) + s_ * g.N, pf, g, TileAt(tl_, g));
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
   while (have) {
     const TileAt pos(tile, g);
     const int sc = s, pc = ph;
-    double x[2][M];
+    T x[2][M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       x[0][j] = pf[j];
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
     }
     if (have) fetch(tile, s, ph);
     if (pc == 2) {
-      double y[1][M];
+      T y[1][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = x[0][j];
       const SolveTab* tb[1] = {at.P(sc)};
@@ -271,7 +276,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
       const LT* lb[2] = {at.lT(sc), at.lS(sc)};
       line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
-      for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
+      for (int j = 0; j < M; ++j) x[0][j] = T(9) * x[0][j] - T(8) * x[1][j];
       tile_store<M, L, P, NT>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
     }
   }
@@ -283,12 +288,12 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
 // 32-line tile of long chunks fits the register budget.  Each species' pass
 // evaluates its f from the tile's lines of every species.
 // ---------------------------------------------------------------------------
-template <int S, int M>
-__device__ __forceinline__ void react_species(const Rx& rx, const double (&U)[S][M], int s,
-                                              double (&f)[M]) {
+template <int S, int M, typename T>
+__device__ __forceinline__ void react_species(const Rx& rx, const T (&U)[S][M], int s,
+                                              T (&f)[M]) {
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    double uu[S], ff[S];
+    T uu[S], ff[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) uu[q] = U[q][j];
     react<S>(rx, uu, ff);
@@ -296,17 +301,18 @@ __device__ __forceinline__ void react_species(const Rx& rx, const double (&U)[S]
   }
 }
 
-template <int M, int S, int L, int P, bool NT, bool E1>
+template <int M, int S, int L, int P, bool NT, bool E1, typename T>
 __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
-    const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
-    double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g) {
-  extern __shared__ double lds[];
-  using LT = LaneTabT<kSegLanes<P>>;
+    const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
+    T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k, PassGeom g) {
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kSegLanes<P>, T>;
   LT* lt = reinterpret_cast<LT*>(lds);
-  double* tl = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>, T> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
@@ -317,7 +323,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
   // the buffer is dead between its uses); later species re-read the tile's
   // lines (mostly from HBM: parking them in LDS instead cost the second tile
   // buffer and measured slower).
-  double Un[S][M];
+  T Un[S][M];
   auto fetch = [&](int64_t t_) {
     const TileAt p(t_, g);
 #pragma unroll
@@ -326,9 +332,9 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
   if (have) fetch(tile);
   // Phase helpers; with pre set, the lines of tile pf are fetched once the
   // phase's right-hand side is built (every pass over a tile fetches once).
-  auto first_p_phase = [&](const double (&Us)[M], const double (&fs)[M], int s_,
+  auto first_p_phase = [&](const T (&Us)[M], const T (&fs)[M], int s_,
                            const TileAt& pos, bool pre, int64_t pf) {  // w = P_1 (U + k f)
-    double y[1][M];
+    T y[1][M];
 #pragma unroll
     for (int j = 0; j < M; ++j) y[0][j] = fma(k, fs[j], Us[j]);
     if (pre) fetch(pf);
@@ -337,9 +343,9 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     line_solve<M, 1, P>(tb, lb, y, lane);
     tile_store<M, L, P, NT>(w + s_ * g.N, y[0], tl, g, pos, cur);
   };
-  auto first_rs_phase = [&](const double (&v)[M], int s_, double* out, const TileAt& pos,
+  auto first_rs_phase = [&](const T (&v)[M], int s_, T* out, const TileAt& pos,
                             bool pre, int64_t pf) {  // out = R_1 v = 9 T_1 v - 8 S_1 v
-    double x[2][M];
+    T x[2][M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       x[0][j] = v[j];
@@ -350,7 +356,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     const LT* lb[2] = {at.lT(s_), at.lS(s_)};
     line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
-    for (int j = 0; j < M; ++j) x[0][j] = 9.0 * x[0][j] - 8.0 * x[1][j];
+    for (int j = 0; j < M; ++j) x[0][j] = T(9) * x[0][j] - T(8) * x[1][j];
     tile_store<M, L, P, NT>(out + s_ * g.N, x[0], tl, g, pos, cur);
   };
   // The scheme (E1: the ETD1 predictor alone) is a template parameter, so
@@ -358,7 +364,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
   while (have) {
     const TileAt pos(tile, g);
     const bool have_next = walk.next(next);
-    double U[S][M];
+    T U[S][M];
 #pragma unroll
     for (int q = 0; q < S; ++q)
 #pragma unroll
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
 #pragma unroll
         for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, U[q], g, pos);
       }
-      double f[M];
+      T f[M];
       react_species<S, M>(rx, U, s, f);
       const int64_t pf = have_next ? next : tile;
       first_p_phase(U[s], f, s, pos, E1 && s == S - 1, pf);
@@ -389,26 +395,27 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
 // faster), so that a 16- or 32-line tile of long chunks fits the register
 // budget.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, int P, bool NT>
+template <int M, int S, int L, int P, bool NT, typename T>
 __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
-    double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
-    const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
+    T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
+    const T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k,
     PassGeom g, int etd1) {
-  extern __shared__ double lds[];
-  using LT = LaneTabT<kSegLanes<P>>;
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kSegLanes<P>, T>;
   LT* lt = reinterpret_cast<LT*>(lds);
-  double* tl = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>, T> at{tabs, lt};
   const int lane = threadIdx.x & 63;
-  const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
+  const T k2 = T(2) * k, k15 = T(1.5) * k, k05 = T(0.5) * k;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   while (walk.next(tile)) {
     const TileAt pos(tile, g);
-    double us[S][M];
+    T us[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s) line_load<M, P>(w + s * g.N, us[s], g, pos);
     {
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double uu[S], ff[S];
+      T uu[S], ff[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) uu[s] = us[s][j];
       react<S>(rx, uu, ff);
@@ -437,14 +444,14 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      double x[2][M], b[M];
+      T x[2][M], b[M];
       line_load<M, P>(c1 + s * g.N, x[0], g, pos);
       line_load<M, P>(c2 + s * g.N, b, g, pos);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const double a = x[0][j];
-        x[0][j] = fma(k, us[s][j], fma(k2, b[j], 9.0 * a));
-        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], 8.0 * a));
+        const T a = x[0][j];
+        x[0][j] = fma(k, us[s][j], fma(k2, b[j], T(9) * a));
+        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], T(8) * a));
       }
       const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
       const LT* lb[2] = {at.lT(s), at.lS(s)};
@@ -462,24 +469,26 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
 // all species; then c1, c2 of each species); each group is fetched into
 // registers one group ahead.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, bool NT>
+template <int M, int S, int L, bool NT, typename T>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
-    double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
-    const double* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, double k,
+    T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
+    const T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k,
     PassGeom g, int etd1) {
-  extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kLanes, T>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   stage_lane_tabs(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kLanes, T> at{tabs, lt};
   const int lane = threadIdx.x & 63;
-  const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
+  const T k2 = T(2) * k, k15 = T(1.5) * k, k05 = T(0.5) * k;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   bool have = walk.next(tile);
-  double pf[2][M];  // S <= 2
+  T pf[2][M];  // S <= 2
   auto fetch_w = [&](int64_t tl_) {
     const TileAt p(tl_, g);
 #pragma unroll
@@ -494,7 +503,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
   while (have) {
     const TileAt pos(tile, g);
     const int64_t tcur = tile;
-    double us[S][M];
+    T us[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -507,7 +516,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
     }
     {
       const SolveTab* tb[S];
-      const LaneTab* lb[S];
+      const LT* lb[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         tb[s] = at.P(s);
@@ -523,7 +532,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
     // us holds U*; f* = F(U*) overwrites it.
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double uu[S], ff[S];
+      T uu[S], ff[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) uu[s] = us[s][j];
       react<S>(rx, uu, ff);
@@ -532,7 +541,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      double a[M], b[M], x[2][M];
+      T a[M], b[M], x[2][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         a[j] = pf[0][j];
@@ -546,11 +555,11 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
       }
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        x[0][j] = fma(k, us[s][j], fma(k2, b[j], 9.0 * a[j]));
-        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], 8.0 * a[j]));
+        x[0][j] = fma(k, us[s][j], fma(k2, b[j], T(9) * a[j]));
+        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], T(8) * a[j]));
       }
       const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
-      const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
+      const LT* lb[2] = {at.lT(s), at.lS(s)};
       line_solve<M, 2>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
@@ -703,7 +712,8 @@ size_t geom_lds(const Geom& g, size_t fixed_lds) {
   return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
 }
 
-PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, bool one_line) {
+PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, bool one_line,
+                   size_t esize) {
   const int64_t n1 = c->n[0], n2 = c->n[1], n3 = (c->d == 3) ? c->n[2] : 1;
   PassGeom g{};
   g.N = c->N;
@@ -744,13 +754,13 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, 
   g.pitch = tile_pitch(g.n);
   g.lines = lines;
   g.tile = lines * g.pitch;
-  g.nbuf = tile_buffers(fixed_lds, lines, g.tile);
+  g.nbuf = tile_buffers(fixed_lds, lines, g.tile, esize);
   g.nFblk = (g.nF + lines - 1) / lines;
   return g;
 }
 
-size_t pass_lds(const PassGeom& g, size_t fixed_lds) {
-  return fixed_lds + sizeof(double) * (size_t)g.nbuf * g.tile;
+size_t pass_lds(const PassGeom& g, size_t fixed_lds, size_t esize) {
+  return fixed_lds + esize * (size_t)g.nbuf * g.tile;
 }
 
 namespace {
@@ -775,13 +785,13 @@ inline bool use_nt(const etd_rdp_ctx* c) {
 }
 
 // Launchers, templated on the chunk length and species count.
-template <int M, int S, int P, bool NT>
-hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
-                          double* w, const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
+template <int M, int S, int P, bool NT, typename T>
+hipError_t launch_first_s(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
+                          T* w, const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int L = kStreamWaves * P;
-  const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
+  const PassGeom g = pass_geom(c, kPassFirst, fixed, L, false, sizeof(T));
+  const size_t lds = pass_lds(g, fixed, sizeof(T));
   auto go = [&](auto kern) {
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
@@ -789,155 +799,155 @@ hipError_t launch_first_s(const etd_rdp_ctx* c, const double* u, double* c1, dou
     e = persistent_grid(kern, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
-                       c->rx, c->k, g);
+                       c->rx, static_cast<T>(c->k), g);
     return hipGetLastError();
   };
-  return (c->scheme == ETD_SCHEME_ETD1) ? go(k_first_s<M, S, L, P, NT, true>)
-                                        : go(k_first_s<M, S, L, P, NT, false>);
+  return (c->scheme == ETD_SCHEME_ETD1) ? go(k_first_s<M, S, L, P, NT, true, T>)
+                                        : go(k_first_s<M, S, L, P, NT, false, T>);
 }
 
-template <int M, int S, int P, bool NT>
-hipError_t launch_last_s(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
-                         const double* w, const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
+template <int M, int S, int P, bool NT, typename T>
+hipError_t launch_last_s(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
+                         const T* w, const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int L = kStreamWaves * P;
-  const PassGeom g = pass_geom(c, kPassLast, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_last_s<M, S, L, P, NT>, lds);
+  const PassGeom g = pass_geom(c, kPassLast, fixed, L, false, sizeof(T));
+  const size_t lds = pass_lds(g, fixed, sizeof(T));
+  hipError_t e = set_lds(k_last_s<M, S, L, P, NT, T>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_last_s<M, S, L, P, NT>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+  e = persistent_grid(k_last_s<M, S, L, P, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_last_s<M, S, L, P, NT>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
-                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  hipLaunchKernelGGL((k_last_s<M, S, L, P, NT, T>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
+                     c->rx, static_cast<T>(c->k), g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S, bool NT>
-hipError_t launch_first_n(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
-                        double* w, const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds(3 * S);
+template <int M, int S, bool NT, typename T>
+hipError_t launch_first_n(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
+                        T* w, const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds<kLanes, T>(3 * S);
   constexpr int L = kLinesFor<M>;
-  const PassGeom g = pass_geom(c, kPassFirst, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_first<M, S, L, NT>, lds);
+  const PassGeom g = pass_geom(c, kPassFirst, fixed, L, false, sizeof(T));
+  const size_t lds = pass_lds(g, fixed, sizeof(T));
+  hipError_t e = set_lds(k_first<M, S, L, NT, T>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_first<M, S, L, NT>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  e = persistent_grid(k_first<M, S, L, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_first<M, S, L, NT>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
-                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  hipLaunchKernelGGL((k_first<M, S, L, NT, T>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+                     c->rx, static_cast<T>(c->k), g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S>
-hipError_t launch_first(const etd_rdp_ctx* c, const double* u, double* c1, double* c2,
-                        double* w, const SolveTab* tabs, hipStream_t st) {
+template <int M, int S, typename T>
+hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
+                        T* w, const SolveTab* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
     if (c->P[0] == 2)
-      return nt ? launch_first_s<M, S, 2, true>(c, u, c1, c2, w, tabs, st)
-                : launch_first_s<M, S, 2, false>(c, u, c1, c2, w, tabs, st);
+      return nt ? launch_first_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_first_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
   }
   if constexpr (M >= kStreamFirstFrom) {
-    return nt ? launch_first_s<M, S, 1, true>(c, u, c1, c2, w, tabs, st)
-              : launch_first_s<M, S, 1, false>(c, u, c1, c2, w, tabs, st);
+    return nt ? launch_first_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
+              : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
-    return nt ? launch_first_n<M, S, true>(c, u, c1, c2, w, tabs, st)
-              : launch_first_n<M, S, false>(c, u, c1, c2, w, tabs, st);
+    return nt ? launch_first_n<M, S, true, T>(c, u, c1, c2, w, tabs, st)
+              : launch_first_n<M, S, false, T>(c, u, c1, c2, w, tabs, st);
   }
 }
 
-template <int M, int S, int P, bool NT>
-hipError_t launch_mid_s(const etd_rdp_ctx* c, const double* c1, const double* c2,
-                        const double* w, double* o1, double* o2, double* ow,
+template <int M, int S, int P, bool NT, typename T>
+hipError_t launch_mid_s(const etd_rdp_ctx* c, const T* c1, const T* c2,
+                        const T* w, T* o1, T* o2, T* ow,
                         const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds<kSegLanes<P>>(3 * S);
+  const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int L = kStreamWaves * P;
-  const PassGeom g = pass_geom(c, kPassMid, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_mid_s<M, S, L, P, NT>, lds);
+  const PassGeom g = pass_geom(c, kPassMid, fixed, L, false, sizeof(T));
+  const size_t lds = pass_lds(g, fixed, sizeof(T));
+  hipError_t e = set_lds(k_mid_s<M, S, L, P, NT, T>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_mid_s<M, S, L, P, NT>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+  e = persistent_grid(k_mid_s<M, S, L, P, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid_s<M, S, L, P, NT>), dim3(grid), dim3(64 * kStreamWaves), lds, st, c1, c2, w, o1, o2,
+  hipLaunchKernelGGL((k_mid_s<M, S, L, P, NT, T>), dim3(grid), dim3(64 * kStreamWaves), lds, st, c1, c2, w, o1, o2,
                      ow, tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S, bool NT>
-hipError_t launch_mid_n(const etd_rdp_ctx* c, const double* c1, const double* c2,
-                      const double* w, double* o1, double* o2, double* ow,
+template <int M, int S, bool NT, typename T>
+hipError_t launch_mid_n(const etd_rdp_ctx* c, const T* c1, const T* c2,
+                      const T* w, T* o1, T* o2, T* ow,
                       const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds(3 * S);
+  const size_t fixed = lane_lds<kLanes, T>(3 * S);
   constexpr int L = kLinesFor<M>;
-  const PassGeom g = pass_geom(c, kPassMid, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_mid<M, S, L, NT>, lds);
+  const PassGeom g = pass_geom(c, kPassMid, fixed, L, false, sizeof(T));
+  const size_t lds = pass_lds(g, fixed, sizeof(T));
+  hipError_t e = set_lds(k_mid<M, S, L, NT, T>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_mid<M, S, L, NT>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  e = persistent_grid(k_mid<M, S, L, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<M, S, L, NT>), dim3(grid), dim3(64 * L), lds, st, c1, c2, w, o1, o2, ow,
+  hipLaunchKernelGGL((k_mid<M, S, L, NT, T>), dim3(grid), dim3(64 * L), lds, st, c1, c2, w, o1, o2, ow,
                      tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S>
-hipError_t launch_mid(const etd_rdp_ctx* c, const double* c1, const double* c2,
-                      const double* w, double* o1, double* o2, double* ow,
+template <int M, int S, typename T>
+hipError_t launch_mid(const etd_rdp_ctx* c, const T* c1, const T* c2,
+                      const T* w, T* o1, T* o2, T* ow,
                       const SolveTab* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
     if (c->P[1] == 2)
-      return nt ? launch_mid_s<M, S, 2, true>(c, c1, c2, w, o1, o2, ow, tabs, st)
-                : launch_mid_s<M, S, 2, false>(c, c1, c2, w, o1, o2, ow, tabs, st);
+      return nt ? launch_mid_s<M, S, 2, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
+                : launch_mid_s<M, S, 2, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
   }
   if constexpr (M >= kStreamMidFrom) {
-    return nt ? launch_mid_s<M, S, 1, true>(c, c1, c2, w, o1, o2, ow, tabs, st)
-              : launch_mid_s<M, S, 1, false>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    return nt ? launch_mid_s<M, S, 1, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
+              : launch_mid_s<M, S, 1, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
   } else {
-    return nt ? launch_mid_n<M, S, true>(c, c1, c2, w, o1, o2, ow, tabs, st)
-              : launch_mid_n<M, S, false>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    return nt ? launch_mid_n<M, S, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
+              : launch_mid_n<M, S, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
   }
 }
 
-template <int M, int S, bool NT>
-hipError_t launch_last_n(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
-                       const double* w, const SolveTab* tabs, hipStream_t st) {
-  const size_t fixed = lane_lds(3 * S);
+template <int M, int S, bool NT, typename T>
+hipError_t launch_last_n(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
+                       const T* w, const SolveTab* tabs, hipStream_t st) {
+  const size_t fixed = lane_lds<kLanes, T>(3 * S);
   constexpr int L = kLinesFor<M>;
-  const PassGeom g = pass_geom(c, kPassLast, fixed, L);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = set_lds(k_last<M, S, L, NT>, lds);
+  const PassGeom g = pass_geom(c, kPassLast, fixed, L, false, sizeof(T));
+  const size_t lds = pass_lds(g, fixed, sizeof(T));
+  hipError_t e = set_lds(k_last<M, S, L, NT, T>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_last<M, S, L, NT>, lds, g.nFblk * g.nT, &grid, 64 * L);
+  e = persistent_grid(k_last<M, S, L, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_last<M, S, L, NT>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
-                     c->rx, c->k, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
+  hipLaunchKernelGGL((k_last<M, S, L, NT, T>), dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs,
+                     c->rx, static_cast<T>(c->k), g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S>
-hipError_t launch_last(const etd_rdp_ctx* c, double* u, const double* c1, const double* c2,
-                       const double* w, const SolveTab* tabs, hipStream_t st) {
+template <int M, int S, typename T>
+hipError_t launch_last(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
+                       const T* w, const SolveTab* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
     if (c->P[c->d - 1] == 2)
-      return nt ? launch_last_s<M, S, 2, true>(c, u, c1, c2, w, tabs, st)
-                : launch_last_s<M, S, 2, false>(c, u, c1, c2, w, tabs, st);
+      return nt ? launch_last_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_last_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
   }
   if constexpr (M >= kStreamLastFrom) {
-    return nt ? launch_last_s<M, S, 1, true>(c, u, c1, c2, w, tabs, st)
-              : launch_last_s<M, S, 1, false>(c, u, c1, c2, w, tabs, st);
+    return nt ? launch_last_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
+              : launch_last_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
-    return nt ? launch_last_n<M, S, true>(c, u, c1, c2, w, tabs, st)
-              : launch_last_n<M, S, false>(c, u, c1, c2, w, tabs, st);
+    return nt ? launch_last_n<M, S, true, T>(c, u, c1, c2, w, tabs, st)
+              : launch_last_n<M, S, false, T>(c, u, c1, c2, w, tabs, st);
   }
 }
 
@@ -968,37 +978,43 @@ hipError_t launch_solve(const etd_rdp_ctx* c, double* x, const SolveTab* tab, in
 
 }  // namespace
 
-int launch_pass(etd_rdp_ctx* c, int p, double* u, double* const (&in)[3],
-                double* const (&out)[3], const SolveTab* tabs, hipStream_t st) {
+template <typename T>
+int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[3],
+                const SolveTab* tabs, hipStream_t st) {
   const int S = c->s;
   const SolveTab* ta = tabs + tab_index(p, 0, 0, S);
   const int m = c->m[p];
   hipError_t e = hipSuccess;
   if (p == 0) {
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1>(c, u, out[0], out[1], out[2], ta, st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2>(c, u, out[0], out[1], out[2], ta, st))); }
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2, T>(c, u, out[0], out[1], out[2], ta, st))); }
   } else if (p == c->d - 1) {
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1>(c, u, in[0], in[1], in[2], ta, st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2>(c, u, in[0], in[1], in[2], ta, st))); }
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2, T>(c, u, in[0], in[1], in[2], ta, st))); }
   } else {
     if (S == 1) {
-      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     } else {
-      ETD_DISPATCH_M(m, e = (launch_mid<M_, 2>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 2, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     }
   }
   if (e != hipSuccess) return hip_fail(c, e);
   return ETD_OK;
 }
+template int launch_pass<double>(etd_rdp_ctx*, int, double*, double* const (&)[3],
+                                 double* const (&)[3], const SolveTab*, hipStream_t);
+template int launch_pass<float>(etd_rdp_ctx*, int, float*, float* const (&)[3],
+                                float* const (&)[3], const SolveTab*, hipStream_t);
 
 namespace {
 
 // Passes first..npasses-1 of a step: pass 1 writes A, pass 2 (3-D) reads A
 // and writes B, pass d reads the last triple written.
-int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipStream_t st) {
+template <typename T>
+int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream_t st) {
   const SolveTab* tabs = static_cast<const SolveTab*>(ws);
-  double* const A[3] = {ws_array(c, ws, 0), ws_array(c, ws, 1), ws_array(c, ws, 2)};
-  double* const B[3] = {ws_array(c, ws, 3), ws_array(c, ws, 4), ws_array(c, ws, 5)};
+  T* const A[3] = {ws_array<T>(c, ws, 0), ws_array<T>(c, ws, 1), ws_array<T>(c, ws, 2)};
+  T* const B[3] = {ws_array<T>(c, ws, 3), ws_array<T>(c, ws, 4), ws_array<T>(c, ws, 5)};
   for (int p = first; p < npasses; ++p) {
     const bool into_b = (p == 1 && c->d == 3);
     const bool from_b = (p == 2);
@@ -1008,6 +1024,39 @@ int run_passes(etd_rdp_ctx* c, double* u, void* ws, int first, int npasses, hipS
   return ETD_OK;
 }
 
+}  // namespace
+}  // namespace etd
+
+namespace etd {
+namespace {
+template <typename T>
+int step_impl(etd_rdp_ctx* ctx, T* u, void* ws, size_t ws_bytes, int64_t nsteps, void* stream) {
+  if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;
+  if (elem_bytes(ctx) != sizeof(T)) return ETD_ERR_ARG;  // the context's precision
+  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
+  if (rc) return rc;
+  if (nsteps == 0) return ETD_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    rc = run_passes(ctx, u, ws, 0, ctx->d, st);
+    if (rc) return rc;
+  }
+  return ETD_OK;
+}
+
+template <typename T>
+int run_pass_impl(etd_rdp_ctx* ctx, T* u, void* ws, size_t ws_bytes, int32_t pass, void* stream) {
+  if (!ctx || !u || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
+  if (elem_bytes(ctx) != sizeof(T)) return ETD_ERR_ARG;
+  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  return run_passes(ctx, u, ws, pass - 1, pass, st);
+}
 }  // namespace
 }  // namespace etd
 
@@ -1039,6 +1088,9 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
   const int lpw = scheme ? scheme->lines_per_wave : ETD_LINES_AUTO;
   if (lpw != ETD_LINES_AUTO && lpw != ETD_LINES_ONE && lpw != ETD_LINES_TWO) return ETD_ERR_ARG;
+  const int prec = scheme ? scheme->precision : ETD_PRECISION_F64;
+  if (prec != ETD_PRECISION_F64 && prec != ETD_PRECISION_F32) return ETD_ERR_ARG;
+  if (scheme && scheme->reserved != 0) return ETD_ERR_ARG;
   for (int i = 0; i < s; ++i)
     if (!(std::isfinite(D[i]) && D[i] >= 0)) return ETD_ERR_ARG;
   for (int i = 0; i < ETD_MAX_PARAMS; ++i)
@@ -1052,6 +1104,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   c->s = s;
   c->k = k;
   c->scheme = sch;
+  c->precision = prec;
   int64_t N = 1;
   for (int i = 0; i < d; ++i) N *= grid->n[i];
   for (int i = 0; i < d; ++i) {
@@ -1102,7 +1155,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
           }
         }
   c->tab_bytes = round_up(c->tabs.size() * sizeof(SolveTab), 256);
-  c->arr_bytes = round_up(sizeof(double) * static_cast<size_t>(N) * s, 256);
+  c->arr_bytes = round_up(elem_bytes(c) * static_cast<size_t>(N) * s, 256);
   c->ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes;
   c->nparams = reaction_param_count(rx->model, s);
   c->part_bytes = round_up(sizeof(double) * kAdjPasses * kAdjMaxBlocks * kGradSlots, 256);
@@ -1150,25 +1203,21 @@ int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m, int32_t
   return ETD_OK;
 }
 
+
 int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int64_t nsteps,
                  void* stream) {
-  if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;
-  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
-  if (rc) return rc;
-  if (nsteps == 0) return ETD_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  rc = ensure_tables(ctx, ws, st);
-  if (rc) return rc;
-  for (int64_t i = 0; i < nsteps; ++i) {
-    rc = run_passes(ctx, u, ws, 0, ctx->d, st);
-    if (rc) return rc;
-  }
-  return ETD_OK;
+  return step_impl(ctx, u, ws, ws_bytes, nsteps, stream);
+}
+
+int etd_rdp_step_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes, int64_t nsteps,
+                     void* stream) {
+  return step_impl(ctx, u, ws, ws_bytes, nsteps, stream);
 }
 
 int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                          int32_t npasses, void* stream) {
   if (!ctx || !u || npasses < 1 || npasses > ctx->d) return ETD_ERR_ARG;
+  if (ctx->precision != ETD_PRECISION_F64) return ETD_ERR_UNSUPPORTED;
   int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1179,18 +1228,18 @@ int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
 
 int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int32_t pass,
                      void* stream) {
-  if (!ctx || !u || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
-  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
-  if (rc) return rc;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  rc = ensure_tables(ctx, ws, st);
-  if (rc) return rc;
-  return run_passes(ctx, u, ws, pass - 1, pass, st);
+  return run_pass_impl(ctx, u, ws, ws_bytes, pass, stream);
+}
+
+int etd_rdp_run_pass_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes, int32_t pass,
+                         void* stream) {
+  return run_pass_impl(ctx, u, ws, ws_bytes, pass, stream);
 }
 
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, int32_t axis,
                         int32_t sigma, int32_t gamma, void* stream) {
   if (!ctx || !x || axis < 1 || axis > ctx->d || sigma < 0 || sigma >= ctx->s) return ETD_ERR_ARG;
+  if (ctx->precision != ETD_PRECISION_F64) return ETD_ERR_UNSUPPORTED;
   const int slot = gamma == 1 ? 0 : (gamma == 3 ? 1 : (gamma == 4 ? 2 : -1));
   if (slot < 0) return ETD_ERR_ARG;
   int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
@@ -1218,10 +1267,11 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const char* nt = use_nt(ctx) ? "true" : "false";
   // Streamed pass 1 also carries the scheme (true: the ETD1 predictor alone).
   const char* e1 = first ? (ctx->scheme == ETD_SCHEME_ETD1 ? ", true" : ", false") : "";
-  const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s%s>", base, m, ctx->s,
-                                         kStreamWaves * P, P, nt, e1)
-                         : std::snprintf(name, size, "%s<%d, %d, %d, %s>", base, m, ctx->s,
-                                         lines_for(m), nt);
+  const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : "double";
+  const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s%s, %s>", base, m,
+                                         ctx->s, kStreamWaves * P, P, nt, e1, ty)
+                         : std::snprintf(name, size, "%s<%d, %d, %d, %s, %s>", base, m, ctx->s,
+                                         lines_for(m), nt, ty);
   return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
 }
 

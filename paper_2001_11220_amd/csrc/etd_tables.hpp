@@ -38,18 +38,19 @@ constexpr int kLanes = 64;     // wavefront width
 constexpr int kMaxPcr = 6;     // log2(64)
 
 // Per-lane data of one line-solve operator (structure of arrays, index =
-// chunk = separator), for W chunks.  Tables hold W = 64; a kernel that solves
-// two lines of 32 chunks per wavefront copies the first 32 of every array
-// into LDS (LaneTabT<32>), the others all 64.
-template <int W>
+// chunk = separator), for W chunks, in element type T.  Tables hold W = 64
+// FP64 values; a kernel that solves two lines of 32 chunks per wavefront
+// copies the first 32 of every array into LDS (LaneTabT<32>), the others all
+// 64, converted to the kernel's element type.
+template <int W, typename T = double>
 struct LaneTabT {
-  double k1[kMaxPcr][W];  // PCR multipliers of the lane-s neighbour
-  double k2[kMaxPcr][W];  // PCR multipliers of the lane+s neighbour
-  double inv[W];          // 1 / reduced diagonal after the last step
-  double z[W];            // Sherman-Morrison vector Mred'^{-1} u
-  double wl[W];           // reduced-RHS weight of g_c[m-2]
-  double wr[W];           // reduced-RHS weight of g_{c+1}[0]
-  double wg[W];           // reduced-RHS weight of g_c[1] (lane 0 only)
+  T k1[kMaxPcr][W];  // PCR multipliers of the lane-s neighbour
+  T k2[kMaxPcr][W];  // PCR multipliers of the lane+s neighbour
+  T inv[W];          // 1 / reduced diagonal after the last step
+  T z[W];            // Sherman-Morrison vector Mred'^{-1} u
+  T wl[W];           // reduced-RHS weight of g_c[m-2]
+  T wr[W];           // reduced-RHS weight of g_{c+1}[0]
+  T wg[W];           // reduced-RHS weight of g_c[1] (lane 0 only)
 };
 using LaneTab = LaneTabT<kLanes>;
 constexpr int kLaneTabRows = 2 * kMaxPcr + 5;  // arrays of W doubles in a LaneTabT

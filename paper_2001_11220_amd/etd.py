@@ -29,6 +29,7 @@ MODELS = {"linear": 0, "enzyme": 1, "brusselator": 2, "gray_scott": 3,
 MODEL_PARAMS = {"enzyme": (), "brusselator": ("a", "b"), "gray_scott": ("F", "kappa"),
                 "schnakenberg": ("a", "b", "gamma"), "cgl": ("beta",)}
 SCHEMES = {"rdp": 0, "etd1": 1}
+PRECISIONS = {"f64": 0, "f32": 1}
 
 MAX_DIM, MAX_SPECIES, MAX_PARAMS = 3, 2, 16
 
@@ -51,7 +52,8 @@ class Instance(ctypes.Structure):
 
 
 class Scheme(ctypes.Structure):
-    _fields_ = [("scheme", ctypes.c_int32), ("lines_per_wave", ctypes.c_int32)]
+    _fields_ = [("scheme", ctypes.c_int32), ("lines_per_wave", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class EtdError(RuntimeError):
@@ -73,8 +75,10 @@ def _load():
         "etd_rdp_workspace_layout": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ),
                                                     ctypes.POINTER(SZ), ctypes.POINTER(I64)]),
         "etd_rdp_step": (ctypes.c_int, [P, P, P, SZ, I64, P]),
+        "etd_rdp_step_f32": (ctypes.c_int, [P, P, P, SZ, I64, P]),
         "etd_rdp_debug_passes": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_run_pass": (ctypes.c_int, [P, P, P, SZ, I32, P]),
+        "etd_rdp_run_pass_f32": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_apply_solve": (ctypes.c_int, [P, P, P, SZ, I32, I32, I32, P]),
         "etd_rdp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "etd_rdp_last_hip_error": (ctypes.c_int, [P]),
@@ -136,10 +140,12 @@ class EtdRdp:
     tensors of shape ``(s, n_d, ..., n_1)`` on a HIP device.  ``h`` entries of
     0 (or ``None``) select the unit-domain spacing of each boundary condition.
     ``lines_per_wave`` is "auto", 1 or 2 (ETD_LINES_* of the C ABI).
+    ``precision`` "f32" makes the state and the carried arrays float32 (the
+    reverse-mode step and the single solves stay "f64" only).
     """
 
     def __init__(self, shape, bcs, D, k, model, params, h=None, shift=None,
-                 scheme="rdp", device=None, lines_per_wave="auto"):
+                 scheme="rdp", device=None, lines_per_wave="auto", precision="f64"):
         d = len(shape)
         s = len(D)
         g = Grid()
@@ -153,6 +159,8 @@ class EtdRdp:
         sch = Scheme()
         sch.scheme = SCHEMES[scheme]
         sch.lines_per_wave = 0 if lines_per_wave == "auto" else int(lines_per_wave)
+        sch.precision = PRECISIONS[precision]
+        self.precision = precision
         rx = reaction_struct(model, params, shift, s)
         ctx = ctypes.c_void_p()
         _check(lib.etd_rdp_init(ctypes.byref(g), bc_arr, D_arr, float(k), ctypes.byref(sch),
@@ -246,12 +254,17 @@ class EtdRdp:
         return m.value, c.value
 
     # -- compute ------------------------------------------------------------
-    def _state_ptr(self, u, nspecies):
+    def _state_ptr(self, u, nspecies, dtype=None):
         import torch
         want = (nspecies,) + self.shape[::-1]
-        if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous() or tuple(u.shape) != want:
-            raise ValueError(f"expected a contiguous float64 device tensor of shape {want}")
+        dt = dtype if dtype is not None else torch.float64
+        if u.dtype != dt or not u.is_cuda or not u.is_contiguous() or tuple(u.shape) != want:
+            raise ValueError(f"expected a contiguous {dt} device tensor of shape {want}")
         return u.data_ptr()
+
+    def _elem_dtype(self):
+        import torch
+        return torch.float32 if self.precision == "f32" else torch.float64
 
     @staticmethod
     def _stream(stream):
@@ -260,10 +273,13 @@ class EtdRdp:
         return ctypes.c_void_p(st.cuda_stream)
 
     def step(self, u, nsteps=1, stream=None):
-        """Advance ``u`` in place by ``nsteps`` steps (asynchronous)."""
-        p = self._state_ptr(u, self.s)
-        _check(lib.etd_rdp_step(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
-                                self.ws_bytes, int(nsteps), self._stream(stream)), "etd_rdp_step")
+        """Advance ``u`` in place by ``nsteps`` steps (asynchronous).  ``u`` is
+        float64, or float32 for a precision="f32" problem."""
+        p = self._state_ptr(u, self.s, self._elem_dtype())
+        fn, name = ((lib.etd_rdp_step_f32, "etd_rdp_step_f32") if self.precision == "f32"
+                    else (lib.etd_rdp_step, "etd_rdp_step"))
+        _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                  self.ws_bytes, int(nsteps), self._stream(stream)), name)
         return u
 
     def debug_passes(self, u, npasses, stream=None):
@@ -274,9 +290,11 @@ class EtdRdp:
 
     def run_pass(self, u, npass, stream=None):
         """Run pass ``npass`` (1..d) of a step alone (kernel timing)."""
-        p = self._state_ptr(u, self.s)
-        _check(lib.etd_rdp_run_pass(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
-                                    self.ws_bytes, int(npass), self._stream(stream)), "etd_rdp_run_pass")
+        p = self._state_ptr(u, self.s, self._elem_dtype())
+        fn, name = ((lib.etd_rdp_run_pass_f32, "etd_rdp_run_pass_f32") if self.precision == "f32"
+                    else (lib.etd_rdp_run_pass, "etd_rdp_run_pass"))
+        _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                  self.ws_bytes, int(npass), self._stream(stream)), name)
 
     def adjoint(self, u_n, lam, lam_out=None, grad=None, stream=None):
         """One reverse step: returns (dL/dU_n, grad) for lam = dL/dU_{n+1}.

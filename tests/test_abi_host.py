@@ -36,10 +36,11 @@ def test_library_exports_every_declared_symbol():
 
 
 def _init(shape, bcs, D=(0.1, 0.2), k=0.01, model="brusselator", params=None, h=None, scheme="rdp",
-          lines_per_wave="auto"):
+          lines_per_wave="auto", precision="f64"):
     etd = _lib()
     params = params if params is not None else {"a": 1.0, "b": 3.0}
-    return etd.EtdRdp(shape, bcs, D, k, model, params, h=h, scheme=scheme, lines_per_wave=lines_per_wave)
+    return etd.EtdRdp(shape, bcs, D, k, model, params, h=h, scheme=scheme, lines_per_wave=lines_per_wave,
+                      precision=precision)
 
 
 @pytest.mark.parametrize("bc", ["dirichlet", "neumann", "periodic"])
@@ -62,11 +63,11 @@ def test_lines_per_wave_option():
     # pass with at least 32768 lines
     big = _init((256, 256, 160), bcs)
     assert [big.line_split(a) for a in (1, 2, 3)] == [(8, 32), (8, 32), (5, 32)]
-    assert big.pass_kernel(1) == "k_first_s<8, 2, 32, 2, true, false>"
+    assert big.pass_kernel(1) == "k_first_s<8, 2, 32, 2, true, false, double>"
     small = _init((256, 12, 10), bcs)
-    assert small.line_split(1) == (4, 64) and small.pass_kernel(1) == "k_first<4, 2, 16, false>"
+    assert small.line_split(1) == (4, 64) and small.pass_kernel(1) == "k_first<4, 2, 16, false, double>"
     two = _init((256, 12, 10), bcs, lines_per_wave=2)
-    assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_s<8, 2, 32, 2, false, false>"
+    assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_s<8, 2, 32, 2, false, false, double>"
     assert two.line_split(2) == (1, 12)  # lengths that are not 32 m keep one line
     one = _init((256, 192, 160), bcs, lines_per_wave=1)
     assert [one.line_split(a) for a in (1, 2, 3)] == [(4, 64), (3, 64), (4, 40)]
@@ -76,6 +77,39 @@ def test_lines_per_wave_option():
         p.close()
     with pytest.raises(etd.EtdError):
         _init((64, 64), ("periodic",) * 2, lines_per_wave=3)
+
+
+def test_precision_option():
+    from paper_2001_11220_amd import etd
+    bcs = ("periodic", "neumann", "dirichlet")
+    d64 = _init((256, 256, 160), bcs)
+    f32 = _init((256, 256, 160), bcs, precision="f32")
+    assert d64.pass_kernel(2) == "k_mid_s<8, 2, 32, 2, true, double>"
+    # 2 x 10.5M floats = 84 MB per array: still above the non-temporal threshold
+    assert f32.pass_kernel(2) == "k_mid_s<8, 2, 32, 2, true, float>"
+    # the carried arrays halve; the FP64 tables are the same
+    n = 256 * 256 * 160 * 2
+    assert d64.ws_bytes - f32.ws_bytes == 6 * (8 - 4) * n
+    small = _init((64, 48), ("neumann", "periodic"), precision="f32")
+    assert small.pass_kernel(1) == "k_first<1, 2, 16, false, float>"
+    for p in (d64, f32, small):
+        p.close()
+    with pytest.raises(KeyError):
+        _init((64, 64), ("periodic",) * 2, precision="f16")
+    # the C ABI rejects unknown precision codes and a non-zero reserved field
+    sch = etd.Scheme()
+    for prec, res in ((2, 0), (0, 1)):
+        sch.precision, sch.reserved = prec, res
+        g = etd.Grid()
+        g.d, g.s = 2, 2
+        g.n[0], g.n[1] = 64, 64
+        bc = (ctypes.c_int32 * 3)(1, 1, 0)
+        D = (ctypes.c_double * 2)(0.1, 0.2)
+        rx = etd.reaction_struct("brusselator", {"a": 1.0, "b": 3.0}, None, 2)
+        ctx = ctypes.c_void_p()
+        rc = etd.lib.etd_rdp_init(ctypes.byref(g), bc, D, 0.01, ctypes.byref(sch), ctypes.byref(rx),
+                                  ctypes.byref(ctx))
+        assert rc == etd.ETD_ERR_ARG
 
 
 def test_tables_build_for_stiff_coefficients():
