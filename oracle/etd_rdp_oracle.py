@@ -18,6 +18,13 @@ independent 1-D solve along axis ``i`` with the per-species matrix
 lines are solved with LAPACK's banded Gaussian elimination
 (``scipy.linalg.solve_banded``); periodic lines are circulant and are solved
 by diagonalisation with the FFT, the route Section 7 itself describes.
+
+Complex species.  A complex scalar diffusion coefficient (the complex
+Ginzburg-Landau equation with alpha != 0, and the cubic Schroedinger
+equation, Section 8.3 and 8.4) is handled by the same functions with complex
+arrays: a complex state of shape ``(s, n_d, ..., n_1)`` and complex ``D``.
+The line systems ``I + (k/gamma) D_sigma B_p`` are then complex tridiagonal
+(or circulant), solved by the same banded elimination or FFT.
 """
 
 from __future__ import annotations
@@ -79,20 +86,23 @@ def line_matrix(n: int, bc: str, h: float, coef: float) -> np.ndarray:
     return np.eye(n) + coef * laplacian_matrix(n, bc, h)
 
 
-def _solve_lines(n: int, bc: str, h: float, coef: float, rhs: np.ndarray) -> np.ndarray:
-    """Solve ``(I + coef B_p) X = rhs`` for every column of ``rhs`` (n, m)."""
+def _solve_lines(n: int, bc: str, h: float, coef, rhs: np.ndarray) -> np.ndarray:
+    """Solve ``(I + coef B_p) X = rhs`` for every column of ``rhs`` (n, m);
+    ``coef`` and ``rhs`` may be complex."""
     if coef == 0.0:
         return rhs.copy()
+    real = not (np.iscomplexobj(rhs) or isinstance(coef, complex))
     if bc == BC_PERIODIC:
         # Circulant: first column (1 + 2rho, -rho, 0, ..., 0, -rho); its
         # eigenvalues are the DFT of that column (Section 7).
-        col = np.zeros(n)
+        col = np.zeros(n, dtype=np.float64 if real else np.complex128)
         col[0] = 1.0
         col += coef * laplacian_matrix(n, bc, h)[:, 0]
         lam = np.fft.fft(col)
-        return np.real(np.fft.ifft(np.fft.fft(rhs, axis=0) / lam[:, None], axis=0))
+        X = np.fft.ifft(np.fft.fft(rhs, axis=0) / lam[:, None], axis=0)
+        return np.real(X) if real else X
     M = line_matrix(n, bc, h, coef)
-    ab = np.zeros((3, n))
+    ab = np.zeros((3, n), dtype=M.dtype)
     ab[0, 1:] = np.diag(M, 1)
     ab[1, :] = np.diag(M)
     ab[2, :-1] = np.diag(M, -1)
@@ -105,12 +115,14 @@ def solve_axis(U: np.ndarray, axis: int, coefs, bc: str, h: float) -> np.ndarray
     every grid line and species, species ``sigma`` using ``coefs[sigma]``."""
     d = U.ndim - 1
     npax = d - axis + 1
-    out = np.empty_like(U)
+    cplx = np.iscomplexobj(U) or np.iscomplexobj(coefs)
+    out = np.empty(U.shape, dtype=np.complex128 if cplx else np.float64)
     n = U.shape[npax]
     for sigma in range(U.shape[0]):
         X = np.moveaxis(U[sigma], npax - 1, 0)
         shp = X.shape
-        Y = _solve_lines(n, bc, h, float(coefs[sigma]), X.reshape(n, -1))
+        cf = complex(coefs[sigma]) if cplx else float(coefs[sigma])
+        Y = _solve_lines(n, bc, h, cf, X.reshape(n, -1))
         out[sigma] = np.moveaxis(Y.reshape(shp), 0, npax - 1)
     return out
 
@@ -118,7 +130,7 @@ def solve_axis(U: np.ndarray, axis: int, coefs, bc: str, h: float) -> np.ndarray
 def apply_R(U, axis, k, D, bc, h):
     """``R_RDP(k A_axis) U = 9 T U - 8 S U`` with ``T = (I + k/3 A)^{-1}`` and
     ``S = (I + k/4 A)^{-1}`` (partial fractions of Section 6)."""
-    D = np.asarray(D, dtype=np.float64)
+    D = _coefs(D)
     T = solve_axis(U, axis, k * D / 3.0, bc, h)
     S = solve_axis(U, axis, k * D / 4.0, bc, h)
     return 9.0 * T - 8.0 * S
@@ -130,13 +142,13 @@ def apply_R(U, axis, k, D, bc, h):
 
 def r_rdp(z):
     """``R_RDP(z) = (1 - 5z/12) / ((1 + z/3)(1 + z/4))`` (eq. padenonlinear)."""
-    z = np.asarray(z, dtype=np.float64)
+    z = _coefs(z)
     return (1.0 - 5.0 * z / 12.0) / ((1.0 + z / 3.0) * (1.0 + z / 4.0))
 
 
 def r_pade01(z):
     """``R_01(z) = 1/(1 + z)`` (eq. pade01)."""
-    z = np.asarray(z, dtype=np.float64)
+    z = _coefs(z)
     return 1.0 / (1.0 + z)
 
 
@@ -187,12 +199,37 @@ def reaction(model: str, params: dict, U: np.ndarray) -> np.ndarray:
         p, q = U[0], U[1]
         m2 = p * p + q * q
         return np.stack([p - (p - beta * q) * m2, q - (q + beta * p) * m2])
+    if model == "cgl_z":
+        # Complex Ginzburg-Landau for a complex state, s = 1 (Section 8.3):
+        # f = u - (1 + i beta) u |u|^2; alpha enters through D = 1 + i alpha.
+        beta = params["beta"]
+        u = U
+        return u - (1.0 + 1j * beta) * u * (u * np.conj(u)).real
+    if model == "nls_z":
+        # Cubic Schroedinger equation i psi_t + Lap psi = q psi with
+        # q = B + C |psi|^2, written as psi_t = i Lap psi - i q psi
+        # (D = i, Section 8.4); B and C constant here.
+        B, C = params["B"], params["C"]
+        u = U
+        return -1j * (B + C * (u * np.conj(u)).real) * u
     raise ValueError(model)
 
 
 # ---------------------------------------------------------------------------
 # The ETD-RDP-IF step (Section 6, eq. donedone and the d-dimensional frame)
 # ---------------------------------------------------------------------------
+
+def _coefs(D):
+    """Diffusion coefficients as a float64 array, or complex128 when any is
+    complex."""
+    D = np.asarray(D)
+    return D.astype(np.complex128) if np.iscomplexobj(D) else D.astype(np.float64)
+
+
+def _state(U):
+    U = np.asarray(U)
+    return U.astype(np.complex128) if np.iscomplexobj(U) else U.astype(np.float64)
+
 
 def _check(U, D, bcs, hs):
     d = U.ndim - 1
@@ -219,8 +256,8 @@ def step_intermediates(U, k, D, bcs, hs, model, params):
     first term of ``f_2`` with the opposite sign, which is taken as a misprint
     (with D = 0 only this reading reduces to Heun's method).
     """
-    U = np.asarray(U, dtype=np.float64)
-    D = np.asarray(D, dtype=np.float64)
+    U = _state(U)
+    D = _coefs(D)
     _check(U, D, bcs, hs)
     d = U.ndim - 1
     out = {}
@@ -266,8 +303,8 @@ def etd_rdp_if_run(U, k, D, bcs, hs, model, params, nsteps):
 def etd1_if_step(U, k, D, bcs, hs, model, params):
     """First-order predictor alone (ETD1 = IMEX backward Euler with the same
     integrating-factor splitting, eq. duhamel3t with the Pade-(0,1) factor)."""
-    U = np.asarray(U, dtype=np.float64)
-    D = np.asarray(D, dtype=np.float64)
+    U = _state(U)
+    D = _coefs(D)
     _check(U, D, bcs, hs)
     y = U + k * reaction(model, params, U)
     for i in range(1, U.ndim):
