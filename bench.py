@@ -14,7 +14,8 @@ state, which is resident in HBM before timing starts.  Prints one JSON line.
                of one launch / its average duration.  Algorithmic bytes per
                cell-species: pass 1 reads U and writes c1, c2, w (4 words),
                a middle pass reads and writes all three (6 words), the last
-               pass reads three and writes U (4 words); 1 word = 8 bytes.
+               pass reads three and writes U (4 words); 1 word = 8 bytes
+               (4 with --precision f32, 16 for a complex species).
                step_effective_GBps is the same ratio for the whole step.
 * cpu_baseline the FP64 oracle on the host, one thread, on a bounded
                sample of the same workload (stated in "sample").
@@ -56,7 +57,7 @@ def cpu_baseline(name: str, budget_s: float = 12.0):
     from paper_2001_11220_amd import workloads as W
 
     sample_n = {"grayscott3d": 64, "schnakenberg3d": 64, "brusselator2d": 64,
-                "schnakenberg3d_adjoint": 64}[name]
+                "schnakenberg3d_adjoint": 64, "cgl3d_complex": 64}[name]
     prob = W.WORKLOADS[name](n=sample_n)
     u = prob.initial()
     cs = prob.cells * prob.s
@@ -116,10 +117,18 @@ def main():
         args.steps = prob.nsteps
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    prec = args.precision
+    if prob.is_complex:
+        if prec != "f64":
+            print(f"bench.py: workload {args.workload} runs in complex FP64 only", file=sys.stderr)
+            sys.exit(2)
+        prec = "c128"
     e = EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
-               shift=prob.shift, device=dev, precision=args.precision)
-    esize = 8 if args.precision == "f64" else 4
-    u = torch.from_numpy(prob.initial()).to(dev, torch.float64 if esize == 8 else torch.float32)
+               shift=prob.shift, device=dev, precision=prec)
+    esize = {"f64": 8, "f32": 4, "c128": 16}[prec]
+    u = torch.from_numpy(prob.initial()).to(dev)
+    if prec == "f32":
+        u = u.float()
     e.workspace()
     stream = torch.cuda.current_stream()
     print(f"[bench] {prob.name} shape={prob.shape} bcs={prob.bcs} ws={e.ws_bytes/2**30:.2f} GiB",
@@ -199,7 +208,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": prec,
         "data": "synthetic (seeded initial data, no dataset)",
         "config": {"workload": prob.name, "grid": list(prob.shape), "bcs": list(prob.bcs),
                    "species": prob.s, "k": prob.k, "model": prob.model,

@@ -68,6 +68,12 @@ extern "C" {
                                  g(b-u^2v)                                  */
 #define ETD_RX_CGL 5          /* s=2 (Re,Im), alpha=0: params beta:
                                  u - (1+i beta) u |u|^2        (Section 8.3) */
+/* Models of one complex species (ETD_PRECISION_C128 contexts only):        */
+#define ETD_RX_CGL_Z 6        /* s=1 complex, D = 1 + i alpha: params beta:
+                                 u - (1+i beta) u |u|^2        (Section 8.3) */
+#define ETD_RX_NLS_Z 7        /* s=1 complex, D = i (cubic Schroedinger
+                                 i u_t + Lap u = q u): params B, C:
+                                 F = -i (B + C |u|^2) u        (Section 8.4) */
 
 /* ---- time-stepping scheme --------------------------------------------- */
 #define ETD_SCHEME_RDP 0   /* ETD-RDP-IF, second order (Section 6)          */
@@ -111,6 +117,16 @@ typedef struct etd_reaction_t {
  * FP64 only (ETD_ERR_UNSUPPORTED). */
 #define ETD_PRECISION_F64 0
 #define ETD_PRECISION_F32 1
+/* Complex species (a complex diffusion coefficient, Sections 8.3 and 8.4):
+ * u holds s*N complex FP64 values as interleaved (re, im) pairs, D holds s
+ * (re, im) pairs with Re D >= 0, the model is ETD_RX_CGL_Z or ETD_RX_NLS_Z
+ * (and those models need this precision), shift must be 0.  Every solve is
+ * a complex line solve.  Lines run one per wavefront (ETD_LINES_TWO is
+ * ETD_ERR_UNSUPPORTED) with chunks of at most 4 rows, so n <= 256 per axis
+ * (ETD_ERR_UNSUPPORTED otherwise).  Step with etd_rdp_step_z /
+ * etd_rdp_run_pass_z; the other entry points return ETD_ERR_ARG or
+ * ETD_ERR_UNSUPPORTED for such a context. */
+#define ETD_PRECISION_C128 2
 
 typedef struct etd_scheme_t {
   int32_t scheme;                   /* ETD_SCHEME_RDP or ETD_SCHEME_ETD1     */
@@ -127,7 +143,8 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  *
  *  grid  : dimension, species, sizes, spacings (above).
  *  bc    : bc[i] for axis i+1, one of ETD_BC_*.
- *  D     : s diffusion coefficients, finite and >= 0 (diagonal D, Section 2).
+ *  D     : s diffusion coefficients, finite and >= 0 (diagonal D, Section 2);
+ *          for ETD_PRECISION_C128, s complex ones as (re, im) pairs.
  *  k     : time step, finite and > 0.
  *  scheme: NULL selects ETD_SCHEME_RDP with ETD_LINES_AUTO.
  *  rx    : reaction model and parameters; must match s.
@@ -201,6 +218,17 @@ int etd_rdp_step_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes,
                      int64_t nsteps, void* stream);
 
 /*
+ * etd_rdp_step_z -- etd_rdp_step for a context created with
+ * ETD_PRECISION_C128 (Sections 8.3 and 8.4: complex diffusion coefficient).
+ *  u : device, s*N complex values as 2*s*N doubles, (re, im) interleaved,
+ *      16-byte aligned; otherwise the layout of etd_rdp_step.
+ * The carried arrays are complex.  ETD_ERR_ARG if the context is not
+ * complex or u is misaligned; other errors as etd_rdp_step.
+ */
+int etd_rdp_step_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
+                   int64_t nsteps, void* stream);
+
+/*
  * etd_rdp_debug_passes -- run only the first `npasses` passes (1..d) of one
  * step and stop, leaving the carried arrays in the workspace (see
  * etd_rdp_workspace_layout).  Pass 1's triple holds c1 = R_1 U,
@@ -225,6 +253,10 @@ int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
 /* etd_rdp_run_pass for an ETD_PRECISION_F32 context (u holds floats). */
 int etd_rdp_run_pass_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes,
                          int32_t pass, void* stream);
+
+/* etd_rdp_run_pass for an ETD_PRECISION_C128 context (u as etd_rdp_step_z). */
+int etd_rdp_run_pass_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
+                       int32_t pass, void* stream);
 
 /*
  * etd_rdp_apply_solve -- x <- (I + (k/gamma) D_sigma A_axis)^{-1} x for a

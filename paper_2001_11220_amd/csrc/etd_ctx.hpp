@@ -18,6 +18,7 @@ struct etd_rdp_ctx {
   double h[3] = {0, 0, 0};
   int bc[3] = {0, 0, 0};
   double D[ETD_MAX_SPECIES] = {0, 0};
+  double Dim[ETD_MAX_SPECIES] = {0, 0};  // imaginary parts (complex species)
   double k = 0;
   int scheme = ETD_SCHEME_RDP;
   int precision = ETD_PRECISION_F64;  // element type of u and the carried arrays
@@ -31,6 +32,7 @@ struct etd_rdp_ctx {
   // per wavefront, a second set with one line per wavefront follows at index
   // tab1 (the reverse-mode kernels and single solves use it), else tab1 = 0.
   std::vector<etd::SolveTab> tabs;
+  std::vector<etd::SolveTabZ> tabz;  // complex species: the forward tables
   int tab1 = 0;
   size_t tab_bytes = 0, arr_bytes = 0, ws_bytes = 0;
   size_t part_bytes = 0, adj_ws_bytes = 0;
@@ -44,8 +46,12 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Bytes of one state / carried-array element of a context.
 inline size_t elem_bytes(const etd_rdp_ctx* c) {
+  if (c->precision == ETD_PRECISION_C128) return sizeof(zd);
   return c->precision == ETD_PRECISION_F32 ? sizeof(float) : sizeof(double);
 }
+
+// Longest chunk complex species run (n <= 4 * 64 rows per line).
+constexpr int kMaxComplexM = 4;
 
 // Two lines per wavefront: an axis whose lines are n = 32 m rows with
 // m in [kMinTwoLineM, kMaxM] runs its forward pass with 32 chunks of m rows
@@ -102,9 +108,9 @@ inline T* ws_array(const etd_rdp_ctx* c, void* ws, int i) {
 // Launches forward pass p (0-based) of one step.  Pass 0 reads u and writes
 // the carried triple `out`; a middle pass reads `in` and writes `out` (which
 // must not overlap); the last pass reads `in` and writes u.
-// Instantiated for double and float (the context's precision).
+// Instantiated for double, float and zd (the context's precision).
 template <typename T>
 int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[3],
-                const SolveTab* tabs, hipStream_t st);
+                const TabOf<T>* tabs, hipStream_t st);
 
 }  // namespace etd

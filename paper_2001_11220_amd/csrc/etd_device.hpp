@@ -13,9 +13,39 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "etd_tables.hpp"
 
 namespace etd {
+
+// ---------------------------------------------------------------------------
+// Complex FP64 arithmetic (element type zd of complex species).
+// ---------------------------------------------------------------------------
+using ::fma;
+__device__ __forceinline__ zd operator+(zd a, zd b) { return zd(a.re + b.re, a.im + b.im); }
+__device__ __forceinline__ zd operator-(zd a, zd b) { return zd(a.re - b.re, a.im - b.im); }
+__device__ __forceinline__ zd operator-(zd a) { return zd(-a.re, -a.im); }
+__device__ __forceinline__ zd operator*(zd a, zd b) {
+  return zd(fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re));
+}
+// a * b + c
+__device__ __forceinline__ zd fma(zd a, zd b, zd c) {
+  return zd(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
+}
+
+// Table value type of an element type: FP64 for real species (an FP32
+// kernel converts on load), complex FP64 for complex ones.
+template <typename T>
+struct CoefOf { using type = double; };
+template <>
+struct CoefOf<zd> { using type = zd; };
+template <typename T>
+using Coef = typename CoefOf<T>::type;
+template <typename T>
+using TabOf = SolveTabT<Coef<T>>;
+template <typename T>
+constexpr bool kIsComplex = std::is_same<T, zd>::value;
 
 enum Model : int {
   kLinear = 0,
@@ -24,6 +54,8 @@ enum Model : int {
   kGrayScott = 3,
   kSchnakenberg = 4,
   kCgl = 5,
+  kCglZ = 6,  // complex species
+  kNlsZ = 7,  // complex species
 };
 
 struct Rx {
@@ -33,9 +65,37 @@ struct Rx {
   double shift[2];
 };
 
+template <int S, typename T>
+__device__ __forceinline__ void react_real(const Rx& rx, const T (&uin)[S], T (&f)[S]);
+
 // F(u + shift) at one cell.  The model id is uniform across the launch.
+// Complex species (the Ginzburg-Landau and Schroedinger models) have no
+// shift.
 template <int S, typename T = double>
 __device__ __forceinline__ void react(const Rx& rx, const T (&uin)[S], T (&f)[S]) {
+  if constexpr (kIsComplex<T>) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const zd u = uin[i];
+      const double m2 = fma(u.re, u.re, u.im * u.im);
+      if (rx.model == kCglZ) {
+        // u - (1 + i beta) u |u|^2
+        const double beta = rx.p[0];
+        f[i] = zd(fma(-m2, fma(-beta, u.im, u.re), u.re), fma(-m2, fma(beta, u.re, u.im), u.im));
+      } else {
+        // -i q u with q = B + C |u|^2
+        const double q = fma(rx.p[1], m2, rx.p[0]);
+        f[i] = zd(q * u.im, -q * u.re);
+      }
+    }
+    return;
+  } else {
+    react_real<S, T>(rx, uin, f);
+  }
+}
+
+template <int S, typename T>
+__device__ __forceinline__ void react_real(const Rx& rx, const T (&uin)[S], T (&f)[S]) {
   T u[S];
 #pragma unroll
   for (int i = 0; i < S; ++i) u[i] = uin[i] + static_cast<T>(rx.shift[i]);
@@ -188,6 +248,25 @@ __device__ __forceinline__ float rows_swap16(float v, bool odd_row) {
   return __uint_as_float(odd_row ? q[0] : q[1]);
 }
 
+// The same moves for complex values: the real and imaginary parts in turn.
+__device__ __forceinline__ zd lane_value(zd v, int src) {
+  return zd(lane_value(v.re, src), lane_value(v.im, src));
+}
+__device__ __forceinline__ zd bperm(int addr, zd v) { return zd(bperm(addr, v.re), bperm(addr, v.im)); }
+__device__ __forceinline__ zd from_prev(zd v) { return zd(from_prev(v.re), from_prev(v.im)); }
+__device__ __forceinline__ zd from_next(zd v) { return zd(from_next(v.re), from_next(v.im)); }
+__device__ __forceinline__ void halves_swap(zd v, zd& up, zd& dn) {
+  halves_swap(v.re, up.re, dn.re);
+  halves_swap(v.im, up.im, dn.im);
+}
+__device__ __forceinline__ void quarters_shift(zd v, bool row1, bool row2, zd& up, zd& dn) {
+  quarters_shift(v.re, row1, row2, up.re, dn.re);
+  quarters_shift(v.im, row1, row2, up.im, dn.im);
+}
+__device__ __forceinline__ zd rows_swap16(zd v, bool odd_row) {
+  return zd(rows_swap16(v.re, odd_row), rows_swap16(v.im, odd_row));
+}
+
 // Lines per wavefront.  With P = 1 a wavefront solves one line, lane c
 // holding chunk c.  With P = 2 it solves two lines of exactly 32 chunks
 // each: lane c holds chunk c % 32 of the wavefront's line c / 32 (its
@@ -221,14 +300,14 @@ constexpr int kBlockLines = 8;
 // With W < 64 only the first W entries of every array are copied; values
 // are converted to the element type T.
 template <int W = kLanes, typename T = double>
-__device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tabs, int nt,
+__device__ __forceinline__ void stage_lane_tabs(const TabOf<T>* __restrict__ tabs, int nt,
                                                 LaneTabT<W, T>* dst) {
   constexpr int E = kLaneTabRows * W;  // values per staged table
   for (int i = threadIdx.x; i < nt * E; i += blockDim.x) {
     const int t = i / E, j = i - t * E;
     const int row = j / W, col = j - row * W;
     reinterpret_cast<T*>(dst + t)[j] =
-        static_cast<T>(reinterpret_cast<const double*>(&tabs[t].lane)[row * kLanes + col]);
+        static_cast<T>(reinterpret_cast<const Coef<T>*>(&tabs[t].lane)[row * kLanes + col]);
   }
 }
 
@@ -239,7 +318,7 @@ __device__ __forceinline__ void stage_lane_tabs(const SolveTab* __restrict__ tab
 // 2; with 2, the table has exactly 32 chunks).  All 64 lanes must call it
 // together.
 template <int M, int K, int P = 1, typename T = double>
-__device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
+__device__ __forceinline__ void line_solve(const TabOf<T>* const (&tab)[K],
                                            const LaneTabT<kSegLanes<P>, T>* const (&lt)[K],
                                            T (&x)[K][M], int lane) {
   constexpr int Q = M - 1;
@@ -255,7 +334,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   const int z0 = opaque_zero();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const SolveTab* t = tab[k] + z0;
+    const TabOf<T>* t = tab[k] + z0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       h[k].ip[j] = static_cast<T>(t->ip[j]);
@@ -354,7 +433,7 @@ __device__ __forceinline__ void line_solve(const SolveTab* const (&tab)[K],
   const int z1 = opaque_zero();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const SolveTab* t = tab[k] + z1;
+    const TabOf<T>* t = tab[k] + z1;
     T s = d[k] * lt[k]->inv[c];
     if (t->sm) {
       const T vy = seg_value<P>(s, 0, lane) + static_cast<T>(t->vfac) * seg_value<P>(s, C - 1, lane);
@@ -591,7 +670,10 @@ __device__ __forceinline__ void tile_store(T* __restrict__ A, const T (&x)[M],
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       const T v = B[col * g.pitch + i * g.C + q];
-      if constexpr (NT) {
+      if constexpr (NT && kIsComplex<T>) {
+        __builtin_nontemporal_store(v.re, &dst[i * g.outRow].re);
+        __builtin_nontemporal_store(v.im, &dst[i * g.outRow].im);
+      } else if constexpr (NT) {
         __builtin_nontemporal_store(v, dst + i * g.outRow);
       } else {
         dst[i * g.outRow] = v;
@@ -662,11 +744,11 @@ __device__ __forceinline__ void store_chunk(T* __restrict__ p, const T (&v)[M]) 
 // headers in global memory and per-lane parts staged in LDS.
 template <int S, int W = kLanes, typename E = double>
 struct AxisTabs {
-  const SolveTab* g;
+  const TabOf<E>* g;
   const LaneTabT<W, E>* l;
-  __device__ const SolveTab* P(int s) const { return g + tab_index(0, s, 0, S); }
-  __device__ const SolveTab* T(int s) const { return g + tab_index(0, s, 1, S); }
-  __device__ const SolveTab* Sx(int s) const { return g + tab_index(0, s, 2, S); }
+  __device__ const TabOf<E>* P(int s) const { return g + tab_index(0, s, 0, S); }
+  __device__ const TabOf<E>* T(int s) const { return g + tab_index(0, s, 1, S); }
+  __device__ const TabOf<E>* Sx(int s) const { return g + tab_index(0, s, 2, S); }
   __device__ const LaneTabT<W, E>* lP(int s) const { return l + tab_index(0, s, 0, S); }
   __device__ const LaneTabT<W, E>* lT(int s) const { return l + tab_index(0, s, 1, S); }
   __device__ const LaneTabT<W, E>* lS(int s) const { return l + tab_index(0, s, 2, S); }

@@ -55,6 +55,13 @@ constexpr int kLinesFor = lines_for(M);
 template <int M>
 constexpr int kMinWaves = (M <= 4) ? 4 : 2;
 
+// Complex species hold two doubles per row: 8-line tiles and two waves per
+// SIMD (a 256-register budget) for every chunk length.
+template <int M, typename T>
+constexpr int kPassLines = kIsComplex<T> ? 8 : kLinesFor<M>;
+template <int M, typename T>
+constexpr int kPassWaves = kIsComplex<T> ? 2 : kMinWaves<M>;
+
 // LDS pitch of a line of n rows in a tile buffer: n rounded up to 8 (mod 32)
 // doubles, so that the transposes are bank-conflict free.
 inline int tile_pitch(int n) { return n + ((8 - n % 32) + 32) % 32; }
@@ -79,6 +86,16 @@ inline int tile_buffers(size_t fixed_lds, int lines, int tile_elems, size_t elem
     case 7: { constexpr int M_ = 7; CALL; } break; \
     case 8: { constexpr int M_ = 8; CALL; } break; \
     default: return ETD_ERR_INTERNAL;               \
+  }
+
+// The same for the chunk lengths complex species run (1..4).
+#define ETD_DISPATCH_M4(m, CALL) \
+  switch (m) {                  \
+    case 1: { constexpr int M_ = 1; CALL; } break; \
+    case 2: { constexpr int M_ = 2; CALL; } break; \
+    case 3: { constexpr int M_ = 3; CALL; } break; \
+    case 4: { constexpr int M_ = 4; CALL; } break; \
+    default: return ETD_ERR_UNSUPPORTED;            \
   }
 
 

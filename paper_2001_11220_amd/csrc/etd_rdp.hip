@@ -50,9 +50,9 @@ namespace etd {
 // never occupy registers together).
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, bool NT, typename T>
-__global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
+__global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void k_first(
     const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
-    T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k, PassGeom g,
+    T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g,
     int etd1) {
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
           have = walk.next(tile);
           if (have) fetch(tile);
         }
-        const SolveTab* tb[1] = {at.P(s)};
+        const TabOf<T>* tb[1] = {at.P(s)};
         const LT* lb[1] = {at.lP(s)};
         line_solve<M, 1>(tb, lb, x, lane);
         tile_store<M, L, 1, NT>(w + s * g.N, x[0], tl, g, pos, cur);
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
         have = walk.next(tile);
         if (have) fetch(tile);
       }
-      const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
+      const TabOf<T>* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
       const LT* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
       line_solve<M, 5>(tb, lb, x, lane);
 #pragma unroll
@@ -141,10 +141,10 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_first(
 // is solved.
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, bool NT, typename T>
-__global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
+__global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void k_mid(
     const T* __restrict__ c1, const T* __restrict__ c2,
     const T* __restrict__ w, T* __restrict__ o1, T* __restrict__ o2,
-    T* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
+    T* __restrict__ ow, const TabOf<T>* __restrict__ tabs, PassGeom g, int etd1) {
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
   using LT = LaneTabT<kLanes, T>;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
       T y[1][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = x[4][j];
-      const SolveTab* tb[1] = {at.P(sc)};
+      const TabOf<T>* tb[1] = {at.P(sc)};
       const LT* lb[1] = {at.lP(sc)};
       line_solve<M, 1>(tb, lb, y, lane);
       tile_store<M, L, 1, NT>(ow + sc * g.N, y[0], tl, g, pos, cur);
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_mid(
       x[2][j] = x[0][j];
       x[3][j] = x[1][j];
     }
-    const SolveTab* tb[5] = {at.T(sc), at.T(sc), at.Sx(sc), at.Sx(sc), at.P(sc)};
+    const TabOf<T>* tb[5] = {at.T(sc), at.T(sc), at.Sx(sc), at.Sx(sc), at.P(sc)};
     const LT* lb[5] = {at.lT(sc), at.lT(sc), at.lS(sc), at.lS(sc), at.lP(sc)};
     line_solve<M, 5>(tb, lb, x, lane);
 #pragma unroll
@@ -224,7 +224,7 @@ template <int M, int S, int L, int P, bool NT, typename T>
 __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
     const T* __restrict__ c1, const T* __restrict__ c2,
     const T* __restrict__ w, T* __restrict__ o1, T* __restrict__ o2,
-    T* __restrict__ ow, const SolveTab* __restrict__ tabs, PassGeom g, int etd1) {
+    T* __restrict__ ow, const TabOf<T>* __restrict__ tabs, PassGeom g, int etd1) {
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
   using LT = LaneTabT<kSegLanes<P>, T>;
@@ -267,12 +267,12 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
       T y[1][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = x[0][j];
-      const SolveTab* tb[1] = {at.P(sc)};
+      const TabOf<T>* tb[1] = {at.P(sc)};
       const LT* lb[1] = {at.lP(sc)};
       line_solve<M, 1, P>(tb, lb, y, lane);
       tile_store<M, L, P, NT>(ow + sc * g.N, y[0], tl, g, pos, cur);
     } else {
-      const SolveTab* tb[2] = {at.T(sc), at.Sx(sc)};
+      const TabOf<T>* tb[2] = {at.T(sc), at.Sx(sc)};
       const LT* lb[2] = {at.lT(sc), at.lS(sc)};
       line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
@@ -304,7 +304,7 @@ __device__ __forceinline__ void react_species(const Rx& rx, const T (&U)[S][M], 
 template <int M, int S, int L, int P, bool NT, bool E1, typename T>
 __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
     const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
-    T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k, PassGeom g) {
+    T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g) {
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
   using LT = LaneTabT<kSegLanes<P>, T>;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
 #pragma unroll
     for (int j = 0; j < M; ++j) y[0][j] = fma(k, fs[j], Us[j]);
     if (pre) fetch(pf);
-    const SolveTab* tb[1] = {at.P(s_)};
+    const TabOf<T>* tb[1] = {at.P(s_)};
     const LT* lb[1] = {at.lP(s_)};
     line_solve<M, 1, P>(tb, lb, y, lane);
     tile_store<M, L, P, NT>(w + s_ * g.N, y[0], tl, g, pos, cur);
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
       x[1][j] = v[j];
     }
     if (pre) fetch(pf);
-    const SolveTab* tb[2] = {at.T(s_), at.Sx(s_)};
+    const TabOf<T>* tb[2] = {at.T(s_), at.Sx(s_)};
     const LT* lb[2] = {at.lT(s_), at.lS(s_)};
     line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
 template <int M, int S, int L, int P, bool NT, typename T>
 __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
     T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
-    const T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k,
+    const T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k,
     PassGeom g, int etd1) {
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
 #pragma unroll
     for (int s = 0; s < S; ++s) line_load<M, P>(w + s * g.N, us[s], g, pos);
     {
-      const SolveTab* tb[S];
+      const TabOf<T>* tb[S];
       const LT* lb[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
         x[0][j] = fma(k, us[s][j], fma(k2, b[j], T(9) * a));
         x[1][j] = fma(k05, us[s][j], fma(k15, b[j], T(8) * a));
       }
-      const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
+      const TabOf<T>* tb[2] = {at.T(s), at.Sx(s)};
       const LT* lb[2] = {at.lT(s), at.lS(s)};
       line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
@@ -470,9 +470,9 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
 // registers one group ahead.
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, bool NT, typename T>
-__global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
+__global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void k_last(
     T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
-    const T* __restrict__ w, const SolveTab* __restrict__ tabs, Rx rx, T k,
+    const T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k,
     PassGeom g, int etd1) {
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
       fetch_c(tcur, 0);
     }
     {
-      const SolveTab* tb[S];
+      const TabOf<T>* tb[S];
       const LT* lb[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void k_last(
         x[0][j] = fma(k, us[s][j], fma(k2, b[j], T(9) * a[j]));
         x[1][j] = fma(k05, us[s][j], fma(k15, b[j], T(8) * a[j]));
       }
-      const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
+      const TabOf<T>* tb[2] = {at.T(s), at.Sx(s)};
       const LT* lb[2] = {at.lT(s), at.lS(s)};
       line_solve<M, 2>(tb, lb, x, lane);
 #pragma unroll
@@ -644,8 +644,11 @@ int check_ws(const void* ws, size_t have, size_t need) {
 
 int ensure_tables(etd_rdp_ctx* c, void* ws, hipStream_t st) {
   if (c->uploaded_ws == ws) return ETD_OK;
-  hipError_t e = hipMemcpyAsync(ws, c->tabs.data(), c->tabs.size() * sizeof(SolveTab),
-                                hipMemcpyHostToDevice, st);
+  const bool z = (c->precision == ETD_PRECISION_C128);
+  hipError_t e = z ? hipMemcpyAsync(ws, c->tabz.data(), c->tabz.size() * sizeof(SolveTabZ),
+                                    hipMemcpyHostToDevice, st)
+                   : hipMemcpyAsync(ws, c->tabs.data(), c->tabs.size() * sizeof(SolveTab),
+                                    hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(c, e);
   c->uploaded_ws = ws;
   return ETD_OK;
@@ -660,6 +663,8 @@ int species_of_model(int model) {
     case ETD_RX_GRAY_SCOTT:
     case ETD_RX_SCHNAKENBERG:
     case ETD_RX_CGL: return 2;
+    case ETD_RX_CGL_Z:
+    case ETD_RX_NLS_Z: return 1;  // one complex species
     case ETD_RX_LINEAR: return 0;  // any s
     default: return -1;
   }
@@ -781,13 +786,13 @@ constexpr int kStreamWaves = 16;
 // arrays stay cache-resident between passes.
 constexpr size_t kNtMinBytes = size_t(64) << 20;
 inline bool use_nt(const etd_rdp_ctx* c) {
-  return sizeof(double) * static_cast<size_t>(c->s) * static_cast<size_t>(c->N) >= kNtMinBytes;
+  return elem_bytes(c) * static_cast<size_t>(c->s) * static_cast<size_t>(c->N) >= kNtMinBytes;
 }
 
 // Launchers, templated on the chunk length and species count.
 template <int M, int S, int P, bool NT, typename T>
 hipError_t launch_first_s(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
-                          T* w, const SolveTab* tabs, hipStream_t st) {
+                          T* w, const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L, false, sizeof(T));
@@ -808,7 +813,7 @@ hipError_t launch_first_s(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
 
 template <int M, int S, int P, bool NT, typename T>
 hipError_t launch_last_s(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
-                         const T* w, const SolveTab* tabs, hipStream_t st) {
+                         const T* w, const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassLast, fixed, L, false, sizeof(T));
@@ -825,9 +830,9 @@ hipError_t launch_last_s(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
 
 template <int M, int S, bool NT, typename T>
 hipError_t launch_first_n(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
-                        T* w, const SolveTab* tabs, hipStream_t st) {
+                        T* w, const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kLanes, T>(3 * S);
-  constexpr int L = kLinesFor<M>;
+  constexpr int L = kPassLines<M, T>;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_first<M, S, L, NT, T>, lds);
@@ -842,7 +847,7 @@ hipError_t launch_first_n(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
 
 template <int M, int S, typename T>
 hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
-                        T* w, const SolveTab* tabs, hipStream_t st) {
+                        T* w, const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
@@ -862,7 +867,7 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
 template <int M, int S, int P, bool NT, typename T>
 hipError_t launch_mid_s(const etd_rdp_ctx* c, const T* c1, const T* c2,
                         const T* w, T* o1, T* o2, T* ow,
-                        const SolveTab* tabs, hipStream_t st) {
+                        const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int L = kStreamWaves * P;
   const PassGeom g = pass_geom(c, kPassMid, fixed, L, false, sizeof(T));
@@ -880,9 +885,9 @@ hipError_t launch_mid_s(const etd_rdp_ctx* c, const T* c1, const T* c2,
 template <int M, int S, bool NT, typename T>
 hipError_t launch_mid_n(const etd_rdp_ctx* c, const T* c1, const T* c2,
                       const T* w, T* o1, T* o2, T* ow,
-                      const SolveTab* tabs, hipStream_t st) {
+                      const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kLanes, T>(3 * S);
-  constexpr int L = kLinesFor<M>;
+  constexpr int L = kPassLines<M, T>;
   const PassGeom g = pass_geom(c, kPassMid, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_mid<M, S, L, NT, T>, lds);
@@ -898,7 +903,7 @@ hipError_t launch_mid_n(const etd_rdp_ctx* c, const T* c1, const T* c2,
 template <int M, int S, typename T>
 hipError_t launch_mid(const etd_rdp_ctx* c, const T* c1, const T* c2,
                       const T* w, T* o1, T* o2, T* ow,
-                      const SolveTab* tabs, hipStream_t st) {
+                      const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
@@ -917,9 +922,9 @@ hipError_t launch_mid(const etd_rdp_ctx* c, const T* c1, const T* c2,
 
 template <int M, int S, bool NT, typename T>
 hipError_t launch_last_n(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
-                       const T* w, const SolveTab* tabs, hipStream_t st) {
+                       const T* w, const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kLanes, T>(3 * S);
-  constexpr int L = kLinesFor<M>;
+  constexpr int L = kPassLines<M, T>;
   const PassGeom g = pass_geom(c, kPassLast, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_last<M, S, L, NT, T>, lds);
@@ -934,7 +939,7 @@ hipError_t launch_last_n(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
 
 template <int M, int S, typename T>
 hipError_t launch_last(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
-                       const T* w, const SolveTab* tabs, hipStream_t st) {
+                       const T* w, const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
   if constexpr (M >= kMinTwoLineM) {
@@ -980,31 +985,47 @@ hipError_t launch_solve(const etd_rdp_ctx* c, double* x, const SolveTab* tab, in
 
 template <typename T>
 int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[3],
-                const SolveTab* tabs, hipStream_t st) {
+                const TabOf<T>* tabs, hipStream_t st) {
   const int S = c->s;
-  const SolveTab* ta = tabs + tab_index(p, 0, 0, S);
+  const TabOf<T>* ta = tabs + tab_index(p, 0, 0, S);
   const int m = c->m[p];
   hipError_t e = hipSuccess;
-  if (p == 0) {
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2, T>(c, u, out[0], out[1], out[2], ta, st))); }
-  } else if (p == c->d - 1) {
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2, T>(c, u, in[0], in[1], in[2], ta, st))); }
-  } else {
-    if (S == 1) {
-      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+  if constexpr (kIsComplex<T>) {
+    // One complex species, chunks of up to 4 rows, one line per wavefront.
+    if (S != 1) return ETD_ERR_UNSUPPORTED;
+    if (p == 0) {
+      ETD_DISPATCH_M4(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st)));
+    } else if (p == c->d - 1) {
+      ETD_DISPATCH_M4(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st)));
     } else {
-      ETD_DISPATCH_M(m, e = (launch_mid<M_, 2, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+      ETD_DISPATCH_M4(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     }
+    if (e != hipSuccess) return hip_fail(c, e);
+    return ETD_OK;
+  } else {
+    if (p == 0) {
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2, T>(c, u, out[0], out[1], out[2], ta, st))); }
+    } else if (p == c->d - 1) {
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2, T>(c, u, in[0], in[1], in[2], ta, st))); }
+    } else {
+      if (S == 1) {
+        ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+      } else {
+        ETD_DISPATCH_M(m, e = (launch_mid<M_, 2, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+      }
+    }
+    if (e != hipSuccess) return hip_fail(c, e);
+    return ETD_OK;
   }
-  if (e != hipSuccess) return hip_fail(c, e);
-  return ETD_OK;
 }
 template int launch_pass<double>(etd_rdp_ctx*, int, double*, double* const (&)[3],
                                  double* const (&)[3], const SolveTab*, hipStream_t);
 template int launch_pass<float>(etd_rdp_ctx*, int, float*, float* const (&)[3],
                                 float* const (&)[3], const SolveTab*, hipStream_t);
+template int launch_pass<zd>(etd_rdp_ctx*, int, zd*, zd* const (&)[3], zd* const (&)[3],
+                             const SolveTabZ*, hipStream_t);
 
 namespace {
 
@@ -1012,7 +1033,7 @@ namespace {
 // and writes B, pass d reads the last triple written.
 template <typename T>
 int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream_t st) {
-  const SolveTab* tabs = static_cast<const SolveTab*>(ws);
+  const TabOf<T>* tabs = static_cast<const TabOf<T>*>(ws);
   T* const A[3] = {ws_array<T>(c, ws, 0), ws_array<T>(c, ws, 1), ws_array<T>(c, ws, 2)};
   T* const B[3] = {ws_array<T>(c, ws, 3), ws_array<T>(c, ws, 4), ws_array<T>(c, ws, 5)};
   for (int p = first; p < npasses; ++p) {
@@ -1089,14 +1110,23 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   const int lpw = scheme ? scheme->lines_per_wave : ETD_LINES_AUTO;
   if (lpw != ETD_LINES_AUTO && lpw != ETD_LINES_ONE && lpw != ETD_LINES_TWO) return ETD_ERR_ARG;
   const int prec = scheme ? scheme->precision : ETD_PRECISION_F64;
-  if (prec != ETD_PRECISION_F64 && prec != ETD_PRECISION_F32) return ETD_ERR_ARG;
+  if (prec != ETD_PRECISION_F64 && prec != ETD_PRECISION_F32 && prec != ETD_PRECISION_C128)
+    return ETD_ERR_ARG;
   if (scheme && scheme->reserved != 0) return ETD_ERR_ARG;
-  for (int i = 0; i < s; ++i)
-    if (!(std::isfinite(D[i]) && D[i] >= 0)) return ETD_ERR_ARG;
+  // Complex species: complex models only, D given as (re, im) pairs with
+  // Re D >= 0, no shift, one line per wavefront.
+  const bool cplx = (prec == ETD_PRECISION_C128);
+  const bool cmodel = (rx->model == ETD_RX_CGL_Z || rx->model == ETD_RX_NLS_Z);
+  if (cplx != cmodel) return ETD_ERR_ARG;
+  for (int i = 0; i < s; ++i) {
+    const double re = cplx ? D[2 * i] : D[i], im = cplx ? D[2 * i + 1] : 0.0;
+    if (!(std::isfinite(re) && std::isfinite(im) && re >= 0)) return ETD_ERR_ARG;
+  }
   for (int i = 0; i < ETD_MAX_PARAMS; ++i)
     if (!std::isfinite(rx->params[i])) return ETD_ERR_ARG;
   for (int i = 0; i < s; ++i)
-    if (!std::isfinite(rx->shift[i])) return ETD_ERR_ARG;
+    if (!std::isfinite(rx->shift[i]) || (cplx && rx->shift[i] != 0.0)) return ETD_ERR_ARG;
+  if (cplx && lpw == ETD_LINES_TWO) return ETD_ERR_UNSUPPORTED;
 
   etd_rdp_ctx* c = new (std::nothrow) etd_rdp_ctx();
   if (!c) return ETD_ERR_INTERNAL;
@@ -1117,9 +1147,10 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     if (h == 0.0) h = (b == ETD_BC_DIRICHLET) ? 1.0 / (n + 1) : (b == ETD_BC_NEUMANN ? 1.0 / (n - 1) : 1.0 / n);
     if (!(std::isfinite(h) && h > 0)) { delete c; return ETD_ERR_ARG; }
     const int m = choose_chunk(n);
-    if (m == 0) { delete c; return ETD_ERR_UNSUPPORTED; }
+    if (m == 0 || (cplx && m > kMaxComplexM)) { delete c; return ETD_ERR_UNSUPPORTED; }
     const int64_t lines = N / n;
-    const bool two_ok = (lpw == ETD_LINES_TWO) || (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines);
+    const bool two_ok = !cplx && ((lpw == ETD_LINES_TWO) ||
+                                  (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines));
     const int m2 = two_ok ? two_line_chunk(n) : 0;
     c->n[i] = n;
     c->h[i] = h;
@@ -1129,7 +1160,10 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     c->P[i] = m2 ? 2 : 1;
   }
   c->N = N;
-  for (int i = 0; i < s; ++i) c->D[i] = D[i];
+  for (int i = 0; i < s; ++i) {
+    c->D[i] = cplx ? D[2 * i] : D[i];
+    c->Dim[i] = cplx ? D[2 * i + 1] : 0.0;
+  }
   c->rx.model = rx->model;
   for (int i = 0; i < 16; ++i) c->rx.p[i] = rx->params[i];
   for (int i = 0; i < s; ++i) c->rx.shift[i] = rx->shift[i];
@@ -1139,8 +1173,24 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   bool two = false;
   for (int a = 0; a < d; ++a) two = two || (c->P[a] == 2);
   c->tab1 = two ? nt : 0;
-  c->tabs.resize(static_cast<size_t>(two ? 2 * nt : nt));
-  for (int set = 0; set < (two ? 2 : 1); ++set)
+  if (cplx) {
+    c->tabz.resize(static_cast<size_t>(nt));
+    for (int a = 0; a < d; ++a)
+      for (int sp = 0; sp < s; ++sp)
+        for (int gi = 0; gi < 3; ++gi) {
+          std::string err;
+          const zd coef(k * c->D[sp] / gam[gi], k * c->Dim[sp] / gam[gi]);
+          if (!build_solve_table_z(c->n[a], c->bc[a], c->h[a], coef, c->m[a],
+                                   &c->tabz[tab_index(a, sp, gi, s)], &err)) {
+            std::fprintf(stderr, "etd_rdp_init: complex table (axis %d, gamma %g): %s\n", a + 1,
+                         gam[gi], err.c_str());
+            delete c;
+            return ETD_ERR_INTERNAL;
+          }
+        }
+  }
+  c->tabs.resize(cplx ? 0 : static_cast<size_t>(two ? 2 * nt : nt));
+  for (int set = 0; set < (cplx ? 0 : (two ? 2 : 1)); ++set)
     for (int a = 0; a < d; ++a)
       for (int sp = 0; sp < s; ++sp)
         for (int gi = 0; gi < 3; ++gi) {
@@ -1154,7 +1204,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
             return ETD_ERR_INTERNAL;
           }
         }
-  c->tab_bytes = round_up(c->tabs.size() * sizeof(SolveTab), 256);
+  c->tab_bytes = round_up(cplx ? c->tabz.size() * sizeof(SolveTabZ) : c->tabs.size() * sizeof(SolveTab), 256);
   c->arr_bytes = round_up(elem_bytes(c) * static_cast<size_t>(N) * s, 256);
   c->ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes;
   c->nparams = reaction_param_count(rx->model, s);
@@ -1214,6 +1264,12 @@ int etd_rdp_step_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes, int6
   return step_impl(ctx, u, ws, ws_bytes, nsteps, stream);
 }
 
+int etd_rdp_step_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int64_t nsteps,
+                   void* stream) {
+  if (reinterpret_cast<uintptr_t>(u) % alignof(zd) != 0) return ETD_ERR_ARG;
+  return step_impl(ctx, reinterpret_cast<zd*>(u), ws, ws_bytes, nsteps, stream);
+}
+
 int etd_rdp_debug_passes(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                          int32_t npasses, void* stream) {
   if (!ctx || !u || npasses < 1 || npasses > ctx->d) return ETD_ERR_ARG;
@@ -1234,6 +1290,12 @@ int etd_rdp_run_pass(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int
 int etd_rdp_run_pass_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes, int32_t pass,
                          void* stream) {
   return run_pass_impl(ctx, u, ws, ws_bytes, pass, stream);
+}
+
+int etd_rdp_run_pass_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, int32_t pass,
+                       void* stream) {
+  if (reinterpret_cast<uintptr_t>(u) % alignof(zd) != 0) return ETD_ERR_ARG;
+  return run_pass_impl(ctx, reinterpret_cast<zd*>(u), ws, ws_bytes, pass, stream);
 }
 
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, int32_t axis,
@@ -1267,11 +1329,12 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const char* nt = use_nt(ctx) ? "true" : "false";
   // Streamed pass 1 also carries the scheme (true: the ETD1 predictor alone).
   const char* e1 = first ? (ctx->scheme == ETD_SCHEME_ETD1 ? ", true" : ", false") : "";
-  const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : "double";
+  const bool z = (ctx->precision == ETD_PRECISION_C128);
+  const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : (z ? "zd" : "double");
   const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s%s, %s>", base, m,
                                          ctx->s, kStreamWaves * P, P, nt, e1, ty)
                          : std::snprintf(name, size, "%s<%d, %d, %d, %s, %s>", base, m, ctx->s,
-                                         lines_for(m), nt, ty);
+                                         z ? 8 : lines_for(m), nt, ty);
   return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
 }
 

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <utility>
@@ -26,22 +27,24 @@ int choose_chunk(int64_t n) {
 
 namespace {
 
-using Entries = std::map<int64_t, double>;  // unknown index -> coefficient
+template <typename V>
+using Entries = std::map<int64_t, V>;  // unknown index -> coefficient
 
 // The linear system on one line, with a ghost unknown (index -1) for the
 // Neumann reflection at row 0 so that row 0 keeps the interior stencil.
+template <typename V>
 struct LineSystem {
   int64_t n;
   int bc;
-  double r, delta;
+  V r, delta;
   bool ghost;
 
   // Coefficients of equation e (-1 = ghost equation x_{-1} - x_1 = 0).
-  Entries eq(int64_t e) const {
-    Entries out;
+  Entries<V> eq(int64_t e) const {
+    Entries<V> out;
     if (e == -1) {
-      out[-1] += 1.0;
-      out[1] += -1.0;
+      out[-1] += V(1.0);
+      out[1] += V(-1.0);
       return out;
     }
     out[e] += delta;
@@ -75,11 +78,11 @@ struct Split {
 };
 
 // Dense tridiagonal solve without pivoting (diagonally dominant input).
-void thomas(std::vector<double> a, std::vector<double> b, std::vector<double> c,
-            std::vector<double>& x) {
+template <typename V>
+void thomas(std::vector<V> a, std::vector<V> b, std::vector<V> c, std::vector<V>& x) {
   const size_t N = b.size();
   for (size_t i = 1; i < N; ++i) {
-    double w = a[i] / b[i - 1];
+    V w = a[i] / b[i - 1];
     b[i] -= w * c[i - 1];
     x[i] -= w * x[i - 1];
   }
@@ -88,88 +91,103 @@ void thomas(std::vector<double> a, std::vector<double> b, std::vector<double> c,
 }
 
 // The device algorithm, executed on the host for the residual self-check.
-void emulate(const SolveTab& t, const double* b, double* x) {
+template <typename V>
+void emulate(const SolveTabT<V>& t, const V* b, V* x) {
   const int m = t.m, C = t.C, q = m - 1;
-  double g[kLanes][kMaxM] = {};
-  double d[kLanes] = {};
+  std::vector<V> gv(kLanes * kMaxM, V(0.0));
+  auto g = [&](int c, int j) -> V& { return gv[c * kMaxM + j]; };
+  V d[kLanes] = {};
   for (int c = 0; c < C; ++c) {
-    const double* bc = b + static_cast<int64_t>(c) * m;
+    const V* bc = b + static_cast<int64_t>(c) * m;
     if (q > 0) {
-      double y[kMaxM];
+      V y[kMaxM];
       y[0] = bc[0] * t.ip[0];
       for (int j = 1; j < q; ++j) y[j] = (bc[j] + t.r * y[j - 1]) * t.ip[j];
-      g[c][q - 1] = y[q - 1];
-      for (int j = q - 1; j-- > 0;) g[c][j] = y[j] + t.cp[j] * g[c][j + 1];
+      g(c, q - 1) = y[q - 1];
+      for (int j = q - 1; j-- > 0;) g(c, j) = y[j] + t.cp[j] * g(c, j + 1);
     }
   }
   for (int c = 0; c < C; ++c) {
     const int cn = (c + 1 == C) ? 0 : c + 1;
-    double v = b[static_cast<int64_t>(c) * m + m - 1];
-    if (q > 0) v += t.lane.wl[c] * g[c][q - 1] + t.lane.wr[c] * g[cn][0];
-    if (q > 1) v += t.lane.wg[c] * g[c][1];
+    V v = b[static_cast<int64_t>(c) * m + m - 1];
+    if (q > 0) v += t.lane.wl[c] * g(c, q - 1) + t.lane.wr[c] * g(cn, 0);
+    if (q > 1) v += t.lane.wg[c] * g(c, 1);
     d[c] = v;
   }
   for (int st = 0; st < t.npcr; ++st) {
     const int sh = 1 << st;
-    double nd[kLanes];
+    V nd[kLanes];
     for (int c = 0; c < C; ++c) {
-      double dm = (c - sh >= 0) ? d[c - sh] : 0.0;
-      double dp = (c + sh < C) ? d[c + sh] : 0.0;
+      V dm = (c - sh >= 0) ? d[c - sh] : V(0.0);
+      V dp = (c + sh < C) ? d[c + sh] : V(0.0);
       nd[c] = d[c] - t.lane.k1[st][c] * dm - t.lane.k2[st][c] * dp;
     }
-    std::memcpy(d, nd, sizeof(double) * C);
+    for (int c = 0; c < C; ++c) d[c] = nd[c];
   }
-  double s[kLanes];
+  V s[kLanes];
   for (int c = 0; c < C; ++c) s[c] = d[c] * t.lane.inv[c];
   if (t.sm) {
-    const double gam = (s[0] + t.vfac * s[C - 1]) * t.smfac;
+    const V gam = (s[0] + t.vfac * s[C - 1]) * t.smfac;
     for (int c = 0; c < C; ++c) s[c] -= gam * t.lane.z[c];
   }
   for (int c = 0; c < C; ++c) {
-    double sl;
+    V sl;
     if (c > 0) {
       sl = s[c - 1];
     } else {
-      sl = t.gh0 * s[0] + t.ghw * s[C - 1] + (q > 1 ? t.ghd * g[0][1] : 0.0);
+      sl = t.gh0 * s[0] + t.ghw * s[C - 1] + (q > 1 ? t.ghd * g(0, 1) : V(0.0));
     }
-    double* xc = x + static_cast<int64_t>(c) * m;
-    for (int j = 0; j < q; ++j) xc[j] = g[c][j] + sl * t.al[j] + s[c] * t.be[j];
+    V* xc = x + static_cast<int64_t>(c) * m;
+    for (int j = 0; j < q; ++j) xc[j] = g(c, j) + sl * t.al[j] + s[c] * t.be[j];
     xc[m - 1] = s[c];
   }
 }
 
-}  // namespace
+// Random right-hand side entries in [-0.5, 0.5) (and the same for the
+// imaginary part of a complex one).
+inline double next_uniform(uint64_t& state) {
+  state = state * 6364136223846793005ull + 1442695040888963407ull;
+  return static_cast<double>(state >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+inline void random_entry(uint64_t& state, double& v) { v = next_uniform(state); }
+inline void random_entry(uint64_t& state, std::complex<double>& v) {
+  const double re = next_uniform(state);
+  v = std::complex<double>(re, next_uniform(state));
+}
 
-bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
-                       SolveTab* out, std::string* err) {
+// The table builder for real (V = double) or complex (std::complex<double>)
+// coefficients.
+template <typename V>
+bool build_impl(int64_t n, int bc, double h, V coef, int m, SolveTabT<V>* out,
+                std::string* err) {
   auto fail = [&](const std::string& why) {
     if (err) *err = why;
     return false;
   };
   if (m < 1 || m > kMaxM || n % m != 0 || n / m > kLanes || n < 1)
     return fail("bad chunking");
-  std::memset(static_cast<void*>(out), 0, sizeof(SolveTab));
-  const double r = coef / (h * h);
-  LineSystem L{n, bc, r, 1.0 + 2.0 * r, bc == 1};
+  *out = SolveTabT<V>{};
+  const V r = coef / (h * h);
+  LineSystem<V> L{n, bc, r, V(1.0) + V(2.0) * r, bc == 1};
   Split S{n, m, static_cast<int>(n / m), L.ghost ? 1 : 0};
   const int C = S.C, q = m - 1, Cx = C + S.g;
-  SolveTab& t = *out;
+  SolveTabT<V>& t = *out;
   t.r = r;
   t.C = C;
   t.m = m;
 
   // Interior factors of T = tridiag(-r, 1+2r, -r) of size q.
-  std::vector<std::vector<double>> Tinv(q, std::vector<double>(q, 0.0));
+  std::vector<std::vector<V>> Tinv(q, std::vector<V>(q, V(0.0)));
   if (q > 0) {
-    double p = L.delta;
+    V p = L.delta;
     for (int j = 0; j < q; ++j) {
       if (j > 0) p = L.delta - r * r / p;
-      t.ip[j] = 1.0 / p;
+      t.ip[j] = V(1.0) / p;
       t.cp[j] = r * t.ip[j];
     }
     for (int col = 0; col < q; ++col) {
-      std::vector<double> a(q, -r), b(q, L.delta), c(q, -r), x(q, 0.0);
-      x[col] = 1.0;
+      std::vector<V> a(q, -r), b(q, L.delta), c(q, -r), x(q, V(0.0));
+      x[col] = V(1.0);
       thomas(a, b, c, x);
       for (int j = 0; j < q; ++j) Tinv[j][col] = x[j];
     }
@@ -180,8 +198,8 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   }
 
   // Assemble E_SS and collect E_IS / E_SI per chunk.
-  std::vector<std::vector<double>> Mx(Cx, std::vector<double>(Cx, 0.0));
-  struct Ent { int slot; int sep; double v; };
+  std::vector<std::vector<V>> Mx(Cx, std::vector<V>(Cx, V(0.0)));
+  struct Ent { int slot; int sep; V v; };
   std::vector<std::vector<Ent>> EIS(C), ESI(C);  // per chunk
   auto all_eqs = [&](auto&& fn) {
     if (L.ghost) fn(int64_t(-1));
@@ -190,7 +208,7 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   bool bad = false;
   std::string why;
   all_eqs([&](int64_t e) {
-    Entries row = L.eq(e);
+    Entries<V> row = L.eq(e);
     if (S.is_sep(e)) {
       const int p = S.sep_index(e);
       for (auto& kv : row) {
@@ -205,7 +223,7 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
         } else {
           // interior-interior coupling must be the shared T block
           const int c2 = S.chunk(kv.first), j2 = S.slot(kv.first);
-          double want = (j2 == j) ? L.delta : -r;
+          const V want = (j2 == j) ? L.delta : -r;
           if (c2 != c || std::abs(j2 - j) > 1 || kv.second != want) {
             bad = true;
             why = "interior block is not the shared tridiagonal";
@@ -220,9 +238,9 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   // (previous chunk, ghost, periodic wrap, or none) and slot q-1 to the own
   // separator, both -r.  These are what the spikes al/be encode.
   for (int c = 0; c < C && q > 0; ++c) {
-    std::map<std::pair<int, int>, double> got;
+    std::map<std::pair<int, int>, V> got;
     for (auto& en : EIS[c]) got[{en.slot, en.sep}] += en.v;
-    std::map<std::pair<int, int>, double> want;
+    std::map<std::pair<int, int>, V> want;
     int left = -2;
     if (c > 0) left = S.g + c - 1;
     else if (bc == 1) left = 0;
@@ -240,8 +258,8 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
 
   // Reduced right-hand-side weights (per separator, then checked to be
   // uniform apart from the first and last separator).
-  std::vector<double> wl(C, 0.0), wr(C, 0.0), wg(C, 0.0);
-  double cg = 0.0;  // ghost equation: d_g = cg * g_0[1]
+  std::vector<V> wl(C, V(0.0)), wr(C, V(0.0)), wg(C, V(0.0));
+  V cg = V(0.0);  // ghost equation: d_g = cg * g_0[1]
   for (int c = 0; c < C; ++c) {
     for (auto& a : ESI[c]) {
       const int p = a.sep;
@@ -263,29 +281,29 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   }
 
   // Eliminate the Neumann ghost separator.
-  std::vector<std::vector<double>> Mr(C, std::vector<double>(C, 0.0));
+  std::vector<std::vector<V>> Mr(C, std::vector<V>(C, V(0.0)));
   if (L.ghost) {
-    const double pg = Mx[0][0];
+    const V pg = Mx[0][0];
     for (int i = 0; i < C; ++i)
       for (int j = 0; j < C; ++j)
         Mr[i][j] = Mx[i + 1][j + 1] - Mx[i + 1][0] * Mx[0][j + 1] / pg;
     for (int i = 1; i < C; ++i)
-      if (Mx[i + 1][0] != 0.0) return fail("ghost couples beyond separator 0");
+      if (Mx[i + 1][0] != V(0.0)) return fail("ghost couples beyond separator 0");
     wg[0] = -(Mx[1][0] / pg) * cg;
     t.ghd = cg / pg;
     t.gh0 = -Mx[0][1] / pg;
     if (q > 0)
       for (int j = 1; j < C; ++j)
-        if (Mx[0][j + 1] != 0.0) return fail("ghost row couples beyond s_0");
+        if (Mx[0][j + 1] != V(0.0)) return fail("ghost row couples beyond s_0");
   } else {
     Mr = Mx;
-    if (bc == 2) t.ghw = 1.0;
+    if (bc == 2) t.ghw = V(1.0);
   }
 
   // Reduced matrix must be tridiagonal plus (periodic) two corners.
   double scale = 0.0;
-  for (auto& row : Mr) for (double v : row) scale = std::max(scale, std::abs(v));
-  double ctop = 0.0, cbot = 0.0;
+  for (auto& row : Mr) for (const V& v : row) scale = std::max(scale, std::abs(v));
+  V ctop = V(0.0), cbot = V(0.0);
   for (int i = 0; i < C; ++i)
     for (int j = 0; j < C; ++j) {
       if (std::abs(i - j) <= 1) continue;
@@ -294,7 +312,7 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
       if (std::abs(Mr[i][j]) > 1e-14 * scale)
         return fail("reduced matrix is not tridiagonal");
     }
-  std::vector<double> ra(C, 0.0), rb(C, 0.0), rc(C, 0.0);
+  std::vector<V> ra(C, V(0.0)), rb(C, V(0.0)), rc(C, V(0.0));
   for (int i = 0; i < C; ++i) {
     rb[i] = Mr[i][i];
     if (i > 0) ra[i] = Mr[i][i - 1];
@@ -303,16 +321,16 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   if (bc == 2 && C >= 3) {
     ctop = Mr[0][C - 1];
     cbot = Mr[C - 1][0];
-    const double gam = -rb[0];
+    const V gam = -rb[0];
     rb[0] -= gam;
     rb[C - 1] -= cbot * ctop / gam;
-    std::vector<double> u(C, 0.0);
+    std::vector<V> u(C, V(0.0));
     u[0] = gam;
     u[C - 1] = cbot;
     thomas(ra, rb, rc, u);
     for (int i = 0; i < C; ++i) t.lane.z[i] = u[i];
     t.vfac = ctop / gam;
-    t.smfac = 1.0 / (1.0 + t.lane.z[0] + t.vfac * t.lane.z[C - 1]);
+    t.smfac = V(1.0) / (V(1.0) + t.lane.z[0] + t.vfac * t.lane.z[C - 1]);
     t.sm = 1;
   }
 
@@ -322,22 +340,22 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   t.npcr = npcr;
   for (int st = 0; st < npcr; ++st) {
     const int sh = 1 << st;
-    std::vector<double> na(C, 0.0), nb(C, 0.0), nc(C, 0.0);
+    std::vector<V> na(C, V(0.0)), nb(C, V(0.0)), nc(C, V(0.0));
     for (int i = 0; i < C; ++i) {
-      const double k1 = (i - sh >= 0) ? ra[i] / rb[i - sh] : 0.0;
-      const double k2 = (i + sh < C) ? rc[i] / rb[i + sh] : 0.0;
+      const V k1 = (i - sh >= 0) ? ra[i] / rb[i - sh] : V(0.0);
+      const V k2 = (i + sh < C) ? rc[i] / rb[i + sh] : V(0.0);
       t.lane.k1[st][i] = k1;
       t.lane.k2[st][i] = k2;
-      nb[i] = rb[i] - ((i - sh >= 0) ? k1 * rc[i - sh] : 0.0) -
-              ((i + sh < C) ? k2 * ra[i + sh] : 0.0);
-      na[i] = (i - sh >= 0) ? -k1 * ra[i - sh] : 0.0;
-      nc[i] = (i + sh < C) ? -k2 * rc[i + sh] : 0.0;
+      nb[i] = rb[i] - ((i - sh >= 0) ? k1 * rc[i - sh] : V(0.0)) -
+              ((i + sh < C) ? k2 * ra[i + sh] : V(0.0));
+      na[i] = (i - sh >= 0) ? -k1 * ra[i - sh] : V(0.0);
+      nc[i] = (i + sh < C) ? -k2 * rc[i + sh] : V(0.0);
     }
     ra.swap(na);
     rb.swap(nb);
     rc.swap(nc);
   }
-  for (int i = 0; i < C; ++i) t.lane.inv[i] = 1.0 / rb[i];
+  for (int i = 0; i < C; ++i) t.lane.inv[i] = V(1.0) / rb[i];
 
   // Uniform reduced-RHS weights.
   t.wl_gen = r;
@@ -348,41 +366,88 @@ bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
   for (int c = 0; c + 1 < C; ++c)
     if (q > 0 && (wl[c] != r || wr[c] != r)) return fail("non-uniform reduced weights");
   for (int c = 1; c < C; ++c)
-    if (wg[c] != 0.0) return fail("ghost weight beyond separator 0");
+    if (wg[c] != V(0.0)) return fail("ghost weight beyond separator 0");
   // Per-lane copies of the weights (zero on lanes without a chunk): the
   // device reads these instead of selecting between the uniform values.
   for (int c = 0; c < C; ++c) {
     t.lane.wl[c] = (c + 1 == C) ? t.wl_last : t.wl_gen;
     t.lane.wr[c] = (c + 1 == C) ? t.wr_last : t.wr_gen;
-    t.lane.wg[c] = (c == 0) ? t.wg0 : 0.0;
+    t.lane.wg[c] = (c == 0) ? t.wg0 : V(0.0);
   }
 
   // Residual self-check of the chunked algorithm on the original line matrix.
   uint64_t state = 0x9E3779B97F4A7C15ull ^ static_cast<uint64_t>(n * 131 + bc);
-  std::vector<double> b(n), x(n);
+  std::vector<V> b(n), x(n);
   for (int trial = 0; trial < 2; ++trial) {
-    for (int64_t i = 0; i < n; ++i) {
-      state = state * 6364136223846793005ull + 1442695040888963407ull;
-      b[i] = static_cast<double>(state >> 11) * (1.0 / 9007199254740992.0) - 0.5;
-    }
+    for (int64_t i = 0; i < n; ++i) random_entry(state, b[i]);
     emulate(t, b.data(), x.data());
     double rmax = 0.0, bmax = 0.0, xmax = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-      double lhs = L.delta * x[i];
-      double xl = 0.0, xr = 0.0;
+      V lhs = L.delta * x[i];
+      V xl = V(0.0), xr = V(0.0);
       if (i > 0) xl = x[i - 1];
-      else if (bc == 1) xl = (n > 1) ? x[1] : 0.0;
+      else if (bc == 1) xl = (n > 1) ? x[1] : V(0.0);
       else if (bc == 2) xl = x[n - 1];
       if (i < n - 1) xr = x[i + 1];
-      else if (bc == 1) xr = (n > 1) ? x[n - 2] : 0.0;
+      else if (bc == 1) xr = (n > 1) ? x[n - 2] : V(0.0);
       else if (bc == 2) xr = x[0];
       lhs -= r * (xl + xr);
       rmax = std::max(rmax, std::abs(lhs - b[i]));
       bmax = std::max(bmax, std::abs(b[i]));
       xmax = std::max(xmax, std::abs(x[i]));
     }
-    if (!(rmax <= 1e-10 * (bmax + (1.0 + 4.0 * r) * xmax)))
+    if (!(rmax <= 1e-10 * (bmax + (1.0 + 4.0 * std::abs(r)) * xmax)))
       return fail("residual self-check failed");
+  }
+  return true;
+}
+
+}  // namespace
+
+bool build_solve_table(int64_t n, int bc, double h, double coef, int m, SolveTab* out,
+                       std::string* err) {
+  return build_impl<double>(n, bc, h, coef, m, out, err);
+}
+
+bool build_solve_table_z(int64_t n, int bc, double h, zd coef, int m, SolveTabZ* out,
+                         std::string* err) {
+  using C = std::complex<double>;
+  std::vector<SolveTabT<C>> tmp(1);
+  if (!build_impl<C>(n, bc, h, C(coef.re, coef.im), m, tmp.data(), err)) return false;
+  const SolveTabT<C>& a = tmp[0];
+  auto z = [](const C& v) { return zd(v.real(), v.imag()); };
+  *out = SolveTabZ{};
+  for (int j = 0; j < kMaxM; ++j) {
+    out->ip[j] = z(a.ip[j]);
+    out->cp[j] = z(a.cp[j]);
+    out->al[j] = z(a.al[j]);
+    out->be[j] = z(a.be[j]);
+  }
+  out->r = z(a.r);
+  out->wl_gen = z(a.wl_gen);
+  out->wl_last = z(a.wl_last);
+  out->wr_gen = z(a.wr_gen);
+  out->wr_last = z(a.wr_last);
+  out->wg0 = z(a.wg0);
+  out->ghd = z(a.ghd);
+  out->gh0 = z(a.gh0);
+  out->ghw = z(a.ghw);
+  out->vfac = z(a.vfac);
+  out->smfac = z(a.smfac);
+  out->C = a.C;
+  out->m = a.m;
+  out->npcr = a.npcr;
+  out->sm = a.sm;
+  for (int c = 0; c < kLanes; ++c) {
+    for (int st = 0; st < kMaxPcr; ++st) {
+      out->lane.k1[st][c] = z(a.lane.k1[st][c]);
+      out->lane.k2[st][c] = z(a.lane.k2[st][c]);
+    }
+    out->lane.inv[c] = z(a.lane.inv[c]);
+    out->lane.z[c] = z(a.lane.z[c]);
+    out->lane.wl[c] = z(a.lane.wl[c]);
+    out->lane.wr[c] = z(a.lane.wr[c]);
+    out->lane.wg[c] = z(a.lane.wg[c]);
   }
   return true;
 }

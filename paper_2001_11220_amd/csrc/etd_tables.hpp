@@ -37,6 +37,15 @@ constexpr int kMaxM = 8;       // max rows per chunk
 constexpr int kLanes = 64;     // wavefront width
 constexpr int kMaxPcr = 6;     // log2(64)
 
+// A complex FP64 value: the element and table type of complex species (a
+// complex diffusion coefficient, Sections 8.3 and 8.4).  Plain data; the
+// device code defines its arithmetic.
+struct alignas(16) zd {
+  double re, im;
+  zd() = default;
+  constexpr explicit zd(double r, double i = 0.0) : re(r), im(i) {}
+};
+
 // Per-lane data of one line-solve operator (structure of arrays, index =
 // chunk = separator), for W chunks, in element type T.  Tables hold W = 64
 // FP64 values; a kernel that solves two lines of 32 chunks per wavefront
@@ -58,27 +67,31 @@ constexpr int kLaneTabRows = 2 * kMaxPcr + 5;  // arrays of W doubles in a LaneT
 // One line-solve operator (axis, species, gamma).  POD, 256-byte multiple,
 // copied verbatim to device memory.  The header fields are uniform across a
 // wavefront (chunk-interior factors are indexed by the row inside the chunk).
-struct alignas(256) SolveTab {
+// V = double for real species, zd for complex ones.
+template <typename V>
+struct alignas(256) SolveTabT {
   // Chunk-interior factors, index j < m-1.
-  double ip[kMaxM];   // inverse pivots of T
-  double cp[kMaxM];   // back-substitution multipliers r * ip[j]
-  double al[kMaxM];   // left spike  r T^{-1} e_0
-  double be[kMaxM];   // right spike r T^{-1} e_{m-2}
-  double r;           // off-diagonal magnitude k D / (gamma h^2)
-  double wl_gen, wl_last;  // reduced-RHS weights of g_c[m-2]
-  double wr_gen, wr_last;  // reduced-RHS weights of g_{c+1}[0]
-  double wg0;              // reduced-RHS weight of g_0[1] (Neumann ghost)
-  double ghd;         // lane 0 ghost: sl_0 = ghd g_0[1] + gh0 s_0 + ghw s_{C-1}
-  double gh0;
-  double ghw;
-  double vfac;        // Sherman-Morrison: v = e_0 + vfac e_{C-1}
-  double smfac;       // 1 / (1 + v.z); 0 when the reduced system is not cyclic
-  int32_t C;          // number of chunks (active lanes)
-  int32_t m;          // rows per chunk
-  int32_t npcr;       // PCR steps = ceil(log2 C)
-  int32_t sm;         // 1 if the Sherman-Morrison correction is applied
-  LaneTab lane;
+  V ip[kMaxM];   // inverse pivots of T
+  V cp[kMaxM];   // back-substitution multipliers r * ip[j]
+  V al[kMaxM];   // left spike  r T^{-1} e_0
+  V be[kMaxM];   // right spike r T^{-1} e_{m-2}
+  V r;           // off-diagonal magnitude k D / (gamma h^2)
+  V wl_gen, wl_last;  // reduced-RHS weights of g_c[m-2]
+  V wr_gen, wr_last;  // reduced-RHS weights of g_{c+1}[0]
+  V wg0;              // reduced-RHS weight of g_0[1] (Neumann ghost)
+  V ghd;         // lane 0 ghost: sl_0 = ghd g_0[1] + gh0 s_0 + ghw s_{C-1}
+  V gh0;
+  V ghw;
+  V vfac;        // Sherman-Morrison: v = e_0 + vfac e_{C-1}
+  V smfac;       // 1 / (1 + v.z); 0 when the reduced system is not cyclic
+  int32_t C;     // number of chunks (active lanes)
+  int32_t m;     // rows per chunk
+  int32_t npcr;  // PCR steps = ceil(log2 C)
+  int32_t sm;    // 1 if the Sherman-Morrison correction is applied
+  LaneTabT<kLanes, V> lane;
 };
+using SolveTab = SolveTabT<double>;
+using SolveTabZ = SolveTabT<zd>;
 
 // Pick the chunk length for a line of n rows: the smallest m <= kMaxM that
 // divides n with n / m <= kLanes.  Returns 0 if none exists.
@@ -92,5 +105,11 @@ int choose_chunk(int64_t n);
 // check fails.
 bool build_solve_table(int64_t n, int bc, double h, double coef, int m,
                        SolveTab* out, std::string* err);
+
+// The same for a complex coefficient coef = k D / gamma (complex D with
+// Re D >= 0: the line matrix stays strictly diagonally dominant, so the
+// elimination needs no pivoting).  Same checks, on complex right-hand sides.
+bool build_solve_table_z(int64_t n, int bc, double h, zd coef, int m, SolveTabZ* out,
+                         std::string* err);
 
 }  // namespace etd

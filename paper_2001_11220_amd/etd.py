@@ -24,12 +24,13 @@ ETD_ERR_INTERNAL = -5
 
 BC = {"dirichlet": 0, "neumann": 1, "periodic": 2}
 MODELS = {"linear": 0, "enzyme": 1, "brusselator": 2, "gray_scott": 3,
-          "schnakenberg": 4, "cgl": 5}
+          "schnakenberg": 4, "cgl": 5, "cgl_z": 6, "nls_z": 7}
 # parameter order of each model in etd_reaction_t.params
 MODEL_PARAMS = {"enzyme": (), "brusselator": ("a", "b"), "gray_scott": ("F", "kappa"),
-                "schnakenberg": ("a", "b", "gamma"), "cgl": ("beta",)}
+                "schnakenberg": ("a", "b", "gamma"), "cgl": ("beta",),
+                "cgl_z": ("beta",), "nls_z": ("B", "C")}
 SCHEMES = {"rdp": 0, "etd1": 1}
-PRECISIONS = {"f64": 0, "f32": 1}
+PRECISIONS = {"f64": 0, "f32": 1, "c128": 2}
 
 MAX_DIM, MAX_SPECIES, MAX_PARAMS = 3, 2, 16
 
@@ -76,9 +77,11 @@ def _load():
                                                     ctypes.POINTER(SZ), ctypes.POINTER(I64)]),
         "etd_rdp_step": (ctypes.c_int, [P, P, P, SZ, I64, P]),
         "etd_rdp_step_f32": (ctypes.c_int, [P, P, P, SZ, I64, P]),
+        "etd_rdp_step_z": (ctypes.c_int, [P, P, P, SZ, I64, P]),
         "etd_rdp_debug_passes": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_run_pass": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_run_pass_f32": (ctypes.c_int, [P, P, P, SZ, I32, P]),
+        "etd_rdp_run_pass_z": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_apply_solve": (ctypes.c_int, [P, P, P, SZ, I32, I32, I32, P]),
         "etd_rdp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "etd_rdp_last_hip_error": (ctypes.c_int, [P]),
@@ -141,7 +144,9 @@ class EtdRdp:
     0 (or ``None``) select the unit-domain spacing of each boundary condition.
     ``lines_per_wave`` is "auto", 1 or 2 (ETD_LINES_* of the C ABI).
     ``precision`` "f32" makes the state and the carried arrays float32 (the
-    reverse-mode step and the single solves stay "f64" only).
+    reverse-mode step and the single solves stay "f64" only); "c128" is for
+    one complex species (models "cgl_z", "nls_z", complex ``D``): states are
+    complex128 tensors.
     """
 
     def __init__(self, shape, bcs, D, k, model, params, h=None, shift=None,
@@ -155,7 +160,11 @@ class EtdRdp:
             g.h[i] = float(h[i]) if h is not None and h[i] is not None else 0.0
         bc_arr = (ctypes.c_int32 * MAX_DIM)(*[BC[b] if isinstance(b, str) else int(b) for b in bcs],
                                             *([0] * (MAX_DIM - d)))
-        D_arr = (ctypes.c_double * MAX_SPECIES)(*[float(v) for v in D], *([0.0] * (MAX_SPECIES - s)))
+        if precision == "c128":
+            parts = [float(x) for v in D for x in (complex(v).real, complex(v).imag)]
+            D_arr = (ctypes.c_double * (2 * MAX_SPECIES))(*parts, *([0.0] * (2 * MAX_SPECIES - 2 * s)))
+        else:
+            D_arr = (ctypes.c_double * MAX_SPECIES)(*[float(v) for v in D], *([0.0] * (MAX_SPECIES - s)))
         sch = Scheme()
         sch.scheme = SCHEMES[scheme]
         sch.lines_per_wave = 0 if lines_per_wave == "auto" else int(lines_per_wave)
@@ -163,11 +172,12 @@ class EtdRdp:
         self.precision = precision
         rx = reaction_struct(model, params, shift, s)
         ctx = ctypes.c_void_p()
-        _check(lib.etd_rdp_init(ctypes.byref(g), bc_arr, D_arr, float(k), ctypes.byref(sch),
+        _check(lib.etd_rdp_init(ctypes.byref(g), bc_arr, ctypes.cast(D_arr, ctypes.POINTER(ctypes.c_double)),
+                                float(k), ctypes.byref(sch),
                                 ctypes.byref(rx), ctypes.byref(ctx)), "etd_rdp_init")
         self._ctx = ctx
         self.shape, self.s, self.d = tuple(int(v) for v in shape), s, d
-        self.D = tuple(float(v) for v in D)
+        self.D = tuple((complex(v) if precision == "c128" else float(v)) for v in D)
         self.model = model
         self._rx_params = tuple(float(rx.params[i]) for i in range(MAX_PARAMS))
         nb = ctypes.c_size_t()
@@ -264,7 +274,7 @@ class EtdRdp:
 
     def _elem_dtype(self):
         import torch
-        return torch.float32 if self.precision == "f32" else torch.float64
+        return {"f32": torch.float32, "c128": torch.complex128}.get(self.precision, torch.float64)
 
     @staticmethod
     def _stream(stream):
@@ -274,10 +284,11 @@ class EtdRdp:
 
     def step(self, u, nsteps=1, stream=None):
         """Advance ``u`` in place by ``nsteps`` steps (asynchronous).  ``u`` is
-        float64, or float32 for a precision="f32" problem."""
+        float64, float32 for a precision="f32" problem, complex128 for "c128"."""
         p = self._state_ptr(u, self.s, self._elem_dtype())
-        fn, name = ((lib.etd_rdp_step_f32, "etd_rdp_step_f32") if self.precision == "f32"
-                    else (lib.etd_rdp_step, "etd_rdp_step"))
+        fn, name = {"f32": (lib.etd_rdp_step_f32, "etd_rdp_step_f32"),
+                    "c128": (lib.etd_rdp_step_z, "etd_rdp_step_z")}.get(
+                        self.precision, (lib.etd_rdp_step, "etd_rdp_step"))
         _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
                   self.ws_bytes, int(nsteps), self._stream(stream)), name)
         return u
@@ -291,8 +302,9 @@ class EtdRdp:
     def run_pass(self, u, npass, stream=None):
         """Run pass ``npass`` (1..d) of a step alone (kernel timing)."""
         p = self._state_ptr(u, self.s, self._elem_dtype())
-        fn, name = ((lib.etd_rdp_run_pass_f32, "etd_rdp_run_pass_f32") if self.precision == "f32"
-                    else (lib.etd_rdp_run_pass, "etd_rdp_run_pass"))
+        fn, name = {"f32": (lib.etd_rdp_run_pass_f32, "etd_rdp_run_pass_f32"),
+                    "c128": (lib.etd_rdp_run_pass_z, "etd_rdp_run_pass_z")}.get(
+                        self.precision, (lib.etd_rdp_run_pass, "etd_rdp_run_pass"))
         _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
                   self.ws_bytes, int(npass), self._stream(stream)), name)
 

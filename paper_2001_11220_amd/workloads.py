@@ -52,6 +52,15 @@ class Problem:
     def cells(self) -> int:
         return int(np.prod(self.shape))
 
+    @property
+    def is_complex(self) -> bool:
+        """One complex species (complex diffusion coefficient)."""
+        return any(isinstance(v, complex) for v in self.D)
+
+    @property
+    def precision(self) -> str:
+        return "c128" if self.is_complex else "f64"
+
     def state_shape(self) -> Tuple[int, ...]:
         return (self.s,) + tuple(self.shape[::-1])
 
@@ -108,6 +117,22 @@ def initial_data(p: Problem) -> np.ndarray:
         u[sl] = 1.0 - amp * rng.random(pshape)
         v[sl] = amp * rng.random(pshape)
         return np.stack([u, v])
+    if p.ic == "gaussian_pulses":
+        # Section 8.3: exp(-|x - c1|^2 / w) - exp(-|x - c2|^2 / w) on the grid
+        # x_i = i h (complex state, zero imaginary part).
+        w = p.ic_args.get("width", 1000.0)
+        c1, c2 = p.ic_args.get("c1", 50.0), p.ic_args.get("c2", 100.0)
+        axes = [np.arange(n) * h for n, h in zip(p.shape, p.hs())]
+        grids = np.meshgrid(*axes[::-1], indexing="ij")  # (n_d, ..., n_1)
+        r1 = sum((g - c1) ** 2 for g in grids)
+        r2 = sum((g - c2) ** 2 for g in grids)
+        u = np.exp(-r1 / w) - np.exp(-r2 / w)
+        return u[None].astype(np.complex128)
+    if p.ic == "complex_noise":
+        # Section 8.3's normal random field: real and imaginary parts
+        # standard normal, scaled by amp.
+        amp = p.ic_args.get("amp", 1.0)
+        return amp * (rng.standard_normal(shp) + 1j * rng.standard_normal(shp))
     raise ValueError(p.ic)
 
 
@@ -139,6 +164,20 @@ def schnakenberg3d_adjoint(n: int = 128, nsteps: int = 400, seed: int = 0) -> Pr
     return Problem("schnakenberg3d_adjoint", (n, n, n), ("neumann",) * 3, (1.0, 10.0), 1e-3,
                    "schnakenberg", dict(SCHNAK), nsteps, seed=seed, ic="gaussian_noise",
                    ic_args={"amp": 1e-3, "offset": SCHNAK_STEADY})
+
+
+CGL_ALPHA, CGL_BETA = 0.5, 1.3
+
+
+def cgl3d_complex(n: int = 200, nsteps: int = 100, seed: int = 0, shape=None) -> Problem:
+    """Complex Ginzburg-Landau on the periodic cube [0, 200]^3 (Section 8.3:
+    p = 200, h = 1, k = 1/20, beta = 1.3, Gaussian pulses), with linear
+    dispersion alpha = 0.5 (D = 1 + 0.5 i)."""
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    L = 200.0
+    return Problem("cgl3d_complex", shape, ("periodic",) * 3, (complex(1.0, CGL_ALPHA),), 0.05,
+                   "cgl_z", {"beta": CGL_BETA}, nsteps, h=tuple(L / m for m in shape), seed=seed,
+                   ic="gaussian_pulses", ic_args={"width": 1000.0, "c1": 50.0, "c2": 100.0})
 
 
 @dataclass
@@ -185,4 +224,5 @@ WORKLOADS = {
     "grayscott3d": grayscott3d,
     "schnakenberg3d": schnakenberg3d,
     "schnakenberg3d_adjoint": schnakenberg3d_adjoint,
+    "cgl3d_complex": cgl3d_complex,
 }

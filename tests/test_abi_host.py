@@ -98,7 +98,7 @@ def test_precision_option():
         _init((64, 64), ("periodic",) * 2, precision="f16")
     # the C ABI rejects unknown precision codes and a non-zero reserved field
     sch = etd.Scheme()
-    for prec, res in ((2, 0), (0, 1)):
+    for prec, res in ((3, 0), (0, 1)):
         sch.precision, sch.reserved = prec, res
         g = etd.Grid()
         g.d, g.s = 2, 2
@@ -110,6 +110,35 @@ def test_precision_option():
         rc = etd.lib.etd_rdp_init(ctypes.byref(g), bc, D, 0.01, ctypes.byref(sch), ctypes.byref(rx),
                                   ctypes.byref(ctx))
         assert rc == etd.ETD_ERR_ARG
+
+
+def test_complex_precision_option():
+    from paper_2001_11220_amd import etd
+    bcs = ("periodic",) * 3
+    z = _init((200, 200, 200), bcs, D=(1 + 0.5j,), k=0.05, model="cgl_z", params={"beta": 1.3},
+              h=(1.0, 1.0, 1.0), precision="c128")
+    assert [z.pass_kernel(p) for p in (1, 2, 3)] == ["k_first<4, 1, 8, true, zd>", "k_mid<4, 1, 8, true, zd>",
+                                                     "k_last<4, 1, 8, true, zd>"]
+    assert z.line_split(1) == (4, 50)
+    n = 200 ** 3
+    assert z.ws_bytes >= 6 * 16 * n and z.ws_bytes < 6 * 16 * n + (1 << 20)
+    small = _init((64, 48), ("neumann", "dirichlet"), D=(1j,), model="nls_z", params={"B": 0.0, "C": -1.0},
+                  precision="c128")
+    assert small.pass_kernel(2) == "k_last<1, 1, 8, false, zd>"
+    for p in (z, small):
+        p.close()
+    ok = dict(D=(1 + 1j,), model="cgl_z", params={"beta": 1.0}, precision="c128")
+    cases = [
+        ((300, 16), ok, etd.ETD_ERR_UNSUPPORTED),  # 300 = 60 x 5: chunks over 4 rows
+        ((64, 16), dict(ok, lines_per_wave=2), etd.ETD_ERR_UNSUPPORTED),
+        ((64, 16), dict(ok, D=(-0.1 + 1j,)), etd.ETD_ERR_ARG),  # Re D < 0
+        ((64, 16), dict(ok, precision="f64", D=(1.0,)), etd.ETD_ERR_ARG),  # complex model, real context
+        ((64, 16), dict(ok, model="cgl", D=(1.0, 1.0)), etd.ETD_ERR_ARG),  # real model, complex context
+    ]
+    for shape, kw, code in cases:
+        with pytest.raises(etd.EtdError) as ei:
+            _init(shape, ("periodic", "periodic"), **kw)
+        assert ei.value.status == code, kw
 
 
 def test_tables_build_for_stiff_coefficients():

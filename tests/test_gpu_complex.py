@@ -1,0 +1,126 @@
+"""GPU parity of the complex-species path (etd_rdp_step_z: complex diffusion
+coefficient, the Ginzburg-Landau equation with alpha != 0 and the cubic
+Schroedinger equation, Sections 8.3 and 8.4) against the FP64 oracle.
+
+Tolerances as for the real FP64 path: rel-L2 <= 1e-12 after one step and
+<= 1e-10 after 50 steps."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2001_11220_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _etd():
+    from paper_2001_11220_amd import etd
+    return etd
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def Z(shape, bcs, D, model, params, k, h=None, ic="complex_noise", amp=0.5, seed=0):
+    return W.Problem("z", tuple(shape), tuple(bcs), (complex(D),), k, model, params, 1, h=h, seed=seed,
+                     ic=ic, ic_args={"amp": amp})
+
+
+CGL = {"beta": 1.3}
+NLS = {"B": 0.4, "C": -1.0}
+CASES = [
+    Z((50, 37), ("periodic", "neumann"), 1 + 0.5j, "cgl_z", CGL, 0.05, h=(0.5, 0.5)),
+    Z((100, 150), ("dirichlet", "periodic"), 1j, "nls_z", NLS, 1e-4),
+    Z((200, 24, 36), ("periodic", "neumann", "dirichlet"), 1 - 0.8j, "cgl_z", CGL, 0.05, h=(1.0, 1.0, 1.0)),
+    Z((64, 200, 150), ("neumann", "periodic", "dirichlet"), 1j, "nls_z", NLS, 2e-5),
+    Z((40, 33, 256), ("dirichlet",) * 3, 0.3 + 2.0j, "cgl_z", CGL, 1e-4),
+    Z((2, 3, 1), ("neumann", "periodic", "dirichlet"), 1 + 1j, "cgl_z", CGL, 0.05),  # smallest lines
+]
+
+
+def run_gpu(prob, u0, nsteps, scheme="rdp"):
+    torch = _torch()
+    e = _etd().EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
+                      precision="c128", scheme=scheme)
+    names = [e.pass_kernel(p) for p in range(1, len(prob.shape) + 1)]
+    assert all(nm.endswith(", zd>") for nm in names), names
+    u = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    e.step(u, nsteps)
+    torch.cuda.synchronize()
+    e.close()
+    return u.cpu().numpy()
+
+
+@pytest.mark.parametrize("prob", CASES, ids=lambda p: f"{p.model}-{'x'.join(map(str, p.shape))}")
+def test_one_step_complex_matches_oracle(prob):
+    u0 = prob.initial()
+    got = run_gpu(prob, u0, 1)
+    ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params(), 1)
+    err = rel_l2(got, ref)
+    print(f"[complex one step] {prob.model} {prob.shape} rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-12, err
+
+
+def test_etd1_complex_matches_oracle():
+    prob = CASES[2]
+    u0 = prob.initial()
+    got = run_gpu(prob, u0, 1, scheme="etd1")
+    ref = O.etd1_if_step(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params())
+    err = rel_l2(got, ref)
+    print(f"[complex etd1] rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-12, err
+
+
+def test_50_steps_complex_matches_oracle():
+    prob = Z((48, 40, 20), ("periodic", "neumann", "periodic"), 1 + 0.5j, "cgl_z", CGL, 0.05,
+             h=(1.0, 1.0, 1.0), ic="gaussian_pulses")
+    prob.ic_args.update({"width": 100.0, "c1": 10.0, "c2": 25.0})
+    u0 = prob.initial()
+    got = run_gpu(prob, u0, 50)
+    ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params(), 50)
+    err = rel_l2(got, ref)
+    print(f"[complex 50 steps] rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-10, err
+
+
+def test_full_size_cgl3d_one_step():
+    """The benchmark workload (200^3, non-temporal stores), one step."""
+    prob = W.cgl3d_complex()
+    u0 = prob.initial()
+    got = run_gpu(prob, u0, 1)
+    ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params(), 1)
+    err = rel_l2(got, ref)
+    print(f"[complex 200^3] rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-12, err
+
+
+def test_complex_context_refuses_other_entry_points():
+    torch = _torch()
+    etd = _etd()
+    prob = CASES[0]
+    e = etd.EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
+                   precision="c128")
+    u = torch.zeros((1, 37, 50), dtype=torch.complex128, device="cuda")
+    ws = ctypes.c_void_p(e._ws_ptr())
+    rc = etd.lib.etd_rdp_step(e._ctx, ctypes.c_void_p(u.data_ptr()), ws, e.ws_bytes, 1, None)
+    assert rc == etd.ETD_ERR_ARG
+    rc = etd.lib.etd_rdp_step_f32(e._ctx, ctypes.c_void_p(u.data_ptr()), ws, e.ws_bytes, 1, None)
+    assert rc == etd.ETD_ERR_ARG
+    with pytest.raises(ValueError):
+        e.step(torch.zeros((1, 37, 50), dtype=torch.float64, device="cuda"))
+    e.close()
+    f = etd.EtdRdp((50, 37), ("periodic", "neumann"), (0.3,), 0.05, "enzyme", {})
+    x = torch.zeros((1, 37, 50), dtype=torch.float64, device="cuda")
+    rc = etd.lib.etd_rdp_step_z(f._ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(f._ws_ptr()),
+                                f.ws_bytes, 1, None)
+    assert rc == etd.ETD_ERR_ARG
+    f.close()
