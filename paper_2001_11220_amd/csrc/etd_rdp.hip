@@ -778,6 +778,11 @@ constexpr int kStreamFirstFrom = 8;
 constexpr int kStreamMidFrom = 5;
 constexpr int kStreamLastFrom = 5;
 constexpr int kStreamWaves = 16;
+// Complex species run streamed from these chunk lengths (a complex row
+// holds as many registers as two real ones).
+constexpr int kStreamFirstFromZ = 3;
+constexpr int kStreamMidFromZ = 3;
+constexpr int kStreamLastFromZ = 3;
 
 // Carried arrays of at least kNtMinBytes are written with non-temporal
 // stores: the next pass reads them only after the whole array has streamed
@@ -850,6 +855,11 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
                         T* w, const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
+  if constexpr (kIsComplex<T>) {
+    if constexpr (M >= kStreamFirstFromZ)
+      return nt ? launch_first_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
+  }
   if constexpr (M >= kMinTwoLineM) {
     if (c->P[0] == 2)
       return nt ? launch_first_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
@@ -906,6 +916,11 @@ hipError_t launch_mid(const etd_rdp_ctx* c, const T* c1, const T* c2,
                       const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
+  if constexpr (kIsComplex<T>) {
+    if constexpr (M >= kStreamMidFromZ)
+      return nt ? launch_mid_s<M, S, 1, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
+                : launch_mid_s<M, S, 1, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+  }
   if constexpr (M >= kMinTwoLineM) {
     if (c->P[1] == 2)
       return nt ? launch_mid_s<M, S, 2, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
@@ -942,6 +957,11 @@ hipError_t launch_last(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
                        const T* w, const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
+  if constexpr (kIsComplex<T>) {
+    if constexpr (M >= kStreamLastFromZ)
+      return nt ? launch_last_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_last_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
+  }
   if constexpr (M >= kMinTwoLineM) {
     if (c->P[c->d - 1] == 2)
       return nt ? launch_last_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
@@ -1323,8 +1343,11 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   if (!ctx || !name || size == 0 || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
   const int p = pass - 1, m = ctx->m[p], P = ctx->P[p];
   const bool first = (p == 0), last = (p == ctx->d - 1);
-  const bool streamed = (P == 2) || (first ? (m >= kStreamFirstFrom)
-                                           : (last ? (m >= kStreamLastFrom) : (m >= kStreamMidFrom)));
+  const bool zc = (ctx->precision == ETD_PRECISION_C128);
+  const bool streamed =
+      (P == 2) || (first ? (m >= (zc ? kStreamFirstFromZ : kStreamFirstFrom))
+                         : (last ? (m >= (zc ? kStreamLastFromZ : kStreamLastFrom))
+                                 : (m >= (zc ? kStreamMidFromZ : kStreamMidFrom))));
   const char* base = first ? "k_first" : (last ? "k_last" : "k_mid");
   const char* nt = use_nt(ctx) ? "true" : "false";
   // Streamed pass 1 also carries the scheme (true: the ETD1 predictor alone).
