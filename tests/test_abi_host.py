@@ -117,8 +117,10 @@ def test_complex_precision_option():
     bcs = ("periodic",) * 3
     z = _init((200, 200, 200), bcs, D=(1 + 0.5j,), k=0.05, model="cgl_z", params={"beta": 1.3},
               h=(1.0, 1.0, 1.0), precision="c128")
-    assert [z.pass_kernel(p) for p in (1, 2, 3)] == ["k_first<4, 1, 8, true, zd>", "k_mid<4, 1, 8, true, zd>",
-                                                     "k_last<4, 1, 8, true, zd>"]
+    # chunk length 4: the streamed passes (16-line tiles, one line per wavefront)
+    assert [z.pass_kernel(p) for p in (1, 2, 3)] == ["k_first_s<4, 1, 16, 1, true, false, zd>",
+                                                     "k_mid_s<4, 1, 16, 1, true, zd>",
+                                                     "k_last_s<4, 1, 16, 1, true, zd>"]
     assert z.line_split(1) == (4, 50)
     n = 200 ** 3
     assert z.ws_bytes >= 6 * 16 * n and z.ws_bytes < 6 * 16 * n + (1 << 20)
