@@ -12,8 +12,10 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  - Arithmetic is IEEE FP64 throughout.
- *  - A state is a contiguous, caller-owned device array of s * N doubles,
+ *  - Arithmetic is IEEE FP64 unless a context is created with another
+ *    etd_scheme_t.precision (FP32, or complex FP64 for complex species).
+ *  - A state is a contiguous, caller-owned device array of s * N doubles
+ *    (floats, or interleaved complex pairs, for the other precisions),
  *    N = n[0] * ... * n[d-1], laid out species-planar:
  *        u[sigma][i_d]...[i_2][i_1],  i_1 (axis 1) fastest.
  *    Axis i is the axis of the paper's A_i (eq. Ai): axis 1 carries B_p in the
