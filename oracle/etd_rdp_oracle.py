@@ -208,10 +208,15 @@ def reaction(model: str, params: dict, U: np.ndarray) -> np.ndarray:
     if model == "nls_z":
         # Cubic Schroedinger equation i psi_t + Lap psi = q psi with
         # q = B + C |psi|^2, written as psi_t = i Lap psi - i q psi
-        # (D = i, Section 8.4); B and C constant here.
+        # (D = i, Section 8.4).  An optional per-cell field (params["Bfield"],
+        # shaped like one species) is added to the constant B: the spatially
+        # varying B(x, y) of the 2-D example.
         B, C = params["B"], params["C"]
-        u = U
-        return -1j * (B + C * (u * np.conj(u)).real) * u
+        Bf = params.get("Bfield")
+        q = B + C * (U * np.conj(U)).real
+        if Bf is not None:
+            q = q + np.asarray(Bf, dtype=np.float64)
+        return -1j * q * U
     raise ValueError(model)
 
 

@@ -137,3 +137,39 @@ def test_cgl_conjugation_symmetry():
     np.testing.assert_allclose(a, np.conj(b), rtol=1e-13, atol=1e-14)
     c = O.etd_rdp_if_step(U, k, [1.0 - 0.8j], bcs, hs, "cgl_z", {"beta": 1.3})
     assert np.max(np.abs(a - c)) > 1e-3  # alpha's sign matters
+
+
+def _nls2d_exact_error(n, k, T=1.0):
+    """Section 8.4, 2-D Schroedinger example: Neumann unit square,
+    q = B(x, y) + C |psi|^2 with B = (1 - 2 pi^2)(1 - cos^2(pi x) cos^2(pi y)),
+    C = 1 - 2 pi^2, exact solution psi = exp(-i t) cos(pi x) cos(pi y).
+    Max error at t = T."""
+    h = 1.0 / (n - 1)
+    c = np.cos(np.pi * np.arange(n) * h)
+    psi0 = np.multiply.outer(c, c)  # (y, x)
+    C = 1.0 - 2.0 * np.pi ** 2
+    field = C * (1.0 - psi0 ** 2)
+    U = O.etd_rdp_if_run(psi0[None].astype(complex), k, [1j], ["neumann"] * 2, [h, h], "nls_z",
+                         {"B": 0.0, "C": C, "Bfield": field}, int(round(T / k)))
+    return float(np.max(np.abs(U[0] - np.exp(-1j * T) * psi0)))
+
+
+def test_schroedinger_2d_field_converges_second_order_to_exact_solution():
+    errs = [_nls2d_exact_error(n, k) for n, k in ((21, 0.004), (41, 0.002), (81, 0.001))]
+    eoc = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.85 <= e <= 2.3 for e in eoc), (errs, eoc)
+    assert errs[-1] < 5e-3, errs
+
+
+def test_constant_field_equals_constant_B():
+    rng = np.random.default_rng(4)
+    U = rng.standard_normal((1, 6, 9)) + 1j * rng.standard_normal((1, 6, 9))
+    bcs, hs, k = ["neumann", "dirichlet"], [0.2, 0.3], 0.01
+    a = O.etd_rdp_if_step(U, k, [1j], bcs, hs, "nls_z", {"B": 0.7, "C": -1.1})
+    b = O.etd_rdp_if_step(U, k, [1j], bcs, hs, "nls_z", {"B": 0.0, "C": -1.1, "Bfield": np.full((6, 9), 0.7)})
+    np.testing.assert_allclose(a, b, rtol=1e-15, atol=1e-15)
+    # and a non-constant field changes the result where it differs
+    f = np.full((6, 9), 0.7)
+    f[2, 3] = 2.0
+    c = O.etd_rdp_if_step(U, k, [1j], bcs, hs, "nls_z", {"B": 0.0, "C": -1.1, "Bfield": f})
+    assert abs(c[0, 2, 3] - a[0, 2, 3]) > 1e-4
