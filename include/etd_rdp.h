@@ -97,7 +97,10 @@ typedef struct etd_grid_t {
 
 typedef struct etd_reaction_t {
   int32_t model;                    /* ETD_RX_*                              */
-  int32_t pad_;
+  int32_t field;                    /* 1: a per-cell field b(x) is added to
+                                       ETD_RX_NLS_Z's B (Section 8.4's 2-D
+                                       example), set with etd_rdp_set_field;
+                                       0 otherwise (other models: must be 0) */
   double params[ETD_MAX_PARAMS];    /* model parameters (see ETD_RX_*)       */
   double shift[ETD_MAX_SPECIES];    /* F evaluated at u + shift              */
 } etd_reaction_t;
@@ -259,6 +262,21 @@ int etd_rdp_run_pass_f32(etd_rdp_ctx* ctx, float* u, void* ws, size_t ws_bytes,
 /* etd_rdp_run_pass for an ETD_PRECISION_C128 context (u as etd_rdp_step_z). */
 int etd_rdp_run_pass_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                        int32_t pass, void* stream);
+
+/*
+ * etd_rdp_set_field -- store the per-cell reaction field b (Section 8.4:
+ * q = B + b(x) + C |u|^2) of a context created with etd_reaction_t.field = 1
+ * in the workspace ws, on `stream`.
+ *  b  : device, N doubles in the layout of one species of u; read only
+ *       during the call's stream work (the library keeps two copies in ws,
+ *       one in the layout each reading pass uses).
+ * Steps on that context must use this workspace afterwards (another
+ * workspace: ETD_ERR_ARG until set_field is called for it).
+ * Errors: ETD_ERR_ARG (NULL pointers, a context without a field),
+ * ETD_ERR_WORKSPACE, ETD_ERR_HIP.
+ */
+int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double* b,
+                      void* stream);
 
 /*
  * etd_rdp_apply_solve -- x <- (I + (k/gamma) D_sigma A_axis)^{-1} x for a

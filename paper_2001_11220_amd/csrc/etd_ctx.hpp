@@ -37,6 +37,9 @@ struct etd_rdp_ctx {
   size_t tab_bytes = 0, arr_bytes = 0, ws_bytes = 0;
   size_t part_bytes = 0, adj_ws_bytes = 0;
   const void* uploaded_ws = nullptr;
+  bool has_field = false;        // per-cell reaction field (two copies in ws)
+  size_t field_off = 0, field_bytes = 0;
+  const void* field_ws = nullptr;  // workspace the field was last stored in
   int last_hip = 0;
 };
 

@@ -63,6 +63,11 @@ struct Rx {
   int pad;
   double p[16];
   double shift[2];
+  // Per-cell reaction field (added to the Schroedinger model's B), in the
+  // layout pass 1 reads (fld1) and the one pass d reads (fldd); null when
+  // the problem has none.
+  const double* fld1;
+  const double* fldd;
 };
 
 template <int S, typename T>
@@ -70,9 +75,10 @@ __device__ __forceinline__ void react_real(const Rx& rx, const T (&uin)[S], T (&
 
 // F(u + shift) at one cell.  The model id is uniform across the launch.
 // Complex species (the Ginzburg-Landau and Schroedinger models) have no
-// shift.
+// shift; bf is the cell's value of the reaction field (0 without one).
 template <int S, typename T = double>
-__device__ __forceinline__ void react(const Rx& rx, const T (&uin)[S], T (&f)[S]) {
+__device__ __forceinline__ void react(const Rx& rx, const T (&uin)[S], T (&f)[S],
+                                      double bf = 0.0) {
   if constexpr (kIsComplex<T>) {
 #pragma unroll
     for (int i = 0; i < S; ++i) {
@@ -83,8 +89,8 @@ __device__ __forceinline__ void react(const Rx& rx, const T (&uin)[S], T (&f)[S]
         const double beta = rx.p[0];
         f[i] = zd(fma(-m2, fma(-beta, u.im, u.re), u.re), fma(-m2, fma(beta, u.re, u.im), u.im));
       } else {
-        // -i q u with q = B + C |u|^2
-        const double q = fma(rx.p[1], m2, rx.p[0]);
+        // -i q u with q = B + b(x) + C |u|^2
+        const double q = fma(rx.p[1], m2, rx.p[0] + bf);
         f[i] = zd(q * u.im, -q * u.re);
       }
     }

@@ -18,6 +18,7 @@
 // etd_device.hpp).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -42,6 +43,19 @@ namespace etd {
 // A tile is 8 or 16 lines (kLinesFor) with adjacent indices in the output's
 // fastest dimension, so every transposed row write is a run of adjacent
 // doubles.
+
+// This lane's chunk of the reaction field on its line (zeros without a
+// field).  Only complex species carry one; for the others it is zeros at
+// compile time.
+template <int M, int P, typename T>
+__device__ __forceinline__ void field_line(const double* fld, double (&bf)[M], const PassGeom& g,
+                                           const TileAt& pos) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) bf[j] = 0.0;
+  if constexpr (kIsComplex<T>) {
+    if (fld) line_load<M, P>(fld, bf, g, pos);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Pass 1 (axis 1).  Tiles of 8 or 16 x-lines with adjacent y; the next
@@ -81,12 +95,14 @@ __global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void k_first(
     for (int s = 0; s < S; ++s)
 #pragma unroll
       for (int j = 0; j < M; ++j) U[s][j] = Un[s][j];
+    double bf[M];
+    field_line<M, 1, T>(rx.fld1, bf, g, pos);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       T uu[S], ff[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) uu[s] = U[s][j];
-      react<S>(rx, uu, ff);
+      react<S>(rx, uu, ff, bf[j]);
 #pragma unroll
       for (int s = 0; s < S; ++s) f[s][j] = ff[s];
     }
@@ -290,13 +306,13 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
 // ---------------------------------------------------------------------------
 template <int S, int M, typename T>
 __device__ __forceinline__ void react_species(const Rx& rx, const T (&U)[S][M], int s,
-                                              T (&f)[M]) {
+                                              const double (&bf)[M], T (&f)[M]) {
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     T uu[S], ff[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) uu[q] = U[q][j];
-    react<S>(rx, uu, ff);
+    react<S>(rx, uu, ff, bf[j]);
     f[j] = ff[s];
   }
 }
@@ -376,7 +392,9 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
         for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, U[q], g, pos);
       }
       T f[M];
-      react_species<S, M>(rx, U, s, f);
+      double bf[M];
+      field_line<M, P, T>(rx.fld1, bf, g, pos);
+      react_species<S, M>(rx, U, s, bf, f);
       const int64_t pf = have_next ? next : tile;
       first_p_phase(U[s], f, s, pos, E1 && s == S - 1, pf);
       if (!E1) {
@@ -433,14 +451,18 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
       for (int s = 0; s < S; ++s) tile_store<M, L, P, NT>(u + s * g.N, us[s], tl, g, pos, cur);
       continue;
     }
+    {
+      double bf[M];
+      field_line<M, P, T>(rx.fldd, bf, g, pos);
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      T uu[S], ff[S];
+      for (int j = 0; j < M; ++j) {
+        T uu[S], ff[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) uu[s] = us[s][j];
-      react<S>(rx, uu, ff);
+        for (int s = 0; s < S; ++s) uu[s] = us[s][j];
+        react<S>(rx, uu, ff, bf[j]);
 #pragma unroll
-      for (int s = 0; s < S; ++s) us[s][j] = ff[s];
+        for (int s = 0; s < S; ++s) us[s][j] = ff[s];
+      }
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -530,12 +552,14 @@ __global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void k_last(
       continue;
     }
     // us holds U*; f* = F(U*) overwrites it.
+    double bf[M];
+    field_line<M, 1, T>(rx.fldd, bf, g, pos);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       T uu[S], ff[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) uu[s] = us[s][j];
-      react<S>(rx, uu, ff);
+      react<S>(rx, uu, ff, bf[j]);
 #pragma unroll
       for (int s = 0; s < S; ++s) us[s][j] = ff[s];
     }
@@ -629,6 +653,21 @@ __global__ __launch_bounds__(kBlock) void k_solve_strided(
 using namespace etd;
 
 namespace etd {
+
+// The reaction field in the layout the last pass reads its lines in:
+// out[i_1][i_2][i_3] = in[i_3][i_2][i_1] (3-D; n3 = 1 in 2-D gives
+// out[i_1][i_2] = in[i_2][i_1]).  Runs once per set_field call.
+__global__ __launch_bounds__(256) void k_field_last_layout(const double* __restrict__ in,
+                                                           double* __restrict__ out, int64_t n1,
+                                                           int64_t n2, int64_t n3) {
+  const int64_t N = n1 * n2 * n3;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < N;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = o % n3, r = o / n3;
+    const int64_t y = r % n2, x = r / n2;
+    out[o] = in[(z * n2 + y) * n1 + x];
+  }
+}
 
 int hip_fail(etd_rdp_ctx* c, hipError_t e) {
   if (c) c->last_hip = static_cast<int>(e);
@@ -1056,6 +1095,12 @@ int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream
   const TabOf<T>* tabs = static_cast<const TabOf<T>*>(ws);
   T* const A[3] = {ws_array<T>(c, ws, 0), ws_array<T>(c, ws, 1), ws_array<T>(c, ws, 2)};
   T* const B[3] = {ws_array<T>(c, ws, 3), ws_array<T>(c, ws, 4), ws_array<T>(c, ws, 5)};
+  // The reaction field's two copies (pass 1's layout, pass d's layout).
+  c->rx.fld1 = c->has_field ? reinterpret_cast<const double*>(static_cast<char*>(ws) + c->field_off)
+                            : nullptr;
+  c->rx.fldd = c->has_field ? reinterpret_cast<const double*>(static_cast<char*>(ws) + c->field_off +
+                                                              c->field_bytes)
+                            : nullptr;
   for (int p = first; p < npasses; ++p) {
     const bool into_b = (p == 1 && c->d == 3);
     const bool from_b = (p == 2);
@@ -1074,6 +1119,7 @@ template <typename T>
 int step_impl(etd_rdp_ctx* ctx, T* u, void* ws, size_t ws_bytes, int64_t nsteps, void* stream) {
   if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;
   if (elem_bytes(ctx) != sizeof(T)) return ETD_ERR_ARG;  // the context's precision
+  if (ctx->has_field && ctx->field_ws != ws) return ETD_ERR_ARG;  // field not stored in ws
   int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   if (nsteps == 0) return ETD_OK;
@@ -1091,6 +1137,7 @@ template <typename T>
 int run_pass_impl(etd_rdp_ctx* ctx, T* u, void* ws, size_t ws_bytes, int32_t pass, void* stream) {
   if (!ctx || !u || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
   if (elem_bytes(ctx) != sizeof(T)) return ETD_ERR_ARG;
+  if (ctx->has_field && ctx->field_ws != ws) return ETD_ERR_ARG;
   int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1147,6 +1194,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   for (int i = 0; i < s; ++i)
     if (!std::isfinite(rx->shift[i]) || (cplx && rx->shift[i] != 0.0)) return ETD_ERR_ARG;
   if (cplx && lpw == ETD_LINES_TWO) return ETD_ERR_UNSUPPORTED;
+  if (rx->field != 0 && (rx->field != 1 || rx->model != ETD_RX_NLS_Z)) return ETD_ERR_ARG;
 
   etd_rdp_ctx* c = new (std::nothrow) etd_rdp_ctx();
   if (!c) return ETD_ERR_INTERNAL;
@@ -1227,6 +1275,12 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   c->tab_bytes = round_up(cplx ? c->tabz.size() * sizeof(SolveTabZ) : c->tabs.size() * sizeof(SolveTab), 256);
   c->arr_bytes = round_up(elem_bytes(c) * static_cast<size_t>(N) * s, 256);
   c->ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes;
+  if (rx->field) {
+    c->has_field = true;
+    c->field_off = c->ws_bytes;
+    c->field_bytes = round_up(sizeof(double) * static_cast<size_t>(N), 256);
+    c->ws_bytes += 2 * c->field_bytes;
+  }
   c->nparams = reaction_param_count(rx->model, s);
   c->part_bytes = round_up(sizeof(double) * kAdjPasses * kAdjMaxBlocks * kGradSlots, 256);
   c->adj_ws_bytes = c->tab_bytes + (d == 3 ? 9 : 6) * c->arr_bytes + c->part_bytes;
@@ -1316,6 +1370,28 @@ int etd_rdp_run_pass_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, i
                        void* stream) {
   if (reinterpret_cast<uintptr_t>(u) % alignof(zd) != 0) return ETD_ERR_ARG;
   return run_pass_impl(ctx, reinterpret_cast<zd*>(u), ws, ws_bytes, pass, stream);
+}
+
+int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double* b,
+                      void* stream) {
+  if (!ctx || !b || !ctx->has_field) return ETD_ERR_ARG;
+  int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws) + ctx->field_off;
+  double* f1 = reinterpret_cast<double*>(base);
+  double* fd = reinterpret_cast<double*>(base + ctx->field_bytes);
+  const int64_t N = ctx->N;
+  hipError_t e = hipMemcpyAsync(f1, b, sizeof(double) * static_cast<size_t>(N),
+                                hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  const int64_t blocks = std::min<int64_t>((N + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_field_last_layout, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, b,
+                     fd, ctx->n[0], ctx->n[1], ctx->d == 3 ? ctx->n[2] : int64_t(1));
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  ctx->field_ws = ws;
+  return ETD_OK;
 }
 
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, int32_t axis,

@@ -41,7 +41,7 @@ class Grid(ctypes.Structure):
 
 
 class Reaction(ctypes.Structure):
-    _fields_ = [("model", ctypes.c_int32), ("pad_", ctypes.c_int32),
+    _fields_ = [("model", ctypes.c_int32), ("field", ctypes.c_int32),
                 ("params", ctypes.c_double * MAX_PARAMS),
                 ("shift", ctypes.c_double * MAX_SPECIES)]
 
@@ -82,6 +82,7 @@ def _load():
         "etd_rdp_run_pass": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_run_pass_f32": (ctypes.c_int, [P, P, P, SZ, I32, P]),
         "etd_rdp_run_pass_z": (ctypes.c_int, [P, P, P, SZ, I32, P]),
+        "etd_rdp_set_field": (ctypes.c_int, [P, P, SZ, P, P]),
         "etd_rdp_apply_solve": (ctypes.c_int, [P, P, P, SZ, I32, I32, I32, P]),
         "etd_rdp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "etd_rdp_last_hip_error": (ctypes.c_int, [P]),
@@ -150,7 +151,7 @@ class EtdRdp:
     """
 
     def __init__(self, shape, bcs, D, k, model, params, h=None, shift=None,
-                 scheme="rdp", device=None, lines_per_wave="auto", precision="f64"):
+                 scheme="rdp", device=None, lines_per_wave="auto", precision="f64", field=False):
         d = len(shape)
         s = len(D)
         g = Grid()
@@ -171,6 +172,7 @@ class EtdRdp:
         sch.precision = PRECISIONS[precision]
         self.precision = precision
         rx = reaction_struct(model, params, shift, s)
+        rx.field = 1 if field else 0
         ctx = ctypes.c_void_p()
         _check(lib.etd_rdp_init(ctypes.byref(g), bc_arr, ctypes.cast(D_arr, ctypes.POINTER(ctypes.c_double)),
                                 float(k), ctypes.byref(sch),
@@ -292,6 +294,18 @@ class EtdRdp:
         _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
                   self.ws_bytes, int(nsteps), self._stream(stream)), name)
         return u
+
+    def set_field(self, b, stream=None):
+        """Store the per-cell reaction field ``b`` (a float64 device tensor
+        shaped like one species, ``shape[::-1]``) of a ``field=True``
+        problem in this object's workspace."""
+        import torch
+        want = self.shape[::-1]
+        if b.dtype != torch.float64 or not b.is_cuda or not b.is_contiguous() or tuple(b.shape) != want:
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {want}")
+        _check(lib.etd_rdp_set_field(self._ctx, ctypes.c_void_p(self._ws_ptr()), self.ws_bytes,
+                                     ctypes.c_void_p(b.data_ptr()), self._stream(stream)), "etd_rdp_set_field")
+        self._field_ref = b  # the copy is asynchronous on the stream
 
     def debug_passes(self, u, npasses, stream=None):
         p = self._state_ptr(u, self.s)

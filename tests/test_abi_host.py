@@ -143,6 +143,22 @@ def test_complex_precision_option():
         assert ei.value.status == code, kw
 
 
+def test_reaction_field_option():
+    from paper_2001_11220_amd import etd
+    kw = dict(D=(1j,), model="nls_z", params={"B": 0.0, "C": -1.0}, precision="c128")
+    plain = _init((81, 81), ("neumann", "neumann"), **kw)
+    etd_f = _lib().EtdRdp((81, 81), ("neumann", "neumann"), (1j,), 0.01, "nls_z", {"B": 0.0, "C": -1.0},
+                          precision="c128", field=True)
+    # two copies of the N-double field (each rounded up to 256 bytes)
+    assert etd_f.ws_bytes - plain.ws_bytes == 2 * ((8 * 81 * 81 + 255) // 256 * 256)
+    plain.close()
+    etd_f.close()
+    with pytest.raises(etd.EtdError) as ei:  # a field only for the Schroedinger model
+        _lib().EtdRdp((64, 16), ("periodic",) * 2, (1 + 1j,), 0.01, "cgl_z", {"beta": 1.0}, precision="c128",
+                      field=True)
+    assert ei.value.status == etd.ETD_ERR_ARG
+
+
 def test_tables_build_for_stiff_coefficients():
     # r = k D / h^2 up to ~5e6 still passes the residual self-check
     for D in (1e-9, 1.0, 1e3):

@@ -124,3 +124,68 @@ def test_complex_context_refuses_other_entry_points():
                                 f.ws_bytes, 1, None)
     assert rc == etd.ETD_ERR_ARG
     f.close()
+
+
+def _field_run(prob, u0, field, nsteps):
+    torch = _torch()
+    e = _etd().EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
+                      precision="c128", field=True)
+    u = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    e.set_field(torch.from_numpy(np.ascontiguousarray(field)).cuda())
+    e.step(u, nsteps)
+    torch.cuda.synchronize()
+    e.close()
+    return u.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape,bcs", [((40, 33, 24), ("neumann", "periodic", "dirichlet")),
+                                       ((50, 37), ("periodic", "neumann")),
+                                       ((150, 12, 200), ("dirichlet", "neumann", "periodic"))])
+def test_reaction_field_one_step_matches_oracle(shape, bcs):
+    prob = Z(shape, bcs, 1j, "nls_z", NLS, 1e-4)
+    u0 = prob.initial()
+    rng = np.random.default_rng(7)
+    field = rng.standard_normal(shape[::-1])
+    got = _field_run(prob, u0, field, 1)
+    p = dict(prob.oracle_params(), Bfield=field)
+    ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, p, 1)
+    err = rel_l2(got, ref)
+    print(f"[complex field one step] {shape} rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-12, err
+
+
+def test_schroedinger_2d_example_matches_oracle():
+    """Section 8.4's 2-D example on the Neumann unit square (81^2, k = 0.0125,
+    T = 1): the GPU run against the oracle's, and both near the exact
+    solution exp(-i t) cos(pi x) cos(pi y) as the oracle is at this k."""
+    n, k = 81, 0.0125
+    h = 1.0 / (n - 1)
+    c = np.cos(np.pi * np.arange(n) * h)
+    psi0 = np.multiply.outer(c, c)
+    C = 1.0 - 2.0 * np.pi ** 2
+    field = C * (1.0 - psi0 ** 2)
+    prob = W.Problem("nls2d", (n, n), ("neumann", "neumann"), (1j,), k, "nls_z", {"B": 0.0, "C": C}, 80,
+                     h=(h, h))
+    u0 = psi0[None].astype(complex)
+    got = _field_run(prob, u0, field, 80)
+    ref = O.etd_rdp_if_run(u0, k, prob.D, prob.bcs, prob.hs(), "nls_z", {"B": 0.0, "C": C, "Bfield": field}, 80)
+    err = rel_l2(got, ref)
+    print(f"[complex 2-D Schroedinger, 80 steps] rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-10, err
+
+
+def test_field_must_be_set_in_the_stepping_workspace():
+    torch = _torch()
+    etd = _etd()
+    prob = Z((50, 37), ("periodic", "neumann"), 1j, "nls_z", NLS, 1e-4)
+    e = etd.EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, precision="c128",
+                   field=True)
+    u = torch.zeros((1, 37, 50), dtype=torch.complex128, device="cuda")
+    with pytest.raises(etd.EtdError) as ei:
+        e.step(u, 1)  # no field stored yet
+    assert ei.value.status == etd.ETD_ERR_ARG
+    e.close()
+    f = etd.EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, precision="c128")
+    with pytest.raises(etd.EtdError):
+        f.set_field(torch.zeros((37, 50), dtype=torch.float64, device="cuda"))  # no field declared
+    f.close()
