@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--pass-steps", type=int, default=50)
     ap.add_argument("--checkpoint-every", type=int, default=20,
                     help="gradient workload: steps between stored states")
+    ap.add_argument("--n", type=int, default=None,
+                    help="grid points per axis (default: the workload's own size)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
                     help="arithmetic and storage type of the single-problem workloads")
     ap.add_argument("--calib-copy", action="store_true",
@@ -112,7 +114,7 @@ def main():
         return bench_ensemble(args)
     if args.workload == "schnakenberg3d_adjoint":
         return bench_adjoint(args)
-    prob = W.WORKLOADS[args.workload]()
+    prob = W.WORKLOADS[args.workload](**({"n": args.n} if args.n else {}))
     if args.steps is None:
         args.steps = prob.nsteps
     torch.cuda.set_device(0)
@@ -334,7 +336,7 @@ def bench_adjoint(args):
     from paper_2001_11220_amd.adjoint import trajectory
     from paper_2001_11220_amd.etd import EtdRdp
 
-    prob = W.schnakenberg3d_adjoint()
+    prob = W.schnakenberg3d_adjoint(**({"n": args.n} if args.n else {}))
     steps = args.steps if args.steps is not None else prob.nsteps
     every = args.checkpoint_every
     torch.cuda.set_device(0)
