@@ -127,8 +127,8 @@ typedef struct etd_reaction_t {
  * (re, im) pairs with Re D >= 0, the model is ETD_RX_CGL_Z or ETD_RX_NLS_Z
  * (and those models need this precision), shift must be 0.  Every solve is
  * a complex line solve.  Lines run one per wavefront (ETD_LINES_TWO is
- * ETD_ERR_UNSUPPORTED) with chunks of at most 4 rows, so n <= 256 per axis
- * (ETD_ERR_UNSUPPORTED otherwise).  Step with etd_rdp_step_z /
+ * ETD_ERR_UNSUPPORTED), with the same line lengths as real species.  Step
+ * with etd_rdp_step_z /
  * etd_rdp_run_pass_z; the other entry points return ETD_ERR_ARG or
  * ETD_ERR_UNSUPPORTED for such a context. */
 #define ETD_PRECISION_C128 2

@@ -53,9 +53,6 @@ inline size_t elem_bytes(const etd_rdp_ctx* c) {
   return c->precision == ETD_PRECISION_F32 ? sizeof(float) : sizeof(double);
 }
 
-// Longest chunk complex species run (n <= 4 * 64 rows per line).
-constexpr int kMaxComplexM = 4;
-
 // Two lines per wavefront: an axis whose lines are n = 32 m rows with
 // m in [kMinTwoLineM, kMaxM] runs its forward pass with 32 chunks of m rows
 // per line and two lines per wavefront (the streamed kernels); returns m, or

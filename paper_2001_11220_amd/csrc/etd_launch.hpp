@@ -62,6 +62,14 @@ constexpr int kPassLines = kIsComplex<T> ? 8 : kLinesFor<M>;
 template <int M, typename T>
 constexpr int kPassWaves = kIsComplex<T> ? 2 : kMinWaves<M>;
 
+// Streamed passes: 16 waves per block, asking for 4 per SIMD (128
+// registers); complex chunks of more than 4 rows: 8 waves per block and 2 per
+// SIMD (256 registers).
+template <int M, typename T>
+constexpr int kStreamBlockWaves = (kIsComplex<T> && M > 4) ? 8 : 16;
+template <int M, typename T>
+constexpr int kStreamSimdWaves = (kIsComplex<T> && M > 4) ? 2 : 4;
+
 // LDS pitch of a line of n rows in a tile buffer: n rounded up to 8 (mod 32)
 // doubles, so that the transposes are bank-conflict free.
 inline int tile_pitch(int n) { return n + ((8 - n % 32) + 32) % 32; }
@@ -88,15 +96,6 @@ inline int tile_buffers(size_t fixed_lds, int lines, int tile_elems, size_t elem
     default: return ETD_ERR_INTERNAL;               \
   }
 
-// The same for the chunk lengths complex species run (1..4).
-#define ETD_DISPATCH_M4(m, CALL) \
-  switch (m) {                  \
-    case 1: { constexpr int M_ = 1; CALL; } break; \
-    case 2: { constexpr int M_ = 2; CALL; } break; \
-    case 3: { constexpr int M_ = 3; CALL; } break; \
-    case 4: { constexpr int M_ = 4; CALL; } break; \
-    default: return ETD_ERR_UNSUPPORTED;            \
-  }
 
 
 }  // namespace etd

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void k_mid(
 // chunks.
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, int P, bool NT, typename T>
-__global__ __launch_bounds__(64 * L / P, 4) void k_mid_s(
+__global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_mid_s(
     const T* __restrict__ c1, const T* __restrict__ c2,
     const T* __restrict__ w, T* __restrict__ o1, T* __restrict__ o2,
     T* __restrict__ ow, const TabOf<T>* __restrict__ tabs, PassGeom g, int etd1) {
@@ -318,7 +318,7 @@ __device__ __forceinline__ void react_species(const Rx& rx, const T (&U)[S][M], 
 }
 
 template <int M, int S, int L, int P, bool NT, bool E1, typename T>
-__global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
+__global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_first_s(
     const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
     T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g) {
   extern __shared__ double lds_raw[];
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(64 * L / P, 4) void k_first_s(
 // budget.
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, int P, bool NT, typename T>
-__global__ __launch_bounds__(64 * L / P, 4) void k_last_s(
+__global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_last_s(
     T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
     const T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k,
     PassGeom g, int etd1) {
@@ -838,16 +838,17 @@ template <int M, int S, int P, bool NT, typename T>
 hipError_t launch_first_s(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
                           T* w, const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
-  constexpr int L = kStreamWaves * P;
+  constexpr int W = kStreamBlockWaves<M, T>;
+  constexpr int L = W * P;
   const PassGeom g = pass_geom(c, kPassFirst, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   auto go = [&](auto kern) {
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
     unsigned grid;
-    e = persistent_grid(kern, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+    e = persistent_grid(kern, lds, g.nFblk * g.nT, &grid, 64 * W);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), lds, st, u, c1, c2, w, tabs,
                        c->rx, static_cast<T>(c->k), g);
     return hipGetLastError();
   };
@@ -859,15 +860,16 @@ template <int M, int S, int P, bool NT, typename T>
 hipError_t launch_last_s(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
                          const T* w, const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
-  constexpr int L = kStreamWaves * P;
+  constexpr int W = kStreamBlockWaves<M, T>;
+  constexpr int L = W * P;
   const PassGeom g = pass_geom(c, kPassLast, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_last_s<M, S, L, P, NT, T>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_last_s<M, S, L, P, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+  e = persistent_grid(k_last_s<M, S, L, P, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * W);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_last_s<M, S, L, P, NT, T>), dim3(grid), dim3(64 * kStreamWaves), lds, st, u, c1, c2, w, tabs,
+  hipLaunchKernelGGL((k_last_s<M, S, L, P, NT, T>), dim3(grid), dim3(64 * W), lds, st, u, c1, c2, w, tabs,
                      c->rx, static_cast<T>(c->k), g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
@@ -894,22 +896,22 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
                         T* w, const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
-  if constexpr (kIsComplex<T>) {
-    if constexpr (M >= kStreamFirstFromZ)
-      return nt ? launch_first_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
-                : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
-  }
-  if constexpr (M >= kMinTwoLineM) {
-    if (c->P[0] == 2)
-      return nt ? launch_first_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
-                : launch_first_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
-  }
-  if constexpr (M >= kStreamFirstFrom) {
+  if constexpr (kIsComplex<T> && M >= kStreamFirstFromZ) {
     return nt ? launch_first_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
               : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
-    return nt ? launch_first_n<M, S, true, T>(c, u, c1, c2, w, tabs, st)
-              : launch_first_n<M, S, false, T>(c, u, c1, c2, w, tabs, st);
+    if constexpr (M >= kMinTwoLineM) {
+      if (c->P[0] == 2)
+        return nt ? launch_first_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
+                  : launch_first_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
+    }
+    if constexpr (M >= kStreamFirstFrom) {
+      return nt ? launch_first_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
+    } else {
+      return nt ? launch_first_n<M, S, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_first_n<M, S, false, T>(c, u, c1, c2, w, tabs, st);
+    }
   }
 }
 
@@ -918,15 +920,16 @@ hipError_t launch_mid_s(const etd_rdp_ctx* c, const T* c1, const T* c2,
                         const T* w, T* o1, T* o2, T* ow,
                         const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
-  constexpr int L = kStreamWaves * P;
+  constexpr int W = kStreamBlockWaves<M, T>;
+  constexpr int L = W * P;
   const PassGeom g = pass_geom(c, kPassMid, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_mid_s<M, S, L, P, NT, T>, lds);
   if (e != hipSuccess) return e;
   unsigned grid;
-  e = persistent_grid(k_mid_s<M, S, L, P, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * kStreamWaves);
+  e = persistent_grid(k_mid_s<M, S, L, P, NT, T>, lds, g.nFblk * g.nT, &grid, 64 * W);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid_s<M, S, L, P, NT, T>), dim3(grid), dim3(64 * kStreamWaves), lds, st, c1, c2, w, o1, o2,
+  hipLaunchKernelGGL((k_mid_s<M, S, L, P, NT, T>), dim3(grid), dim3(64 * W), lds, st, c1, c2, w, o1, o2,
                      ow, tabs, g, c->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
@@ -955,22 +958,22 @@ hipError_t launch_mid(const etd_rdp_ctx* c, const T* c1, const T* c2,
                       const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
-  if constexpr (kIsComplex<T>) {
-    if constexpr (M >= kStreamMidFromZ)
-      return nt ? launch_mid_s<M, S, 1, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
-                : launch_mid_s<M, S, 1, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
-  }
-  if constexpr (M >= kMinTwoLineM) {
-    if (c->P[1] == 2)
-      return nt ? launch_mid_s<M, S, 2, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
-                : launch_mid_s<M, S, 2, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
-  }
-  if constexpr (M >= kStreamMidFrom) {
+  if constexpr (kIsComplex<T> && M >= kStreamMidFromZ) {
     return nt ? launch_mid_s<M, S, 1, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
               : launch_mid_s<M, S, 1, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
   } else {
-    return nt ? launch_mid_n<M, S, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
-              : launch_mid_n<M, S, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    if constexpr (M >= kMinTwoLineM) {
+      if (c->P[1] == 2)
+        return nt ? launch_mid_s<M, S, 2, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
+                  : launch_mid_s<M, S, 2, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    }
+    if constexpr (M >= kStreamMidFrom) {
+      return nt ? launch_mid_s<M, S, 1, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
+                : launch_mid_s<M, S, 1, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    } else {
+      return nt ? launch_mid_n<M, S, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
+                : launch_mid_n<M, S, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    }
   }
 }
 
@@ -996,22 +999,22 @@ hipError_t launch_last(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
                        const T* w, const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
-  if constexpr (kIsComplex<T>) {
-    if constexpr (M >= kStreamLastFromZ)
-      return nt ? launch_last_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
-                : launch_last_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
-  }
-  if constexpr (M >= kMinTwoLineM) {
-    if (c->P[c->d - 1] == 2)
-      return nt ? launch_last_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
-                : launch_last_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
-  }
-  if constexpr (M >= kStreamLastFrom) {
+  if constexpr (kIsComplex<T> && M >= kStreamLastFromZ) {
     return nt ? launch_last_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
               : launch_last_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
-    return nt ? launch_last_n<M, S, true, T>(c, u, c1, c2, w, tabs, st)
-              : launch_last_n<M, S, false, T>(c, u, c1, c2, w, tabs, st);
+    if constexpr (M >= kMinTwoLineM) {
+      if (c->P[c->d - 1] == 2)
+        return nt ? launch_last_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
+                  : launch_last_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
+    }
+    if constexpr (M >= kStreamLastFrom) {
+      return nt ? launch_last_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_last_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
+    } else {
+      return nt ? launch_last_n<M, S, true, T>(c, u, c1, c2, w, tabs, st)
+                : launch_last_n<M, S, false, T>(c, u, c1, c2, w, tabs, st);
+    }
   }
 }
 
@@ -1050,14 +1053,14 @@ int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[
   const int m = c->m[p];
   hipError_t e = hipSuccess;
   if constexpr (kIsComplex<T>) {
-    // One complex species, chunks of up to 4 rows, one line per wavefront.
+    // One complex species, one line per wavefront.
     if (S != 1) return ETD_ERR_UNSUPPORTED;
     if (p == 0) {
-      ETD_DISPATCH_M4(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st)));
+      ETD_DISPATCH_M(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st)));
     } else if (p == c->d - 1) {
-      ETD_DISPATCH_M4(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st)));
+      ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st)));
     } else {
-      ETD_DISPATCH_M4(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     }
     if (e != hipSuccess) return hip_fail(c, e);
     return ETD_OK;
@@ -1215,7 +1218,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     if (h == 0.0) h = (b == ETD_BC_DIRICHLET) ? 1.0 / (n + 1) : (b == ETD_BC_NEUMANN ? 1.0 / (n - 1) : 1.0 / n);
     if (!(std::isfinite(h) && h > 0)) { delete c; return ETD_ERR_ARG; }
     const int m = choose_chunk(n);
-    if (m == 0 || (cplx && m > kMaxComplexM)) { delete c; return ETD_ERR_UNSUPPORTED; }
+    if (m == 0) { delete c; return ETD_ERR_UNSUPPORTED; }
     const int64_t lines = N / n;
     const bool two_ok = !cplx && ((lpw == ETD_LINES_TWO) ||
                                   (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines));
@@ -1430,8 +1433,9 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const char* e1 = first ? (ctx->scheme == ETD_SCHEME_ETD1 ? ", true" : ", false") : "";
   const bool z = (ctx->precision == ETD_PRECISION_C128);
   const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : (z ? "zd" : "double");
+  const int sw = (z && m > 4) ? 8 : kStreamWaves;  // kStreamBlockWaves
   const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s%s, %s>", base, m,
-                                         ctx->s, kStreamWaves * P, P, nt, e1, ty)
+                                         ctx->s, sw * P, P, nt, e1, ty)
                          : std::snprintf(name, size, "%s<%d, %d, %d, %s, %s>", base, m, ctx->s,
                                          z ? 8 : lines_for(m), nt, ty);
   return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;

@@ -127,11 +127,16 @@ def test_complex_precision_option():
     small = _init((64, 48), ("neumann", "dirichlet"), D=(1j,), model="nls_z", params={"B": 0.0, "C": -1.0},
                   precision="c128")
     assert small.pass_kernel(2) == "k_last<1, 1, 8, false, zd>"
-    for p in (z, small):
+    # chunks of 5-8 rows: streamed passes with 8-line tiles
+    long = _init((300, 448), ("periodic", "dirichlet"), D=(1 + 1j,), model="cgl_z", params={"beta": 1.0},
+                 precision="c128")
+    assert long.pass_kernel(1) == "k_first_s<5, 1, 8, 1, false, false, zd>"
+    assert long.pass_kernel(2) == "k_last_s<7, 1, 8, 1, false, zd>"
+    for p in (z, small, long):
         p.close()
     ok = dict(D=(1 + 1j,), model="cgl_z", params={"beta": 1.0}, precision="c128")
     cases = [
-        ((300, 16), ok, etd.ETD_ERR_UNSUPPORTED),  # 300 = 60 x 5: chunks over 4 rows
+        ((521, 16), ok, etd.ETD_ERR_UNSUPPORTED),  # no chunking of 521 rows
         ((64, 16), dict(ok, lines_per_wave=2), etd.ETD_ERR_UNSUPPORTED),
         ((64, 16), dict(ok, D=(-0.1 + 1j,)), etd.ETD_ERR_ARG),  # Re D < 0
         ((64, 16), dict(ok, precision="f64", D=(1.0,)), etd.ETD_ERR_ARG),  # complex model, real context

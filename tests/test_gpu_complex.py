@@ -44,6 +44,10 @@ CASES = [
     Z((64, 200, 150), ("neumann", "periodic", "dirichlet"), 1j, "nls_z", NLS, 2e-5),
     Z((40, 33, 256), ("dirichlet",) * 3, 0.3 + 2.0j, "cgl_z", CGL, 1e-4),
     Z((2, 3, 1), ("neumann", "periodic", "dirichlet"), 1 + 1j, "cgl_z", CGL, 0.05),  # smallest lines
+    # chunks of 5-8 rows (8-line streamed tiles); 400^2 with h = 1/2 is Section 8.3's 2-D size
+    Z((400, 400), ("periodic", "periodic"), 1 + 0.5j, "cgl_z", CGL, 0.05, h=(0.5, 0.5)),
+    Z((300, 20, 448), ("dirichlet", "periodic", "neumann"), 1j, "nls_z", NLS, 1e-5),
+    Z((336, 512), ("neumann", "dirichlet"), 0.2 + 1.5j, "cgl_z", CGL, 1e-4),
 ]
 
 
