@@ -128,6 +128,16 @@ def initial_data(p: Problem) -> np.ndarray:
         r2 = sum((g - c2) ** 2 for g in grids)
         u = np.exp(-r1 / w) - np.exp(-r2 / w)
         return u[None].astype(np.complex128)
+    if p.ic == "gaussian_pulses_2d":
+        # Section 8.3, 2-D: exp(-|x - (50, 50)|^2 / w) - exp(-|x - (100, 100)|^2 / w)
+        # + exp(-|x - (100, 50)|^2 / w) on the grid x_i = i h.
+        w = p.ic_args.get("width", 1000.0)
+        x = np.arange(p.shape[0]) * p.hs()[0]
+        y = np.arange(p.shape[1]) * p.hs()[1]
+        Y, X = np.meshgrid(y, x, indexing="ij")  # (n_2, n_1)
+        g = lambda cx, cy: np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / w)
+        u = g(50.0, 50.0) - g(100.0, 100.0) + g(100.0, 50.0)
+        return u[None].astype(np.complex128)
     if p.ic == "complex_noise":
         # Section 8.3's normal random field: real and imaginary parts
         # standard normal, scaled by amp.
@@ -180,6 +190,16 @@ def cgl3d_complex(n: int = 200, nsteps: int = 100, seed: int = 0, shape=None) ->
                    ic="gaussian_pulses", ic_args={"width": 1000.0, "c1": 50.0, "c2": 100.0})
 
 
+def cgl2d_complex(n: int = 400, nsteps: int = 200, seed: int = 0) -> Problem:
+    """Complex Ginzburg-Landau on the periodic square [0, 200]^2 at Section
+    8.3's 2-D size (p = 400, h = 1/2, k = 1/20, beta = 1.3, its three
+    Gaussian pulses), with alpha = 0.5."""
+    L = 200.0
+    return Problem("cgl2d_complex", (n, n), ("periodic",) * 2, (complex(1.0, CGL_ALPHA),), 0.05,
+                   "cgl_z", {"beta": CGL_BETA}, nsteps, h=(L / n, L / n), seed=seed,
+                   ic="gaussian_pulses_2d", ic_args={"width": 1000.0})
+
+
 @dataclass
 class Ensemble:
     """A batch of independent 2-D problems (one reaction model, one k)."""
@@ -225,4 +245,5 @@ WORKLOADS = {
     "schnakenberg3d": schnakenberg3d,
     "schnakenberg3d_adjoint": schnakenberg3d_adjoint,
     "cgl3d_complex": cgl3d_complex,
+    "cgl2d_complex": cgl2d_complex,
 }
