@@ -151,3 +151,29 @@ def test_precision_mismatch_is_refused():
     with pytest.raises(etd.EtdError):
         e32.adjoint(u64, u64)
     e32.close()
+
+
+def test_f32_matches_f64_gpu_at_512():
+    """The 512^3 Dirichlet workload (one line per wavefront, streamed
+    16-line tiles), one step in FP32 against the FP64 GPU step.  Both
+    states are stored as the shifted unknown w = u - u* of size 1e-3, so the
+    error is measured relative to w."""
+    torch = _torch()
+    prob = W.schnakenberg3d()
+    u0 = prob.initial()
+    mk = lambda prec: _etd().EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params,
+                                    h=prob.h, shift=prob.shift, precision=prec)
+    e64, e32 = mk("f64"), mk("f32")
+    assert e32.pass_kernel(2) == "k_mid_s<8, 2, 16, 1, true, float>"
+    u64 = torch.from_numpy(u0).cuda()
+    u32 = u64.float()
+    e64.step(u64, 1)
+    e32.step(u32, 1)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(u32.double() - u64) / torch.linalg.norm(u64))
+    e64.close()
+    e32.close()
+    r = max(prob.k * d / h ** 2 for d in prob.D for h in prob.hs())
+    tol = max(1e-5, 5 * EPS32 * (1 + 4 * r))
+    print(f"[f32 vs f64 GPU, 512^3] rel_l2={err:.2e} tol={tol:.2e}", flush=True)
+    assert err <= tol, (err, tol)
