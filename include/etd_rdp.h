@@ -6,7 +6,8 @@
  * Kleefeld and Wade, "A second-order exponential time differencing scheme for
  * non-linear reaction-diffusion systems with dimensional splitting") with the
  * second-order L-stable ETD-RDP-IF scheme: the d-dimensional frame of
- * Section 6 (eq. donedone for d = 3, eq. done for d = 2).  Every split factor
+ * Section 6 (eq. donedone for d = 3, eq. done for d = 2, its general-d form
+ * for d = 4).  Every split factor
  * (I + (k/gamma) A_i)^{-1}, gamma in {1, 3, 4}, is applied as a batch of exact
  * 1-D line solves (Section 7) fused with the pointwise reaction.
  *
@@ -82,12 +83,12 @@ extern "C" {
 #define ETD_SCHEME_ETD1 1  /* predictor only: ETD1-IF with Pade-(0,1),
                               first order (eq. duhamel3t)                    */
 
-#define ETD_MAX_DIM 3
+#define ETD_MAX_DIM 4
 #define ETD_MAX_SPECIES 2
 #define ETD_MAX_PARAMS 16
 
 typedef struct etd_grid_t {
-  int32_t d;                  /* spatial dimension: 2 or 3                   */
+  int32_t d;                  /* spatial dimension: 2, 3 or 4                */
   int32_t s;                  /* number of species: 1 or 2                   */
   int64_t n[ETD_MAX_DIM];     /* unknowns per axis, n[0] = axis 1 (fastest)  */
   double h[ETD_MAX_DIM];      /* spacing per axis; 0 selects the unit-domain
@@ -156,7 +157,7 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  *  out   : receives the new context (owned by the library; free it with
  *          etd_rdp_destroy).
  *
- * Errors: ETD_ERR_ARG for a NULL pointer, d not in {2,3}, s not in {1,2},
+ * Errors: ETD_ERR_ARG for a NULL pointer, d not in {2,3,4}, s not in {1,2},
  * n below the minimum of its BC (Dirichlet 1, Neumann 2, periodic 3), a
  * non-finite or non-positive h or k, a negative or non-finite D, an unknown
  * model or one whose species count differs from s, lines_per_wave not one of
@@ -175,8 +176,9 @@ int etd_rdp_destroy(etd_rdp_ctx* ctx);
 /*
  * Bytes of device workspace a step needs: the factor tables plus the
  * carried FP64 arrays of s*N values each (the passes' intermediates): one
- * triple (c1, c2, w) written by pass 1 and, for d = 3, a second triple
- * written by pass 2 (six arrays in 3-D, three in 2-D).
+ * triple (c1, c2, w) written by pass 1 and, for d >= 3, a second triple
+ * written by pass 2 (six arrays in 3-D and 4-D, three in 2-D; in 4-D pass 3
+ * writes the first triple again).
  */
 int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
 
@@ -187,7 +189,9 @@ int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * inside each species plane (species planes are N doubles apart).  Each
  * pass writes the layout the next pass reads line by line: pass 1 writes
  * axis 2 fastest, then axis 1, then axis 3 ([z][x][y]); pass 2 writes axis 3
- * fastest, then axis 2, then axis 1 ([x][y][z]).  After a full step the
+ * fastest, then axis 2, then axis 1 ([x][y][z]).  In 4-D, pass 1 writes
+ * [i4][i3][i1][i2], pass 2 [i1][i2][i4][i3] and pass 3 (into the first
+ * triple's arrays) [i1][i2][i3][i4].  After a full step the
  * contents are unspecified; etd_rdp_debug_passes leaves defined values.
  * Errors: ETD_ERR_ARG (NULL pointer, pass outside 1..d-1).
  */
@@ -282,7 +286,8 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
  * etd_rdp_apply_solve -- x <- (I + (k/gamma) D_sigma A_axis)^{-1} x for a
  * single-species grid array x of N doubles (layout as one species of u),
  * gamma = 1, 3 or 4 (Section 7: the systems the scheme solves).  axis is
- * 1-based.  Exposes the line solver alone for testing.
+ * 1-based.  Exposes the line solver alone for testing.  FP64 contexts with
+ * d <= 3 only (ETD_ERR_UNSUPPORTED otherwise).
  */
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes,
                         int32_t axis, int32_t sigma, int32_t gamma,
@@ -347,7 +352,8 @@ int etd_rdp_adjoint_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * The result is bitwise reproducible for a given device (fixed reduction
  * order).  Asynchronous on `stream`.
  * Errors: ETD_ERR_ARG (NULL pointer, u_n == lam_n), ETD_ERR_UNSUPPORTED
- * (scheme ETD1), ETD_ERR_WORKSPACE, ETD_ERR_HIP.
+ * (scheme ETD1, d = 4, FP32 or complex contexts), ETD_ERR_WORKSPACE,
+ * ETD_ERR_HIP.
  */
 int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1,
                     double* lam_n, double* grad, void* ws, size_t ws_bytes,

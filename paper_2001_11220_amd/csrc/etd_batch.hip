@@ -67,7 +67,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
     }
     const AxisTabs<S> at{I.tab1, lt};
     const PassGeom g = I.g1;
-    const TileAt pos(0, (int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
+    const TileAt pos((int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
     double U[S][M], f[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s) line_load<M>(u + I.off + s * g.N, U[s], g, pos);
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_last(
     }
     const AxisTabs<S> at{I.tab2, lt};
     const PassGeom g = I.g2;
-    const TileAt pos(0, (int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
+    const TileAt pos((int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
     double us[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s) line_load<M>(w + I.off + s * g.N, us[s], g, pos);

@@ -14,9 +14,9 @@
 
 struct etd_rdp_ctx {
   int d = 0, s = 0;
-  int64_t n[3] = {1, 1, 1};
-  double h[3] = {0, 0, 0};
-  int bc[3] = {0, 0, 0};
+  int64_t n[ETD_MAX_DIM] = {1, 1, 1, 1};
+  double h[ETD_MAX_DIM] = {0, 0, 0, 0};
+  int bc[ETD_MAX_DIM] = {0, 0, 0, 0};
   double D[ETD_MAX_SPECIES] = {0, 0};
   double Dim[ETD_MAX_SPECIES] = {0, 0};  // imaginary parts (complex species)
   double k = 0;
@@ -24,9 +24,9 @@ struct etd_rdp_ctx {
   int precision = ETD_PRECISION_F64;  // element type of u and the carried arrays
   etd::Rx rx{};
   int nparams = 0;             // reaction parameters with a gradient
-  int m[3] = {0, 0, 0};         // chunk length of the forward passes' tables
-  int P[3] = {1, 1, 1};         // lines per wavefront of the forward passes
-  int m1[3] = {0, 0, 0};        // chunk length with one line per wavefront
+  int m[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length of the forward passes' tables
+  int P[ETD_MAX_DIM] = {1, 1, 1, 1};  // lines per wavefront of the forward passes
+  int m1[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length with one line per wavefront
   int64_t N = 0;
   // [axis][species][3] for the forward passes; when some axis runs two lines
   // per wavefront, a second set with one line per wavefront follows at index
@@ -93,7 +93,8 @@ size_t geom_lds(const Geom& g, size_t fixed_lds);
 
 // Pass geometries of the single-problem stepper (see PassGeom), with the
 // forward passes' chunking or (one_line) the one-line-per-wavefront one.
-enum PassKind : int { kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3 };
+// kPassMid is axis 2 (3-D and 4-D), kPassMid2 axis 3 of a 4-D step.
+enum PassKind : int { kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3, kPassMid2 = 4 };
 // esize: bytes per element of the tile buffers.
 PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines,
                    bool one_line = false, size_t esize = sizeof(double));

@@ -591,6 +591,9 @@ __device__ __forceinline__ void load_chunk(const T* __restrict__ p, T (&v)[M], b
 struct PassGeom {
   int64_t nF, nT, nFblk;
   int64_t inF, inT, outT, outRow;
+  // Two-level line index (4-D): t = ta * nT2 + tb sits at ta * inT + tb * inT2
+  // (ta * outT + tb * outT2 in the output); nT2 <= 1 means one level.
+  int64_t nT2, inT2, outT2;
   int64_t N;                    // species stride
   int n, C, pitch, nbuf, tile;  // line length, chunks, LDS pitch/buffers/size
   int lines;                    // lines per tile = wavefronts per block
@@ -598,9 +601,20 @@ struct PassGeom {
 
 struct TileAt {
   int64_t t, f0;
+  int64_t tin, tout;  // offsets of line group t in the input and the output
   __device__ __forceinline__ TileAt(int64_t tile, const PassGeom& g)
-      : t(tile / g.nFblk), f0((tile % g.nFblk) * g.lines) {}
-  __device__ __forceinline__ TileAt(int64_t t_, int64_t f0_) : t(t_), f0(f0_) {}
+      : t(tile / g.nFblk), f0((tile % g.nFblk) * g.lines) {
+    if (g.nT2 > 1) {
+      const int64_t ta = t / g.nT2, tb = t - ta * g.nT2;
+      tin = ta * g.inT + tb * g.inT2;
+      tout = ta * g.outT + tb * g.outT2;
+    } else {
+      tin = t * g.inT;
+      tout = t * g.outT;
+    }
+  }
+  // Line group 0 (the batch kernels, whose tiles carry their own offsets).
+  __device__ __forceinline__ explicit TileAt(int64_t f0_) : t(0), f0(f0_), tin(0), tout(0) {}
 };
 
 // This lane's chunk of its line read directly; zeros for a line past nF or
@@ -613,7 +627,7 @@ __device__ __forceinline__ void line_load(const T* __restrict__ A, T (&v)[M],
   const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
   const int64_t f = p.f0 + w * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
   const bool ok = (c < g.C) && (f < g.nF);
-  const T* src = ok ? A + f * g.inF + p.t * g.inT + (int64_t)c * M : A;
+  const T* src = ok ? A + f * g.inF + p.tin + (int64_t)c * M : A;
   load_chunk<M>(src, v, ok);
 }
 
@@ -626,7 +640,7 @@ __device__ __forceinline__ void tile_fetch(const double* __restrict__ A, double 
   const int tid = threadIdx.x;
   const int col = tid & (L - 1), q = tid / L;
   if (q < g.C && p.f0 + col < g.nF) {
-    const double* src = A + p.f0 + col + p.t * g.outT + (int64_t)(q * M) * g.outRow;
+    const double* src = A + p.f0 + col + p.tout + (int64_t)(q * M) * g.outRow;
 #pragma unroll
     for (int i = 0; i < M; ++i) r[i] = src[i * g.outRow];
   } else {
@@ -672,7 +686,7 @@ __device__ __forceinline__ void tile_store(T* __restrict__ A, const T (&x)[M],
   __syncthreads();
   const int col = tid & (L - 1), q = tid / L;
   if (q < g.C && p.f0 + col < g.nF) {
-    T* dst = A + p.f0 + col + p.t * g.outT + (int64_t)(q * M) * g.outRow;
+    T* dst = A + p.f0 + col + p.tout + (int64_t)(q * M) * g.outRow;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       const T v = B[col * g.pitch + i * g.C + q];

@@ -654,18 +654,22 @@ using namespace etd;
 
 namespace etd {
 
-// The reaction field in the layout the last pass reads its lines in:
-// out[i_1][i_2][i_3] = in[i_3][i_2][i_1] (3-D; n3 = 1 in 2-D gives
-// out[i_1][i_2] = in[i_2][i_1]).  Runs once per set_field call.
+// The reaction field in the layout the last pass reads its lines in, the
+// state layout with the axis order reversed: out[i_1][i_2][i_3][i_4] =
+// in[i_4][i_3][i_2][i_1] (unused trailing axes have extent 1).  Runs once per
+// set_field call.
 __global__ __launch_bounds__(256) void k_field_last_layout(const double* __restrict__ in,
                                                            double* __restrict__ out, int64_t n1,
-                                                           int64_t n2, int64_t n3) {
-  const int64_t N = n1 * n2 * n3;
+                                                           int64_t n2, int64_t n3, int64_t n4) {
+  const int64_t N = n1 * n2 * n3 * n4;
   for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < N;
        o += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t z = o % n3, r = o / n3;
-    const int64_t y = r % n2, x = r / n2;
-    out[o] = in[(z * n2 + y) * n1 + x];
+    int64_t r = o;
+    const int64_t i4 = r % n4; r /= n4;
+    const int64_t i3 = r % n3; r /= n3;
+    const int64_t i2 = r % n2;
+    const int64_t i1 = r / n2;
+    out[o] = in[((i4 * n3 + i3) * n2 + i2) * n1 + i1];
   }
 }
 
@@ -758,7 +762,10 @@ size_t geom_lds(const Geom& g, size_t fixed_lds) {
 
 PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, bool one_line,
                    size_t esize) {
-  const int64_t n1 = c->n[0], n2 = c->n[1], n3 = (c->d == 3) ? c->n[2] : 1;
+  // In 4-D, passes 1 and 2 see axes 3 and 4 as one flattened axis (n3 below,
+  // axis 3 the faster), which their layouts keep contiguous.
+  const int64_t n1 = c->n[0], n2 = c->n[1];
+  const int64_t n3 = (c->d >= 3) ? c->n[2] * (c->d == 4 ? c->n[3] : 1) : 1;
   PassGeom g{};
   g.N = c->N;
   int axis0 = 0;
@@ -775,10 +782,25 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, 
       g.inF = n1 * n2; g.inT = n2;
       g.outT = n2 * n3; g.outRow = n3;
       break;
-    case kPassLast:  // lines (x, y) along axis d of B (3-D) or A (2-D) -> u
+    case kPassMid2: {  // 4-D: i3-lines of B [i1][i2][i4][i3] -> A [i1][i2][i3][i4]
+      const int64_t m3 = c->n[2], m4 = c->n[3];
+      axis0 = 2;
+      g.nF = m4; g.inF = m3;                       // f = i4
+      g.nT = n1 * n2; g.nT2 = n2;                  // t = (i1, i2)
+      g.inT = n2 * m4 * m3; g.inT2 = m4 * m3;
+      g.outT = n2 * m3 * m4; g.outT2 = m3 * m4; g.outRow = m4;
+      break;
+    }
+    case kPassLast:  // lines (x, y) along axis d of B (3-D) or A (2-D, 4-D) -> u
       axis0 = c->d - 1;
       g.nF = n1;
-      if (c->d == 3) {
+      if (c->d == 4) {  // i4-lines of A [i1][i2][i3][i4], t = (i3, i2)
+        const int64_t m3 = c->n[2], m4 = c->n[3];
+        g.inF = n2 * m3 * m4;
+        g.nT = m3 * n2; g.nT2 = n2;
+        g.inT = m4; g.inT2 = m3 * m4;
+        g.outT = n1 * n2; g.outT2 = n1; g.outRow = n1 * n2 * m3;
+      } else if (c->d == 3) {
         g.nT = n2; g.inF = n2 * n3; g.inT = n3;
         g.outT = n1; g.outRow = n1 * n2;
       } else {
@@ -916,13 +938,13 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
 }
 
 template <int M, int S, int P, bool NT, typename T>
-hipError_t launch_mid_s(const etd_rdp_ctx* c, const T* c1, const T* c2,
+hipError_t launch_mid_s(const etd_rdp_ctx* c, int p, const T* c1, const T* c2,
                         const T* w, T* o1, T* o2, T* ow,
                         const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int W = kStreamBlockWaves<M, T>;
   constexpr int L = W * P;
-  const PassGeom g = pass_geom(c, kPassMid, fixed, L, false, sizeof(T));
+  const PassGeom g = pass_geom(c, p == 2 ? kPassMid2 : kPassMid, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_mid_s<M, S, L, P, NT, T>, lds);
   if (e != hipSuccess) return e;
@@ -935,12 +957,12 @@ hipError_t launch_mid_s(const etd_rdp_ctx* c, const T* c1, const T* c2,
 }
 
 template <int M, int S, bool NT, typename T>
-hipError_t launch_mid_n(const etd_rdp_ctx* c, const T* c1, const T* c2,
+hipError_t launch_mid_n(const etd_rdp_ctx* c, int p, const T* c1, const T* c2,
                       const T* w, T* o1, T* o2, T* ow,
                       const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kLanes, T>(3 * S);
   constexpr int L = kPassLines<M, T>;
-  const PassGeom g = pass_geom(c, kPassMid, fixed, L, false, sizeof(T));
+  const PassGeom g = pass_geom(c, p == 2 ? kPassMid2 : kPassMid, fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_mid<M, S, L, NT, T>, lds);
   if (e != hipSuccess) return e;
@@ -953,26 +975,26 @@ hipError_t launch_mid_n(const etd_rdp_ctx* c, const T* c1, const T* c2,
 }
 
 template <int M, int S, typename T>
-hipError_t launch_mid(const etd_rdp_ctx* c, const T* c1, const T* c2,
+hipError_t launch_mid(const etd_rdp_ctx* c, int p, const T* c1, const T* c2,
                       const T* w, T* o1, T* o2, T* ow,
                       const TabOf<T>* tabs, hipStream_t st) {
   // Non-temporal stores for large arrays (see use_nt).
   const bool nt = use_nt(c);
   if constexpr (kIsComplex<T> && M >= kStreamMidFromZ) {
-    return nt ? launch_mid_s<M, S, 1, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
-              : launch_mid_s<M, S, 1, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+    return nt ? launch_mid_s<M, S, 1, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
+              : launch_mid_s<M, S, 1, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
-      if (c->P[1] == 2)
-        return nt ? launch_mid_s<M, S, 2, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
-                  : launch_mid_s<M, S, 2, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+      if (c->P[p] == 2)
+        return nt ? launch_mid_s<M, S, 2, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
+                  : launch_mid_s<M, S, 2, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
     }
     if constexpr (M >= kStreamMidFrom) {
-      return nt ? launch_mid_s<M, S, 1, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
-                : launch_mid_s<M, S, 1, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+      return nt ? launch_mid_s<M, S, 1, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
+                : launch_mid_s<M, S, 1, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
     } else {
-      return nt ? launch_mid_n<M, S, true, T>(c, c1, c2, w, o1, o2, ow, tabs, st)
-                : launch_mid_n<M, S, false, T>(c, c1, c2, w, o1, o2, ow, tabs, st);
+      return nt ? launch_mid_n<M, S, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
+                : launch_mid_n<M, S, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
     }
   }
 }
@@ -1060,7 +1082,7 @@ int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[
     } else if (p == c->d - 1) {
       ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st)));
     } else {
-      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+      ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, p, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     }
     if (e != hipSuccess) return hip_fail(c, e);
     return ETD_OK;
@@ -1073,9 +1095,9 @@ int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[
       else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2, T>(c, u, in[0], in[1], in[2], ta, st))); }
     } else {
       if (S == 1) {
-        ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+        ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, p, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
       } else {
-        ETD_DISPATCH_M(m, e = (launch_mid<M_, 2, T>(c, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
+        ETD_DISPATCH_M(m, e = (launch_mid<M_, 2, T>(c, p, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
       }
     }
     if (e != hipSuccess) return hip_fail(c, e);
@@ -1091,8 +1113,9 @@ template int launch_pass<zd>(etd_rdp_ctx*, int, zd*, zd* const (&)[3], zd* const
 
 namespace {
 
-// Passes first..npasses-1 of a step: pass 1 writes A, pass 2 (3-D) reads A
-// and writes B, pass d reads the last triple written.
+// Passes first..npasses-1 of a step: pass 1 writes A, pass 2 (3-D, 4-D) reads
+// A and writes B, pass 3 of a 4-D step reads B and writes A, pass d reads the
+// last triple written.
 template <typename T>
 int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream_t st) {
   const TabOf<T>* tabs = static_cast<const TabOf<T>*>(ws);
@@ -1105,8 +1128,9 @@ int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream
                                                               c->field_bytes)
                             : nullptr;
   for (int p = first; p < npasses; ++p) {
-    const bool into_b = (p == 1 && c->d == 3);
-    const bool from_b = (p == 2);
+    // Pass p writes A (p even) or B (p odd) and reads what pass p - 1 wrote.
+    const bool into_b = (p % 2 == 1);
+    const bool from_b = (p % 2 == 0);
     const int rc = launch_pass(c, p, u, from_b ? B : A, into_b ? B : A, tabs, st);
     if (rc) return rc;
   }
@@ -1170,7 +1194,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   if (!grid || !bc || !D || !rx || !out) return ETD_ERR_ARG;
   *out = nullptr;
   const int d = grid->d, s = grid->s;
-  if (d < 2 || d > 3) return ETD_ERR_ARG;
+  if (d < 2 || d > ETD_MAX_DIM) return ETD_ERR_ARG;
   if (s < 1 || s > ETD_MAX_SPECIES) return ETD_ERR_ARG;
   if (!(std::isfinite(k) && k > 0)) return ETD_ERR_ARG;
   const int want_s = species_of_model(rx->model);
@@ -1277,7 +1301,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
         }
   c->tab_bytes = round_up(cplx ? c->tabz.size() * sizeof(SolveTabZ) : c->tabs.size() * sizeof(SolveTab), 256);
   c->arr_bytes = round_up(elem_bytes(c) * static_cast<size_t>(N) * s, 256);
-  c->ws_bytes = c->tab_bytes + (d == 3 ? 6 : 3) * c->arr_bytes;
+  c->ws_bytes = c->tab_bytes + (d >= 3 ? 6 : 3) * c->arr_bytes;
   if (rx->field) {
     c->has_field = true;
     c->field_off = c->ws_bytes;
@@ -1306,19 +1330,27 @@ int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass, size_t* off_c
                              size_t* off_c2, size_t* off_w, int64_t* strides) {
   if (!ctx || !off_c1 || !off_c2 || !off_w || !strides) return ETD_ERR_ARG;
   if (pass < 1 || pass > ctx->d - 1) return ETD_ERR_ARG;
-  const int first = (pass == 1) ? 0 : 3;
+  const int first = (pass % 2 == 1) ? 0 : 3;  // passes 1 and 3 write A, pass 2 writes B
   *off_c1 = ctx->tab_bytes + first * ctx->arr_bytes;
   *off_c2 = ctx->tab_bytes + (first + 1) * ctx->arr_bytes;
   *off_w = ctx->tab_bytes + (first + 2) * ctx->arr_bytes;
-  const int64_t n1 = ctx->n[0], n2 = ctx->n[1], n3 = (ctx->d == 3) ? ctx->n[2] : 1;
-  if (pass == 1) {  // [z][x][y]
+  const int64_t n1 = ctx->n[0], n2 = ctx->n[1];
+  const int64_t n3 = (ctx->d >= 3) ? ctx->n[2] : 1, n4 = (ctx->d == 4) ? ctx->n[3] : 1;
+  if (pass == 1) {  // [i4][i3][i1][i2]
     strides[0] = n2;
     strides[1] = 1;
-    if (ctx->d == 3) strides[2] = n1 * n2;
-  } else {  // [x][y][z]
-    strides[0] = n2 * n3;
-    strides[1] = n3;
+    if (ctx->d >= 3) strides[2] = n1 * n2;
+    if (ctx->d == 4) strides[3] = n1 * n2 * n3;
+  } else if (pass == 2) {  // [i1][i2][i4][i3]
+    strides[0] = n2 * n3 * n4;
+    strides[1] = n3 * n4;
     strides[2] = 1;
+    if (ctx->d == 4) strides[3] = n3;
+  } else {  // 4-D pass 3: [i1][i2][i3][i4]
+    strides[0] = n2 * n3 * n4;
+    strides[1] = n3 * n4;
+    strides[2] = n4;
+    strides[3] = 1;
   }
   return ETD_OK;
 }
@@ -1390,7 +1422,8 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
   if (e != hipSuccess) return hip_fail(ctx, e);
   const int64_t blocks = std::min<int64_t>((N + 255) / 256, 4096);
   hipLaunchKernelGGL(k_field_last_layout, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, b,
-                     fd, ctx->n[0], ctx->n[1], ctx->d == 3 ? ctx->n[2] : int64_t(1));
+                     fd, ctx->n[0], ctx->n[1], ctx->d >= 3 ? ctx->n[2] : int64_t(1),
+                     ctx->d == 4 ? ctx->n[3] : int64_t(1));
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e);
   ctx->field_ws = ws;
@@ -1400,7 +1433,7 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, int32_t axis,
                         int32_t sigma, int32_t gamma, void* stream) {
   if (!ctx || !x || axis < 1 || axis > ctx->d || sigma < 0 || sigma >= ctx->s) return ETD_ERR_ARG;
-  if (ctx->precision != ETD_PRECISION_F64) return ETD_ERR_UNSUPPORTED;
+  if (ctx->precision != ETD_PRECISION_F64 || ctx->d > 3) return ETD_ERR_UNSUPPORTED;
   const int slot = gamma == 1 ? 0 : (gamma == 3 ? 1 : (gamma == 4 ? 2 : -1));
   if (slot < 0) return ETD_ERR_ARG;
   int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);

@@ -32,7 +32,7 @@ MODEL_PARAMS = {"enzyme": (), "brusselator": ("a", "b"), "gray_scott": ("F", "ka
 SCHEMES = {"rdp": 0, "etd1": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "c128": 2}
 
-MAX_DIM, MAX_SPECIES, MAX_PARAMS = 3, 2, 16
+MAX_DIM, MAX_SPECIES, MAX_PARAMS = 4, 2, 16
 
 
 class Grid(ctypes.Structure):
@@ -154,6 +154,8 @@ class EtdRdp:
                  scheme="rdp", device=None, lines_per_wave="auto", precision="f64", field=False):
         d = len(shape)
         s = len(D)
+        if not 1 <= d <= MAX_DIM:
+            raise ValueError(f"{d}-D grid: the library takes up to {MAX_DIM} axes")
         g = Grid()
         g.d, g.s = d, s
         for i in range(d):

@@ -164,6 +164,34 @@ def test_reaction_field_option():
     assert ei.value.status == etd.ETD_ERR_ARG
 
 
+def test_four_dimensional_option():
+    from paper_2001_11220_amd import etd
+    e = _init((96, 8, 70, 5), ("neumann", "periodic", "dirichlet", "neumann"))
+    assert [e.pass_kernel(p) for p in (1, 2, 3, 4)] == [
+        "k_first<2, 2, 16, false, double>", "k_mid<1, 2, 16, false, double>",
+        "k_mid<2, 2, 16, false, double>", "k_last<1, 2, 16, false, double>"]
+    n1, n2, n3, n4 = 96, 8, 70, 5
+    # layouts of the carried triples (axis strides 1..4)
+    assert e.layout(1)[1] == (n2, 1, n1 * n2, n1 * n2 * n3)
+    assert e.layout(2)[1] == (n2 * n3 * n4, n3 * n4, 1, n3)
+    assert e.layout(3)[1] == (n2 * n3 * n4, n3 * n4, n4, 1)
+    assert e.layout(3)[0] == e.layout(1)[0]  # pass 3 writes the first triple again
+    e.close()
+    with pytest.raises(ValueError):  # five axes do not fit the grid struct
+        _init((4, 4, 4, 4, 4), ("periodic",) * 5)
+    g = etd.Grid()  # the C ABI refuses d = 5 (and d = 1)
+    for d in (5, 1):
+        g.d, g.s = d, 2
+        for i in range(4):
+            g.n[i] = 8
+        bc = (ctypes.c_int32 * 5)(1, 1, 1, 1, 1)
+        D = (ctypes.c_double * 2)(0.1, 0.2)
+        rx = etd.reaction_struct("brusselator", {"a": 1.0, "b": 3.0}, None, 2)
+        ctx = ctypes.c_void_p()
+        rc = etd.lib.etd_rdp_init(ctypes.byref(g), bc, D, 0.01, None, ctypes.byref(rx), ctypes.byref(ctx))
+        assert rc == etd.ETD_ERR_ARG
+
+
 def test_tables_build_for_stiff_coefficients():
     # r = k D / h^2 up to ~5e6 still passes the residual self-check
     for D in (1e-9, 1.0, 1e3):
