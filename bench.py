@@ -57,7 +57,8 @@ def cpu_baseline(name: str, budget_s: float = 12.0):
     from paper_2001_11220_amd import workloads as W
 
     sample_n = {"grayscott3d": 64, "schnakenberg3d": 64, "brusselator2d": 64,
-                "schnakenberg3d_adjoint": 64, "cgl3d_complex": 64, "cgl2d_complex": 400}[name]
+                "schnakenberg3d_adjoint": 64, "cgl3d_complex": 64, "cgl2d_complex": 400,
+                "grayscott4d": 16}[name]
     prob = W.WORKLOADS[name](n=sample_n)
     u = prob.initial()
     cs = prob.cells * prob.s

@@ -159,6 +159,16 @@ def grayscott3d(n: int = 256, nsteps: int = 500, seed: int = 0, shape=None) -> P
                    ic="cube_patch", ic_args={"amp": 0.25})
 
 
+def grayscott4d(n: int = 64, nsteps: int = 100, seed: int = 0, shape=None) -> Problem:
+    """The Gray-Scott benchmark system on the periodic unit 4-cube (the
+    general-d frame of Section 6), 64^4 cells, same coefficients, k and
+    initial-data recipe as the 3-D workload."""
+    shape = tuple(shape) if shape is not None else (n, n, n, n)
+    return Problem("grayscott4d", shape, ("periodic",) * 4, (2e-5, 1e-5), 1.0,
+                   "gray_scott", {"F": 0.04, "kappa": 0.06}, nsteps, seed=seed,
+                   ic="cube_patch", ic_args={"amp": 0.25})
+
+
 SCHNAK = {"a": 0.1, "b": 0.9, "gamma": 1.0}
 SCHNAK_STEADY = (SCHNAK["a"] + SCHNAK["b"], SCHNAK["b"] / (SCHNAK["a"] + SCHNAK["b"]) ** 2)
 
@@ -242,6 +252,7 @@ def brusselator_ensemble(ninst: int = 1024, nsteps: int = 200, seed: int = 0,
 WORKLOADS = {
     "brusselator2d": brusselator2d,
     "grayscott3d": grayscott3d,
+    "grayscott4d": grayscott4d,
     "schnakenberg3d": schnakenberg3d,
     "schnakenberg3d_adjoint": schnakenberg3d_adjoint,
     "cgl3d_complex": cgl3d_complex,
