@@ -108,7 +108,7 @@ typedef struct etd_reaction_t {
 
 /* Lines per wavefront of the forward passes (etd_scheme_t.lines_per_wave).
  * A wavefront solves one grid line with up to 64 chunks, or two lines of
- * 32 chunks each when the line length is n = 32 m with 5 <= m <= 8 (fewer
+ * 32 chunks each when the line length is n = 32 m with 2 <= m <= 8 (fewer
  * cross-lane reduction levels per line, 32-line tiles).  Results agree with
  * the one-line form to rounding (the chunking differs). */
 #define ETD_LINES_AUTO 0   /* two where n allows and a pass has >= 32768 lines */

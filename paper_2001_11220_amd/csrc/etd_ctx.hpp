@@ -57,7 +57,7 @@ inline size_t elem_bytes(const etd_rdp_ctx* c) {
 // m in [kMinTwoLineM, kMaxM] runs its forward pass with 32 chunks of m rows
 // per line and two lines per wavefront (the streamed kernels); returns m, or
 // 0 when the axis runs one line per wavefront.
-constexpr int kMinTwoLineM = 5;
+constexpr int kMinTwoLineM = 2;
 // Lines a pass needs before ETD_LINES_AUTO takes two lines per wavefront:
 // 1024 tiles of 32 lines, four per block of a persistent grid.
 constexpr int64_t kTwoLineMinLines = 32768;

@@ -148,7 +148,7 @@ ONE_STEP = [
     P((2, 3, 1), ("neumann", "periodic", "dirichlet")),  # smallest line lengths
 ]
 
-# Lines of 32 m rows, m = 5..8, forced to two lines per wavefront: every
+# Lines of 32 m rows, m = 2..8, forced to two lines per wavefront: every
 # pass, every boundary condition, one and two species, ragged tile tails.
 TWO_LINE = [
     P((256, 12, 10), ("neumann", "periodic", "dirichlet")),
@@ -160,6 +160,11 @@ TWO_LINE = [
     P((224, 256), ("periodic", "dirichlet"), model="enzyme", params={}, D=(0.2,), k=0.05),
     P((192, 7), ("neumann", "periodic"), model="cgl", params={"beta": 1.3}, D=(1.0, 1.0), k=0.05,
       h=(0.5, 0.5)),
+    # chunks of 2-4 rows (lines of 64, 96, 128)
+    P((64, 20, 12), ("periodic", "neumann", "dirichlet")),
+    P((9, 96, 7), ("dirichlet", "periodic", "neumann"), model="gray_scott", params={"F": 0.04, "kappa": 0.06},
+      D=(2e-5, 1e-5), k=1.0, ic="cube_patch"),
+    P((6, 10, 128), ("neumann", "dirichlet", "periodic")),
 ]
 
 
