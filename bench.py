@@ -16,7 +16,9 @@ state, which is resident in HBM before timing starts.  Prints one JSON line.
                a middle pass reads and writes all three (6 words), the last
                pass reads three and writes U (4 words); 1 word = 8 bytes
                (4 with --precision f32, 16 for a complex species).
-               step_effective_GBps is the same ratio for the whole step.
+               step_effective_GBps is the same ratio for the whole step;
+               traffic (counter-measured HBM bytes per launch, when stored
+               for these kernel sources) gives traffic_GBps beside it.
 * cpu_baseline the FP64 oracle on the host, one thread, on a bounded
                sample of the same workload (stated in "sample").
 """
@@ -195,6 +197,10 @@ def main():
             "alg_bytes_per_launch": dom["alg_bytes"],
             "step_effective_GBps": step_bytes / (ms_step / 1e3) / 1e9,
             "passes": [{k: r[k] for k in ("pass", "kernel", "avg_ms", "GBps")} for r in per]}
+    if traffic is not None:
+        # counted HBM bytes of the dominant kernel per second of its launch time
+        roof["traffic_GBps"] = traffic / (dom["avg_ms"] / 1e3) / 1e9
+        roof["traffic_frac"] = roof["traffic_GBps"] / HBM_PEAK_GBS
 
     cpu = None
     if not args.no_cpu_baseline:
