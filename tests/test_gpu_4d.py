@@ -123,3 +123,24 @@ def test_4d_f32_and_complex():
     errz = rel_l2(uz.cpu().numpy(), refz)
     print(f"[4-D f32] rel_l2={err32:.2e}  [4-D complex] rel_l2={errz:.2e}", flush=True)
     assert err32 <= 1e-5 and errz <= 1e-12, (err32, errz)
+
+
+def test_4d_schroedinger_with_field_matches_oracle():
+    """The per-cell reaction field in 4-D (its copy in the last pass's layout
+    reverses all four axes)."""
+    torch = _torch()
+    shape = (12, 7, 10, 9)
+    z = W.Problem("z4f", shape, ("neumann", "periodic", "dirichlet", "neumann"), (1j,), 1e-3, "nls_z",
+                  {"B": 0.4, "C": -1.0}, 1, seed=0, ic="complex_noise", ic_args={"amp": 0.5})
+    z0 = z.initial()
+    field = np.random.default_rng(5).standard_normal(shape[::-1])
+    e = _etd().EtdRdp(z.shape, z.bcs, z.D, z.k, z.model, z.params, precision="c128", field=True)
+    u = torch.from_numpy(z0).cuda()
+    e.set_field(torch.from_numpy(field).cuda())
+    e.step(u, 2)
+    torch.cuda.synchronize()
+    e.close()
+    ref = O.etd_rdp_if_run(z0, z.k, z.D, z.bcs, z.hs(), z.model, dict(z.oracle_params(), Bfield=field), 2)
+    err = rel_l2(u.cpu().numpy(), ref)
+    print(f"[4-D complex field, 2 steps] rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-12, err
