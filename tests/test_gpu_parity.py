@@ -290,3 +290,15 @@ def test_schnakenberg3d_full_size_one_step_sampled():
     x0s = [0, 255, 511]
     ref = _sampled_step_reference(prob, u0, x0s)
     assert rel_l2(got[..., x0s], ref) < 1e-12
+
+
+def test_grayscott4d_full_size_one_step_sampled():
+    """64^4 periodic (two lines of 32 two-row chunks per wavefront on every
+    axis), benchmark launch configuration; planes x = x0 checked against the
+    oracle."""
+    prob = W.grayscott4d()
+    u0 = prob.initial()
+    got = gpu_run(prob, u0, 1)
+    x0s = [0, 31, 63]
+    ref = _sampled_step_reference(prob, u0, x0s)
+    assert rel_l2(got[..., x0s], ref) < 1e-12
