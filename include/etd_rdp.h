@@ -7,7 +7,7 @@
  * non-linear reaction-diffusion systems with dimensional splitting") with the
  * second-order L-stable ETD-RDP-IF scheme: the d-dimensional frame of
  * Section 6 (eq. donedone for d = 3, eq. done for d = 2, its general-d form
- * for d = 4).  Every split factor
+ * for d = 4; for d = 1 the unsplit ETD-RDP, eq. finalle).  Every split factor
  * (I + (k/gamma) A_i)^{-1}, gamma in {1, 3, 4}, is applied as a batch of exact
  * 1-D line solves (Section 7) fused with the pointwise reaction.
  *
@@ -88,7 +88,7 @@ extern "C" {
 #define ETD_MAX_PARAMS 16
 
 typedef struct etd_grid_t {
-  int32_t d;                  /* spatial dimension: 2, 3 or 4                */
+  int32_t d;                  /* spatial dimension: 1, 2, 3 or 4             */
   int32_t s;                  /* number of species: 1 or 2                   */
   int64_t n[ETD_MAX_DIM];     /* unknowns per axis, n[0] = axis 1 (fastest)  */
   double h[ETD_MAX_DIM];      /* spacing per axis; 0 selects the unit-domain
@@ -157,7 +157,7 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  *  out   : receives the new context (owned by the library; free it with
  *          etd_rdp_destroy).
  *
- * Errors: ETD_ERR_ARG for a NULL pointer, d not in {2,3,4}, s not in {1,2},
+ * Errors: ETD_ERR_ARG for a NULL pointer, d not in {1,2,3,4}, s not in {1,2},
  * n below the minimum of its BC (Dirichlet 1, Neumann 2, periodic 3), a
  * non-finite or non-positive h or k, a negative or non-finite D, an unknown
  * model or one whose species count differs from s, lines_per_wave not one of
@@ -352,7 +352,7 @@ int etd_rdp_adjoint_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * The result is bitwise reproducible for a given device (fixed reduction
  * order).  Asynchronous on `stream`.
  * Errors: ETD_ERR_ARG (NULL pointer, u_n == lam_n), ETD_ERR_UNSUPPORTED
- * (scheme ETD1, d = 4, FP32 or complex contexts), ETD_ERR_WORKSPACE,
+ * (scheme ETD1, d = 1 or 4, FP32 or complex contexts), ETD_ERR_WORKSPACE,
  * ETD_ERR_HIP.
  */
 int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1,

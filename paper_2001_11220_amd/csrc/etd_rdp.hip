@@ -654,6 +654,29 @@ using namespace etd;
 
 namespace etd {
 
+// d = 1 (the unsplit ETD-RDP of Section 6): the last-pass inputs without an
+// R chain, c2 = F(U) and w = U + k F(U), cell by cell (c1 is U itself).
+template <int S, typename T>
+__global__ __launch_bounds__(256) void k_pre1d(const T* __restrict__ u, T* __restrict__ c2,
+                                               T* __restrict__ w, Rx rx, T k, int64_t N) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T uu[S], ff[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) uu[s] = u[s * N + i];
+    double bf = 0.0;
+    if constexpr (kIsComplex<T>) {
+      if (rx.fld1) bf = rx.fld1[i];
+    }
+    react<S>(rx, uu, ff, bf);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      c2[s * N + i] = ff[s];
+      w[s * N + i] = fma(k, ff[s], uu[s]);
+    }
+  }
+}
+
 // The reaction field in the layout the last pass reads its lines in, the
 // state layout with the axis order reversed: out[i_1][i_2][i_3][i_4] =
 // in[i_4][i_3][i_2][i_1] (unused trailing axes have extent 1).  Runs once per
@@ -803,9 +826,12 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, 
       } else if (c->d == 3) {
         g.nT = n2; g.inF = n2 * n3; g.inT = n3;
         g.outT = n1; g.outRow = n1 * n2;
-      } else {
+      } else if (c->d == 2) {
         g.nT = 1; g.inF = n2; g.inT = 0;
         g.outT = 0; g.outRow = n1;
+      } else {  // d = 1: the single line of each species, in place
+        g.nF = 1; g.nT = 1; g.inF = 0; g.inT = 0;
+        g.outT = 0; g.outRow = 1;
       }
       break;
     default:  // kPassAdjMid: y-lines (x, z), direct from A, transposed in u's layout
@@ -1074,25 +1100,39 @@ int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[
   const TabOf<T>* ta = tabs + tab_index(p, 0, 0, S);
   const int m = c->m[p];
   hipError_t e = hipSuccess;
+  if (c->d == 1) {
+    // One pass: the pre-pass writes (c2, w) into `out`; the last pass reads
+    // c1 = u and writes u (each species' lines are read before written).
+    const int64_t N = c->N;
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((N + 255) / 256, 1024));
+    if (S == 1) hipLaunchKernelGGL((k_pre1d<1, T>), dim3(blocks), dim3(256), 0, st, u, out[1], out[2], c->rx,
+                                   static_cast<T>(c->k), N);
+    else hipLaunchKernelGGL((k_pre1d<2, T>), dim3(blocks), dim3(256), 0, st, u, out[1], out[2], c->rx,
+                            static_cast<T>(c->k), N);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e);
+  }
+  T* const c1_in = (c->d == 1) ? u : in[0];
+  T* const (&lin)[3] = (c->d == 1) ? out : in;
   if constexpr (kIsComplex<T>) {
     // One complex species, one line per wavefront.
     if (S != 1) return ETD_ERR_UNSUPPORTED;
-    if (p == 0) {
+    if (p == 0 && c->d > 1) {
       ETD_DISPATCH_M(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st)));
     } else if (p == c->d - 1) {
-      ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st)));
+      ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, c1_in, lin[1], lin[2], ta, st)));
     } else {
       ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, p, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
     }
     if (e != hipSuccess) return hip_fail(c, e);
     return ETD_OK;
   } else {
-    if (p == 0) {
+    if (p == 0 && c->d > 1) {
       if (S == 1) { ETD_DISPATCH_M(m, e = (launch_first<M_, 1, T>(c, u, out[0], out[1], out[2], ta, st))); }
       else { ETD_DISPATCH_M(m, e = (launch_first<M_, 2, T>(c, u, out[0], out[1], out[2], ta, st))); }
     } else if (p == c->d - 1) {
-      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, in[0], in[1], in[2], ta, st))); }
-      else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2, T>(c, u, in[0], in[1], in[2], ta, st))); }
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_last<M_, 1, T>(c, u, c1_in, lin[1], lin[2], ta, st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_last<M_, 2, T>(c, u, c1_in, lin[1], lin[2], ta, st))); }
     } else {
       if (S == 1) {
         ETD_DISPATCH_M(m, e = (launch_mid<M_, 1, T>(c, p, in[0], in[1], in[2], out[0], out[1], out[2], ta, st)));
@@ -1194,7 +1234,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   if (!grid || !bc || !D || !rx || !out) return ETD_ERR_ARG;
   *out = nullptr;
   const int d = grid->d, s = grid->s;
-  if (d < 2 || d > ETD_MAX_DIM) return ETD_ERR_ARG;
+  if (d < 1 || d > ETD_MAX_DIM) return ETD_ERR_ARG;
   if (s < 1 || s > ETD_MAX_SPECIES) return ETD_ERR_ARG;
   if (!(std::isfinite(k) && k > 0)) return ETD_ERR_ARG;
   const int want_s = species_of_model(rx->model);
@@ -1454,7 +1494,8 @@ int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx) { return ctx ? ctx->last_hip 
 int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t size) {
   if (!ctx || !name || size == 0 || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
   const int p = pass - 1, m = ctx->m[p], P = ctx->P[p];
-  const bool first = (p == 0), last = (p == ctx->d - 1);
+  // d = 1: the one pass is the last-pass kernel (after an elementwise pre-pass)
+  const bool first = (p == 0) && ctx->d > 1, last = (p == ctx->d - 1);
   const bool zc = (ctx->precision == ETD_PRECISION_C128);
   const bool streamed =
       (P == 2) || (first ? (m >= (zc ? kStreamFirstFromZ : kStreamFirstFrom))

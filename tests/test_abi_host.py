@@ -182,8 +182,8 @@ def test_four_dimensional_option():
     e.close()
     with pytest.raises(ValueError):  # five axes do not fit the grid struct
         _init((4, 4, 4, 4, 4), ("periodic",) * 5)
-    g = etd.Grid()  # the C ABI refuses d = 5 (and d = 1)
-    for d in (5, 1):
+    g = etd.Grid()  # the C ABI refuses d = 5 and d = 0
+    for d in (5, 0):
         g.d, g.s = d, 2
         for i in range(4):
             g.n[i] = 8
@@ -193,6 +193,15 @@ def test_four_dimensional_option():
         ctx = ctypes.c_void_p()
         rc = etd.lib.etd_rdp_init(ctypes.byref(g), bc, D, 0.01, None, ctypes.byref(rx), ctypes.byref(ctx))
         assert rc == etd.ETD_ERR_ARG
+
+
+def test_one_dimensional_option():
+    e = _init((512,), ("dirichlet",), D=(1.0, 10.0), k=1e-4, model="schnakenberg",
+              params={"a": 0.1, "b": 0.9, "gamma": 1.0})
+    # one pass: the last-pass kernel after an elementwise pre-pass
+    assert e.pass_kernel(1) == "k_last_s<8, 2, 16, 1, false, double>"
+    assert e.line_split(1) == (8, 64)
+    e.close()
 
 
 def test_tables_build_for_stiff_coefficients():
@@ -225,7 +234,7 @@ def test_invalid_arguments():
     etd = _lib()
     E = etd.EtdError
     with pytest.raises(E) as e:
-        _init((8,), ("neumann",))  # d = 1 not supported by this build
+        _init((1,), ("neumann",), D=(0.2,), model="enzyme", params={})  # Neumann needs n >= 2
     assert e.value.status == etd.ETD_ERR_ARG
     for bad in [dict(k=0.0), dict(k=float("nan")), dict(D=(-1.0, 0.1)), dict(D=(float("inf"), 0.1)),
                 dict(model="enzyme", params={}), dict(h=(-0.1, 0.0))]:

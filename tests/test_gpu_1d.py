@@ -1,0 +1,105 @@
+"""GPU parity of the 1-D scheme (d = 1: the unsplit ETD-RDP of Section 6,
+eq. finalle: predictor P(U + kF), corrector T(9U + 2kF + kF*) -
+S(8U + 3k/2 F + k/2 F*), all on one line per species) against the FP64
+oracle.  Tolerances: rel-L2 <= 1e-12 after one step, <= 1e-10 after many."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2001_11220_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _etd():
+    from paper_2001_11220_amd import etd
+    return etd
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def P(n, bc, D=(0.02, 0.011), k=0.05, model="brusselator", params=None, h=None, ic="uniform_noise"):
+    params = params if params is not None else {"a": 1.0, "b": 3.4}
+    return W.Problem("t1", (n,), (bc,), tuple(D), k, model, params, 1, h=h, seed=0, ic=ic,
+                     ic_args={"base": 0.5, "amp": 0.3})
+
+
+SCHNAK = {"a": 0.1, "b": 0.9, "gamma": 1.0}
+CASES = [
+    P(64, "neumann"),
+    P(200, "periodic", model="gray_scott", params={"F": 0.04, "kappa": 0.06}, D=(2e-5, 1e-5), k=1.0),
+    P(512, "dirichlet", model="schnakenberg", params=SCHNAK, D=(1.0, 10.0), k=1e-4),  # streamed, m = 8
+    P(37, "neumann", model="enzyme", params={}, D=(0.2,)),
+    P(1, "dirichlet", model="enzyme", params={}, D=(0.2,)),
+    P(3, "periodic"),
+    P(96, "dirichlet", model="cgl", params={"beta": 1.3}, D=(1.0, 1.0), h=(0.5,)),
+]
+
+
+def _run(prob, u0, nsteps, scheme="rdp", precision="f64", field=None):
+    torch = _torch()
+    e = _etd().EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
+                      shift=prob.shift, scheme=scheme, precision=precision, field=field is not None)
+    assert e.pass_kernel(1).startswith("k_last")
+    u = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    if precision == "f32":
+        u = u.float()
+    if field is not None:
+        e.set_field(torch.from_numpy(field).cuda())
+    e.step(u, nsteps)
+    torch.cuda.synchronize()
+    e.close()
+    return u.cpu().numpy().astype(np.complex128 if precision == "c128" else np.float64)
+
+
+@pytest.mark.parametrize("prob", CASES, ids=lambda p: f"{p.model}-{p.shape[0]}-{p.bcs[0]}")
+def test_one_step_1d_matches_oracle(prob):
+    u0 = prob.initial()
+    got = _run(prob, u0, 1)
+    ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params(), 1)
+    err = rel_l2(got, ref)
+    print(f"[1-D one step] {prob.model} n={prob.shape[0]} {prob.bcs[0]} rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-12, err
+
+
+def test_1d_many_steps_etd1_and_f32():
+    prob = CASES[0]
+    u0 = prob.initial()
+    got = _run(prob, u0, 200)
+    ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params(), 200)
+    e200 = rel_l2(got, ref)
+    g1 = _run(prob, u0, 1, scheme="etd1")
+    r1 = O.etd1_if_step(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params())
+    e1 = rel_l2(g1, r1)
+    g32 = _run(prob, u0, 1, precision="f32")
+    r32 = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params(), 1)
+    e32 = rel_l2(g32, r32)
+    print(f"[1-D] 200 steps {e200:.2e}  etd1 {e1:.2e}  f32 {e32:.2e}", flush=True)
+    assert e200 <= 1e-10 and e1 <= 1e-12 and e32 <= 1e-5, (e200, e1, e32)
+
+
+def test_1d_schroedinger_soliton_matches_oracle():
+    """Section 8.4's 1-D soliton setup on 360 points of [-80, 99.5] (the
+    paper's 361 points have no chunking with at most 8 rows per lane),
+    Neumann, h = 1/2, k = 1/100: 1000 steps against the oracle, and the
+    trapezoidal mass conserved as in the paper's run."""
+    n, h, k, a, c = 360, 0.5, 0.01, 0.01, 0.1
+    x = -80.0 + h * np.arange(n)
+    psi0 = (np.sqrt(2 * a) * np.exp(1j * c / 2 * x) / np.cosh(np.sqrt(a) * x))[None]
+    prob = W.Problem("nls1d", (n,), ("neumann",), (1j,), k, "nls_z", {"B": 0.0, "C": -1.0}, 1, h=(h,))
+    got = _run(prob, psi0, 1000, precision="c128")
+    ref = O.etd_rdp_if_run(psi0, k, [1j], ["neumann"], [h], "nls_z", {"B": 0.0, "C": -1.0}, 1000)
+    err = rel_l2(got, ref)
+    mass = lambda u: h / 2 * (abs(u[0]) ** 2 + 2 * np.sum(abs(u[1:-1]) ** 2) + abs(u[-1]) ** 2)
+    dm = abs(mass(got[0]) - mass(psi0[0]))
+    print(f"[1-D soliton, 1000 steps] rel_l2={err:.2e} mass drift={dm:.1e}", flush=True)
+    assert err <= 1e-10, err
+    assert dm < 1e-10, dm
