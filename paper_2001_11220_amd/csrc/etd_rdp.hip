@@ -336,8 +336,9 @@ __global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_first_
   bool have = walk.next(tile);
   // A tile's lines are fetched during the previous tile's last phase (when
   // its U is no longer live; the last tile re-reads its own, unused, so that
-  // the buffer is dead between its uses); later species re-read the tile's
-  // lines (mostly from HBM: parking them in LDS instead cost the second tile
+  // the buffer is dead between its uses).  A later species re-reads the
+  // tile's lines the same way, fetched during the previous species' last
+  // phase (mostly from HBM: parking them in LDS instead cost the second tile
   // buffer and measured slower).
   T Un[S][M];
   auto fetch = [&](int64_t t_) {
@@ -388,18 +389,21 @@ __global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_first_
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       if (s > 0) {
+        // this tile's lines, fetched during the previous species' last phase
 #pragma unroll
-        for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, U[q], g, pos);
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+          for (int j = 0; j < M; ++j) U[q][j] = Un[q][j];
       }
       T f[M];
       double bf[M];
       field_line<M, P, T>(rx.fld1, bf, g, pos);
       react_species<S, M>(rx, U, s, bf, f);
-      const int64_t pf = have_next ? next : tile;
-      first_p_phase(U[s], f, s, pos, E1 && s == S - 1, pf);
+      const int64_t pf = (s == S - 1) ? (have_next ? next : tile) : tile;
+      first_p_phase(U[s], f, s, pos, E1, pf);
       if (!E1) {
         first_rs_phase(f, s, c2, pos, false, pf);
-        first_rs_phase(U[s], s, c1, pos, s == S - 1, pf);
+        first_rs_phase(U[s], s, c1, pos, true, pf);
       }
     }
     tile = next;
