@@ -103,3 +103,16 @@ def test_1d_schroedinger_soliton_matches_oracle():
     print(f"[1-D soliton, 1000 steps] rel_l2={err:.2e} mass drift={dm:.1e}", flush=True)
     assert err <= 1e-10, err
     assert dm < 1e-10, dm
+
+
+def test_1d_schroedinger_with_field_matches_oracle():
+    prob = W.Problem("nls1f", (96,), ("dirichlet",), (1j,), 1e-3, "nls_z", {"B": 0.4, "C": -1.0}, 1, seed=0,
+                     ic="complex_noise", ic_args={"amp": 0.5})
+    u0 = prob.initial()
+    field = np.random.default_rng(6).standard_normal((96,))
+    got = _run(prob, u0, 3, precision="c128", field=field)
+    ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model,
+                           dict(prob.oracle_params(), Bfield=field), 3)
+    err = rel_l2(got, ref)
+    print(f"[1-D complex field, 3 steps] rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-12, err
