@@ -120,14 +120,14 @@ def main():
     prob = W.WORKLOADS[args.workload](**({"n": args.n} if args.n else {}))
     if args.steps is None:
         args.steps = prob.nsteps
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
     prec = args.precision
     if prob.is_complex:
         if prec != "f64":
             print(f"bench.py: workload {args.workload} runs in complex FP64 only", file=sys.stderr)
             sys.exit(2)
         prec = "c128"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
     e = EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, h=prob.h,
                shift=prob.shift, device=dev, precision=prec)
     esize = {"f64": 8, "f32": 4, "c128": 16}[prec]

@@ -40,3 +40,11 @@ def test_pass_kernel_names():
     import bench
     assert bench.pass_names(e, 3) == [e.pass_kernel(p) for p in (1, 2, 3)]
     assert bench.pass_words(3) == [4, 6, 4] and bench.pass_words(2) == [4, 4]
+
+
+def test_precision_option_is_refused_where_not_built():
+    for wl in ("brusselator_ensemble", "schnakenberg3d_adjoint", "cgl3d_complex"):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", wl,
+                            "--precision", "f32"], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2, (wl, r.stderr)
+        assert r.stdout.strip() == ""
