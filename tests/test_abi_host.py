@@ -276,6 +276,21 @@ def test_step_validates_workspace_without_touching_the_gpu():
     assert etd.lib.etd_rdp_apply_solve(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, 1, 0, 2, None) == etd.ETD_ERR_ARG
     assert etd.lib.etd_rdp_apply_solve(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, 3, 0, 1, None) == etd.ETD_ERR_ARG
     assert etd.status_string(etd.ETD_ERR_WORKSPACE).startswith("workspace")
+    # zero steps: a no-op that enqueues nothing (valid arguments, no HIP call)
+    assert etd.lib.etd_rdp_step(ctx, fake_u, ctypes.c_void_p(0x2000), p.ws_bytes, 0, None) == etd.ETD_OK
+
+
+def test_empty_and_degenerate_grids():
+    etd = _lib()
+    for shape, bcs in (((0, 8), ("dirichlet", "neumann")),      # an empty axis
+                       ((8, 1), ("neumann", "neumann")),        # Neumann needs two points
+                       ((8, 2), ("periodic", "periodic"))):     # periodic needs three
+        with pytest.raises(etd.EtdError) as ei:
+            _init(shape, bcs)
+        assert ei.value.status == etd.ETD_ERR_ARG, shape
+    one = _init((1, 1), ("dirichlet", "dirichlet"))  # a single cell is a valid problem
+    assert one.line_split(1) == (1, 1) and one.line_split(2) == (1, 1)
+    one.close()
 
 
 def test_adjoint_workspace_and_gradient_size():
