@@ -1,0 +1,82 @@
+"""Seeded random configurations (dimension 1-4, line lengths with ragged
+tiles, boundary conditions, models, FP64 / FP32 / complex, one or two lines
+per wavefront, both schemes), each one step on the GPU against the oracle.
+Tolerances: 1e-12 (FP64, complex), max(1e-5, 5 eps32 (1 + 4 r_max)) (FP32)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2001_11220_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# line lengths that chunk into <= 64 chunks of <= 8 rows, including ones
+# that run two lines per wavefront (32 m) and odd ones
+LENGTHS = [1, 2, 3, 5, 7, 16, 31, 33, 47, 64, 65, 96, 100, 128, 130, 160, 192, 224, 256, 300, 448, 512]
+REAL_MODELS = [("brusselator", {"a": 1.0, "b": 3.4}, (0.02, 0.011)),
+               ("gray_scott", {"F": 0.04, "kappa": 0.06}, (2e-3, 1e-3)),
+               ("schnakenberg", {"a": 0.1, "b": 0.9, "gamma": 1.0}, (0.01, 0.1)),
+               ("enzyme", {}, (0.2,)),
+               ("cgl", {"beta": 1.3}, (0.05, 0.05)),
+               ("linear", {"C": [[-0.3, 0.2], [0.1, -0.5]]}, (0.3, 0.1))]
+MIN_N = {"dirichlet": 1, "neumann": 2, "periodic": 3}
+EPS32 = 2.0 ** -24
+
+
+def _config(seed):
+    rng = np.random.default_rng(1000 + seed)
+    d = int(rng.integers(1, 5))
+    budget = {1: 512, 2: 512 * 64, 3: 64 * 64 * 48, 4: 24 * 20 * 16 * 12}[d]
+    while True:
+        shape = tuple(int(rng.choice(LENGTHS)) for _ in range(d))
+        if int(np.prod(shape)) <= budget:
+            break
+    bcs = []
+    for n in shape:
+        ok = [b for b in ("dirichlet", "neumann", "periodic") if n >= MIN_N[b]]
+        bcs.append(str(rng.choice(ok)))
+    prec = str(rng.choice(["f64", "f64", "f32", "c128"]))
+    lpw = "auto" if prec == "c128" else rng.choice(["auto", 1, 2]).item()
+    scheme = str(rng.choice(["rdp", "rdp", "etd1"]))
+    if prec == "c128":
+        model, params = str(rng.choice(["cgl_z", "nls_z"])), None
+        params = {"beta": 1.3} if model == "cgl_z" else {"B": 0.4, "C": -1.0}
+        D = (complex(float(rng.uniform(0.0, 1.0)), float(rng.uniform(-1.0, 1.0))),)
+        ic, ic_args = "complex_noise", {"amp": 0.5}
+    else:
+        model, params, D = REAL_MODELS[int(rng.integers(len(REAL_MODELS)))]
+        ic, ic_args = "uniform_noise", {"base": 0.5, "amp": 0.3}
+    k = float(10.0 ** rng.uniform(-4, -1))
+    prob = W.Problem("r", shape, tuple(bcs), tuple(D), k, model, params, 1, seed=seed, ic=ic,
+                     ic_args=ic_args)
+    return prob, prec, lpw, scheme
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_configuration_matches_oracle(seed):
+    import torch
+    from paper_2001_11220_amd import etd
+    prob, prec, lpw, scheme = _config(seed)
+    u0 = prob.initial()
+    e = etd.EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, scheme=scheme,
+                   lines_per_wave=lpw, precision=prec)
+    names = [e.pass_kernel(p) for p in range(1, len(prob.shape) + 1)]
+    u = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    if prec == "f32":
+        u = u.float()
+    e.step(u, 1)
+    torch.cuda.synchronize()
+    e.close()
+    got = u.cpu().numpy().astype(np.complex128 if prec == "c128" else np.float64)
+    step = O.etd1_if_step if scheme == "etd1" else O.etd_rdp_if_step
+    ref = step(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params())
+    err = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+    if prec == "f32":
+        r = max(prob.k * abs(dv) / h ** 2 for dv in prob.D for h in prob.hs())
+        tol = max(1e-5, 5 * EPS32 * (1 + 4 * r))
+    else:
+        tol = 1e-12
+    print(f"[random {seed}] {prob.shape} {prob.bcs} {prob.model} {prec} lpw={lpw} {scheme} "
+          f"{names} rel_l2={err:.2e}", flush=True)
+    assert err <= tol, (err, tol)
