@@ -80,3 +80,41 @@ def test_random_configuration_matches_oracle(seed):
     print(f"[random {seed}] {prob.shape} {prob.bcs} {prob.model} {prec} lpw={lpw} {scheme} "
           f"{names} rel_l2={err:.2e}", flush=True)
     assert err <= tol, (err, tol)
+
+
+@pytest.mark.parametrize("seed,model,params_of,s", [
+    (0, "brusselator", lambda r: {"a": 1.0, "b": float(r.uniform(2.0, 4.0))}, 2),
+    (1, "gray_scott", lambda r: {"F": float(r.uniform(0.02, 0.06)), "kappa": 0.06}, 2),
+    (2, "enzyme", lambda r: {}, 1),
+    (3, "schnakenberg", lambda r: {"a": 0.1, "b": float(r.uniform(0.5, 1.0)), "gamma": 1.0}, 2),
+])
+def test_random_ensemble_matches_oracle(seed, model, params_of, s):
+    """A batch of uneven, non-square instances with every boundary condition
+    (and per-instance h) in one graph; every instance against the oracle."""
+    import torch
+    from paper_2001_11220_amd.etd import EtdRdpBatch
+    rng = np.random.default_rng(2000 + seed)
+    insts, states = [], []
+    for _ in range(12):
+        shape = tuple(int(rng.choice(LENGTHS[:-3])) for _ in range(2))  # up to 256 per axis
+        bcs = tuple(str(rng.choice([b for b in ("dirichlet", "neumann", "periodic") if n >= MIN_N[b]]))
+                    for n in shape)
+        h = tuple(float(rng.uniform(0.005, 0.05)) if rng.random() < 0.5 else 0.0 for _ in range(2))
+        D = tuple(float(v) for v in rng.uniform(1e-4, 5e-3, size=s))
+        insts.append({"shape": shape, "bcs": bcs, "D": D, "params": params_of(rng), "h": h})
+        states.append(0.5 + 0.3 * rng.random((s, shape[1], shape[0])))
+    k = 0.01
+    b = EtdRdpBatch(insts, s, model, k)
+    u = b.pack(states)
+    b.step(u, 2, use_graph=True)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, ins in enumerate(insts):
+        got = b.view(u, i).cpu().numpy()
+        hs = [hv if hv else O.default_h(n, bc) for hv, n, bc in zip(ins["h"], ins["shape"], ins["bcs"])]
+        ref = O.etd_rdp_if_run(states[i], k, ins["D"], ins["bcs"], hs, model, ins["params"], 2)
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        worst = max(worst, err)
+        assert err <= 1e-12, (i, ins["shape"], ins["bcs"], err)
+    b.close()
+    print(f"[random ensemble {model}] 12 instances, worst rel_l2={worst:.2e}", flush=True)
