@@ -118,3 +118,46 @@ def test_random_ensemble_matches_oracle(seed, model, params_of, s):
         assert err <= 1e-12, (i, ins["shape"], ins["bcs"], err)
     b.close()
     print(f"[random ensemble {model}] 12 instances, worst rel_l2={worst:.2e}", flush=True)
+
+
+ADJ_MODELS = [("brusselator", {"a": 1.0, "b": 3.4}, (0.02, 0.011), (0.6, 0.9)),
+              ("gray_scott", {"F": 0.04, "kappa": 0.06}, (2e-3, 1e-3), (0.5, 0.3)),
+              ("schnakenberg", {"a": 0.1, "b": 0.9, "gamma": 1.0}, (0.01, 0.1), (1.0, 0.9)),
+              ("enzyme", {}, (0.2,), (0.5,)),
+              ("cgl", {"beta": 1.3}, (0.05, 0.05), (0.3, -0.2)),
+              ("linear", {"C": [[-0.3, 0.2], [0.1, -0.5]]}, (0.3, 0.1), (0.4, 0.6))]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_reverse_step_matches_oracle(seed):
+    """Reverse step (state and parameter gradients) on random 2-D / 3-D
+    configurations; tolerances of the reverse-mode tests."""
+    import torch
+    from paper_2001_11220_amd import etd
+    rng = np.random.default_rng(3000 + seed)
+    d = int(rng.integers(2, 4))
+    small = [n for n in LENGTHS if n <= 64]
+    while True:
+        shape = tuple(int(rng.choice(small)) for _ in range(d))
+        if int(np.prod(shape)) <= 48 * 48 * 16:
+            break
+    bcs = tuple(str(rng.choice([b for b in ("dirichlet", "neumann", "periodic") if n >= MIN_N[b]]))
+                for n in shape)
+    model, params, D, offset = ADJ_MODELS[int(rng.integers(len(ADJ_MODELS)))]
+    k = float(10.0 ** rng.uniform(-3, -1))
+    s = len(D)
+    U = np.stack([offset[i] + 0.2 * rng.random(shape[::-1]) for i in range(s)])
+    lam = rng.standard_normal(U.shape)
+    e = etd.EtdRdp(shape, bcs, D, k, model, params)
+    lo, g = e.adjoint(torch.from_numpy(U).cuda(), torch.from_numpy(lam).cuda())
+    torch.cuda.synchronize()
+    lo, g = lo.cpu().numpy(), g.cpu().numpy()
+    e.close()
+    hs = [O.default_h(n, b) for n, b in zip(shape, bcs)]
+    lo_o, gD, gth = O.adjoint_step(U, lam, k, D, bcs, hs, model, dict(params))
+    go = np.concatenate([gD, gth])
+    err = float(np.linalg.norm(lo - lo_o) / np.linalg.norm(lo_o))
+    print(f"[random reverse {seed}] {shape} {bcs} {model} k={k:.1e} rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-11, err
+    tol = 1e-9 * np.abs(go) + 1e-11 * float(np.max(np.abs(go)))
+    assert np.all(np.abs(g - go) <= tol), (g, go)
