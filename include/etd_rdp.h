@@ -118,9 +118,9 @@ typedef struct etd_reaction_t {
 /* Element type of the state and of the carried arrays
  * (etd_scheme_t.precision).  The line-solve tables are built and held in
  * FP64 either way; an FP32 context converts them when its kernels load them.
- * FP32 contexts step with etd_rdp_step_f32 / etd_rdp_run_pass_f32; the
- * reverse-mode step, the single solves, debug_passes and the batch API are
- * FP64 only (ETD_ERR_UNSUPPORTED). */
+ * FP32 contexts step with etd_rdp_step_f32 / etd_rdp_run_pass_f32, FP32
+ * ensembles with etd_rdp_batch_step_f32; the reverse-mode step, the single
+ * solves and debug_passes are FP64 only (ETD_ERR_UNSUPPORTED). */
 #define ETD_PRECISION_F64 0
 #define ETD_PRECISION_F32 1
 /* Complex species (a complex diffusion coefficient, Sections 8.3 and 8.4):
@@ -364,9 +364,9 @@ int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1,
  * All instances share the number of species s, the reaction model, the time
  * step k and the scheme; each has its own grid, boundary conditions,
  * diffusion coefficients and reaction parameters.  The states are packed
- * back to back in one device array, instance i at the offset (in doubles)
- * that etd_rdp_batch_offsets reports, each laid out like a single problem's
- * state.
+ * back to back in one device array, instance i at the offset (in elements:
+ * doubles, or floats for an FP32 ensemble) that etd_rdp_batch_offsets
+ * reports, each laid out like a single problem's state.
  * ====================================================================== */
 
 typedef struct etd_instance_t {
@@ -383,7 +383,10 @@ typedef struct etd_rdp_batch etd_rdp_batch;
 /*
  * etd_rdp_batch_init -- validate ninst >= 1 instances and build their tables
  * on the host (no HIP call).  s and model as in etd_rdp_init; every instance
- * obeys etd_rdp_init's rules for d = 2.  Errors as etd_rdp_init.
+ * obeys etd_rdp_init's rules for d = 2.  scheme (may be NULL: ETD-RDP, FP64)
+ * selects ETD_SCHEME_RDP or ETD_SCHEME_ETD1 and ETD_PRECISION_F64 or
+ * ETD_PRECISION_F32 (complex: ETD_ERR_UNSUPPORTED); its other fields are
+ * ignored.  Errors as etd_rdp_init.
  */
 int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s,
                        int32_t model, double k, const etd_scheme_t* scheme,
@@ -391,7 +394,7 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s,
 
 int etd_rdp_batch_destroy(etd_rdp_batch* b);
 
-/* offsets[0..ninst]: start of instance i in the packed state (doubles);
+/* offsets[0..ninst]: start of instance i in the packed state (elements);
  * offsets[ninst] is the total length.  Offsets are multiples of 32. */
 int etd_rdp_batch_offsets(const etd_rdp_batch* b, int64_t* offsets);
 
@@ -405,10 +408,22 @@ int etd_rdp_batch_workspace_bytes(const etd_rdp_batch* b, size_t* bytes);
  * graph (on a private capture stream) and launches that graph on `stream`;
  * the graph is kept and replayed while (u, ws, nsteps) stay the same.
  * Otherwise the kernels are launched one by one.  Asynchronous.
+ * ETD_ERR_ARG for an FP32 ensemble.
  */
 int etd_rdp_batch_step(etd_rdp_batch* b, double* u_packed, void* ws,
                        size_t ws_bytes, int64_t nsteps, int32_t use_graph,
                        void* stream);
+
+/*
+ * etd_rdp_batch_step_f32 -- etd_rdp_batch_step for an ensemble created with
+ * ETD_PRECISION_F32: u_packed holds offsets[ninst] floats, the carried
+ * arrays are FP32 and every solve and reaction evaluation runs in FP32
+ * (tables converted from FP64), as etd_rdp_step_f32 does for one problem.
+ * ETD_ERR_ARG for an FP64 ensemble.
+ */
+int etd_rdp_batch_step_f32(etd_rdp_batch* b, float* u_packed, void* ws,
+                           size_t ws_bytes, int64_t nsteps, int32_t use_graph,
+                           void* stream);
 
 /* Number of kernel launches of one step (for tests and reports). */
 int etd_rdp_batch_launches_per_step(const etd_rdp_batch* b, int32_t* n);

@@ -7,7 +7,9 @@
 // (one kernel instantiation per m); one launch per (pass, group) walks the
 // group's tiles, 8 or 16 lines each, in instance order.  A persistent block re-stages the per-lane PCR data in LDS
 // only when its next tile belongs to another instance.  The launches of all
-// steps can be recorded into one HIP graph.
+// steps can be recorded into one HIP graph.  The kernels take the element
+// type as a template parameter (FP64, or FP32 with the FP64 tables
+// converted as they are staged), as the single-problem kernels do.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +19,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "etd_device.hpp"
@@ -40,15 +43,17 @@ struct BatchInst {
 
 // Pass 1 of the ensemble (axis 1).  A tile is L x-lines of one instance with
 // adjacent y; tile_loc gives its first line / L.
-template <int M, int S, int L>
+template <int M, int S, int L, typename T>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
-    const double* __restrict__ u, double* __restrict__ c1, double* __restrict__ c2,
-    double* __restrict__ w, const BatchInst* __restrict__ insts,
+    const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
+    T* __restrict__ w, const BatchInst* __restrict__ insts,
     const int* __restrict__ tile_inst, const int* __restrict__ tile_loc, int64_t ntiles,
-    double k, int etd1) {
-  extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+    T k, int etd1) {
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kLanes, T>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   const int lane = threadIdx.x & 63;
   int staged = -1;
   TileCursor cur;
@@ -65,15 +70,15 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
       __syncthreads();
       staged = ii;
     }
-    const AxisTabs<S> at{I.tab1, lt};
+    const AxisTabs<S, kLanes, T> at{I.tab1, lt};
     const PassGeom g = I.g1;
     const TileAt pos((int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
-    double U[S][M], f[S][M];
+    T U[S][M], f[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s) line_load<M>(u + I.off + s * g.N, U[s], g, pos);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double uu[S], ff[S];
+      T uu[S], ff[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) uu[s] = U[s][j];
       react<S>(I.rx, uu, ff);
@@ -84,16 +89,16 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
     for (int s = 0; s < S; ++s) {
       const int64_t o = I.off + s * g.N;
       if (etd1) {
-        double x[1][M];
+        T x[1][M];
 #pragma unroll
         for (int j = 0; j < M; ++j) x[0][j] = fma(k, f[s][j], U[s][j]);
-        const SolveTab* tb[1] = {at.P(s)};
-        const LaneTab* lb[1] = {at.lP(s)};
+        const TabOf<T>* tb[1] = {at.P(s)};
+        const LT* lb[1] = {at.lP(s)};
         line_solve<M, 1>(tb, lb, x, lane);
         tile_store<M, L>(w + o, x[0], tl, g, pos, cur);
         continue;
       }
-      double x[5][M];
+      T x[5][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         x[0][j] = U[s][j];
@@ -102,13 +107,13 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
         x[3][j] = f[s][j];
         x[4][j] = fma(k, f[s][j], U[s][j]);
       }
-      const SolveTab* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
-      const LaneTab* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
+      const TabOf<T>* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
+      const LT* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
       line_solve<M, 5>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        x[0][j] = 9.0 * x[0][j] - 8.0 * x[2][j];
-        x[1][j] = 9.0 * x[1][j] - 8.0 * x[3][j];
+        x[0][j] = T(9) * x[0][j] - T(8) * x[2][j];
+        x[1][j] = T(9) * x[1][j] - T(8) * x[3][j];
       }
       tile_store<M, L>(c1 + o, x[0], tl, g, pos, cur);
       tile_store<M, L>(c2 + o, x[1], tl, g, pos, cur);
@@ -120,17 +125,19 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
 // Pass 2 of the ensemble (axis 2).  A tile is L y-lines of one instance with
 // adjacent x, read line by line from the carried triple; u is written
 // through the LDS transpose.
-template <int M, int S, int L>
+template <int M, int S, int L, typename T>
 __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_last(
-    double* __restrict__ u, const double* __restrict__ c1, const double* __restrict__ c2,
-    const double* __restrict__ w, const BatchInst* __restrict__ insts,
+    T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
+    const T* __restrict__ w, const BatchInst* __restrict__ insts,
     const int* __restrict__ tile_inst, const int* __restrict__ tile_loc, int64_t ntiles,
-    double k, int etd1) {
-  extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* tl = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+    T k, int etd1) {
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kLanes, T>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
   const int lane = threadIdx.x & 63;
-  const double k2 = 2.0 * k, k15 = 1.5 * k, k05 = 0.5 * k;
+  const T k2 = T(2) * k, k15 = T(1.5) * k, k05 = T(0.5) * k;
   int staged = -1;
   TileCursor cur;
   TileWalk walk(ntiles);
@@ -146,15 +153,15 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_last(
       __syncthreads();
       staged = ii;
     }
-    const AxisTabs<S> at{I.tab2, lt};
+    const AxisTabs<S, kLanes, T> at{I.tab2, lt};
     const PassGeom g = I.g2;
     const TileAt pos((int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
-    double us[S][M];
+    T us[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s) line_load<M>(w + I.off + s * g.N, us[s], g, pos);
     {
-      const SolveTab* tb[S];
-      const LaneTab* lb[S];
+      const TabOf<T>* tb[S];
+      const LT* lb[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         tb[s] = at.P(s);
@@ -169,7 +176,7 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_last(
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double uu[S], ff[S];
+      T uu[S], ff[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) uu[s] = us[s][j];
       react<S>(I.rx, uu, ff);
@@ -179,16 +186,16 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_last(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int64_t o = I.off + s * g.N;
-      double a[M], b[M], x[2][M];
+      T a[M], b[M], x[2][M];
       line_load<M>(c1 + o, a, g, pos);
       line_load<M>(c2 + o, b, g, pos);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        x[0][j] = fma(k, us[s][j], fma(k2, b[j], 9.0 * a[j]));
-        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], 8.0 * a[j]));
+        x[0][j] = fma(k, us[s][j], fma(k2, b[j], T(9) * a[j]));
+        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], T(8) * a[j]));
       }
-      const SolveTab* tb[2] = {at.T(s), at.Sx(s)};
-      const LaneTab* lb[2] = {at.lT(s), at.lS(s)};
+      const TabOf<T>* tb[2] = {at.T(s), at.Sx(s)};
+      const LT* lb[2] = {at.lT(s), at.lS(s)};
       line_solve<M, 2>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
@@ -210,7 +217,7 @@ struct Group {
   std::vector<int> tile_inst;     // per tile
   std::vector<int> tile_loc;      // per tile: tile index inside its instance
   int max_n = 0;                  // largest line length
-  int tile = 0, nbuf = 1;         // LDS tile buffer (doubles) and buffer count
+  int tile = 0, nbuf = 1;         // LDS tile buffer (elements) and buffer count
   size_t lds = 0;                 // dynamic LDS of the launch
   size_t off_tile_inst = 0, off_tile_loc = 0;  // workspace offsets
 };
@@ -226,6 +233,7 @@ struct GraphCache {
 
 struct etd_rdp_batch {
   int ninst = 0, s = 0, model = 0, scheme = ETD_SCHEME_RDP;
+  int precision = ETD_PRECISION_F64;  // element type of the state and carried arrays
   double k = 0;
   std::vector<etd_instance_t> inst;
   std::vector<int64_t> n1, n2, offsets;
@@ -244,6 +252,10 @@ struct etd_rdp_batch {
 namespace {
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(const etd_rdp_batch* b) {
+  return b->precision == ETD_PRECISION_F32 ? sizeof(float) : sizeof(double);
+}
 
 int species_of(int model) {
   switch (model) {
@@ -275,12 +287,14 @@ void build_groups(etd_rdp_batch* b, int axis, std::vector<Group>& out) {
     }
   }
   out.clear();
-  const size_t fixed = lane_lds(3 * b->s);
+  const size_t esize = elem_bytes(b);
+  const size_t fixed = b->precision == ETD_PRECISION_F32 ? lane_lds<kLanes, float>(3 * b->s)
+                                                         : lane_lds<kLanes, double>(3 * b->s);
   for (auto& kv : by_m) {
     Group& g = kv.second;
     g.tile = g.lines * tile_pitch(g.max_n);
-    g.nbuf = tile_buffers(fixed, g.lines, g.tile);
-    g.lds = fixed + sizeof(double) * (size_t)g.nbuf * g.tile;
+    g.nbuf = tile_buffers(fixed, g.lines, g.tile, esize);
+    g.lds = fixed + esize * (size_t)g.nbuf * g.tile;
     out.push_back(g);
   }
 }
@@ -347,56 +361,57 @@ void build_image(etd_rdp_batch* b, char* ws) {
     }
 }
 
-template <int M, int S>
-hipError_t launch_b1(const etd_rdp_batch* b, const Group& g, const double* u, char* ws,
+template <int M, int S, typename T>
+hipError_t launch_b1(const etd_rdp_batch* b, const Group& g, const T* u, char* ws,
                      hipStream_t st) {
   constexpr int L = kLinesFor<M>;
-  hipError_t e = set_lds(kb_first<M, S, L>, g.lds);
+  hipError_t e = set_lds(kb_first<M, S, L, T>, g.lds);
   if (e != hipSuccess) return e;
   unsigned grid;
   const int64_t nt = static_cast<int64_t>(g.tile_inst.size());
-  e = persistent_grid(kb_first<M, S, L>, g.lds, nt, &grid, 64 * L);
+  e = persistent_grid(kb_first<M, S, L, T>, g.lds, nt, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((kb_first<M, S, L>), dim3(grid), dim3(64 * L), g.lds, st, u,
-                     reinterpret_cast<double*>(ws + b->off_c1), reinterpret_cast<double*>(ws + b->off_c2),
-                     reinterpret_cast<double*>(ws + b->off_w),
+  hipLaunchKernelGGL((kb_first<M, S, L, T>), dim3(grid), dim3(64 * L), g.lds, st, u,
+                     reinterpret_cast<T*>(ws + b->off_c1), reinterpret_cast<T*>(ws + b->off_c2),
+                     reinterpret_cast<T*>(ws + b->off_w),
                      reinterpret_cast<const BatchInst*>(ws + b->off_insts),
                      reinterpret_cast<const int*>(ws + g.off_tile_inst),
-                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, b->k,
+                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, static_cast<T>(b->k),
                      b->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-template <int M, int S>
-hipError_t launch_b2(const etd_rdp_batch* b, const Group& g, double* u, char* ws, hipStream_t st) {
+template <int M, int S, typename T>
+hipError_t launch_b2(const etd_rdp_batch* b, const Group& g, T* u, char* ws, hipStream_t st) {
   constexpr int L = kLinesFor<M>;
-  hipError_t e = set_lds(kb_last<M, S, L>, g.lds);
+  hipError_t e = set_lds(kb_last<M, S, L, T>, g.lds);
   if (e != hipSuccess) return e;
   unsigned grid;
   const int64_t nt = static_cast<int64_t>(g.tile_inst.size());
-  e = persistent_grid(kb_last<M, S, L>, g.lds, nt, &grid, 64 * L);
+  e = persistent_grid(kb_last<M, S, L, T>, g.lds, nt, &grid, 64 * L);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((kb_last<M, S, L>), dim3(grid), dim3(64 * L), g.lds, st, u,
-                     reinterpret_cast<const double*>(ws + b->off_c1),
-                     reinterpret_cast<const double*>(ws + b->off_c2),
-                     reinterpret_cast<const double*>(ws + b->off_w),
+  hipLaunchKernelGGL((kb_last<M, S, L, T>), dim3(grid), dim3(64 * L), g.lds, st, u,
+                     reinterpret_cast<const T*>(ws + b->off_c1),
+                     reinterpret_cast<const T*>(ws + b->off_c2),
+                     reinterpret_cast<const T*>(ws + b->off_w),
                      reinterpret_cast<const BatchInst*>(ws + b->off_insts),
                      reinterpret_cast<const int*>(ws + g.off_tile_inst),
-                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, b->k,
+                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, static_cast<T>(b->k),
                      b->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
   return hipGetLastError();
 }
 
-int batch_one_step(etd_rdp_batch* b, double* u, char* ws, hipStream_t st) {
+template <typename T>
+int batch_one_step(etd_rdp_batch* b, T* u, char* ws, hipStream_t st) {
   hipError_t e = hipSuccess;
   for (const Group& g : b->g1) {
-    if (b->s == 1) { ETD_DISPATCH_M(g.m, e = (launch_b1<M_, 1>(b, g, u, ws, st))); }
-    else { ETD_DISPATCH_M(g.m, e = (launch_b1<M_, 2>(b, g, u, ws, st))); }
+    if (b->s == 1) { ETD_DISPATCH_M(g.m, e = (launch_b1<M_, 1, T>(b, g, u, ws, st))); }
+    else { ETD_DISPATCH_M(g.m, e = (launch_b1<M_, 2, T>(b, g, u, ws, st))); }
     if (e != hipSuccess) { b->last_hip = e; return ETD_ERR_HIP; }
   }
   for (const Group& g : b->g2) {
-    if (b->s == 1) { ETD_DISPATCH_M(g.m, e = (launch_b2<M_, 1>(b, g, u, ws, st))); }
-    else { ETD_DISPATCH_M(g.m, e = (launch_b2<M_, 2>(b, g, u, ws, st))); }
+    if (b->s == 1) { ETD_DISPATCH_M(g.m, e = (launch_b2<M_, 1, T>(b, g, u, ws, st))); }
+    else { ETD_DISPATCH_M(g.m, e = (launch_b2<M_, 2, T>(b, g, u, ws, st))); }
     if (e != hipSuccess) { b->last_hip = e; return ETD_ERR_HIP; }
   }
   return ETD_OK;
@@ -420,7 +435,8 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s, int
   if (ws_ < 0 || (ws_ > 0 && ws_ != s)) return ETD_ERR_ARG;
   if (!(std::isfinite(k) && k > 0)) return ETD_ERR_ARG;
   const int sch = scheme ? scheme->scheme : ETD_SCHEME_RDP;
-  if (scheme && scheme->precision != ETD_PRECISION_F64) return ETD_ERR_UNSUPPORTED;
+  const int prec = scheme ? scheme->precision : ETD_PRECISION_F64;
+  if (prec != ETD_PRECISION_F64 && prec != ETD_PRECISION_F32) return ETD_ERR_UNSUPPORTED;
   if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
   etd_rdp_batch* b = new (std::nothrow) etd_rdp_batch();
   if (!b) return ETD_ERR_INTERNAL;
@@ -429,6 +445,7 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s, int
   b->model = model;
   b->k = k;
   b->scheme = sch;
+  b->precision = prec;
   b->inst.assign(inst, inst + ninst);
   b->offsets.push_back(0);
   const double gam[3] = {1.0, 3.0, 4.0};
@@ -487,7 +504,7 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s, int
       g.off_tile_loc = off;
       off = round_up(off + sizeof(int) * g.tile_loc.size(), 256);
     }
-  b->arr_bytes = round_up(sizeof(double) * static_cast<size_t>(b->offsets.back()), 256);
+  b->arr_bytes = round_up(elem_bytes(b) * static_cast<size_t>(b->offsets.back()), 256);
   b->off_c1 = off;
   b->off_c2 = off + b->arr_bytes;
   b->off_w = off + 2 * b->arr_bytes;
@@ -522,9 +539,15 @@ int etd_rdp_batch_launches_per_step(const etd_rdp_batch* b, int32_t* n) {
   return ETD_OK;
 }
 
-int etd_rdp_batch_step(etd_rdp_batch* b, double* u, void* ws, size_t ws_bytes, int64_t nsteps,
-                       int32_t use_graph, void* stream) {
-  if (!b || !u || nsteps < 0) return ETD_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int batch_step_impl(etd_rdp_batch* b, T* u, void* ws, size_t ws_bytes, int64_t nsteps,
+                    int32_t use_graph, void* stream) {
+  constexpr int kPrec = std::is_same<T, float>::value ? ETD_PRECISION_F32 : ETD_PRECISION_F64;
+  if (!b || !u || nsteps < 0 || b->precision != kPrec) return ETD_ERR_ARG;
   if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0 || ws_bytes < b->ws_bytes) return ETD_ERR_WORKSPACE;
   if (nsteps == 0) return ETD_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -571,6 +594,20 @@ int etd_rdp_batch_step(etd_rdp_batch* b, double* u, void* ws, size_t ws_bytes, i
   hipError_t e = hipGraphLaunch(b->graph.exec, st);
   if (e != hipSuccess) { b->last_hip = e; return ETD_ERR_HIP; }
   return ETD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int etd_rdp_batch_step(etd_rdp_batch* b, double* u, void* ws, size_t ws_bytes, int64_t nsteps,
+                       int32_t use_graph, void* stream) {
+  return batch_step_impl(b, u, ws, ws_bytes, nsteps, use_graph, stream);
+}
+
+int etd_rdp_batch_step_f32(etd_rdp_batch* b, float* u, void* ws, size_t ws_bytes, int64_t nsteps,
+                           int32_t use_graph, void* stream) {
+  return batch_step_impl(b, u, ws, ws_bytes, nsteps, use_graph, stream);
 }
 
 }  // extern "C"

@@ -97,6 +97,7 @@ def _load():
         "etd_rdp_batch_offsets": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "etd_rdp_batch_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
         "etd_rdp_batch_step": (ctypes.c_int, [P, P, P, SZ, I64, I32, P]),
+        "etd_rdp_batch_step_f32": (ctypes.c_int, [P, P, P, SZ, I64, I32, P]),
         "etd_rdp_batch_launches_per_step": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
     }
     for name, (res, args) in sig.items():
@@ -357,11 +358,14 @@ class EtdRdpBatch:
 
     ``instances``: sequence of dicts with keys ``shape`` (n_1, n_2), ``bcs``,
     ``D`` and ``params`` (and optionally ``h``, ``shift``).  The packed state
-    is one float64 device tensor of ``offsets[-1]`` doubles; instance i is
+    is one device tensor of ``offsets[-1]`` elements (float64, or float32
+    with ``precision="f32"``); instance i is
     ``u[offsets[i]: offsets[i] + s*n_1*n_2]`` viewed as ``(s, n_2, n_1)``.
     """
 
-    def __init__(self, instances, s, model, k, scheme="rdp", device=None):
+    def __init__(self, instances, s, model, k, scheme="rdp", device=None, precision="f64"):
+        if precision not in ("f64", "f32"):
+            raise ValueError(f"ensembles run in f64 or f32, not {precision!r}")
         n = len(instances)
         arr = (Instance * n)()
         for i, ins in enumerate(instances):
@@ -381,11 +385,13 @@ class EtdRdpBatch:
                 a.shift[q] = rx.shift[q]
         sch = Scheme()
         sch.scheme = SCHEMES[scheme]
+        sch.precision = PRECISIONS[precision]
         ctx = ctypes.c_void_p()
         _check(lib.etd_rdp_batch_init(n, arr, int(s), MODELS[model], float(k), ctypes.byref(sch),
                                       ctypes.byref(ctx)), "etd_rdp_batch_init")
         self._ctx = ctx
         self.n, self.s = n, int(s)
+        self.precision = precision
         self.shapes = [tuple(int(v) for v in ins["shape"]) for ins in instances]
         offs = (ctypes.c_int64 * (n + 1))()
         _check(lib.etd_rdp_batch_offsets(ctx, offs), "etd_rdp_batch_offsets")
@@ -421,12 +427,12 @@ class EtdRdpBatch:
 
     def pack(self, states):
         """Pack per-instance numpy/torch states (s, n_2, n_1) into one
-        float64 torch tensor (on the workspace's device)."""
+        torch tensor of the ensemble's dtype (on the workspace's device)."""
         import torch
         ws = self.workspace()
-        u = torch.zeros(self.offsets[-1], dtype=torch.float64, device=ws.device)
+        u = torch.zeros(self.offsets[-1], dtype=self.dtype, device=ws.device)
         for i, st in enumerate(states):
-            t = torch.as_tensor(st, dtype=torch.float64).reshape(-1)
+            t = torch.as_tensor(st).to(self.dtype).reshape(-1)
             u[self.offsets[i]: self.offsets[i] + t.numel()] = t.to(ws.device)
         return u
 
@@ -434,12 +440,18 @@ class EtdRdpBatch:
         n1, n2 = self.shapes[i]
         return u[self.offsets[i]: self.offsets[i] + self.s * n1 * n2].view(self.s, n2, n1)
 
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.precision == "f32" else torch.float64
+
     def step(self, u, nsteps=1, use_graph=True, stream=None):
         import torch
-        if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous() or u.numel() != self.offsets[-1]:
-            raise ValueError("expected the packed contiguous float64 device state")
+        if u.dtype != self.dtype or not u.is_cuda or not u.is_contiguous() or u.numel() != self.offsets[-1]:
+            raise ValueError(f"expected the packed contiguous {self.dtype} device state")
         st = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib.etd_rdp_batch_step(self._ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(self._ws_ptr()),
-                                      self.ws_bytes, int(nsteps), 1 if use_graph else 0,
-                                      ctypes.c_void_p(st.cuda_stream)), "etd_rdp_batch_step")
+        name = "etd_rdp_batch_step_f32" if self.precision == "f32" else "etd_rdp_batch_step"
+        _check(getattr(lib, name)(self._ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(self._ws_ptr()),
+                                  self.ws_bytes, int(nsteps), 1 if use_graph else 0,
+                                  ctypes.c_void_p(st.cuda_stream)), name)
         return u

@@ -337,3 +337,37 @@ def test_adjoint_validates_arguments_without_touching_the_gpu():
     assert f(q._ctx, u, lam, lo, g, ws, q.adj_ws_bytes, None) == etd.ETD_ERR_UNSUPPORTED
     n = ctypes.c_int32()
     assert etd.lib.etd_rdp_grad_size(None, ctypes.byref(n)) == etd.ETD_ERR_ARG
+
+
+def test_batch_precision_option_without_touching_the_gpu():
+    """An FP32 ensemble halves the carried arrays; each step entry point
+    refuses the other precision before any device work."""
+    etd = _lib()
+    ins = [dict(shape=(40, 24), bcs=("neumann", "periodic"), D=(0.02, 0.01), params={"a": 1.0, "b": 3.0}),
+           dict(shape=(17, 64), bcs=("periodic", "dirichlet"), D=(0.01, 0.03), params={"a": 1.2, "b": 2.8})]
+    b64 = etd.EtdRdpBatch(ins, 2, "brusselator", 0.01)
+    b32 = etd.EtdRdpBatch(ins, 2, "brusselator", 0.01, precision="f32")
+    assert b32.offsets == b64.offsets and b32.launches_per_step == b64.launches_per_step
+    # the three carried arrays (each rounded up to 256 bytes) are the only
+    # part of the workspace that depends on the element size
+    ru = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    tot = b64.offsets[-1]
+    assert b64.ws_bytes - b32.ws_bytes == 3 * (ru(8 * tot) - ru(4 * tot))
+    u, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x10000)
+    assert etd.lib.etd_rdp_batch_step(b32._ctx, u, ws, b32.ws_bytes, 1, 0, None) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_batch_step_f32(b64._ctx, u, ws, b64.ws_bytes, 1, 0, None) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_batch_step_f32(None, u, ws, b64.ws_bytes, 1, 0, None) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_batch_step_f32(b32._ctx, u, None, b32.ws_bytes, 1, 0, None) == etd.ETD_ERR_WORKSPACE
+    # zero steps is a no-op that touches nothing
+    assert etd.lib.etd_rdp_batch_step_f32(b32._ctx, u, ws, b32.ws_bytes, 0, 0, None) == etd.ETD_OK
+    with pytest.raises(ValueError):
+        etd.EtdRdpBatch(ins, 2, "brusselator", 0.01, precision="c128")
+    sch = etd.Scheme()
+    sch.precision = etd.PRECISIONS["c128"]
+    arr_t = (etd.Instance * 1)()
+    arr_t[0].n[0], arr_t[0].n[1] = 16, 16
+    arr_t[0].bc[0], arr_t[0].bc[1] = 1, 1
+    arr_t[0].D[0] = 0.01
+    ctx = ctypes.c_void_p()
+    assert etd.lib.etd_rdp_batch_init(1, arr_t, 1, etd.MODELS["linear"], 0.01, ctypes.byref(sch),
+                                      ctypes.byref(ctx)) == etd.ETD_ERR_UNSUPPORTED

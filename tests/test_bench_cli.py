@@ -43,7 +43,7 @@ def test_pass_kernel_names():
 
 
 def test_precision_option_is_refused_where_not_built():
-    for wl in ("brusselator_ensemble", "schnakenberg3d_adjoint", "cgl3d_complex"):
+    for wl in ("schnakenberg3d_adjoint", "cgl3d_complex"):
         r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", wl,
                             "--precision", "f32"], capture_output=True, text=True, timeout=120)
         assert r.returncode == 2, (wl, r.stderr)

@@ -60,3 +60,46 @@ def test_graph_replay_equals_direct_launches():
     b.step(g, 2, use_graph=True)   # replays (same u, ws, nsteps)
     torch.cuda.synchronize()
     assert torch.equal(a, g)
+
+
+EPS32 = 2.0 ** -24
+
+
+def test_f32_ensemble_matches_oracle_and_single_problem_f32_path():
+    """FP32 ensemble (etd_rdp_batch_step_f32): every instance against the
+    FP64 oracle within n steps of the single-problem FP32 bound (one step:
+    rel-L2 <= max(1e-5, 5 eps32 (1 + 4 r)), r = max k D / h^2), and against
+    the single-problem FP32 GPU path on that instance."""
+    import torch
+    from paper_2001_11220_amd.etd import EtdRdp, EtdRdpBatch
+    ens = small_ensemble()
+    nsteps = 3
+    b = EtdRdpBatch(ens.instances, ens.s, ens.model, ens.k, precision="f32")
+    u = b.pack(ens.states)
+    assert u.dtype == torch.float32
+    b.step(u, nsteps)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, ins in enumerate(ens.instances):
+        got = b.view(u, i).cpu().numpy().astype(np.float64)
+        hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
+        ref = O.etd_rdp_if_run(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"], nsteps)
+        r = max(ens.k * dv / (hv * hv) for dv in ins["D"] for hv in hs)
+        tol = nsteps * max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        worst = max(worst, err)
+        assert err <= tol, (i, ins["shape"], err, tol)
+        e = EtdRdp(ins["shape"], ins["bcs"], ins["D"], ens.k, ens.model, ins["params"], precision="f32")
+        us = torch.from_numpy(ens.states[i].astype(np.float32)).cuda()
+        e.step(us, nsteps)
+        torch.cuda.synchronize()
+        single = us.cpu().numpy().astype(np.float64)
+        assert np.abs(got - single).max() <= 1e-5 * np.abs(single).max(), i
+    print(f"[f32 ensemble] {b.n} instances, worst rel_l2={worst:.2e}", flush=True)
+    # graph replay equals direct launches in FP32 too
+    u0 = b.pack(ens.states)
+    a, g = u0.clone(), u0.clone()
+    b.step(a, 2, use_graph=False)
+    b.step(g, 2, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, g)
