@@ -103,3 +103,28 @@ def test_f32_ensemble_matches_oracle_and_single_problem_f32_path():
     b.step(g, 2, use_graph=True)
     torch.cuda.synchronize()
     assert torch.equal(a, g)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_etd1_ensemble_matches_oracle(prec):
+    """The ensemble's first-order scheme (the ETD1 predictor alone, P_2 P_1
+    (U + k F(U))): one step of every instance against the oracle's ETD1
+    step (FP64: 1e-12; FP32: the one-step bound above)."""
+    import torch
+    from paper_2001_11220_amd.etd import EtdRdpBatch
+    ens = small_ensemble()
+    b = EtdRdpBatch(ens.instances, ens.s, ens.model, ens.k, scheme="etd1", precision=prec)
+    u = b.pack(ens.states)
+    b.step(u, 1)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, ins in enumerate(ens.instances):
+        got = b.view(u, i).cpu().numpy().astype(np.float64)
+        hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
+        ref = O.etd1_if_step(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"])
+        r = max(ens.k * dv / (hv * hv) for dv in ins["D"] for hv in hs)
+        tol = 1e-12 if prec == "f64" else max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        worst = max(worst, err)
+        assert err <= tol, (i, ins["shape"], err, tol)
+    print(f"[etd1 ensemble {prec}] {b.n} instances, worst rel_l2={worst:.2e}", flush=True)
