@@ -128,3 +128,37 @@ def test_etd1_ensemble_matches_oracle(prec):
         worst = max(worst, err)
         assert err <= tol, (i, ins["shape"], err, tol)
     print(f"[etd1 ensemble {prec}] {b.n} instances, worst rel_l2={worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_ensemble_one_step_sampled(prec):
+    """The benchmark's ensemble (1024 instances, N = 64..512, recorded into a
+    HIP graph as bench.py runs it): one step, then the first instance of
+    every chunk-length group, the largest instance and the last one against
+    the oracle (FP64: 1e-12; FP32: the one-step bound above)."""
+    import torch
+    from paper_2001_11220_amd.etd import EtdRdpBatch
+    ens = W.brusselator_ensemble()
+    b = EtdRdpBatch(ens.instances, ens.s, ens.model, ens.k, precision=prec)
+    u = b.pack(ens.states)
+    b.step(u, 1, use_graph=True)
+    torch.cuda.synchronize()
+    first_of = {}
+    for i, ins in enumerate(ens.instances):
+        n = ins["shape"][0]
+        first_of.setdefault(next(m for m in range(1, 9) if n % m == 0 and n // m <= 64), i)
+    largest = max(range(b.n), key=lambda i: ens.instances[i]["shape"][0])
+    sample = sorted(set(first_of.values()) | {largest, b.n - 1})
+    assert len(first_of) == 8 and b.launches_per_step == 16
+    worst = 0.0
+    for i in sample:
+        ins = ens.instances[i]
+        got = b.view(u, i).cpu().numpy().astype(np.float64)
+        hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
+        ref = O.etd_rdp_if_step(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"])
+        r = max(ens.k * dv / (hv * hv) for dv in ins["D"] for hv in hs)
+        tol = 1e-12 if prec == "f64" else max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        worst = max(worst, err)
+        assert err <= tol, (i, ins["shape"], err, tol)
+    print(f"[full ensemble {prec}] {len(sample)} sampled instances, worst rel_l2={worst:.2e}", flush=True)
