@@ -122,11 +122,22 @@ __global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
   }
 }
 
+// Lines per tile of pass 2: as in the single-problem kernels, except that
+// FP32 chunks of 5-8 rows take 16-line tiles at four waves per SIMD (their
+// registers fit 128 VGPRs, where FP64 ones need 2 waves).  last_lines is
+// the host side of the same rule.
+template <int M, typename T>
+constexpr int kLastLines = (std::is_same<T, float>::value && M >= 5) ? 16 : kLinesFor<M>;
+
+inline int last_lines(int m, int precision) {
+  return (precision == ETD_PRECISION_F32 && m >= 5) ? 16 : lines_for(m);
+}
+
 // Pass 2 of the ensemble (axis 2).  A tile is L y-lines of one instance with
 // adjacent x, read line by line from the carried triple; u is written
 // through the LDS transpose.
 template <int M, int S, int L, typename T>
-__global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_last(
+__global__ __launch_bounds__(64 * L, (L >= 16 ? 4 : 2)) void kb_last(
     T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
     const T* __restrict__ w, const BatchInst* __restrict__ insts,
     const int* __restrict__ tile_inst, const int* __restrict__ tile_loc, int64_t ntiles,
@@ -277,7 +288,7 @@ void build_groups(etd_rdp_batch* b, int axis, std::vector<Group>& out) {
     const int m = choose_chunk(n);
     Group& g = by_m[m];
     g.m = m;
-    g.lines = lines_for(m);
+    g.lines = axis == 1 ? last_lines(m, b->precision) : lines_for(m);
     g.inst.push_back(i);
     g.max_n = std::max<int>(g.max_n, static_cast<int>(n));
     const int64_t nt = (lines + g.lines - 1) / g.lines;
@@ -383,7 +394,8 @@ hipError_t launch_b1(const etd_rdp_batch* b, const Group& g, const T* u, char* w
 
 template <int M, int S, typename T>
 hipError_t launch_b2(const etd_rdp_batch* b, const Group& g, T* u, char* ws, hipStream_t st) {
-  constexpr int L = kLinesFor<M>;
+  constexpr int L = kLastLines<M, T>;
+  if (g.lines != L) return hipErrorInvalidValue;  // the tile map assumes L lines per tile
   hipError_t e = set_lds(kb_last<M, S, L, T>, g.lds);
   if (e != hipSuccess) return e;
   unsigned grid;
