@@ -12,8 +12,9 @@ citations of each function.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against values the paper or the mathematics fix (closed forms, eigenvector
-expansions, dense Kronecker brute force, Heun reduction, invariants, observed
-convergence order).  No function is "parity unpinned".
+expansions, dense Kronecker brute force, reaction values worked out by hand,
+Heun reduction, invariants, observed convergence order against the printed
+orders, central differences for the reverse mode).
 """
 
 from .etd_rdp_oracle import (  # noqa: F401
@@ -31,7 +32,6 @@ from .etd_rdp_oracle import (  # noqa: F401
     step_intermediates,
     etd1_if_step,
     r_rdp,
-    r_pade01,
     adjoint_step,
     param_names,
     reaction_jacobian,

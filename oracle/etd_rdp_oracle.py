@@ -146,12 +146,6 @@ def r_rdp(z):
     return (1.0 - 5.0 * z / 12.0) / ((1.0 + z / 3.0) * (1.0 + z / 4.0))
 
 
-def r_pade01(z):
-    """``R_01(z) = 1/(1 + z)`` (eq. pade01)."""
-    z = _coefs(z)
-    return 1.0 / (1.0 + z)
-
-
 # ---------------------------------------------------------------------------
 # Reactions F(u) (Section 8 workloads and the benchmark systems)
 # ---------------------------------------------------------------------------

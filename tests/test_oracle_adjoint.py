@@ -13,6 +13,9 @@ CASES = [
     ("brusselator", {"a": 1.0, "b": 3.4}, ("neumann", "periodic"), (0.05, 0.02), 0.05),
     ("cgl", {"beta": 1.3}, ("dirichlet", "neumann", "periodic"), (0.3, 0.3), 0.05),
     ("linear", {"C": [[-0.3, 0.2], [0.1, -0.5]]}, ("neumann", "dirichlet"), (0.2, 0.05), 0.1),
+    # Section 8.1's model, one species: its Jacobian -1/(1+u)^2 enters the
+    # state gradient and the D gradient; it has no reaction parameters
+    ("enzyme", {}, ("dirichlet", "neumann", "periodic"), (0.2,), 0.05),
 ]
 
 
@@ -21,6 +24,8 @@ def _setup(model, bcs, seed=0):
     shape = (2, 4, 5, 3)[: len(bcs) + 1] if len(bcs) == 3 else (2, 5, 4)
     base = {"schnakenberg": (1.0, 0.9)}.get(model, (0.6, 0.4))
     U = np.stack([base[0] + 0.2 * rng.random(shape[1:]), base[1] + 0.2 * rng.random(shape[1:])])
+    if model == "enzyme":
+        U = U[:1]
     tgt = U + 0.1 * rng.standard_normal(U.shape)
     ns = U.shape[1:][::-1]
     hs = [O.default_h(n, b) for n, b in zip(ns, bcs)]

@@ -98,10 +98,32 @@ def _one_d_mode_step(bc, n, j, z, nsteps=1, F=None):
 def test_F0_single_mode_is_rdp_closed_form(bc):
     num = GOLD["rdp_numerator_coef"]["value"]
     p1, p2 = GOLD["rdp_poles"]["value"]
+    w1, w2 = GOLD["partial_fractions"]["value"]["R"]
     for z in (1e-3, 0.2, 1.0, 7.5, 300.0):
         got, v = _one_d_mode_step(bc, 12, 2, z)
         r = (1.0 - num * z) / ((1.0 + z / p1) * (1.0 + z / p2))
         np.testing.assert_allclose(got, r * v, rtol=1e-12, atol=1e-14)
+        # the same number through the printed partial fractions 9T - 8S
+        np.testing.assert_allclose(got, (w1 / (1.0 + z / p1) + w2 / (1.0 + z / p2)) * v,
+                                   rtol=1e-12, atol=1e-14)
+
+
+def test_partial_fraction_identities():
+    """The three decompositions of Section 6, with the printed weights, hold as
+    rational functions of z (T = 1/(1 + z/3), S = 1/(1 + z/4)):
+    R_RDP = 9T - 8S, ST = 4T - 3S, (1 + z/6) ST = 2T - S."""
+    pf = GOLD["partial_fractions"]["value"]
+    p1, p2 = GOLD["rdp_poles"]["value"]
+    num = GOLD["rdp_numerator_coef"]["value"]
+    z = np.concatenate([np.linspace(0.0, 20.0, 401), np.logspace(1, 6, 50)])
+    T, S = 1.0 / (1.0 + z / p1), 1.0 / (1.0 + z / p2)
+    np.testing.assert_allclose(pf["R"][0] * T + pf["R"][1] * S, (1.0 - num * z) * S * T,
+                               rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(pf["ST"][0] * T + pf["ST"][1] * S, S * T, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(pf["I_plus_k6A_ST"][0] * T + pf["I_plus_k6A_ST"][1] * S,
+                               (1.0 + z / 6.0) * S * T, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(O.r_rdp(z), pf["R"][0] * T + pf["R"][1] * S, rtol=1e-12,
+                               atol=1e-15)
 
 
 def test_rdp_l_stability_and_order():
@@ -125,17 +147,80 @@ def test_rdp_l_stability_and_order():
 
 
 def test_predictor_is_pade01():
+    # Pade-(0,1) of eq. pade01: 1/(1 + z/pole) with the printed pole 1
+    pole = GOLD["pade01_pole"]["value"]
     for bc in BCS:
         v, lam, h = _mode(10, bc, 1)
-        k, z = 0.1, 2.5
-        U = v[None, :]
-        got = O.etd1_if_step(U, k, [z / (k * lam)], [bc], [h], "linear", {"C": [[0.0]]})[0]
-        np.testing.assert_allclose(got, v / (1.0 + z), rtol=1e-12, atol=1e-14)
+        k = 0.1
+        for z in (0.05, 2.5, 40.0):
+            U = v[None, :]
+            got = O.etd1_if_step(U, k, [z / (k * lam)], [bc], [h], "linear", {"C": [[0.0]]})[0]
+            np.testing.assert_allclose(got, v / (1.0 + z / pole), rtol=1e-12, atol=1e-14)
 
 
 # ---------------------------------------------------------------------------
 # Whole step: dense Kronecker brute force (Example 2, eq. donedone)
 # ---------------------------------------------------------------------------
+
+def _dense_ops(U, D, bcs, hs):
+    """Dense A_1..A_d of eq. Ai for a state shaped like U, and the maps
+    between a state and the paper's vector (species index innermost, then
+    spatial axis 1, ..., axis d outermost; A_i = I x .. x B_p (position
+    d-i+1) x .. x I x D)."""
+    s = U.shape[0]
+    d = U.ndim - 1
+    ns = [U.shape[d - i + 1] for i in range(1, d + 1)]  # n_1..n_d
+    Dm = np.diag(D)
+    A = []
+    for i in range(1, d + 1):
+        mats = []
+        for pos in range(1, d + 1):  # Kronecker position 1 = outermost = axis d
+            ax = d - pos + 1
+            mats.append(O.laplacian_matrix(ns[ax - 1], bcs[ax - 1], hs[ax - 1]) if ax == i
+                        else np.eye(ns[ax - 1]))
+        K = mats[0]
+        for M in mats[1:]:
+            K = np.kron(K, M)
+        A.append(np.kron(K, Dm))
+    vec = lambda X: np.moveaxis(X, 0, -1).reshape(-1)
+    unvec = lambda x: np.moveaxis(x.reshape(U.shape[1:] + (s,)), -1, 0)
+    return A, vec, unvec
+
+
+def test_step_intermediates_match_dense_operators():
+    """Each intermediate the GPU passes are compared with is what its name
+    says: y_i = (I + k A_i)^{-1} y_{i-1}, cU_i = (9 (I + k/3 A_i)^{-1}
+    - 8 (I + k/4 A_i)^{-1}) cU_{i-1} (and cf_i likewise), f* = F(U*),
+    f1 = 9 cU + 2k cf + k f*, f2 = 8 cU + 3k/2 cf + k/2 f*."""
+    rng = np.random.default_rng(11)
+    U = 0.5 + 0.3 * rng.random((2, 4, 3, 5))  # n_1 = 5, n_2 = 3, n_3 = 4
+    bcs = (O.BC_PERIODIC, O.BC_NEUMANN, O.BC_DIRICHLET)
+    hs = [O.default_h(n, b) for n, b in zip((5, 3, 4), bcs)]
+    D, k = np.array([0.03, 0.011]), 0.07
+    p = {"F": 0.04, "kappa": 0.06}
+    out = O.step_intermediates(U, k, D, bcs, hs, "gray_scott", p)
+    A, vec, unvec = _dense_ops(U, D, bcs, hs)
+    I = np.eye(A[0].shape[0])
+    sol = lambda g, i, x: unvec(np.linalg.solve(I + k / g * A[i - 1], vec(x)))
+    tol = dict(rtol=1e-12, atol=1e-14)
+    f = O.reaction("gray_scott", p, U)
+    np.testing.assert_allclose(out["w"], U + k * f, **tol)
+    y = U + k * f
+    for i in (1, 2, 3):
+        y = sol(1.0, i, y)
+        np.testing.assert_allclose(out[f"y{i}"], y, **tol)
+    np.testing.assert_allclose(out["Ustar"], y, **tol)
+    cU, cf = U, f
+    for i in (1, 2):
+        cU = 9 * sol(3.0, i, cU) - 8 * sol(4.0, i, cU)
+        cf = 9 * sol(3.0, i, cf) - 8 * sol(4.0, i, cf)
+        np.testing.assert_allclose(out[f"cU{i}"], cU, **tol)
+        np.testing.assert_allclose(out[f"cf{i}"], cf, **tol)
+    fs = O.reaction("gray_scott", p, y)
+    np.testing.assert_allclose(out["fstar"], fs, **tol)
+    np.testing.assert_allclose(out["f1"], 9 * cU + 2 * k * cf + k * fs, **tol)
+    np.testing.assert_allclose(out["f2"], 8 * cU + 1.5 * k * cf + 0.5 * k * fs, **tol)
+
 
 def _dense_step(U, k, D, bcs, hs, model, params):
     """The frame of Section 6 with explicit dense matrices.
@@ -390,6 +475,29 @@ def test_brusselator_2d_observed_order_two():
     lo = min(GOLD["brusselator_eoc_etd_rdp_if"]["value"]) - 0.15
     hi = max(GOLD["brusselator_eoc_etd_rdp_if"]["value"]) + 0.05
     assert np.all(eoc > lo) and np.all(eoc < hi), eoc
+
+
+def test_enzyme_2d_observed_order_two():
+    """Section 8.1 (Table enztable): enzyme kinetics on the unit square,
+    homogeneous Dirichlet, D = 0.2, h = 0.0125 (79 interior points), initial
+    value one, T = 1, k = 0.05 ... 0.00625.  The error against a fine-k run of
+    the same space discretisation decays at the printed order (the printed
+    errors themselves depend on a reference solution the paper does not
+    state)."""
+    n = 79
+    h = 1.0 / (n + 1)
+    assert abs(h - 0.0125) < 1e-15
+    U0 = np.ones((1, n, n))
+    args = ([0.2], [O.BC_DIRICHLET] * 2, [h, h], "enzyme", {})
+    ref = O.etd_rdp_if_run(U0, 1.0 / 1280, *args, 1280)
+    errs = [np.abs(O.etd_rdp_if_run(U0, 1.0 / nst, *args, nst) - ref).max()
+            for nst in (20, 40, 80, 160)]
+    eoc = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    lo = min(GOLD["enzyme_eoc_etd_rdp_if"]["value"]) - 0.15
+    hi = max(GOLD["enzyme_eoc_etd_rdp_if"]["value"]) + 0.05
+    assert np.all(eoc > lo) and np.all(eoc < hi), eoc
+    # the solution decays (f = -u/(1+u) < 0 for u > 0) and stays positive
+    assert 0.0 < ref.min() and ref.max() < 1.0
 
 
 def test_brusselator_3d_approaches_printed_limit():
