@@ -205,7 +205,10 @@ int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass,
  *  u        : device, s*N doubles, caller-owned, read and overwritten.
  *  ws       : device workspace of at least etd_rdp_workspace_bytes bytes,
  *             256-byte aligned; its first use (or a change of ws) uploads
- *             the tables with an asynchronous copy on `stream`.
+ *             the tables with an asynchronous copy on `stream`.  Calls that
+ *             pass the address of the last workspace reuse the tables it
+ *             holds: after freeing or overwriting that buffer, call
+ *             etd_rdp_forget_workspace first.
  *  nsteps   : >= 0; 0 is a no-op.
  *  stream   : hipStream_t (NULL = null stream).  The call only enqueues work;
  *             it does not synchronise.
@@ -292,6 +295,19 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes,
                         int32_t axis, int32_t sigma, int32_t gamma,
                         void* stream);
+
+/*
+ * etd_rdp_forget_workspace -- the workspace this context last used may no
+ * longer hold its tables (it was freed and reallocated, possibly at the same
+ * address, or written by something else).  A context uploads its tables
+ * into a workspace on first use and skips the upload while later calls pass
+ * the same address; it cannot tell a new buffer at an old address from the
+ * old one, so the caller must call this whenever that can happen.  The next
+ * call that takes a workspace uploads the tables again; a reaction field
+ * must be stored again with etd_rdp_set_field.
+ * Errors: ETD_ERR_ARG (NULL).
+ */
+int etd_rdp_forget_workspace(etd_rdp_ctx* ctx);
 
 /* Human-readable text of a status code (static storage). */
 const char* etd_rdp_status_string(int status);
@@ -425,8 +441,32 @@ int etd_rdp_batch_step_f32(etd_rdp_batch* b, float* u_packed, void* ws,
                            size_t ws_bytes, int64_t nsteps, int32_t use_graph,
                            void* stream);
 
+/* etd_rdp_forget_workspace for an ensemble: the next step uploads the
+ * tables, instance descriptors and tile maps again and records a new graph.
+ * Errors: ETD_ERR_ARG (NULL). */
+int etd_rdp_batch_forget_workspace(etd_rdp_batch* b);
+
 /* Number of kernel launches of one step (for tests and reports). */
 int etd_rdp_batch_launches_per_step(const etd_rdp_batch* b, int32_t* n);
+
+/* ======================================================================
+ * Bandwidth calibration (for reports; not part of the scheme).
+ * ====================================================================== */
+
+/*
+ * etd_calib_stream -- one streaming sweep over `bytes` bytes of device
+ * memory on `stream`, with `blocks` workgroups of 256 threads:
+ *   kind 0: copy src -> dst (reads and writes `bytes`),
+ *   kind 1: read src (dst: device, at least 8 bytes; written only if the
+ *           sum of src is -1e308, which finite data never reaches),
+ *   kind 2: write dst (src unused, may be NULL).
+ * Timing these against the passes gives the rate simple streaming code
+ * reaches on this device.  bytes must be a multiple of 16 and the pointers
+ * 16-byte aligned; the buffers are the caller's.
+ * Errors: ETD_ERR_ARG (bad kind, size, alignment or NULL), ETD_ERR_HIP.
+ */
+int etd_calib_stream(int32_t kind, const void* src, void* dst, size_t bytes,
+                     int32_t blocks, void* stream);
 
 #ifdef __cplusplus
 }

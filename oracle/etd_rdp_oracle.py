@@ -425,13 +425,18 @@ def laplacian_axis(U, axis, bc, h):
     return out
 
 
-def adjoint_step(U, lam, k, D, bcs, hs, model, params):
+def adjoint_step(U, lam, k, D, bcs, hs, model, params, term_scale=None):
     """Vector-Jacobian product of one ETD-RDP-IF step.
 
     Given U_n and lam = dL/dU_{n+1}, returns (dL/dU_n, dL/dD, dL/dtheta) for
     this step, where theta are the reaction parameters (``param_names``).
     A solve x = M^{-1} y with M = I + (k/gamma) D_sigma B_p contributes
     -(k/gamma) <M^{-T} xbar, B_p x>_sigma to dL/dD_sigma.
+
+    ``term_scale``: optional dict that receives, under "D" and "theta", the
+    sum of the absolute values of every per-cell term added into each
+    gradient entry (the size of the terms before they cancel; a diagnostic
+    for judging how many digits of an entry rounding leaves).
     """
     U = np.asarray(U, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
@@ -440,15 +445,19 @@ def adjoint_step(U, lam, k, D, bcs, hs, model, params):
     s = U.shape[0]
     gD = np.zeros(s)
     gth = np.zeros(len(param_names(model, s)))
+    sD = np.zeros(s)
+    sth = np.zeros(len(gth))
 
     def dgrad(ybar, x, axis, gamma):
         Lx = laplacian_axis(x, axis, bcs[axis - 1], hs[axis - 1])
         for sg in range(s):
             gD[sg] += -(k / gamma) * float(np.sum(ybar[sg] * Lx[sg]))
+            sD[sg] += (k / gamma) * float(np.sum(np.abs(ybar[sg] * Lx[sg])))
 
     def pgrad(Uat, fbar):
         for i, dF in enumerate(reaction_param_grads(model, params, Uat)):
             gth[i] += float(np.sum(dF * fbar))
+            sth[i] += float(np.sum(np.abs(dF * fbar)))
 
     # forward recomputation
     f = reaction(model, params, U)
@@ -492,4 +501,7 @@ def adjoint_step(U, lam, k, D, bcs, hs, model, params):
     fbar = cfbar + k * nu
     pgrad(U, fbar)
     lam_n = cUbar + nu + _jac_T(reaction_jacobian(model, params, U), fbar)
+    if term_scale is not None:
+        term_scale["D"] = sD
+        term_scale["theta"] = sth
     return lam_n, gD, gth

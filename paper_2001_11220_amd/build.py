@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libetdrdp.so")
 
-SOURCES = ["etd_rdp.hip", "etd_adjoint.hip", "etd_batch.hip", "etd_tables.cpp"]
+SOURCES = ["etd_rdp.hip", "etd_adjoint.hip", "etd_batch.hip", "etd_tables.cpp", "etd_calib.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

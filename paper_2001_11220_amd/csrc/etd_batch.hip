@@ -545,6 +545,13 @@ int etd_rdp_batch_workspace_bytes(const etd_rdp_batch* b, size_t* bytes) {
   return ETD_OK;
 }
 
+int etd_rdp_batch_forget_workspace(etd_rdp_batch* b) {
+  if (!b) return ETD_ERR_ARG;
+  b->uploaded_ws = nullptr;
+  drop_graph(b);
+  return ETD_OK;
+}
+
 int etd_rdp_batch_launches_per_step(const etd_rdp_batch* b, int32_t* n) {
   if (!b || !n) return ETD_ERR_ARG;
   *n = static_cast<int32_t>(b->g1.size() + b->g2.size());

@@ -1495,6 +1495,13 @@ int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, 
 
 int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
 
+int etd_rdp_forget_workspace(etd_rdp_ctx* ctx) {
+  if (!ctx) return ETD_ERR_ARG;
+  ctx->uploaded_ws = nullptr;
+  ctx->field_ws = nullptr;
+  return ETD_OK;
+}
+
 int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t size) {
   if (!ctx || !name || size == 0 || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
   const int p = pass - 1, m = ctx->m[p], P = ctx->P[p];

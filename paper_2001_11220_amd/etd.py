@@ -99,6 +99,9 @@ def _load():
         "etd_rdp_batch_step": (ctypes.c_int, [P, P, P, SZ, I64, I32, P]),
         "etd_rdp_batch_step_f32": (ctypes.c_int, [P, P, P, SZ, I64, I32, P]),
         "etd_rdp_batch_launches_per_step": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
+        "etd_calib_stream": (ctypes.c_int, [I32, P, P, SZ, I32, P]),
+        "etd_rdp_forget_workspace": (ctypes.c_int, [P]),
+        "etd_rdp_batch_forget_workspace": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -117,6 +120,18 @@ def status_string(status: int) -> str:
 def _check(status: int, what: str):
     if status != ETD_OK:
         raise EtdError(status, what)
+
+
+def calib_stream(kind: str, src, dst, nbytes: int, blocks: int, stream=None):
+    """One bandwidth-calibration sweep (etd_calib_stream) over torch device
+    tensors: kind "copy" (src -> dst), "read" (src; dst a small sink) or
+    "write" (dst)."""
+    import torch
+    k = {"copy": 0, "read": 1, "write": 2}[kind]
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.etd_calib_stream(k, None if src is None else src.data_ptr(), dst.data_ptr(),
+                                int(nbytes), int(blocks), ctypes.c_void_p(st.cuda_stream)),
+           "etd_calib_stream")
 
 
 def reaction_struct(model: str, params: dict, shift: Optional[Sequence[float]] = None,
@@ -225,12 +240,20 @@ class EtdRdp:
             self._ws = None
             self._ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
             self._ws_cap = need
+            # a new buffer, possibly at the old address: upload the tables again
+            _check(lib.etd_rdp_forget_workspace(self._ctx), "etd_rdp_forget_workspace")
         return self._ws
 
     def _ws_ptr(self):
         ws = self.workspace()
         p = ws.data_ptr()
         return p + (-p) % 256
+
+    def forget_workspace(self):
+        """The workspace's contents were changed outside the library: the
+        next call uploads the tables again (a reaction field must be set
+        again)."""
+        _check(lib.etd_rdp_forget_workspace(self._ctx), "etd_rdp_forget_workspace")
 
     def layout(self, npass=1):
         """(offsets of c1, c2, w in bytes, element strides of axes 1..d) of
@@ -418,12 +441,18 @@ class EtdRdpBatch:
         if self._ws is None:
             dev = self._device if self._device is not None else torch.device("cuda", torch.cuda.current_device())
             self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+            _check(lib.etd_rdp_batch_forget_workspace(self._ctx), "etd_rdp_batch_forget_workspace")
         return self._ws
 
     def _ws_ptr(self):
         ws = self.workspace()
         p = ws.data_ptr()
         return p + (-p) % 256
+
+    def forget_workspace(self):
+        """The workspace's contents were changed outside the library: the
+        next step uploads the tables again and records a new graph."""
+        _check(lib.etd_rdp_batch_forget_workspace(self._ctx), "etd_rdp_batch_forget_workspace")
 
     def pack(self, states):
         """Pack per-instance numpy/torch states (s, n_2, n_1) into one

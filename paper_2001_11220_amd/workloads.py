@@ -17,7 +17,8 @@ benchmark configurations of the build):
   n=512^3, homogeneous Dirichlet on w = u - u* with u* = (a+b, b/(a+b)^2)
   (h = 1/513), k = 1e-4, 200 steps, w = 1e-3 N(0,1).
 * ``schnakenberg3d_adjoint``  128^3 Neumann (h = 1/127), k = 1e-3, 400 steps,
-  u = u* + 1e-3 N(0,1) (unshifted).
+  u = u* + 1e-3 N(0,1) (unshifted); the loss's target is the same run with
+  (Du, Dv, a, b) perturbed by up to 5 % (``gradient_target``).
 """
 
 from __future__ import annotations
@@ -184,6 +185,19 @@ def schnakenberg3d_adjoint(n: int = 128, nsteps: int = 400, seed: int = 0) -> Pr
     return Problem("schnakenberg3d_adjoint", (n, n, n), ("neumann",) * 3, (1.0, 10.0), 1e-3,
                    "schnakenberg", dict(SCHNAK), nsteps, seed=seed, ic="gaussian_noise",
                    ic_args={"amp": 1e-3, "offset": SCHNAK_STEADY})
+
+
+def gradient_target(prob: Problem):
+    """Parameters of the target run of the gradient workload: theta =
+    (Du, Dv, a, b) each multiplied by 1 + 0.05 U[-1, 1), drawn in that order
+    from default_rng(seed + 1); gamma is kept.  Returns (D_t, params_t)."""
+    rng = np.random.default_rng(prob.seed + 1)
+    f = [1.0 + 0.05 * rng.uniform(-1.0, 1.0) for _ in range(4)]
+    D_t = (prob.D[0] * f[0], prob.D[1] * f[1])
+    params_t = dict(prob.params)
+    params_t["a"] = prob.params["a"] * f[2]
+    params_t["b"] = prob.params["b"] * f[3]
+    return D_t, params_t
 
 
 CGL_ALPHA, CGL_BETA = 0.5, 1.3

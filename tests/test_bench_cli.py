@@ -48,3 +48,40 @@ def test_precision_option_is_refused_where_not_built():
                             "--precision", "f32"], capture_output=True, text=True, timeout=120)
         assert r.returncode == 2, (wl, r.stderr)
         assert r.stdout.strip() == ""
+
+
+def test_unknown_workload_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "unknown workload" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_pooled_oracle_equals_the_plain_oracle():
+    """The all-core timing of cpu_baseline spreads the oracle's own line
+    routines over worker processes; the step it computes is the same."""
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle as O
+    from paper_2001_11220_amd import workloads as W
+
+    prob = W.grayscott3d(shape=(12, 10, 8))
+    prob.bcs = ("periodic", "neumann", "dirichlet")
+    u = prob.initial()
+    lam = np.random.default_rng(2).standard_normal(u.shape)
+    ref = O.etd_rdp_if_step(u, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.params)
+    aref = O.adjoint_step(u, lam, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.params)
+    pool = bench.OraclePool(3, u.nbytes)
+    try:
+        with pool:
+            got = O.etd_rdp_if_step(u, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.params)
+            agot = O.adjoint_step(u, lam, prob.k, prob.D, prob.bcs, prob.hs(), prob.model,
+                                  prob.params)
+        assert O.etd_rdp_oracle.solve_axis is bench._POOL["orig"]["solve_axis"]
+    finally:
+        pool.close()
+    assert np.array_equal(got, ref)
+    assert np.array_equal(agot[0], aref[0])
+    assert np.allclose(agot[1], aref[1], rtol=1e-13) and np.allclose(agot[2], aref[2], rtol=1e-13)

@@ -39,10 +39,10 @@ def test_ensemble_matches_single_problem_path_and_oracle():
         torch.cuda.synchronize()
         single = u.cpu().numpy()
         assert np.abs(got[i] - single).max() <= 1e-14 * np.abs(single).max(), i
-        if i < 4:
-            hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
-            ref = O.etd_rdp_if_run(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"], 3)
-            assert np.linalg.norm(got[i] - ref) / np.linalg.norm(ref) < 1e-12, i
+        hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
+        ref = O.etd_rdp_if_run(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"], 3)
+        assert np.linalg.norm(got[i] - ref) / np.linalg.norm(ref) < 1e-12, i
+        assert np.abs(got[i] - ref).max() / np.abs(ref).max() < 1e-12, i
 
 
 def test_graph_replay_equals_direct_launches():
@@ -62,14 +62,11 @@ def test_graph_replay_equals_direct_launches():
     assert torch.equal(a, g)
 
 
-EPS32 = 2.0 ** -24
-
-
 def test_f32_ensemble_matches_oracle_and_single_problem_f32_path():
     """FP32 ensemble (etd_rdp_batch_step_f32): every instance against the
-    FP64 oracle within n steps of the single-problem FP32 bound (one step:
-    rel-L2 <= max(1e-5, 5 eps32 (1 + 4 r)), r = max k D / h^2), and against
-    the single-problem FP32 GPU path on that instance."""
+    FP64 oracle within n times the single-problem FP32 tolerance (rel-L2
+    1e-5 per step), and against the single-problem FP32 GPU path on that
+    instance."""
     import torch
     from paper_2001_11220_amd.etd import EtdRdp, EtdRdpBatch
     ens = small_ensemble()
@@ -84,8 +81,7 @@ def test_f32_ensemble_matches_oracle_and_single_problem_f32_path():
         got = b.view(u, i).cpu().numpy().astype(np.float64)
         hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
         ref = O.etd_rdp_if_run(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"], nsteps)
-        r = max(ens.k * dv / (hv * hv) for dv in ins["D"] for hv in hs)
-        tol = nsteps * max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        tol = nsteps * 1e-5
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         worst = max(worst, err)
         assert err <= tol, (i, ins["shape"], err, tol)
@@ -109,7 +105,7 @@ def test_f32_ensemble_matches_oracle_and_single_problem_f32_path():
 def test_etd1_ensemble_matches_oracle(prec):
     """The ensemble's first-order scheme (the ETD1 predictor alone, P_2 P_1
     (U + k F(U))): one step of every instance against the oracle's ETD1
-    step (FP64: 1e-12; FP32: the one-step bound above)."""
+    step (FP64: 1e-12; FP32: 1e-5)."""
     import torch
     from paper_2001_11220_amd.etd import EtdRdpBatch
     ens = small_ensemble()
@@ -122,8 +118,7 @@ def test_etd1_ensemble_matches_oracle(prec):
         got = b.view(u, i).cpu().numpy().astype(np.float64)
         hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
         ref = O.etd1_if_step(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"])
-        r = max(ens.k * dv / (hv * hv) for dv in ins["D"] for hv in hs)
-        tol = 1e-12 if prec == "f64" else max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        tol = 1e-12 if prec == "f64" else 1e-5
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         worst = max(worst, err)
         assert err <= tol, (i, ins["shape"], err, tol)
@@ -135,7 +130,7 @@ def test_full_size_ensemble_one_step_sampled(prec):
     """The benchmark's ensemble (1024 instances, N = 64..512, recorded into a
     HIP graph as bench.py runs it): one step, then the first instance of
     every chunk-length group, the largest instance and the last one against
-    the oracle (FP64: 1e-12; FP32: the one-step bound above)."""
+    the oracle (FP64: 1e-12; FP32: 1e-5)."""
     import torch
     from paper_2001_11220_amd.etd import EtdRdpBatch
     ens = W.brusselator_ensemble()
@@ -156,8 +151,7 @@ def test_full_size_ensemble_one_step_sampled(prec):
         got = b.view(u, i).cpu().numpy().astype(np.float64)
         hs = [1.0 / (n - 1) if bc == "neumann" else 1.0 / n for n, bc in zip(ins["shape"], ins["bcs"])]
         ref = O.etd_rdp_if_step(ens.states[i], ens.k, ins["D"], ins["bcs"], hs, ens.model, ins["params"])
-        r = max(ens.k * dv / (hv * hv) for dv in ins["D"] for hv in hs)
-        tol = 1e-12 if prec == "f64" else max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        tol = 1e-12 if prec == "f64" else 1e-5
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         worst = max(worst, err)
         assert err <= tol, (i, ins["shape"], err, tol)

@@ -1,12 +1,13 @@
 """GPU parity of the single-precision forward path (etd_rdp_step_f32)
 against the FP64 oracle.
 
-Tolerance: one step agrees with the oracle to rel-L2 <= max(1e-5,
-5 eps32 (1 + 4 r_max)), r_max = max k D_sigma / h_i^2: both sides are
-backward-stable line solves, the FP32 one with unit roundoff eps32 = 2^-24,
-and each solve's forward error is at most its condition number (<= 1 + 4r)
-times that.  Longer runs are checked against a bound that grows with the
-step count."""
+Tolerance: one step agrees with the oracle to rel-L2 <= 1e-5 (measured
+1.0e-6 to 2.9e-6 over every case here, up to r = k D / h^2 of ~6e4).  For
+information the tests print the condition-number bound
+5 eps32 (1 + 4 r_max), eps32 = 2^-24 (both sides are backward-stable line
+solves and a solve's forward error is at most its condition number, at most
+1 + 4r, times that); it is not what they assert.  Longer runs are checked
+against n times the one-step tolerance."""
 
 import numpy as np
 import pytest
@@ -87,9 +88,10 @@ def test_one_step_f32_matches_oracle(prob, lpw):
     u0 = prob.initial()
     got = run_f32(prob, u0, 1, lpw)
     ref = O.etd_rdp_if_run(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params(), 1)
-    tol = max(1e-5, 5 * EPS32 * (1 + 4 * r_max(prob)))
+    tol = 1e-5
     err = rel_l2(got, ref)
-    print(f"[f32 one step] {prob.model} {prob.shape} rel_l2={err:.2e} tol={tol:.2e}", flush=True)
+    print(f"[f32 one step] {prob.model} {prob.shape} rel_l2={err:.2e} tol={tol:.2e} "
+          f"(condition bound {5 * EPS32 * (1 + 4 * r_max(prob)):.1e})", flush=True)
     assert err <= tol, (err, tol)
 
 
@@ -110,8 +112,9 @@ def test_f32_100_steps_error_curve():
         errs.append(rel_l2(u.cpu().numpy().astype(np.float64), ref))
     e.close()
     print("[f32 error curve] every 10 steps:", " ".join(f"{v:.1e}" for v in errs), flush=True)
-    # rounding errors accumulate at most linearly in the step count here
-    assert errs[-1] <= 100 * 1e-5, errs
+    # rounding errors accumulate at most linearly in the step count: n steps
+    # within n times the one-step tolerance (measured 5.9e-6 after 100)
+    assert all(e <= 10 * (i + 1) * 1e-5 for i, e in enumerate(errs)), errs
 
 
 def test_f32_matches_f64_gpu_at_full_size():
@@ -174,6 +177,7 @@ def test_f32_matches_f64_gpu_at_512():
     e64.close()
     e32.close()
     r = max(prob.k * d / h ** 2 for d in prob.D for h in prob.hs())
-    tol = max(1e-5, 5 * EPS32 * (1 + 4 * r))
-    print(f"[f32 vs f64 GPU, 512^3] rel_l2={err:.2e} tol={tol:.2e}", flush=True)
+    tol = 1e-5
+    print(f"[f32 vs f64 GPU, 512^3] rel_l2={err:.2e} tol={tol:.2e} "
+          f"(condition bound {5 * EPS32 * (1 + 4 * r):.1e})", flush=True)
     assert err <= tol, (err, tol)

@@ -1,7 +1,7 @@
 """Seeded random configurations (dimension 1-4, line lengths with ragged
 tiles, boundary conditions, models, FP64 / FP32 / complex, one or two lines
 per wavefront, both schemes), each one step on the GPU against the oracle.
-Tolerances: 1e-12 (FP64, complex), max(1e-5, 5 eps32 (1 + 4 r_max)) (FP32)."""
+Tolerances: 1e-12 (FP64, complex), 1e-5 per step (FP32)."""
 
 import numpy as np
 import pytest
@@ -21,7 +21,6 @@ REAL_MODELS = [("brusselator", {"a": 1.0, "b": 3.4}, (0.02, 0.011)),
                ("cgl", {"beta": 1.3}, (0.05, 0.05)),
                ("linear", {"C": [[-0.3, 0.2], [0.1, -0.5]]}, (0.3, 0.1))]
 MIN_N = {"dirichlet": 1, "neumann": 2, "periodic": 3}
-EPS32 = 2.0 ** -24
 
 
 def _config(seed):
@@ -73,8 +72,7 @@ def test_random_configuration_matches_oracle(seed):
     ref = step(u0, prob.k, prob.D, prob.bcs, prob.hs(), prob.model, prob.oracle_params())
     err = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
     if prec == "f32":
-        r = max(prob.k * abs(dv) / h ** 2 for dv in prob.D for h in prob.hs())
-        tol = max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        tol = 1e-5
     else:
         tol = 1e-12
     print(f"[random {seed}] {prob.shape} {prob.bcs} {prob.model} {prec} lpw={lpw} {scheme} "
@@ -92,7 +90,7 @@ def test_random_configuration_matches_oracle(seed):
 def test_random_ensemble_matches_oracle(seed, model, params_of, s, prec):
     """A batch of uneven, non-square instances with every boundary condition
     (and per-instance h) in one graph; every instance against the oracle
-    (FP32: two steps of the single-problem FP32 bound)."""
+    (FP32: two steps of the single-problem FP32 tolerance, 1e-5 per step)."""
     import torch
     from paper_2001_11220_amd.etd import EtdRdpBatch
     rng = np.random.default_rng(2000 + seed)
@@ -117,8 +115,7 @@ def test_random_ensemble_matches_oracle(seed, model, params_of, s, prec):
         ref = O.etd_rdp_if_run(states[i], k, ins["D"], ins["bcs"], hs, model, ins["params"], 2)
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         worst = max(worst, err)
-        r = max(k * dv / (hv * hv) for dv in ins["D"] for hv in hs)
-        tol = 1e-12 if prec == "f64" else 2 * max(1e-5, 5 * EPS32 * (1 + 4 * r))
+        tol = 1e-12 if prec == "f64" else 2 * 1e-5
         assert err <= tol, (i, ins["shape"], ins["bcs"], err, tol)
     b.close()
     print(f"[random ensemble {model} {prec}] 12 instances, worst rel_l2={worst:.2e}", flush=True)
@@ -158,10 +155,14 @@ def test_random_reverse_step_matches_oracle(seed):
     lo, g = lo.cpu().numpy(), g.cpu().numpy()
     e.close()
     hs = [O.default_h(n, b) for n, b in zip(shape, bcs)]
-    lo_o, gD, gth = O.adjoint_step(U, lam, k, D, bcs, hs, model, dict(params))
+    ts = {}
+    lo_o, gD, gth = O.adjoint_step(U, lam, k, D, bcs, hs, model, dict(params), term_scale=ts)
     go = np.concatenate([gD, gth])
+    terms = np.concatenate([ts["D"], ts["theta"]])
     err = float(np.linalg.norm(lo - lo_o) / np.linalg.norm(lo_o))
-    print(f"[random reverse {seed}] {shape} {bcs} {model} k={k:.1e} rel_l2={err:.2e}", flush=True)
+    print(f"[random reverse {seed}] {shape} {bcs} {model} k={k:.1e} rel_l2={err:.2e} gradient error / "
+          f"(eps sum|terms|) {np.array2string(np.abs(g - go) / (2.0**-52 * terms), precision=2)}", flush=True)
     assert err <= 1e-11, err
-    tol = 1e-9 * np.abs(go) + 1e-11 * float(np.max(np.abs(go)))
-    assert np.all(np.abs(g - go) <= tol), (g, go)
+    # the reverse-mode tests' per-entry bound (see tests/test_gpu_adjoint.py)
+    tol = 1e-10 * np.abs(go) + 1e4 * 2.0**-52 * terms
+    assert np.all(np.abs(g - go) <= tol), (g, go, terms)

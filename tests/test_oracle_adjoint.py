@@ -91,3 +91,17 @@ def test_shifted_reaction_adjoint():
     lp = np.sum((O.etd_rdp_if_step(U + eps * V, k, D, bcs, hs, "schnakenberg", params) - tgt) ** 2)
     lm = np.sum((O.etd_rdp_if_step(U - eps * V, k, D, bcs, hs, "schnakenberg", params) - tgt) ** 2)
     assert abs((lp - lm) / (2 * eps) - np.sum(gU * V)) <= 1e-6 * abs(np.sum(gU * V))
+
+
+def test_term_scale_bounds_every_entry():
+    """The optional term-size output is the sum of |terms| of each entry: it
+    bounds the entry (triangle inequality) and leaves the results unchanged."""
+    model, params, bcs, D, k = CASES[1]
+    U, tgt, hs, rng = _setup(model, bcs)
+    lam = rng.standard_normal(U.shape)
+    ts = {}
+    a = O.adjoint_step(U, lam, k, D, bcs, hs, model, params)
+    b = O.adjoint_step(U, lam, k, D, bcs, hs, model, params, term_scale=ts)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert np.all(np.abs(b[1]) <= ts["D"]) and np.all(ts["D"] > 0)
+    assert np.all(np.abs(b[2]) <= ts["theta"]) and np.all(ts["theta"] > 0)
