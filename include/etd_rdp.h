@@ -219,6 +219,27 @@ int etd_rdp_step(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
                  int64_t nsteps, void* stream);
 
 /*
+ * etd_rdp_step_static -- etd_rdp_step without a caller workspace, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * device array of ETD_STATIC_SCRATCH_BYTES inside the library, one per
+ * device, which each device holds until the process ends; the call makes no
+ * allocation.  u, nsteps and stream as etd_rdp_step; FP64 contexts only.
+ *
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other host threads, other streams) race and give wrong
+ * results; calls ordered on one stream do not.  The tables are uploaded
+ * (an asynchronous copy on `stream`) whenever another context used the
+ * array last; nothing else in it needs clearing.
+ * Errors: ETD_ERR_ARG (NULL ctx/u, nsteps < 0, not an FP64 context),
+ * ETD_ERR_WORKSPACE (etd_rdp_workspace_bytes of the context exceeds
+ * ETD_STATIC_SCRATCH_BYTES: use etd_rdp_step), ETD_ERR_UNSUPPORTED (a
+ * context with a reaction field; a device index above 63), ETD_ERR_HIP.
+ */
+#define ETD_STATIC_SCRATCH_BYTES (64u << 20)
+int etd_rdp_step_static(etd_rdp_ctx* ctx, double* u, int64_t nsteps, void* stream);
+
+/*
  * etd_rdp_step_f32 -- etd_rdp_step for a context created with
  * ETD_PRECISION_F32: u holds s*N floats (same layout), the carried arrays
  * are FP32 and every solve and reaction evaluation runs in FP32 arithmetic

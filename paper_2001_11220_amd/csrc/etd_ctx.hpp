@@ -41,6 +41,7 @@ struct etd_rdp_ctx {
   size_t field_off = 0, field_bytes = 0;
   const void* field_ws = nullptr;  // workspace the field was last stored in
   int last_hip = 0;
+  uint64_t uid = 0;  // unique per context of the process (never reused)
 };
 
 namespace etd {

@@ -19,9 +19,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1219,7 +1221,67 @@ int run_pass_impl(etd_rdp_ctx* ctx, T* u, void* ws, size_t ws_bytes, int32_t pas
 }  // namespace
 }  // namespace etd
 
+// ---------------------------------------------------------------------------
+// Workspace of etd_rdp_step_static, for callers that cannot allocate: one
+// copy per device, held until the process ends.  In host code the name is a
+// stand-in for the device symbol; kernels get the device address that
+// hipGetSymbolAddress returned for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[ETD_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};    // device address of `scratch`, per device
+uint64_t g_scratch_owner[kMaxDevices] = {};  // uid of the context whose tables it holds
+}  // namespace
+
 extern "C" {
+
+int etd_rdp_step_static(etd_rdp_ctx* ctx, double* u, int64_t nsteps, void* stream) {
+  if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;
+  if (ctx->precision != ETD_PRECISION_F64) return ETD_ERR_ARG;
+  if (ctx->has_field) return ETD_ERR_UNSUPPORTED;
+  if (ctx->ws_bytes > static_cast<size_t>(ETD_STATIC_SCRATCH_BYTES)) return ETD_ERR_WORKSPACE;
+  if (nsteps == 0) return ETD_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  if (dev < 0 || dev >= kMaxDevices) return ETD_ERR_UNSUPPORTED;
+  void* ws = nullptr;
+  bool upload = false;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      // once per device, with that device current
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) return hip_fail(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol);
+      g_scratch_ptr[dev] = p;
+    }
+    ws = g_scratch_ptr[dev];
+    // The tables sit at the front; another context's call may have replaced
+    // them since this one last ran here.  The carried arrays need no
+    // clearing: every pass writes its outputs before the next reads them.
+    upload = g_scratch_owner[dev] != ctx->uid;
+    g_scratch_owner[dev] = ctx->uid;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (upload) {
+    e = hipMemcpyAsync(ws, ctx->tabs.data(), ctx->tabs.size() * sizeof(SolveTab),
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      g_scratch_owner[dev] = 0;
+      return hip_fail(ctx, e);
+    }
+  }
+  for (int64_t i = 0; i < nsteps; ++i) {
+    const int rc = run_passes(ctx, u, ws, 0, ctx->d, st);
+    if (rc) return rc;
+  }
+  return ETD_OK;
+}
 
 const char* etd_rdp_status_string(int status) {
   switch (status) {
@@ -1269,6 +1331,8 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
 
   etd_rdp_ctx* c = new (std::nothrow) etd_rdp_ctx();
   if (!c) return ETD_ERR_INTERNAL;
+  static std::atomic<uint64_t> next_uid{1};
+  c->uid = next_uid.fetch_add(1);
   c->d = d;
   c->s = s;
   c->k = k;

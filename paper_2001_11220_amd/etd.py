@@ -101,6 +101,7 @@ def _load():
         "etd_rdp_batch_launches_per_step": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
         "etd_calib_stream": (ctypes.c_int, [I32, P, P, SZ, I32, P]),
         "etd_rdp_forget_workspace": (ctypes.c_int, [P]),
+        "etd_rdp_step_static": (ctypes.c_int, [P, P, I64, P]),
         "etd_rdp_batch_forget_workspace": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
@@ -319,6 +320,16 @@ class EtdRdp:
                         self.precision, (lib.etd_rdp_step, "etd_rdp_step"))
         _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
                   self.ws_bytes, int(nsteps), self._stream(stream)), name)
+        return u
+
+    def step_static(self, u, nsteps=1, stream=None):
+        """``step`` with the library's own per-device workspace
+        (etd_rdp_step_static): no allocation, FP64 problems whose workspace
+        fits ETD_STATIC_SCRATCH_BYTES (64 MiB); calls that overlap on one
+        device race."""
+        p = self._state_ptr(u, self.s)
+        _check(lib.etd_rdp_step_static(self._ctx, ctypes.c_void_p(p), int(nsteps),
+                                       self._stream(stream)), "etd_rdp_step_static")
         return u
 
     def set_field(self, b, stream=None):
