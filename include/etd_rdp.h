@@ -330,6 +330,20 @@ int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes,
  */
 int etd_rdp_forget_workspace(etd_rdp_ctx* ctx);
 
+/*
+ * etd_rdp_set_slab -- schedule of a 3-D step: with planes > 0, passes 1 and 2
+ * run slab by slab, `planes` planes of axis 3 at a time (pass 2 of a slab
+ * reads what pass 1 of the same slab has just written, while much of it is
+ * still in the device's caches); pass 3 runs over the whole grid.  0 (the
+ * default, and any value >= n[2]) runs each pass over the whole grid.  The
+ * result is the same bit for bit; only the launch order changes (2 launches
+ * per slab instead of 2 per step).  Contexts with a reaction field ignore it.
+ * etd_rdp_get_slab reads it back.  Errors: ETD_ERR_ARG (NULL, planes < 0),
+ * ETD_ERR_UNSUPPORTED (planes > 0 and d != 3).
+ */
+int etd_rdp_set_slab(etd_rdp_ctx* ctx, int64_t planes);
+int etd_rdp_get_slab(const etd_rdp_ctx* ctx, int64_t* planes);
+
 /* Human-readable text of a status code (static storage). */
 const char* etd_rdp_status_string(int status);
 

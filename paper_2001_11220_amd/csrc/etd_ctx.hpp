@@ -42,6 +42,11 @@ struct etd_rdp_ctx {
   const void* field_ws = nullptr;  // workspace the field was last stored in
   int last_hip = 0;
   uint64_t uid = 0;  // unique per context of the process (never reused)
+  // 3-D slab schedule: passes 1 and 2 run on slabs of slab_planes planes of
+  // axis 3 in turn (0: each pass over the whole grid).  slab_nz > 0 while a
+  // launch is restricted to planes [slab_z0, slab_z0 + slab_nz).
+  int64_t slab_planes = 0;
+  int64_t slab_z0 = 0, slab_nz = 0;
 };
 
 namespace etd {

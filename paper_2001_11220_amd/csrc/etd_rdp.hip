@@ -847,6 +847,12 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, 
       g.outT = n1 * n2; g.outRow = n1;
       break;
   }
+  if (c->slab_nz > 0) {
+    // a slab of planes of axis 3 (3-D passes 1 and 2; the caller offsets
+    // the arrays to the slab's first plane)
+    if (kind == kPassFirst) g.nT = c->slab_nz;
+    else if (kind == kPassMid) g.nF = c->slab_nz;
+  }
   g.n = static_cast<int>(c->n[axis0]);
   g.C = g.n / (one_line ? c->m1[axis0] : c->m[axis0]);
   g.pitch = tile_pitch(g.n);
@@ -1173,7 +1179,25 @@ int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream
   c->rx.fldd = c->has_field ? reinterpret_cast<const double*>(static_cast<char*>(ws) + c->field_off +
                                                               c->field_bytes)
                             : nullptr;
-  for (int p = first; p < npasses; ++p) {
+  int p = first;
+  if (c->d == 3 && c->slab_planes > 0 && !c->has_field && first == 0 && npasses >= 2) {
+    // Passes 1 and 2 slab by slab along axis 3: pass 2 of a slab reads what
+    // pass 1 of the same slab has just written.  Plane z starts at z*n1*n2 in
+    // u and in A (layout [z][x][y]) and at z in B ([x][y][z]).
+    const int64_t n3 = c->n[2], plane = c->n[0] * c->n[1];
+    for (int64_t z0 = 0; z0 < n3; z0 += c->slab_planes) {
+      c->slab_z0 = z0;
+      c->slab_nz = std::min<int64_t>(c->slab_planes, n3 - z0);
+      T* const As[3] = {A[0] + z0 * plane, A[1] + z0 * plane, A[2] + z0 * plane};
+      T* const Bs[3] = {B[0] + z0, B[1] + z0, B[2] + z0};
+      int rc = launch_pass(c, 0, u + z0 * plane, As, As, tabs, st);
+      if (!rc) rc = launch_pass(c, 1, u, As, Bs, tabs, st);
+      c->slab_nz = 0;
+      if (rc) return rc;
+    }
+    p = 2;
+  }
+  for (; p < npasses; ++p) {
     // Pass p writes A (p even) or B (p odd) and reads what pass p - 1 wrote.
     const bool into_b = (p % 2 == 1);
     const bool from_b = (p % 2 == 0);
@@ -1558,6 +1582,19 @@ int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, 
 }
 
 int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+int etd_rdp_set_slab(etd_rdp_ctx* ctx, int64_t planes) {
+  if (!ctx || planes < 0) return ETD_ERR_ARG;
+  if (planes > 0 && ctx->d != 3) return ETD_ERR_UNSUPPORTED;
+  ctx->slab_planes = (planes >= ctx->n[2]) ? 0 : planes;
+  return ETD_OK;
+}
+
+int etd_rdp_get_slab(const etd_rdp_ctx* ctx, int64_t* planes) {
+  if (!ctx || !planes) return ETD_ERR_ARG;
+  *planes = ctx->slab_planes;
+  return ETD_OK;
+}
 
 int etd_rdp_forget_workspace(etd_rdp_ctx* ctx) {
   if (!ctx) return ETD_ERR_ARG;

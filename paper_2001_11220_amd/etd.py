@@ -102,6 +102,8 @@ def _load():
         "etd_calib_stream": (ctypes.c_int, [I32, P, P, SZ, I32, P]),
         "etd_rdp_forget_workspace": (ctypes.c_int, [P]),
         "etd_rdp_step_static": (ctypes.c_int, [P, P, I64, P]),
+        "etd_rdp_set_slab": (ctypes.c_int, [P, I64]),
+        "etd_rdp_get_slab": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "etd_rdp_batch_forget_workspace": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
@@ -321,6 +323,17 @@ class EtdRdp:
         _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
                   self.ws_bytes, int(nsteps), self._stream(stream)), name)
         return u
+
+    @property
+    def slab(self):
+        """Planes of axis 3 per slab of passes 1-2 (0: whole passes)."""
+        v = ctypes.c_int64()
+        _check(lib.etd_rdp_get_slab(self._ctx, ctypes.byref(v)), "etd_rdp_get_slab")
+        return v.value
+
+    @slab.setter
+    def slab(self, planes):
+        _check(lib.etd_rdp_set_slab(self._ctx, int(planes)), "etd_rdp_set_slab")
 
     def step_static(self, u, nsteps=1, stream=None):
         """``step`` with the library's own per-device workspace
