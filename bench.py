@@ -510,20 +510,35 @@ def bench_ensemble(args, cpu=None):
     prec = args.precision
     wb = 4 if prec == "f32" else 8  # bytes per word
     b = EtdRdpBatch(ens.instances, ens.s, ens.model, ens.k, device=dev, precision=prec)
-    u = b.pack(ens.states)
     stream = torch.cuda.current_stream()
     steps = args.steps
-    print(f"[bench] ensemble of {b.n} instances, {ens.cell_species:.3e} cell-species, "
-          f"{b.launches_per_step} launches/step, ws={b.ws_bytes/2**30:.2f} GiB", file=sys.stderr, flush=True)
-    b.step(u, steps, use_graph=True)  # records the graph (untimed warm-up of `steps` steps)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    b.step(u, steps, use_graph=True)  # one graph launch
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    print(f"[bench] ensemble of {b.n} instances in {len(b.groups())} groups, {ens.cell_species:.3e} "
+          f"cell-species, {b.launches_per_step} launches/step, ws={b.ws_bytes/2**30:.2f} GiB",
+          file=sys.stderr, flush=True)
+
+    def graph_run():
+        u = b.pack(ens.states)
+        b.step(u, steps, use_graph=True)  # records the graph (untimed warm-up of `steps` steps)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        b.step(u, steps, use_graph=True)  # one graph launch
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return u, ev0.elapsed_time(ev1)
+
+    default_plan = b.plan
+    _, ms_default = graph_run()
+    # the autotuner (on a scratch copy of the state), then the timed run
+    times = b.tune(b.pack(ens.states), reps=3)
+    tuned_plan = b.plan
+    u, ms = graph_run()
     ms_step = ms / steps
+    print(f"[bench] default plan {ms_default / steps * 1e3:.1f} us/step, tuned plan {ms_step * 1e3:.1f} "
+          f"us/step", file=sys.stderr, flush=True)
+    for g, (n1, n2, cnt) in enumerate(b.groups()):
+        print(f"[bench]   group {n1}x{n2} ({cnt}): pass 1 {times[g][0]} ms, pass 2 {times[g][1]} ms -> "
+              f"forms {tuned_plan[2 * g]}, {tuned_plan[2 * g + 1]}", file=sys.stderr, flush=True)
     value = ens.cell_species * steps / (ms / 1e3)
     finite = bool(torch.isfinite(u).all().item())
     # plain 2-D solver at the largest instance size, same coefficients range
@@ -533,6 +548,7 @@ def bench_ensemble(args, cpu=None):
                                     for _ in range(2)])).to(dev, b.dtype)
     p.step(up, 20)
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     p.step(up, steps)
     ev1.record(stream)
@@ -557,7 +573,13 @@ def bench_ensemble(args, cpu=None):
         "data": "synthetic (seeded instance parameters and initial data, no dataset)",
         "config": {"workload": "brusselator_ensemble", "instances": b.n,
                    "cell_species": ens.cell_species, "launches_per_step": b.launches_per_step,
-                   "graph": "all steps in one HIP graph launch", "state_finite": finite},
+                   "graph": "all steps in one HIP graph launch", "state_finite": finite,
+                   "groups": [list(g) for g in b.groups()],
+                   "plan": "autotuned (etd_rdp_batch_tune), forms per (group, pass): "
+                           + ",".join(map(str, tuned_plan)),
+                   "default_plan_ms_per_step": ms_default / steps,
+                   "default_plan": ",".join(map(str, default_plan)),
+                   "tune_times_ms": times},
         "roofline": {"bound": "hbm", "achieved": eff, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": eff / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "whole step (all groups, 2 passes)",

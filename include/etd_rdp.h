@@ -446,7 +446,9 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s,
 int etd_rdp_batch_destroy(etd_rdp_batch* b);
 
 /* offsets[0..ninst]: start of instance i in the packed state (elements);
- * offsets[ninst] is the total length.  Offsets are multiples of 32. */
+ * offsets[ninst] is the total length.  Offsets are multiples of 32.
+ * Instances of one grid shape sit next to each other (see the groups below),
+ * so the offsets are not in instance order. */
 int etd_rdp_batch_offsets(const etd_rdp_batch* b, int64_t* offsets);
 
 /* Device workspace bytes (tables, instance descriptors, tile maps and the
@@ -481,8 +483,73 @@ int etd_rdp_batch_step_f32(etd_rdp_batch* b, float* u_packed, void* ws,
  * Errors: ETD_ERR_ARG (NULL). */
 int etd_rdp_batch_forget_workspace(etd_rdp_batch* b);
 
-/* Number of kernel launches of one step (for tests and reports). */
+/* Number of kernel launches of one step (for tests and reports): two per
+ * group. */
 int etd_rdp_batch_launches_per_step(const etd_rdp_batch* b, int32_t* n);
+
+/* ----------------------------------------------------------------------
+ * Groups, plans and the autotuner.
+ *
+ * Instances of the same grid shape (n1, n2) form a group, stored next to
+ * each other at equal spacing (so etd_rdp_batch_offsets is not in instance
+ * order); a step is one launch per (group, pass).  Each (group, pass) runs
+ * one of three kernel forms, its plan entry:
+ *   ETD_FORM_UNSPLIT   all solves of a species at once; 16-line tiles for
+ *                      chunks of up to 4 rows, 8-line tiles otherwise;
+ *   ETD_FORM_STREAMED  solves in phases of at most two, 16-line tiles
+ *                      (chunks of at least 3 rows; not pass 1 of ETD1);
+ *   ETD_FORM_TWO_LINE  streamed with two lines of 32 chunks per wavefront,
+ *                      32-line tiles (lines of n = 32 m rows, 2 <= m <= 8;
+ *                      not pass 1 of ETD1).
+ * A plan is an int32 array of 2 * ngroups entries: plan[2 g + p] is the form
+ * of pass p (0: axis 1, 1: axis 2) of group g.  Every form computes the same
+ * step up to rounding (the chunking of the two-line form differs).
+ * ---------------------------------------------------------------------- */
+#define ETD_FORM_UNSPLIT 0
+#define ETD_FORM_STREAMED 1
+#define ETD_FORM_TWO_LINE 2
+
+/* Number of groups; if shapes is not NULL, shapes[2 g], shapes[2 g + 1] get
+ * group g's (n1, n2); if counts is not NULL, counts[g] its instance count.
+ * Errors: ETD_ERR_ARG (NULL b or ngroups). */
+int etd_rdp_batch_groups(const etd_rdp_batch* b, int32_t* ngroups, int64_t* shapes,
+                         int32_t* counts);
+
+/* The current plan (2 * ngroups entries).  A new ensemble starts with a
+ * default plan from the single-problem rules.  Errors: ETD_ERR_ARG. */
+int etd_rdp_batch_get_plan(const etd_rdp_batch* b, int32_t* plan);
+
+/* Replace the plan (e.g. one etd_rdp_batch_tune found earlier and a caller
+ * kept).  ETD_ERR_ARG (and no change) if any entry is not a form that
+ * (group, pass) allows.  Drops a recorded graph. */
+int etd_rdp_batch_set_plan(etd_rdp_batch* b, const int32_t* plan);
+
+/* *allowed = 1 if (group, pass) may run `form`, else 0.  Errors:
+ * ETD_ERR_ARG (NULL, index out of range). */
+int etd_rdp_batch_form_allowed(const etd_rdp_batch* b, int32_t group, int32_t pass,
+                               int32_t form, int32_t* allowed);
+
+/*
+ * etd_rdp_batch_tune -- the autotuner: for every group and pass, time `reps`
+ * launches (after one untimed launch) of every form it allows, on `stream`
+ * with HIP events, and keep the fastest in the plan.  Works on the caller's
+ * state: u (device, offsets[ninst] elements of the ensemble's precision) is
+ * advanced by exactly one step of the new plan.  times (may be NULL):
+ * 2 * ngroups * 3 doubles, times[(2 g + p) * 3 + form] = milliseconds per
+ * launch, or -1 for a form the (group, pass) does not allow.  Synchronises
+ * the stream before returning.  Errors: ETD_ERR_ARG, ETD_ERR_WORKSPACE,
+ * ETD_ERR_HIP.
+ */
+int etd_rdp_batch_tune(etd_rdp_batch* b, void* u, void* ws, size_t ws_bytes, int32_t reps,
+                       void* stream, double* times);
+
+/* Launch pass `pass` of group `group` alone in form `form` (-1: the plan's),
+ * on the same arrays as inside a step (pass 0 reads u and writes the carried
+ * arrays, pass 1 reads them and writes u).  For timing and tests.  Errors:
+ * ETD_ERR_ARG (bad index, a form the group does not allow), ETD_ERR_WORKSPACE,
+ * ETD_ERR_HIP. */
+int etd_rdp_batch_group_pass(etd_rdp_batch* b, void* u, void* ws, size_t ws_bytes,
+                             int32_t group, int32_t pass, int32_t form, void* stream);
 
 /* ======================================================================
  * Bandwidth calibration (for reports; not part of the scheme).

@@ -1,15 +1,27 @@
 // Ensembles of independent 2-D ETD-RDP-IF problems of uneven size.
 //
-// Every instance runs the same two passes as a single 2-D problem (the frame
-// of Section 6, eq. done): pass 1 along axis 1 (f, w, R_1 U, R_1 f, P_1 w)
-// and pass 2 along axis 2 (P_2, f*, T_2 / S_2), with the same data layouts
-// and tiles.  Instances are grouped by the chunk length m of the pass's axis
-// (one kernel instantiation per m); one launch per (pass, group) walks the
-// group's tiles, 8 or 16 lines each, in instance order.  A persistent block re-stages the per-lane PCR data in LDS
-// only when its next tile belongs to another instance.  The launches of all
-// steps can be recorded into one HIP graph.  The kernels take the element
-// type as a template parameter (FP64, or FP32 with the FP64 tables
-// converted as they are staged), as the single-problem kernels do.
+// Every instance runs the two passes of a single 2-D problem (the frame of
+// Section 6, eq. done): pass 1 along axis 1 (f, w, R_1 U, R_1 f, P_1 w) and
+// pass 2 along axis 2 (P_2, f*, T_2 / S_2), with the same data layouts.
+//
+// Instances of the same grid shape (n1, n2) form a group.  A group's states
+// sit next to each other at a fixed stride, so the group is one strided pass
+// geometry with one more line-group dimension, the instance: a group's pass
+// is one launch of the single-problem pass kernels (etd_passes.hpp) in their
+// ensemble form, which re-stages the per-lane solver tables in LDS when a
+// block moves to the next instance and takes each instance's reaction
+// parameters from a table.  Boundary conditions and coefficients only enter
+// the tables, so instances of one group may differ in both.
+//
+// Each (group, pass) runs one of three kernel forms (its plan entry):
+//   kFormUnsplit    every solve of a species at once, 16-line tiles for
+//                   chunks of up to 4 rows, 8-line tiles otherwise;
+//   kFormStreamed   solves in phases of at most two (16-line tiles);
+//   kFormTwoLine    streamed, two lines of 32 chunks per wavefront (32-line
+//                   tiles), for lines of n = 32 m rows, 2 <= m <= 8.
+// The default plan follows the single-problem rules; etd_rdp_batch_tune
+// times every form a (group, pass) allows and keeps the fastest.  The
+// launches of all steps can be recorded into one HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,199 +32,55 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
+#include "etd_ctx.hpp"
 #include "etd_device.hpp"
 #include "etd_launch.hpp"
+#include "etd_passes.hpp"
 #include "etd_rdp.h"
 #include "etd_tables.hpp"
 
 namespace etd {
 
-// Device descriptor of one instance: its offset in the packed arrays and the
-// geometry of its two passes.  Pass 1 reads x-lines of u and writes the
-// instance's carried triple with y fastest ([s][x][y]); pass 2 reads those
-// y-lines and writes u (the same rotation as the single-problem 2-D step).
-struct BatchInst {
-  int64_t off;            // start of the instance's state and carried arrays
-  PassGeom g1, g2;        // pass geometries (tile buffers sized per group)
-  const SolveTab* tab1;   // 3*S tables of axis 1
-  const SolveTab* tab2;   // 3*S tables of axis 2
-  Rx rx;
-};
+enum BatchForm : int { kFormUnsplit = 0, kFormStreamed = 1, kFormTwoLine = 2, kNumForms = 3 };
 
-// Pass 1 of the ensemble (axis 1).  A tile is L x-lines of one instance with
-// adjacent y; tile_loc gives its first line / L.
+// Smallest chunk length the streamed one-line form is built for (shorter
+// chunks leave too little work between the phases' exchanges).
+constexpr int kGroupStreamMinM = 3;
+
+// Ensemble forms of the pass kernels (G = true in etd_passes.hpp).
 template <int M, int S, int L, typename T>
-__global__ __launch_bounds__(64 * L, kMinWaves<M>) void kb_first(
+__global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void kg_first(
     const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
-    T* __restrict__ w, const BatchInst* __restrict__ insts,
-    const int* __restrict__ tile_inst, const int* __restrict__ tile_loc, int64_t ntiles,
-    T k, int etd1) {
-  extern __shared__ double lds_raw[];
-  char* const lds = reinterpret_cast<char*>(lds_raw);
-  using LT = LaneTabT<kLanes, T>;
-  LT* lt = reinterpret_cast<LT*>(lds);
-  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
-  const int lane = threadIdx.x & 63;
-  int staged = -1;
-  TileCursor cur;
-  TileWalk walk(ntiles);
-  int64_t tile;
-  while (walk.next(tile)) {
-    // Wave-uniform by construction; readfirstlane lets the descriptor loads
-    // go to scalar registers.
-    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
-    const BatchInst& I = insts[ii];
-    if (ii != staged) {
-      __syncthreads();
-      stage_lane_tabs(I.tab1, 3 * S, lt);
-      __syncthreads();
-      staged = ii;
-    }
-    const AxisTabs<S, kLanes, T> at{I.tab1, lt};
-    const PassGeom g = I.g1;
-    const TileAt pos((int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
-    T U[S][M], f[S][M];
-#pragma unroll
-    for (int s = 0; s < S; ++s) line_load<M>(u + I.off + s * g.N, U[s], g, pos);
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      T uu[S], ff[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) uu[s] = U[s][j];
-      react<S>(I.rx, uu, ff);
-#pragma unroll
-      for (int s = 0; s < S; ++s) f[s][j] = ff[s];
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int64_t o = I.off + s * g.N;
-      if (etd1) {
-        T x[1][M];
-#pragma unroll
-        for (int j = 0; j < M; ++j) x[0][j] = fma(k, f[s][j], U[s][j]);
-        const TabOf<T>* tb[1] = {at.P(s)};
-        const LT* lb[1] = {at.lP(s)};
-        line_solve<M, 1>(tb, lb, x, lane);
-        tile_store<M, L>(w + o, x[0], tl, g, pos, cur);
-        continue;
-      }
-      T x[5][M];
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        x[0][j] = U[s][j];
-        x[1][j] = f[s][j];
-        x[2][j] = U[s][j];
-        x[3][j] = f[s][j];
-        x[4][j] = fma(k, f[s][j], U[s][j]);
-      }
-      const TabOf<T>* tb[5] = {at.T(s), at.T(s), at.Sx(s), at.Sx(s), at.P(s)};
-      const LT* lb[5] = {at.lT(s), at.lT(s), at.lS(s), at.lS(s), at.lP(s)};
-      line_solve<M, 5>(tb, lb, x, lane);
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        x[0][j] = T(9) * x[0][j] - T(8) * x[2][j];
-        x[1][j] = T(9) * x[1][j] - T(8) * x[3][j];
-      }
-      tile_store<M, L>(c1 + o, x[0], tl, g, pos, cur);
-      tile_store<M, L>(c2 + o, x[1], tl, g, pos, cur);
-      tile_store<M, L>(w + o, x[4], tl, g, pos, cur);
-    }
-  }
+    T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g,
+    int etd1, GroupCoef gc) {
+  k_first_body<M, S, L, false, T, true>(u, c1, c2, w, tabs, rx, k, g, etd1, gc);
 }
 
-// Lines per tile of pass 2: as in the single-problem kernels, except that
-// FP32 chunks of 5-8 rows take 16-line tiles at four waves per SIMD (their
-// registers fit 128 VGPRs, where FP64 ones need 2 waves).  last_lines is
-// the host side of the same rule.
-template <int M, typename T>
-constexpr int kLastLines = (std::is_same<T, float>::value && M >= 5) ? 16 : kLinesFor<M>;
-
-inline int last_lines(int m, int precision) {
-  return (precision == ETD_PRECISION_F32 && m >= 5) ? 16 : lines_for(m);
+template <int M, int S, int L, int P, typename T>
+__global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void kg_first_s(
+    const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
+    T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g,
+    GroupCoef gc) {
+  k_first_s_body<M, S, L, P, false, false, T, true>(u, c1, c2, w, tabs, rx, k, g, gc);
 }
 
-// Pass 2 of the ensemble (axis 2).  A tile is L y-lines of one instance with
-// adjacent x, read line by line from the carried triple; u is written
-// through the LDS transpose.
 template <int M, int S, int L, typename T>
-__global__ __launch_bounds__(64 * L, (L >= 16 ? 4 : 2)) void kb_last(
+__global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void kg_last(
     T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
-    const T* __restrict__ w, const BatchInst* __restrict__ insts,
-    const int* __restrict__ tile_inst, const int* __restrict__ tile_loc, int64_t ntiles,
-    T k, int etd1) {
-  extern __shared__ double lds_raw[];
-  char* const lds = reinterpret_cast<char*>(lds_raw);
-  using LT = LaneTabT<kLanes, T>;
-  LT* lt = reinterpret_cast<LT*>(lds);
-  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
-  const int lane = threadIdx.x & 63;
-  const T k2 = T(2) * k, k15 = T(1.5) * k, k05 = T(0.5) * k;
-  int staged = -1;
-  TileCursor cur;
-  TileWalk walk(ntiles);
-  int64_t tile;
-  while (walk.next(tile)) {
-    // Wave-uniform by construction; readfirstlane lets the descriptor loads
-    // go to scalar registers.
-    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
-    const BatchInst& I = insts[ii];
-    if (ii != staged) {
-      __syncthreads();
-      stage_lane_tabs(I.tab2, 3 * S, lt);
-      __syncthreads();
-      staged = ii;
-    }
-    const AxisTabs<S, kLanes, T> at{I.tab2, lt};
-    const PassGeom g = I.g2;
-    const TileAt pos((int64_t)__builtin_amdgcn_readfirstlane(tile_loc[tile]) * L);
-    T us[S][M];
-#pragma unroll
-    for (int s = 0; s < S; ++s) line_load<M>(w + I.off + s * g.N, us[s], g, pos);
-    {
-      const TabOf<T>* tb[S];
-      const LT* lb[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        tb[s] = at.P(s);
-        lb[s] = at.lP(s);
-      }
-      line_solve<M, S>(tb, lb, us, lane);
-    }
-    if (etd1) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M, L>(u + I.off + s * g.N, us[s], tl, g, pos, cur);
-      continue;
-    }
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      T uu[S], ff[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) uu[s] = us[s][j];
-      react<S>(I.rx, uu, ff);
-#pragma unroll
-      for (int s = 0; s < S; ++s) us[s][j] = ff[s];
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int64_t o = I.off + s * g.N;
-      T a[M], b[M], x[2][M];
-      line_load<M>(c1 + o, a, g, pos);
-      line_load<M>(c2 + o, b, g, pos);
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        x[0][j] = fma(k, us[s][j], fma(k2, b[j], T(9) * a[j]));
-        x[1][j] = fma(k05, us[s][j], fma(k15, b[j], T(8) * a[j]));
-      }
-      const TabOf<T>* tb[2] = {at.T(s), at.Sx(s)};
-      const LT* lb[2] = {at.lT(s), at.lS(s)};
-      line_solve<M, 2>(tb, lb, x, lane);
-#pragma unroll
-      for (int j = 0; j < M; ++j) a[j] = x[0][j] - x[1][j];
-      tile_store<M, L>(u + o, a, tl, g, pos, cur);
-    }
-  }
+    const T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k,
+    PassGeom g, int etd1, GroupCoef gc) {
+  k_last_body<M, S, L, false, T, true>(u, c1, c2, w, tabs, rx, k, g, etd1, gc);
+}
+
+template <int M, int S, int L, int P, typename T>
+__global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void kg_last_s(
+    T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
+    const T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k,
+    PassGeom g, int etd1, GroupCoef gc) {
+  k_last_s_body<M, S, L, P, false, T, true>(u, c1, c2, w, tabs, rx, k, g, etd1, gc);
 }
 
 }  // namespace etd
@@ -221,16 +89,18 @@ using namespace etd;
 
 namespace {
 
+// One group: instances of one grid shape, stored back to back at `stride`
+// elements from offset `off`.
 struct Group {
-  int m = 0;
-  int lines = 8;                  // lines per tile (lines_for(m))
-  std::vector<int> inst;          // instance ids, ascending
-  std::vector<int> tile_inst;     // per tile
-  std::vector<int> tile_loc;      // per tile: tile index inside its instance
-  int max_n = 0;                  // largest line length
-  int tile = 0, nbuf = 1;         // LDS tile buffer (elements) and buffer count
-  size_t lds = 0;                 // dynamic LDS of the launch
-  size_t off_tile_inst = 0, off_tile_loc = 0;  // workspace offsets
+  int64_t n1 = 0, n2 = 0;
+  std::vector<int> inst;     // instance ids, ascending
+  int64_t off = 0, stride = 0;
+  int m1[2] = {0, 0};        // chunk length, one line per wavefront (axis 1, 2)
+  int m2[2] = {0, 0};        // chunk length with two lines per wavefront (0: n != 32 m)
+  size_t tab1[2] = {0, 0};   // first table (index) of the one-line sets, per axis
+  size_t tab2[2] = {0, 0};   // the same for the two-line sets (if m2)
+  size_t rx_index = 0;       // first reaction record of the group
+  int form[2] = {kFormUnsplit, kFormUnsplit};  // plan: kernel form per pass
 };
 
 struct GraphCache {
@@ -247,13 +117,13 @@ struct etd_rdp_batch {
   int precision = ETD_PRECISION_F64;  // element type of the state and carried arrays
   double k = 0;
   std::vector<etd_instance_t> inst;
-  std::vector<int64_t> n1, n2, offsets;
-  std::vector<double> h1, h2;
-  std::vector<SolveTab> tabs;        // [instance][axis][species][3]
-  std::vector<Group> g1, g2;         // pass-1 and pass-2 groups
-  size_t off_tabs = 0, off_insts = 0, off_maps = 0, off_c1 = 0, off_c2 = 0, off_w = 0;
-  size_t ws_bytes = 0, arr_bytes = 0;
-  std::vector<char> image;           // static part of the workspace
+  std::vector<int64_t> offsets;      // per instance (layout order differs from id order)
+  int64_t total = 0;
+  std::vector<SolveTab> tabs;        // per group, axis and chunking: [instance][species][3]
+  std::vector<Rx> rxs;               // per group, instance order within the group
+  std::vector<Group> groups;
+  size_t off_tabs = 0, off_rx = 0, off_c1 = 0, off_c2 = 0, off_w = 0;
+  size_t ws_bytes = 0, arr_bytes = 0, image_bytes = 0;
   const void* uploaded_ws = nullptr;
   GraphCache graph;
   hipStream_t capture = nullptr;
@@ -261,8 +131,6 @@ struct etd_rdp_batch {
 };
 
 namespace {
-
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_bytes(const etd_rdp_batch* b) {
   return b->precision == ETD_PRECISION_F32 ? sizeof(float) : sizeof(double);
@@ -280,158 +148,268 @@ int species_of(int model) {
   }
 }
 
-void build_groups(etd_rdp_batch* b, int axis, std::vector<Group>& out) {
-  std::map<int, Group> by_m;
-  for (int i = 0; i < b->ninst; ++i) {
-    const int64_t n = axis == 0 ? b->n1[i] : b->n2[i];
-    const int64_t lines = axis == 0 ? b->n2[i] : b->n1[i];
-    const int m = choose_chunk(n);
-    Group& g = by_m[m];
-    g.m = m;
-    g.lines = axis == 1 ? last_lines(m, b->precision) : lines_for(m);
-    g.inst.push_back(i);
-    g.max_n = std::max<int>(g.max_n, static_cast<int>(n));
-    const int64_t nt = (lines + g.lines - 1) / g.lines;
-    for (int64_t t = 0; t < nt; ++t) {
-      g.tile_inst.push_back(i);
-      g.tile_loc.push_back(static_cast<int>(t));
-    }
-  }
-  out.clear();
-  const size_t esize = elem_bytes(b);
-  const size_t fixed = b->precision == ETD_PRECISION_F32 ? lane_lds<kLanes, float>(3 * b->s)
-                                                         : lane_lds<kLanes, double>(3 * b->s);
-  for (auto& kv : by_m) {
-    Group& g = kv.second;
-    g.tile = g.lines * tile_pitch(g.max_n);
-    g.nbuf = tile_buffers(fixed, g.lines, g.tile, esize);
-    g.lds = fixed + esize * (size_t)g.nbuf * g.tile;
-    out.push_back(g);
-  }
+// Whether a (group, pass) may run a form (the kernels exist and the line
+// length allows it).  pass: 0 (axis 1) or 1 (axis 2).
+bool form_allowed(const etd_rdp_batch* b, const Group& g, int pass, int form) {
+  if (form == kFormUnsplit) return true;
+  if (pass == 0 && b->scheme == ETD_SCHEME_ETD1) return false;  // a single solve: unsplit only
+  if (form == kFormStreamed) return g.m1[pass] >= kGroupStreamMinM;
+  if (form == kFormTwoLine) return g.m2[pass] >= kMinTwoLineM;
+  return false;
 }
 
-// Pass geometry of one instance inside its group.
-PassGeom inst_geom(const etd_rdp_batch* b, int i, int axis, const Group& grp) {
-  const int64_t n1 = b->n1[i], n2 = b->n2[i];
+// The default plan: the single-problem rules (two lines per wavefront for
+// passes of at least kTwoLineMinLines lines, streamed from the chunk lengths
+// where the single-problem passes switch).
+int default_form(const etd_rdp_batch* b, const Group& g, int pass) {
+  const int64_t lines = static_cast<int64_t>(g.inst.size()) * (pass == 0 ? g.n2 : g.n1);
+  if (lines >= kTwoLineMinLines && form_allowed(b, g, pass, kFormTwoLine)) return kFormTwoLine;
+  const int from = (pass == 0) ? 8 : 5;
+  if (g.m1[pass] >= from && form_allowed(b, g, pass, kFormStreamed)) return kFormStreamed;
+  return kFormUnsplit;
+}
+
+// Lines per tile and lines per wavefront of a form.
+int form_lines(int form, int m, int precision) {
+  if (form == kFormTwoLine) return 32;
+  if (form == kFormStreamed) return 16;
+  (void)precision;
+  return lines_for(m);
+}
+
+// Pass geometry of a group: line group t is instance t of the group.
+PassGeom group_geom(const etd_rdp_batch* b, const Group& grp, int pass, int form) {
   PassGeom g{};
-  g.N = n1 * n2;
-  g.nT = 1;
-  g.inT = 0;
-  g.outT = 0;
-  if (axis == 0) {  // x-lines (f = y) of u -> [x][y]
-    g.nF = n2;
-    g.inF = n1;
-    g.outRow = n2;
-    g.n = static_cast<int>(n1);
+  g.N = grp.n1 * grp.n2;
+  g.nT = static_cast<int64_t>(grp.inst.size());
+  g.inT = grp.stride;
+  g.outT = grp.stride;
+  if (pass == 0) {  // x-lines (f = y) of u -> [x][y]
+    g.nF = grp.n2;
+    g.inF = grp.n1;
+    g.outRow = grp.n2;
+    g.n = static_cast<int>(grp.n1);
   } else {  // y-lines (f = x) of [x][y] -> u
-    g.nF = n1;
-    g.inF = n2;
-    g.outRow = n1;
-    g.n = static_cast<int>(n2);
+    g.nF = grp.n1;
+    g.inF = grp.n2;
+    g.outRow = grp.n1;
+    g.n = static_cast<int>(grp.n2);
   }
-  g.C = g.n / grp.m;
+  const int m = (form == kFormTwoLine) ? grp.m2[pass] : grp.m1[pass];
+  g.C = g.n / m;
   g.pitch = tile_pitch(g.n);
-  g.lines = grp.lines;
-  g.tile = grp.tile;
-  g.nbuf = grp.nbuf;
-  g.nFblk = (g.nF + grp.lines - 1) / grp.lines;
+  g.lines = form_lines(form, m, b->precision);
+  g.tile = g.lines * g.pitch;
+  const size_t esize = elem_bytes(b);
+  const int W = (form == kFormTwoLine) ? 32 : kLanes;
+  const size_t fixed = (b->precision == ETD_PRECISION_F32)
+                           ? (W == 32 ? lane_lds<32, float>(3 * b->s) : lane_lds<kLanes, float>(3 * b->s))
+                           : (W == 32 ? lane_lds<32, double>(3 * b->s) : lane_lds<kLanes, double>(3 * b->s));
+  g.nbuf = tile_buffers(fixed, g.lines, g.tile, esize);
+  g.nFblk = (g.nF + g.lines - 1) / g.lines;
   return g;
 }
 
-const Group& group_of(const std::vector<Group>& gs, int64_t n) {
-  const int m = choose_chunk(n);
-  for (const Group& g : gs)
-    if (g.m == m) return g;
-  return gs.front();  // unreachable: every instance is in a group
+template <typename T>
+struct Arrays {
+  T* u;
+  T* c1;
+  T* c2;
+  T* w;
+  const SolveTab* tabs;
+  const Rx* rxs;
+};
+
+template <typename KernelT>
+hipError_t prepare(KernelT kern, size_t lds, int64_t ntiles, int threads, unsigned* grid) {
+  hipError_t e = set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  return persistent_grid(kern, lds, ntiles, grid, threads);
 }
 
-// Static workspace image: tables, instance descriptors (device pointers into
-// ws) and tile maps.
-void build_image(etd_rdp_batch* b, char* ws) {
-  b->image.assign(b->off_c1, 0);
-  std::memcpy(b->image.data() + b->off_tabs, b->tabs.data(), b->tabs.size() * sizeof(SolveTab));
-  const SolveTab* dev_tabs = reinterpret_cast<const SolveTab*>(ws + b->off_tabs);
-  BatchInst* bi = reinterpret_cast<BatchInst*>(b->image.data() + b->off_insts);
-  const int S = b->s;
-  for (int i = 0; i < b->ninst; ++i) {
-    BatchInst d{};
-    d.off = b->offsets[i];
-    d.g1 = inst_geom(b, i, 0, group_of(b->g1, b->n1[i]));
-    d.g2 = inst_geom(b, i, 1, group_of(b->g2, b->n2[i]));
-    d.tab1 = dev_tabs + (static_cast<size_t>(i) * 2 + 0) * 3 * S;
-    d.tab2 = dev_tabs + (static_cast<size_t>(i) * 2 + 1) * 3 * S;
-    d.rx.model = b->model;
-    for (int q = 0; q < 16; ++q) d.rx.p[q] = b->inst[i].params[q];
-    for (int q = 0; q < S; ++q) d.rx.shift[q] = b->inst[i].shift[q];
-    bi[i] = d;
+template <int M, int S, typename T>
+hipError_t launch_group_first(const etd_rdp_batch* b, const Group& grp, int form,
+                              const Arrays<T>& a, hipStream_t st) {
+  const PassGeom g = group_geom(b, grp, 0, form);
+  const int64_t o = grp.off;
+  const TabOf<T>* tabs =
+      a.tabs + ((form == kFormTwoLine) ? grp.tab2[0] : grp.tab1[0]);
+  const GroupCoef gc{3 * b->s, a.rxs + grp.rx_index};
+  const Rx rx = b->rxs[grp.rx_index];
+  const T k = static_cast<T>(b->k);
+  const int64_t ntiles = g.nFblk * g.nT;
+  unsigned grid = 0;
+  hipError_t e = hipSuccess;
+  if (form == kFormUnsplit) {
+    constexpr int L = kPassLines<M, T>;
+    if (g.lines != L) return hipErrorInvalidValue;
+    const size_t lds = pass_lds(g, lane_lds<kLanes, T>(3 * S), sizeof(T));
+    e = prepare(kg_first<M, S, L, T>, lds, ntiles, 64 * L, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((kg_first<M, S, L, T>), dim3(grid), dim3(64 * L), lds, st, a.u + o, a.c1 + o,
+                       a.c2 + o, a.w + o, tabs, rx, k, g, b->scheme == ETD_SCHEME_ETD1 ? 1 : 0, gc);
+    return hipGetLastError();
   }
-  for (auto* gs : {&b->g1, &b->g2})
-    for (auto& g : *gs) {
-      std::memcpy(b->image.data() + g.off_tile_inst, g.tile_inst.data(), g.tile_inst.size() * sizeof(int));
-      std::memcpy(b->image.data() + g.off_tile_loc, g.tile_loc.data(), g.tile_loc.size() * sizeof(int));
+  if constexpr (M >= kGroupStreamMinM) {
+    if (form == kFormStreamed) {
+      constexpr int W = kStreamBlockWaves<M, T>, L = W;
+      const size_t lds = pass_lds(g, lane_lds<kLanes, T>(3 * S), sizeof(T));
+      e = prepare(kg_first_s<M, S, L, 1, T>, lds, ntiles, 64 * W, &grid);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((kg_first_s<M, S, L, 1, T>), dim3(grid), dim3(64 * W), lds, st, a.u + o,
+                         a.c1 + o, a.c2 + o, a.w + o, tabs, rx, k, g, gc);
+      return hipGetLastError();
     }
+  }
+  if constexpr (M >= kMinTwoLineM) {
+    if (form == kFormTwoLine) {
+      constexpr int W = kStreamBlockWaves<M, T>, L = 2 * W;
+      const size_t lds = pass_lds(g, lane_lds<32, T>(3 * S), sizeof(T));
+      e = prepare(kg_first_s<M, S, L, 2, T>, lds, ntiles, 64 * W, &grid);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((kg_first_s<M, S, L, 2, T>), dim3(grid), dim3(64 * W), lds, st, a.u + o,
+                         a.c1 + o, a.c2 + o, a.w + o, tabs, rx, k, g, gc);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int M, int S, typename T>
-hipError_t launch_b1(const etd_rdp_batch* b, const Group& g, const T* u, char* ws,
-                     hipStream_t st) {
-  constexpr int L = kLinesFor<M>;
-  hipError_t e = set_lds(kb_first<M, S, L, T>, g.lds);
-  if (e != hipSuccess) return e;
-  unsigned grid;
-  const int64_t nt = static_cast<int64_t>(g.tile_inst.size());
-  e = persistent_grid(kb_first<M, S, L, T>, g.lds, nt, &grid, 64 * L);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((kb_first<M, S, L, T>), dim3(grid), dim3(64 * L), g.lds, st, u,
-                     reinterpret_cast<T*>(ws + b->off_c1), reinterpret_cast<T*>(ws + b->off_c2),
-                     reinterpret_cast<T*>(ws + b->off_w),
-                     reinterpret_cast<const BatchInst*>(ws + b->off_insts),
-                     reinterpret_cast<const int*>(ws + g.off_tile_inst),
-                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, static_cast<T>(b->k),
-                     b->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
-  return hipGetLastError();
+hipError_t launch_group_last(const etd_rdp_batch* b, const Group& grp, int form,
+                             const Arrays<T>& a, hipStream_t st) {
+  const PassGeom g = group_geom(b, grp, 1, form);
+  const int64_t o = grp.off;
+  const TabOf<T>* tabs =
+      a.tabs + ((form == kFormTwoLine) ? grp.tab2[1] : grp.tab1[1]);
+  const GroupCoef gc{3 * b->s, a.rxs + grp.rx_index};
+  const Rx rx = b->rxs[grp.rx_index];
+  const T k = static_cast<T>(b->k);
+  const int etd1 = b->scheme == ETD_SCHEME_ETD1 ? 1 : 0;
+  const int64_t ntiles = g.nFblk * g.nT;
+  unsigned grid = 0;
+  hipError_t e = hipSuccess;
+  if (form == kFormUnsplit) {
+    constexpr int L = kPassLines<M, T>;
+    if (g.lines != L) return hipErrorInvalidValue;
+    const size_t lds = pass_lds(g, lane_lds<kLanes, T>(3 * S), sizeof(T));
+    e = prepare(kg_last<M, S, L, T>, lds, ntiles, 64 * L, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((kg_last<M, S, L, T>), dim3(grid), dim3(64 * L), lds, st, a.u + o, a.c1 + o,
+                       a.c2 + o, a.w + o, tabs, rx, k, g, etd1, gc);
+    return hipGetLastError();
+  }
+  if constexpr (M >= kGroupStreamMinM) {
+    if (form == kFormStreamed) {
+      constexpr int W = kStreamBlockWaves<M, T>, L = W;
+      const size_t lds = pass_lds(g, lane_lds<kLanes, T>(3 * S), sizeof(T));
+      e = prepare(kg_last_s<M, S, L, 1, T>, lds, ntiles, 64 * W, &grid);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((kg_last_s<M, S, L, 1, T>), dim3(grid), dim3(64 * W), lds, st, a.u + o,
+                         a.c1 + o, a.c2 + o, a.w + o, tabs, rx, k, g, etd1, gc);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (M >= kMinTwoLineM) {
+    if (form == kFormTwoLine) {
+      constexpr int W = kStreamBlockWaves<M, T>, L = 2 * W;
+      const size_t lds = pass_lds(g, lane_lds<32, T>(3 * S), sizeof(T));
+      e = prepare(kg_last_s<M, S, L, 2, T>, lds, ntiles, 64 * W, &grid);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((kg_last_s<M, S, L, 2, T>), dim3(grid), dim3(64 * W), lds, st, a.u + o,
+                         a.c1 + o, a.c2 + o, a.w + o, tabs, rx, k, g, etd1, gc);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
-template <int M, int S, typename T>
-hipError_t launch_b2(const etd_rdp_batch* b, const Group& g, T* u, char* ws, hipStream_t st) {
-  constexpr int L = kLastLines<M, T>;
-  if (g.lines != L) return hipErrorInvalidValue;  // the tile map assumes L lines per tile
-  hipError_t e = set_lds(kb_last<M, S, L, T>, g.lds);
-  if (e != hipSuccess) return e;
-  unsigned grid;
-  const int64_t nt = static_cast<int64_t>(g.tile_inst.size());
-  e = persistent_grid(kb_last<M, S, L, T>, g.lds, nt, &grid, 64 * L);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((kb_last<M, S, L, T>), dim3(grid), dim3(64 * L), g.lds, st, u,
-                     reinterpret_cast<const T*>(ws + b->off_c1),
-                     reinterpret_cast<const T*>(ws + b->off_c2),
-                     reinterpret_cast<const T*>(ws + b->off_w),
-                     reinterpret_cast<const BatchInst*>(ws + b->off_insts),
-                     reinterpret_cast<const int*>(ws + g.off_tile_inst),
-                     reinterpret_cast<const int*>(ws + g.off_tile_loc), nt, static_cast<T>(b->k),
-                     b->scheme == ETD_SCHEME_ETD1 ? 1 : 0);
-  return hipGetLastError();
+template <typename T>
+Arrays<T> arrays_of(const etd_rdp_batch* b, T* u, char* ws) {
+  return Arrays<T>{u, reinterpret_cast<T*>(ws + b->off_c1), reinterpret_cast<T*>(ws + b->off_c2),
+                   reinterpret_cast<T*>(ws + b->off_w),
+                   reinterpret_cast<const SolveTab*>(ws + b->off_tabs),
+                   reinterpret_cast<const Rx*>(ws + b->off_rx)};
+}
+
+// One launch: pass `pass` of group `gi` in form `form`.
+template <typename T>
+int launch_group(etd_rdp_batch* b, int gi, int pass, int form, T* u, char* ws, hipStream_t st) {
+  const Group& g = b->groups[gi];
+  if (!form_allowed(b, g, pass, form)) return ETD_ERR_ARG;
+  const Arrays<T> a = arrays_of(b, u, ws);
+  const int m = (form == kFormTwoLine) ? g.m2[pass] : g.m1[pass];
+  hipError_t e = hipSuccess;
+  if (pass == 0) {
+    if (b->s == 1) { ETD_DISPATCH_M(m, e = (launch_group_first<M_, 1, T>(b, g, form, a, st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_group_first<M_, 2, T>(b, g, form, a, st))); }
+  } else {
+    if (b->s == 1) { ETD_DISPATCH_M(m, e = (launch_group_last<M_, 1, T>(b, g, form, a, st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_group_last<M_, 2, T>(b, g, form, a, st))); }
+  }
+  if (e != hipSuccess) {
+    b->last_hip = e;
+    return ETD_ERR_HIP;
+  }
+  return ETD_OK;
 }
 
 template <typename T>
 int batch_one_step(etd_rdp_batch* b, T* u, char* ws, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  for (const Group& g : b->g1) {
-    if (b->s == 1) { ETD_DISPATCH_M(g.m, e = (launch_b1<M_, 1, T>(b, g, u, ws, st))); }
-    else { ETD_DISPATCH_M(g.m, e = (launch_b1<M_, 2, T>(b, g, u, ws, st))); }
-    if (e != hipSuccess) { b->last_hip = e; return ETD_ERR_HIP; }
-  }
-  for (const Group& g : b->g2) {
-    if (b->s == 1) { ETD_DISPATCH_M(g.m, e = (launch_b2<M_, 1, T>(b, g, u, ws, st))); }
-    else { ETD_DISPATCH_M(g.m, e = (launch_b2<M_, 2, T>(b, g, u, ws, st))); }
-    if (e != hipSuccess) { b->last_hip = e; return ETD_ERR_HIP; }
-  }
+  const int ng = static_cast<int>(b->groups.size());
+  for (int pass = 0; pass < 2; ++pass)
+    for (int gi = 0; gi < ng; ++gi) {
+      const int rc = launch_group(b, gi, pass, b->groups[gi].form[pass], u, ws, st);
+      if (rc) return rc;
+    }
   return ETD_OK;
 }
 
 void drop_graph(etd_rdp_batch* b) {
   if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
   b->graph = GraphCache{};
+}
+
+// The static front of the workspace: tables and reaction records.
+int upload(etd_rdp_batch* b, void* ws, hipStream_t st) {
+  if (b->uploaded_ws == ws) return ETD_OK;
+  char* w = static_cast<char*>(ws);
+  hipError_t e = hipMemcpyAsync(w + b->off_tabs, b->tabs.data(), b->tabs.size() * sizeof(SolveTab),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(w + b->off_rx, b->rxs.data(), b->rxs.size() * sizeof(Rx), hipMemcpyHostToDevice,
+                       st);
+  if (e != hipSuccess) {
+    b->last_hip = e;
+    return ETD_ERR_HIP;
+  }
+  b->uploaded_ws = ws;
+  drop_graph(b);
+  return ETD_OK;
+}
+
+bool add_tables(etd_rdp_batch* b, const Group& g, int axis, int m, size_t* first) {
+  static const double gam[3] = {1.0, 3.0, 4.0};
+  *first = b->tabs.size();
+  const int S = b->s;
+  for (int id : g.inst) {
+    const etd_instance_t& I = b->inst[id];
+    const int64_t n = axis == 0 ? g.n1 : g.n2;
+    const int bc = I.bc[axis];
+    double h = I.h[axis];
+    if (h == 0.0) h = bc == ETD_BC_DIRICHLET ? 1.0 / (n + 1) : (bc == ETD_BC_NEUMANN ? 1.0 / (n - 1) : 1.0 / n);
+    for (int q = 0; q < S; ++q)
+      for (int gi = 0; gi < 3; ++gi) {
+        SolveTab t;
+        std::string err;
+        if (!build_solve_table(n, bc, h, b->k * I.D[q] / gam[gi], m, &t, &err)) {
+          std::fprintf(stderr, "etd_rdp_batch_init: instance %d axis %d: %s\n", id, axis + 1, err.c_str());
+          return false;
+        }
+        b->tabs.push_back(t);
+      }
+  }
+  return true;
 }
 
 }  // namespace
@@ -450,6 +428,24 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s, int
   const int prec = scheme ? scheme->precision : ETD_PRECISION_F64;
   if (prec != ETD_PRECISION_F64 && prec != ETD_PRECISION_F32) return ETD_ERR_UNSUPPORTED;
   if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
+  // validate every instance first
+  for (int i = 0; i < ninst; ++i) {
+    const etd_instance_t& I = inst[i];
+    for (int a = 0; a < 2; ++a) {
+      const int bc = I.bc[a];
+      const int64_t n = I.n[a];
+      if (bc < 0 || bc > 2) return ETD_ERR_ARG;
+      const int64_t nmin = bc == ETD_BC_DIRICHLET ? 1 : (bc == ETD_BC_NEUMANN ? 2 : 3);
+      if (n < nmin) return ETD_ERR_ARG;
+      const double h = I.h[a];
+      if (!(std::isfinite(h) && h >= 0)) return ETD_ERR_ARG;
+    }
+    for (int q = 0; q < s; ++q)
+      if (!(std::isfinite(I.D[q]) && I.D[q] >= 0) || !std::isfinite(I.shift[q])) return ETD_ERR_ARG;
+    for (int q = 0; q < ETD_MAX_PARAMS; ++q)
+      if (!std::isfinite(I.params[q])) return ETD_ERR_ARG;
+    if (choose_chunk(I.n[0]) == 0 || choose_chunk(I.n[1]) == 0) return ETD_ERR_UNSUPPORTED;
+  }
   etd_rdp_batch* b = new (std::nothrow) etd_rdp_batch();
   if (!b) return ETD_ERR_INTERNAL;
   b->ninst = ninst;
@@ -459,68 +455,58 @@ int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s, int
   b->scheme = sch;
   b->precision = prec;
   b->inst.assign(inst, inst + ninst);
-  b->offsets.push_back(0);
-  const double gam[3] = {1.0, 3.0, 4.0};
-  b->tabs.resize(static_cast<size_t>(ninst) * 2 * 3 * s);
+  // groups by grid shape, in order of first appearance
+  std::map<std::pair<int64_t, int64_t>, int> gid;
   for (int i = 0; i < ninst; ++i) {
-    const etd_instance_t& I = inst[i];
-    int64_t nn[2];
-    double hh[2];
-    for (int a = 0; a < 2; ++a) {
-      const int bc = I.bc[a];
-      const int64_t n = I.n[a];
-      if (bc < 0 || bc > 2) { delete b; return ETD_ERR_ARG; }
-      const int64_t nmin = bc == ETD_BC_DIRICHLET ? 1 : (bc == ETD_BC_NEUMANN ? 2 : 3);
-      if (n < nmin) { delete b; return ETD_ERR_ARG; }
-      double h = I.h[a];
-      if (h == 0.0) h = bc == ETD_BC_DIRICHLET ? 1.0 / (n + 1) : (bc == ETD_BC_NEUMANN ? 1.0 / (n - 1) : 1.0 / n);
-      if (!(std::isfinite(h) && h > 0)) { delete b; return ETD_ERR_ARG; }
-      if (choose_chunk(n) == 0) { delete b; return ETD_ERR_UNSUPPORTED; }
-      nn[a] = n;
-      hh[a] = h;
+    const auto key = std::make_pair(inst[i].n[0], inst[i].n[1]);
+    auto it = gid.find(key);
+    if (it == gid.end()) {
+      it = gid.emplace(key, static_cast<int>(b->groups.size())).first;
+      Group g;
+      g.n1 = key.first;
+      g.n2 = key.second;
+      b->groups.push_back(g);
     }
-    for (int q = 0; q < s; ++q)
-      if (!(std::isfinite(I.D[q]) && I.D[q] >= 0) || !std::isfinite(I.shift[q])) { delete b; return ETD_ERR_ARG; }
-    for (int q = 0; q < ETD_MAX_PARAMS; ++q)
-      if (!std::isfinite(I.params[q])) { delete b; return ETD_ERR_ARG; }
-    b->n1.push_back(nn[0]);
-    b->n2.push_back(nn[1]);
-    b->h1.push_back(hh[0]);
-    b->h2.push_back(hh[1]);
-    const int64_t len = static_cast<int64_t>(round_up(static_cast<size_t>(nn[0] * nn[1] * s), 32));
-    b->offsets.push_back(b->offsets.back() + len);
-    for (int a = 0; a < 2; ++a)
-      for (int q = 0; q < s; ++q)
-        for (int gi = 0; gi < 3; ++gi) {
-          std::string err;
-          SolveTab& t = b->tabs[((static_cast<size_t>(i) * 2 + a) * s + q) * 3 + gi];
-          if (!build_solve_table(nn[a], I.bc[a], hh[a], k * I.D[q] / gam[gi], choose_chunk(nn[a]), &t, &err)) {
-            std::fprintf(stderr, "etd_rdp_batch_init: instance %d axis %d: %s\n", i, a + 1, err.c_str());
-            delete b;
-            return ETD_ERR_INTERNAL;
-          }
-        }
+    b->groups[it->second].inst.push_back(i);
   }
-  build_groups(b, 0, b->g1);
-  build_groups(b, 1, b->g2);
-  size_t off = 0;
-  b->off_tabs = off;
-  off = round_up(off + b->tabs.size() * sizeof(SolveTab), 256);
-  b->off_insts = off;
-  off = round_up(off + sizeof(BatchInst) * ninst, 256);
-  b->off_maps = off;
-  for (auto* gs : {&b->g1, &b->g2})
-    for (auto& g : *gs) {
-      g.off_tile_inst = off;
-      off = round_up(off + sizeof(int) * g.tile_inst.size(), 256);
-      g.off_tile_loc = off;
-      off = round_up(off + sizeof(int) * g.tile_loc.size(), 256);
+  b->offsets.assign(ninst + 1, 0);
+  int64_t off = 0;
+  for (Group& g : b->groups) {
+    g.stride = static_cast<int64_t>(round_up(static_cast<size_t>(g.n1 * g.n2 * s), 32));
+    g.off = off;
+    for (size_t t = 0; t < g.inst.size(); ++t) b->offsets[g.inst[t]] = off + static_cast<int64_t>(t) * g.stride;
+    off += g.stride * static_cast<int64_t>(g.inst.size());
+    const int64_t ns[2] = {g.n1, g.n2};
+    for (int a = 0; a < 2; ++a) {
+      g.m1[a] = choose_chunk(ns[a]);
+      g.m2[a] = (prec == ETD_PRECISION_F64 || prec == ETD_PRECISION_F32) ? two_line_chunk(ns[a]) : 0;
+      if (!add_tables(b, g, a, g.m1[a], &g.tab1[a])) { delete b; return ETD_ERR_INTERNAL; }
+      if (g.m2[a] && !add_tables(b, g, a, g.m2[a], &g.tab2[a])) { delete b; return ETD_ERR_INTERNAL; }
     }
-  b->arr_bytes = round_up(elem_bytes(b) * static_cast<size_t>(b->offsets.back()), 256);
-  b->off_c1 = off;
-  b->off_c2 = off + b->arr_bytes;
-  b->off_w = off + 2 * b->arr_bytes;
-  b->ws_bytes = off + 3 * b->arr_bytes;
+    g.rx_index = b->rxs.size();
+    for (int id : g.inst) {
+      Rx r{};
+      r.model = model;
+      for (int q = 0; q < 16; ++q) r.p[q] = inst[id].params[q];
+      for (int q = 0; q < s; ++q) r.shift[q] = inst[id].shift[q];
+      b->rxs.push_back(r);
+    }
+  }
+  b->total = off;
+  b->offsets[ninst] = off;
+  for (Group& g : b->groups)
+    for (int p = 0; p < 2; ++p) g.form[p] = default_form(b, g, p);
+  size_t o = 0;
+  b->off_tabs = o;
+  o = round_up(o + b->tabs.size() * sizeof(SolveTab), 256);
+  b->off_rx = o;
+  o = round_up(o + b->rxs.size() * sizeof(Rx), 256);
+  b->image_bytes = o;
+  b->arr_bytes = round_up(elem_bytes(b) * static_cast<size_t>(b->total), 256);
+  b->off_c1 = o;
+  b->off_c2 = o + b->arr_bytes;
+  b->off_w = o + 2 * b->arr_bytes;
+  b->ws_bytes = o + 3 * b->arr_bytes;
   *out = b;
   return ETD_OK;
 }
@@ -554,7 +540,50 @@ int etd_rdp_batch_forget_workspace(etd_rdp_batch* b) {
 
 int etd_rdp_batch_launches_per_step(const etd_rdp_batch* b, int32_t* n) {
   if (!b || !n) return ETD_ERR_ARG;
-  *n = static_cast<int32_t>(b->g1.size() + b->g2.size());
+  *n = static_cast<int32_t>(2 * b->groups.size());
+  return ETD_OK;
+}
+
+int etd_rdp_batch_groups(const etd_rdp_batch* b, int32_t* ngroups, int64_t* shapes,
+                         int32_t* counts) {
+  if (!b || !ngroups) return ETD_ERR_ARG;
+  *ngroups = static_cast<int32_t>(b->groups.size());
+  for (size_t i = 0; i < b->groups.size(); ++i) {
+    if (shapes) {
+      shapes[2 * i] = b->groups[i].n1;
+      shapes[2 * i + 1] = b->groups[i].n2;
+    }
+    if (counts) counts[i] = static_cast<int32_t>(b->groups[i].inst.size());
+  }
+  return ETD_OK;
+}
+
+int etd_rdp_batch_get_plan(const etd_rdp_batch* b, int32_t* plan) {
+  if (!b || !plan) return ETD_ERR_ARG;
+  for (size_t i = 0; i < b->groups.size(); ++i)
+    for (int p = 0; p < 2; ++p) plan[2 * i + p] = b->groups[i].form[p];
+  return ETD_OK;
+}
+
+int etd_rdp_batch_set_plan(etd_rdp_batch* b, const int32_t* plan) {
+  if (!b || !plan) return ETD_ERR_ARG;
+  for (size_t i = 0; i < b->groups.size(); ++i)
+    for (int p = 0; p < 2; ++p) {
+      const int f = plan[2 * i + p];
+      if (f < 0 || f >= kNumForms || !form_allowed(b, b->groups[i], p, f)) return ETD_ERR_ARG;
+    }
+  for (size_t i = 0; i < b->groups.size(); ++i)
+    for (int p = 0; p < 2; ++p) b->groups[i].form[p] = plan[2 * i + p];
+  drop_graph(b);
+  return ETD_OK;
+}
+
+int etd_rdp_batch_form_allowed(const etd_rdp_batch* b, int32_t group, int32_t pass, int32_t form,
+                               int32_t* allowed) {
+  if (!b || !allowed || group < 0 || group >= static_cast<int32_t>(b->groups.size()) || pass < 0 ||
+      pass > 1 || form < 0 || form >= kNumForms)
+    return ETD_ERR_ARG;
+  *allowed = form_allowed(b, b->groups[group], pass, form) ? 1 : 0;
   return ETD_OK;
 }
 
@@ -571,16 +600,11 @@ int batch_step_impl(etd_rdp_batch* b, T* u, void* ws, size_t ws_bytes, int64_t n
   if (nsteps == 0) return ETD_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (b->uploaded_ws != ws) {
-    build_image(b, w);
-    hipError_t e = hipMemcpyAsync(ws, b->image.data(), b->image.size(), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) { b->last_hip = e; return ETD_ERR_HIP; }
-    b->uploaded_ws = ws;
-    drop_graph(b);
-  }
+  int rc = upload(b, ws, st);
+  if (rc) return rc;
   if (!use_graph) {
     for (int64_t i = 0; i < nsteps; ++i) {
-      const int rc = batch_one_step(b, u, w, st);
+      rc = batch_one_step(b, u, w, st);
       if (rc) return rc;
     }
     return ETD_OK;
@@ -594,7 +618,7 @@ int batch_step_impl(etd_rdp_batch* b, T* u, void* ws, size_t ws_bytes, int64_t n
     }
     e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { b->last_hip = e; return ETD_ERR_HIP; }
-    int rc = ETD_OK;
+    rc = ETD_OK;
     for (int64_t i = 0; i < nsteps && rc == ETD_OK; ++i) rc = batch_one_step(b, u, w, b->capture);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->capture, &graph);
@@ -615,6 +639,83 @@ int batch_step_impl(etd_rdp_batch* b, T* u, void* ws, size_t ws_bytes, int64_t n
   return ETD_OK;
 }
 
+// Times `reps` launches of one (group, pass, form) on st; ms per launch.
+template <typename T>
+int time_form(etd_rdp_batch* b, int gi, int pass, int form, T* u, char* ws, int reps,
+              hipStream_t st, hipEvent_t e0, hipEvent_t e1, double* ms) {
+  int rc = launch_group(b, gi, pass, form, u, ws, st);  // untimed: first launch of a kernel
+  if (rc) return rc;
+  hipError_t e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && rc == ETD_OK && e == hipSuccess; ++r) rc = launch_group(b, gi, pass, form, u, ws, st);
+  if (rc) return rc;
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e != hipSuccess) {
+    b->last_hip = e;
+    return ETD_ERR_HIP;
+  }
+  *ms = static_cast<double>(t) / reps;
+  return ETD_OK;
+}
+
+template <typename T>
+int batch_tune_impl(etd_rdp_batch* b, T* u, void* ws, size_t ws_bytes, int32_t reps, void* stream,
+                    double* times) {
+  constexpr int kPrec = std::is_same<T, float>::value ? ETD_PRECISION_F32 : ETD_PRECISION_F64;
+  if (!b || !u || reps < 1 || b->precision != kPrec) return ETD_ERR_ARG;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0 || ws_bytes < b->ws_bytes) return ETD_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  int rc = upload(b, ws, st);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    b->last_hip = e;
+    return ETD_ERR_HIP;
+  }
+  const int ng = static_cast<int>(b->groups.size());
+  for (int gi = 0; gi < ng && rc == ETD_OK; ++gi) {
+    for (int pass = 0; pass < 2 && rc == ETD_OK; ++pass) {
+      int best = b->groups[gi].form[pass];
+      double best_ms = 0.0;
+      bool have = false;
+      for (int f = 0; f < kNumForms && rc == ETD_OK; ++f) {
+        double ms = -1.0;
+        if (form_allowed(b, b->groups[gi], pass, f)) {
+          rc = time_form(b, gi, pass, f, u, w, reps, st, e0, e1, &ms);
+          if (rc == ETD_OK && (!have || ms < best_ms)) {
+            best = f;
+            best_ms = ms;
+            have = true;
+          }
+        }
+        if (times) times[(static_cast<size_t>(gi) * 2 + pass) * kNumForms + f] = ms;
+      }
+      if (rc == ETD_OK) {
+        b->groups[gi].form[pass] = best;
+        // leave this pass's output as the chosen form computes it
+        rc = launch_group(b, gi, pass, best, u, w, st);
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop_graph(b);
+  if (rc == ETD_OK) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      b->last_hip = e;
+      return ETD_ERR_HIP;
+    }
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -627,6 +728,28 @@ int etd_rdp_batch_step(etd_rdp_batch* b, double* u, void* ws, size_t ws_bytes, i
 int etd_rdp_batch_step_f32(etd_rdp_batch* b, float* u, void* ws, size_t ws_bytes, int64_t nsteps,
                            int32_t use_graph, void* stream) {
   return batch_step_impl(b, u, ws, ws_bytes, nsteps, use_graph, stream);
+}
+
+int etd_rdp_batch_tune(etd_rdp_batch* b, void* u, void* ws, size_t ws_bytes, int32_t reps,
+                       void* stream, double* times) {
+  if (!b) return ETD_ERR_ARG;
+  if (b->precision == ETD_PRECISION_F32)
+    return batch_tune_impl(b, static_cast<float*>(u), ws, ws_bytes, reps, stream, times);
+  return batch_tune_impl(b, static_cast<double*>(u), ws, ws_bytes, reps, stream, times);
+}
+
+int etd_rdp_batch_group_pass(etd_rdp_batch* b, void* u, void* ws, size_t ws_bytes, int32_t group,
+                             int32_t pass, int32_t form, void* stream) {
+  if (!b || !u || group < 0 || group >= static_cast<int32_t>(b->groups.size()) || pass < 0 || pass > 1)
+    return ETD_ERR_ARG;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 != 0 || ws_bytes < b->ws_bytes) return ETD_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int rc = upload(b, ws, st);
+  if (rc) return rc;
+  const int f = form < 0 ? b->groups[group].form[pass] : form;
+  if (b->precision == ETD_PRECISION_F32)
+    return launch_group(b, group, pass, f, static_cast<float*>(u), static_cast<char*>(ws), st);
+  return launch_group(b, group, pass, f, static_cast<double*>(u), static_cast<char*>(ws), st);
 }
 
 }  // extern "C"

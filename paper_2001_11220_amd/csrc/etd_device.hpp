@@ -462,15 +462,25 @@ __device__ __forceinline__ void line_solve(const TabOf<T>* const (&tab)[K],
 // Persistent-block tile walk.  The dispatcher places block b on XCD b % 8;
 // each XCD's blocks take a contiguous range of tiles, so that neighbouring
 // tiles (which share cache lines at their edges) meet in the same L2.
+// With `contiguous`, each block takes a contiguous run of its XCD's range
+// instead of every per-th tile (ensembles: a block's tiles then mostly belong
+// to one instance, whose tables it stages once).
 struct TileWalk {
   int64_t cur, end, step;
-  __device__ __forceinline__ explicit TileWalk(int64_t ntiles) {
+  __device__ __forceinline__ explicit TileWalk(int64_t ntiles, bool contiguous = false) {
     const int64_t x = blockIdx.x % 8, per = gridDim.x / 8, i = blockIdx.x / 8;
     const int64_t q = ntiles / 8, r = ntiles % 8;
     const int64_t lo = x * q + (x < r ? x : r);
     end = lo + q + (x < r ? 1 : 0);
-    cur = lo + i;
-    step = per;
+    if (contiguous) {
+      const int64_t cnt = end - lo;
+      cur = lo + (cnt * i) / per;
+      end = lo + (cnt * (i + 1)) / per;
+      step = 1;
+    } else {
+      cur = lo + i;
+      step = per;
+    }
   }
   __device__ __forceinline__ bool next(int64_t& tile) {
     if (cur >= end) return false;

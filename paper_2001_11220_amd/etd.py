@@ -101,6 +101,12 @@ def _load():
         "etd_rdp_batch_launches_per_step": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
         "etd_calib_stream": (ctypes.c_int, [I32, P, P, SZ, I32, P]),
         "etd_rdp_forget_workspace": (ctypes.c_int, [P]),
+        "etd_rdp_batch_groups": (ctypes.c_int, [P, ctypes.POINTER(I32), P, P]),
+        "etd_rdp_batch_get_plan": (ctypes.c_int, [P, P]),
+        "etd_rdp_batch_set_plan": (ctypes.c_int, [P, P]),
+        "etd_rdp_batch_form_allowed": (ctypes.c_int, [P, I32, I32, I32, ctypes.POINTER(I32)]),
+        "etd_rdp_batch_tune": (ctypes.c_int, [P, P, P, SZ, I32, P, P]),
+        "etd_rdp_batch_group_pass": (ctypes.c_int, [P, P, P, SZ, I32, I32, I32, P]),
         "etd_rdp_step_static": (ctypes.c_int, [P, P, I64, P]),
         "etd_rdp_set_slab": (ctypes.c_int, [P, I64]),
         "etd_rdp_get_slab": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
@@ -439,6 +445,7 @@ class EtdRdpBatch:
         self._ctx = ctx
         self.n, self.s = n, int(s)
         self.precision = precision
+        self.model, self.scheme = model, scheme
         self.shapes = [tuple(int(v) for v in ins["shape"]) for ins in instances]
         offs = (ctypes.c_int64 * (n + 1))()
         _check(lib.etd_rdp_batch_offsets(ctx, offs), "etd_rdp_batch_offsets")
@@ -472,6 +479,66 @@ class EtdRdpBatch:
         ws = self.workspace()
         p = ws.data_ptr()
         return p + (-p) % 256
+
+    FORMS = ("unsplit", "streamed", "two_line")
+
+    def groups(self):
+        """[(n1, n2, instances)] of the ensemble's groups (instances of one
+        grid shape, one launch per pass each)."""
+        ng = ctypes.c_int32()
+        _check(lib.etd_rdp_batch_groups(self._ctx, ctypes.byref(ng), None, None), "etd_rdp_batch_groups")
+        shapes = (ctypes.c_int64 * (2 * ng.value))()
+        counts = (ctypes.c_int32 * ng.value)()
+        _check(lib.etd_rdp_batch_groups(self._ctx, ctypes.byref(ng), shapes, counts), "etd_rdp_batch_groups")
+        return [(int(shapes[2 * g]), int(shapes[2 * g + 1]), int(counts[g])) for g in range(ng.value)]
+
+    @property
+    def plan(self):
+        """Kernel form of every (group, pass): plan[2 g + p] in ETD_FORM_*."""
+        n = 2 * len(self.groups())
+        arr = (ctypes.c_int32 * n)()
+        _check(lib.etd_rdp_batch_get_plan(self._ctx, arr), "etd_rdp_batch_get_plan")
+        return [int(v) for v in arr]
+
+    @plan.setter
+    def plan(self, plan):
+        arr = (ctypes.c_int32 * len(plan))(*[int(v) for v in plan])
+        if len(plan) != 2 * len(self.groups()):
+            raise ValueError("a plan has two entries per group")
+        _check(lib.etd_rdp_batch_set_plan(self._ctx, arr), "etd_rdp_batch_set_plan")
+
+    def form_allowed(self, group, npass, form):
+        v = ctypes.c_int32()
+        _check(lib.etd_rdp_batch_form_allowed(self._ctx, int(group), int(npass), int(form), ctypes.byref(v)),
+               "etd_rdp_batch_form_allowed")
+        return bool(v.value)
+
+    def tune(self, u, reps=3, stream=None):
+        """Run the library's autotuner on the packed state ``u`` (advanced by
+        one step): every allowed form of every (group, pass) is timed and the
+        fastest kept in the plan.  Returns times[group][pass][form] in ms per
+        launch (None where a form is not allowed)."""
+        import torch
+        if u.dtype != self.dtype or not u.is_cuda or not u.is_contiguous() or u.numel() != self.offsets[-1]:
+            raise ValueError(f"expected the packed contiguous {self.dtype} device state")
+        ng = len(self.groups())
+        times = (ctypes.c_double * (6 * ng))()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib.etd_rdp_batch_tune(self._ctx, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(self._ws_ptr()),
+                                      self.ws_bytes, int(reps), ctypes.c_void_p(st.cuda_stream), times),
+               "etd_rdp_batch_tune")
+        return [[[None if times[(2 * g + p) * 3 + f] < 0 else float(times[(2 * g + p) * 3 + f])
+                  for f in range(3)] for p in range(2)] for g in range(ng)]
+
+    def group_pass(self, u, group, npass, form=-1, stream=None):
+        """Launch one pass of one group alone (pass 0 reads u and writes the
+        carried arrays, pass 1 reads them and writes u)."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib.etd_rdp_batch_group_pass(self._ctx, ctypes.c_void_p(u.data_ptr()),
+                                            ctypes.c_void_p(self._ws_ptr()), self.ws_bytes, int(group),
+                                            int(npass), int(form), ctypes.c_void_p(st.cuda_stream)),
+               "etd_rdp_batch_group_pass")
 
     def forget_workspace(self):
         """The workspace's contents were changed outside the library: the

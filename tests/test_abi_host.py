@@ -371,3 +371,36 @@ def test_batch_precision_option_without_touching_the_gpu():
     ctx = ctypes.c_void_p()
     assert etd.lib.etd_rdp_batch_init(1, arr_t, 1, etd.MODELS["linear"], 0.01, ctypes.byref(sch),
                                       ctypes.byref(ctx)) == etd.ETD_ERR_UNSUPPORTED
+
+
+def test_batch_groups_and_plans_without_touching_the_gpu():
+    """Instances of one grid shape form a group stored at equal spacing; the
+    default plan and set_plan only take forms a (group, pass) allows."""
+    etd = _lib()
+    ins = [dict(shape=(64, 64), bcs=("neumann", "periodic"), D=(0.02, 0.01), params={"a": 1.0, "b": 3.0}),
+           dict(shape=(40, 30), bcs=("periodic", "dirichlet"), D=(0.01, 0.03), params={"a": 1.0, "b": 2.0}),
+           dict(shape=(64, 64), bcs=("dirichlet", "neumann"), D=(0.03, 0.02), params={"a": 1.0, "b": 3.5}),
+           dict(shape=(512, 40), bcs=("neumann", "neumann"), D=(0.01, 0.01), params={"a": 1.0, "b": 2.5})]
+    b = etd.EtdRdpBatch(ins, 2, "brusselator", 0.01)
+    assert b.groups() == [(64, 64, 2), (40, 30, 1), (512, 40, 1)]
+    assert b.launches_per_step == 6
+    off = b.offsets
+    assert off[2] - off[0] == 2 * 64 * 64  # the two 64^2 instances, back to back
+    assert off[-1] == 2 * (2 * 64 * 64) + 2 * 40 * 30 + 2 * 512 * 40
+    assert all(v % 32 == 0 for v in off)
+    # lines of 64 = 32 x 2: every form; 40 and 30 (chunks of 1): unsplit only;
+    # 512 (chunks of 8) on axis 1: unsplit or streamed
+    allowed = {(g, p): [f for f in range(3) if b.form_allowed(g, p, f)] for g in range(3) for p in range(2)}
+    assert allowed[(0, 0)] == [0, 2] and allowed[(0, 1)] == [0, 2]   # 64 = 32 x 2 (m1 = 1)
+    assert allowed[(1, 0)] == [0] and allowed[(1, 1)] == [0]
+    assert allowed[(2, 0)] == [0, 1] and allowed[(2, 1)] == [0]
+    assert b.plan == [0, 0, 0, 0, 1, 0]
+    b.plan = [2, 2, 0, 0, 0, 0]
+    assert b.plan == [2, 2, 0, 0, 0, 0]
+    with pytest.raises(etd.EtdError):
+        b.plan = [1, 0, 0, 0, 0, 0]  # 64: chunks of one row, no streamed form
+    assert b.plan == [2, 2, 0, 0, 0, 0]
+    e1 = etd.EtdRdpBatch(ins, 2, "brusselator", 0.01, scheme="etd1")
+    assert not e1.form_allowed(2, 0, 1) and not e1.form_allowed(0, 0, 2) and e1.form_allowed(0, 1, 2)
+    b.close()
+    e1.close()

@@ -128,23 +128,25 @@ def test_etd1_ensemble_matches_oracle(prec):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_full_size_ensemble_one_step_sampled(prec):
     """The benchmark's ensemble (1024 instances, N = 64..512, recorded into a
-    HIP graph as bench.py runs it): one step, then the first instance of
-    every chunk-length group, the largest instance and the last one against
-    the oracle (FP64: 1e-12; FP32: 1e-5)."""
+    HIP graph as bench.py runs it, with the plan the autotuner picks on the
+    device): one step, then the first and the last instance of every group
+    (grid shape) and the last instance against the oracle (FP64: 1e-12;
+    FP32: 1e-5)."""
     import torch
     from paper_2001_11220_amd.etd import EtdRdpBatch
     ens = W.brusselator_ensemble()
     b = EtdRdpBatch(ens.instances, ens.s, ens.model, ens.k, precision=prec)
+    b.tune(b.pack(ens.states), reps=1)
+    print(f"[full ensemble {prec}] tuned plan {b.plan}", flush=True)
     u = b.pack(ens.states)
     b.step(u, 1, use_graph=True)
     torch.cuda.synchronize()
-    first_of = {}
+    first_of, last_of = {}, {}
     for i, ins in enumerate(ens.instances):
-        n = ins["shape"][0]
-        first_of.setdefault(next(m for m in range(1, 9) if n % m == 0 and n // m <= 64), i)
-    largest = max(range(b.n), key=lambda i: ens.instances[i]["shape"][0])
-    sample = sorted(set(first_of.values()) | {largest, b.n - 1})
-    assert len(first_of) == 8 and b.launches_per_step == 16
+        first_of.setdefault(tuple(ins["shape"]), i)
+        last_of[tuple(ins["shape"])] = i
+    sample = sorted(set(first_of.values()) | set(last_of.values()) | {b.n - 1})
+    assert len(first_of) == 15 and b.launches_per_step == 30
     worst = 0.0
     for i in sample:
         ins = ens.instances[i]
