@@ -344,6 +344,26 @@ int etd_rdp_forget_workspace(etd_rdp_ctx* ctx);
 int etd_rdp_set_slab(etd_rdp_ctx* ctx, int64_t planes);
 int etd_rdp_get_slab(const etd_rdp_ctx* ctx, int64_t* planes);
 
+/*
+ * etd_rdp_set_graph -- on = 1: etd_rdp_step (and _f32, _z) records the
+ * launches of its nsteps steps into a HIP graph, on a private capture
+ * stream, and launches the graph on the caller's stream; the graph is kept
+ * and replayed while (u, ws, nsteps) stay the same (a new triple records a
+ * new one).  Removes the per-launch host overhead of small problems; the
+ * results are the same bit for bit.  on = 0 (the default) launches the
+ * kernels one by one.  A recorded graph holds the workspace address: after
+ * freeing that buffer call etd_rdp_forget_workspace, which also drops the
+ * graph.  Errors: ETD_ERR_ARG (NULL, on not 0 or 1).
+ */
+int etd_rdp_set_graph(etd_rdp_ctx* ctx, int32_t on);
+
+/* Record the graph of nsteps steps on (u, ws) without running it (graph
+ * mode only), so that the next etd_rdp_step with the same arguments only
+ * replays it.  The tables must already be in ws (a step on ws uploads
+ * them).  Errors: ETD_ERR_ARG (NULL, nsteps < 1, graph mode off),
+ * ETD_ERR_WORKSPACE, ETD_ERR_HIP. */
+int etd_rdp_record_graph(etd_rdp_ctx* ctx, void* u, void* ws, size_t ws_bytes, int64_t nsteps);
+
 /* Human-readable text of a status code (static storage). */
 const char* etd_rdp_status_string(int status);
 

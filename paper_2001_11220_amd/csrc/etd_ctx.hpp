@@ -47,6 +47,15 @@ struct etd_rdp_ctx {
   // launch is restricted to planes [slab_z0, slab_z0 + slab_nz).
   int64_t slab_planes = 0;
   int64_t slab_z0 = 0, slab_nz = 0;
+  // Graph mode (etd_rdp_set_graph): etd_rdp_step records its launches into
+  // a HIP graph on a private capture stream and replays it while (u, ws,
+  // nsteps) stay the same.
+  bool use_graph = false;
+  hipGraphExec_t graph = nullptr;
+  const void* graph_u = nullptr;
+  const void* graph_ws = nullptr;
+  int64_t graph_nsteps = -1;
+  hipStream_t capture = nullptr;
 };
 
 namespace etd {

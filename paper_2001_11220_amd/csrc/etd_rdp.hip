@@ -849,6 +849,46 @@ int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream
 
 namespace etd {
 namespace {
+void drop_graph(etd_rdp_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_u = nullptr;
+  c->graph_ws = nullptr;
+  c->graph_nsteps = -1;
+}
+
+// Records nsteps steps into the context's graph (private capture stream).
+template <typename T>
+int record_graph(etd_rdp_ctx* ctx, T* u, void* ws, int64_t nsteps) {
+  drop_graph(ctx);
+  hipError_t e = hipSuccess;
+  if (!ctx->capture) {
+    e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+  }
+  e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  int rc = ETD_OK;
+  for (int64_t i = 0; i < nsteps && rc == ETD_OK; ++i) rc = run_passes(ctx, u, ws, 0, ctx->d, ctx->capture);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(ctx->capture, &g);
+  if (rc != ETD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ctx->graph = nullptr;
+    return hip_fail(ctx, e);
+  }
+  ctx->graph_u = u;
+  ctx->graph_ws = ws;
+  ctx->graph_nsteps = nsteps;
+  return ETD_OK;
+}
+
 template <typename T>
 int step_impl(etd_rdp_ctx* ctx, T* u, void* ws, size_t ws_bytes, int64_t nsteps, void* stream) {
   if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;
@@ -860,6 +900,15 @@ int step_impl(etd_rdp_ctx* ctx, T* u, void* ws, size_t ws_bytes, int64_t nsteps,
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = ensure_tables(ctx, ws, st);
   if (rc) return rc;
+  if (ctx->use_graph) {
+    if (!(ctx->graph && ctx->graph_u == u && ctx->graph_ws == ws && ctx->graph_nsteps == nsteps)) {
+      rc = record_graph(ctx, u, ws, nsteps);
+      if (rc) return rc;
+    }
+    const hipError_t e = hipGraphLaunch(ctx->graph, st);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    return ETD_OK;
+  }
   for (int64_t i = 0; i < nsteps; ++i) {
     rc = run_passes(ctx, u, ws, 0, ctx->d, st);
     if (rc) return rc;
@@ -1085,6 +1134,9 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
 }
 
 int etd_rdp_destroy(etd_rdp_ctx* ctx) {
+  if (!ctx) return ETD_OK;
+  drop_graph(ctx);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
   return ETD_OK;
 }
@@ -1224,6 +1276,24 @@ int etd_rdp_set_slab(etd_rdp_ctx* ctx, int64_t planes) {
   if (!ctx || planes < 0) return ETD_ERR_ARG;
   if (planes > 0 && ctx->d != 3) return ETD_ERR_UNSUPPORTED;
   ctx->slab_planes = (planes >= ctx->n[2]) ? 0 : planes;
+  drop_graph(ctx);
+  return ETD_OK;
+}
+
+int etd_rdp_record_graph(etd_rdp_ctx* ctx, void* u, void* ws, size_t ws_bytes, int64_t nsteps) {
+  if (!ctx || !u || nsteps < 1 || !ctx->use_graph) return ETD_ERR_ARG;
+  if (ctx->has_field && ctx->field_ws != ws) return ETD_ERR_ARG;
+  const int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
+  if (rc) return rc;
+  if (ctx->precision == ETD_PRECISION_F32) return record_graph(ctx, static_cast<float*>(u), ws, nsteps);
+  if (ctx->precision == ETD_PRECISION_C128) return record_graph(ctx, static_cast<zd*>(u), ws, nsteps);
+  return record_graph(ctx, static_cast<double*>(u), ws, nsteps);
+}
+
+int etd_rdp_set_graph(etd_rdp_ctx* ctx, int32_t on) {
+  if (!ctx || (on != 0 && on != 1)) return ETD_ERR_ARG;
+  ctx->use_graph = (on == 1);
+  if (!ctx->use_graph) drop_graph(ctx);
   return ETD_OK;
 }
 
@@ -1237,6 +1307,7 @@ int etd_rdp_forget_workspace(etd_rdp_ctx* ctx) {
   if (!ctx) return ETD_ERR_ARG;
   ctx->uploaded_ws = nullptr;
   ctx->field_ws = nullptr;
+  drop_graph(ctx);
   return ETD_OK;
 }
 

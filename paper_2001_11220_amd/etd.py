@@ -109,6 +109,8 @@ def _load():
         "etd_rdp_batch_group_pass": (ctypes.c_int, [P, P, P, SZ, I32, I32, I32, P]),
         "etd_rdp_step_static": (ctypes.c_int, [P, P, I64, P]),
         "etd_rdp_set_slab": (ctypes.c_int, [P, I64]),
+        "etd_rdp_set_graph": (ctypes.c_int, [P, I32]),
+        "etd_rdp_record_graph": (ctypes.c_int, [P, P, P, SZ, I64]),
         "etd_rdp_get_slab": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "etd_rdp_batch_forget_workspace": (ctypes.c_int, [P]),
     }
@@ -340,6 +342,17 @@ class EtdRdp:
     @slab.setter
     def slab(self, planes):
         _check(lib.etd_rdp_set_slab(self._ctx, int(planes)), "etd_rdp_set_slab")
+
+    def use_graph(self, on=True):
+        """Record step() calls into a HIP graph, replayed while (u, workspace,
+        nsteps) repeat (etd_rdp_set_graph)."""
+        _check(lib.etd_rdp_set_graph(self._ctx, 1 if on else 0), "etd_rdp_set_graph")
+
+    def record_graph(self, u, nsteps):
+        """Record (without running) the graph that step(u, nsteps) replays."""
+        p = self._state_ptr(u, self.s, self._elem_dtype())
+        _check(lib.etd_rdp_record_graph(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                                        self.ws_bytes, int(nsteps)), "etd_rdp_record_graph")
 
     def step_static(self, u, nsteps=1, stream=None):
         """``step`` with the library's own per-device workspace
