@@ -106,7 +106,16 @@ typedef struct etd_reaction_t {
   double shift[ETD_MAX_SPECIES];    /* F evaluated at u + shift              */
 } etd_reaction_t;
 
-/* Lines per wavefront of the forward passes (etd_scheme_t.lines_per_wave).
+/* Line lengths.  A line of n rows is cut into at most 64 chunks solved by
+ * the lanes of one wavefront.  Where some m <= 8 divides n with n/m <= 64
+ * the chunks are equal ("regular" lines).  Any other n <= 1024 (n prime or
+ * with no such divisor, or n > 512) is a "general" line: m = ceil(n/64)
+ * rows per chunk, C = ceil(n/m) chunks, the last one shorter when m does
+ * not divide n.  The forward step runs general lines with kernels of their
+ * own (one line per wavefront); the reverse-mode step, the single solves
+ * and the ensembles take regular lines only.
+ *
+ * Lines per wavefront of the forward passes (etd_scheme_t.lines_per_wave).
  * A wavefront solves one grid line with up to 64 chunks, or two lines of
  * 32 chunks each when the line length is n = 32 m with 2 <= m <= 8 (fewer
  * cross-lane reduction levels per line, 32-line tiles).  Results agree with
@@ -161,9 +170,8 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  * n below the minimum of its BC (Dirichlet 1, Neumann 2, periodic 3), a
  * non-finite or non-positive h or k, a negative or non-finite D, an unknown
  * model or one whose species count differs from s, lines_per_wave not one of
- * ETD_LINES_*, precision not one of ETD_PRECISION_*.  ETD_ERR_UNSUPPORTED when
- * a line length n cannot be split into at most 64 chunks of at most 8 rows
- * (n > 512, or n > 64 with no divisor m <= 8 such that n/m <= 64).
+ * ETD_LINES_*, precision not one of ETD_PRECISION_*.  ETD_ERR_UNSUPPORTED for
+ * a line length n > 1024 (longer than 64 chunks of 16 rows).
  * ETD_ERR_INTERNAL if a table self-check fails.
  */
 int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D,
@@ -311,7 +319,8 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
  * single-species grid array x of N doubles (layout as one species of u),
  * gamma = 1, 3 or 4 (Section 7: the systems the scheme solves).  axis is
  * 1-based.  Exposes the line solver alone for testing.  FP64 contexts with
- * d <= 3 only (ETD_ERR_UNSUPPORTED otherwise).
+ * d <= 3 and a regular line length on the axis only (ETD_ERR_UNSUPPORTED
+ * otherwise).
  */
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes,
                         int32_t axis, int32_t sigma, int32_t gamma,
@@ -378,8 +387,8 @@ int etd_rdp_last_hip_error(const etd_rdp_ctx* ctx);
 int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name,
                         size_t size);
 
-/* Chunk length m and chunk count C = n/m the line solver uses on an axis
- * (1-based); for tests and tuning. */
+/* Chunk length m and chunk count C = ceil(n/m) the line solver uses on an
+ * axis (1-based); for tests and tuning. */
 int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m,
                        int32_t* chunks);
 
@@ -423,7 +432,8 @@ int etd_rdp_adjoint_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * The result is bitwise reproducible for a given device (fixed reduction
  * order).  Asynchronous on `stream`.
  * Errors: ETD_ERR_ARG (NULL pointer, u_n == lam_n), ETD_ERR_UNSUPPORTED
- * (scheme ETD1, d = 1 or 4, FP32 or complex contexts), ETD_ERR_WORKSPACE,
+ * (scheme ETD1, d = 1 or 4, FP32 or complex contexts, a general line length
+ * on some axis), ETD_ERR_WORKSPACE,
  * ETD_ERR_HIP.
  */
 int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1,
@@ -457,7 +467,8 @@ typedef struct etd_rdp_batch etd_rdp_batch;
  * obeys etd_rdp_init's rules for d = 2.  scheme (may be NULL: ETD-RDP, FP64)
  * selects ETD_SCHEME_RDP or ETD_SCHEME_ETD1 and ETD_PRECISION_F64 or
  * ETD_PRECISION_F32 (complex: ETD_ERR_UNSUPPORTED); its other fields are
- * ignored.  Errors as etd_rdp_init.
+ * ignored.  Errors as etd_rdp_init; ETD_ERR_UNSUPPORTED also for an instance
+ * with a general line length (regular lines only).
  */
 int etd_rdp_batch_init(int32_t ninst, const etd_instance_t* inst, int32_t s,
                        int32_t model, double k, const etd_scheme_t* scheme,

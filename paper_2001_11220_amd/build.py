@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libetdrdp.so")
 
-SOURCES = ["etd_rdp.hip", "etd_adjoint.hip", "etd_batch.hip", "etd_tables.cpp", "etd_calib.hip"]
+SOURCES = ["etd_rdp.hip", "etd_general.hip", "etd_adjoint.hip", "etd_batch.hip", "etd_tables.cpp",
+           "etd_calib.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

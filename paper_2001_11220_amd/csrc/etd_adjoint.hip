@@ -758,7 +758,7 @@ int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1, 
   if (!ctx || !u_n || !lam_np1 || !lam_n || !grad) return ETD_ERR_ARG;
   if (u_n == lam_n) return ETD_ERR_ARG;
   if (ctx->scheme != ETD_SCHEME_RDP || ctx->precision != ETD_PRECISION_F64 || ctx->d > 3 ||
-      ctx->d < 2)
+      ctx->d < 2 || has_general_axis(ctx))
     return ETD_ERR_UNSUPPORTED;
   int rc = check_ws(ws, ws_bytes, ctx->adj_ws_bytes);
   if (rc) return rc;

@@ -27,6 +27,10 @@ struct etd_rdp_ctx {
   int m[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length of the forward passes' tables
   int P[ETD_MAX_DIM] = {1, 1, 1, 1};  // lines per wavefront of the forward passes
   int m1[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length with one line per wavefront
+  // 1 on an axis whose lines have no chunking into <= 64 equal chunks of
+  // <= kMaxRegularM rows: general_chunk's m, the last chunk possibly shorter,
+  // run by the general pass kernels (etd_general.hip).
+  int gen[ETD_MAX_DIM] = {0, 0, 0, 0};
   int64_t N = 0;
   // [axis][species][3] for the forward passes; when some axis runs two lines
   // per wavefront, a second set with one line per wavefront follows at index
@@ -78,7 +82,7 @@ constexpr int kMinTwoLineM = 2;
 constexpr int64_t kTwoLineMinLines = 32768;
 inline int two_line_chunk(int64_t n) {
   const int64_t m = n / 32;
-  return (n % 32 == 0 && m >= kMinTwoLineM && m <= kMaxM) ? static_cast<int>(m) : 0;
+  return (n % 32 == 0 && m >= kMinTwoLineM && m <= kMaxRegularM) ? static_cast<int>(m) : 0;
 }
 
 // Reverse-mode step: gradient slots per block (s diffusion coefficients, then
@@ -128,5 +132,28 @@ inline T* ws_array(const etd_rdp_ctx* c, void* ws, int i) {
 template <typename T>
 int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[3],
                 const TabOf<T>* tabs, hipStream_t st);
+
+// Forward pass p on a general axis (c->gen[p]): pass 0 (d > 1) reads u and
+// writes out[0..2]; a middle pass reads in[] and writes out[]; the last pass
+// reads c1 and lin[1], lin[2] and writes u.  tabs: the pass's tables.
+template <typename T>
+hipError_t launch_general(const etd_rdp_ctx* c, int p, T* u, const T* c1, T* const (&lin)[3],
+                          T* const (&in)[3], T* const (&out)[3], const TabOf<T>* tabs,
+                          hipStream_t st);
+
+// Slot capacity (4, 8 or 16) of the general kernels that run chunks of m
+// rows; 0 for m outside [1, kMaxM].
+int general_capacity(int m);
+
+// Kernel name of general pass p (see etd_rdp_pass_kernel); 0 on success, -1
+// if name[0..size) is too small.
+int general_kernel_name(const etd_rdp_ctx* c, int p, char* name, size_t size);
+
+// True if some axis of the context is general (the forward step only).
+inline bool has_general_axis(const etd_rdp_ctx* c) {
+  for (int a = 0; a < c->d; ++a)
+    if (c->gen[a]) return true;
+  return false;
+}
 
 }  // namespace etd

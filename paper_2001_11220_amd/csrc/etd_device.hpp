@@ -323,7 +323,17 @@ __device__ __forceinline__ void stage_lane_tabs(const TabOf<T>* __restrict__ tab
 // data in LDS, indexed by the lane's chunk).  P lines per wavefront (1 or
 // 2; with 2, the table has exactly 32 chunks).  All 64 lanes must call it
 // together.
-template <int M, int K, int P = 1, typename T = double>
+//
+// RAGGED (general lines, one line per wavefront): the table's chunk length
+// m may be below the slot capacity M, and the last chunk may be shorter
+// still (ql < m - 1 interior rows).  A chunk of q interior rows holds them in
+// slots 0..q-1 and its separator in slot M - 1; slots q..M-2 are unused.
+// The forward sweep writes zero there (by selection, whatever they held), so
+// the back substitution starts at slot q - 1; slot q - 1 feeds the reduced
+// right-hand side and the shorter last chunk is corrected with its own
+// spikes.  The interior factors of a shorter chunk are a prefix of the full
+// chunk's.
+template <int M, int K, int P = 1, typename T = double, bool RAGGED = false>
 __device__ __forceinline__ void line_solve(const TabOf<T>* const (&tab)[K],
                                            const LaneTabT<kSegLanes<P>, T>* const (&lt)[K],
                                            T (&x)[K][M], int lane) {
@@ -350,15 +360,26 @@ __device__ __forceinline__ void line_solve(const TabOf<T>* const (&tab)[K],
   }
   const int C = (tab[0] + z0)->C;
   const int npcr = (tab[0] + z0)->npcr;
+  // RAGGED: this lane's interior rows (every table of a line shares the
+  // chunking).
+  [[maybe_unused]] int q = Q;
+  [[maybe_unused]] bool short_lane = false;
+  if constexpr (RAGGED) {
+    const int ql = (tab[0] + z0)->ql, mt = (tab[0] + z0)->m;
+    short_lane = (c == C - 1) && (ql < mt - 1);
+    q = (c == C - 1) ? ql : mt - 1;
+  }
   // 1. Thomas on the chunk interior (factors shared by every chunk).
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if constexpr (Q > 0) {
       T y = x[k][0] * h[k].ip[0];
+      if constexpr (RAGGED) y = (q > 0) ? y : T(0);
       x[k][0] = y;
 #pragma unroll
       for (int j = 1; j < Q; ++j) {
         y = fma(h[k].r, y, x[k][j]) * h[k].ip[j];
+        if constexpr (RAGGED) y = (j < q) ? y : T(0);
         x[k][j] = y;
       }
 #pragma unroll
@@ -376,7 +397,14 @@ __device__ __forceinline__ void line_solve(const TabOf<T>* const (&tab)[K],
     T v = x[k][M - 1];
     if constexpr (Q > 0) {
       const T gn = bperm(a_next, x[k][0]);
-      v = fma(lt[k]->wl[c], x[k][Q - 1], v);
+      T glast = x[k][Q - 1];
+      if constexpr (RAGGED) {
+        // the chunk's last interior row (slot q - 1; none if q = 0)
+        glast = T(0);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) glast = (j == q - 1) ? x[k][j] : glast;
+      }
+      v = fma(lt[k]->wl[c], glast, v);
       v = fma(lt[k]->wr[c], gn, v);
     }
     if constexpr (Q > 1) v = fma(lt[k]->wg[c], x[k][1], v);
@@ -453,10 +481,27 @@ __device__ __forceinline__ void line_solve(const TabOf<T>* const (&tab)[K],
     if constexpr (Q > 1) ghost = fma(static_cast<T>(t->ghd), x[k][1], ghost);
     const T sl = (c == 0) ? ghost : sprev;
 #pragma unroll
-    for (int j = 0; j < Q; ++j)
-      x[k][j] = fma(sl, static_cast<T>(t->al[j]), fma(s, static_cast<T>(t->be[j]), x[k][j]));
+    for (int j = 0; j < Q; ++j) {
+      T alj = static_cast<T>(t->al[j]), bej = static_cast<T>(t->be[j]);
+      if constexpr (RAGGED) {
+        alj = short_lane ? static_cast<T>(t->al_last[j]) : alj;
+        bej = short_lane ? static_cast<T>(t->be_last[j]) : bej;
+      }
+      x[k][j] = fma(sl, alj, fma(s, bej, x[k][j]));
+    }
     x[k][M - 1] = s;
   }
+}
+
+// RAGGED lines: row of the line held in slot j (of M) of chunk c, for
+// chunks of m rows (C of them, the last with ql interior rows) on a line of
+// n rows; -1 for an unused slot.
+__device__ __forceinline__ int64_t ragged_row(int c, int j, int M, int m, int C, int ql,
+                                              int64_t n) {
+  const bool last = (c + 1 == C);
+  if (j == M - 1) return last ? n - 1 : static_cast<int64_t>(c) * m + m - 1;
+  const int q = last ? ql : m - 1;
+  return (j < q) ? static_cast<int64_t>(c) * m + j : -1;
 }
 
 // Persistent-block tile walk.  The dispatcher places block b on XCD b % 8;
@@ -607,6 +652,7 @@ struct PassGeom {
   int64_t N;                    // species stride
   int n, C, pitch, nbuf, tile;  // line length, chunks, LDS pitch/buffers/size
   int lines;                    // lines per tile = wavefronts per block
+  int m, ql;                    // RAGGED kernels: chunk length, last chunk's interior rows
 };
 
 struct TileAt {
@@ -630,15 +676,25 @@ struct TileAt {
 // This lane's chunk of its line read directly; zeros for a line past nF or
 // a lane without a chunk.  Wavefront w holds lines f0 + w*P .. f0 + w*P + P-1
 // of the tile (one per segment).
-template <int M, int P = 1, typename T = double>
+template <int M, int P = 1, typename T = double, bool RAGGED = false>
 __device__ __forceinline__ void line_load(const T* __restrict__ A, T (&v)[M],
                                           const PassGeom& g, const TileAt& p) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
   const int64_t f = p.f0 + w * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
   const bool ok = (c < g.C) && (f < g.nF);
-  const T* src = ok ? A + f * g.inF + p.tin + (int64_t)c * M : A;
-  load_chunk<M>(src, v, ok);
+  if constexpr (RAGGED) {
+    // row by row (line starts are not aligned); unused slots read zero
+    const T* line = A + f * g.inF + p.tin;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t row = ok ? ragged_row(c, j, M, g.m, g.C, g.ql, g.n) : -1;
+      v[j] = (row >= 0) ? line[row] : T(0);
+    }
+  } else {
+    const T* src = ok ? A + f * g.inF + p.tin + (int64_t)c * M : A;
+    load_chunk<M>(src, v, ok);
+  }
 }
 
 // Transposed read, split for software pipelining as tile_fetch/tile_commit
@@ -680,7 +736,7 @@ __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M]
 // Transposed write of every wave's line chunks (all threads call it).  The
 // block has 64*L/P threads; in the write-out thread (col, q) moves rows
 // q*M .. q*M+M-1 of the tile's line col.  NT: non-temporal global stores.
-template <int M, int L, int P = 1, bool NT = false, typename T = double>
+template <int M, int L, int P = 1, bool NT = false, typename T = double, bool RAGGED = false>
 __device__ __forceinline__ void tile_store(T* __restrict__ A, const T (&x)[M],
                                            T* lds, const PassGeom& g, const TileAt& p,
                                            TileCursor& cur) {
@@ -695,7 +751,16 @@ __device__ __forceinline__ void tile_store(T* __restrict__ A, const T (&x)[M],
   }
   __syncthreads();
   const int col = tid & (L - 1), q = tid / L;
-  if (q < g.C && p.f0 + col < g.nF) {
+  if constexpr (RAGGED) {
+    if (q < g.C && p.f0 + col < g.nF) {
+      T* dst = A + p.f0 + col + p.tout;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const int64_t row = ragged_row(q, i, M, g.m, g.C, g.ql, g.n);
+        if (row >= 0) dst[row * g.outRow] = B[col * g.pitch + i * g.C + q];
+      }
+    }
+  } else if (q < g.C && p.f0 + col < g.nF) {
     T* dst = A + p.f0 + col + p.tout + (int64_t)(q * M) * g.outRow;
 #pragma unroll
     for (int i = 0; i < M; ++i) {

@@ -54,13 +54,13 @@ __device__ __forceinline__ void react_at(const Rx& rx, const GroupCoef& gc, int6
 // This lane's chunk of the reaction field on its line (zeros without a
 // field).  Only complex species carry one; for the others it is zeros at
 // compile time.
-template <int M, int P, typename T>
+template <int M, int P, typename T, bool R = false>
 __device__ __forceinline__ void field_line(const double* fld, double (&bf)[M], const PassGeom& g,
                                            const TileAt& pos) {
 #pragma unroll
   for (int j = 0; j < M; ++j) bf[j] = 0.0;
   if constexpr (kIsComplex<T>) {
-    if (fld) line_load<M, P>(fld, bf, g, pos);
+    if (fld) line_load<M, P, double, R>(fld, bf, g, pos);
   }
 }
 
@@ -181,7 +181,7 @@ __device__ __forceinline__ void react_species(const Rx& rx, const GroupCoef& gc,
   }
 }
 
-template <int M, int S, int L, int P, bool NT, bool E1, typename T, bool G>
+template <int M, int S, int L, int P, bool NT, bool E1, typename T, bool G, bool R = false>
 __device__ __forceinline__ void k_first_s_body(
     const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
     T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g, const GroupCoef& gc) {
@@ -211,7 +211,7 @@ __device__ __forceinline__ void k_first_s_body(
   auto fetch = [&](int64_t t_) {
     const TileAt p(t_, g);
 #pragma unroll
-    for (int q = 0; q < S; ++q) line_load<M, P>(u + q * g.N, Un[q], g, p);
+    for (int q = 0; q < S; ++q) line_load<M, P, T, R>(u + q * g.N, Un[q], g, p);
   };
   if (have) fetch(tile);
   // Phase helpers; with pre set, the lines of tile pf are fetched once the
@@ -224,8 +224,8 @@ __device__ __forceinline__ void k_first_s_body(
     if (pre) fetch(pf);
     const TabOf<T>* tb[1] = {at.P(s_)};
     const LT* lb[1] = {at.lP(s_)};
-    line_solve<M, 1, P>(tb, lb, y, lane);
-    tile_store<M, L, P, NT>(w + s_ * g.N, y[0], tl, g, pos, cur);
+    line_solve<M, 1, P, T, R>(tb, lb, y, lane);
+    tile_store<M, L, P, NT, T, R>(w + s_ * g.N, y[0], tl, g, pos, cur);
   };
   auto first_rs_phase = [&](const T (&v)[M], int s_, T* out, const TileAt& pos,
                             bool pre, int64_t pf) {  // out = R_1 v = 9 T_1 v - 8 S_1 v
@@ -238,10 +238,10 @@ __device__ __forceinline__ void k_first_s_body(
     if (pre) fetch(pf);
     const TabOf<T>* tb[2] = {at.T(s_), at.Sx(s_)};
     const LT* lb[2] = {at.lT(s_), at.lS(s_)};
-    line_solve<M, 2, P>(tb, lb, x, lane);
+    line_solve<M, 2, P, T, R>(tb, lb, x, lane);
 #pragma unroll
     for (int j = 0; j < M; ++j) x[0][j] = T(9) * x[0][j] - T(8) * x[1][j];
-    tile_store<M, L, P, NT>(out + s_ * g.N, x[0], tl, g, pos, cur);
+    tile_store<M, L, P, NT, T, R>(out + s_ * g.N, x[0], tl, g, pos, cur);
   };
   // The scheme (E1: the ETD1 predictor alone) is a template parameter, so
   // that each scheme's phase sequence is allocated registers on its own.
@@ -265,7 +265,7 @@ __device__ __forceinline__ void k_first_s_body(
       }
       T f[M];
       double bf[M];
-      field_line<M, P, T>(rx.fld1, bf, g, pos);
+      field_line<M, P, T, R>(rx.fld1, bf, g, pos);
       react_species<G, S, M>(rx, gc, pos.t, U, s, bf, f);
       const int64_t pf = (s == S - 1) ? (have_next ? next : tile) : tile;
       first_p_phase(U[s], f, s, pos, E1, pf);
@@ -280,12 +280,81 @@ __device__ __forceinline__ void k_first_s_body(
 }
 
 // ---------------------------------------------------------------------------
+// Middle pass (axes 2 .. d-1), streamed: the same work as k_mid in phases of one input array
+// each (T and S on c1, T and S on c2, P on w), so that only one input and its
+// two solves are in registers; the next phase's input is fetched while the
+// current one is solved.  Fewer registers per wave than k_mid, for long
+// chunks.
+// ---------------------------------------------------------------------------
+template <int M, int S, int L, int P, bool NT, typename T, bool R = false>
+__device__ __forceinline__ void k_mid_s_body(
+    const T* __restrict__ c1, const T* __restrict__ c2,
+    const T* __restrict__ w, T* __restrict__ o1, T* __restrict__ o2,
+    T* __restrict__ ow, const TabOf<T>* __restrict__ tabs, PassGeom g, int etd1) {
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<kSegLanes<P>, T>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S, kSegLanes<P>, T> at{tabs, lt};
+  const int lane = threadIdx.x & 63;
+  const int first_phase = etd1 ? 2 : 0;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  bool have = walk.next(tile);
+  int s = 0, ph = first_phase;
+  T pf[M];
+  auto src = [&](int ph_) { return ph_ == 0 ? c1 : (ph_ == 1 ? c2 : w); };
+  auto fetch = [&](int64_t tl_, int s_, int ph_) {
+    line_load<M, P, T, R>(src(ph_) + s_ * g.N, pf, g, TileAt(tl_, g));
+  };
+  if (have) fetch(tile, 0, ph);
+  while (have) {
+    const TileAt pos(tile, g);
+    const int sc = s, pc = ph;
+    T x[2][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      x[0][j] = pf[j];
+      x[1][j] = pf[j];
+    }
+    if (++ph == 3) {
+      ph = first_phase;
+      if (++s == S) {
+        s = 0;
+        have = walk.next(tile);
+      }
+    }
+    if (have) fetch(tile, s, ph);
+    if (pc == 2) {
+      T y[1][M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) y[0][j] = x[0][j];
+      const TabOf<T>* tb[1] = {at.P(sc)};
+      const LT* lb[1] = {at.lP(sc)};
+      line_solve<M, 1, P, T, R>(tb, lb, y, lane);
+      tile_store<M, L, P, NT, T, R>(ow + sc * g.N, y[0], tl, g, pos, cur);
+    } else {
+      const TabOf<T>* tb[2] = {at.T(sc), at.Sx(sc)};
+      const LT* lb[2] = {at.lT(sc), at.lS(sc)};
+      line_solve<M, 2, P, T, R>(tb, lb, x, lane);
+#pragma unroll
+      for (int j = 0; j < M; ++j) x[0][j] = T(9) * x[0][j] - T(8) * x[1][j];
+      tile_store<M, L, P, NT, T, R>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Last pass, streamed: the work of k_last with the corrector inputs read per
 // species when they are used and no cross-tile prefetch (one measured no
 // faster), so that a 16- or 32-line tile of long chunks fits the register
 // budget.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L, int P, bool NT, typename T, bool G>
+template <int M, int S, int L, int P, bool NT, typename T, bool G, bool R = false>
 __device__ __forceinline__ void k_last_s_body(
     T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
     const T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k,
@@ -311,7 +380,7 @@ __device__ __forceinline__ void k_last_s_body(
     restage<G, S>(at, lt, tabs, gc, pos.t, staged);
     T us[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) line_load<M, P>(w + s * g.N, us[s], g, pos);
+    for (int s = 0; s < S; ++s) line_load<M, P, T, R>(w + s * g.N, us[s], g, pos);
     {
       const TabOf<T>* tb[S];
       const LT* lb[S];
@@ -320,16 +389,16 @@ __device__ __forceinline__ void k_last_s_body(
         tb[s] = at.P(s);
         lb[s] = at.lP(s);
       }
-      line_solve<M, S, P>(tb, lb, us, lane);
+      line_solve<M, S, P, T, R>(tb, lb, us, lane);
     }
     if (etd1) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) tile_store<M, L, P, NT>(u + s * g.N, us[s], tl, g, pos, cur);
+      for (int s = 0; s < S; ++s) tile_store<M, L, P, NT, T, R>(u + s * g.N, us[s], tl, g, pos, cur);
       continue;
     }
     {
       double bf[M];
-      field_line<M, P, T>(rx.fldd, bf, g, pos);
+      field_line<M, P, T, R>(rx.fldd, bf, g, pos);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         T uu[S], ff[S];
@@ -343,8 +412,8 @@ __device__ __forceinline__ void k_last_s_body(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       T x[2][M], b[M];
-      line_load<M, P>(c1 + s * g.N, x[0], g, pos);
-      line_load<M, P>(c2 + s * g.N, b, g, pos);
+      line_load<M, P, T, R>(c1 + s * g.N, x[0], g, pos);
+      line_load<M, P, T, R>(c2 + s * g.N, b, g, pos);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const T a = x[0][j];
@@ -353,10 +422,10 @@ __device__ __forceinline__ void k_last_s_body(
       }
       const TabOf<T>* tb[2] = {at.T(s), at.Sx(s)};
       const LT* lb[2] = {at.lT(s), at.lS(s)};
-      line_solve<M, 2, P>(tb, lb, x, lane);
+      line_solve<M, 2, P, T, R>(tb, lb, x, lane);
 #pragma unroll
       for (int j = 0; j < M; ++j) x[0][j] = x[0][j] - x[1][j];
-      tile_store<M, L, P, NT>(u + s * g.N, x[0], tl, g, pos, cur);
+      tile_store<M, L, P, NT, T, R>(u + s * g.N, x[0], tl, g, pos, cur);
     }
   }
 }

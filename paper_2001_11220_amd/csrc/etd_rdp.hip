@@ -139,73 +139,13 @@ __global__ __launch_bounds__(64 * L, (kPassWaves<M, T>)) void k_mid(
   }
 }
 
-// ---------------------------------------------------------------------------
-// Middle pass, streamed: the same work as k_mid in phases of one input array
-// each (T and S on c1, T and S on c2, P on w), so that only one input and its
-// two solves are in registers; the next phase's input is fetched while the
-// current one is solved.  Fewer registers per wave than k_mid, for long
-// chunks.
-// ---------------------------------------------------------------------------
+// Middle pass, streamed (k_mid_s_body, in etd_passes.hpp).
 template <int M, int S, int L, int P, bool NT, typename T>
 __global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_mid_s(
     const T* __restrict__ c1, const T* __restrict__ c2,
     const T* __restrict__ w, T* __restrict__ o1, T* __restrict__ o2,
     T* __restrict__ ow, const TabOf<T>* __restrict__ tabs, PassGeom g, int etd1) {
-  extern __shared__ double lds_raw[];
-  char* const lds = reinterpret_cast<char*>(lds_raw);
-  using LT = LaneTabT<kSegLanes<P>, T>;
-  LT* lt = reinterpret_cast<LT*>(lds);
-  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
-  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
-  __syncthreads();
-  const AxisTabs<S, kSegLanes<P>, T> at{tabs, lt};
-  const int lane = threadIdx.x & 63;
-  const int first_phase = etd1 ? 2 : 0;
-  TileCursor cur;
-  TileWalk walk(g.nFblk * g.nT);
-  int64_t tile;
-  bool have = walk.next(tile);
-  int s = 0, ph = first_phase;
-  T pf[M];
-  auto src = [&](int ph_) { return ph_ == 0 ? c1 : (ph_ == 1 ? c2 : w); };
-  auto fetch = [&](int64_t tl_, int s_, int ph_) {
-    line_load<M, P>(src(ph_) + s_ * g.N, pf, g, TileAt(tl_, g));
-  };
-  if (have) fetch(tile, 0, ph);
-  while (have) {
-    const TileAt pos(tile, g);
-    const int sc = s, pc = ph;
-    T x[2][M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      x[0][j] = pf[j];
-      x[1][j] = pf[j];
-    }
-    if (++ph == 3) {
-      ph = first_phase;
-      if (++s == S) {
-        s = 0;
-        have = walk.next(tile);
-      }
-    }
-    if (have) fetch(tile, s, ph);
-    if (pc == 2) {
-      T y[1][M];
-#pragma unroll
-      for (int j = 0; j < M; ++j) y[0][j] = x[0][j];
-      const TabOf<T>* tb[1] = {at.P(sc)};
-      const LT* lb[1] = {at.lP(sc)};
-      line_solve<M, 1, P>(tb, lb, y, lane);
-      tile_store<M, L, P, NT>(ow + sc * g.N, y[0], tl, g, pos, cur);
-    } else {
-      const TabOf<T>* tb[2] = {at.T(sc), at.Sx(sc)};
-      const LT* lb[2] = {at.lT(sc), at.lS(sc)};
-      line_solve<M, 2, P>(tb, lb, x, lane);
-#pragma unroll
-      for (int j = 0; j < M; ++j) x[0][j] = T(9) * x[0][j] - T(8) * x[1][j];
-      tile_store<M, L, P, NT>((pc == 0 ? o1 : o2) + sc * g.N, x[0], tl, g, pos, cur);
-    }
-  }
+  k_mid_s_body<M, S, L, P, NT, T>(c1, c2, w, o1, o2, ow, tabs, g, etd1);
 }
 
 // ---------------------------------------------------------------------------
@@ -491,8 +431,10 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, 
     else if (kind == kPassMid) g.nF = c->slab_nz;
   }
   g.n = static_cast<int>(c->n[axis0]);
-  g.C = g.n / (one_line ? c->m1[axis0] : c->m[axis0]);
-  g.pitch = tile_pitch(g.n);
+  g.m = one_line ? c->m1[axis0] : c->m[axis0];
+  g.C = (g.n + g.m - 1) / g.m;
+  g.ql = g.n - (g.C - 1) * g.m - 1;  // m - 1 unless the last chunk is shorter
+  g.pitch = tile_pitch(g.n);  // the general kernels widen it to C times their slots
   g.lines = lines;
   g.tile = lines * g.pitch;
   g.nbuf = tile_buffers(fixed_lds, lines, g.tile, esize);
@@ -763,6 +705,11 @@ int launch_pass(etd_rdp_ctx* c, int p, T* u, T* const (&in)[3], T* const (&out)[
   }
   T* const c1_in = (c->d == 1) ? u : in[0];
   T* const (&lin)[3] = (c->d == 1) ? out : in;
+  if (c->gen[p]) {
+    e = launch_general<T>(c, p, u, c1_in, lin, in, out, ta, st);
+    if (e != hipSuccess) return hip_fail(c, e);
+    return ETD_OK;
+  }
   if constexpr (kIsComplex<T>) {
     // One complex species, one line per wavefront.
     if (S != 1) return ETD_ERR_UNSUPPORTED;
@@ -1059,12 +1006,17 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     double h = grid->h[i];
     if (h == 0.0) h = (b == ETD_BC_DIRICHLET) ? 1.0 / (n + 1) : (b == ETD_BC_NEUMANN ? 1.0 / (n - 1) : 1.0 / n);
     if (!(std::isfinite(h) && h > 0)) { delete c; return ETD_ERR_ARG; }
-    const int m = choose_chunk(n);
+    // Regular chunking where it exists, else the general kernels' (a line
+    // length up to 64 * kMaxM).
+    int m = choose_chunk(n);
+    const bool general = (m == 0);
+    if (general) m = general_chunk(n);
     if (m == 0) { delete c; return ETD_ERR_UNSUPPORTED; }
     const int64_t lines = N / n;
-    const bool two_ok = !cplx && ((lpw == ETD_LINES_TWO) ||
-                                  (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines));
+    const bool two_ok = !cplx && !general &&
+                        ((lpw == ETD_LINES_TWO) || (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines));
     const int m2 = two_ok ? two_line_chunk(n) : 0;
+    c->gen[i] = general ? 1 : 0;
     c->n[i] = n;
     c->h[i] = h;
     c->bc[i] = b;
@@ -1179,7 +1131,7 @@ int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass, size_t* off_c
 int etd_rdp_line_split(const etd_rdp_ctx* ctx, int32_t axis, int32_t* m, int32_t* chunks) {
   if (!ctx || !m || !chunks || axis < 1 || axis > ctx->d) return ETD_ERR_ARG;
   *m = ctx->m[axis - 1];
-  *chunks = static_cast<int32_t>(ctx->n[axis - 1] / ctx->m[axis - 1]);
+  *chunks = static_cast<int32_t>((ctx->n[axis - 1] + *m - 1) / *m);
   return ETD_OK;
 }
 
@@ -1255,6 +1207,7 @@ int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, 
                         int32_t sigma, int32_t gamma, void* stream) {
   if (!ctx || !x || axis < 1 || axis > ctx->d || sigma < 0 || sigma >= ctx->s) return ETD_ERR_ARG;
   if (ctx->precision != ETD_PRECISION_F64 || ctx->d > 3) return ETD_ERR_UNSUPPORTED;
+  if (ctx->gen[axis - 1]) return ETD_ERR_UNSUPPORTED;
   const int slot = gamma == 1 ? 0 : (gamma == 3 ? 1 : (gamma == 4 ? 2 : -1));
   if (slot < 0) return ETD_ERR_ARG;
   int rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
@@ -1314,6 +1267,7 @@ int etd_rdp_forget_workspace(etd_rdp_ctx* ctx) {
 int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t size) {
   if (!ctx || !name || size == 0 || pass < 1 || pass > ctx->d) return ETD_ERR_ARG;
   const int p = pass - 1, m = ctx->m[p], P = ctx->P[p];
+  if (ctx->gen[p]) return general_kernel_name(ctx, p, name, size) == 0 ? ETD_OK : ETD_ERR_ARG;
   // d = 1: the one pass is the last-pass kernel (after an elementwise pre-pass)
   const bool first = (p == 0) && ctx->d > 1, last = (p == ctx->d - 1);
   const bool zc = (ctx->precision == ETD_PRECISION_C128);

@@ -20,9 +20,14 @@ namespace etd {
 
 int choose_chunk(int64_t n) {
   if (n < 1) return 0;
-  for (int m = 1; m <= kMaxM; ++m)
+  for (int m = 1; m <= kMaxRegularM; ++m)
     if (n % m == 0 && n / m <= kLanes) return m;
   return 0;
+}
+
+int general_chunk(int64_t n) {
+  if (n < 1 || n > kMaxLine) return 0;
+  return static_cast<int>((n + kLanes - 1) / kLanes);
 }
 
 namespace {
@@ -66,15 +71,20 @@ struct LineSystem {
   }
 };
 
+// Chunks of m rows, the last one possibly shorter: its separator is row
+// n - 1 whatever its length.
 struct Split {
   int64_t n;
   int m, C, g;  // g = 1 if a ghost separator comes first
-  bool is_sep(int64_t u) const { return u == -1 || (u % m) == m - 1; }
+  bool is_sep(int64_t u) const { return u == -1 || u == n - 1 || (u % m) == m - 1; }
   int sep_index(int64_t u) const {
-    return u == -1 ? 0 : g + static_cast<int>(u / m);
+    return u == -1 ? 0 : g + (u == n - 1 ? C - 1 : static_cast<int>(u / m));
   }
   int chunk(int64_t u) const { return static_cast<int>(u / m); }
   int slot(int64_t u) const { return static_cast<int>(u % m); }
+  int q(int c) const {  // interior rows of chunk c
+    return (c + 1 < C) ? m - 1 : static_cast<int>(n - 1 - int64_t(c) * m);
+  }
 };
 
 // Dense tridiagonal solve without pivoting (diagonally dominant input).
@@ -91,26 +101,32 @@ void thomas(std::vector<V> a, std::vector<V> b, std::vector<V> c, std::vector<V>
 }
 
 // The device algorithm, executed on the host for the residual self-check.
+// A shorter last chunk runs the same steps with its own interior length
+// (the interior factors are a prefix of the full chunk's) and spikes.
 template <typename V>
 void emulate(const SolveTabT<V>& t, const V* b, V* x) {
   const int m = t.m, C = t.C, q = m - 1;
+  auto qc = [&](int c) { return (c + 1 < C) ? q : t.ql; };
+  auto sep_row = [&](int c) { return (c + 1 < C) ? int64_t(c) * m + m - 1 : int64_t(t.n) - 1; };
   std::vector<V> gv(kLanes * kMaxM, V(0.0));
   auto g = [&](int c, int j) -> V& { return gv[c * kMaxM + j]; };
   V d[kLanes] = {};
   for (int c = 0; c < C; ++c) {
     const V* bc = b + static_cast<int64_t>(c) * m;
-    if (q > 0) {
+    const int qq = qc(c);
+    if (qq > 0) {
       V y[kMaxM];
       y[0] = bc[0] * t.ip[0];
-      for (int j = 1; j < q; ++j) y[j] = (bc[j] + t.r * y[j - 1]) * t.ip[j];
-      g(c, q - 1) = y[q - 1];
-      for (int j = q - 1; j-- > 0;) g(c, j) = y[j] + t.cp[j] * g(c, j + 1);
+      for (int j = 1; j < qq; ++j) y[j] = (bc[j] + t.r * y[j - 1]) * t.ip[j];
+      g(c, qq - 1) = y[qq - 1];
+      for (int j = qq - 1; j-- > 0;) g(c, j) = y[j] + t.cp[j] * g(c, j + 1);
     }
   }
   for (int c = 0; c < C; ++c) {
     const int cn = (c + 1 == C) ? 0 : c + 1;
-    V v = b[static_cast<int64_t>(c) * m + m - 1];
-    if (q > 0) v += t.lane.wl[c] * g(c, q - 1) + t.lane.wr[c] * g(cn, 0);
+    const int qq = qc(c);
+    V v = b[sep_row(c)];
+    if (q > 0) v += t.lane.wl[c] * (qq > 0 ? g(c, qq - 1) : V(0.0)) + t.lane.wr[c] * g(cn, 0);
     if (q > 1) v += t.lane.wg[c] * g(c, 1);
     d[c] = v;
   }
@@ -138,8 +154,10 @@ void emulate(const SolveTabT<V>& t, const V* b, V* x) {
       sl = t.gh0 * s[0] + t.ghw * s[C - 1] + (q > 1 ? t.ghd * g(0, 1) : V(0.0));
     }
     V* xc = x + static_cast<int64_t>(c) * m;
-    for (int j = 0; j < q; ++j) xc[j] = g(c, j) + sl * t.al[j] + s[c] * t.be[j];
-    xc[m - 1] = s[c];
+    const bool last_short = (c + 1 == C) && t.ql < q;
+    for (int j = 0; j < qc(c); ++j)
+      xc[j] = g(c, j) + sl * (last_short ? t.al_last[j] : t.al[j]) + s[c] * (last_short ? t.be_last[j] : t.be[j]);
+    x[sep_row(c)] = s[c];
   }
 }
 
@@ -164,17 +182,23 @@ bool build_impl(int64_t n, int bc, double h, V coef, int m, SolveTabT<V>* out,
     if (err) *err = why;
     return false;
   };
-  if (m < 1 || m > kMaxM || n % m != 0 || n / m > kLanes || n < 1)
-    return fail("bad chunking");
+  if (m < 1 || m > kMaxM || n < 1 || (n + m - 1) / m > kLanes) return fail("bad chunking");
+  const int C0 = static_cast<int>((n + m - 1) / m);
+  // a shorter last chunk needs a full first chunk (C >= 2) for the boundary
+  // rows of lane 0
+  if (n % m != 0 && C0 < 2) return fail("bad chunking");
   *out = SolveTabT<V>{};
   const V r = coef / (h * h);
   LineSystem<V> L{n, bc, r, V(1.0) + V(2.0) * r, bc == 1};
-  Split S{n, m, static_cast<int>(n / m), L.ghost ? 1 : 0};
+  Split S{n, m, C0, L.ghost ? 1 : 0};
   const int C = S.C, q = m - 1, Cx = C + S.g;
+  const int ql = S.q(C - 1);
   SolveTabT<V>& t = *out;
   t.r = r;
   t.C = C;
   t.m = m;
+  t.ql = ql;
+  t.n = static_cast<int32_t>(n);
 
   // Interior factors of T = tridiag(-r, 1+2r, -r) of size q.
   std::vector<std::vector<V>> Tinv(q, std::vector<V>(q, V(0.0)));
@@ -196,6 +220,20 @@ bool build_impl(int64_t n, int bc, double h, V coef, int m, SolveTabT<V>* out,
       t.be[j] = r * Tinv[j][q - 1];
     }
   }
+  // The last chunk's interior inverse (its own size when shorter).
+  std::vector<std::vector<V>> TinvL(ql, std::vector<V>(ql, V(0.0)));
+  for (int col = 0; col < ql; ++col) {
+    std::vector<V> a(ql, -r), b(ql, L.delta), c(ql, -r), x(ql, V(0.0));
+    x[col] = V(1.0);
+    thomas(a, b, c, x);
+    for (int j = 0; j < ql; ++j) TinvL[j][col] = x[j];
+  }
+  if (ql < q)
+    for (int j = 0; j < ql; ++j) {
+      t.al_last[j] = r * TinvL[j][0];
+      t.be_last[j] = r * TinvL[j][ql - 1];
+    }
+  auto tinv = [&](int c, int i, int j) -> const V& { return (c + 1 == C) ? TinvL[i][j] : Tinv[i][j]; };
 
   // Assemble E_SS and collect E_IS / E_SI per chunk.
   std::vector<std::vector<V>> Mx(Cx, std::vector<V>(Cx, V(0.0)));
@@ -235,9 +273,11 @@ bool build_impl(int64_t n, int bc, double h, V coef, int m, SolveTabT<V>* out,
   if (bad) return fail(why);
 
   // Expected interior-to-separator couplings: slot 0 to the left separator
-  // (previous chunk, ghost, periodic wrap, or none) and slot q-1 to the own
-  // separator, both -r.  These are what the spikes al/be encode.
-  for (int c = 0; c < C && q > 0; ++c) {
+  // (previous chunk, ghost, periodic wrap, or none) and the last interior
+  // slot to the own separator, both -r.  These are what the spikes encode.
+  for (int c = 0; c < C; ++c) {
+    const int qq = S.q(c);
+    if (qq == 0) continue;
     std::map<std::pair<int, int>, V> got;
     for (auto& en : EIS[c]) got[{en.slot, en.sep}] += en.v;
     std::map<std::pair<int, int>, V> want;
@@ -246,15 +286,15 @@ bool build_impl(int64_t n, int bc, double h, V coef, int m, SolveTabT<V>* out,
     else if (bc == 1) left = 0;
     else if (bc == 2) left = S.g + C - 1;
     if (left >= 0) want[{0, left}] += -r;
-    want[{q - 1, S.g + c}] += -r;
+    want[{qq - 1, S.g + c}] += -r;
     if (got != want) return fail("unexpected interior-separator coupling");
   }
 
-  // Schur complement Mx -= E_SI T^{-1} E_IS.
+  // Schur complement Mx -= E_SI T^{-1} E_IS (each chunk with its own T).
   for (int c = 0; c < C; ++c)
     for (auto& a : ESI[c])
       for (auto& b : EIS[c])
-        Mx[a.sep][b.sep] -= a.v * Tinv[a.slot][b.slot] * b.v;
+        Mx[a.sep][b.sep] -= a.v * tinv(c, a.slot, b.slot) * b.v;
 
   // Reduced right-hand-side weights (per separator, then checked to be
   // uniform apart from the first and last separator).
@@ -270,7 +310,7 @@ bool build_impl(int64_t n, int bc, double h, V coef, int m, SolveTabT<V>* out,
       }
       const int sc = p - S.g;  // separator's chunk
       const int cn = (sc + 1 == C) ? 0 : sc + 1;
-      if (c == sc && a.slot == q - 1 && !(c == cn && a.slot == 0)) {
+      if (c == sc && a.slot == S.q(c) - 1 && !(c == cn && a.slot == 0)) {
         wl[sc] += -a.v;
       } else if (c == cn && a.slot == 0 && c != sc) {
         wr[sc] += -a.v;
@@ -357,21 +397,25 @@ bool build_impl(int64_t n, int bc, double h, V coef, int m, SolveTabT<V>* out,
   }
   for (int i = 0; i < C; ++i) t.lane.inv[i] = V(1.0) / rb[i];
 
-  // Uniform reduced-RHS weights.
+  // Reduced-RHS weights: r everywhere except next to the line's ends.
   t.wl_gen = r;
   t.wr_gen = r;
   t.wl_last = wl[C - 1];
   t.wr_last = wr[C - 1];
   t.wg0 = wg[0];
-  for (int c = 0; c + 1 < C; ++c)
-    if (q > 0 && (wl[c] != r || wr[c] != r)) return fail("non-uniform reduced weights");
+  for (int c = 0; c + 1 < C; ++c) {
+    if (q == 0) continue;
+    // the one before a last chunk without interior rows has no right weight
+    const V want_r = (c + 2 == C && ql == 0) ? V(0.0) : r;
+    if (wl[c] != r || wr[c] != want_r) return fail("non-uniform reduced weights");
+  }
   for (int c = 1; c < C; ++c)
     if (wg[c] != V(0.0)) return fail("ghost weight beyond separator 0");
   // Per-lane copies of the weights (zero on lanes without a chunk): the
   // device reads these instead of selecting between the uniform values.
   for (int c = 0; c < C; ++c) {
-    t.lane.wl[c] = (c + 1 == C) ? t.wl_last : t.wl_gen;
-    t.lane.wr[c] = (c + 1 == C) ? t.wr_last : t.wr_gen;
+    t.lane.wl[c] = wl[c];
+    t.lane.wr[c] = wr[c];
     t.lane.wg[c] = (c == 0) ? t.wg0 : V(0.0);
   }
 
@@ -438,6 +482,12 @@ bool build_solve_table_z(int64_t n, int bc, double h, zd coef, int m, SolveTabZ*
   out->m = a.m;
   out->npcr = a.npcr;
   out->sm = a.sm;
+  out->ql = a.ql;
+  out->n = a.n;
+  for (int j = 0; j < kMaxM; ++j) {
+    out->al_last[j] = z(a.al_last[j]);
+    out->be_last[j] = z(a.be_last[j]);
+  }
   for (int c = 0; c < kLanes; ++c) {
     for (int st = 0; st < kMaxPcr; ++st) {
       out->lane.k1[st][c] = z(a.lane.k1[st][c]);

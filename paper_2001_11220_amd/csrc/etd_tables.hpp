@@ -33,8 +33,10 @@
 
 namespace etd {
 
-constexpr int kMaxM = 8;       // max rows per chunk
+constexpr int kMaxM = 16;      // max rows per chunk (tables)
+constexpr int kMaxRegularM = 8;  // max rows per chunk of the regular kernels
 constexpr int kLanes = 64;     // wavefront width
+constexpr int64_t kMaxLine = int64_t(kLanes) * kMaxM;  // longest line
 constexpr int kMaxPcr = 6;     // log2(64)
 
 // A complex FP64 value: the element and table type of complex species (a
@@ -88,18 +90,30 @@ struct alignas(256) SolveTabT {
   int32_t m;     // rows per chunk
   int32_t npcr;  // PCR steps = ceil(log2 C)
   int32_t sm;    // 1 if the Sherman-Morrison correction is applied
+  int32_t ql;    // interior rows of the last chunk (m - 1 unless the line is ragged)
+  int32_t n;     // rows of the line (C m, or fewer with a shorter last chunk)
+  // Spikes of the last chunk's interior when it is shorter (ql < m - 1):
+  // r T'^{-1} e_0 and r T'^{-1} e_{ql-1}, T' of size ql; zero beyond ql.
+  V al_last[kMaxM], be_last[kMaxM];
   LaneTabT<kLanes, V> lane;
 };
 using SolveTab = SolveTabT<double>;
 using SolveTabZ = SolveTabT<zd>;
 
-// Pick the chunk length for a line of n rows: the smallest m <= kMaxM that
-// divides n with n / m <= kLanes.  Returns 0 if none exists.
+// Pick the chunk length for a line of n rows: the smallest m <= kMaxRegularM
+// that divides n with n / m <= kLanes.  Returns 0 if none exists.
 int choose_chunk(int64_t n);
+
+// Chunk length of a line that has no regular chunking (or rows beyond
+// kLanes * kMaxRegularM): m = ceil(n / 64) <= kMaxM rows per chunk, C =
+// ceil(n / m) chunks, the last one shorter when m does not divide n (a
+// "ragged" line).  Returns 0 for n < 1 or n > kMaxLine.
+int general_chunk(int64_t n);
 
 // Build the table of (I + coef * B_p) on n rows with boundary condition bc
 // (0 Dirichlet, 1 Neumann, 2 periodic) and spacing h, coef = k D / gamma.
-// Uses chunk length m (n % m == 0, n / m <= 64).  Checks the structure the
+// Uses chunk length m: C = ceil(n / m) <= 64 chunks, all of m rows except
+// possibly a shorter last one (whose separator is row n - 1).  Checks the structure the
 // device code relies on and, on random right-hand sides, the residual of the
 // chunked algorithm the tables encode; returns false and sets *err if a
 // check fails.

@@ -29,7 +29,7 @@ def kernel_rev() -> str:
     """Hash of the kernel sources; stored counter traffic is only valid for
     the revision it was measured on."""
     h = hashlib.sha1()
-    for fn in ("etd_rdp.hip", "etd_batch.hip", "etd_adjoint.hip", "etd_passes.hpp",
+    for fn in ("etd_rdp.hip", "etd_general.hip", "etd_batch.hip", "etd_adjoint.hip", "etd_passes.hpp",
                "etd_device.hpp", "etd_launch.hpp", "etd_ctx.hpp", "etd_tables.hpp",
                "etd_tables.cpp"):
         with open(os.path.join(ROOT, "paper_2001_11220_amd", "csrc", fn), "rb") as f:

@@ -45,14 +45,22 @@ def _init(shape, bcs, D=(0.1, 0.2), k=0.01, model="brusselator", params=None, h=
 
 @pytest.mark.parametrize("bc", ["dirichlet", "neumann", "periodic"])
 def test_tables_build_for_every_line_length(bc):
+    """Every line length 1..1024 builds its tables (each passes the table
+    builder's residual self-check of the chunked algorithm).  Regular
+    lengths split into C <= 64 equal chunks of m <= 8 rows; the others
+    ("general" lines) into m = ceil(n/64) rows per chunk and C = ceil(n/m)
+    chunks, the last one shorter when m does not divide n."""
     nmin = {"dirichlet": 1, "neumann": 2, "periodic": 3}[bc]
-    sizes = list(range(nmin, 70)) + [96, 128, 160, 192, 224, 256, 288, 320, 384, 416, 480, 512]
-    for n in sizes:
-        if not any(n % m == 0 and n // m <= 64 for m in range(1, 9)):
-            continue
-        p = _init((n, 4), (bc, "neumann"), D=(0.5, 3.0), k=0.3)
+    for n in range(nmin, 1025):
+        p = _init((n,), (bc,), D=(0.5, 3.0), k=0.3)
         m, C = p.line_split(1)
-        assert m * C == n and C <= 64 and 1 <= m <= 8
+        regular = any(n % q == 0 and n // q <= 64 for q in range(1, 9))
+        if regular:
+            assert m * C == n and C <= 64 and 1 <= m <= 8, (n, m, C)
+            assert not p.pass_kernel(1).startswith("kr_")
+        else:
+            assert m == -(-n // 64) and C == -(-n // m) and (C - 1) * m < n <= C * m, (n, m, C)
+            assert p.pass_kernel(1).startswith("kr_last<"), p.pass_kernel(1)
         p.close()
 
 
@@ -139,7 +147,7 @@ def test_complex_precision_option():
         p.close()
     ok = dict(D=(1 + 1j,), model="cgl_z", params={"beta": 1.0}, precision="c128")
     cases = [
-        ((521, 16), ok, etd.ETD_ERR_UNSUPPORTED),  # no chunking of 521 rows
+        ((1025, 16), ok, etd.ETD_ERR_UNSUPPORTED),  # longer than 64 chunks of 16 rows
         ((64, 16), dict(ok, lines_per_wave=2), etd.ETD_ERR_UNSUPPORTED),
         ((64, 16), dict(ok, D=(-0.1 + 1j,)), etd.ETD_ERR_ARG),  # Re D < 0
         ((64, 16), dict(ok, precision="f64", D=(1.0,)), etd.ETD_ERR_ARG),  # complex model, real context
@@ -247,10 +255,42 @@ def test_invalid_arguments():
     with pytest.raises(E) as e:
         _init((1, 8), ("neumann", "neumann"))  # Neumann needs n >= 2
     assert e.value.status == etd.ETD_ERR_ARG
-    for n in (67, 1024, 8 * 64 + 8):
+    for n in (1025, 2048):
         with pytest.raises(E) as e:
             _init((n, 8), ("dirichlet", "neumann"))
         assert e.value.status == etd.ETD_ERR_UNSUPPORTED, n
+
+
+def test_general_line_lengths_without_touching_the_gpu():
+    """General line lengths (no split into <= 64 equal chunks of <= 8 rows)
+    run the forward step with the general kernels, on any pass; the
+    reverse-mode step, single solves and ensembles refuse them."""
+    etd = _lib()
+    p = _init((79, 1024, 361), ("dirichlet", "neumann", "periodic"), D=(0.5, 3.0), k=0.3)
+    assert [p.line_split(a) for a in (1, 2, 3)] == [(2, 40), (16, 64), (6, 61)]
+    assert [p.pass_kernel(a) for a in (1, 2, 3)] == ["kr_first<4, 2, 8, false, double>",
+                                                     "kr_mid<16, 2, 8, double>",
+                                                     "kr_last<8, 2, 8, double>"]
+    u, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x10000)
+    x = ctypes.c_void_p(0x2000)
+    assert etd.lib.etd_rdp_apply_solve(p._ctx, x, ws, p.ws_bytes, 1, 0, 3, None) == etd.ETD_ERR_UNSUPPORTED
+    g = ctypes.c_void_p(0x3000)
+    assert etd.lib.etd_rdp_adjoint(p._ctx, u, x, g, g, ws, 1 << 40, None) == etd.ETD_ERR_UNSUPPORTED
+    p.close()
+    z = _init((799, 16), ("periodic", "neumann"), D=(1 + 1j,), model="cgl_z", params={"beta": 1.0},
+              precision="c128")
+    assert z.pass_kernel(1) == "kr_first<16, 1, 4, false, zd>" and z.line_split(1) == (13, 62)
+    z.close()
+    f = _init((801, 16), ("neumann", "neumann"), precision="f32", scheme="etd1")
+    assert f.pass_kernel(1) == "kr_first<16, 2, 8, true, float>" and f.line_split(1) == (13, 62)
+    f.close()
+    arr_t = (etd.Instance * 1)()
+    arr_t[0].n[0], arr_t[0].n[1] = 79, 16
+    arr_t[0].bc[0], arr_t[0].bc[1] = 1, 1
+    arr_t[0].D[0] = 0.01
+    ctx = ctypes.c_void_p()
+    assert etd.lib.etd_rdp_batch_init(1, arr_t, 1, etd.MODELS["linear"], 0.01, None,
+                                      ctypes.byref(ctx)) == etd.ETD_ERR_UNSUPPORTED
 
 
 def test_null_pointers_rejected():

@@ -159,10 +159,10 @@ def test_reaction_field_one_step_matches_oracle(shape, bcs):
 
 
 def test_schroedinger_2d_example_matches_oracle():
-    """Section 8.4's 2-D example on the Neumann unit square (81^2, k = 0.0125,
-    T = 1): the GPU run against the oracle's, and both near the exact
-    solution exp(-i t) cos(pi x) cos(pi y) as the oracle is at this k."""
-    n, k = 81, 0.0125
+    """Section 8.4's 2-D example on the Neumann unit square with the paper's
+    h = 1/78 (79^2 points, a general line length), k = 0.0125, T = 1: the
+    GPU run against the oracle's."""
+    n, k = 79, 0.0125
     h = 1.0 / (n - 1)
     c = np.cos(np.pi * np.arange(n) * h)
     psi0 = np.multiply.outer(c, c)

@@ -1,7 +1,13 @@
 """Seeded random configurations (dimension 1-4, line lengths with ragged
 tiles, boundary conditions, models, FP64 / FP32 / complex, one or two lines
 per wavefront, both schemes), each one step on the GPU against the oracle.
-Tolerances: 1e-12 (FP64, complex), 1e-5 per step (FP32)."""
+
+Tolerances: FP32 1e-5 per step.  FP64 and complex 1e-12, raised to
+2 eps kappa where the line systems' condition number kappa = 1 + 4 max
+|k D| / h^2 (largest over axes and species) makes that larger: every FP64
+solve of such a system, the oracle's included, carries a forward error of
+that order (at kappa = 2.9e4 the oracle's FFT and dense LU solves of one
+step differ by 4.6e-12)."""
 
 import numpy as np
 import pytest
@@ -14,6 +20,9 @@ pytestmark = pytest.mark.gpu
 # line lengths that chunk into <= 64 chunks of <= 8 rows, including ones
 # that run two lines per wavefront (32 m) and odd ones
 LENGTHS = [1, 2, 3, 5, 7, 16, 31, 33, 47, 64, 65, 96, 100, 128, 130, 160, 192, 224, 256, 300, 448, 512]
+# general line lengths (no such chunking: the last chunk is shorter, or
+# chunks of more than 8 rows)
+GENERAL = [67, 79, 97, 127, 257, 361, 521, 640, 799, 801, 1000, 1021, 1024]
 REAL_MODELS = [("brusselator", {"a": 1.0, "b": 3.4}, (0.02, 0.011)),
                ("gray_scott", {"F": 0.04, "kappa": 0.06}, (2e-3, 1e-3)),
                ("schnakenberg", {"a": 0.1, "b": 0.9, "gamma": 1.0}, (0.01, 0.1)),
@@ -23,12 +32,12 @@ REAL_MODELS = [("brusselator", {"a": 1.0, "b": 3.4}, (0.02, 0.011)),
 MIN_N = {"dirichlet": 1, "neumann": 2, "periodic": 3}
 
 
-def _config(seed):
+def _config(seed, lengths=LENGTHS):
     rng = np.random.default_rng(1000 + seed)
     d = int(rng.integers(1, 5))
-    budget = {1: 512, 2: 512 * 64, 3: 64 * 64 * 48, 4: 24 * 20 * 16 * 12}[d]
+    budget = {1: 1024, 2: 512 * 64, 3: 64 * 64 * 48, 4: 24 * 20 * 16 * 12}[d]
     while True:
-        shape = tuple(int(rng.choice(LENGTHS)) for _ in range(d))
+        shape = tuple(int(rng.choice(lengths)) for _ in range(d))
         if int(np.prod(shape)) <= budget:
             break
     bcs = []
@@ -52,11 +61,12 @@ def _config(seed):
     return prob, prec, lpw, scheme
 
 
-@pytest.mark.parametrize("seed", range(40))
+@pytest.mark.parametrize("seed", range(60))
 def test_random_configuration_matches_oracle(seed):
+    """Seeds 0-39 draw regular line lengths, seeds 40-59 general ones too."""
     import torch
     from paper_2001_11220_amd import etd
-    prob, prec, lpw, scheme = _config(seed)
+    prob, prec, lpw, scheme = _config(seed, LENGTHS if seed < 40 else LENGTHS + GENERAL)
     u0 = prob.initial()
     e = etd.EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, scheme=scheme,
                    lines_per_wave=lpw, precision=prec)
@@ -74,7 +84,8 @@ def test_random_configuration_matches_oracle(seed):
     if prec == "f32":
         tol = 1e-5
     else:
-        tol = 1e-12
+        kappa = 1.0 + 4.0 * max(abs(prob.k * D) / h ** 2 for D in prob.D for h in prob.hs())
+        tol = max(1e-12, 2.0 * np.finfo(np.float64).eps * kappa)
     print(f"[random {seed}] {prob.shape} {prob.bcs} {prob.model} {prec} lpw={lpw} {scheme} "
           f"{names} rel_l2={err:.2e}", flush=True)
     assert err <= tol, (err, tol)
