@@ -120,7 +120,7 @@ typedef struct etd_reaction_t {
  * 32 chunks each when the line length is n = 32 m with 2 <= m <= 8 (fewer
  * cross-lane reduction levels per line, 32-line tiles).  Results agree with
  * the one-line form to rounding (the chunking differs). */
-#define ETD_LINES_AUTO 0   /* two where n allows and a pass has >= 32768 lines */
+#define ETD_LINES_AUTO 0   /* two where n allows and a pass has >= 8192 lines  */
 #define ETD_LINES_ONE 1    /* always one                                       */
 #define ETD_LINES_TWO 2    /* two wherever n allows                            */
 

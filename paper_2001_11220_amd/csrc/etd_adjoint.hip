@@ -22,11 +22,13 @@
 // Example 1 W A_i is symmetric with W = diag(1/2, 1, ..., 1, 1/2), so
 // M^{-T} = W M^{-1} W^{-1}: double the two end rows, solve, halve them.
 //
-// Kernels (one wavefront per line, as in the forward passes):
+// Kernels (one line per wavefront, or two where the forward passes run two
+// and the chunks are short, as in the forward passes):
 //   ka_last   axis d: recompute U*, f*, f1, f2; 6 solves per species
 //   ka_mid    axis 2 of 3-D: 10 solves per species (ka_mid_s: the same in
 //             phases of two solves, for short chunks)
 //   ka_first  axis 1: recompute f, U + k f; 10 solves per species; lam_n
+//             (one line per wavefront)
 // The forward carried triples the reverse passes need come from a forward
 // recompute (k_first, and k_mid in 3-D); the reverse passes read them line
 // by line and keep the adjoints in a third triple in u's layout, which
@@ -48,29 +50,38 @@ namespace etd {
 constexpr int kRed = kBlockLines * kGradSlots;  // LDS doubles for block sums
 constexpr int kRedMax = 16 * kGradSlots;        // ... for blocks of up to 16 waves
 
+// Chunk of this lane within its line with P lines per wavefront.
+template <int P>
+__device__ __forceinline__ int seg_chunk(int lane) {
+  return (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
+}
+
 // Neumann transposes: scale the line's first and last rows by f.
-template <int M>
+template <int M, int P = 1>
 __device__ __forceinline__ void ends_scale(double (&x)[M], int lane, int C, double f) {
-  x[0] *= (lane == 0) ? f : 1.0;
-  x[M - 1] *= (lane == C - 1) ? f : 1.0;
+  const int c = seg_chunk<P>(lane);
+  x[0] *= (c == 0) ? f : 1.0;
+  x[M - 1] *= (c == C - 1) ? f : 1.0;
 }
 
 // sum_j yb_j (B x)_j over this lane's rows, B the second difference
 // [-1 2 -1] of the axis with its boundary closure (Example 1); 0 on lanes
-// without a chunk.  All 64 lanes must call it together.
-template <int M>
+// without a chunk.  All 64 lanes must call it together.  With P = 2 the
+// neighbours' rows across a segment edge are replaced by the closure.
+template <int M, int P = 1>
 __device__ __forceinline__ double lap_dot(const double (&yb)[M], const double (&x)[M], int lane,
                                           int C, int bc) {
+  const int c = seg_chunk<P>(lane);
   const double pl = from_prev(x[M - 1]);  // row c*M - 1
   const double pr = from_next(x[0]);      // row c*M + M
-  const double xlast = lane_value(x[M - 1], C - 1);
-  const double xfirst = lane_value(x[0], 0);
+  const double xlast = seg_value<P>(x[M - 1], C - 1, lane);
+  const double xfirst = seg_value<P>(x[0], 0, lane);
   double xl = pl, xr = pr;
-  if (lane == 0) {
+  if (c == 0) {
     xl = (bc == ETD_BC_PERIODIC) ? xlast : 0.0;
     if (bc == ETD_BC_NEUMANN) xl = (M > 1) ? x[M > 1 ? 1 : 0] : pr;
   }
-  if (lane == C - 1) {
+  if (c == C - 1) {
     xr = (bc == ETD_BC_PERIODIC) ? xfirst : 0.0;
     if (bc == ETD_BC_NEUMANN) xr = (M > 1) ? x[M > 1 ? M - 2 : 0] : pl;
   }
@@ -81,7 +92,7 @@ __device__ __forceinline__ double lap_dot(const double (&yb)[M], const double (&
     const double right = (j < M - 1) ? x[j < M - 1 ? j + 1 : 0] : xr;
     acc = fma(yb[j], 2.0 * x[j] - left - right, acc);
   }
-  return (lane < C) ? acc : 0.0;
+  return (c < C) ? acc : 0.0;
 }
 
 // At one cell u (+ shift): jt = J(u)^T fb and g[p] = (dF/dtheta_p(u)) . fb.
@@ -169,12 +180,12 @@ __device__ __forceinline__ void block_partials(const double (&acc)[kGradSlots], 
   }
 }
 
-template <int M, int L>
+template <int M, int L, int P = 1>
 __device__ __forceinline__ void tile_load(const double* __restrict__ A, double (&x)[M], double* tl,
                                           const PassGeom& g, const TileAt& p, TileCursor& cur) {
   double r[M];
   tile_fetch<M, L>(A, r, g, p);
-  tile_commit<M, L>(r, x, tl, g, cur);
+  tile_commit<M, L, P>(r, x, tl, g, cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -183,19 +194,21 @@ __device__ __forceinline__ void tile_load(const double* __restrict__ A, double (
 // u's layout); out: their adjoints ((R'U)bar, (R'f)bar, P_d^T mu) into the
 // triple Y in u's layout.
 // ---------------------------------------------------------------------------
-template <int M, int S>
+template <int M, int S, int P>
 __global__ __launch_bounds__(kBlock) void ka_last(
     const double* __restrict__ c1, const double* __restrict__ c2, const double* __restrict__ w,
     const double* __restrict__ lam, double* __restrict__ y1, double* __restrict__ y2,
     double* __restrict__ yw, const SolveTab* __restrict__ tabs, Rx rx, double k, PassGeom g,
     int bc, double dsc, double* __restrict__ part) {
+  constexpr int L = kBlockLines * P;  // lines per tile
+  using LT = LaneTabT<kSegLanes<P>>;
   extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  LT* lt = reinterpret_cast<LT*>(lds);
+  double* red = lds + (3 * S * sizeof(LT)) / sizeof(double);
   double* tl = red + kRed;
-  stage_lane_tabs(tabs, 3 * S, lt);
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int C = g.C;
   const bool neu = (bc == ETD_BC_NEUMANN);
@@ -208,19 +221,20 @@ __global__ __launch_bounds__(kBlock) void ka_last(
   int64_t tile;
   while (walk.next(tile)) {
     const TileAt pos(tile, g);
-    const bool valid = (lane < C) && (pos.f0 + wv < g.nF);
+    const bool valid =
+        (seg_chunk<P>(lane) < C) && (pos.f0 + wv * P + ((P == 1) ? 0 : lane / kSegLanes<P>) < g.nF);
     double us[S][M], fb[S][M];
 #pragma unroll
-    for (int s = 0; s < S; ++s) line_load<M>(w + s * g.N, us[s], g, pos);
+    for (int s = 0; s < S; ++s) line_load<M, P>(w + s * g.N, us[s], g, pos);
     {
       const SolveTab* tb[S];
-      const LaneTab* lb[S];
+      const LT* lb[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         tb[s] = at.P(s);
         lb[s] = at.lP(s);
       }
-      line_solve<M, S>(tb, lb, us, lane);  // U*
+      line_solve<M, S, P>(tb, lb, us, lane);  // U*
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -234,9 +248,9 @@ __global__ __launch_bounds__(kBlock) void ka_last(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double x[4][M], cb[M];
-      line_load<M>(c1 + s * g.N, x[0], g, pos);
-      line_load<M>(c2 + s * g.N, cb, g, pos);
-      tile_load<M, kBlockLines>(lam + s * g.N, x[2], tl, g, pos, cur);
+      line_load<M, P>(c1 + s * g.N, x[0], g, pos);
+      line_load<M, P>(c2 + s * g.N, cb, g, pos);
+      tile_load<M, L, P>(lam + s * g.N, x[2], tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const double ca = x[0][j];
@@ -245,26 +259,26 @@ __global__ __launch_bounds__(kBlock) void ka_last(
         x[3][j] = x[2][j];
       }
       if (neu) {
-        ends_scale<M>(x[2], lane, C, 2.0);
-        ends_scale<M>(x[3], lane, C, 2.0);
+        ends_scale<M, P>(x[2], lane, C, 2.0);
+        ends_scale<M, P>(x[3], lane, C, 2.0);
       }
       const SolveTab* tb[4] = {at.T(s), at.Sx(s), at.T(s), at.Sx(s)};
-      const LaneTab* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
-      line_solve<M, 4>(tb, lb, x, lane);
+      const LT* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
+      line_solve<M, 4, P>(tb, lb, x, lane);
       if (neu) {
-        ends_scale<M>(x[2], lane, C, 0.5);
-        ends_scale<M>(x[3], lane, C, 0.5);
+        ends_scale<M, P>(x[2], lane, C, 0.5);
+        ends_scale<M, P>(x[3], lane, C, 0.5);
       }
       // x[2] = a = T^T lam, x[3] = b = S^T lam
-      acc[s] += (dsc / 3.0) * lap_dot<M>(x[2], x[0], lane, C, bc) -
-                (dsc / 4.0) * lap_dot<M>(x[3], x[1], lane, C, bc);
+      acc[s] += (dsc / 3.0) * lap_dot<M, P>(x[2], x[0], lane, C, bc) -
+                (dsc / 4.0) * lap_dot<M, P>(x[3], x[1], lane, C, bc);
       double o[M];
 #pragma unroll
       for (int j = 0; j < M; ++j) o[j] = fma(9.0, x[2][j], -8.0 * x[3][j]);
-      tile_store<M, kBlockLines>(y1 + s * g.N, o, tl, g, pos, cur);
+      tile_store<M, L, P>(y1 + s * g.N, o, tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) o[j] = fma(k2, x[2][j], -k15 * x[3][j]);
-      tile_store<M, kBlockLines>(y2 + s * g.N, o, tl, g, pos, cur);
+      tile_store<M, L, P>(y2 + s * g.N, o, tl, g, pos, cur);
 #pragma unroll
       for (int j = 0; j < M; ++j) fb[s][j] = fma(k, x[2][j], -k05 * x[3][j]);  // f*bar
     }
@@ -285,20 +299,20 @@ __global__ __launch_bounds__(kBlock) void ka_last(
     }
     {
       const SolveTab* tb[S];
-      const LaneTab* lb[S];
+      const LT* lb[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         tb[s] = at.P(s);
         lb[s] = at.lP(s);
-        if (neu) ends_scale<M>(fb[s], lane, C, 2.0);
+        if (neu) ends_scale<M, P>(fb[s], lane, C, 2.0);
       }
-      line_solve<M, S>(tb, lb, fb, lane);
+      line_solve<M, S, P>(tb, lb, fb, lane);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      if (neu) ends_scale<M>(fb[s], lane, C, 0.5);
-      acc[s] += dsc * lap_dot<M>(fb[s], us[s], lane, C, bc);
-      tile_store<M, kBlockLines>(yw + s * g.N, fb[s], tl, g, pos, cur);
+      if (neu) ends_scale<M, P>(fb[s], lane, C, 0.5);
+      acc[s] += dsc * lap_dot<M, P>(fb[s], us[s], lane, C, bc);
+      tile_store<M, L, P>(yw + s * g.N, fb[s], tl, g, pos, cur);
     }
   }
   block_partials<kBlockLines>(acc, red, part);
@@ -385,18 +399,19 @@ __global__ __launch_bounds__(kBlock) void ka_mid(
 // solve and the transposed solve of the same matrix), one species per work
 // item, so that 16-line tiles fit the register budget.
 // ---------------------------------------------------------------------------
-template <int M, int S, int L>
-__global__ __launch_bounds__(64 * L, 4) void ka_mid_s(
+template <int M, int S, int L, int P>
+__global__ __launch_bounds__(64 * L / P, 4) void ka_mid_s(
     const double* __restrict__ c1, const double* __restrict__ c2, const double* __restrict__ w,
     double* __restrict__ y1, double* __restrict__ y2, double* __restrict__ yw,
     const SolveTab* __restrict__ tabs, PassGeom g, int bc, double dsc, double* __restrict__ part) {
+  using LT = LaneTabT<kSegLanes<P>>;
   extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  LT* lt = reinterpret_cast<LT*>(lds);
+  double* red = lds + (3 * S * sizeof(LT)) / sizeof(double);
   double* tl = red + kRedMax;
-  stage_lane_tabs(tabs, 3 * S, lt);
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
   const int lane = threadIdx.x & 63;
   const int C = g.C;
   const bool neu = (bc == ETD_BC_NEUMANN);
@@ -415,9 +430,9 @@ __global__ __launch_bounds__(64 * L, 4) void ka_mid_s(
       const double* fw = (r == 0 ? c1 : c2) + s * g.N;
       double* bk = (r == 0 ? y1 : y2) + s * g.N;
       double cin[M], yin[M], a[M];
-      line_load<M>(fw, cin, g, pos);
-      tile_load<M, L>(bk, yin, tl, g, pos, cur);
-      if (neu) ends_scale<M>(yin, lane, C, 2.0);
+      line_load<M, P>(fw, cin, g, pos);
+      tile_load<M, L, P>(bk, yin, tl, g, pos, cur);
+      if (neu) ends_scale<M, P>(yin, lane, C, 2.0);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {  // T (gamma 3), then S (gamma 4)
         double x[2][M];
@@ -427,10 +442,10 @@ __global__ __launch_bounds__(64 * L, 4) void ka_mid_s(
           x[1][j] = yin[j];
         }
         const SolveTab* tb[2] = {h == 0 ? at.T(s) : at.Sx(s), h == 0 ? at.T(s) : at.Sx(s)};
-        const LaneTab* lb[2] = {h == 0 ? at.lT(s) : at.lS(s), h == 0 ? at.lT(s) : at.lS(s)};
-        line_solve<M, 2>(tb, lb, x, lane);
-        if (neu) ends_scale<M>(x[1], lane, C, 0.5);
-        const double dot = lap_dot<M>(x[1], x[0], lane, C, bc);
+        const LT* lb[2] = {h == 0 ? at.lT(s) : at.lS(s), h == 0 ? at.lT(s) : at.lS(s)};
+        line_solve<M, 2, P>(tb, lb, x, lane);
+        if (neu) ends_scale<M, P>(x[1], lane, C, 0.5);
+        const double dot = lap_dot<M, P>(x[1], x[0], lane, C, bc);
         if (h == 0) {
           da += (3.0 * dsc) * dot;
 #pragma unroll
@@ -441,53 +456,60 @@ __global__ __launch_bounds__(64 * L, 4) void ka_mid_s(
           for (int j = 0; j < M; ++j) a[j] = fma(9.0, a[j], -8.0 * x[1][j]);
         }
       }
-      tile_store<M, L>(bk, a, tl, g, pos, cur);
+      tile_store<M, L, P>(bk, a, tl, g, pos, cur);
     }
     double y[2][M];
-    line_load<M>(w + s * g.N, y[0], g, pos);
-    tile_load<M, L>(yw + s * g.N, y[1], tl, g, pos, cur);
-    if (neu) ends_scale<M>(y[1], lane, C, 2.0);
+    line_load<M, P>(w + s * g.N, y[0], g, pos);
+    tile_load<M, L, P>(yw + s * g.N, y[1], tl, g, pos, cur);
+    if (neu) ends_scale<M, P>(y[1], lane, C, 2.0);
     const SolveTab* tb[2] = {at.P(s), at.P(s)};
-    const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
-    line_solve<M, 2>(tb, lb, y, lane);
-    if (neu) ends_scale<M>(y[1], lane, C, 0.5);
-    da += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
-    tile_store<M, L>(yw + s * g.N, y[1], tl, g, pos, cur);
+    const LT* lb[2] = {at.lP(s), at.lP(s)};
+    line_solve<M, 2, P>(tb, lb, y, lane);
+    if (neu) ends_scale<M, P>(y[1], lane, C, 0.5);
+    da += dsc * lap_dot<M, P>(y[1], y[0], lane, C, bc);
+    tile_store<M, L, P>(yw + s * g.N, y[1], tl, g, pos, cur);
 #pragma unroll
     for (int q = 0; q < S; ++q) acc[q] += (q == s) ? da : 0.0;
   }
-  block_partials<L>(acc, red, part);
+  block_partials<L / P>(acc, red, part);
 }
 
 // ---------------------------------------------------------------------------
 // Axis 1 (first forward pass).  In: U_n and, in u's layout, the adjoints
 // (b1, b2, bw) of pass 1's outputs (R_1 U, R_1 f, P_1 (U + k f)); out: lam_n.
 // ---------------------------------------------------------------------------
-template <int M, int S>
+template <int M, int S, int P>
 __global__ __launch_bounds__(kBlock) void ka_first(
     const double* __restrict__ u, const double* __restrict__ b1,
     const double* __restrict__ b2, const double* __restrict__ bw,
     double* __restrict__ lam_out, const SolveTab* __restrict__ tabs, Rx rx, double k,
     int64_t n1, int64_t nlines, int64_t N, int bc, double dsc, double* __restrict__ part) {
+  constexpr int L = kBlockLines * P;  // lines per tile
+  using LT = LaneTabT<kSegLanes<P>>;
   extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
-  stage_lane_tabs(tabs, 3 * S, lt);
+  LT* lt = reinterpret_cast<LT*>(lds);
+  double* red = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int C = tabs[0].C;
-  const bool act = lane < C;
+  const int c = seg_chunk<P>(lane);
   const bool neu = (bc == ETD_BC_NEUMANN);
   double acc[kGradSlots];
 #pragma unroll
   for (int q = 0; q < kGradSlots; ++q) acc[q] = 0.0;
-  TileWalk walk((nlines + kBlockLines - 1) / kBlockLines);
+  TileWalk walk((nlines + L - 1) / L);
   int64_t tile;
   while (walk.next(tile)) {
-    const int64_t line = tile * kBlockLines + wv;
-    if (line >= nlines) continue;  // wave-uniform
-    const int64_t off = line * n1 + (int64_t)lane * M;
+    const int64_t line = tile * L + wv * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
+    if constexpr (P == 1) {
+      if (line >= nlines) continue;  // wave-uniform
+    }
+    // (P = 2: a segment past the last line computes on zeros, stores
+    // nothing and adds nothing)
+    const bool act = (c < C) && (line < nlines);
+    const int64_t off = act ? line * n1 + (int64_t)c * M : 0;
     double U[S][M], f[S][M], Ub[S][M], fbar[S][M];
 #pragma unroll
     for (int s = 0; s < S; ++s) load_chunk<M>(u + s * N + off, U[s], act);
@@ -513,18 +535,18 @@ __global__ __launch_bounds__(kBlock) void ka_first(
           x[3][j] = x[2][j];
         }
         if (neu) {
-          ends_scale<M>(x[2], lane, C, 2.0);
-          ends_scale<M>(x[3], lane, C, 2.0);
+          ends_scale<M, P>(x[2], lane, C, 2.0);
+          ends_scale<M, P>(x[3], lane, C, 2.0);
         }
         const SolveTab* tb[4] = {at.T(s), at.Sx(s), at.T(s), at.Sx(s)};
-        const LaneTab* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
-        line_solve<M, 4>(tb, lb, x, lane);
+        const LT* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
+        line_solve<M, 4, P>(tb, lb, x, lane);
         if (neu) {
-          ends_scale<M>(x[2], lane, C, 0.5);
-          ends_scale<M>(x[3], lane, C, 0.5);
+          ends_scale<M, P>(x[2], lane, C, 0.5);
+          ends_scale<M, P>(x[3], lane, C, 0.5);
         }
-        acc[s] += (3.0 * dsc) * lap_dot<M>(x[2], x[0], lane, C, bc) -
-                  (2.0 * dsc) * lap_dot<M>(x[3], x[1], lane, C, bc);
+        acc[s] += (3.0 * dsc) * lap_dot<M, P>(x[2], x[0], lane, C, bc) -
+                  (2.0 * dsc) * lap_dot<M, P>(x[3], x[1], lane, C, bc);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
           const double v = fma(9.0, x[2][j], -8.0 * x[3][j]);
@@ -536,12 +558,12 @@ __global__ __launch_bounds__(kBlock) void ka_first(
       load_chunk<M>(bw + s * N + off, y[1], act);
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[s][j], U[s][j]);
-      if (neu) ends_scale<M>(y[1], lane, C, 2.0);
+      if (neu) ends_scale<M, P>(y[1], lane, C, 2.0);
       const SolveTab* tb[2] = {at.P(s), at.P(s)};
-      const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
-      line_solve<M, 2>(tb, lb, y, lane);
-      if (neu) ends_scale<M>(y[1], lane, C, 0.5);
-      acc[s] += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
+      const LT* lb[2] = {at.lP(s), at.lP(s)};
+      line_solve<M, 2, P>(tb, lb, y, lane);
+      if (neu) ends_scale<M, P>(y[1], lane, C, 0.5);
+      acc[s] += dsc * lap_dot<M, P>(y[1], y[0], lane, C, bc);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         Ub[s][j] += y[1][j];
@@ -600,8 +622,6 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 namespace {
 
-inline size_t adj_fixed_lds(int S) { return lane_lds(3 * S) + sizeof(double) * kRed; }
-
 template <typename KernelT>
 hipError_t adj_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid,
                     int threads = kBlock) {
@@ -616,71 +636,108 @@ hipError_t adj_grid(KernelT kern, size_t lds, int64_t ntiles, unsigned* grid,
 double d_scale(const etd_rdp_ctx* c, int axis0) { return -c->k / (c->h[axis0] * c->h[axis0]); }
 
 // Chunk lengths up to which the axis-2 reverse pass runs streamed (ka_mid_s,
-// 16-line tiles); longer chunks keep ka_mid.  (Streamed forms of the other
+// 16-wave blocks); longer chunks keep ka_mid.  (Streamed forms of the other
 // two reverse passes spill at 128 registers and measured slower.)
 constexpr int kAdjStreamMidTo = 2;
-constexpr int kAdjStreamLines = 16;
-inline size_t adj_fixed_lds_s(int S) { return lane_lds(3 * S) + sizeof(double) * kRedMax; }
+constexpr int kAdjStreamWaves = 16;
+template <int P>
+inline size_t adj_fixed_lds(int S) {
+  return lane_lds<kSegLanes<P>>(3 * S) + sizeof(double) * kRed;
+}
+template <int P>
+inline size_t adj_fixed_lds_s(int S) {
+  return lane_lds<kSegLanes<P>>(3 * S) + sizeof(double) * kRedMax;
+}
 
-template <int M, int S>
+// Lines per wavefront of the reverse pass over axis a: two where the forward
+// passes run two (n = 32 m) and the chunks are short enough for the reverse
+// kernels' registers, else one.  Axis 1 (ka_first, which holds U, U-bar and
+// f-bar of every species) keeps one: at 128^3 its two-line form (chunks of
+// 4 rows) spills and took 163 us against 129 us, while ka_last went from 125
+// to 89 us and ka_mid_s from 146 to 128 us with two lines.
+constexpr int kAdjTwoLineMaxM = 4;
+inline int adj_lines(const etd_rdp_ctx* c, int a) {
+  return (a > 0 && c->P[a] == 2 && c->m[a] <= kAdjTwoLineMaxM) ? 2 : 1;
+}
+// The tables of axis a for P lines per wavefront: the forward set (two
+// lines) or the one-line set.
+inline const SolveTab* adj_tabs(const etd_rdp_ctx* c, const SolveTab* tabs, int a, int P) {
+  return tabs + (P == 2 ? 0 : c->tab1) + tab_index(a, 0, 0, c->s);
+}
+
+template <int M, int S, int P>
 hipError_t launch_ka_mid_s(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&Y)[3],
                            const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
-  constexpr int L = kAdjStreamLines;
+  constexpr int W = kAdjStreamWaves;
+  constexpr int L = W * P;
   const int a = 1;
-  const size_t fixed = adj_fixed_lds_s(S);
-  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, L, true);
+  const size_t fixed = adj_fixed_lds_s<P>(S);
+  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, L, P == 1);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = adj_grid(ka_mid_s<M, S, L>, lds, g.nFblk * g.nT * S, nblk, 64 * L);
+  hipError_t e = adj_grid(ka_mid_s<M, S, L, P>, lds, g.nFblk * g.nT * S, nblk, 64 * W);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((ka_mid_s<M, S, L>), dim3(*nblk), dim3(64 * L), lds, st, A[0], A[1], A[2],
-                     Y[0], Y[1], Y[2], tabs, g, c->bc[a], d_scale(c, a), part);
+  hipLaunchKernelGGL((ka_mid_s<M, S, L, P>), dim3(*nblk), dim3(64 * W), lds, st, A[0], A[1],
+                     A[2], Y[0], Y[1], Y[2], tabs, g, c->bc[a], d_scale(c, a), part);
   return hipGetLastError();
 }
 
-template <int M, int S>
+template <int M, int S, int P>
 hipError_t launch_ka_last(const etd_rdp_ctx* c, double* const (&X)[3], const double* lam,
                           double* const (&Y)[3], const SolveTab* tabs, double* part,
                           unsigned* nblk, hipStream_t st) {
   const int a = c->d - 1;
-  const size_t fixed = adj_fixed_lds(S);
-  const PassGeom g = pass_geom(c, kPassLast, fixed, kBlockLines, true);
+  const size_t fixed = adj_fixed_lds<P>(S);
+  const PassGeom g = pass_geom(c, kPassLast, fixed, kBlockLines * P, P == 1);
   const size_t lds = pass_lds(g, fixed);
-  hipError_t e = adj_grid(ka_last<M, S>, lds, g.nFblk * g.nT, nblk);
+  hipError_t e = adj_grid(ka_last<M, S, P>, lds, g.nFblk * g.nT, nblk);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((ka_last<M, S>), dim3(*nblk), dim3(kBlock), lds, st, X[0], X[1], X[2], lam,
-                     Y[0], Y[1], Y[2], tabs, c->rx, c->k, g, c->bc[a], d_scale(c, a), part);
+  hipLaunchKernelGGL((ka_last<M, S, P>), dim3(*nblk), dim3(kBlock), lds, st, X[0], X[1], X[2],
+                     lam, Y[0], Y[1], Y[2], tabs, c->rx, c->k, g, c->bc[a], d_scale(c, a), part);
   return hipGetLastError();
 }
 
 template <int M, int S>
 hipError_t launch_ka_mid(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&Y)[3],
                          const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
-  if constexpr (M <= kAdjStreamMidTo) return launch_ka_mid_s<M, S>(c, A, Y, tabs, part, nblk, st);
-  const int a = 1;
-  const size_t fixed = adj_fixed_lds(S);
-  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, kBlockLines, true);
-  const size_t lds = pass_lds(g, fixed);
-  hipError_t e = adj_grid(ka_mid<M, S>, lds, g.nFblk * g.nT, nblk);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((ka_mid<M, S>), dim3(*nblk), dim3(kBlock), lds, st, A[0], A[1], A[2], Y[0],
-                     Y[1], Y[2], tabs, g, c->bc[a], d_scale(c, a), part);
-  return hipGetLastError();
+  if constexpr (M <= kAdjStreamMidTo) {
+    return launch_ka_mid_s<M, S, 1>(c, A, Y, tabs, part, nblk, st);
+  } else {
+    const int a = 1;
+    const size_t fixed = adj_fixed_lds<1>(S);
+    const PassGeom g = pass_geom(c, kPassAdjMid, fixed, kBlockLines, true);
+    const size_t lds = pass_lds(g, fixed);
+    hipError_t e = adj_grid(ka_mid<M, S>, lds, g.nFblk * g.nT, nblk);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ka_mid<M, S>), dim3(*nblk), dim3(kBlock), lds, st, A[0], A[1], A[2], Y[0],
+                       Y[1], Y[2], tabs, g, c->bc[a], d_scale(c, a), part);
+    return hipGetLastError();
+  }
 }
 
-template <int M, int S>
+template <int M, int S, int P>
 hipError_t launch_ka_first(const etd_rdp_ctx* c, const double* u, double* const (&A)[3],
                            double* lam_out, const SolveTab* tabs, double* part, unsigned* nblk,
                            hipStream_t st) {
-
   const int64_t nlines = c->N / c->n[0];
-  const size_t lds = adj_fixed_lds(S);
-  hipError_t e = adj_grid(ka_first<M, S>, lds, (nlines + kBlockLines - 1) / kBlockLines, nblk);
+  constexpr int L = kBlockLines * P;
+  const size_t lds = adj_fixed_lds<P>(S);
+  hipError_t e = adj_grid(ka_first<M, S, P>, lds, (nlines + L - 1) / L, nblk);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((ka_first<M, S>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1], A[2],
+  hipLaunchKernelGGL((ka_first<M, S, P>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1], A[2],
                      lam_out, tabs, c->rx, c->k, c->n[0], nlines, c->N, c->bc[0], d_scale(c, 0),
                      part);
   return hipGetLastError();
 }
+
+// Runtime chunk length -> template dispatch of the two-line reverse kernels
+// (chunks of 2..kAdjTwoLineMaxM rows).
+#define ETD_DISPATCH_M2(m, CALL) \
+  switch (m) {                   \
+    case 2: { constexpr int M_ = 2; CALL; } break; \
+    case 3: { constexpr int M_ = 3; CALL; } break; \
+    case 4: { constexpr int M_ = 4; CALL; } break; \
+    default: return ETD_ERR_INTERNAL;               \
+  }
 
 int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* lam_out,
                 double* grad, void* ws, hipStream_t st) {
@@ -702,29 +759,41 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
   unsigned nb[kAdjPasses] = {0, 0, 0};
   hipError_t e = hipSuccess;
   // Axis d: reads the triple pass d reads (B in 3-D, A in 2-D) and lam.
+  // Each axis runs one or two lines per wavefront (adj_lines) with the
+  // matching tables.
   {
-    const int a = c->d - 1, m = c->m1[a];
-    const SolveTab* ta = tabs + c->tab1 + tab_index(a, 0, 0, S);
+    const int a = c->d - 1, P = adj_lines(c, a), m = (P == 2) ? c->m[a] : c->m1[a];
+    const SolveTab* ta = adj_tabs(c, tabs, a, P);
     double* const(&X)[3] = (c->d == 3) ? B : A;
     double* pp = part;
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 1>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 2>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
+    if (P == 2) {
+      if (S == 1) { ETD_DISPATCH_M2(m, e = (launch_ka_last<M_, 1, 2>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
+      else { ETD_DISPATCH_M2(m, e = (launch_ka_last<M_, 2, 2>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
+    } else {
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 1, 1>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_ka_last<M_, 2, 1>(c, X, lam_in, Y, ta, pp, &nb[0], st))); }
+    }
     if (e != hipSuccess) return hip_fail(c, e);
   }
   if (c->d == 3) {
-    const int m = c->m1[1];
-    const SolveTab* ta = tabs + c->tab1 + tab_index(1, 0, 0, S);
+    const int P = adj_lines(c, 1), m = (P == 2) ? c->m[1] : c->m1[1];
+    const SolveTab* ta = adj_tabs(c, tabs, 1, P);
     double* pp = part + (size_t)kAdjMaxBlocks * kGradSlots;
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 1>(c, A, Y, ta, pp, &nb[1], st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 2>(c, A, Y, ta, pp, &nb[1], st))); }
+    if (P == 2) {
+      if (S == 1) { ETD_DISPATCH_M2(m, e = (launch_ka_mid_s<M_, 1, 2>(c, A, Y, ta, pp, &nb[1], st))); }
+      else { ETD_DISPATCH_M2(m, e = (launch_ka_mid_s<M_, 2, 2>(c, A, Y, ta, pp, &nb[1], st))); }
+    } else {
+      if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 1>(c, A, Y, ta, pp, &nb[1], st))); }
+      else { ETD_DISPATCH_M(m, e = (launch_ka_mid<M_, 2>(c, A, Y, ta, pp, &nb[1], st))); }
+    }
     if (e != hipSuccess) return hip_fail(c, e);
   }
   {
     const int m = c->m1[0];
-    const SolveTab* ta = tabs + c->tab1 + tab_index(0, 0, 0, S);
+    const SolveTab* ta = adj_tabs(c, tabs, 0, 1);
     double* pp = part + 2 * (size_t)kAdjMaxBlocks * kGradSlots;
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
-    else { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 2>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
+    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
+    else { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 2, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
     if (e != hipSuccess) return hip_fail(c, e);
   }
   hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, part, (int)nb[0], (int)nb[1],

@@ -158,12 +158,16 @@ bool form_allowed(const etd_rdp_batch* b, const Group& g, int pass, int form) {
   return false;
 }
 
-// The default plan: the single-problem rules (two lines per wavefront for
-// passes of at least kTwoLineMinLines lines, streamed from the chunk lengths
-// where the single-problem passes switch).
+// Lines of a group's pass from which the default plan takes two lines per
+// wavefront (the autotuner decides per device).
+constexpr int64_t kGroupTwoLineMinLines = 32768;
+
+// The default plan: two lines per wavefront for passes of at least
+// kGroupTwoLineMinLines lines, streamed from the chunk lengths where the
+// single-problem passes switch.
 int default_form(const etd_rdp_batch* b, const Group& g, int pass) {
   const int64_t lines = static_cast<int64_t>(g.inst.size()) * (pass == 0 ? g.n2 : g.n1);
-  if (lines >= kTwoLineMinLines && form_allowed(b, g, pass, kFormTwoLine)) return kFormTwoLine;
+  if (lines >= kGroupTwoLineMinLines && form_allowed(b, g, pass, kFormTwoLine)) return kFormTwoLine;
   const int from = (pass == 0) ? 8 : 5;
   if (g.m1[pass] >= from && form_allowed(b, g, pass, kFormStreamed)) return kFormStreamed;
   return kFormUnsplit;

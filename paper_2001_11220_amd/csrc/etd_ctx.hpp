@@ -78,8 +78,10 @@ inline size_t elem_bytes(const etd_rdp_ctx* c) {
 // 0 when the axis runs one line per wavefront.
 constexpr int kMinTwoLineM = 2;
 // Lines a pass needs before ETD_LINES_AUTO takes two lines per wavefront:
-// 1024 tiles of 32 lines, four per block of a persistent grid.
-constexpr int64_t kTwoLineMinLines = 32768;
+// 256 tiles of 32 lines.  Measured (3-D Schnakenberg, one step): 96^3 (9216
+// lines per pass) 125 -> 102 us and 128^3 174 -> 129 us with two lines,
+// but 64^3 (4096 lines) 52 -> 57 us and 2-D grids of 256 lines 33 -> 43 us.
+constexpr int64_t kTwoLineMinLines = 8192;
 inline int two_line_chunk(int64_t n) {
   const int64_t m = n / 32;
   return (n % 32 == 0 && m >= kMinTwoLineM && m <= kMaxRegularM) ? static_cast<int>(m) : 0;

@@ -715,7 +715,9 @@ __device__ __forceinline__ void tile_fetch(const double* __restrict__ A, double 
   }
 }
 
-template <int M, int L>
+// P lines per wavefront: lane c of segment q of wave w takes chunk c of the
+// tile's line w*P + q (as tile_store writes them).
+template <int M, int L, int P = 1>
 __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M], double* lds,
                                             const PassGeom& g, TileCursor& cur) {
   const int tid = threadIdx.x;
@@ -727,8 +729,10 @@ __device__ __forceinline__ void tile_commit(const double (&r)[M], double (&x)[M]
   }
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63;
+  const int c = (P == 1) ? lane : (lane & (kSegLanes<P> - 1));
+  const int li = w * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
 #pragma unroll
-  for (int j = 0; j < M; ++j) x[j] = (lane < g.C) ? T[w * g.pitch + j * g.C + lane] : 0.0;
+  for (int j = 0; j < M; ++j) x[j] = (c < g.C) ? T[li * g.pitch + j * g.C + c] : 0.0;
   if (g.nbuf == 1) __syncthreads();
   else cur.buf ^= 1;
 }

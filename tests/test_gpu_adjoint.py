@@ -50,6 +50,16 @@ CASES = {
                          "brusselator", {"a": 1.0, "b": 3.4}, None, (1.0, 3.4)),
     "gs2d_two_line": ((256, 160), ("periodic", "neumann"), (2e-5, 1e-5), 1.0, "gray_scott",
                       {"F": 0.04, "kappa": 0.06}, None, (0.7, 0.2)),
+    # forward recompute and reverse passes with two lines per wavefront
+    # (chunks of 2, 3, 4 rows: n = 64, 96, 128)
+    "schnak3d_rev_two_line": ((128, 64, 96), ("neumann", "periodic", "dirichlet"), (1.0, 10.0), 1e-3,
+                              "schnakenberg", SCHNAK, None, (1.0, 0.9)),
+    "bruss3d_rev_two_line": ((96, 128, 64), ("dirichlet", "neumann", "periodic"), (0.02, 0.011), 0.05,
+                             "brusselator", {"a": 1.0, "b": 3.4}, None, (1.0, 3.4)),
+    "lin1_3d_rev_two_line": ((64, 96, 128), ("periodic", "dirichlet", "neumann"), (0.02,), 0.04, "linear",
+                             {"C": [[-0.7]]}, None, (0.0,)),
+    "gs2d_rev_two_line": ((128, 96), ("periodic", "neumann"), (2e-5, 1e-5), 1.0, "gray_scott",
+                          {"F": 0.04, "kappa": 0.06}, None, (0.7, 0.2)),
 }
 
 
