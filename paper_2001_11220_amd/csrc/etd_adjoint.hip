@@ -592,6 +592,136 @@ __global__ __launch_bounds__(kBlock) void ka_first(
   block_partials<kBlockLines>(acc, red, part);
 }
 
+// ---------------------------------------------------------------------------
+// Axis 1 with two species, one wavefront per (line, species): the waves of a
+// pair hold the same line; each evaluates F(U) at its rows, runs its own
+// species' ten solves, and the pair swaps f-bar through LDS for the final
+// J(U)^T product (the only step that couples the species).  Half the
+// registers and half the serial solves per wave of ka_first, twice the
+// waves per line.  The parameter gradient of that product is taken by the
+// species-0 wave alone.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void ka_first_sp(
+    const double* __restrict__ u, const double* __restrict__ b1,
+    const double* __restrict__ b2, const double* __restrict__ bw,
+    double* __restrict__ lam_out, const SolveTab* __restrict__ tabs, Rx rx, double k,
+    int64_t n1, int64_t nlines, int64_t N, int bc, double dsc, double* __restrict__ part) {
+  constexpr int S = 2;
+  constexpr int L = kBlockLines / S;  // lines per tile
+  extern __shared__ double lds[];
+  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
+  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
+  double* xch = red + kRed;  // [line slot][species][row][lane]
+  stage_lane_tabs(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S> at{tabs, lt};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // wave-uniform (scalar) species and line slot, so that the species'
+  // table headers load into scalar registers
+  const int s = __builtin_amdgcn_readfirstlane(wv & 1);
+  const int slot = __builtin_amdgcn_readfirstlane(wv >> 1);
+  const int C = tabs[0].C;
+  const bool neu = (bc == ETD_BC_NEUMANN);
+  double acc[kGradSlots];
+#pragma unroll
+  for (int q = 0; q < kGradSlots; ++q) acc[q] = 0.0;
+  TileWalk walk((nlines + L - 1) / L);
+  int64_t tile;
+  while (walk.next(tile)) {
+    const int64_t line = tile * L + slot;
+    // a pair past the last line still takes part in the barriers below
+    const bool act = (lane < C) && (line < nlines);
+    const int64_t off = act ? line * n1 + (int64_t)lane * M : 0;
+    double U[S][M], f[M], Ub[M], fb[M];
+#pragma unroll
+    for (int q = 0; q < S; ++q) load_chunk<M>(u + q * N + off, U[q], act);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double uu[S], ff[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) uu[q] = U[q][j];
+      react<S>(rx, uu, ff);
+      f[j] = s ? ff[1] : ff[0];
+    }
+    const double* Us = s ? U[1] : U[0];
+    double da = 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {  // R_1 U, then R_1 f
+      double x[4][M];
+      load_chunk<M>((r == 0 ? b1 : b2) + s * N + off, x[2], act);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        x[0][j] = (r == 0) ? Us[j] : f[j];
+        x[1][j] = x[0][j];
+        x[3][j] = x[2][j];
+      }
+      if (neu) {
+        ends_scale<M>(x[2], lane, C, 2.0);
+        ends_scale<M>(x[3], lane, C, 2.0);
+      }
+      const SolveTab* tb[4] = {at.T(s), at.Sx(s), at.T(s), at.Sx(s)};
+      const LaneTab* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
+      line_solve<M, 4>(tb, lb, x, lane);
+      if (neu) {
+        ends_scale<M>(x[2], lane, C, 0.5);
+        ends_scale<M>(x[3], lane, C, 0.5);
+      }
+      da += (3.0 * dsc) * lap_dot<M>(x[2], x[0], lane, C, bc) -
+            (2.0 * dsc) * lap_dot<M>(x[3], x[1], lane, C, bc);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const double v = fma(9.0, x[2][j], -8.0 * x[3][j]);
+        if (r == 0) Ub[j] = v;
+        else fb[j] = v;
+      }
+    }
+    {
+      double y[2][M];
+      load_chunk<M>(bw + s * N + off, y[1], act);
+#pragma unroll
+      for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], Us[j]);
+      if (neu) ends_scale<M>(y[1], lane, C, 2.0);
+      const SolveTab* tb[2] = {at.P(s), at.P(s)};
+      const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
+      line_solve<M, 2>(tb, lb, y, lane);
+      if (neu) ends_scale<M>(y[1], lane, C, 0.5);
+      da += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        Ub[j] += y[1][j];
+        fb[j] = fma(k, y[1][j], fb[j]);
+      }
+    }
+    acc[0] += s ? 0.0 : da;
+    acc[1] += s ? da : 0.0;
+    // swap f-bar with the pair's other wave
+    double* mine = xch + ((slot * S + s) * M) * 64;
+    const double* other = xch + ((slot * S + (1 - s)) * M) * 64;
+#pragma unroll
+    for (int j = 0; j < M; ++j) mine[j * 64 + lane] = fb[j];
+    __syncthreads();
+    double fo[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) fo[j] = other[j * 64 + lane];
+    __syncthreads();  // the next tile overwrites the exchange
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double uu[S], ff[S], jt[S], gp[kGradSlots - S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) uu[q] = U[q][j];
+      ff[0] = s ? fo[j] : fb[j];
+      ff[1] = s ? fb[j] : fo[j];
+      react_adj<S>(rx, uu, ff, jt, gp);
+      Ub[j] += s ? jt[1] : jt[0];
+#pragma unroll
+      for (int q = 0; q < kGradSlots - S; ++q) acc[S + q] += (act && s == 0) ? gp[q] : 0.0;
+    }
+    if (act) store_chunk<M>(lam_out + s * N + off, Ub);
+  }
+  block_partials<kBlockLines>(acc, red, part);
+}
+
 // grad[q] += sum over passes p < npass and blocks b < nblk[p] of
 // part[p][b][q], q < nq, in a fixed order.  One block of 256 threads.
 __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ part, int nb0,
@@ -714,11 +844,28 @@ hipError_t launch_ka_mid(const etd_rdp_ctx* c, double* const (&A)[3], double* co
   }
 }
 
+// Chunk lengths from which two-species axis-1 reverse passes run one
+// wavefront per (line, species) (ka_first_sp): at 256^3 (chunks of 4 rows)
+// the reverse step went 3.44 -> 3.14 ms; with chunks of 2 rows (128^3)
+// ka_first_sp took 157 us against ka_first's 129 us.
+constexpr int kAdjSpeciesWavesFromM = 3;
+
 template <int M, int S, int P>
 hipError_t launch_ka_first(const etd_rdp_ctx* c, const double* u, double* const (&A)[3],
                            double* lam_out, const SolveTab* tabs, double* part, unsigned* nblk,
                            hipStream_t st) {
   const int64_t nlines = c->N / c->n[0];
+  if constexpr (S == 2 && P == 1 && M >= kAdjSpeciesWavesFromM) {
+    // one wavefront per (line, species)
+    constexpr int L = kBlockLines / S;
+    const size_t lds = adj_fixed_lds<1>(S) + sizeof(double) * kBlockLines * M * 64;
+    hipError_t e = adj_grid(ka_first_sp<M>, lds, (nlines + L - 1) / L, nblk);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ka_first_sp<M>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1], A[2],
+                       lam_out, tabs, c->rx, c->k, c->n[0], nlines, c->N, c->bc[0],
+                       d_scale(c, 0), part);
+    return hipGetLastError();
+  }
   constexpr int L = kBlockLines * P;
   const size_t lds = adj_fixed_lds<P>(S);
   hipError_t e = adj_grid(ka_first<M, S, P>, lds, (nlines + L - 1) / L, nblk);
