@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void ka_mid(
 // item, so that 16-line tiles fit the register budget.
 // ---------------------------------------------------------------------------
 template <int M, int S, int L, int P>
-__global__ __launch_bounds__(64 * L / P, 4) void ka_mid_s(
+__global__ __launch_bounds__(64 * L / P, (L / P >= 16 ? 4 : 3)) void ka_mid_s(
     const double* __restrict__ c1, const double* __restrict__ c2, const double* __restrict__ w,
     double* __restrict__ y1, double* __restrict__ y2, double* __restrict__ yw,
     const SolveTab* __restrict__ tabs, PassGeom g, int bc, double dsc, double* __restrict__ part) {
@@ -601,27 +601,29 @@ __global__ __launch_bounds__(kBlock) void ka_first(
 // waves per line.  The parameter gradient of that product is taken by the
 // species-0 wave alone.
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, int P>
 __global__ __launch_bounds__(kBlock) void ka_first_sp(
     const double* __restrict__ u, const double* __restrict__ b1,
     const double* __restrict__ b2, const double* __restrict__ bw,
     double* __restrict__ lam_out, const SolveTab* __restrict__ tabs, Rx rx, double k,
     int64_t n1, int64_t nlines, int64_t N, int bc, double dsc, double* __restrict__ part) {
   constexpr int S = 2;
-  constexpr int L = kBlockLines / S;  // lines per tile
+  constexpr int L = kBlockLines / S * P;  // lines per tile
+  using LT = LaneTabT<kSegLanes<P>>;
   extern __shared__ double lds[];
-  LaneTab* lt = reinterpret_cast<LaneTab*>(lds);
-  double* red = lds + (3 * S * sizeof(LaneTab)) / sizeof(double);
-  double* xch = red + kRed;  // [line slot][species][row][lane]
-  stage_lane_tabs(tabs, 3 * S, lt);
+  LT* lt = reinterpret_cast<LT*>(lds);
+  double* red = lds + (3 * S * sizeof(LT)) / sizeof(double);
+  double* xch = red + kRed;  // [wave pair][species][row][lane]
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>> at{tabs, lt};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // wave-uniform (scalar) species and line slot, so that the species'
   // table headers load into scalar registers
   const int s = __builtin_amdgcn_readfirstlane(wv & 1);
   const int slot = __builtin_amdgcn_readfirstlane(wv >> 1);
   const int C = tabs[0].C;
+  const int c = seg_chunk<P>(lane);
   const bool neu = (bc == ETD_BC_NEUMANN);
   double acc[kGradSlots];
 #pragma unroll
@@ -629,10 +631,10 @@ __global__ __launch_bounds__(kBlock) void ka_first_sp(
   TileWalk walk((nlines + L - 1) / L);
   int64_t tile;
   while (walk.next(tile)) {
-    const int64_t line = tile * L + slot;
+    const int64_t line = tile * L + slot * P + ((P == 1) ? 0 : lane / kSegLanes<P>);
     // a pair past the last line still takes part in the barriers below
-    const bool act = (lane < C) && (line < nlines);
-    const int64_t off = act ? line * n1 + (int64_t)lane * M : 0;
+    const bool act = (c < C) && (line < nlines);
+    const int64_t off = act ? line * n1 + (int64_t)c * M : 0;
     double U[S][M], f[M], Ub[M], fb[M];
 #pragma unroll
     for (int q = 0; q < S; ++q) load_chunk<M>(u + q * N + off, U[q], act);
@@ -657,18 +659,18 @@ __global__ __launch_bounds__(kBlock) void ka_first_sp(
         x[3][j] = x[2][j];
       }
       if (neu) {
-        ends_scale<M>(x[2], lane, C, 2.0);
-        ends_scale<M>(x[3], lane, C, 2.0);
+        ends_scale<M, P>(x[2], lane, C, 2.0);
+        ends_scale<M, P>(x[3], lane, C, 2.0);
       }
       const SolveTab* tb[4] = {at.T(s), at.Sx(s), at.T(s), at.Sx(s)};
-      const LaneTab* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
-      line_solve<M, 4>(tb, lb, x, lane);
+      const LT* lb[4] = {at.lT(s), at.lS(s), at.lT(s), at.lS(s)};
+      line_solve<M, 4, P>(tb, lb, x, lane);
       if (neu) {
-        ends_scale<M>(x[2], lane, C, 0.5);
-        ends_scale<M>(x[3], lane, C, 0.5);
+        ends_scale<M, P>(x[2], lane, C, 0.5);
+        ends_scale<M, P>(x[3], lane, C, 0.5);
       }
-      da += (3.0 * dsc) * lap_dot<M>(x[2], x[0], lane, C, bc) -
-            (2.0 * dsc) * lap_dot<M>(x[3], x[1], lane, C, bc);
+      da += (3.0 * dsc) * lap_dot<M, P>(x[2], x[0], lane, C, bc) -
+            (2.0 * dsc) * lap_dot<M, P>(x[3], x[1], lane, C, bc);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const double v = fma(9.0, x[2][j], -8.0 * x[3][j]);
@@ -681,12 +683,12 @@ __global__ __launch_bounds__(kBlock) void ka_first_sp(
       load_chunk<M>(bw + s * N + off, y[1], act);
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], Us[j]);
-      if (neu) ends_scale<M>(y[1], lane, C, 2.0);
+      if (neu) ends_scale<M, P>(y[1], lane, C, 2.0);
       const SolveTab* tb[2] = {at.P(s), at.P(s)};
-      const LaneTab* lb[2] = {at.lP(s), at.lP(s)};
-      line_solve<M, 2>(tb, lb, y, lane);
-      if (neu) ends_scale<M>(y[1], lane, C, 0.5);
-      da += dsc * lap_dot<M>(y[1], y[0], lane, C, bc);
+      const LT* lb[2] = {at.lP(s), at.lP(s)};
+      line_solve<M, 2, P>(tb, lb, y, lane);
+      if (neu) ends_scale<M, P>(y[1], lane, C, 0.5);
+      da += dsc * lap_dot<M, P>(y[1], y[0], lane, C, bc);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         Ub[j] += y[1][j];
@@ -723,28 +725,23 @@ __global__ __launch_bounds__(kBlock) void ka_first_sp(
 }
 
 // grad[q] += sum over passes p < npass and blocks b < nblk[p] of
-// part[p][b][q], q < nq, in a fixed order.  One block of 256 threads.
-__global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ part, int nb0,
-                                                     int nb1, int nb2, int nq,
-                                                     double* __restrict__ grad) {
-  __shared__ double sh[256];
-  const int tid = threadIdx.x;
+// part[p][b][q], q < nq <= kGradSlots, in a fixed order: one wavefront per
+// q (lane l adds blocks l, l + 64, ... of each pass, then a butterfly over
+// the lanes), one block of kGradSlots wavefronts.
+__global__ __launch_bounds__(64 * kGradSlots) void k_grad_reduce(const double* __restrict__ part,
+                                                                 int nb0, int nb1, int nb2, int nq,
+                                                                 double* __restrict__ grad) {
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (q >= nq) return;  // whole wavefronts; no barrier follows
   const int nb[kAdjPasses] = {nb0, nb1, nb2};
-  for (int q = 0; q < nq; ++q) {
-    double t = 0.0;
-    for (int p = 0; p < kAdjPasses; ++p) {
-      const double* src = part + (int64_t)p * kAdjMaxBlocks * kGradSlots;
-      for (int b = tid; b < nb[p]; b += 256) t += src[(int64_t)b * kGradSlots + q];
-    }
-    sh[tid] = t;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) sh[tid] += sh[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) grad[q] += sh[0];
-    __syncthreads();
+  double t = 0.0;
+  for (int p = 0; p < kAdjPasses; ++p) {
+    const double* src = part + (int64_t)p * kAdjMaxBlocks * kGradSlots;
+    for (int b = lane; b < nb[p]; b += 64) t += src[(int64_t)b * kGradSlots + q];
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) grad[q] += t;
 }
 
 // ---------------------------------------------------------------------------
@@ -770,6 +767,10 @@ double d_scale(const etd_rdp_ctx* c, int axis0) { return -c->k / (c->h[axis0] * 
 // two reverse passes spill at 128 registers and measured slower.)
 constexpr int kAdjStreamMidTo = 2;
 constexpr int kAdjStreamWaves = 16;
+// Waves per block of ka_mid_s: 16 (4 per SIMD, 128 registers), or 8 (2 per
+// SIMD, 256 registers) for two-line chunks of 3-4 rows, which spill at 128.
+template <int M, int P>
+constexpr int kAdjMidWaves = (P == 2 && M >= 3) ? 4 : kAdjStreamWaves;
 template <int P>
 inline size_t adj_fixed_lds(int S) {
   return lane_lds<kSegLanes<P>>(3 * S) + sizeof(double) * kRed;
@@ -781,13 +782,15 @@ inline size_t adj_fixed_lds_s(int S) {
 
 // Lines per wavefront of the reverse pass over axis a: two where the forward
 // passes run two (n = 32 m) and the chunks are short enough for the reverse
-// kernels' registers, else one.  Axis 1 (ka_first, which holds U, U-bar and
-// f-bar of every species) keeps one: at 128^3 its two-line form (chunks of
-// 4 rows) spills and took 163 us against 129 us, while ka_last went from 125
-// to 89 us and ka_mid_s from 146 to 128 us with two lines.
+// kernels' registers, else one.  At 128^3 (chunks of 4 rows with two
+// lines) ka_last went from 125 to 89 us and ka_mid_s from 146 to 128 us.
+// Axis 1 takes two lines only with two species, in ka_first_sp (one
+// wavefront per line pair and species): ka_first's two-line form, which
+// holds U, U-bar and f-bar of every species, spills and took 163 us
+// against 129 us with one line.
 constexpr int kAdjTwoLineMaxM = 4;
 inline int adj_lines(const etd_rdp_ctx* c, int a) {
-  return (a > 0 && c->P[a] == 2 && c->m[a] <= kAdjTwoLineMaxM) ? 2 : 1;
+  return ((a > 0 || c->s == 2) && c->P[a] == 2 && c->m[a] <= kAdjTwoLineMaxM) ? 2 : 1;
 }
 // The tables of axis a for P lines per wavefront: the forward set (two
 // lines) or the one-line set.
@@ -798,7 +801,7 @@ inline const SolveTab* adj_tabs(const etd_rdp_ctx* c, const SolveTab* tabs, int 
 template <int M, int S, int P>
 hipError_t launch_ka_mid_s(const etd_rdp_ctx* c, double* const (&A)[3], double* const (&Y)[3],
                            const SolveTab* tabs, double* part, unsigned* nblk, hipStream_t st) {
-  constexpr int W = kAdjStreamWaves;
+  constexpr int W = kAdjMidWaves<M, P>;
   constexpr int L = W * P;
   const int a = 1;
   const size_t fixed = adj_fixed_lds_s<P>(S);
@@ -855,25 +858,26 @@ hipError_t launch_ka_first(const etd_rdp_ctx* c, const double* u, double* const 
                            double* lam_out, const SolveTab* tabs, double* part, unsigned* nblk,
                            hipStream_t st) {
   const int64_t nlines = c->N / c->n[0];
-  if constexpr (S == 2 && P == 1 && M >= kAdjSpeciesWavesFromM) {
-    // one wavefront per (line, species)
-    constexpr int L = kBlockLines / S;
-    const size_t lds = adj_fixed_lds<1>(S) + sizeof(double) * kBlockLines * M * 64;
-    hipError_t e = adj_grid(ka_first_sp<M>, lds, (nlines + L - 1) / L, nblk);
+  if constexpr (S == 2 && (P == 2 || M >= kAdjSpeciesWavesFromM)) {
+    // one wavefront per (line or line pair, species)
+    constexpr int L = kBlockLines / S * P;
+    const size_t lds = adj_fixed_lds<P>(S) + sizeof(double) * kBlockLines * M * 64;
+    hipError_t e = adj_grid(ka_first_sp<M, P>, lds, (nlines + L - 1) / L, nblk);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ka_first_sp<M>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1], A[2],
-                       lam_out, tabs, c->rx, c->k, c->n[0], nlines, c->N, c->bc[0],
+    hipLaunchKernelGGL((ka_first_sp<M, P>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1],
+                       A[2], lam_out, tabs, c->rx, c->k, c->n[0], nlines, c->N, c->bc[0],
+                       d_scale(c, 0), part);
+    return hipGetLastError();
+  } else {
+    constexpr int L = kBlockLines * P;
+    const size_t lds = adj_fixed_lds<P>(S);
+    hipError_t e = adj_grid(ka_first<M, S, P>, lds, (nlines + L - 1) / L, nblk);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ka_first<M, S, P>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1],
+                       A[2], lam_out, tabs, c->rx, c->k, c->n[0], nlines, c->N, c->bc[0],
                        d_scale(c, 0), part);
     return hipGetLastError();
   }
-  constexpr int L = kBlockLines * P;
-  const size_t lds = adj_fixed_lds<P>(S);
-  hipError_t e = adj_grid(ka_first<M, S, P>, lds, (nlines + L - 1) / L, nblk);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((ka_first<M, S, P>), dim3(*nblk), dim3(kBlock), lds, st, u, A[0], A[1], A[2],
-                     lam_out, tabs, c->rx, c->k, c->n[0], nlines, c->N, c->bc[0], d_scale(c, 0),
-                     part);
-  return hipGetLastError();
 }
 
 // Runtime chunk length -> template dispatch of the two-line reverse kernels
@@ -936,14 +940,15 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
     if (e != hipSuccess) return hip_fail(c, e);
   }
   {
-    const int m = c->m1[0];
-    const SolveTab* ta = adj_tabs(c, tabs, 0, 1);
+    const int P = adj_lines(c, 0), m = (P == 2) ? c->m[0] : c->m1[0];
+    const SolveTab* ta = adj_tabs(c, tabs, 0, P);
     double* pp = part + 2 * (size_t)kAdjMaxBlocks * kGradSlots;
-    if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
+    if (P == 2) { ETD_DISPATCH_M2(m, e = (launch_ka_first<M_, 2, 2>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
+    else if (S == 1) { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 1, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
     else { ETD_DISPATCH_M(m, e = (launch_ka_first<M_, 2, 1>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }
     if (e != hipSuccess) return hip_fail(c, e);
   }
-  hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, part, (int)nb[0], (int)nb[1],
+  hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(64 * kGradSlots), 0, st, part, (int)nb[0], (int)nb[1],
                      (int)nb[2], c->s + c->nparams, grad);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e);
