@@ -280,6 +280,140 @@ __device__ __forceinline__ void k_first_s_body(
 }
 
 // ---------------------------------------------------------------------------
+// Pass 1 with two lines per wavefront and two real species, one wavefront
+// per (line pair, species).  The two waves of a pair hold the same two
+// lines, each its own species; at a tile's start they swap their U chunks
+// through the tile buffer, so that each evaluates F at its rows from both
+// species, and then run their own species' phases (P on U + k f, T and S
+// on f, T and S on U) with wave-uniform tables.  No species re-reads the
+// tile's lines (k_first_s re-reads them for its second species).  A tile
+// is L lines (W = L waves: L / 2 pairs of two lines); its transposed
+// stores hold 2 L slots, species-major, so that each species writes whole
+// rows of L adjacent values.
+// ---------------------------------------------------------------------------
+template <int M, int L, typename T>
+__device__ __forceinline__ void pair_load(const T* __restrict__ A, T (&v)[M], const PassGeom& g,
+                                          const TileAt& p, int li) {
+  const int lane = threadIdx.x & 63, c = lane & 31;
+  const int64_t f = p.f0 + li;
+  const bool ok = (c < g.C) && (f < g.nF);
+  const T* src = ok ? A + f * g.inF + p.tin + (int64_t)c * M : A;
+  load_chunk<M>(src, v, ok);
+}
+
+// Transposed store of the tile's 2 L slots (slot s * L + li holds species
+// s of tile line li) into A (species s at A + s N).  Block-wide.
+template <int M, int L, bool NT, typename T>
+__device__ __forceinline__ void pair_store(T* __restrict__ A, const T (&x)[M], T* lds,
+                                           const PassGeom& g, const TileAt& p, TileCursor& cur,
+                                           int s, int li) {
+  const int tid = threadIdx.x, lane = tid & 63, c = lane & 31;
+  T* B = lds + cur.buf * g.tile;
+  if (c < g.C) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) B[(s * L + li) * g.pitch + j * g.C + c] = x[j];
+  }
+  __syncthreads();
+  constexpr int SL = 2 * L;  // slots
+  const int col = tid & (SL - 1), q = tid / SL;
+  const int ss = col / L, ll = col - ss * L;
+  if (q < g.C && p.f0 + ll < g.nF) {
+    T* dst = A + ss * g.N + p.f0 + ll + p.tout + (int64_t)(q * M) * g.outRow;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const T v = B[col * g.pitch + i * g.C + q];
+      if constexpr (NT) {
+        __builtin_nontemporal_store(v, dst + i * g.outRow);
+      } else {
+        dst[i * g.outRow] = v;
+      }
+    }
+  }
+  if (g.nbuf == 1) __syncthreads();
+  else cur.buf ^= 1;
+}
+
+template <int M, int L, bool NT, bool E1, typename T>
+__device__ __forceinline__ void k_first_pair_body(
+    const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
+    T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g) {
+  static_assert(!kIsComplex<T>, "two real species");
+  constexpr int S = 2;
+  extern __shared__ double lds_raw[];
+  char* const lds = reinterpret_cast<char*>(lds_raw);
+  using LT = LaneTabT<32, T>;
+  LT* lt = reinterpret_cast<LT*>(lds);
+  T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
+  stage_lane_tabs<32>(tabs, 3 * S, lt);
+  __syncthreads();
+  const AxisTabs<S, 32, T> at{tabs, lt};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // wave-uniform species and pair, so that the tables' headers stay scalar
+  const int s = __builtin_amdgcn_readfirstlane(wv & 1);
+  const int li = 2 * __builtin_amdgcn_readfirstlane(wv >> 1) + (lane >> 5);  // tile line
+  const T* us = u + s * g.N;
+  TileCursor cur;
+  TileWalk walk(g.nFblk * g.nT);
+  int64_t tile;
+  bool have = walk.next(tile);
+  T Un[M];
+  if (have) pair_load<M, L>(us, Un, g, TileAt(tile, g), li);
+  while (have) {
+    const TileAt pos(tile, g);
+    T U[M], f[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) U[j] = Un[j];
+    {
+      // swap U with the pair's other wave (the tile buffer, used as a store)
+      T* X = tl + cur.buf * g.tile;
+#pragma unroll
+      for (int j = 0; j < M; ++j) X[(wv * M + j) * 64 + lane] = U[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const T v = X[((wv ^ 1) * M + j) * 64 + lane];
+        T uu[S], ff[S];
+        uu[0] = s ? v : U[j];
+        uu[1] = s ? U[j] : v;
+        react<S>(rx, uu, ff);
+        f[j] = s ? ff[1] : ff[0];
+      }
+      if (g.nbuf == 1) __syncthreads();
+      else cur.buf ^= 1;
+    }
+    have = walk.next(tile);
+    {  // w = P (U + k f)
+      T y[1][M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], U[j]);
+      if (E1 && have) pair_load<M, L>(us, Un, g, TileAt(tile, g), li);
+      const TabOf<T>* tb[1] = {at.P(s)};
+      const LT* lb[1] = {at.lP(s)};
+      line_solve<M, 1, 2>(tb, lb, y, lane);
+      pair_store<M, L, NT>(w, y[0], tl, g, pos, cur, s, li);
+    }
+    if constexpr (!E1) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {  // c2 = R f, then c1 = R U
+        T x[2][M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          x[0][j] = (r == 0) ? f[j] : U[j];
+          x[1][j] = x[0][j];
+        }
+        if (r == 1 && have) pair_load<M, L>(us, Un, g, TileAt(tile, g), li);
+        const TabOf<T>* tb[2] = {at.T(s), at.Sx(s)};
+        const LT* lb[2] = {at.lT(s), at.lS(s)};
+        line_solve<M, 2, 2>(tb, lb, x, lane);
+#pragma unroll
+        for (int j = 0; j < M; ++j) x[0][j] = T(9) * x[0][j] - T(8) * x[1][j];
+        pair_store<M, L, NT>(r == 0 ? c2 : c1, x[0], tl, g, pos, cur, s, li);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Middle pass (axes 2 .. d-1), streamed: the same work as k_mid in phases of one input array
 // each (T and S on c1, T and S on c2, P on w), so that only one input and its
 // two solves are in registers; the next phase's input is fetched while the

@@ -159,6 +159,15 @@ __global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_first_
   k_first_s_body<M, S, L, P, NT, E1, T, false>(u, c1, c2, w, tabs, rx, k, g, GroupCoef{});
 }
 
+// Pass 1 with two lines per wavefront and two real species, one wavefront
+// per (line pair, species) (k_first_pair_body, in etd_passes.hpp).
+template <int M, int L, bool NT, bool E1, typename T>
+__global__ __launch_bounds__(64 * L, (kStreamSimdWaves<M, T>)) void k_first_pair(
+    const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
+    T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g) {
+  k_first_pair_body<M, L, NT, E1, T>(u, c1, c2, w, tabs, rx, k, g);
+}
+
 template <int M, int S, int L, int P, bool NT, typename T>
 __global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_last_s(
     T* __restrict__ u, const T* __restrict__ c1, const T* __restrict__ c2,
@@ -495,6 +504,32 @@ hipError_t launch_first_s(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
                                         : go(k_first_s<M, S, L, P, NT, false, T>);
 }
 
+// Lines per tile (= waves per block) of k_first_pair.
+constexpr int kPairLines = 16;
+
+template <int M, bool NT, typename T>
+hipError_t launch_first_pair(const etd_rdp_ctx* c, const T* u, T* c1, T* c2, T* w,
+                             const TabOf<T>* tabs, hipStream_t st) {
+  constexpr int L = kPairLines;
+  const size_t fixed = lane_lds<32, T>(3 * 2);
+  PassGeom g = pass_geom(c, kPassFirst, fixed, L, false, sizeof(T));
+  g.tile = 2 * L * g.pitch;  // two species' slots per tile line
+  g.nbuf = tile_buffers(fixed, 2 * L, g.tile, sizeof(T));
+  const size_t lds = pass_lds(g, fixed, sizeof(T));
+  auto go = [&](auto kern) {
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    unsigned grid;
+    e = persistent_grid(kern, lds, g.nFblk * g.nT, &grid, 64 * L);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs, c->rx,
+                       static_cast<T>(c->k), g);
+    return hipGetLastError();
+  };
+  return (c->scheme == ETD_SCHEME_ETD1) ? go(k_first_pair<M, L, NT, true, T>)
+                                        : go(k_first_pair<M, L, NT, false, T>);
+}
+
 template <int M, int S, int P, bool NT, typename T>
 hipError_t launch_last_s(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
                          const T* w, const TabOf<T>* tabs, hipStream_t st) {
@@ -540,9 +575,15 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
               : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
-      if (c->P[0] == 2)
-        return nt ? launch_first_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
-                  : launch_first_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
+      if (c->P[0] == 2) {
+        if constexpr (S == 2) {
+          return nt ? launch_first_pair<M, true, T>(c, u, c1, c2, w, tabs, st)
+                    : launch_first_pair<M, false, T>(c, u, c1, c2, w, tabs, st);
+        } else {
+          return nt ? launch_first_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
+                    : launch_first_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
+        }
+      }
     }
     if constexpr (M >= kStreamFirstFrom) {
       return nt ? launch_first_s<M, S, 1, true, T>(c, u, c1, c2, w, tabs, st)
@@ -1282,6 +1323,10 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const bool z = (ctx->precision == ETD_PRECISION_C128);
   const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : (z ? "zd" : "double");
   const int sw = (z && m > 4) ? 8 : kStreamWaves;  // kStreamBlockWaves
+  if (first && P == 2 && ctx->s == 2 && !z) {
+    const int n = std::snprintf(name, size, "k_first_pair<%d, %d, %s%s, %s>", m, kPairLines, nt, e1, ty);
+    return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
+  }
   const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s%s, %s>", base, m,
                                          ctx->s, sw * P, P, nt, e1, ty)
                          : std::snprintf(name, size, "%s<%d, %d, %d, %s, %s>", base, m, ctx->s,

@@ -71,11 +71,11 @@ def test_lines_per_wave_option():
     # pass with at least 8192 lines
     big = _init((256, 256, 160), bcs)
     assert [big.line_split(a) for a in (1, 2, 3)] == [(8, 32), (8, 32), (5, 32)]
-    assert big.pass_kernel(1) == "k_first_s<8, 2, 32, 2, true, false, double>"
+    assert big.pass_kernel(1) == "k_first_pair<8, 16, true, false, double>"
     small = _init((256, 12, 10), bcs)
     assert small.line_split(1) == (4, 64) and small.pass_kernel(1) == "k_first<4, 2, 16, false, double>"
     two = _init((256, 12, 10), bcs, lines_per_wave=2)
-    assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_s<8, 2, 32, 2, false, false, double>"
+    assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_pair<8, 16, false, false, double>"
     assert two.line_split(2) == (1, 12)  # lengths that are not 32 m keep one line
     one = _init((256, 192, 160), bcs, lines_per_wave=1)
     assert [one.line_split(a) for a in (1, 2, 3)] == [(4, 64), (3, 64), (4, 40)]
