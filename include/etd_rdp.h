@@ -118,11 +118,14 @@ typedef struct etd_reaction_t {
  * Lines per wavefront of the forward passes (etd_scheme_t.lines_per_wave).
  * A wavefront solves one grid line with up to 64 chunks, or two lines of
  * 32 chunks each when the line length is n = 32 m with 2 <= m <= 8 (fewer
- * cross-lane reduction levels per line, 32-line tiles).  Results agree with
- * the one-line form to rounding (the chunking differs). */
+ * cross-lane reduction levels per line, 32-line tiles), or, on request,
+ * four lines of 16 chunks when n = 16 m with 2 <= m <= 8 (64-line tiles).
+ * Results agree with the one-line form to rounding (the chunking differs). */
 #define ETD_LINES_AUTO 0   /* two where n allows and a pass has >= 8192 lines  */
 #define ETD_LINES_ONE 1    /* always one                                       */
 #define ETD_LINES_TWO 2    /* two wherever n allows                            */
+#define ETD_LINES_FOUR 4   /* four lines of 16 chunks where n = 16 m (2 <= m <=
+                              8, n <= 128), else as ETD_LINES_TWO              */
 
 /* Element type of the state and of the carried arrays
  * (etd_scheme_t.precision).  The line-solve tables are built and held in
@@ -136,7 +139,8 @@ typedef struct etd_reaction_t {
  * u holds s*N complex FP64 values as interleaved (re, im) pairs, D holds s
  * (re, im) pairs with Re D >= 0, the model is ETD_RX_CGL_Z or ETD_RX_NLS_Z
  * (and those models need this precision), shift must be 0.  Every solve is
- * a complex line solve.  Lines run one per wavefront (ETD_LINES_TWO is
+ * a complex line solve.  Lines run one per wavefront (ETD_LINES_TWO and
+ * ETD_LINES_FOUR are
  * ETD_ERR_UNSUPPORTED), with the same line lengths as real species.  Step
  * with etd_rdp_step_z /
  * etd_rdp_run_pass_z; the other entry points return ETD_ERR_ARG or

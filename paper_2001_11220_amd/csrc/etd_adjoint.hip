@@ -789,13 +789,33 @@ inline size_t adj_fixed_lds_s(int S) {
 // holds U, U-bar and f-bar of every species, spills and took 163 us
 // against 129 us with one line.
 constexpr int kAdjTwoLineMaxM = 4;
-inline int adj_lines(const etd_rdp_ctx* c, int a) {
-  return ((a > 0 || c->s == 2) && c->P[a] == 2 && c->m[a] <= kAdjTwoLineMaxM) ? 2 : 1;
+// An axis whose forward pass runs four lines per wavefront runs its reverse
+// pass with two, on the two-line table set.
+inline int adj_m2(const etd_rdp_ctx* c, int a) {
+  return (c->P[a] == 2) ? c->m[a] : ((c->P[a] == 4) ? c->m2[a] : 0);
 }
-// The tables of axis a for P lines per wavefront: the forward set (two
-// lines) or the one-line set.
+inline int adj_lines(const etd_rdp_ctx* c, int a) {
+  const int m2 = adj_m2(c, a);
+  return ((a > 0 || c->s == 2) && m2 > 0 && m2 <= kAdjTwoLineMaxM) ? 2 : 1;
+}
+// The tables of axis a for P lines per wavefront: the two-line set (the
+// forward set when the forward pass runs two lines) or the one-line set.
 inline const SolveTab* adj_tabs(const etd_rdp_ctx* c, const SolveTab* tabs, int a, int P) {
-  return tabs + (P == 2 ? 0 : c->tab1) + tab_index(a, 0, 0, c->s);
+  const int set = (P == 2) ? (c->P[a] == 2 ? 0 : c->tab2) : c->tab1;
+  return tabs + set + tab_index(a, 0, 0, c->s);
+}
+
+// Geometry of a reverse pass over axis `axis` with P lines per wavefront:
+// with two lines on an axis whose forward pass runs four, the chunking is
+// the two-line one.
+PassGeom adj_geom(const etd_rdp_ctx* c, int kind, size_t fixed, int lines, int P, int axis) {
+  PassGeom g = pass_geom(c, kind, fixed, lines, P == 1);
+  if (P == 2 && c->P[axis] == 4) {
+    g.m = c->m2[axis];
+    g.C = g.n / g.m;
+    g.ql = g.m - 1;
+  }
+  return g;
 }
 
 template <int M, int S, int P>
@@ -805,7 +825,7 @@ hipError_t launch_ka_mid_s(const etd_rdp_ctx* c, double* const (&A)[3], double* 
   constexpr int L = W * P;
   const int a = 1;
   const size_t fixed = adj_fixed_lds_s<P>(S);
-  const PassGeom g = pass_geom(c, kPassAdjMid, fixed, L, P == 1);
+  const PassGeom g = adj_geom(c, kPassAdjMid, fixed, L, P, 1);
   const size_t lds = pass_lds(g, fixed);
   hipError_t e = adj_grid(ka_mid_s<M, S, L, P>, lds, g.nFblk * g.nT * S, nblk, 64 * W);
   if (e != hipSuccess) return e;
@@ -820,7 +840,7 @@ hipError_t launch_ka_last(const etd_rdp_ctx* c, double* const (&X)[3], const dou
                           unsigned* nblk, hipStream_t st) {
   const int a = c->d - 1;
   const size_t fixed = adj_fixed_lds<P>(S);
-  const PassGeom g = pass_geom(c, kPassLast, fixed, kBlockLines * P, P == 1);
+  const PassGeom g = adj_geom(c, kPassLast, fixed, kBlockLines * P, P, c->d - 1);
   const size_t lds = pass_lds(g, fixed);
   hipError_t e = adj_grid(ka_last<M, S, P>, lds, g.nFblk * g.nT, nblk);
   if (e != hipSuccess) return e;
@@ -913,7 +933,7 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
   // Each axis runs one or two lines per wavefront (adj_lines) with the
   // matching tables.
   {
-    const int a = c->d - 1, P = adj_lines(c, a), m = (P == 2) ? c->m[a] : c->m1[a];
+    const int a = c->d - 1, P = adj_lines(c, a), m = (P == 2) ? adj_m2(c, a) : c->m1[a];
     const SolveTab* ta = adj_tabs(c, tabs, a, P);
     double* const(&X)[3] = (c->d == 3) ? B : A;
     double* pp = part;
@@ -927,7 +947,7 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
     if (e != hipSuccess) return hip_fail(c, e);
   }
   if (c->d == 3) {
-    const int P = adj_lines(c, 1), m = (P == 2) ? c->m[1] : c->m1[1];
+    const int P = adj_lines(c, 1), m = (P == 2) ? adj_m2(c, 1) : c->m1[1];
     const SolveTab* ta = adj_tabs(c, tabs, 1, P);
     double* pp = part + (size_t)kAdjMaxBlocks * kGradSlots;
     if (P == 2) {
@@ -940,7 +960,7 @@ int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* l
     if (e != hipSuccess) return hip_fail(c, e);
   }
   {
-    const int P = adj_lines(c, 0), m = (P == 2) ? c->m[0] : c->m1[0];
+    const int P = adj_lines(c, 0), m = (P == 2) ? adj_m2(c, 0) : c->m1[0];
     const SolveTab* ta = adj_tabs(c, tabs, 0, P);
     double* pp = part + 2 * (size_t)kAdjMaxBlocks * kGradSlots;
     if (P == 2) { ETD_DISPATCH_M2(m, e = (launch_ka_first<M_, 2, 2>(c, u, Y, lam_out, ta, pp, &nb[2], st))); }

@@ -25,8 +25,9 @@ struct etd_rdp_ctx {
   etd::Rx rx{};
   int nparams = 0;             // reaction parameters with a gradient
   int m[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length of the forward passes' tables
-  int P[ETD_MAX_DIM] = {1, 1, 1, 1};  // lines per wavefront of the forward passes
+  int P[ETD_MAX_DIM] = {1, 1, 1, 1};  // lines per wavefront of the forward passes (1, 2, 4)
   int m1[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length with one line per wavefront
+  int m2[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length with two (0: n is not 32 m)
   // 1 on an axis whose lines have no chunking into <= 64 equal chunks of
   // <= kMaxRegularM rows: general_chunk's m, the last chunk possibly shorter,
   // run by the general pass kernels (etd_general.hip).
@@ -38,6 +39,7 @@ struct etd_rdp_ctx {
   std::vector<etd::SolveTab> tabs;
   std::vector<etd::SolveTabZ> tabz;  // complex species: the forward tables
   int tab1 = 0;
+  int tab2 = 0;  // first table of the two-line set (some axis runs four lines), else 0
   size_t tab_bytes = 0, arr_bytes = 0, ws_bytes = 0;
   size_t part_bytes = 0, adj_ws_bytes = 0;
   const void* uploaded_ws = nullptr;
@@ -82,6 +84,12 @@ constexpr int kMinTwoLineM = 2;
 // lines per pass) 125 -> 102 us and 128^3 174 -> 129 us with two lines,
 // but 64^3 (4096 lines) 52 -> 57 us and 2-D grids of 256 lines 33 -> 43 us.
 constexpr int64_t kTwoLineMinLines = 8192;
+// Four lines per wavefront (ETD_LINES_FOUR): lines of n = 16 m rows with m in
+// [kMinTwoLineM, kMaxRegularM], 16 chunks per line; returns m or 0.
+inline int four_line_chunk(int64_t n) {
+  const int64_t m = n / 16;
+  return (n % 16 == 0 && m >= kMinTwoLineM && m <= kMaxRegularM) ? static_cast<int>(m) : 0;
+}
 inline int two_line_chunk(int64_t n) {
   const int64_t m = n / 32;
   return (n % 32 == 0 && m >= kMinTwoLineM && m <= kMaxRegularM) ? static_cast<int>(m) : 0;

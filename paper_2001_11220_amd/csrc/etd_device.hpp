@@ -274,10 +274,11 @@ __device__ __forceinline__ zd rows_swap16(zd v, bool odd_row) {
 }
 
 // Lines per wavefront.  With P = 1 a wavefront solves one line, lane c
-// holding chunk c.  With P = 2 it solves two lines of exactly 32 chunks
-// each: lane c holds chunk c % 32 of the wavefront's line c / 32 (its
-// segment).  Cross-lane reads that leave a segment only ever meet a zero
-// multiplier, so the exchanges are the same as for one line.
+// holding chunk c.  With P = 2 (4) it solves two (four) lines of exactly 32
+// (16) chunks each: lane c holds chunk c % (64 / P) of the wavefront's line
+// c / (64 / P) (its segment).  Cross-lane reads that leave a segment only
+// ever meet a zero multiplier, so the exchanges are the same as for one
+// line, minus the reduction levels a segment does not need.
 template <int P>
 constexpr int kSegLanes = 64 / P;
 
@@ -286,11 +287,18 @@ template <int P, typename T>
 __device__ __forceinline__ T seg_value(T v, int idx, int lane) {
   if constexpr (P == 1) {
     return lane_value(v, idx);
-  } else {
-    static_assert(P == 2, "one or two lines per wavefront");
+  } else if constexpr (P == 2) {
     const T a = lane_value(v, idx);
     const T b = lane_value(v, kSegLanes<P> + idx);
     return (lane >= kSegLanes<P>) ? b : a;
+  } else {
+    static_assert(P == 4, "one, two or four lines per wavefront");
+    const T a = lane_value(v, idx);
+    const T b = lane_value(v, 16 + idx);
+    const T c = lane_value(v, 32 + idx);
+    const T d = lane_value(v, 48 + idx);
+    const int q = lane >> 4;
+    return (q == 0) ? a : ((q == 1) ? b : ((q == 2) ? c : d));
   }
 }
 

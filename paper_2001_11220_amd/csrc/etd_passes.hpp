@@ -280,21 +280,21 @@ __device__ __forceinline__ void k_first_s_body(
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1 with two lines per wavefront and two real species, one wavefront
-// per (line pair, species).  The two waves of a pair hold the same two
-// lines, each its own species; at a tile's start they swap their U chunks
-// through the tile buffer, so that each evaluates F at its rows from both
-// species, and then run their own species' phases (P on U + k f, T and S
-// on f, T and S on U) with wave-uniform tables.  No species re-reads the
-// tile's lines (k_first_s re-reads them for its second species).  A tile
-// is L lines (W = L waves: L / 2 pairs of two lines); its transposed
-// stores hold 2 L slots, species-major, so that each species writes whole
-// rows of L adjacent values.
+// Pass 1 with P = 2 or 4 lines per wavefront and two real species, one
+// wavefront per (group of P lines, species).  The two waves of a pair hold
+// the same P lines, each its own species; at a tile's start they swap their
+// U chunks through the tile buffer, so that each evaluates F at its rows
+// from both species, and then run their own species' phases (P on U + k f,
+// T and S on f, T and S on U) with wave-uniform tables.  No species
+// re-reads the tile's lines (k_first_s re-reads them for its second
+// species).  A block of W waves holds W / 2 pairs, a tile L = W P / 2
+// lines; its transposed stores hold 2 L slots, species-major, so that each
+// species writes whole rows of L adjacent values.
 // ---------------------------------------------------------------------------
-template <int M, int L, typename T>
+template <int M, int P, typename T>
 __device__ __forceinline__ void pair_load(const T* __restrict__ A, T (&v)[M], const PassGeom& g,
                                           const TileAt& p, int li) {
-  const int lane = threadIdx.x & 63, c = lane & 31;
+  const int lane = threadIdx.x & 63, c = lane & (kSegLanes<P> - 1);
   const int64_t f = p.f0 + li;
   const bool ok = (c < g.C) && (f < g.nF);
   const T* src = ok ? A + f * g.inF + p.tin + (int64_t)c * M : A;
@@ -303,11 +303,11 @@ __device__ __forceinline__ void pair_load(const T* __restrict__ A, T (&v)[M], co
 
 // Transposed store of the tile's 2 L slots (slot s * L + li holds species
 // s of tile line li) into A (species s at A + s N).  Block-wide.
-template <int M, int L, bool NT, typename T>
+template <int M, int L, int P, bool NT, typename T>
 __device__ __forceinline__ void pair_store(T* __restrict__ A, const T (&x)[M], T* lds,
                                            const PassGeom& g, const TileAt& p, TileCursor& cur,
                                            int s, int li) {
-  const int tid = threadIdx.x, lane = tid & 63, c = lane & 31;
+  const int tid = threadIdx.x, lane = tid & 63, c = lane & (kSegLanes<P> - 1);
   T* B = lds + cur.buf * g.tile;
   if (c < g.C) {
 #pragma unroll
@@ -333,7 +333,7 @@ __device__ __forceinline__ void pair_store(T* __restrict__ A, const T (&x)[M], T
   else cur.buf ^= 1;
 }
 
-template <int M, int L, bool NT, bool E1, typename T>
+template <int M, int L, int P, bool NT, bool E1, typename T>
 __device__ __forceinline__ void k_first_pair_body(
     const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
     T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g) {
@@ -341,23 +341,24 @@ __device__ __forceinline__ void k_first_pair_body(
   constexpr int S = 2;
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
-  using LT = LaneTabT<32, T>;
+  static_assert(P == 2 || P == 4, "two or four lines per wavefront");
+  using LT = LaneTabT<kSegLanes<P>, T>;
   LT* lt = reinterpret_cast<LT*>(lds);
   T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));
-  stage_lane_tabs<32>(tabs, 3 * S, lt);
+  stage_lane_tabs<kSegLanes<P>>(tabs, 3 * S, lt);
   __syncthreads();
-  const AxisTabs<S, 32, T> at{tabs, lt};
+  const AxisTabs<S, kSegLanes<P>, T> at{tabs, lt};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // wave-uniform species and pair, so that the tables' headers stay scalar
   const int s = __builtin_amdgcn_readfirstlane(wv & 1);
-  const int li = 2 * __builtin_amdgcn_readfirstlane(wv >> 1) + (lane >> 5);  // tile line
+  const int li = P * __builtin_amdgcn_readfirstlane(wv >> 1) + lane / kSegLanes<P>;  // tile line
   const T* us = u + s * g.N;
   TileCursor cur;
   TileWalk walk(g.nFblk * g.nT);
   int64_t tile;
   bool have = walk.next(tile);
   T Un[M];
-  if (have) pair_load<M, L>(us, Un, g, TileAt(tile, g), li);
+  if (have) pair_load<M, P>(us, Un, g, TileAt(tile, g), li);
   while (have) {
     const TileAt pos(tile, g);
     T U[M], f[M];
@@ -386,11 +387,11 @@ __device__ __forceinline__ void k_first_pair_body(
       T y[1][M];
 #pragma unroll
       for (int j = 0; j < M; ++j) y[0][j] = fma(k, f[j], U[j]);
-      if (E1 && have) pair_load<M, L>(us, Un, g, TileAt(tile, g), li);
+      if (E1 && have) pair_load<M, P>(us, Un, g, TileAt(tile, g), li);
       const TabOf<T>* tb[1] = {at.P(s)};
       const LT* lb[1] = {at.lP(s)};
-      line_solve<M, 1, 2>(tb, lb, y, lane);
-      pair_store<M, L, NT>(w, y[0], tl, g, pos, cur, s, li);
+      line_solve<M, 1, P>(tb, lb, y, lane);
+      pair_store<M, L, P, NT>(w, y[0], tl, g, pos, cur, s, li);
     }
     if constexpr (!E1) {
 #pragma unroll
@@ -401,13 +402,13 @@ __device__ __forceinline__ void k_first_pair_body(
           x[0][j] = (r == 0) ? f[j] : U[j];
           x[1][j] = x[0][j];
         }
-        if (r == 1 && have) pair_load<M, L>(us, Un, g, TileAt(tile, g), li);
+        if (r == 1 && have) pair_load<M, P>(us, Un, g, TileAt(tile, g), li);
         const TabOf<T>* tb[2] = {at.T(s), at.Sx(s)};
         const LT* lb[2] = {at.lT(s), at.lS(s)};
-        line_solve<M, 2, 2>(tb, lb, x, lane);
+        line_solve<M, 2, P>(tb, lb, x, lane);
 #pragma unroll
         for (int j = 0; j < M; ++j) x[0][j] = T(9) * x[0][j] - T(8) * x[1][j];
-        pair_store<M, L, NT>(r == 0 ? c2 : c1, x[0], tl, g, pos, cur, s, li);
+        pair_store<M, L, P, NT>(r == 0 ? c2 : c1, x[0], tl, g, pos, cur, s, li);
       }
     }
   }

@@ -159,13 +159,14 @@ __global__ __launch_bounds__(64 * L / P, (kStreamSimdWaves<M, T>)) void k_first_
   k_first_s_body<M, S, L, P, NT, E1, T, false>(u, c1, c2, w, tabs, rx, k, g, GroupCoef{});
 }
 
-// Pass 1 with two lines per wavefront and two real species, one wavefront
-// per (line pair, species) (k_first_pair_body, in etd_passes.hpp).
-template <int M, int L, bool NT, bool E1, typename T>
-__global__ __launch_bounds__(64 * L, (kStreamSimdWaves<M, T>)) void k_first_pair(
+// Pass 1 with P = 2 or 4 lines per wavefront and two real species, one
+// wavefront per (group of P lines, species) (k_first_pair_body, in
+// etd_passes.hpp): 2 L / P waves per block.
+template <int M, int L, int P, bool NT, bool E1, typename T>
+__global__ __launch_bounds__(128 * L / P, (kStreamSimdWaves<M, T>)) void k_first_pair(
     const T* __restrict__ u, T* __restrict__ c1, T* __restrict__ c2,
     T* __restrict__ w, const TabOf<T>* __restrict__ tabs, Rx rx, T k, PassGeom g) {
-  k_first_pair_body<M, L, NT, E1, T>(u, c1, c2, w, tabs, rx, k, g);
+  k_first_pair_body<M, L, P, NT, E1, T>(u, c1, c2, w, tabs, rx, k, g);
 }
 
 template <int M, int S, int L, int P, bool NT, typename T>
@@ -504,14 +505,14 @@ hipError_t launch_first_s(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
                                         : go(k_first_s<M, S, L, P, NT, false, T>);
 }
 
-// Lines per tile (= waves per block) of k_first_pair.
-constexpr int kPairLines = 16;
+// Waves per block of k_first_pair (a tile is kPairWaves / 2 * P lines).
+constexpr int kPairWaves = 16;
 
-template <int M, bool NT, typename T>
+template <int M, int P, bool NT, typename T>
 hipError_t launch_first_pair(const etd_rdp_ctx* c, const T* u, T* c1, T* c2, T* w,
                              const TabOf<T>* tabs, hipStream_t st) {
-  constexpr int L = kPairLines;
-  const size_t fixed = lane_lds<32, T>(3 * 2);
+  constexpr int L = kPairWaves / 2 * P;
+  const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * 2);
   PassGeom g = pass_geom(c, kPassFirst, fixed, L, false, sizeof(T));
   g.tile = 2 * L * g.pitch;  // two species' slots per tile line
   g.nbuf = tile_buffers(fixed, 2 * L, g.tile, sizeof(T));
@@ -520,14 +521,14 @@ hipError_t launch_first_pair(const etd_rdp_ctx* c, const T* u, T* c1, T* c2, T* 
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
     unsigned grid;
-    e = persistent_grid(kern, lds, g.nFblk * g.nT, &grid, 64 * L);
+    e = persistent_grid(kern, lds, g.nFblk * g.nT, &grid, 64 * kPairWaves);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * L), lds, st, u, c1, c2, w, tabs, c->rx,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kPairWaves), lds, st, u, c1, c2, w, tabs, c->rx,
                        static_cast<T>(c->k), g);
     return hipGetLastError();
   };
-  return (c->scheme == ETD_SCHEME_ETD1) ? go(k_first_pair<M, L, NT, true, T>)
-                                        : go(k_first_pair<M, L, NT, false, T>);
+  return (c->scheme == ETD_SCHEME_ETD1) ? go(k_first_pair<M, L, P, NT, true, T>)
+                                        : go(k_first_pair<M, L, P, NT, false, T>);
 }
 
 template <int M, int S, int P, bool NT, typename T>
@@ -575,10 +576,19 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
               : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
+      if (c->P[0] == 4) {
+        if constexpr (S == 2) {
+          return nt ? launch_first_pair<M, 4, true, T>(c, u, c1, c2, w, tabs, st)
+                    : launch_first_pair<M, 4, false, T>(c, u, c1, c2, w, tabs, st);
+        } else {
+          return nt ? launch_first_s<M, S, 4, true, T>(c, u, c1, c2, w, tabs, st)
+                    : launch_first_s<M, S, 4, false, T>(c, u, c1, c2, w, tabs, st);
+        }
+      }
       if (c->P[0] == 2) {
         if constexpr (S == 2) {
-          return nt ? launch_first_pair<M, true, T>(c, u, c1, c2, w, tabs, st)
-                    : launch_first_pair<M, false, T>(c, u, c1, c2, w, tabs, st);
+          return nt ? launch_first_pair<M, 2, true, T>(c, u, c1, c2, w, tabs, st)
+                    : launch_first_pair<M, 2, false, T>(c, u, c1, c2, w, tabs, st);
         } else {
           return nt ? launch_first_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
                     : launch_first_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
@@ -643,6 +653,9 @@ hipError_t launch_mid(const etd_rdp_ctx* c, int p, const T* c1, const T* c2,
               : launch_mid_s<M, S, 1, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
+      if (c->P[p] == 4)
+        return nt ? launch_mid_s<M, S, 4, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
+                  : launch_mid_s<M, S, 4, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
       if (c->P[p] == 2)
         return nt ? launch_mid_s<M, S, 2, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
                   : launch_mid_s<M, S, 2, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
@@ -684,6 +697,9 @@ hipError_t launch_last(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
               : launch_last_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
+      if (c->P[c->d - 1] == 4)
+        return nt ? launch_last_s<M, S, 4, true, T>(c, u, c1, c2, w, tabs, st)
+                  : launch_last_s<M, S, 4, false, T>(c, u, c1, c2, w, tabs, st);
       if (c->P[c->d - 1] == 2)
         return nt ? launch_last_s<M, S, 2, true, T>(c, u, c1, c2, w, tabs, st)
                   : launch_last_s<M, S, 2, false, T>(c, u, c1, c2, w, tabs, st);
@@ -1006,7 +1022,8 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   int sch = scheme ? scheme->scheme : ETD_SCHEME_RDP;
   if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
   const int lpw = scheme ? scheme->lines_per_wave : ETD_LINES_AUTO;
-  if (lpw != ETD_LINES_AUTO && lpw != ETD_LINES_ONE && lpw != ETD_LINES_TWO) return ETD_ERR_ARG;
+  if (lpw != ETD_LINES_AUTO && lpw != ETD_LINES_ONE && lpw != ETD_LINES_TWO && lpw != ETD_LINES_FOUR)
+    return ETD_ERR_ARG;
   const int prec = scheme ? scheme->precision : ETD_PRECISION_F64;
   if (prec != ETD_PRECISION_F64 && prec != ETD_PRECISION_F32 && prec != ETD_PRECISION_C128)
     return ETD_ERR_ARG;
@@ -1024,7 +1041,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     if (!std::isfinite(rx->params[i])) return ETD_ERR_ARG;
   for (int i = 0; i < s; ++i)
     if (!std::isfinite(rx->shift[i]) || (cplx && rx->shift[i] != 0.0)) return ETD_ERR_ARG;
-  if (cplx && lpw == ETD_LINES_TWO) return ETD_ERR_UNSUPPORTED;
+  if (cplx && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR)) return ETD_ERR_UNSUPPORTED;
   if (rx->field != 0 && (rx->field != 1 || rx->model != ETD_RX_NLS_Z)) return ETD_ERR_ARG;
 
   etd_rdp_ctx* c = new (std::nothrow) etd_rdp_ctx();
@@ -1053,17 +1070,23 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     const bool general = (m == 0);
     if (general) m = general_chunk(n);
     if (m == 0) { delete c; return ETD_ERR_UNSUPPORTED; }
+    // Lines per wavefront: automatic takes four lines of 16 chunks where
+    // n = 16 m (n <= 128), else two of 32 where n = 32 m, on passes of at
+    // least kTwoLineMinLines lines (measured, one step: 64^4 1.87 -> 1.18 ms
+    // and 128^3 124 -> 107 us with four lines against two).
     const int64_t lines = N / n;
-    const bool two_ok = !cplx && !general &&
-                        ((lpw == ETD_LINES_TWO) || (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines));
-    const int m2 = two_ok ? two_line_chunk(n) : 0;
+    const bool multi = !cplx && !general;
+    const bool many = (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines);
+    const int m4 = (multi && (lpw == ETD_LINES_FOUR || many)) ? four_line_chunk(n) : 0;
+    const int m2 = (multi && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR || many)) ? two_line_chunk(n) : 0;
+    c->m2[i] = multi ? two_line_chunk(n) : 0;
     c->gen[i] = general ? 1 : 0;
     c->n[i] = n;
     c->h[i] = h;
     c->bc[i] = b;
     c->m1[i] = m;
-    c->m[i] = m2 ? m2 : m;
-    c->P[i] = m2 ? 2 : 1;
+    c->m[i] = m4 ? m4 : (m2 ? m2 : m);
+    c->P[i] = m4 ? 4 : (m2 ? 2 : 1);
   }
   c->N = N;
   for (int i = 0; i < s; ++i) {
@@ -1076,9 +1099,18 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
 
   const double gam[3] = {1.0, 3.0, 4.0};
   const int nt = d * s * 3;
-  bool two = false;
-  for (int a = 0; a < d; ++a) two = two || (c->P[a] == 2);
+  // Table sets: [0] the forward passes' chunking; [tab1] one line per
+  // wavefront (reverse kernels, single solves) when some axis runs more than
+  // one; [tab2] two lines per wavefront (the reverse kernels' two-line form)
+  // when some axis runs four.
+  bool two = false, four = false;
+  for (int a = 0; a < d; ++a) {
+    two = two || (c->P[a] > 1);
+    four = four || (c->P[a] == 4 && c->m2[a] > 0);
+  }
+  const int nsets = 1 + (two ? 1 : 0) + (four ? 1 : 0);
   c->tab1 = two ? nt : 0;
+  c->tab2 = four ? 2 * nt : 0;
   if (cplx) {
     c->tabz.resize(static_cast<size_t>(nt));
     for (int a = 0; a < d; ++a)
@@ -1095,13 +1127,14 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
           }
         }
   }
-  c->tabs.resize(cplx ? 0 : static_cast<size_t>(two ? 2 * nt : nt));
-  for (int set = 0; set < (cplx ? 0 : (two ? 2 : 1)); ++set)
+  c->tabs.resize(cplx ? 0 : static_cast<size_t>(nsets * nt));
+  for (int set = 0; set < (cplx ? 0 : nsets); ++set)
     for (int a = 0; a < d; ++a)
       for (int sp = 0; sp < s; ++sp)
         for (int gi = 0; gi < 3; ++gi) {
           std::string err;
-          const int m = (set == 0) ? c->m[a] : c->m1[a];
+          // set 2 (two lines): axes without a two-line chunking keep one line
+          const int m = (set == 0) ? c->m[a] : ((set == 2 && c->m2[a]) ? c->m2[a] : c->m1[a]);
           if (!build_solve_table(c->n[a], c->bc[a], c->h[a], k * c->D[sp] / gam[gi], m,
                                  &c->tabs[set * nt + tab_index(a, sp, gi, s)], &err)) {
             std::fprintf(stderr, "etd_rdp_init: table (axis %d, species %d, gamma %g): %s\n",
@@ -1313,7 +1346,7 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const bool first = (p == 0) && ctx->d > 1, last = (p == ctx->d - 1);
   const bool zc = (ctx->precision == ETD_PRECISION_C128);
   const bool streamed =
-      (P == 2) || (first ? (m >= (zc ? kStreamFirstFromZ : kStreamFirstFrom))
+      (P > 1) || (first ? (m >= (zc ? kStreamFirstFromZ : kStreamFirstFrom))
                          : (last ? (m >= (zc ? kStreamLastFromZ : kStreamLastFrom))
                                  : (m >= (zc ? kStreamMidFromZ : kStreamMidFrom))));
   const char* base = first ? "k_first" : (last ? "k_last" : "k_mid");
@@ -1323,8 +1356,9 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const bool z = (ctx->precision == ETD_PRECISION_C128);
   const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : (z ? "zd" : "double");
   const int sw = (z && m > 4) ? 8 : kStreamWaves;  // kStreamBlockWaves
-  if (first && P == 2 && ctx->s == 2 && !z) {
-    const int n = std::snprintf(name, size, "k_first_pair<%d, %d, %s%s, %s>", m, kPairLines, nt, e1, ty);
+  if (first && P > 1 && ctx->s == 2 && !z) {
+    const int n = std::snprintf(name, size, "k_first_pair<%d, %d, %d, %s%s, %s>", m, kPairWaves / 2 * P, P,
+                                nt, e1, ty);
     return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;
   }
   const int n = streamed ? std::snprintf(name, size, "%s_s<%d, %d, %d, %d, %s%s, %s>", base, m,

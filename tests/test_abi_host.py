@@ -67,25 +67,28 @@ def test_tables_build_for_every_line_length(bc):
 def test_lines_per_wave_option():
     from paper_2001_11220_amd import etd
     bcs = ("periodic", "neumann", "dirichlet")
-    # automatic: two lines per wavefront only for n = 32 m (m = 2..8) on a
-    # pass with at least 8192 lines
+    # automatic, on passes with at least 8192 lines: four lines per
+    # wavefront for n = 16 m (m = 2..8), else two for n = 32 m (m = 2..8)
     big = _init((256, 256, 160), bcs)
     assert [big.line_split(a) for a in (1, 2, 3)] == [(8, 32), (8, 32), (5, 32)]
-    assert big.pass_kernel(1) == "k_first_pair<8, 16, true, false, double>"
+    assert big.pass_kernel(1) == "k_first_pair<8, 16, 2, true, false, double>"
     small = _init((256, 12, 10), bcs)
     assert small.line_split(1) == (4, 64) and small.pass_kernel(1) == "k_first<4, 2, 16, false, double>"
     two = _init((256, 12, 10), bcs, lines_per_wave=2)
-    assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_pair<8, 16, false, false, double>"
+    assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_pair<8, 16, 2, false, false, double>"
     assert two.line_split(2) == (1, 12)  # lengths that are not 32 m keep one line
     one = _init((256, 192, 160), bcs, lines_per_wave=1)
     assert [one.line_split(a) for a in (1, 2, 3)] == [(4, 64), (3, 64), (4, 40)]
     part = _init((256, 192, 160), bcs)  # 30720 lines on axis 1: two lines per wavefront
     assert [part.line_split(a) for a in (1, 2, 3)] == [(8, 32), (6, 32), (5, 32)]
     few = _init((256, 64, 100), bcs)  # axis 1 has 6400 lines: one line per wavefront
-    assert [few.line_split(a) for a in (1, 2, 3)] == [(4, 64), (2, 32), (2, 50)]
-    four = _init((64, 64, 64, 64), ("periodic",) * 4)  # 262144 lines of 32 chunks of 2 rows
-    assert [four.line_split(a) for a in (1, 2, 3, 4)] == [(2, 32)] * 4
-    assert four.pass_kernel(3) == "k_mid_s<2, 2, 32, 2, true, double>"
+    assert [few.line_split(a) for a in (1, 2, 3)] == [(4, 64), (4, 16), (2, 50)]
+    four = _init((64, 64, 64, 64), ("periodic",) * 4)  # 262144 lines of 16 chunks of 4 rows
+    assert [four.line_split(a) for a in (1, 2, 3, 4)] == [(4, 16)] * 4
+    assert four.pass_kernel(3) == "k_mid_s<4, 2, 64, 4, true, double>"
+    req = _init((256, 48, 10), bcs, lines_per_wave=4)  # four where n = 16 m, else two, else one
+    assert [req.line_split(a) for a in (1, 2, 3)] == [(8, 32), (3, 16), (1, 10)]
+    req.close()
     for p in (big, small, two, one, part, few, four):
         p.close()
     with pytest.raises(etd.EtdError):

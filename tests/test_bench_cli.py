@@ -19,7 +19,7 @@ def test_pass_kernel_names():
     from paper_2001_11220_amd import etd
     e = etd.EtdRdp((256, 256, 256), ("periodic",) * 3, (2e-5, 1e-5), 1.0, "gray_scott",
                    {"F": 0.04, "kappa": 0.06})
-    assert [e.pass_kernel(p) for p in (1, 2, 3)] == ["k_first_pair<8, 16, true, false, double>",
+    assert [e.pass_kernel(p) for p in (1, 2, 3)] == ["k_first_pair<8, 16, 2, true, false, double>",
                                                       "k_mid_s<8, 2, 32, 2, true, double>",
                                                       "k_last_s<8, 2, 32, 2, true, double>"]
     f = etd.EtdRdp((512, 512, 512), ("dirichlet",) * 3, (1.0, 10.0), 1e-4, "schnakenberg",

@@ -60,6 +60,12 @@ CASES = {
                              {"C": [[-0.7]]}, None, (0.0,)),
     "gs2d_rev_two_line": ((128, 96), ("periodic", "neumann"), (2e-5, 1e-5), 1.0, "gray_scott",
                           {"F": 0.04, "kappa": 0.06}, None, (0.7, 0.2)),
+    # forward recompute with four lines per wavefront, reverse passes with
+    # two (their own table set)
+    "schnak3d_four_line": ((128, 64, 96), ("neumann", "periodic", "dirichlet"), (1.0, 10.0), 1e-3,
+                           "schnakenberg", SCHNAK, None, (1.0, 0.9)),
+    "lin1_3d_four_line": ((96, 48, 128), ("dirichlet", "neumann", "periodic"), (0.02,), 0.04, "linear",
+                          {"C": [[-0.7]]}, None, (0.0,)),
 }
 
 
@@ -126,7 +132,7 @@ def test_adjoint_step_matches_oracle(name):
     shape, bcs, D, k, model, params, shift, offset = CASES[name]
     s = len(D)
     print(f"[adjoint step] {name} shape={shape}", flush=True)
-    lpw = 2 if "two_line" in name else "auto"
+    lpw = 4 if "four_line" in name else (2 if "two_line" in name else "auto")
     e = _etd().EtdRdp(shape, bcs, D, k, model, params, shift=shift, lines_per_wave=lpw)
     U, lam = make_inputs(shape, s, offset, seed=len(name))
     lo, g = gpu_adjoint(e, U, lam)
