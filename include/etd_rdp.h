@@ -121,7 +121,9 @@ typedef struct etd_reaction_t {
  * cross-lane reduction levels per line, 32-line tiles), or, on request,
  * four lines of 16 chunks when n = 16 m with 2 <= m <= 8 (64-line tiles).
  * Results agree with the one-line form to rounding (the chunking differs). */
-#define ETD_LINES_AUTO 0   /* two where n allows and a pass has >= 8192 lines  */
+#define ETD_LINES_AUTO 0   /* on passes of >= 8192 lines four where n allows,
+                              else two where n allows; on passes of <= 128
+                              lines two where n allows; else one               */
 #define ETD_LINES_ONE 1    /* always one                                       */
 #define ETD_LINES_TWO 2    /* two wherever n allows                            */
 #define ETD_LINES_FOUR 4   /* four lines of 16 chunks where n = 16 m (2 <= m <=

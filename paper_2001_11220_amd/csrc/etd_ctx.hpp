@@ -84,6 +84,8 @@ constexpr int kMinTwoLineM = 2;
 // lines per pass) 125 -> 102 us and 128^3 174 -> 129 us with two lines,
 // but 64^3 (4096 lines) 52 -> 57 us and 2-D grids of 256 lines 33 -> 43 us.
 constexpr int64_t kTwoLineMinLines = 8192;
+// ... and at most this many (latency-bound small problems).
+constexpr int64_t kTwoLineMaxTinyLines = 128;
 // Four lines per wavefront (ETD_LINES_FOUR): lines of n = 16 m rows with m in
 // [kMinTwoLineM, kMaxRegularM], 16 chunks per line; returns m or 0.
 inline int four_line_chunk(int64_t n) {

@@ -1074,11 +1074,17 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     // n = 16 m (n <= 128), else two of 32 where n = 32 m, on passes of at
     // least kTwoLineMinLines lines (measured, one step: 64^4 1.87 -> 1.18 ms
     // and 128^3 124 -> 107 us with four lines against two).
+    // Passes of at most kTwoLineMaxTinyLines lines (a few tiles, bound by
+    // the latency of one tile's solves) take two lines as well: 2-D 64^2
+    // 23.5 -> 20.6 us and 128^2 27.1 -> 23.6 us per step, while 256^2 ran
+    // slower with two (33 -> 43 us).
     const int64_t lines = N / n;
     const bool multi = !cplx && !general;
     const bool many = (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines);
+    const bool tiny = (lpw == ETD_LINES_AUTO && lines <= kTwoLineMaxTinyLines);
     const int m4 = (multi && (lpw == ETD_LINES_FOUR || many)) ? four_line_chunk(n) : 0;
-    const int m2 = (multi && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR || many)) ? two_line_chunk(n) : 0;
+    const int m2 = (multi && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR || many || tiny))
+                       ? two_line_chunk(n) : 0;
     c->m2[i] = multi ? two_line_chunk(n) : 0;
     c->gen[i] = general ? 1 : 0;
     c->n[i] = n;

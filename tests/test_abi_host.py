@@ -72,8 +72,11 @@ def test_lines_per_wave_option():
     big = _init((256, 256, 160), bcs)
     assert [big.line_split(a) for a in (1, 2, 3)] == [(8, 32), (8, 32), (5, 32)]
     assert big.pass_kernel(1) == "k_first_pair<8, 16, 2, true, false, double>"
-    small = _init((256, 12, 10), bcs)
+    small = _init((256, 24, 10), bcs)  # 240 lines: one line per wavefront
     assert small.line_split(1) == (4, 64) and small.pass_kernel(1) == "k_first<4, 2, 16, false, double>"
+    tiny = _init((256, 12, 10), bcs)  # 120 lines (latency-bound): two
+    assert tiny.line_split(1) == (8, 32)
+    tiny.close()
     two = _init((256, 12, 10), bcs, lines_per_wave=2)
     assert two.line_split(1) == (8, 32) and two.pass_kernel(1) == "k_first_pair<8, 16, 2, false, false, double>"
     assert two.line_split(2) == (1, 12)  # lengths that are not 32 m keep one line
@@ -106,8 +109,8 @@ def test_precision_option():
     # the carried arrays halve; the FP64 tables are the same
     n = 256 * 256 * 160 * 2
     assert d64.ws_bytes - f32.ws_bytes == 6 * (8 - 4) * n
-    small = _init((64, 48), ("neumann", "periodic"), precision="f32")
-    assert small.pass_kernel(1) == "k_first<1, 2, 16, false, float>"
+    small = _init((64, 48), ("neumann", "periodic"), precision="f32")  # 48 lines: two per wavefront
+    assert small.pass_kernel(1) == "k_first_pair<2, 16, 2, false, false, float>"
     for p in (d64, f32, small):
         p.close()
     with pytest.raises(KeyError):

@@ -33,7 +33,10 @@ def test_ensemble_matches_single_problem_path_and_oracle():
     got, b = run_batch(ens, 3)
     assert b.launches_per_step >= 2
     for i, ins in enumerate(ens.instances):
-        e = EtdRdp(ins["shape"], ins["bcs"], ins["D"], ens.k, ens.model, ins["params"])
+        # one line per wavefront: the chunking of the batch's default plan for
+        # groups this small (the single path's automatic choice may take two
+        # lines for passes of at most 128 lines, equal only to rounding)
+        e = EtdRdp(ins["shape"], ins["bcs"], ins["D"], ens.k, ens.model, ins["params"], lines_per_wave=1)
         u = torch.from_numpy(ens.states[i].copy()).cuda()
         e.step(u, 3)
         torch.cuda.synchronize()
@@ -85,7 +88,8 @@ def test_f32_ensemble_matches_oracle_and_single_problem_f32_path():
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         worst = max(worst, err)
         assert err <= tol, (i, ins["shape"], err, tol)
-        e = EtdRdp(ins["shape"], ins["bcs"], ins["D"], ens.k, ens.model, ins["params"], precision="f32")
+        e = EtdRdp(ins["shape"], ins["bcs"], ins["D"], ens.k, ens.model, ins["params"], precision="f32",
+                   lines_per_wave=1)  # the batch default plan's chunking, as above
         us = torch.from_numpy(ens.states[i].astype(np.float32)).cuda()
         e.step(us, nsteps)
         torch.cuda.synchronize()
