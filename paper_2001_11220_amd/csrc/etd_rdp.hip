@@ -586,7 +586,10 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
         }
       }
       if (c->P[0] == 2) {
-        if constexpr (S == 2) {
+        // species-paired only where a species' tile row (16 lines) is a
+        // whole 128-byte line: FP64 (FP32 paired measured 188 us against 175
+        // us with k_first_s at 256^3)
+        if constexpr (S == 2 && sizeof(T) == 8) {
           return nt ? launch_first_pair<M, 2, true, T>(c, u, c1, c2, w, tabs, st)
                     : launch_first_pair<M, 2, false, T>(c, u, c1, c2, w, tabs, st);
         } else {
@@ -1362,7 +1365,7 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const bool z = (ctx->precision == ETD_PRECISION_C128);
   const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : (z ? "zd" : "double");
   const int sw = (z && m > 4) ? 8 : kStreamWaves;  // kStreamBlockWaves
-  if (first && P > 1 && ctx->s == 2 && !z) {
+  if (first && P > 1 && ctx->s == 2 && !z && (P == 4 || ctx->precision == ETD_PRECISION_F64)) {
     const int n = std::snprintf(name, size, "k_first_pair<%d, %d, %d, %s%s, %s>", m, kPairWaves / 2 * P, P,
                                 nt, e1, ty);
     return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;

@@ -110,7 +110,7 @@ def test_precision_option():
     n = 256 * 256 * 160 * 2
     assert d64.ws_bytes - f32.ws_bytes == 6 * (8 - 4) * n
     small = _init((64, 48), ("neumann", "periodic"), precision="f32")  # 48 lines: two per wavefront
-    assert small.pass_kernel(1) == "k_first_pair<2, 16, 2, false, false, float>"
+    assert small.pass_kernel(1) == "k_first_s<2, 2, 32, 2, false, false, float>"
     for p in (d64, f32, small):
         p.close()
     with pytest.raises(KeyError):
