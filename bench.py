@@ -276,7 +276,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-steps", type=int, default=50)
     ap.add_argument("--checkpoint-every", type=int, default=20,
-                    help="gradient workload: steps between stored states")
+                    help="gradient workload: steps between stored states (checkpointed plan)")
+    ap.add_argument("--keep", default="auto", choices=["auto", "true", "false"],
+                    help="gradient workload: store every step's carried arrays (true), "
+                         "checkpoint and recompute (false), or store when it fits (auto)")
     ap.add_argument("--n", type=int, default=None,
                     help="grid points per axis (default: the workload's own size)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
@@ -679,10 +682,18 @@ def bench_adjoint(args, cpu=None):
     print(f"[bench] {prob.name} shape={prob.shape} steps={steps} checkpoint every {every}, "
           f"ws={e.adj_ws_bytes/2**30:.2f} GiB", file=sys.stderr, flush=True)
 
+    keep = {"auto": "auto", "true": True, "false": False}[args.keep]
+    if keep == "auto":
+        free, _ = torch.cuda.mem_get_info(dev)
+        keep = steps * (e.keep_bytes + u0.numel() * 8) <= 0.5 * free
+    plan = "stored" if keep else "checkpointed"
+    print(f"[bench] memory plan: {plan} ({steps} x {e.keep_bytes/2**20:.0f} MiB kept arrays)"
+          if keep else f"[bench] memory plan: {plan}", file=sys.stderr, flush=True)
+
     def grad_run(nsteps):
         x = u0.clone().requires_grad_(True)
         p = torch.tensor(e.param_vector(), dtype=torch.float64, requires_grad=True)
-        uT = trajectory(e, x, nsteps, p, checkpoint_every=every)
+        uT = trajectory(e, x, nsteps, p, checkpoint_every=every, keep=keep)
         loss = ((uT - target) ** 2).sum()
         loss.backward()
         return loss, x.grad, p.grad
@@ -716,14 +727,39 @@ def bench_adjoint(args, cpu=None):
     ev1.record(stream)
     torch.cuda.synchronize()
     adj_ms = ev0.elapsed_time(ev1) / args.pass_steps
+    # the reverse step on kept arrays (what the stored plan runs)
+    kept = e.new_keep(1)
+    e.step_keep(u0.clone(), kept[0])
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.pass_steps):
+        e.adjoint(u0, lam, lam_out=lam, grad=g, kept=kept[0])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    kept_ms = ev0.elapsed_time(ev1) / args.pass_steps
+    del kept
     value = cs * steps / (ms / 1e3)
     # Reverse step: forward recompute of passes 1-2 (4 + 6 words), reverse
-    # passes for axis 3 (7), axis 2 (9) and axis 1 (5): 31 words per cell-species.
+    # passes for axis 3 (7), axis 2 (9) and axis 1 (5): 31 words per
+    # cell-species; 21 on kept arrays (the three reverse passes).
     adj_bytes = 31 * 8 * cs
     adj_gbs = adj_bytes / (adj_ms / 1e3) / 1e9
+    kept_bytes = 21 * 8 * cs
+    kept_gbs = kept_bytes / (kept_ms / 1e3) / 1e9
     print(f"[bench] gradient {ms:.1f} ms ({ms/steps:.3f} ms/step); forward alone {fwd_ms:.1f} ms; "
-          f"reverse step {adj_ms*1e3:.1f} us ({adj_gbs:.0f} GB/s algorithmic); loss={float(loss.detach()):.6e}",
+          f"reverse step {adj_ms*1e3:.1f} us ({adj_gbs:.0f} GB/s algorithmic), on kept arrays "
+          f"{kept_ms*1e3:.1f} us ({kept_gbs:.0f} GB/s); loss={float(loss.detach()):.6e}",
           file=sys.stderr, flush=True)
+    if keep:
+        roof = {"bound": "hbm", "achieved": kept_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": kept_gbs / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "etd_rdp_adjoint_kept (one reverse step on kept arrays: 3 reverse passes)",
+                "avg_launch_us": kept_ms * 1e3, "alg_bytes_per_launch": kept_bytes}
+    else:
+        roof = {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": adj_gbs / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "etd_rdp_adjoint (one reverse step: 2 forward + 3 reverse passes)",
+                "avg_launch_us": adj_ms * 1e3, "alg_bytes_per_launch": adj_bytes}
     out = {
         "metric": "cell-species-steps/sec",
         "value": value,
@@ -740,12 +776,11 @@ def bench_adjoint(args, cpu=None):
         "config": {"workload": prob.name, "grid": list(prob.shape), "bcs": list(prob.bcs),
                    "species": prob.s, "k": prob.k, "model": prob.model,
                    "gradient": "dL/d(u0, D, a, b, gamma) of sum (U(T) - U_target)^2",
-                   "checkpoint_every": every, "grad_finite": finite,
-                   "forward_only_ms": fwd_ms, "gradient_over_forward": ms / fwd_ms},
-        "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": adj_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "etd_rdp_adjoint (one reverse step: 2 forward + 3 reverse passes)",
-                     "avg_launch_us": adj_ms * 1e3, "alg_bytes_per_launch": adj_bytes},
+                   "memory_plan": plan, "checkpoint_every": None if keep else every,
+                   "grad_finite": finite, "forward_only_ms": fwd_ms,
+                   "gradient_over_forward": ms / fwd_ms,
+                   "reverse_step_us": adj_ms * 1e3, "reverse_step_kept_us": kept_ms * 1e3},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -910,22 +910,31 @@ hipError_t launch_ka_first(const etd_rdp_ctx* c, const double* u, double* const 
     default: return ETD_ERR_INTERNAL;               \
   }
 
+// kept: the forward step's carried triples (etd_rdp_step_keep), or null to
+// recompute them in the workspace.
 int run_adjoint(etd_rdp_ctx* c, const double* u, const double* lam_in, double* lam_out,
-                double* grad, void* ws, hipStream_t st) {
+                double* grad, void* ws, hipStream_t st, const void* kept = nullptr) {
   const SolveTab* tabs = static_cast<const SolveTab*>(ws);
   // A: pass 1's triple, B: pass 2's (3-D), Y: the adjoints, in u's layout.
-  double* const A[3] = {ws_array(c, ws, 0), ws_array(c, ws, 1), ws_array(c, ws, 2)};
-  double* const B[3] = {ws_array(c, ws, 3), ws_array(c, ws, 4), ws_array(c, ws, 5)};
+  auto arr = [&](int i) {
+    return kept ? reinterpret_cast<double*>(const_cast<char*>(static_cast<const char*>(kept)) +
+                                            i * c->arr_bytes)
+                : ws_array(c, ws, i);
+  };
+  double* const A[3] = {arr(0), arr(1), arr(2)};
+  double* const B[3] = {arr(3), arr(4), arr(5)};
   const int nY = (c->d == 3) ? 6 : 3;
   double* const Y[3] = {ws_array(c, ws, nY), ws_array(c, ws, nY + 1), ws_array(c, ws, nY + 2)};
   double* part = ws_array(c, ws, nY + 3);
   const int S = c->s;
-  // Forward recompute of the carried triples.
-  int rc = launch_pass<double>(c, 0, const_cast<double*>(u), A, A, tabs, st);
-  if (rc) return rc;
-  if (c->d == 3) {
-    rc = launch_pass<double>(c, 1, nullptr, A, B, tabs, st);
+  // Forward recompute of the carried triples (unless kept).
+  if (!kept) {
+    int rc = launch_pass<double>(c, 0, const_cast<double*>(u), A, A, tabs, st);
     if (rc) return rc;
+    if (c->d == 3) {
+      rc = launch_pass<double>(c, 1, nullptr, A, B, tabs, st);
+      if (rc) return rc;
+    }
   }
   unsigned nb[kAdjPasses] = {0, 0, 0};
   hipError_t e = hipSuccess;
@@ -1007,6 +1016,24 @@ int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1, 
   rc = ensure_tables(ctx, ws, st);
   if (rc) return rc;
   return run_adjoint(ctx, u_n, lam_np1, lam_n, grad, ws, st);
+}
+
+int etd_rdp_adjoint_kept(etd_rdp_ctx* ctx, const double* u_n, const void* keep, size_t keep_bytes,
+                         const double* lam_np1, double* lam_n, double* grad, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!ctx || !u_n || !keep || !lam_np1 || !lam_n || !grad) return ETD_ERR_ARG;
+  if (u_n == lam_n) return ETD_ERR_ARG;
+  if (ctx->scheme != ETD_SCHEME_RDP || ctx->precision != ETD_PRECISION_F64 || ctx->d > 3 ||
+      ctx->d < 2 || has_general_axis(ctx) || ctx->has_field)
+    return ETD_ERR_UNSUPPORTED;
+  const size_t need = (ctx->d == 3 ? 6 : 3) * ctx->arr_bytes;
+  if (keep_bytes < need || reinterpret_cast<uintptr_t>(keep) % 256 != 0) return ETD_ERR_ARG;
+  int rc = check_ws(ws, ws_bytes, ctx->adj_ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  return run_adjoint(ctx, u_n, lam_np1, lam_n, grad, ws, st, keep);
 }
 
 }  // extern "C"

@@ -813,10 +813,17 @@ namespace {
 // A and writes B, pass 3 of a 4-D step reads B and writes A, pass d reads the
 // last triple written.
 template <typename T>
-int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream_t st) {
+int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream_t st,
+               void* keep = nullptr) {
+  // The carried triples live in the workspace, or in `keep` (the same
+  // arrays in the same order, for a caller that keeps them per step).
   const TabOf<T>* tabs = static_cast<const TabOf<T>*>(ws);
-  T* const A[3] = {ws_array<T>(c, ws, 0), ws_array<T>(c, ws, 1), ws_array<T>(c, ws, 2)};
-  T* const B[3] = {ws_array<T>(c, ws, 3), ws_array<T>(c, ws, 4), ws_array<T>(c, ws, 5)};
+  auto arr = [&](int i) {
+    return keep ? reinterpret_cast<T*>(static_cast<char*>(keep) + i * c->arr_bytes)
+                : ws_array<T>(c, ws, i);
+  };
+  T* const A[3] = {arr(0), arr(1), arr(2)};
+  T* const B[3] = {arr(3), arr(4), arr(5)};
   // The reaction field's two copies (pass 1's layout, pass d's layout).
   c->rx.fld1 = c->has_field ? reinterpret_cast<const double*>(static_cast<char*>(ws) + c->field_off)
                             : nullptr;
@@ -954,6 +961,31 @@ uint64_t g_scratch_owner[kMaxDevices] = {};  // uid of the context whose tables 
 }  // namespace
 
 extern "C" {
+
+int etd_rdp_keep_bytes(const etd_rdp_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return ETD_ERR_ARG;
+  // Where the reverse step exists (etd_rdp_adjoint).
+  if (ctx->d < 2 || ctx->d > 3 || ctx->precision != ETD_PRECISION_F64 ||
+      ctx->scheme != ETD_SCHEME_RDP || has_general_axis(ctx) || ctx->has_field)
+    return ETD_ERR_UNSUPPORTED;
+  *bytes = (ctx->d == 3 ? 6 : 3) * ctx->arr_bytes;
+  return ETD_OK;
+}
+
+int etd_rdp_step_keep(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, void* keep,
+                      size_t keep_bytes, void* stream) {
+  if (!ctx || !u) return ETD_ERR_ARG;
+  size_t need = 0;
+  int rc = etd_rdp_keep_bytes(ctx, &need);
+  if (rc) return rc;
+  if (!keep || keep_bytes < need || reinterpret_cast<uintptr_t>(keep) % 256 != 0) return ETD_ERR_ARG;
+  rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = ensure_tables(ctx, ws, st);
+  if (rc) return rc;
+  return run_passes(ctx, u, ws, 0, ctx->d, st, keep);
+}
 
 int etd_rdp_step_static(etd_rdp_ctx* ctx, double* u, int64_t nsteps, void* stream) {
   if (!ctx || !u || nsteps < 0) return ETD_ERR_ARG;

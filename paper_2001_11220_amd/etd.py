@@ -113,6 +113,9 @@ def _load():
         "etd_rdp_record_graph": (ctypes.c_int, [P, P, P, SZ, I64]),
         "etd_rdp_get_slab": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "etd_rdp_batch_forget_workspace": (ctypes.c_int, [P]),
+        "etd_rdp_keep_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
+        "etd_rdp_step_keep": (ctypes.c_int, [P, P, P, SZ, P, SZ, P]),
+        "etd_rdp_adjoint_kept": (ctypes.c_int, [P, P, P, SZ, P, P, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -391,10 +394,12 @@ class EtdRdp:
         _check(fn(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
                   self.ws_bytes, int(npass), self._stream(stream)), name)
 
-    def adjoint(self, u_n, lam, lam_out=None, grad=None, stream=None):
+    def adjoint(self, u_n, lam, lam_out=None, grad=None, stream=None, kept=None):
         """One reverse step: returns (dL/dU_n, grad) for lam = dL/dU_{n+1}.
         ``grad`` (float64 device tensor of ``grad_size``) is accumulated into;
-        a zero one is made if it is None.  ``lam_out`` may be ``lam``."""
+        a zero one is made if it is None.  ``lam_out`` may be ``lam``.
+        ``kept``: the arrays ``step_keep`` left for the step from ``u_n``
+        (the reverse step then skips recomputing them)."""
         import torch
         pu = self._state_ptr(u_n, self.s)
         pl = self._state_ptr(lam, self.s)
@@ -406,10 +411,48 @@ class EtdRdp:
         if grad.dtype != torch.float64 or not grad.is_cuda or not grad.is_contiguous() or grad.numel() != self.grad_size:
             raise ValueError(f"grad must be a contiguous float64 device tensor of {self.grad_size}")
         self.workspace(self.adj_ws_bytes)
+        if kept is not None:
+            _check(lib.etd_rdp_adjoint_kept(self._ctx, ctypes.c_void_p(pu), ctypes.c_void_p(self._keep_ptr(kept)),
+                                            kept.numel() * 8, ctypes.c_void_p(pl), ctypes.c_void_p(po),
+                                            ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(self._ws_ptr()),
+                                            self._ws_cap, self._stream(stream)), "etd_rdp_adjoint_kept")
+            return lam_out, grad
         _check(lib.etd_rdp_adjoint(self._ctx, ctypes.c_void_p(pu), ctypes.c_void_p(pl), ctypes.c_void_p(po),
                                    ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(self._ws_ptr()),
                                    self._ws_cap, self._stream(stream)), "etd_rdp_adjoint")
         return lam_out, grad
+
+    @property
+    def keep_bytes(self):
+        """Bytes of one step's kept carried arrays (etd_rdp_keep_bytes)."""
+        nb = ctypes.c_size_t()
+        _check(lib.etd_rdp_keep_bytes(self._ctx, ctypes.byref(nb)), "etd_rdp_keep_bytes")
+        return nb.value
+
+    def new_keep(self, count=1):
+        """A float64 device tensor holding ``count`` steps' kept arrays
+        (``keep[i]`` for step i)."""
+        import torch
+        n = self.keep_bytes // 8
+        dev = self._device if self._device is not None else torch.device("cuda", torch.cuda.current_device())
+        return torch.empty((count, n), dtype=torch.float64, device=dev)
+
+    def _keep_ptr(self, keep):
+        import torch
+        if keep.dtype != torch.float64 or not keep.is_cuda or not keep.is_contiguous() or \
+                keep.numel() * 8 < self.keep_bytes or keep.data_ptr() % 256 != 0:
+            raise ValueError("keep must be a contiguous, 256-byte aligned float64 device tensor "
+                             f"of at least {self.keep_bytes} bytes (see new_keep)")
+        return keep.data_ptr()
+
+    def step_keep(self, u, keep, stream=None):
+        """One step of ``u`` in place, its carried arrays left in ``keep``
+        (one row of ``new_keep()``) for ``adjoint(..., kept=keep)``."""
+        p = self._state_ptr(u, self.s)
+        _check(lib.etd_rdp_step_keep(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
+                                     self._ws_cap, ctypes.c_void_p(self._keep_ptr(keep)),
+                                     keep.numel() * 8, self._stream(stream)), "etd_rdp_step_keep")
+        return u
 
     def apply_solve(self, x, axis, sigma, gamma, stream=None):
         p = self._state_ptr(x, 1)

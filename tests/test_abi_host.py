@@ -387,6 +387,48 @@ def test_adjoint_validates_arguments_without_touching_the_gpu():
     assert etd.lib.etd_rdp_grad_size(None, ctypes.byref(n)) == etd.ETD_ERR_ARG
 
 
+def test_kept_steps_validate_arguments_without_touching_the_gpu():
+    """etd_rdp_keep_bytes sizes one step's kept arrays (3 triples' worth in
+    2-D, 6 in 3-D, each array rounded up to 256 bytes) and is refused where
+    the reverse step is; the kept step and kept reverse step refuse missing,
+    small and misaligned buffers before any device work."""
+    etd = _lib()
+    nb = ctypes.c_size_t()
+    p = _init((16, 16), ("neumann", "neumann"))
+    assert etd.lib.etd_rdp_keep_bytes(p._ctx, ctypes.byref(nb)) == etd.ETD_OK
+    assert nb.value == 3 * 2 * 16 * 16 * 8
+    assert etd.lib.etd_rdp_keep_bytes(None, ctypes.byref(nb)) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_keep_bytes(p._ctx, None) == etd.ETD_ERR_ARG
+    q = _init((10, 6, 5), ("neumann", "periodic", "dirichlet"), D=(0.3,), model="linear", params={"C": [[-0.5]]})
+    assert etd.lib.etd_rdp_keep_bytes(q._ctx, ctypes.byref(nb)) == etd.ETD_OK
+    assert nb.value == 6 * 2560  # 300 doubles = 2400 bytes, rounded up to 2560
+    q.close()
+    for kw in (dict(scheme="etd1"), dict(precision="f32")):
+        r = _init((16, 16), ("neumann", "neumann"), **kw)
+        assert etd.lib.etd_rdp_keep_bytes(r._ctx, ctypes.byref(nb)) == etd.ETD_ERR_UNSUPPORTED, kw
+        r.close()
+    for shape, bcs in (((79, 16), ("dirichlet", "neumann")), ((8,), ("neumann",)),
+                       ((4, 4, 4, 4), ("neumann",) * 4)):
+        r = _init(shape, bcs)
+        assert etd.lib.etd_rdp_keep_bytes(r._ctx, ctypes.byref(nb)) == etd.ETD_ERR_UNSUPPORTED, shape
+        r.close()
+    need = 3 * 2 * 16 * 16 * 8
+    u, lam, lo, g = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000))
+    ws, kp = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x100000)
+    sk, ak = etd.lib.etd_rdp_step_keep, etd.lib.etd_rdp_adjoint_kept
+    assert sk(p._ctx, u, ws, p.ws_bytes, None, need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, u, ws, p.ws_bytes, kp, need - 8, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, u, ws, p.ws_bytes, ctypes.c_void_p(0x100008), need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, None, ws, p.ws_bytes, kp, need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, u, None, p.ws_bytes, kp, need, None) == etd.ETD_ERR_WORKSPACE
+    assert ak(p._ctx, u, None, need, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert ak(p._ctx, u, kp, need - 8, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert ak(p._ctx, u, ctypes.c_void_p(0x100008), need, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
+    assert ak(p._ctx, u, kp, need, lam, u, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG  # lam_n == u_n
+    assert ak(p._ctx, u, kp, need, lam, lo, g, ws, p.ws_bytes, None) == etd.ETD_ERR_WORKSPACE
+    p.close()
+
+
 def test_batch_precision_option_without_touching_the_gpu():
     """An FP32 ensemble halves the carried arrays; each step entry point
     refuses the other precision before any device work."""

@@ -178,6 +178,56 @@ def test_adjoint_full_size_schnakenberg_128():
     check_grad(g, np.concatenate([gD, gth]), prob.name, np.concatenate([ts["D"], ts["theta"]]))
 
 
+@pytest.mark.parametrize("name,slab", [("bruss2d_neumann", 0), ("bruss3d_mixed", 0), ("bruss3d_mixed", 4),
+                                       ("schnak3d_rev_two_line", 0), ("schnak3d_four_line", 0),
+                                       ("lin1_3d_m4", 0)])
+def test_kept_step_and_adjoint_are_bitwise_the_plain_ones(name, slab):
+    """etd_rdp_step_keep steps u exactly as etd_rdp_step (also on the slab
+    schedule), and etd_rdp_adjoint_kept on its kept arrays gives dL/dU_n and
+    the gradient bit for bit as etd_rdp_adjoint, which recomputes them."""
+    torch = _torch()
+    shape, bcs, D, k, model, params, shift, offset = CASES[name]
+    lpw = 4 if "four_line" in name else (2 if "two_line" in name else "auto")
+    e = _etd().EtdRdp(shape, bcs, D, k, model, params, shift=shift, lines_per_wave=lpw)
+    if slab:
+        e.slab = slab
+    U, lam = make_inputs(shape, len(D), offset, seed=11)
+    u0 = torch.from_numpy(U).cuda()
+    keep = e.new_keep(2)
+    assert keep.shape == (2, e.keep_bytes // 8)
+    u_plain, u_kept = u0.clone(), u0.clone()
+    e.step(u_plain, 1)
+    e.step_keep(u_kept, keep[1])
+    l = torch.from_numpy(lam).cuda()
+    lo_p, g_p = e.adjoint(u0, l)
+    lo_k, g_k = e.adjoint(u0, l, kept=keep[1])
+    torch.cuda.synchronize()
+    print(f"[kept] {name} slab={slab} keep_bytes={e.keep_bytes}", flush=True)
+    assert torch.equal(u_plain, u_kept)
+    assert torch.equal(lo_p, lo_k) and torch.equal(g_p, g_k)
+    e.close()
+
+
+def test_kept_entry_points_refuse_bad_arguments():
+    torch = _torch()
+    etd = _etd()
+    shape, bcs, D, k, model, params, shift, offset = CASES["bruss2d_neumann"]
+    e = etd.EtdRdp(shape, bcs, D, k, model, params)
+    assert e.keep_bytes == 3 * 2 * 64 * 64 * 8
+    u = torch.ones((2, 64, 64), dtype=torch.float64, device="cuda")
+    small = torch.zeros(e.keep_bytes // 8 - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        e.step_keep(u, small)
+    with pytest.raises(ValueError):
+        e.step_keep(u, e.new_keep(2).reshape(-1)[1:])  # not 256-byte aligned
+    e.close()
+    f = etd.EtdRdp((64, 64), bcs, D, k, model, params, precision="f32")
+    with pytest.raises(etd.EtdError) as ei:
+        f.keep_bytes
+    assert ei.value.status == etd.ETD_ERR_UNSUPPORTED
+    f.close()
+
+
 # ---------------------------------------------------------------------------
 # Checkpointed trajectories through torch.autograd
 # ---------------------------------------------------------------------------
@@ -188,8 +238,8 @@ def _traj_problem():
     return shape, bcs, D, k, model, params
 
 
-@pytest.mark.parametrize("every", [1, 5, 20])
-def test_trajectory_gradient_matches_chained_oracle(every):
+@pytest.mark.parametrize("every,keep", [(1, False), (5, False), (20, False), (5, True)])
+def test_trajectory_gradient_matches_chained_oracle(every, keep):
     torch = _torch()
     from paper_2001_11220_amd.adjoint import trajectory
     shape, bcs, D, k, model, params = _traj_problem()
@@ -200,7 +250,7 @@ def test_trajectory_gradient_matches_chained_oracle(every):
     Wt = rng.standard_normal(U0.shape)
     u0 = torch.from_numpy(U0.copy()).cuda().requires_grad_(True)
     p = torch.tensor(e.param_vector(), dtype=torch.float64, requires_grad=True)
-    uT = trajectory(e, u0, nsteps, p, checkpoint_every=every)
+    uT = trajectory(e, u0, nsteps, p, checkpoint_every=every, keep=keep)
     loss = (uT * torch.from_numpy(Wt).cuda()).sum()
     loss.backward()
     torch.cuda.synchronize()
