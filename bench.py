@@ -651,10 +651,13 @@ def cpu_baseline_adjoint(budget_s: float = 10.0):
 
 def bench_adjoint(args, cpu=None):
     """Gradient of a trajectory loss with respect to the initial state, D and
-    the reaction parameters: 128^3 Neumann Schnakenberg, 400 steps,
-    checkpoints every m steps, loss = sum (U(T) - U_target)^2 with U_target
-    from (Du, Dv, a, b) perturbed by up to 5%.  value counts the
-    cell-species-steps of the trajectory per second of forward + backward."""
+    the reaction parameters: 128^3 Neumann Schnakenberg, 400 steps, loss =
+    sum (U(T) - U_target)^2 with U_target from (Du, Dv, a, b) perturbed by up
+    to 5%.  Memory plan (--keep): every step's carried arrays stored when
+    they fit in half the free device memory (then the checkpointed plan,
+    checkpoints every m steps, is timed as well), else checkpoints every m
+    steps.  value counts the cell-species-steps of the trajectory per second
+    of forward + backward in the chosen plan."""
     import numpy as np
     import torch
 
@@ -690,23 +693,37 @@ def bench_adjoint(args, cpu=None):
     print(f"[bench] memory plan: {plan} ({steps} x {e.keep_bytes/2**20:.0f} MiB kept arrays)"
           if keep else f"[bench] memory plan: {plan}", file=sys.stderr, flush=True)
 
-    def grad_run(nsteps):
+    def grad_run(nsteps, plan_keep):
         x = u0.clone().requires_grad_(True)
         p = torch.tensor(e.param_vector(), dtype=torch.float64, requires_grad=True)
-        uT = trajectory(e, x, nsteps, p, checkpoint_every=every, keep=keep)
+        uT = trajectory(e, x, nsteps, p, checkpoint_every=every, keep=plan_keep)
         loss = ((uT - target) ** 2).sum()
         loss.backward()
         return loss, x.grad, p.grad
 
-    grad_run(min(args.warmup, steps))
-    torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    loss, gx, gp = grad_run(steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+
+    def timed_grad(plan_keep):
+        grad_run(min(args.warmup, steps), plan_keep)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        out = grad_run(steps, plan_keep)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return out, ev0.elapsed_time(ev1)
+
+    (loss, gx, gp), ms = timed_grad(keep)
     finite = bool(torch.isfinite(gx).all().item()) and bool(torch.isfinite(gp).all().item())
+    other_ms = None
+    if keep:
+        # the checkpointed plan as well (checkpoints every `every` steps);
+        # its gradient is bitwise the stored plan's
+        (_, gx2, gp2), other_ms = timed_grad(False)
+        same = bool(torch.equal(gx, gx2)) and bool(torch.equal(gp, gp2))
+        print(f"[bench] checkpointed plan: {other_ms:.1f} ms, gradient bitwise equal to the stored "
+              f"plan's: {same}", file=sys.stderr, flush=True)
+        del gx2, gp2
+        torch.cuda.empty_cache()
     # plain forward of the same trajectory
     u = u0.clone()
     e.step(u, 10)
@@ -779,6 +796,8 @@ def bench_adjoint(args, cpu=None):
                    "memory_plan": plan, "checkpoint_every": None if keep else every,
                    "grad_finite": finite, "forward_only_ms": fwd_ms,
                    "gradient_over_forward": ms / fwd_ms,
+                   "checkpointed_ms": ms if not keep else other_ms,
+                   "checkpointed_over_forward": (ms if not keep else other_ms) / fwd_ms,
                    "reverse_step_us": adj_ms * 1e3, "reverse_step_kept_us": kept_ms * 1e3},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -458,20 +458,23 @@ int etd_rdp_adjoint(etd_rdp_ctx* ctx, const double* u_n, const double* lam_np1,
  *   (d = 3) arrays of s*N doubles, each 256-byte aligned.
  *   ETD_ERR_UNSUPPORTED wherever etd_rdp_adjoint is (d not 2 or 3, FP32,
  *   complex, the first-order scheme, a general axis, a reaction field).
- * etd_rdp_step_keep: one step of u (as etd_rdp_step with nsteps = 1, same
- *   arithmetic, also on the slab schedule), its carried arrays written to
- *   keep (device, at least keep_bytes, 256-byte aligned, caller-owned)
- *   instead of the workspace.  ws: a forward or adjoint workspace.  Errors
- *   as etd_rdp_keep_bytes and etd_rdp_step; ETD_ERR_ARG for a missing, small
- *   or misaligned keep.
+ * etd_rdp_step_keep: one step from u_in to u_out (device states in u's
+ *   layout; the same pointer steps in place, as etd_rdp_step with nsteps = 1,
+ *   same arithmetic, also on the slab schedule; distinct states must not
+ *   overlap), its carried arrays written to keep (device, at least
+ *   keep_bytes, 256-byte aligned, caller-owned) instead of the workspace.
+ *   Out of place, a caller that keeps every state needs no copy.  ws: a
+ *   forward or adjoint workspace.  Errors as etd_rdp_keep_bytes and
+ *   etd_rdp_step; ETD_ERR_ARG for a missing, small or misaligned keep and
+ *   for overlapping distinct states.
  * etd_rdp_adjoint_kept: etd_rdp_adjoint for the step that started from u_n,
  *   with that step's kept arrays (read only).  ws: an adjoint workspace as
  *   for etd_rdp_adjoint (its two carried triples are not used).  Errors as
  *   etd_rdp_adjoint; ETD_ERR_ARG for a missing, small or misaligned keep.
  */
 int etd_rdp_keep_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
-int etd_rdp_step_keep(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
-                      void* keep, size_t keep_bytes, void* stream);
+int etd_rdp_step_keep(etd_rdp_ctx* ctx, const double* u_in, double* u_out, void* ws,
+                      size_t ws_bytes, void* keep, size_t keep_bytes, void* stream);
 int etd_rdp_adjoint_kept(etd_rdp_ctx* ctx, const double* u_n, const void* keep,
                          size_t keep_bytes, const double* lam_np1, double* lam_n,
                          double* grad, void* ws, size_t ws_bytes, void* stream);

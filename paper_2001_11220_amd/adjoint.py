@@ -40,18 +40,21 @@ class _Trajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, params, solver, nsteps, every, keep):
         ctx.params_device = params.device
-        u = u0.detach().clone().contiguous()
+        u = u0.detach()
         if keep == "auto":
             keep = nsteps > 0 and _stored_fits(solver, u, nsteps)
         ctx.stored = bool(keep)
         if ctx.stored:
-            states = torch.empty((nsteps,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+            # states[i + 1] = step(states[i]) out of place: no copies
+            states = torch.empty((nsteps + 1,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+            states[0].copy_(u)
             kept = solver.new_keep(nsteps)
             for i in range(nsteps):
-                states[i].copy_(u)
-                solver.step_keep(u, kept[i])
+                solver.step_keep(states[i], kept[i], out=states[i + 1])
+            u = states[nsteps].clone()
             ctx.states, ctx.kept = states, kept
         else:
+            u = u.clone().contiguous()
             ckpts = []
             done = 0
             while done < nsteps:
@@ -74,22 +77,18 @@ class _Trajectory(torch.autograd.Function):
             ctx.states = ctx.kept = None
         elif nsteps > 0:
             m = min(every, nsteps)
+            # a segment's states: its checkpoint, then seg[1..cnt-1]; seg[0]
+            # takes the output of its last step, which the reverse sweep
+            # does not need
             seg = torch.empty((m,) + tuple(lam.shape), dtype=torch.float64, device=lam.device)
             kept = solver.new_keep(m)
             for i in range(len(ctx.ckpts) - 1, -1, -1):
-                start = i * every
-                cnt = min(every, nsteps - start)
-                seg[0].copy_(ctx.ckpts[i])
+                cnt = min(every, nsteps - i * every)
+                st = [ctx.ckpts[i]] + [seg[j] for j in range(1, cnt)]
                 for j in range(cnt):
-                    if j + 1 < cnt:
-                        seg[j + 1].copy_(seg[j])
-                        solver.step_keep(seg[j + 1], kept[j])
-                    else:
-                        # the segment's last state: its step's arrays only
-                        tmp = seg[j].clone()
-                        solver.step_keep(tmp, kept[j])
+                    solver.step_keep(st[j], kept[j], out=st[j + 1] if j + 1 < cnt else seg[0])
                 for j in range(cnt - 1, -1, -1):
-                    solver.adjoint(seg[j], lam, lam_out=lam, grad=grad, kept=kept[j])
+                    solver.adjoint(st[j], lam, lam_out=lam, grad=grad, kept=kept[j])
             ctx.ckpts = None
         return lam, grad.to(device=ctx.params_device), None, None, None, None
 

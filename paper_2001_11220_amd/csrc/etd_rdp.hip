@@ -814,9 +814,11 @@ namespace {
 // last triple written.
 template <typename T>
 int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream_t st,
-               void* keep = nullptr) {
+               void* keep = nullptr, T* u_out = nullptr) {
   // The carried triples live in the workspace, or in `keep` (the same
-  // arrays in the same order, for a caller that keeps them per step).
+  // arrays in the same order, for a caller that keeps them per step).  Pass
+  // 1 reads u and pass d writes u_out (u when null); with d >= 2 no pass
+  // reads what pass d writes.
   const TabOf<T>* tabs = static_cast<const TabOf<T>*>(ws);
   auto arr = [&](int i) {
     return keep ? reinterpret_cast<T*>(static_cast<char*>(keep) + i * c->arr_bytes)
@@ -852,7 +854,8 @@ int run_passes(etd_rdp_ctx* c, T* u, void* ws, int first, int npasses, hipStream
     // Pass p writes A (p even) or B (p odd) and reads what pass p - 1 wrote.
     const bool into_b = (p % 2 == 1);
     const bool from_b = (p % 2 == 0);
-    const int rc = launch_pass(c, p, u, from_b ? B : A, into_b ? B : A, tabs, st);
+    T* const up = (p == c->d - 1 && u_out) ? u_out : u;
+    const int rc = launch_pass(c, p, up, from_b ? B : A, into_b ? B : A, tabs, st);
     if (rc) return rc;
   }
   return ETD_OK;
@@ -972,19 +975,26 @@ int etd_rdp_keep_bytes(const etd_rdp_ctx* ctx, size_t* bytes) {
   return ETD_OK;
 }
 
-int etd_rdp_step_keep(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes, void* keep,
-                      size_t keep_bytes, void* stream) {
-  if (!ctx || !u) return ETD_ERR_ARG;
+int etd_rdp_step_keep(etd_rdp_ctx* ctx, const double* u_in, double* u_out, void* ws,
+                      size_t ws_bytes, void* keep, size_t keep_bytes, void* stream) {
+  if (!ctx || !u_in || !u_out) return ETD_ERR_ARG;
   size_t need = 0;
   int rc = etd_rdp_keep_bytes(ctx, &need);
   if (rc) return rc;
   if (!keep || keep_bytes < need || reinterpret_cast<uintptr_t>(keep) % 256 != 0) return ETD_ERR_ARG;
+  if (u_in != u_out) {
+    // distinct states must not overlap
+    const size_t sb = static_cast<size_t>(ctx->s) * ctx->N * sizeof(double);
+    const char* a = reinterpret_cast<const char*>(u_in);
+    const char* b = reinterpret_cast<const char*>(u_out);
+    if (a < b + sb && b < a + sb) return ETD_ERR_ARG;
+  }
   rc = check_ws(ws, ws_bytes, ctx->ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = ensure_tables(ctx, ws, st);
   if (rc) return rc;
-  return run_passes(ctx, u, ws, 0, ctx->d, st, keep);
+  return run_passes(ctx, const_cast<double*>(u_in), ws, 0, ctx->d, st, keep, u_out);
 }
 
 int etd_rdp_step_static(etd_rdp_ctx* ctx, double* u, int64_t nsteps, void* stream) {

@@ -114,7 +114,7 @@ def _load():
         "etd_rdp_get_slab": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "etd_rdp_batch_forget_workspace": (ctypes.c_int, [P]),
         "etd_rdp_keep_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
-        "etd_rdp_step_keep": (ctypes.c_int, [P, P, P, SZ, P, SZ, P]),
+        "etd_rdp_step_keep": (ctypes.c_int, [P, P, P, P, SZ, P, SZ, P]),
         "etd_rdp_adjoint_kept": (ctypes.c_int, [P, P, P, SZ, P, P, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
@@ -445,14 +445,19 @@ class EtdRdp:
                              f"of at least {self.keep_bytes} bytes (see new_keep)")
         return keep.data_ptr()
 
-    def step_keep(self, u, keep, stream=None):
-        """One step of ``u`` in place, its carried arrays left in ``keep``
-        (one row of ``new_keep()``) for ``adjoint(..., kept=keep)``."""
+    def step_keep(self, u, keep, out=None, stream=None):
+        """One step of ``u`` into ``out`` (``u`` itself when None, in place),
+        its carried arrays left in ``keep`` (one row of ``new_keep()``) for
+        ``adjoint(..., kept=keep)``.  Returns the stepped state."""
         p = self._state_ptr(u, self.s)
-        _check(lib.etd_rdp_step_keep(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(self._ws_ptr()),
-                                     self._ws_cap, ctypes.c_void_p(self._keep_ptr(keep)),
-                                     keep.numel() * 8, self._stream(stream)), "etd_rdp_step_keep")
-        return u
+        if out is None:
+            out = u
+        po = self._state_ptr(out, self.s)
+        _check(lib.etd_rdp_step_keep(self._ctx, ctypes.c_void_p(p), ctypes.c_void_p(po),
+                                     ctypes.c_void_p(self._ws_ptr()), self._ws_cap,
+                                     ctypes.c_void_p(self._keep_ptr(keep)), keep.numel() * 8,
+                                     self._stream(stream)), "etd_rdp_step_keep")
+        return out
 
     def apply_solve(self, x, axis, sigma, gamma, stream=None):
         p = self._state_ptr(x, 1)

@@ -416,11 +416,16 @@ def test_kept_steps_validate_arguments_without_touching_the_gpu():
     u, lam, lo, g = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000))
     ws, kp = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x100000)
     sk, ak = etd.lib.etd_rdp_step_keep, etd.lib.etd_rdp_adjoint_kept
-    assert sk(p._ctx, u, ws, p.ws_bytes, None, need, None) == etd.ETD_ERR_ARG
-    assert sk(p._ctx, u, ws, p.ws_bytes, kp, need - 8, None) == etd.ETD_ERR_ARG
-    assert sk(p._ctx, u, ws, p.ws_bytes, ctypes.c_void_p(0x100008), need, None) == etd.ETD_ERR_ARG
-    assert sk(p._ctx, None, ws, p.ws_bytes, kp, need, None) == etd.ETD_ERR_ARG
-    assert sk(p._ctx, u, None, p.ws_bytes, kp, need, None) == etd.ETD_ERR_WORKSPACE
+    assert sk(p._ctx, u, u, ws, p.ws_bytes, None, need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, u, u, ws, p.ws_bytes, kp, need - 8, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, u, u, ws, p.ws_bytes, ctypes.c_void_p(0x100008), need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, None, u, ws, p.ws_bytes, kp, need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, u, None, ws, p.ws_bytes, kp, need, None) == etd.ETD_ERR_ARG
+    # distinct states that overlap (the state is 2 * 16 * 16 doubles = 4096 bytes)
+    assert sk(p._ctx, u, ctypes.c_void_p(0x1000 + 4088), ws, p.ws_bytes, kp, need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, ctypes.c_void_p(0x1000 + 4088), u, ws, p.ws_bytes, kp, need, None) == etd.ETD_ERR_ARG
+    assert sk(p._ctx, u, u, None, p.ws_bytes, kp, need, None) == etd.ETD_ERR_WORKSPACE
+    assert sk(p._ctx, u, ctypes.c_void_p(0x1000 + 4096), None, p.ws_bytes, kp, need, None) == etd.ETD_ERR_WORKSPACE
     assert ak(p._ctx, u, None, need, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
     assert ak(p._ctx, u, kp, need - 8, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG
     assert ak(p._ctx, u, ctypes.c_void_p(0x100008), need, lam, lo, g, ws, p.adj_ws_bytes, None) == etd.ETD_ERR_ARG

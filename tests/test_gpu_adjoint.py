@@ -183,8 +183,9 @@ def test_adjoint_full_size_schnakenberg_128():
                                        ("lin1_3d_m4", 0)])
 def test_kept_step_and_adjoint_are_bitwise_the_plain_ones(name, slab):
     """etd_rdp_step_keep steps u exactly as etd_rdp_step (also on the slab
-    schedule), and etd_rdp_adjoint_kept on its kept arrays gives dL/dU_n and
-    the gradient bit for bit as etd_rdp_adjoint, which recomputes them."""
+    schedule; in place and out of place alike), and etd_rdp_adjoint_kept on
+    its kept arrays gives dL/dU_n and the gradient bit for bit as
+    etd_rdp_adjoint, which recomputes them."""
     torch = _torch()
     shape, bcs, D, k, model, params, shift, offset = CASES[name]
     lpw = 4 if "four_line" in name else (2 if "two_line" in name else "auto")
@@ -198,12 +199,16 @@ def test_kept_step_and_adjoint_are_bitwise_the_plain_ones(name, slab):
     u_plain, u_kept = u0.clone(), u0.clone()
     e.step(u_plain, 1)
     e.step_keep(u_kept, keep[1])
+    u_out = torch.full_like(u0, float("nan"))
+    e.step_keep(u0, keep[0], out=u_out)  # out of place: u0 unchanged, the same arrays
     l = torch.from_numpy(lam).cuda()
     lo_p, g_p = e.adjoint(u0, l)
     lo_k, g_k = e.adjoint(u0, l, kept=keep[1])
     torch.cuda.synchronize()
     print(f"[kept] {name} slab={slab} keep_bytes={e.keep_bytes}", flush=True)
-    assert torch.equal(u_plain, u_kept)
+    assert torch.equal(u_plain, u_kept) and torch.equal(u_plain, u_out)
+    assert torch.equal(u0, torch.from_numpy(U).cuda())
+    assert torch.equal(keep[0], keep[1])
     assert torch.equal(lo_p, lo_k) and torch.equal(g_p, g_k)
     e.close()
 
