@@ -50,7 +50,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define ETD_OK 0
 #define ETD_ERR_ARG (-1)          /* invalid argument (see etd_rdp_init)    */
-#define ETD_ERR_UNSUPPORTED (-2)  /* valid problem this build does not run  */
+#define ETD_ERR_UNSUPPORTED (-2)  /* valid problem the library does not run */
 #define ETD_ERR_WORKSPACE (-3)    /* workspace NULL, too small, misaligned  */
 #define ETD_ERR_HIP (-4)          /* a HIP runtime call failed              */
 #define ETD_ERR_INTERNAL (-5)     /* a table self-check failed              */

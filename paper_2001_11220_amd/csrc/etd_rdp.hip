@@ -1046,7 +1046,7 @@ const char* etd_rdp_status_string(int status) {
   switch (status) {
     case ETD_OK: return "ok";
     case ETD_ERR_ARG: return "invalid argument";
-    case ETD_ERR_UNSUPPORTED: return "unsupported problem for this build";
+    case ETD_ERR_UNSUPPORTED: return "unsupported problem (valid, but not run by this library)";
     case ETD_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
     case ETD_ERR_HIP: return "HIP runtime error";
     case ETD_ERR_INTERNAL: return "internal table self-check failed";
