@@ -7,7 +7,7 @@
  * non-linear reaction-diffusion systems with dimensional splitting") with the
  * second-order L-stable ETD-RDP-IF scheme: the d-dimensional frame of
  * Section 6 (eq. donedone for d = 3, eq. done for d = 2, its general-d form
- * for d = 4; for d = 1 the unsplit ETD-RDP, eq. finalle).  Every split factor
+ * for d = 4 .. ETD_MAX_DIM; for d = 1 the unsplit ETD-RDP, eq. finalle).  Every split factor
  * (I + (k/gamma) A_i)^{-1}, gamma in {1, 3, 4}, is applied as a batch of exact
  * 1-D line solves (Section 7) fused with the pointwise reaction.
  *
@@ -83,12 +83,12 @@ extern "C" {
 #define ETD_SCHEME_ETD1 1  /* predictor only: ETD1-IF with Pade-(0,1),
                               first order (eq. duhamel3t)                    */
 
-#define ETD_MAX_DIM 4
+#define ETD_MAX_DIM 8
 #define ETD_MAX_SPECIES 2
 #define ETD_MAX_PARAMS 16
 
 typedef struct etd_grid_t {
-  int32_t d;                  /* spatial dimension: 1, 2, 3 or 4             */
+  int32_t d;                  /* spatial dimension: 1 to ETD_MAX_DIM         */
   int32_t s;                  /* number of species: 1 or 2                   */
   int64_t n[ETD_MAX_DIM];     /* unknowns per axis, n[0] = axis 1 (fastest)  */
   double h[ETD_MAX_DIM];      /* spacing per axis; 0 selects the unit-domain
@@ -172,13 +172,14 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  *  out   : receives the new context (owned by the library; free it with
  *          etd_rdp_destroy).
  *
- * Errors: ETD_ERR_ARG for a NULL pointer, d not in {1,2,3,4}, s not in {1,2},
+ * Errors: ETD_ERR_ARG for a NULL pointer, d not in 1..ETD_MAX_DIM, s not in {1,2},
  * n below the minimum of its BC (Dirichlet 1, Neumann 2, periodic 3), a
  * non-finite or non-positive h or k, a negative or non-finite D, an unknown
  * model or one whose species count differs from s, lines_per_wave not one of
  * ETD_LINES_*, precision not one of ETD_PRECISION_*.  ETD_ERR_UNSUPPORTED for
- * a line length n > 1024 (longer than 64 chunks of 16 rows).
- * ETD_ERR_INTERNAL if a table self-check fails.
+ * a line length n > 1024 (longer than 64 chunks of 16 rows), complex
+ * species with two or four lines per wavefront, and a reaction field with
+ * d >= 5.  ETD_ERR_INTERNAL if a table self-check fails.
  */
 int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D,
                  double k, const etd_scheme_t* scheme,
@@ -205,7 +206,9 @@ int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * axis 2 fastest, then axis 1, then axis 3 ([z][x][y]); pass 2 writes axis 3
  * fastest, then axis 2, then axis 1 ([x][y][z]).  In 4-D, pass 1 writes
  * [i4][i3][i1][i2], pass 2 [i1][i2][i4][i3] and pass 3 (into the first
- * triple's arrays) [i1][i2][i3][i4].  After a full step the
+ * triple's arrays) [i1][i2][i3][i4].  With d >= 5 the layouts are cyclic:
+ * pass p writes axis p+1 fastest, then p+2, ..., d, 1, ..., p (odd passes
+ * into the first triple's arrays, even ones into the second's).  After a full step the
  * contents are unspecified; etd_rdp_debug_passes leaves defined values.
  * Errors: ETD_ERR_ARG (NULL pointer, pass outside 1..d-1).
  */
@@ -315,7 +318,8 @@ int etd_rdp_run_pass_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
  * Steps on that context must use this workspace afterwards (another
  * workspace: ETD_ERR_ARG until set_field is called for it).
  * Errors: ETD_ERR_ARG (NULL pointers, a context without a field),
- * ETD_ERR_WORKSPACE, ETD_ERR_HIP.
+ * ETD_ERR_WORKSPACE, ETD_ERR_HIP.  (etd_rdp_init refuses a field with
+ * d >= 5: ETD_ERR_UNSUPPORTED.)
  */
 int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double* b,
                       void* stream);
@@ -438,7 +442,7 @@ int etd_rdp_adjoint_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * The result is bitwise reproducible for a given device (fixed reduction
  * order).  Asynchronous on `stream`.
  * Errors: ETD_ERR_ARG (NULL pointer, u_n == lam_n), ETD_ERR_UNSUPPORTED
- * (scheme ETD1, d = 1 or 4, FP32 or complex contexts, a general line length
+ * (scheme ETD1, d = 1 or d >= 4, FP32 or complex contexts, a general line length
  * on some axis), ETD_ERR_WORKSPACE,
  * ETD_ERR_HIP.
  */

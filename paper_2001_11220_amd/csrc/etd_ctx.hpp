@@ -14,9 +14,9 @@
 
 struct etd_rdp_ctx {
   int d = 0, s = 0;
-  int64_t n[ETD_MAX_DIM] = {1, 1, 1, 1};
-  double h[ETD_MAX_DIM] = {0, 0, 0, 0};
-  int bc[ETD_MAX_DIM] = {0, 0, 0, 0};
+  int64_t n[ETD_MAX_DIM] = {1, 1, 1, 1, 1, 1, 1, 1};
+  double h[ETD_MAX_DIM] = {};
+  int bc[ETD_MAX_DIM] = {};
   double D[ETD_MAX_SPECIES] = {0, 0};
   double Dim[ETD_MAX_SPECIES] = {0, 0};  // imaginary parts (complex species)
   double k = 0;
@@ -24,14 +24,14 @@ struct etd_rdp_ctx {
   int precision = ETD_PRECISION_F64;  // element type of u and the carried arrays
   etd::Rx rx{};
   int nparams = 0;             // reaction parameters with a gradient
-  int m[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length of the forward passes' tables
-  int P[ETD_MAX_DIM] = {1, 1, 1, 1};  // lines per wavefront of the forward passes (1, 2, 4)
-  int m1[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length with one line per wavefront
-  int m2[ETD_MAX_DIM] = {0, 0, 0, 0};  // chunk length with two (0: n is not 32 m)
+  int m[ETD_MAX_DIM] = {};  // chunk length of the forward passes' tables
+  int P[ETD_MAX_DIM] = {1, 1, 1, 1, 1, 1, 1, 1};  // lines per wavefront of the forward passes (1, 2, 4)
+  int m1[ETD_MAX_DIM] = {};  // chunk length with one line per wavefront
+  int m2[ETD_MAX_DIM] = {};  // chunk length with two (0: n is not 32 m)
   // 1 on an axis whose lines have no chunking into <= 64 equal chunks of
   // <= kMaxRegularM rows: general_chunk's m, the last chunk possibly shorter,
   // run by the general pass kernels (etd_general.hip).
-  int gen[ETD_MAX_DIM] = {0, 0, 0, 0};
+  int gen[ETD_MAX_DIM] = {};
   int64_t N = 0;
   // [axis][species][3] for the forward passes; when some axis runs two lines
   // per wavefront, a second set with one line per wavefront follows at index
@@ -124,8 +124,15 @@ size_t geom_lds(const Geom& g, size_t fixed_lds);
 
 // Pass geometries of the single-problem stepper (see PassGeom), with the
 // forward passes' chunking or (one_line) the one-line-per-wavefront one.
-// kPassMid is axis 2 (3-D and 4-D), kPassMid2 axis 3 of a 4-D step.
-enum PassKind : int { kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3, kPassMid2 = 4 };
+// kPassMid is axis 2 (3-D and 4-D), kPassMid2 axis 3 of a 4-D step; with
+// d >= 5, middle pass p (0-based) is kPassMidN + p (mid_kind).
+enum PassKind : int {
+  kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3, kPassMid2 = 4, kPassMidN = 8
+};
+inline int mid_kind(const etd_rdp_ctx* c, int p) {
+  if (c->d >= 5) return kPassMidN + p;
+  return p == 2 ? kPassMid2 : kPassMid;
+}
 // esize: bytes per element of the tile buffers.
 PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines,
                    bool one_line = false, size_t esize = sizeof(double));

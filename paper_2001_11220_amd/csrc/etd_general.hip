@@ -98,7 +98,7 @@ hipError_t gen_pass(const etd_rdp_ctx* c, int p, T* u, const T* c1, T* const (&l
     return run(kr_last<M, S, L, T>, g, lds, 64 * L, st, u, c1, l1, l2, tabs, c->rx, k, g,
                etd1);
   }
-  const PassGeom g = gen_geom(c, p == 2 ? kPassMid2 : kPassMid, fixed, L, M, sizeof(T));
+  const PassGeom g = gen_geom(c, mid_kind(c, p), fixed, L, M, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   const T* i0 = in[0];
   const T* i1 = in[1];

@@ -385,7 +385,18 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, 
   PassGeom g{};
   g.N = c->N;
   int axis0 = 0;
-  switch (kind) {
+  if (c->d >= 5 && kind != kPassAdjMid) {
+    // Cyclic layouts: the input of pass a (axis a, 0-based) has its axes in
+    // the order a, a+1, ..., d-1, 0, ..., a-1 (fastest first; pass 0 reads
+    // u's own order), so its lines are contiguous and indexed by the other
+    // axes in that order; row j of line f goes to f + j * (N / n_a), which
+    // is the next pass's order (pass d-1 writes u's).
+    axis0 = (kind == kPassFirst) ? 0 : (kind == kPassLast ? c->d - 1 : kind - kPassMidN);
+    const int64_t na = c->n[axis0];
+    g.nF = c->N / na; g.nT = 1;
+    g.inF = na; g.inT = 0;
+    g.outT = 0; g.outRow = c->N / na;
+  } else switch (kind) {
     case kPassFirst:  // x-lines (y, z) of u -> A (y fastest)
       axis0 = 0;
       g.nF = n2; g.nT = n3;
@@ -615,7 +626,7 @@ hipError_t launch_mid_s(const etd_rdp_ctx* c, int p, const T* c1, const T* c2,
   const size_t fixed = lane_lds<kSegLanes<P>, T>(3 * S);
   constexpr int W = kStreamBlockWaves<M, T>;
   constexpr int L = W * P;
-  const PassGeom g = pass_geom(c, p == 2 ? kPassMid2 : kPassMid, fixed, L, false, sizeof(T));
+  const PassGeom g = pass_geom(c, mid_kind(c, p), fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_mid_s<M, S, L, P, NT, T>, lds);
   if (e != hipSuccess) return e;
@@ -633,7 +644,7 @@ hipError_t launch_mid_n(const etd_rdp_ctx* c, int p, const T* c1, const T* c2,
                       const TabOf<T>* tabs, hipStream_t st) {
   const size_t fixed = lane_lds<kLanes, T>(3 * S);
   constexpr int L = kPassLines<M, T>;
-  const PassGeom g = pass_geom(c, p == 2 ? kPassMid2 : kPassMid, fixed, L, false, sizeof(T));
+  const PassGeom g = pass_geom(c, mid_kind(c, p), fixed, L, false, sizeof(T));
   const size_t lds = pass_lds(g, fixed, sizeof(T));
   hipError_t e = set_lds(k_mid<M, S, L, NT, T>, lds);
   if (e != hipSuccess) return e;
@@ -1088,6 +1099,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     if (!std::isfinite(rx->shift[i]) || (cplx && rx->shift[i] != 0.0)) return ETD_ERR_ARG;
   if (cplx && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR)) return ETD_ERR_UNSUPPORTED;
   if (rx->field != 0 && (rx->field != 1 || rx->model != ETD_RX_NLS_Z)) return ETD_ERR_ARG;
+  if (rx->field != 0 && d >= 5) return ETD_ERR_UNSUPPORTED;
 
   etd_rdp_ctx* c = new (std::nothrow) etd_rdp_ctx();
   if (!c) return ETD_ERR_INTERNAL;
@@ -1234,6 +1246,17 @@ int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass, size_t* off_c
   *off_w = ctx->tab_bytes + (first + 2) * ctx->arr_bytes;
   const int64_t n1 = ctx->n[0], n2 = ctx->n[1];
   const int64_t n3 = (ctx->d >= 3) ? ctx->n[2] : 1, n4 = (ctx->d == 4) ? ctx->n[3] : 1;
+  if (ctx->d >= 5) {
+    // cyclic: axes pass, pass + 1, ..., d - 1, 0, ..., pass - 1 (0-based),
+    // fastest first
+    int64_t st = 1;
+    for (int i = 0; i < ctx->d; ++i) {
+      const int a = (pass + i) % ctx->d;
+      strides[a] = st;
+      st *= ctx->n[a];
+    }
+    return ETD_OK;
+  }
   if (pass == 1) {  // [i4][i3][i1][i2]
     strides[0] = n2;
     strides[1] = 1;

@@ -32,7 +32,7 @@ MODEL_PARAMS = {"enzyme": (), "brusselator": ("a", "b"), "gray_scott": ("F", "ka
 SCHEMES = {"rdp": 0, "etd1": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "c128": 2}
 
-MAX_DIM, MAX_SPECIES, MAX_PARAMS = 4, 2, 16
+MAX_DIM, MAX_SPECIES, MAX_PARAMS = 8, 2, 16
 
 
 class Grid(ctypes.Structure):

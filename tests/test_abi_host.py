@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -196,14 +197,47 @@ def test_four_dimensional_option():
     assert e.layout(3)[1] == (n2 * n3 * n4, n3 * n4, n4, 1)
     assert e.layout(3)[0] == e.layout(1)[0]  # pass 3 writes the first triple again
     e.close()
-    with pytest.raises(ValueError):  # five axes do not fit the grid struct
-        _init((4, 4, 4, 4, 4), ("periodic",) * 5)
-    g = etd.Grid()  # the C ABI refuses d = 5 and d = 0
-    for d in (5, 0):
+
+
+def test_five_to_eight_dimensions_without_touching_the_gpu():
+    """d = 5 .. 8 (Section 6's frame for any d): every pass reads its lines
+    contiguously from a cyclic layout (pass p writes axis p+1 fastest, then
+    p+2, ..., d, 1, ..., p), with the same kernels as the other dimensions;
+    the reverse step, single solves and reaction fields are refused; the C
+    ABI refuses d = 0 and d = 9."""
+    from paper_2001_11220_amd import etd
+    shape = (6, 5, 4, 3, 7)
+    e = _init(shape, ("neumann", "periodic", "dirichlet", "neumann", "periodic"))
+    assert len([e.pass_kernel(p) for p in range(1, 6)]) == 5
+    N = int(np.prod(shape))
+    for p in range(1, 5):
+        order = [(p + i) % 5 for i in range(5)]  # fastest first
+        want, st = [0] * 5, 1
+        for a in order:
+            want[a] = st
+            st *= shape[a]
+        assert e.layout(p)[1] == tuple(want), p
+    assert e.layout(1)[0] == e.layout(3)[0] and e.layout(2)[0] == e.layout(4)[0] != e.layout(1)[0]
+    assert e.adj_ws_bytes > 0
+    u, x, g, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x10000))
+    assert etd.lib.etd_rdp_adjoint(e._ctx, u, x, g, g, ws, 1 << 40, None) == etd.ETD_ERR_UNSUPPORTED
+    assert etd.lib.etd_rdp_apply_solve(e._ctx, x, ws, e.ws_bytes, 1, 0, 3, None) == etd.ETD_ERR_UNSUPPORTED
+    e.close()
+    e8 = _init((3,) * 8, ("periodic",) * 8, D=(0.3,), model="linear", params={"C": [[-0.5]]})
+    assert e8.line_split(8) == (1, 3)
+    e8.close()
+    with pytest.raises(etd.EtdError) as ei:
+        etd.EtdRdp((4,) * 5, ("periodic",) * 5, (1 + 1j,), 0.01, "nls_z", {"B": 1.0, "C": 1.0},
+                   precision="c128", field=True)
+    assert ei.value.status == etd.ETD_ERR_UNSUPPORTED
+    with pytest.raises(ValueError):  # nine axes do not fit the grid struct
+        _init((3,) * 9, ("periodic",) * 9)
+    g = etd.Grid()  # the C ABI refuses d = 9 and d = 0
+    for d in (9, 0):
         g.d, g.s = d, 2
-        for i in range(4):
+        for i in range(etd.MAX_DIM):
             g.n[i] = 8
-        bc = (ctypes.c_int32 * 5)(1, 1, 1, 1, 1)
+        bc = (ctypes.c_int32 * 9)(*([1] * 9))
         D = (ctypes.c_double * 2)(0.1, 0.2)
         rx = etd.reaction_struct("brusselator", {"a": 1.0, "b": 3.0}, None, 2)
         ctx = ctypes.c_void_p()

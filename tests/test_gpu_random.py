@@ -1,4 +1,5 @@
-"""Seeded random configurations (dimension 1-4, line lengths with ragged
+"""Seeded random configurations (dimension 1-4, and 5-6 on seeds 60-79;
+line lengths with ragged
 tiles, boundary conditions, models, FP64 / FP32 / complex, one or two lines
 per wavefront, both schemes), each one step on the GPU against the oracle.
 
@@ -32,10 +33,11 @@ REAL_MODELS = [("brusselator", {"a": 1.0, "b": 3.4}, (0.02, 0.011)),
 MIN_N = {"dirichlet": 1, "neumann": 2, "periodic": 3}
 
 
-def _config(seed, lengths=LENGTHS):
+def _config(seed, lengths=LENGTHS, dims=(1, 5)):
     rng = np.random.default_rng(1000 + seed)
-    d = int(rng.integers(1, 5))
-    budget = {1: 1024, 2: 512 * 64, 3: 64 * 64 * 48, 4: 24 * 20 * 16 * 12}[d]
+    d = int(rng.integers(*dims))
+    budget = {1: 1024, 2: 512 * 64, 3: 64 * 64 * 48, 4: 24 * 20 * 16 * 12, 5: 16 * 12 * 10 * 8 * 6,
+              6: 8 * 7 * 6 * 5 * 5 * 4}[d]
     while True:
         shape = tuple(int(rng.choice(lengths)) for _ in range(d))
         if int(np.prod(shape)) <= budget:
@@ -61,12 +63,16 @@ def _config(seed, lengths=LENGTHS):
     return prob, prec, lpw, scheme
 
 
-@pytest.mark.parametrize("seed", range(60))
+@pytest.mark.parametrize("seed", range(80))
 def test_random_configuration_matches_oracle(seed):
-    """Seeds 0-39 draw regular line lengths, seeds 40-59 general ones too."""
+    """Seeds 0-39 draw regular line lengths, seeds 40-59 general ones too,
+    seeds 60-79 five or six axes (regular and general lengths)."""
     import torch
     from paper_2001_11220_amd import etd
-    prob, prec, lpw, scheme = _config(seed, LENGTHS if seed < 40 else LENGTHS + GENERAL)
+    if seed < 60:
+        prob, prec, lpw, scheme = _config(seed, LENGTHS if seed < 40 else LENGTHS + GENERAL)
+    else:
+        prob, prec, lpw, scheme = _config(seed, LENGTHS + GENERAL, dims=(5, 7))
     u0 = prob.initial()
     e = etd.EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, scheme=scheme,
                    lines_per_wave=lpw, precision=prec)

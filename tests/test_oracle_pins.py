@@ -299,6 +299,23 @@ def test_step_equals_dense_kronecker_4d(bcs):
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13)
 
 
+@pytest.mark.parametrize("bcs", [
+    (O.BC_NEUMANN, O.BC_PERIODIC, O.BC_DIRICHLET, O.BC_NEUMANN, O.BC_PERIODIC),
+    (O.BC_PERIODIC, O.BC_DIRICHLET, O.BC_NEUMANN, O.BC_PERIODIC, O.BC_DIRICHLET),
+])
+def test_step_equals_dense_kronecker_5d(bcs):
+    # the general-d frame with five split factors (R on axes 1..4)
+    rng = np.random.default_rng(10)
+    ns = (3, 2, 3, 2, 3)  # n_1 .. n_5
+    bcs = tuple(b if not (b == O.BC_PERIODIC and n < 3) else O.BC_NEUMANN for b, n in zip(bcs, ns))
+    U = 0.5 + 0.3 * rng.random((2,) + ns[::-1])
+    hs = [O.default_h(n, b) for n, b in zip(ns, bcs)]
+    D = [0.02, 0.011]
+    got = O.etd_rdp_if_step(U, 0.05, D, bcs, hs, "brusselator", {"a": 1.0, "b": 3.4})
+    ref = _dense_step(U, 0.05, np.array(D), bcs, hs, "brusselator", {"a": 1.0, "b": 3.4})
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13)
+
+
 @pytest.mark.parametrize("bcs", [(O.BC_NEUMANN,) * 2, (O.BC_DIRICHLET, O.BC_PERIODIC)])
 def test_step_equals_dense_kronecker_2d(bcs):
     rng = np.random.default_rng(8)
@@ -328,11 +345,11 @@ def test_zero_diffusion_is_heun():
     np.testing.assert_allclose(got, heun, rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("d", [2, 3, 4])
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6])
 def test_F0_separable_mode_is_product_of_r(d):
-    bcs = [O.BC_DIRICHLET, O.BC_NEUMANN, O.BC_PERIODIC, O.BC_NEUMANN][:d]
-    ns = [7, 9, 8, 5][:d]
-    js = [2, 1, 3, 2][:d]
+    bcs = [O.BC_DIRICHLET, O.BC_NEUMANN, O.BC_PERIODIC, O.BC_NEUMANN, O.BC_PERIODIC, O.BC_DIRICHLET][:d]
+    ns = [7, 9, 8, 5, 6, 4][:d]
+    js = [2, 1, 3, 2, 1, 3][:d]
     k, D = 0.05, [0.8]
     vs, lams, hs = zip(*[_mode(n, b, j) for n, b, j in zip(ns, bcs, js)])
     U = vs[0]
