@@ -192,7 +192,7 @@ def cpu_baseline(name: str, budget_s: float = 10.0):
 
     sample_n = {"grayscott3d": 64, "schnakenberg3d": 64, "brusselator2d": 64,
                 "schnakenberg3d_adjoint": 64, "cgl3d_complex": 64, "cgl2d_complex": 400,
-                "grayscott4d": 16}[name]
+                "grayscott4d": 16, "grayscott5d": 8}[name]
     prob = W.WORKLOADS[name](n=sample_n)
     cs = prob.cells * prob.s
     state = {"u": prob.initial()}

@@ -170,6 +170,16 @@ def grayscott4d(n: int = 64, nsteps: int = 100, seed: int = 0, shape=None) -> Pr
                    ic="cube_patch", ic_args={"amp": 0.25})
 
 
+def grayscott5d(n: int = 32, nsteps: int = 100, seed: int = 0, shape=None) -> Problem:
+    """The same system on the periodic unit 5-cube, 32^5 cells (as many
+    cells as the 256^3 workload): the general-d frame with five split
+    factors."""
+    shape = tuple(shape) if shape is not None else (n,) * 5
+    return Problem("grayscott5d", shape, ("periodic",) * 5, (2e-5, 1e-5), 1.0,
+                   "gray_scott", {"F": 0.04, "kappa": 0.06}, nsteps, seed=seed,
+                   ic="cube_patch", ic_args={"amp": 0.25})
+
+
 SCHNAK = {"a": 0.1, "b": 0.9, "gamma": 1.0}
 SCHNAK_STEADY = (SCHNAK["a"] + SCHNAK["b"], SCHNAK["b"] / (SCHNAK["a"] + SCHNAK["b"]) ** 2)
 
@@ -267,6 +277,7 @@ WORKLOADS = {
     "brusselator2d": brusselator2d,
     "grayscott3d": grayscott3d,
     "grayscott4d": grayscott4d,
+    "grayscott5d": grayscott5d,
     "schnakenberg3d": schnakenberg3d,
     "schnakenberg3d_adjoint": schnakenberg3d_adjoint,
     "cgl3d_complex": cgl3d_complex,

@@ -321,6 +321,18 @@ def test_grayscott4d_full_size_one_step_sampled():
     assert_close(got[..., x0s], ref, 1e-12, "grayscott4d 64^4 sampled")
 
 
+def test_grayscott5d_full_size_one_step_sampled():
+    """32^5 periodic (four lines of 16 two-row chunks per wavefront on every
+    axis, cyclic layouts), benchmark launch configuration; planes x = x0
+    checked against the oracle."""
+    prob = W.grayscott5d()
+    u0 = prob.initial()
+    got = gpu_run(prob, u0, 1)
+    x0s = [0, 15, 31]
+    ref = _sampled_step_reference(prob, u0, x0s)
+    assert_close(got[..., x0s], ref, 1e-12, "grayscott5d 32^5 sampled")
+
+
 def test_f32_full_size_one_step_sampled_against_oracle():
     """The 256^3 workload in FP32 (two lines per wavefront, non-temporal
     stores), one step on the planes x = x0 against the FP64 oracle: the
