@@ -236,21 +236,31 @@ def ceiling(dev, nbytes: int = 1 << 31, reps: int = 10):
     st = torch.cuda.current_stream()
     ncu = torch.cuda.get_device_properties(dev).multi_processor_count
     out = {"bytes": nbytes, "how": f"etd_calib_stream sweeps of {nbytes / 2**30:.0f} GiB "
-                                   "(256-thread blocks, four 16-byte accesses in flight per thread) "
-                                   "and torch's device copy; best over block counts, HIP events"}
+                                   "(256-thread blocks, four 16-byte accesses in flight per thread; "
+                                   "copy and write with plain and with non-temporal stores; a copy "
+                                   "with 1024-thread blocks streaming contiguous ranges) and "
+                                   "torch's device copy; best over block counts and store kinds, "
+                                   "HIP events"}
+    variants = {"copy": ("copy", "copy_nt", "copy_ranges"), "read": ("read",),
+                "write": ("write", "write_nt")}
     for kind, moved in (("copy", 2 * nbytes), ("read", nbytes), ("write", nbytes)):
-        best = 0.0
-        for blocks in (ncu * 4, ncu * 8, ncu * 16):
-            src, dst = (x, y) if kind == "copy" else ((x, sink) if kind == "read" else (None, y))
-            calib_stream(kind, src, dst, nbytes, blocks)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(st)
-            for _ in range(reps):
-                calib_stream(kind, src, dst, nbytes, blocks)
-            b.record(st)
-            torch.cuda.synchronize()
-            best = max(best, moved * reps / (a.elapsed_time(b) / 1e3) / 1e9)
+        best, best_v = 0.0, None
+        for var in variants[kind]:
+            for blocks in ((ncu * 2, ncu * 4, ncu * 8) if var == "copy_ranges" else (ncu * 4, ncu * 8, ncu * 16)):
+                src, dst = (x, y) if kind == "copy" else ((x, sink) if kind == "read" else (None, y))
+                calib_stream(var, src, dst, nbytes, blocks)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(st)
+                for _ in range(reps):
+                    calib_stream(var, src, dst, nbytes, blocks)
+                b.record(st)
+                torch.cuda.synchronize()
+                rate = moved * reps / (a.elapsed_time(b) / 1e3) / 1e9
+                out[f"{var}_{blocks // ncu}x_GBps"] = rate
+                if rate > best:
+                    best, best_v = rate, var
         out[f"{kind}_GBps"] = best
+        out[f"{kind}_variant"] = best_v
     y.copy_(x)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(st)

@@ -631,11 +631,15 @@ int etd_rdp_batch_group_pass(etd_rdp_batch* b, void* u, void* ws, size_t ws_byte
 
 /*
  * etd_calib_stream -- one streaming sweep over `bytes` bytes of device
- * memory on `stream`, with `blocks` workgroups of 256 threads:
+ * memory on `stream`, with `blocks` workgroups (of 256 threads unless
+ * stated):
  *   kind 0: copy src -> dst (reads and writes `bytes`),
  *   kind 1: read src (dst: device, at least 8 bytes; written only if the
  *           sum of src is -1e308, which finite data never reaches),
- *   kind 2: write dst (src unused, may be NULL).
+ *   kind 2: write dst (src unused, may be NULL),
+ *   kind 3, 4: kinds 0 and 2 with non-temporal stores,
+ *   kind 5: copy with workgroups of 1024 threads, each streaming one
+ *           contiguous range of the buffers, non-temporal stores.
  * Timing these against the passes gives the rate simple streaming code
  * reaches on this device.  bytes must be a multiple of 16 and the pointers
  * 16-byte aligned; the buffers are the caller's.

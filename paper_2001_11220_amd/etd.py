@@ -138,10 +138,11 @@ def _check(status: int, what: str):
 
 def calib_stream(kind: str, src, dst, nbytes: int, blocks: int, stream=None):
     """One bandwidth-calibration sweep (etd_calib_stream) over torch device
-    tensors: kind "copy" (src -> dst), "read" (src; dst a small sink) or
-    "write" (dst)."""
+    tensors: kind "copy" (src -> dst), "read" (src; dst a small sink),
+    "write" (dst), "copy_nt" / "write_nt" (non-temporal stores) or
+    "copy_ranges" (1024-thread blocks, one contiguous range each)."""
     import torch
-    k = {"copy": 0, "read": 1, "write": 2}[kind]
+    k = {"copy": 0, "read": 1, "write": 2, "copy_nt": 3, "write_nt": 4, "copy_ranges": 5}[kind]
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(lib.etd_calib_stream(k, None if src is None else src.data_ptr(), dst.data_ptr(),
                                 int(nbytes), int(blocks), ctypes.c_void_p(st.cuda_stream)),

@@ -468,6 +468,22 @@ def test_kept_steps_validate_arguments_without_touching_the_gpu():
     p.close()
 
 
+def test_calibration_sweeps_validate_arguments_without_touching_the_gpu():
+    etd = _lib()
+    f = etd.lib.etd_calib_stream
+    a, b = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert f(6, a, b, 4096, 8, None) == etd.ETD_ERR_ARG       # unknown kind
+    assert f(-1, a, b, 4096, 8, None) == etd.ETD_ERR_ARG
+    for kind in (0, 1, 3, 5):
+        assert f(kind, None, b, 4096, 8, None) == etd.ETD_ERR_ARG  # needs a source
+    for kind in range(6):
+        assert f(kind, a, None, 4096, 8, None) == etd.ETD_ERR_ARG
+        assert f(kind, a, b, 4100, 8, None) == etd.ETD_ERR_ARG     # not whole 16-byte elements
+        assert f(kind, a, ctypes.c_void_p(0x2008), 4096, 8, None) == etd.ETD_ERR_ARG
+        assert f(kind, a, b, 4096, 0, None) == etd.ETD_ERR_ARG
+        assert f(kind, a, b, 0, 8, None) == etd.ETD_OK             # nothing to do
+
+
 def test_batch_precision_option_without_touching_the_gpu():
     """An FP32 ensemble halves the carried arrays; each step entry point
     refuses the other precision before any device work."""
