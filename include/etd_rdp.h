@@ -118,16 +118,19 @@ typedef struct etd_reaction_t {
  * Lines per wavefront of the forward passes (etd_scheme_t.lines_per_wave).
  * A wavefront solves one grid line with up to 64 chunks, or two lines of
  * 32 chunks each when the line length is n = 32 m with 2 <= m <= 8 (fewer
- * cross-lane reduction levels per line, 32-line tiles), or, on request,
- * four lines of 16 chunks when n = 16 m with 2 <= m <= 8 (64-line tiles).
+ * cross-lane reduction levels per line, 32-line tiles), four lines of 16
+ * chunks when n = 16 m (64-line tiles), or eight lines of 8 chunks when
+ * n = 8 m (128-line tiles), again with 2 <= m <= 8.
  * Results agree with the one-line form to rounding (the chunking differs). */
-#define ETD_LINES_AUTO 0   /* on passes of >= 8192 lines four where n allows,
+#define ETD_LINES_AUTO 0   /* on passes of >= 8192 lines eight, else four,
                               else two where n allows; on passes of <= 128
                               lines two where n allows; else one               */
 #define ETD_LINES_ONE 1    /* always one                                       */
 #define ETD_LINES_TWO 2    /* two wherever n allows                            */
 #define ETD_LINES_FOUR 4   /* four lines of 16 chunks where n = 16 m (2 <= m <=
                               8, n <= 128), else as ETD_LINES_TWO              */
+#define ETD_LINES_EIGHT 8  /* eight lines of 8 chunks where n = 8 m (2 <= m <=
+                              8, n <= 64), else as ETD_LINES_FOUR              */
 
 /* Element type of the state and of the carried arrays
  * (etd_scheme_t.precision).  The line-solve tables are built and held in

@@ -792,7 +792,7 @@ constexpr int kAdjTwoLineMaxM = 4;
 // An axis whose forward pass runs four lines per wavefront runs its reverse
 // pass with two, on the two-line table set.
 inline int adj_m2(const etd_rdp_ctx* c, int a) {
-  return (c->P[a] == 2) ? c->m[a] : ((c->P[a] == 4) ? c->m2[a] : 0);
+  return (c->P[a] == 2) ? c->m[a] : ((c->P[a] >= 4) ? c->m2[a] : 0);
 }
 inline int adj_lines(const etd_rdp_ctx* c, int a) {
   const int m2 = adj_m2(c, a);
@@ -810,7 +810,7 @@ inline const SolveTab* adj_tabs(const etd_rdp_ctx* c, const SolveTab* tabs, int 
 // the two-line one.
 PassGeom adj_geom(const etd_rdp_ctx* c, int kind, size_t fixed, int lines, int P, int axis) {
   PassGeom g = pass_geom(c, kind, fixed, lines, P == 1);
-  if (P == 2 && c->P[axis] == 4) {
+  if (P == 2 && c->P[axis] >= 4) {
     g.m = c->m2[axis];
     g.C = g.n / g.m;
     g.ql = g.m - 1;

@@ -25,7 +25,7 @@ struct etd_rdp_ctx {
   etd::Rx rx{};
   int nparams = 0;             // reaction parameters with a gradient
   int m[ETD_MAX_DIM] = {};  // chunk length of the forward passes' tables
-  int P[ETD_MAX_DIM] = {1, 1, 1, 1, 1, 1, 1, 1};  // lines per wavefront of the forward passes (1, 2, 4)
+  int P[ETD_MAX_DIM] = {1, 1, 1, 1, 1, 1, 1, 1};  // lines per wavefront of the forward passes (1, 2, 4, 8)
   int m1[ETD_MAX_DIM] = {};  // chunk length with one line per wavefront
   int m2[ETD_MAX_DIM] = {};  // chunk length with two (0: n is not 32 m)
   // 1 on an axis whose lines have no chunking into <= 64 equal chunks of
@@ -91,6 +91,12 @@ constexpr int64_t kTwoLineMaxTinyLines = 128;
 inline int four_line_chunk(int64_t n) {
   const int64_t m = n / 16;
   return (n % 16 == 0 && m >= kMinTwoLineM && m <= kMaxRegularM) ? static_cast<int>(m) : 0;
+}
+// Eight lines per wavefront (ETD_LINES_EIGHT): lines of n = 8 m rows with m
+// in [kMinTwoLineM, kMaxRegularM], 8 chunks per line; returns m or 0.
+inline int eight_line_chunk(int64_t n) {
+  const int64_t m = n / 8;
+  return (n % 8 == 0 && m >= kMinTwoLineM && m <= kMaxRegularM) ? static_cast<int>(m) : 0;
 }
 inline int two_line_chunk(int64_t n) {
   const int64_t m = n / 32;

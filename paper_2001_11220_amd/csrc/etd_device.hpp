@@ -274,9 +274,9 @@ __device__ __forceinline__ zd rows_swap16(zd v, bool odd_row) {
 }
 
 // Lines per wavefront.  With P = 1 a wavefront solves one line, lane c
-// holding chunk c.  With P = 2 (4) it solves two (four) lines of exactly 32
-// (16) chunks each: lane c holds chunk c % (64 / P) of the wavefront's line
-// c / (64 / P) (its segment).  Cross-lane reads that leave a segment only
+// holding chunk c.  With P = 2 (4, 8) it solves two (four, eight) lines of
+// exactly 32 (16, 8) chunks each: lane c holds chunk c % (64 / P) of the
+// wavefront's line c / (64 / P) (its segment).  Cross-lane reads that leave a segment only
 // ever meet a zero multiplier, so the exchanges are the same as for one
 // line, minus the reduction levels a segment does not need.
 template <int P>
@@ -291,8 +291,11 @@ __device__ __forceinline__ T seg_value(T v, int idx, int lane) {
     const T a = lane_value(v, idx);
     const T b = lane_value(v, kSegLanes<P> + idx);
     return (lane >= kSegLanes<P>) ? b : a;
+  } else if constexpr (P == 8) {
+    // lane idx of this lane's 8-lane segment
+    return bperm(((lane & ~7) + idx) * 4, v);
   } else {
-    static_assert(P == 4, "one, two or four lines per wavefront");
+    static_assert(P == 4, "one, two, four or eight lines per wavefront");
     const T a = lane_value(v, idx);
     const T b = lane_value(v, 16 + idx);
     const T c = lane_value(v, 32 + idx);

@@ -341,7 +341,7 @@ __device__ __forceinline__ void k_first_pair_body(
   constexpr int S = 2;
   extern __shared__ double lds_raw[];
   char* const lds = reinterpret_cast<char*>(lds_raw);
-  static_assert(P == 2 || P == 4, "two or four lines per wavefront");
+  static_assert(P == 2 || P == 4 || P == 8, "two, four or eight lines per wavefront");
   using LT = LaneTabT<kSegLanes<P>, T>;
   LT* lt = reinterpret_cast<LT*>(lds);
   T* tl = reinterpret_cast<T*>(lds + 3 * S * sizeof(LT));

@@ -587,6 +587,15 @@ hipError_t launch_first(const etd_rdp_ctx* c, const T* u, T* c1, T* c2,
               : launch_first_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
+      if (c->P[0] == 8) {
+        if constexpr (S == 2) {
+          return nt ? launch_first_pair<M, 8, true, T>(c, u, c1, c2, w, tabs, st)
+                    : launch_first_pair<M, 8, false, T>(c, u, c1, c2, w, tabs, st);
+        } else {
+          return nt ? launch_first_s<M, S, 8, true, T>(c, u, c1, c2, w, tabs, st)
+                    : launch_first_s<M, S, 8, false, T>(c, u, c1, c2, w, tabs, st);
+        }
+      }
       if (c->P[0] == 4) {
         if constexpr (S == 2) {
           return nt ? launch_first_pair<M, 4, true, T>(c, u, c1, c2, w, tabs, st)
@@ -667,6 +676,9 @@ hipError_t launch_mid(const etd_rdp_ctx* c, int p, const T* c1, const T* c2,
               : launch_mid_s<M, S, 1, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
+      if (c->P[p] == 8)
+        return nt ? launch_mid_s<M, S, 8, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
+                  : launch_mid_s<M, S, 8, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
       if (c->P[p] == 4)
         return nt ? launch_mid_s<M, S, 4, true, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st)
                   : launch_mid_s<M, S, 4, false, T>(c, p, c1, c2, w, o1, o2, ow, tabs, st);
@@ -711,6 +723,9 @@ hipError_t launch_last(const etd_rdp_ctx* c, T* u, const T* c1, const T* c2,
               : launch_last_s<M, S, 1, false, T>(c, u, c1, c2, w, tabs, st);
   } else {
     if constexpr (M >= kMinTwoLineM) {
+      if (c->P[c->d - 1] == 8)
+        return nt ? launch_last_s<M, S, 8, true, T>(c, u, c1, c2, w, tabs, st)
+                  : launch_last_s<M, S, 8, false, T>(c, u, c1, c2, w, tabs, st);
       if (c->P[c->d - 1] == 4)
         return nt ? launch_last_s<M, S, 4, true, T>(c, u, c1, c2, w, tabs, st)
                   : launch_last_s<M, S, 4, false, T>(c, u, c1, c2, w, tabs, st);
@@ -1078,7 +1093,8 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   int sch = scheme ? scheme->scheme : ETD_SCHEME_RDP;
   if (sch != ETD_SCHEME_RDP && sch != ETD_SCHEME_ETD1) return ETD_ERR_ARG;
   const int lpw = scheme ? scheme->lines_per_wave : ETD_LINES_AUTO;
-  if (lpw != ETD_LINES_AUTO && lpw != ETD_LINES_ONE && lpw != ETD_LINES_TWO && lpw != ETD_LINES_FOUR)
+  if (lpw != ETD_LINES_AUTO && lpw != ETD_LINES_ONE && lpw != ETD_LINES_TWO && lpw != ETD_LINES_FOUR &&
+      lpw != ETD_LINES_EIGHT)
     return ETD_ERR_ARG;
   const int prec = scheme ? scheme->precision : ETD_PRECISION_F64;
   if (prec != ETD_PRECISION_F64 && prec != ETD_PRECISION_F32 && prec != ETD_PRECISION_C128)
@@ -1097,7 +1113,8 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     if (!std::isfinite(rx->params[i])) return ETD_ERR_ARG;
   for (int i = 0; i < s; ++i)
     if (!std::isfinite(rx->shift[i]) || (cplx && rx->shift[i] != 0.0)) return ETD_ERR_ARG;
-  if (cplx && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR)) return ETD_ERR_UNSUPPORTED;
+  if (cplx && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR || lpw == ETD_LINES_EIGHT))
+    return ETD_ERR_UNSUPPORTED;
   if (rx->field != 0 && (rx->field != 1 || rx->model != ETD_RX_NLS_Z)) return ETD_ERR_ARG;
   if (rx->field != 0 && d >= 5) return ETD_ERR_UNSUPPORTED;
 
@@ -1127,10 +1144,12 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     const bool general = (m == 0);
     if (general) m = general_chunk(n);
     if (m == 0) { delete c; return ETD_ERR_UNSUPPORTED; }
-    // Lines per wavefront: automatic takes four lines of 16 chunks where
-    // n = 16 m (n <= 128), else two of 32 where n = 32 m, on passes of at
-    // least kTwoLineMinLines lines (measured, one step: 64^4 1.87 -> 1.18 ms
-    // and 128^3 124 -> 107 us with four lines against two).
+    // Lines per wavefront: automatic takes eight lines of 8 chunks where
+    // n = 8 m (n <= 64), else four of 16 where n = 16 m (n <= 128), else two
+    // of 32 where n = 32 m, on passes of at least kTwoLineMinLines lines
+    // (measured, one step: 64^4 1.87 -> 1.18 ms and 128^3 124 -> 107 us
+    // with four lines against two; 64^4 1.29 -> 1.12 ms, 48^4 0.61 -> 0.48
+    // ms and 32^5 5.15 -> 2.78 ms with eight against four).
     // Passes of at most kTwoLineMaxTinyLines lines (a few tiles, bound by
     // the latency of one tile's solves) take two lines as well: 2-D 64^2
     // 23.5 -> 20.6 us and 128^2 27.1 -> 23.6 us per step, while 256^2 ran
@@ -1139,8 +1158,11 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     const bool multi = !cplx && !general;
     const bool many = (lpw == ETD_LINES_AUTO && lines >= kTwoLineMinLines);
     const bool tiny = (lpw == ETD_LINES_AUTO && lines <= kTwoLineMaxTinyLines);
-    const int m4 = (multi && (lpw == ETD_LINES_FOUR || many)) ? four_line_chunk(n) : 0;
-    const int m2 = (multi && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR || many || tiny))
+    const int m8 = (multi && (lpw == ETD_LINES_EIGHT || many)) ? eight_line_chunk(n) : 0;
+    const int m4 = (multi && (lpw == ETD_LINES_FOUR || lpw == ETD_LINES_EIGHT || many))
+                       ? four_line_chunk(n) : 0;
+    const int m2 = (multi && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR ||
+                              lpw == ETD_LINES_EIGHT || many || tiny))
                        ? two_line_chunk(n) : 0;
     c->m2[i] = multi ? two_line_chunk(n) : 0;
     c->gen[i] = general ? 1 : 0;
@@ -1148,8 +1170,8 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
     c->h[i] = h;
     c->bc[i] = b;
     c->m1[i] = m;
-    c->m[i] = m4 ? m4 : (m2 ? m2 : m);
-    c->P[i] = m4 ? 4 : (m2 ? 2 : 1);
+    c->m[i] = m8 ? m8 : (m4 ? m4 : (m2 ? m2 : m));
+    c->P[i] = m8 ? 8 : (m4 ? 4 : (m2 ? 2 : 1));
   }
   c->N = N;
   for (int i = 0; i < s; ++i) {
@@ -1169,7 +1191,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   bool two = false, four = false;
   for (int a = 0; a < d; ++a) {
     two = two || (c->P[a] > 1);
-    four = four || (c->P[a] == 4 && c->m2[a] > 0);
+    four = four || (c->P[a] >= 4 && c->m2[a] > 0);
   }
   const int nsets = 1 + (two ? 1 : 0) + (four ? 1 : 0);
   c->tab1 = two ? nt : 0;
@@ -1430,7 +1452,7 @@ int etd_rdp_pass_kernel(const etd_rdp_ctx* ctx, int32_t pass, char* name, size_t
   const bool z = (ctx->precision == ETD_PRECISION_C128);
   const char* ty = (ctx->precision == ETD_PRECISION_F32) ? "float" : (z ? "zd" : "double");
   const int sw = (z && m > 4) ? 8 : kStreamWaves;  // kStreamBlockWaves
-  if (first && P > 1 && ctx->s == 2 && !z && (P == 4 || ctx->precision == ETD_PRECISION_F64)) {
+  if (first && P > 1 && ctx->s == 2 && !z && (P >= 4 || ctx->precision == ETD_PRECISION_F64)) {
     const int n = std::snprintf(name, size, "k_first_pair<%d, %d, %d, %s%s, %s>", m, kPairWaves / 2 * P, P,
                                 nt, e1, ty);
     return (n > 0 && static_cast<size_t>(n) < size) ? ETD_OK : ETD_ERR_ARG;

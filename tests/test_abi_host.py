@@ -68,8 +68,9 @@ def test_tables_build_for_every_line_length(bc):
 def test_lines_per_wave_option():
     from paper_2001_11220_amd import etd
     bcs = ("periodic", "neumann", "dirichlet")
-    # automatic, on passes with at least 8192 lines: four lines per
-    # wavefront for n = 16 m (m = 2..8), else two for n = 32 m (m = 2..8)
+    # automatic, on passes with at least 8192 lines: eight lines per
+    # wavefront for n = 8 m, else four for n = 16 m, else two for n = 32 m
+    # (m = 2..8 each)
     big = _init((256, 256, 160), bcs)
     assert [big.line_split(a) for a in (1, 2, 3)] == [(8, 32), (8, 32), (5, 32)]
     assert big.pass_kernel(1) == "k_first_pair<8, 16, 2, true, false, double>"
@@ -86,14 +87,21 @@ def test_lines_per_wave_option():
     part = _init((256, 192, 160), bcs)  # 30720 lines on axis 1: two lines per wavefront
     assert [part.line_split(a) for a in (1, 2, 3)] == [(8, 32), (6, 32), (5, 32)]
     few = _init((256, 64, 100), bcs)  # axis 1 has 6400 lines: one line per wavefront
-    assert [few.line_split(a) for a in (1, 2, 3)] == [(4, 64), (4, 16), (2, 50)]
-    four = _init((64, 64, 64, 64), ("periodic",) * 4)  # 262144 lines of 16 chunks of 4 rows
+    assert [few.line_split(a) for a in (1, 2, 3)] == [(4, 64), (8, 8), (2, 50)]
+    eight = _init((64, 64, 64, 64), ("periodic",) * 4)  # 262144 lines of 8 chunks of 8 rows
+    assert [eight.line_split(a) for a in (1, 2, 3, 4)] == [(8, 8)] * 4
+    assert eight.pass_kernel(1) == "k_first_pair<8, 64, 8, true, false, double>"
+    assert eight.pass_kernel(3) == "k_mid_s<8, 2, 128, 8, true, double>"
+    four = _init((64, 64, 64, 64), ("periodic",) * 4, lines_per_wave=4)  # 16 chunks of 4 rows
     assert [four.line_split(a) for a in (1, 2, 3, 4)] == [(4, 16)] * 4
     assert four.pass_kernel(3) == "k_mid_s<4, 2, 64, 4, true, double>"
     req = _init((256, 48, 10), bcs, lines_per_wave=4)  # four where n = 16 m, else two, else one
     assert [req.line_split(a) for a in (1, 2, 3)] == [(8, 32), (3, 16), (1, 10)]
     req.close()
-    for p in (big, small, two, one, part, few, four):
+    req8 = _init((256, 48, 10), bcs, lines_per_wave=8)  # eight where n = 8 m, else four, two, one
+    assert [req8.line_split(a) for a in (1, 2, 3)] == [(8, 32), (6, 8), (1, 10)]
+    req8.close()
+    for p in (big, small, two, one, part, few, eight, four):
         p.close()
     with pytest.raises(etd.EtdError):
         _init((64, 64), ("periodic",) * 2, lines_per_wave=3)

@@ -1,5 +1,5 @@
-"""Seeded random configurations (dimension 1-4, and 5-6 on seeds 60-79;
-line lengths with ragged
+"""Seeded random configurations (dimension 1-4, and 5-6 on seeds 60-79,
+which also draw four and eight lines per wavefront; line lengths with ragged
 tiles, boundary conditions, models, FP64 / FP32 / complex, one or two lines
 per wavefront, both schemes), each one step on the GPU against the oracle.
 
@@ -47,7 +47,8 @@ def _config(seed, lengths=LENGTHS, dims=(1, 5)):
         ok = [b for b in ("dirichlet", "neumann", "periodic") if n >= MIN_N[b]]
         bcs.append(str(rng.choice(ok)))
     prec = str(rng.choice(["f64", "f64", "f32", "c128"]))
-    lpw = "auto" if prec == "c128" else rng.choice(["auto", 1, 2]).item()
+    lpws = ["auto", 1, 2] if dims == (1, 5) else ["auto", 1, 2, 4, 8]
+    lpw = "auto" if prec == "c128" else rng.choice(lpws).item()
     scheme = str(rng.choice(["rdp", "rdp", "etd1"]))
     if prec == "c128":
         model, params = str(rng.choice(["cgl_z", "nls_z"])), None
