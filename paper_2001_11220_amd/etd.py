@@ -174,7 +174,7 @@ class EtdRdp:
     ``shape`` is ``(n_1, ..., n_d)`` (axis 1 first); states are torch float64
     tensors of shape ``(s, n_d, ..., n_1)`` on a HIP device.  ``h`` entries of
     0 (or ``None``) select the unit-domain spacing of each boundary condition.
-    ``lines_per_wave`` is "auto", 1, 2 or 4 (ETD_LINES_* of the C ABI).
+    ``lines_per_wave`` is "auto", 1, 2, 4 or 8 (ETD_LINES_* of the C ABI).
     ``precision`` "f32" makes the state and the carried arrays float32 (the
     reverse-mode step and the single solves stay "f64" only); "c128" is for
     one complex species (models "cgl_z", "nls_z", complex ``D``): states are
