@@ -181,7 +181,7 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  * model or one whose species count differs from s, lines_per_wave not one of
  * ETD_LINES_*, precision not one of ETD_PRECISION_*.  ETD_ERR_UNSUPPORTED for
  * a line length n > 1024 (longer than 64 chunks of 16 rows), complex
- * species with two or four lines per wavefront, and a reaction field with
+ * species with two, four or eight lines per wavefront, and a reaction field with
  * d >= 5.  ETD_ERR_INTERNAL if a table self-check fails.
  */
 int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D,

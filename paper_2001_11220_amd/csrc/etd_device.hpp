@@ -331,8 +331,9 @@ __device__ __forceinline__ void stage_lane_tabs(const TabOf<T>* __restrict__ tab
 // K exact solves at once on this wavefront's line(s): x[k] holds this
 // lane's chunk of right-hand side k on entry and of the solution on exit,
 // with table tab[k] (header in global memory, uniform) and lt[k] (per-lane
-// data in LDS, indexed by the lane's chunk).  P lines per wavefront (1 or
-// 2; with 2, the table has exactly 32 chunks).  All 64 lanes must call it
+// data in LDS, indexed by the lane's chunk).  P lines per wavefront (1, 2,
+// 4 or 8; with P > 1 the table has exactly 64 / P chunks, and the reduction
+// needs log2(64 / P) levels).  All 64 lanes must call it
 // together.
 //
 // RAGGED (general lines, one line per wavefront): the table's chunk length
@@ -425,7 +426,8 @@ __device__ __forceinline__ void line_solve(const TabOf<T>* const (&tab)[K],
   // at distance sh have a zero multiplier; what they read there does not
   // matter.  Distance 1 uses DPP shifts, distances 16 and 32 permlane
   // swaps, the others ds_bpermute.  With two lines per wavefront the last
-  // level has distance 16, within the 32-lane halves: one row swap.
+  // level has distance 16, within the 32-lane halves: one row swap; with
+  // four (eight) the last is distance 8 (4).
   if (npcr > 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {

@@ -471,8 +471,8 @@ namespace {
 
 // Chunk lengths from which the passes run streamed (k_first_s, k_mid_s,
 // k_last_s), and the wavefronts per block those use (a tile is
-// kStreamWaves * P lines).  Axes with two lines per wavefront always run
-// streamed.
+// kStreamWaves * P lines).  Axes with more than one line per wavefront
+// always run streamed.
 constexpr int kStreamFirstFrom = 8;
 constexpr int kStreamMidFrom = 5;
 constexpr int kStreamLastFrom = 5;
@@ -1187,7 +1187,7 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   // Table sets: [0] the forward passes' chunking; [tab1] one line per
   // wavefront (reverse kernels, single solves) when some axis runs more than
   // one; [tab2] two lines per wavefront (the reverse kernels' two-line form)
-  // when some axis runs four.
+  // when some axis runs four or eight.
   bool two = false, four = false;
   for (int a = 0; a < d; ++a) {
     two = two || (c->P[a] > 1);
