@@ -164,8 +164,8 @@ __device__ __forceinline__ void k_first_body(
 // ---------------------------------------------------------------------------
 // Pass 1, streamed: the work of k_first in phases of at most two solves per
 // species (P on U + k f, T and S on f, T and S on U), so that a 16- or
-// 32-line tile of long chunks fits the register budget.  Each species' pass
-// evaluates its f from the tile's lines of every species.
+// 32-line tile of long chunks fits the register budget.  The tile's lines
+// of every species are read once; F is evaluated for all species at once.
 // ---------------------------------------------------------------------------
 template <bool G, int S, int M, typename T>
 __device__ __forceinline__ void react_species(const Rx& rx, const GroupCoef& gc, int64_t t,
@@ -201,12 +201,9 @@ __device__ __forceinline__ void k_first_s_body(
   TileWalk walk(g.nFblk * g.nT, G);
   int64_t tile, next;
   bool have = walk.next(tile);
-  // A tile's lines are fetched during the previous tile's last phase (when
-  // its U is no longer live; the last tile re-reads its own, unused, so that
-  // the buffer is dead between its uses).  A later species re-reads the
-  // tile's lines the same way, fetched during the previous species' last
-  // phase (mostly from HBM: parking them in LDS instead cost the second tile
-  // buffer and measured slower).
+  // A tile's lines (every species) are read once, fetched during the
+  // previous tile's last phase (when its U is no longer live; the last tile
+  // re-reads its own, unused, so that the buffer is dead between its uses).
   T Un[S][M];
   auto fetch = [&](int64_t t_) {
     const TileAt p(t_, g);
@@ -249,29 +246,52 @@ __device__ __forceinline__ void k_first_s_body(
     const TileAt pos(tile, g);
     restage<G, S>(at, lt, tabs, gc, pos.t, staged);
     const bool have_next = walk.next(next);
-    T U[S][M];
+    if constexpr (S == 2) {
+      // Both species' F at once, then P and T, S on f for each species in
+      // turn, then T, S on U for each, so that each input dies after its
+      // last phase.  (Evaluating each species' F in its own phases needs
+      // the other species' U again: held in registers that spilled at m = 8,
+      // or read again from L2, 1.56x the U a 512^3 pass needs and 10%
+      // slower.)
+      T U[S][M], F[S][M];
 #pragma unroll
-    for (int q = 0; q < S; ++q)
+      for (int q = 0; q < S; ++q)
 #pragma unroll
-      for (int j = 0; j < M; ++j) U[q][j] = Un[q][j];
+        for (int j = 0; j < M; ++j) U[q][j] = Un[q][j];
+      double bf[M];
+      field_line<M, P, T, R>(rx.fld1, bf, g, pos);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s > 0) {
-        // this tile's lines, fetched during the previous species' last phase
+      for (int j = 0; j < M; ++j) {
+        T uu[S], ff[S];
 #pragma unroll
-        for (int q = 0; q < S; ++q)
+        for (int q = 0; q < S; ++q) uu[q] = U[q][j];
+        react_at<G, S>(rx, gc, pos.t, uu, ff, bf[j]);
 #pragma unroll
-          for (int j = 0; j < M; ++j) U[q][j] = Un[q][j];
+        for (int q = 0; q < S; ++q) F[q][j] = ff[q];
       }
+      const int64_t pf = have_next ? next : tile;
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        first_p_phase(U[q], F[q], q, pos, E1 && q == S - 1, pf);
+        if (!E1) first_rs_phase(F[q], q, c2, pos, false, pf);
+      }
+      if (!E1) {
+        first_rs_phase(U[0], 0, c1, pos, false, pf);
+        first_rs_phase(U[1], 1, c1, pos, true, pf);
+      }
+    } else {
+      T U[S][M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) U[0][j] = Un[0][j];
       T f[M];
       double bf[M];
       field_line<M, P, T, R>(rx.fld1, bf, g, pos);
-      react_species<G, S, M>(rx, gc, pos.t, U, s, bf, f);
-      const int64_t pf = (s == S - 1) ? (have_next ? next : tile) : tile;
-      first_p_phase(U[s], f, s, pos, E1, pf);
+      react_species<G, S, M>(rx, gc, pos.t, U, 0, bf, f);
+      const int64_t pf = have_next ? next : tile;
+      first_p_phase(U[0], f, 0, pos, E1, pf);
       if (!E1) {
-        first_rs_phase(f, s, c2, pos, false, pf);
-        first_rs_phase(U[s], s, c1, pos, true, pf);
+        first_rs_phase(f, 0, c2, pos, false, pf);
+        first_rs_phase(U[0], 0, c1, pos, true, pf);
       }
     }
     tile = next;
