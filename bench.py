@@ -754,6 +754,13 @@ def bench_adjoint(args, cpu=None):
     ev1.record(stream)
     torch.cuda.synchronize()
     adj_ms = ev0.elapsed_time(ev1) / args.pass_steps
+    if args.calib_copy:
+        # one plain 1 GiB device copy (scale of the counter readings)
+        xc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        yc = torch.empty_like(xc)
+        yc.copy_(xc)
+        torch.cuda.synchronize()
+        del xc, yc
     # the reverse step on kept arrays (what the stored plan runs)
     kept = e.new_keep(1)
     e.step_keep(u0.clone(), kept[0])

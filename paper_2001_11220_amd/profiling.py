@@ -93,11 +93,40 @@ def traffic(fetch_db: str, write_db: str, copy_bytes: int):
     return out
 
 
+# SQ counters read by `sq`: wave-cycles resident, waiting (any reason, or
+# for an instruction's dependency), and with an instruction of each kind in
+# flight, per dispatch summed over the device.
+SQ_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY",
+               "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM")
+
+
+def sq_summary(db: str):
+    """kernel -> {counter: median per dispatch} and the fractions of resident
+    wave-cycles spent waiting / with VALU, LDS or VMEM instructions active."""
+    cs = counters(db)
+    out = {}
+    for (kn, cn), v in cs.items():
+        if not kn.startswith("void etd::") or cn not in SQ_COUNTERS:
+            continue
+        out.setdefault(short_name(kn), {})[cn] = sorted(v)[len(v) // 2]
+    for k, r in out.items():
+        wc = r.get("SQ_WAVE_CYCLES") or 0
+        if wc:
+            for cn, tag in (("SQ_WAIT_ANY", "wait_any"), ("SQ_WAIT_INST_ANY", "wait_inst"),
+                            ("SQ_ACTIVE_INST_VALU", "valu"), ("SQ_ACTIVE_INST_LDS", "lds"),
+                            ("SQ_ACTIVE_INST_VMEM", "vmem"), ("SQ_ACTIVE_INST_ANY", "any_inst")):
+                if cn in r:
+                    r[f"frac_{tag}"] = r[cn] / wc
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     k = sub.add_parser("kernels")
     k.add_argument("db")
+    q = sub.add_parser("sq")
+    q.add_argument("db")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -105,6 +134,14 @@ def main(argv=None):
     t.add_argument("--workload", required=True)
     t.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "sq":
+        res = sq_summary(a.db)
+        print(f"{'kernel':60s} {'waves':>8} {'wait':>6} {'inst':>6} {'valu':>6} {'lds':>6} {'vmem':>6}")
+        for name, r in sorted(res.items()):
+            print(f"{name[:60]:60s} {r.get('SQ_WAVES', 0):8.0f} {r.get('frac_wait_any', 0):6.2f} "
+                  f"{r.get('frac_wait_inst', 0):6.2f} {r.get('frac_valu', 0):6.2f} "
+                  f"{r.get('frac_lds', 0):6.2f} {r.get('frac_vmem', 0):6.2f}")
+        return
     if a.cmd == "kernels":
         times = kernel_times(a.db)
         print(f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10}  kernel")
