@@ -207,11 +207,12 @@ int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * inside each species plane (species planes are N doubles apart).  Each
  * pass writes the layout the next pass reads line by line: pass 1 writes
  * axis 2 fastest, then axis 1, then axis 3 ([z][x][y]); pass 2 writes axis 3
- * fastest, then axis 2, then axis 1 ([x][y][z]).  In 4-D, pass 1 writes
+ * fastest, then axis 2, then axis 1 ([x][y][z]).  With d >= 4 the layouts
+ * are cyclic: pass p writes axis p+1 fastest, then p+2, ..., d, 1, ..., p
+ * (odd passes into the first triple's arrays, even ones into the second's);
+ * except that a 4-D context with a reaction field has pass 1 write
  * [i4][i3][i1][i2], pass 2 [i1][i2][i4][i3] and pass 3 (into the first
- * triple's arrays) [i1][i2][i3][i4].  With d >= 5 the layouts are cyclic:
- * pass p writes axis p+1 fastest, then p+2, ..., d, 1, ..., p (odd passes
- * into the first triple's arrays, even ones into the second's).  After a full step the
+ * triple's arrays) [i1][i2][i3][i4].  After a full step the
  * contents are unspecified; etd_rdp_debug_passes leaves defined values.
  * Errors: ETD_ERR_ARG (NULL pointer, pass outside 1..d-1).
  */

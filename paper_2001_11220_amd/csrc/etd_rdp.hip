@@ -378,14 +378,15 @@ size_t geom_lds(const Geom& g, size_t fixed_lds) {
 
 PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, bool one_line,
                    size_t esize) {
-  // In 4-D, passes 1 and 2 see axes 3 and 4 as one flattened axis (n3 below,
-  // axis 3 the faster), which their layouts keep contiguous.
+  // In 4-D with a reaction field, passes 1 and 2 see axes 3 and 4 as one
+  // flattened axis (n3 below, axis 3 the faster), which their layouts keep
+  // contiguous.
   const int64_t n1 = c->n[0], n2 = c->n[1];
   const int64_t n3 = (c->d >= 3) ? c->n[2] * (c->d == 4 ? c->n[3] : 1) : 1;
   PassGeom g{};
   g.N = c->N;
   int axis0 = 0;
-  if (c->d >= 5 && kind != kPassAdjMid) {
+  if (cyclic_layout(c) && kind != kPassAdjMid) {
     // Cyclic layouts: the input of pass a (axis a, 0-based) has its axes in
     // the order a, a+1, ..., d-1, 0, ..., a-1 (fastest first; pass 0 reads
     // u's own order), so its lines are contiguous and indexed by the other
@@ -1268,7 +1269,7 @@ int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass, size_t* off_c
   *off_w = ctx->tab_bytes + (first + 2) * ctx->arr_bytes;
   const int64_t n1 = ctx->n[0], n2 = ctx->n[1];
   const int64_t n3 = (ctx->d >= 3) ? ctx->n[2] : 1, n4 = (ctx->d == 4) ? ctx->n[3] : 1;
-  if (ctx->d >= 5) {
+  if (cyclic_layout(ctx)) {
     // cyclic: axes pass, pass + 1, ..., d - 1, 0, ..., pass - 1 (0-based),
     // fastest first
     int64_t st = 1;

@@ -199,12 +199,21 @@ def test_four_dimensional_option():
         "k_first<2, 2, 16, false, double>", "k_mid<1, 2, 16, false, double>",
         "k_mid<2, 2, 16, false, double>", "k_last<1, 2, 16, false, double>"]
     n1, n2, n3, n4 = 96, 8, 70, 5
-    # layouts of the carried triples (axis strides 1..4)
-    assert e.layout(1)[1] == (n2, 1, n1 * n2, n1 * n2 * n3)
-    assert e.layout(2)[1] == (n2 * n3 * n4, n3 * n4, 1, n3)
-    assert e.layout(3)[1] == (n2 * n3 * n4, n3 * n4, n4, 1)
+    # layouts of the carried triples (axis strides 1..4): cyclic, pass p
+    # writes axis p+1 fastest, then p+2, ..., 4, 1, ..., p
+    assert e.layout(1)[1] == (n2 * n3 * n4, 1, n2, n2 * n3)
+    assert e.layout(2)[1] == (n3 * n4, n3 * n4 * n1, 1, n3)
+    assert e.layout(3)[1] == (n4, n4 * n1, n4 * n1 * n2, 1)
     assert e.layout(3)[0] == e.layout(1)[0]  # pass 3 writes the first triple again
     e.close()
+    # with a reaction field the fixed 4-D layouts (the field's copies are
+    # stored in them)
+    z = etd.EtdRdp((n1, n2, n3, n4), ("neumann", "periodic", "dirichlet", "neumann"), (1j,), 1e-3, "nls_z",
+                   {"B": 0.4, "C": -1.0}, precision="c128", field=True)
+    assert z.layout(1)[1] == (n2, 1, n1 * n2, n1 * n2 * n3)
+    assert z.layout(2)[1] == (n2 * n3 * n4, n3 * n4, 1, n3)
+    assert z.layout(3)[1] == (n2 * n3 * n4, n3 * n4, n4, 1)
+    z.close()
 
 
 def test_five_to_eight_dimensions_without_touching_the_gpu():
