@@ -181,8 +181,8 @@ typedef struct etd_rdp_ctx etd_rdp_ctx;
  * model or one whose species count differs from s, lines_per_wave not one of
  * ETD_LINES_*, precision not one of ETD_PRECISION_*.  ETD_ERR_UNSUPPORTED for
  * a line length n > 1024 (longer than 64 chunks of 16 rows), complex
- * species with two, four or eight lines per wavefront, and a reaction field with
- * d >= 5.  ETD_ERR_INTERNAL if a table self-check fails.
+ * species with two, four or eight lines per wavefront.  ETD_ERR_INTERNAL if
+ * a table self-check fails.
  */
 int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D,
                  double k, const etd_scheme_t* scheme,
@@ -209,10 +209,8 @@ int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
  * axis 2 fastest, then axis 1, then axis 3 ([z][x][y]); pass 2 writes axis 3
  * fastest, then axis 2, then axis 1 ([x][y][z]).  With d >= 4 the layouts
  * are cyclic: pass p writes axis p+1 fastest, then p+2, ..., d, 1, ..., p
- * (odd passes into the first triple's arrays, even ones into the second's);
- * except that a 4-D context with a reaction field has pass 1 write
- * [i4][i3][i1][i2], pass 2 [i1][i2][i4][i3] and pass 3 (into the first
- * triple's arrays) [i1][i2][i3][i4].  After a full step the
+ * (odd passes into the first triple's arrays, even ones into the second's).
+ * After a full step the
  * contents are unspecified; etd_rdp_debug_passes leaves defined values.
  * Errors: ETD_ERR_ARG (NULL pointer, pass outside 1..d-1).
  */
@@ -322,8 +320,7 @@ int etd_rdp_run_pass_z(etd_rdp_ctx* ctx, double* u, void* ws, size_t ws_bytes,
  * Steps on that context must use this workspace afterwards (another
  * workspace: ETD_ERR_ARG until set_field is called for it).
  * Errors: ETD_ERR_ARG (NULL pointers, a context without a field),
- * ETD_ERR_WORKSPACE, ETD_ERR_HIP.  (etd_rdp_init refuses a field with
- * d >= 5: ETD_ERR_UNSUPPORTED.)
+ * ETD_ERR_WORKSPACE, ETD_ERR_HIP.
  */
 int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double* b,
                       void* stream);

@@ -130,22 +130,17 @@ size_t geom_lds(const Geom& g, size_t fixed_lds);
 
 // Pass geometries of the single-problem stepper (see PassGeom), with the
 // forward passes' chunking or (one_line) the one-line-per-wavefront one.
-// kPassMid is axis 2 (3-D, and 4-D with a reaction field), kPassMid2 axis 3
-// of a 4-D step with a field; with cyclic layouts, middle pass p (0-based) is
-// kPassMidN + p (mid_kind).
+// kPassMid is axis 2 of a 3-D step; with cyclic layouts (d >= 4), middle
+// pass p (0-based) is kPassMidN + p (mid_kind).
 enum PassKind : int {
-  kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3, kPassMid2 = 4, kPassMidN = 8
+  kPassFirst = 0, kPassMid = 1, kPassLast = 2, kPassAdjMid = 3, kPassMidN = 8
 };
 // Cyclic layouts (pass a reads axes a, a+1, ..., d-1, 0, ..., a-1, fastest
 // first, so every pass's lines are contiguous and a tile row spans all N/n_a
-// of them) from four dimensions on.  A 4-D run with a reaction field keeps
-// the fixed 4-D layouts, in which the field's per-pass copies are stored.
-inline bool cyclic_layout(const etd_rdp_ctx* c) {
-  return c->d >= 5 || (c->d == 4 && !c->has_field);
-}
+// of them) from four dimensions on.
+inline bool cyclic_layout(const etd_rdp_ctx* c) { return c->d >= 4; }
 inline int mid_kind(const etd_rdp_ctx* c, int p) {
-  if (cyclic_layout(c)) return kPassMidN + p;
-  return p == 2 ? kPassMid2 : kPassMid;
+  return cyclic_layout(c) ? kPassMidN + p : kPassMid;
 }
 // esize: bytes per element of the tile buffers.
 PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines,

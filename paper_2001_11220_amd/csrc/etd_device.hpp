@@ -659,9 +659,6 @@ __device__ __forceinline__ void load_chunk(const T* __restrict__ p, T (&v)[M], b
 struct PassGeom {
   int64_t nF, nT, nFblk;
   int64_t inF, inT, outT, outRow;
-  // Two-level line index (4-D): t = ta * nT2 + tb sits at ta * inT + tb * inT2
-  // (ta * outT + tb * outT2 in the output); nT2 <= 1 means one level.
-  int64_t nT2, inT2, outT2;
   int64_t N;                    // species stride
   int n, C, pitch, nbuf, tile;  // line length, chunks, LDS pitch/buffers/size
   int lines;                    // lines per tile = wavefronts per block
@@ -672,16 +669,7 @@ struct TileAt {
   int64_t t, f0;
   int64_t tin, tout;  // offsets of line group t in the input and the output
   __device__ __forceinline__ TileAt(int64_t tile, const PassGeom& g)
-      : t(tile / g.nFblk), f0((tile % g.nFblk) * g.lines) {
-    if (g.nT2 > 1) {
-      const int64_t ta = t / g.nT2, tb = t - ta * g.nT2;
-      tin = ta * g.inT + tb * g.inT2;
-      tout = ta * g.outT + tb * g.outT2;
-    } else {
-      tin = t * g.inT;
-      tout = t * g.outT;
-    }
-  }
+      : t(tile / g.nFblk), f0((tile % g.nFblk) * g.lines), tin(t * g.inT), tout(t * g.outT) {}
   // Line group 0 (the batch kernels, whose tiles carry their own offsets).
   __device__ __forceinline__ explicit TileAt(int64_t f0_) : t(0), f0(f0_), tin(0), tout(0) {}
 };

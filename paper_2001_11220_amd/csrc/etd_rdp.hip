@@ -270,10 +270,23 @@ __global__ __launch_bounds__(256) void k_pre1d(const T* __restrict__ u, T* __res
   }
 }
 
-// The reaction field in the layout the last pass reads its lines in, the
-// state layout with the axis order reversed: out[i_1][i_2][i_3][i_4] =
-// in[i_4][i_3][i_2][i_1] (unused trailing axes have extent 1).  Runs once per
-// set_field call.
+// The reaction field in the layout the last pass reads its lines in; runs
+// once per set_field call.  Cyclic layouts (d >= 4): the last pass reads
+// axis d fastest, then axes 1, ..., d-1, i.e. u's layout seen as an
+// (n_d x N/n_d) matrix, transposed: out[i_d + n_d r] = in[i_d (N/n_d) + r].
+__global__ __launch_bounds__(256) void k_field_cyclic_last(const double* __restrict__ in,
+                                                           double* __restrict__ out, int64_t nd,
+                                                           int64_t rest) {
+  const int64_t N = nd * rest;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < N;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = o % nd, r = o / nd;
+    out[o] = in[id * rest + r];
+  }
+}
+
+// d <= 3: the state layout with the axis order reversed, out[i_1][i_2][i_3]
+// = in[i_3][i_2][i_1] (unused trailing axes have extent 1; n4 is 1).
 __global__ __launch_bounds__(256) void k_field_last_layout(const double* __restrict__ in,
                                                            double* __restrict__ out, int64_t n1,
                                                            int64_t n2, int64_t n3, int64_t n4) {
@@ -378,11 +391,8 @@ size_t geom_lds(const Geom& g, size_t fixed_lds) {
 
 PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, bool one_line,
                    size_t esize) {
-  // In 4-D with a reaction field, passes 1 and 2 see axes 3 and 4 as one
-  // flattened axis (n3 below, axis 3 the faster), which their layouts keep
-  // contiguous.
   const int64_t n1 = c->n[0], n2 = c->n[1];
-  const int64_t n3 = (c->d >= 3) ? c->n[2] * (c->d == 4 ? c->n[3] : 1) : 1;
+  const int64_t n3 = (c->d >= 3) ? c->n[2] : 1;
   PassGeom g{};
   g.N = c->N;
   int axis0 = 0;
@@ -410,25 +420,10 @@ PassGeom pass_geom(const etd_rdp_ctx* c, int kind, size_t fixed_lds, int lines, 
       g.inF = n1 * n2; g.inT = n2;
       g.outT = n2 * n3; g.outRow = n3;
       break;
-    case kPassMid2: {  // 4-D: i3-lines of B [i1][i2][i4][i3] -> A [i1][i2][i3][i4]
-      const int64_t m3 = c->n[2], m4 = c->n[3];
-      axis0 = 2;
-      g.nF = m4; g.inF = m3;                       // f = i4
-      g.nT = n1 * n2; g.nT2 = n2;                  // t = (i1, i2)
-      g.inT = n2 * m4 * m3; g.inT2 = m4 * m3;
-      g.outT = n2 * m3 * m4; g.outT2 = m3 * m4; g.outRow = m4;
-      break;
-    }
-    case kPassLast:  // lines (x, y) along axis d of B (3-D) or A (2-D, 4-D) -> u
+    case kPassLast:  // lines (x, y) along axis d of B (3-D) or A (2-D) -> u
       axis0 = c->d - 1;
       g.nF = n1;
-      if (c->d == 4) {  // i4-lines of A [i1][i2][i3][i4], t = (i3, i2)
-        const int64_t m3 = c->n[2], m4 = c->n[3];
-        g.inF = n2 * m3 * m4;
-        g.nT = m3 * n2; g.nT2 = n2;
-        g.inT = m4; g.inT2 = m3 * m4;
-        g.outT = n1 * n2; g.outT2 = n1; g.outRow = n1 * n2 * m3;
-      } else if (c->d == 3) {
+      if (c->d == 3) {
         g.nT = n2; g.inF = n2 * n3; g.inT = n3;
         g.outT = n1; g.outRow = n1 * n2;
       } else if (c->d == 2) {
@@ -1117,7 +1112,6 @@ int etd_rdp_init(const etd_grid_t* grid, const int32_t* bc, const double* D, dou
   if (cplx && (lpw == ETD_LINES_TWO || lpw == ETD_LINES_FOUR || lpw == ETD_LINES_EIGHT))
     return ETD_ERR_UNSUPPORTED;
   if (rx->field != 0 && (rx->field != 1 || rx->model != ETD_RX_NLS_Z)) return ETD_ERR_ARG;
-  if (rx->field != 0 && d >= 5) return ETD_ERR_UNSUPPORTED;
 
   etd_rdp_ctx* c = new (std::nothrow) etd_rdp_ctx();
   if (!c) return ETD_ERR_INTERNAL;
@@ -1268,7 +1262,7 @@ int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass, size_t* off_c
   *off_c2 = ctx->tab_bytes + (first + 1) * ctx->arr_bytes;
   *off_w = ctx->tab_bytes + (first + 2) * ctx->arr_bytes;
   const int64_t n1 = ctx->n[0], n2 = ctx->n[1];
-  const int64_t n3 = (ctx->d >= 3) ? ctx->n[2] : 1, n4 = (ctx->d == 4) ? ctx->n[3] : 1;
+  const int64_t n3 = (ctx->d >= 3) ? ctx->n[2] : 1;
   if (cyclic_layout(ctx)) {
     // cyclic: axes pass, pass + 1, ..., d - 1, 0, ..., pass - 1 (0-based),
     // fastest first
@@ -1280,21 +1274,14 @@ int etd_rdp_workspace_layout(const etd_rdp_ctx* ctx, int32_t pass, size_t* off_c
     }
     return ETD_OK;
   }
-  if (pass == 1) {  // [i4][i3][i1][i2]
+  if (pass == 1) {  // [z][x][y] (2-D: [x][y])
     strides[0] = n2;
     strides[1] = 1;
-    if (ctx->d >= 3) strides[2] = n1 * n2;
-    if (ctx->d == 4) strides[3] = n1 * n2 * n3;
-  } else if (pass == 2) {  // [i1][i2][i4][i3]
-    strides[0] = n2 * n3 * n4;
-    strides[1] = n3 * n4;
+    if (ctx->d == 3) strides[2] = n1 * n2;
+  } else {  // 3-D pass 2: [x][y][z]
+    strides[0] = n2 * n3;
+    strides[1] = n3;
     strides[2] = 1;
-    if (ctx->d == 4) strides[3] = n3;
-  } else {  // 4-D pass 3: [i1][i2][i3][i4]
-    strides[0] = n2 * n3 * n4;
-    strides[1] = n3 * n4;
-    strides[2] = n4;
-    strides[3] = 1;
   }
   return ETD_OK;
 }
@@ -1365,9 +1352,15 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
                                 hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return hip_fail(ctx, e);
   const int64_t blocks = std::min<int64_t>((N + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_field_last_layout, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, b,
-                     fd, ctx->n[0], ctx->n[1], ctx->d >= 3 ? ctx->n[2] : int64_t(1),
-                     ctx->d == 4 ? ctx->n[3] : int64_t(1));
+  if (cyclic_layout(ctx)) {
+    const int64_t nd = ctx->n[ctx->d - 1];
+    hipLaunchKernelGGL(k_field_cyclic_last, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                       b, fd, nd, N / nd);
+  } else {
+    hipLaunchKernelGGL(k_field_last_layout, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                       b, fd, ctx->n[0], ctx->n[1], ctx->d >= 3 ? ctx->n[2] : int64_t(1),
+                       int64_t(1));
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e);
   ctx->field_ws = ws;

@@ -154,6 +154,33 @@ def test_5d_f32_complex_and_etd1():
     assert err32 <= 1e-5 and errz <= 1e-12 and err1 <= 1e-12, (err32, errz, err1)
 
 
+@pytest.mark.parametrize("shape,bcs", [
+    ((7, 5, 6, 4, 9), ("neumann", "periodic", "dirichlet", "neumann", "periodic")),
+    ((5, 4, 3, 6, 4, 7), ("periodic", "dirichlet", "neumann", "periodic", "neumann", "dirichlet")),
+])
+def test_schroedinger_with_field_nd_matches_oracle(shape, bcs):
+    """The per-cell reaction field (Section 8.4's B(x) added to q) in 5-D and
+    6-D: pass 1 reads it in u's layout, the last pass from its copy in the
+    cyclic last-pass layout (axis d fastest, then axes 1 .. d-1)."""
+    torch = _torch()
+    z = W.Problem("zf", shape, bcs, (1j,), 1e-3, "nls_z", {"B": 0.4, "C": -1.0}, 1, seed=0,
+                  ic="complex_noise", ic_args={"amp": 0.5})
+    z0 = z.initial()
+    field = np.random.default_rng(7).standard_normal(shape[::-1])
+    e = _etd().EtdRdp(z.shape, z.bcs, z.D, z.k, z.model, z.params, precision="c128", field=True)
+    u = torch.from_numpy(z0).cuda()
+    e.set_field(torch.from_numpy(field).cuda())
+    e.step(u, 2)
+    torch.cuda.synchronize()
+    e.close()
+    ref = O.etd_rdp_if_run(z0, z.k, z.D, z.bcs, z.hs(), z.model, dict(z.oracle_params(), Bfield=field), 2)
+    got = u.cpu().numpy()
+    err = rel_l2(got, ref)
+    pt = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print(f"[{len(shape)}-D complex field {shape}, 2 steps] rel_l2={err:.2e} pointwise={pt:.2e}", flush=True)
+    assert err <= 1e-12 and pt <= 1e-12, (err, pt)
+
+
 def test_5d_step_splitting_and_graph_are_bitwise():
     """step(3) + step(2) == step(5) and a graph replay equals direct launches,
     bit for bit, in 5-D."""
