@@ -1,5 +1,5 @@
-"""Seeded random configurations (dimension 1-4, and 5-6 on seeds 60-79,
-which also draw four and eight lines per wavefront; line lengths with ragged
+"""Seeded random configurations (dimension 1-4, 5-6 on seeds 60-79 and 4
+on seeds 200-219, which also draw four and eight lines per wavefront; line lengths with ragged
 tiles, boundary conditions, models, FP64 / FP32 / complex, one or two lines
 per wavefront, both schemes), each one step on the GPU against the oracle.
 
@@ -64,16 +64,20 @@ def _config(seed, lengths=LENGTHS, dims=(1, 5)):
     return prob, prec, lpw, scheme
 
 
-@pytest.mark.parametrize("seed", range(80))
+@pytest.mark.parametrize("seed", list(range(80)) + list(range(200, 220)))
 def test_random_configuration_matches_oracle(seed):
     """Seeds 0-39 draw regular line lengths, seeds 40-59 general ones too,
-    seeds 60-79 five or six axes (regular and general lengths)."""
+    seeds 60-79 five or six axes, seeds 200-219 four axes (regular and
+    general lengths; the last two ranges also four and eight lines per
+    wavefront)."""
     import torch
     from paper_2001_11220_amd import etd
     if seed < 60:
         prob, prec, lpw, scheme = _config(seed, LENGTHS if seed < 40 else LENGTHS + GENERAL)
-    else:
+    elif seed < 80:
         prob, prec, lpw, scheme = _config(seed, LENGTHS + GENERAL, dims=(5, 7))
+    else:
+        prob, prec, lpw, scheme = _config(seed, LENGTHS + GENERAL, dims=(4, 5))
     u0 = prob.initial()
     e = etd.EtdRdp(prob.shape, prob.bcs, prob.D, prob.k, prob.model, prob.params, scheme=scheme,
                    lines_per_wave=lpw, precision=prec)
