@@ -195,8 +195,8 @@ int etd_rdp_destroy(etd_rdp_ctx* ctx);
  * Bytes of device workspace a step needs: the factor tables plus the
  * carried FP64 arrays of s*N values each (the passes' intermediates): one
  * triple (c1, c2, w) written by pass 1 and, for d >= 3, a second triple
- * written by pass 2 (six arrays in 3-D and 4-D, three in 2-D; in 4-D pass 3
- * writes the first triple again).
+ * written by pass 2 (six arrays for d >= 3, three in 2-D; later passes
+ * alternate between the two triples, odd passes writing the first).
  */
 int etd_rdp_workspace_bytes(const etd_rdp_ctx* ctx, size_t* bytes);
 
