@@ -330,8 +330,7 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
  * single-species grid array x of N doubles (layout as one species of u),
  * gamma = 1, 3 or 4 (Section 7: the systems the scheme solves).  axis is
  * 1-based.  Exposes the line solver alone for testing.  FP64 contexts with
- * d <= 3 and a regular line length on the axis only (ETD_ERR_UNSUPPORTED
- * otherwise).
+ * a regular line length on the axis only (ETD_ERR_UNSUPPORTED otherwise).
  */
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes,
                         int32_t axis, int32_t sigma, int32_t gamma,

@@ -357,7 +357,6 @@ int reaction_param_count(int model, int s) {
 
 Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds) {
   Geom g{};
-  const int64_t n1 = c->n[0], n2 = c->n[1];
   g.N = c->N;
   g.n = static_cast<int>(c->n[axis0]);
   g.C = g.n / c->m1[axis0];
@@ -365,22 +364,16 @@ Geom make_geom(const etd_rdp_ctx* c, int axis0, size_t fixed_lds) {
   g.tile = kBlockLines * g.pitch;
   // Two tile buffers (one barrier per move) when two blocks still fit a CU.
   g.nbuf = (fixed_lds + 2 * sizeof(double) * (size_t)g.tile <= kLdsMax / 2) ? 2 : 1;
-  if (axis0 == 1 && c->d == 3) {  // lines (x, z) along y
-    g.nF = n1;
-    g.nT = c->n[2];
-    g.sRow = n1;
-    g.sT = n1 * n2;
-  } else if (axis0 == 1) {  // 2-D, lines x along y
-    g.nF = n1;
-    g.nT = 1;
-    g.sRow = n1;
-    g.sT = 0;
-  } else {  // axis 3: lines (x, y) along z
-    g.nF = n1 * n2;
-    g.nT = 1;
-    g.sRow = n1 * n2;
-    g.sT = 0;
-  }
+  // Lines along axis0 >= 1 in u's layout (axis 1 fastest): the faster axes
+  // index the lines of a tile row (nF of them, adjacent), the slower ones the
+  // row groups; row j of a line is j * sRow further on.
+  int64_t faster = 1, slower = 1;
+  for (int a = 0; a < axis0; ++a) faster *= c->n[a];
+  for (int a = axis0 + 1; a < c->d; ++a) slower *= c->n[a];
+  g.nF = faster;
+  g.nT = slower;
+  g.sRow = faster;
+  g.sT = slower > 1 ? faster * c->n[axis0] : 0;
   g.nFblk = (g.nF + kBlockLines - 1) / kBlockLines;
   return g;
 }
@@ -1370,7 +1363,7 @@ int etd_rdp_set_field(etd_rdp_ctx* ctx, void* ws, size_t ws_bytes, const double*
 int etd_rdp_apply_solve(etd_rdp_ctx* ctx, double* x, void* ws, size_t ws_bytes, int32_t axis,
                         int32_t sigma, int32_t gamma, void* stream) {
   if (!ctx || !x || axis < 1 || axis > ctx->d || sigma < 0 || sigma >= ctx->s) return ETD_ERR_ARG;
-  if (ctx->precision != ETD_PRECISION_F64 || ctx->d > 3) return ETD_ERR_UNSUPPORTED;
+  if (ctx->precision != ETD_PRECISION_F64) return ETD_ERR_UNSUPPORTED;
   if (ctx->gen[axis - 1]) return ETD_ERR_UNSUPPORTED;
   const int slot = gamma == 1 ? 0 : (gamma == 3 ? 1 : (gamma == 4 ? 2 : -1));
   if (slot < 0) return ETD_ERR_ARG;

@@ -219,7 +219,7 @@ def test_five_to_eight_dimensions_without_touching_the_gpu():
     """d = 5 .. 8 (Section 6's frame for any d): every pass reads its lines
     contiguously from a cyclic layout (pass p writes axis p+1 fastest, then
     p+2, ..., d, 1, ..., p), with the same kernels as the other dimensions;
-    the reverse step and single solves are refused, a reaction field is
+    the reverse step is refused, single solves and a reaction field are
     accepted; the C ABI refuses d = 0 and d = 9."""
     from paper_2001_11220_amd import etd
     shape = (6, 5, 4, 3, 7)
@@ -237,7 +237,9 @@ def test_five_to_eight_dimensions_without_touching_the_gpu():
     assert e.adj_ws_bytes > 0
     u, x, g, ws = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x10000))
     assert etd.lib.etd_rdp_adjoint(e._ctx, u, x, g, g, ws, 1 << 40, None) == etd.ETD_ERR_UNSUPPORTED
-    assert etd.lib.etd_rdp_apply_solve(e._ctx, x, ws, e.ws_bytes, 1, 0, 3, None) == etd.ETD_ERR_UNSUPPORTED
+    # single solves take any axis of any d; arguments are checked first
+    assert etd.lib.etd_rdp_apply_solve(e._ctx, x, ws, e.ws_bytes, 6, 0, 3, None) == etd.ETD_ERR_ARG
+    assert etd.lib.etd_rdp_apply_solve(e._ctx, x, ws, e.ws_bytes, 5, 0, 2, None) == etd.ETD_ERR_ARG
     e.close()
     e8 = _init((3,) * 8, ("periodic",) * 8, D=(0.3,), model="linear", params={"C": [[-0.5]]})
     assert e8.line_split(8) == (1, 3)
